@@ -1,0 +1,75 @@
+"""H built on the full Hilbert space from Kronecker products (Sec. II, Eqs. ed:eq:genericH and
+ed:eq:OH; site and bond rules of App. A, Eqs. ed:eq:appsiters / ed:eq:appbondrs).
+
+A site rule term c_k O_k is I_{d^(k-1)} (x) O (x) I_{d^(L-k)}; a bond rule term c'_k O_k O'_{k+1}
+is I_{d^(k-1)} (x) B (x) I_{d^(L-k-1)} with B = O (x) O' given as a d^2 x d^2 matrix. Site 1 is
+the leftmost Kronecker factor, i.e. the most significant digit of the state index.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+
+def _embed(op, k, width, L, d, fmt="coo"):
+    """I_{d^(k-1)} (x) op (x) I_{d^(L-k-width+1)} for an operator on sites k..k+width-1 (1-based)."""
+    left = sp.identity(d ** (k - 1), dtype=np.complex128, format="csr")
+    right = sp.identity(d ** (L - k - width + 1), dtype=np.complex128, format="csr")
+    return sp.kron(sp.kron(left, sp.csr_matrix(op), format="csr"), right, format=fmt)
+
+
+def hamiltonian_sparse(desc):
+    """Sparse CSR H = sum_zeta sum_k c_k O_k + sum_zeta sum_k c'_k O_k O'_{k+1}."""
+    L, d = desc.L, desc.d
+    D = d ** L
+    rows, cols, vals = [], [], []
+    terms = []
+    for z in range(len(desc.site_ops)):
+        for k in range(1, L + 1):
+            c = desc.site_coef[z, k - 1]
+            if c != 0.0:
+                terms.append(c * _embed(desc.site_ops[z], k, 1, L, d))
+    for z in range(len(desc.bond_ops)):
+        for k in range(1, L):
+            c = desc.bond_coef[z, k - 1]
+            if c != 0.0:
+                terms.append(c * _embed(desc.bond_ops[z], k, 2, L, d))
+    for t in terms:
+        t = t.tocoo()
+        rows.append(t.row)
+        cols.append(t.col)
+        vals.append(t.data)
+    if not terms:
+        return sp.csr_matrix((D, D), dtype=np.complex128)
+    H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(D, D)).tocsr()   # duplicates are summed
+    H.eliminate_zeros()
+    return H
+
+
+def hamiltonian_dense(desc):
+    """Dense H by numpy.kron (the paper's dense build, Sec. II)."""
+    L, d = desc.L, desc.d
+    D = d ** L
+    H = np.zeros((D, D), np.complex128)
+    for z in range(len(desc.site_ops)):
+        for k in range(1, L + 1):
+            c = desc.site_coef[z, k - 1]
+            if c != 0.0:
+                H += c * np.kron(np.kron(np.eye(d ** (k - 1)), desc.site_ops[z]), np.eye(d ** (L - k)))
+    for z in range(len(desc.bond_ops)):
+        for k in range(1, L):
+            c = desc.bond_coef[z, k - 1]
+            if c != 0.0:
+                H += c * np.kron(np.kron(np.eye(d ** (k - 1)), desc.bond_ops[z]), np.eye(d ** (L - k - 1)))
+    return H
+
+
+def apply_H(desc, psi, H=None):
+    """y = H psi with the explicit sparse H (Krylov mode 1 of Sec. III.C)."""
+    if H is None:
+        H = hamiltonian_sparse(desc)
+    return H @ psi
+
+
+def site_operator(op, k, L, d=2):
+    """Sparse I (x) op (x) I for op on site k (1-based)."""
+    return _embed(op, k, 1, L, d, fmt="csr")
