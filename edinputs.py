@@ -147,3 +147,14 @@ def adjoint_couplings(n_slices, n_bonds, seed, lo=0.5, hi=1.5):
 def trajectory_lengths(n_traj, lengths=(8, 10, 12, 14, 16)):
     """Chain length of trajectory t is lengths[t mod len(lengths)]."""
     return np.array([lengths[t % len(lengths)] for t in range(n_traj)], dtype=np.int32)
+
+
+def random_state_device(L, seed, device):
+    """Complex-normal normalised state of length 2^L generated directly on a torch device
+    (seeded torch generator), for sizes where a host copy would only cost time."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    v = torch.randn(1 << L, dtype=torch.complex128, device=device, generator=g)
+    v /= torch.linalg.vector_norm(v)
+    return v

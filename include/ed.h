@@ -1,0 +1,103 @@
+/*
+ * ed.h -- C ABI of the MI355X exact-diagonalisation hot path (libed.so).
+ *
+ * The library applies a local 1-D lattice Hamiltonian to a dense complex128 state without ever
+ * storing H (the "rule set x psi" product of Sec. III.C, Eq. ed:eq:OKrylov), and builds on that
+ * product: Lanczos ground states (Sec. II statics, computed matrix-free), Krylov time steps
+ * (Sec. III.C), quantum trajectories (Sec. VI.A), a bond-coupling adjoint gradient and the
+ * half-chain bond entropy (Sec. IV).
+ *
+ * Conventions shared by every call
+ *   - d = 2. The state index is x = sum_{k=1..L} i_k 2^(L-k): site 1 is the most significant
+ *     digit (the row-major rank-L tensor view of Sec. IV). Local index 0 = up (sigma^z = +1).
+ *     Site k therefore sits at bit p = L-k, and bond (k, k+1) occupies bits (L-k-1, L-k).
+ *   - Amplitudes are ed_c64 (interleaved re, im; the layout of torch.complex128), D = 2^L.
+ *   - "device" pointers are HIP device memory owned by the caller; the library never frees or
+ *     reallocates them. Host pointers are plain CPU memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream). Calls that return host
+ *     scalars synchronise that stream before returning; ed_apply_H is asynchronous.
+ *   - Every call returns ed_status. On error the outputs are unspecified and ed_last_error()
+ *     returns a message (thread-local). No C++ exception crosses this boundary.
+ *   - Model handles are immutable after creation: concurrent calls that share a handle on
+ *     different streams are safe. Calls that share a workspace must not overlap.
+ */
+#ifndef ED_H
+#define ED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } ed_c64;
+
+typedef enum {
+    ED_OK = 0,
+    ED_ERR_ARG = -1,          /* invalid argument (null pointer, size, range)          */
+    ED_ERR_UNSUPPORTED = -2,  /* valid request outside this build (d != 2, L > 30 ...)  */
+    ED_ERR_NODEVICE = -3,     /* no HIP device visible                                  */
+    ED_ERR_NOMEM = -4,        /* a small internal device/host allocation failed         */
+    ED_ERR_WORKSPACE = -5,    /* caller workspace smaller than the size query returned  */
+    ED_ERR_HIP = -6,          /* a HIP runtime call failed                              */
+    ED_ERR_NOCONV = -7,       /* iteration limit reached before the tolerance           */
+    ED_ERR_NUMERIC = -8       /* non-finite value detected                               */
+} ed_status;
+
+/* Thread-local message describing the last error of this thread ("" if none). */
+const char* ed_last_error(void);
+
+/* Library version string. */
+const char* ed_version(void);
+
+/* ----------------------------------------------------------------------------------------
+ * Model: a rule-set Hamiltonian (Eq. ed:eq:genericH; site and bond rules of App. A,
+ * Eqs. ed:eq:appsiters and ed:eq:appbondrs), with the general coupling w and the
+ * site-dependent c_k folded into one coefficient per term:
+ *
+ *   H = sum_{z<n_site} sum_{k=1..L} site_coef[z][k-1] * O^z_k
+ *     + sum_{z<n_bond} sum_{k=1..L-1} bond_coef[z][k-1] * B^z_{k,k+1}
+ *
+ *   site_op  host, [n_site][2][2] row-major (<i|O|j> at [i][j])
+ *   bond_op  host, [n_bond][4][4] row-major, index i_k*2 + i_{k+1} (site k is the left
+ *            Kronecker factor)
+ *   site_coef host, [n_site][L];  bond_coef host, [n_bond][L-1]   (real)
+ * Operators may be non-Hermitian (the effective Hamiltonian of a trajectory); Hermiticity of a
+ * Hamiltonian is the caller's responsibility, as in the paper's rule sets. All host arrays are
+ * copied; the handle keeps small coefficient tables in device memory of the current device.
+ * Requires 2 <= L <= 30 and d == 2 (else ED_ERR_UNSUPPORTED); n_site, n_bond >= 0; a null
+ * array is allowed only when its count is 0.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct ed_model ed_model;
+
+typedef struct {
+    int L;
+    int d;
+    int n_site;
+    const ed_c64* site_op;
+    const double* site_coef;
+    int n_bond;
+    const ed_c64* bond_op;
+    const double* bond_coef;
+} ed_model_desc;
+
+ed_status ed_model_create(const ed_model_desc* desc, ed_model** out);
+ed_status ed_model_destroy(ed_model* model);
+/* L and D = 2^L of a model. */
+ed_status ed_model_dims(const ed_model* model, int* L, int64_t* D);
+/* Number of streaming passes over the state one ed_apply_H makes (diagnostic). */
+ed_status ed_model_passes(const ed_model* model, int* passes);
+
+/* ----------------------------------------------------------------------------------------
+ * ed_apply_H: out = H psi (Sec. III.C, the rule set applied to the state without building H,
+ * Eq. ed:eq:OKrylov). psi and out are device arrays of D amplitudes that must not overlap.
+ * Asynchronous on stream.
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ED_H */

@@ -73,3 +73,35 @@ def apply_H(desc, psi, H=None):
 def site_operator(op, k, L, d=2):
     """Sparse I (x) op (x) I for op on site k (1-based)."""
     return _embed(op, k, 1, L, d, fmt="csr")
+
+
+def apply_H_entries(desc, psi, xs):
+    """(H psi)[x] for the indices xs, evaluated term by term from the rule definitions: a site
+    term on site k maps psi to sum_{i'} O[i_k(x), i'] psi[x with i_k = i'], a bond term likewise on
+    the two digits of sites k, k+1; all other digits are untouched (the identity factors of the
+    Kronecker product). Used where the full sparse H does not fit in memory."""
+    L = desc.L
+    xs = np.asarray(xs, dtype=np.int64)
+    acc = np.zeros(len(xs), np.complex128)
+    for z in range(len(desc.site_ops)):
+        for k in range(1, L + 1):
+            c = desc.site_coef[z, k - 1]
+            if c == 0.0:
+                continue
+            p = L - k
+            b = (xs >> p) & 1
+            for bp in (0, 1):
+                y = (xs & ~np.int64(1 << p)) | (np.int64(bp) << p)
+                acc += c * desc.site_ops[z][b, bp] * psi[y]
+    for z in range(len(desc.bond_ops)):
+        for k in range(1, L):
+            c = desc.bond_coef[z, k - 1]
+            if c == 0.0:
+                continue
+            p_left, p_right = L - k, L - k - 1
+            row = 2 * ((xs >> p_left) & 1) + ((xs >> p_right) & 1)
+            for col in range(4):
+                y = (xs & ~np.int64((1 << p_left) | (1 << p_right))) \
+                    | (np.int64(col >> 1) << p_left) | (np.int64(col & 1) << p_right)
+                acc += c * desc.bond_ops[z][row, col] * psi[y]
+    return acc

@@ -1,0 +1,72 @@
+"""ctypes view of libed.so (the C ABI declared in include/ed.h).
+
+Argument marshalling only: every step of the hot path runs in the library's HIP kernels. The
+library must be built (paper_1802_10052_amd/build.py); importing without it fails loudly.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libed.so")
+
+
+class EdError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+class c64(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class ModelDescC(C.Structure):
+    _fields_ = [("L", C.c_int), ("d", C.c_int),
+                ("n_site", C.c_int), ("site_op", C.c_void_p), ("site_coef", C.c_void_p),
+                ("n_bond", C.c_int), ("bond_op", C.c_void_p), ("bond_coef", C.c_void_p)]
+
+
+ED_OK = 0
+STATUS = {0: "ED_OK", -1: "ED_ERR_ARG", -2: "ED_ERR_UNSUPPORTED", -3: "ED_ERR_NODEVICE",
+          -4: "ED_ERR_NOMEM", -5: "ED_ERR_WORKSPACE", -6: "ED_ERR_HIP", -7: "ED_ERR_NOCONV",
+          -8: "ED_ERR_NUMERIC"}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libed.so is not built ({LIB_PATH}); run paper_1802_10052_amd/build.py")
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _fn(l, name, argtypes, restype=C.c_int):
+    f = getattr(l, name)
+    f.argtypes = argtypes
+    f.restype = restype
+    return f
+
+
+def _declare(l):
+    P = C.c_void_p
+    _fn(l, "ed_last_error", [], C.c_char_p)
+    _fn(l, "ed_version", [], C.c_char_p)
+    _fn(l, "ed_model_create", [C.POINTER(ModelDescC), C.POINTER(P)])
+    _fn(l, "ed_model_destroy", [P])
+    _fn(l, "ed_model_dims", [P, C.POINTER(C.c_int), C.POINTER(C.c_int64)])
+    _fn(l, "ed_model_passes", [P, C.POINTER(C.c_int)])
+    _fn(l, "ed_apply_H", [P, P, P, P])
+
+
+def check(name, code):
+    if code != ED_OK:
+        msg = lib().ed_last_error().decode(errors="replace")
+        raise EdError(name, STATUS.get(code, code), msg)
+
+
+def call(name, *args):
+    check(name, getattr(lib(), name)(*args))

@@ -1,0 +1,84 @@
+// Internal declarations shared by the translation units of libed.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ed.h"
+
+namespace ed {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+ed_status fail(ed_status code, const std::string& msg);
+
+#define ED_HIP_TRY(expr)                                                                   \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return ::ed::fail(ED_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+#define ED_TRY(expr)                     \
+    do {                                 \
+        ed_status _s = (expr);           \
+        if (_s != ED_OK) return _s;      \
+    } while (0)
+
+ed_status require_device(int* device);
+
+// ---------------------------------------------------------------- H psi plan
+// Tile of one streaming pass: the low `c` bits of the index plus the window of `w` bits starting
+// at bit h0 (h0 >= c, or w == 0). Bonds and sites are assigned to exactly one pass each.
+constexpr int kTileBits = 12;      // amplitudes per workgroup tile = 2^12 (64 KiB of LDS)
+constexpr int kTileThreads = 256;  // threads per tile workgroup
+constexpr int kWindowLow = 3;      // contiguous low bits kept in window passes (128 B runs)
+constexpr int kMaxPasses = 4;
+
+struct PassDesc {
+    int c;            // contiguous low bits in the tile
+    int h0;           // first bit of the window
+    int w;            // window width (0 for the first pass)
+    int first;        // 1: writes out (and adds the diagonal); 0: accumulates into out
+    uint32_t site_mask;  // bit q set: the site on tile-local bit q belongs to this pass
+    uint32_t bond_mask;  // bit q set: the bond on tile-local bits (q, q+1) belongs to this pass
+    int bit_of[kTileBits];  // global bit of tile-local bit q
+};
+
+enum OpClass : unsigned {
+    kSiteOff = 1u,      // some site operator has off-diagonal entries
+    kBondSingle = 2u,   // some bond operator flips exactly one of its two sites
+    kBondDouble = 4u,   // some bond operator flips both sites
+    kOffReal = 8u,      // every off-diagonal entry is real
+    kDiagReal = 16u,    // every diagonal entry is real
+};
+
+}  // namespace ed
+
+// Device-side coefficient tables of a model. All indices are by BIT position p (site at bit p is
+// site k = L - p; the bond at bit p couples bits p and p+1, i.e. sites L-p-1 and L-p).
+struct ed_model {
+    int L = 0;
+    int device = 0;
+    unsigned op_class = 0;
+    // host copies (folded over the rule terms)
+    std::vector<double2> site;   // [L][2][2]  per bit
+    std::vector<double2> bond;   // [L-1][4][4] per bond bit, local index 2*bit(p+1) + bit(p)
+    // device copies
+    double2* d_site = nullptr;   // [L][4]
+    double2* d_bond = nullptr;   // [L-1][16]
+    double2* d_diag_lo = nullptr;  // [256]   bonds 0..6, sites 0..7   (low table)
+    double2* d_diag_mid = nullptr; // [2^(T-7)] bonds 7..T-2, sites 8..T-1
+    double2* d_diag_hi = nullptr;  // [2^(L-T+1)] bonds T-1..L-2, sites T..L-1
+    int tile_bits = 0;           // T = min(L, kTileBits)
+    int n_pass = 0;
+    ed::PassDesc pass[ed::kMaxPasses];
+};
+
+namespace ed {
+// Launch the passes of out = H psi (apply_h.hip).
+ed_status launch_apply_H(const ed_model* m, const double2* psi, double2* out, hipStream_t s);
+}  // namespace ed

@@ -1,0 +1,280 @@
+// Model handle: folds the rule-set terms (Eq. ed:eq:genericH, App. A site and bond rules) into
+// one 2x2 operator per site and one 4x4 operator per bond, classifies the non-zero pattern so the
+// H psi kernels can skip absent terms ("iterate only over non-zero elements", Sec. II), builds the
+// diagonal tables, and plans the streaming passes of H psi.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ed_internal.h"
+
+namespace ed {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+ed_status fail(ed_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+ed_status require_device(int* device) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) return fail(ED_ERR_NODEVICE, "no HIP device visible");
+    ED_HIP_TRY(hipGetDevice(device));
+    return ED_OK;
+}
+
+static void plan_passes(ed_model* m) {
+    const int L = m->L;
+    const int T = kTileBits;
+    m->tile_bits = L < T ? L : T;
+    if (L < T) {
+        m->n_pass = 1;
+        std::memset(&m->pass[0], 0, sizeof(PassDesc));
+        m->pass[0].first = 1;
+        m->pass[0].c = L;
+        return;
+    }
+    int np = 0;
+    // first pass: contiguous low T bits, all terms inside them plus every diagonal
+    PassDesc& p0 = m->pass[np++];
+    std::memset(&p0, 0, sizeof(PassDesc));
+    p0.c = T;
+    p0.h0 = T;
+    p0.w = 0;
+    p0.first = 1;
+    for (int q = 0; q < T; ++q) p0.bit_of[q] = q;
+    p0.site_mask = (1u << T) - 1u;
+    p0.bond_mask = (1u << (T - 1)) - 1u;
+    int done_bits = T;  // sites on bits < done_bits and bonds on bits < done_bits-1 are assigned
+    const int wbits = T - kWindowLow;
+    while (done_bits < L) {
+        PassDesc& pd = m->pass[np++];
+        std::memset(&pd, 0, sizeof(PassDesc));
+        int h0 = done_bits - 1;  // overlap one bit: the bond crossing into the window
+        if (h0 + wbits > L) h0 = L - wbits;
+        pd.c = kWindowLow;
+        pd.h0 = h0;
+        pd.w = wbits;
+        pd.first = 0;
+        for (int q = 0; q < T; ++q) pd.bit_of[q] = q < kWindowLow ? q : h0 + (q - kWindowLow);
+        for (int q = kWindowLow; q < T; ++q) {
+            const int p = pd.bit_of[q];
+            if (p >= done_bits) pd.site_mask |= 1u << q;
+            if (q + 1 < T && p + 1 >= done_bits && p + 1 < L) pd.bond_mask |= 1u << q;
+        }
+        done_bits = h0 + wbits;
+    }
+    m->n_pass = np;
+}
+
+static inline double2 c2(double re, double im) { return make_double2(re, im); }
+
+// diagonal contribution of the sites on bits [s_lo, s_hi) and bonds on bits [b_lo, b_hi)
+// evaluated at index x
+static double2 diag_part(const ed_model* m, uint64_t x, int s_lo, int s_hi, int b_lo, int b_hi) {
+    double re = 0.0, im = 0.0;
+    for (int p = s_lo; p < s_hi; ++p) {
+        const int b = int((x >> p) & 1u);
+        const double2 v = m->site[4 * p + 3 * b];
+        re += v.x;
+        im += v.y;
+    }
+    for (int p = b_lo; p < b_hi; ++p) {
+        const int l = int((x >> p) & 3u);
+        const double2 v = m->bond[16 * p + 5 * l];
+        re += v.x;
+        im += v.y;
+    }
+    return c2(re, im);
+}
+
+static ed_status upload(double2** dst, const std::vector<double2>& src) {
+    const size_t bytes = (src.empty() ? 1 : src.size()) * sizeof(double2);
+    ED_HIP_TRY(hipMalloc(dst, bytes));
+    if (!src.empty()) ED_HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(double2), hipMemcpyHostToDevice));
+    return ED_OK;
+}
+
+static void free_tables(ed_model* m) {
+    double2** ptrs[] = {&m->d_site, &m->d_bond, &m->d_diag_lo, &m->d_diag_mid, &m->d_diag_hi};
+    for (double2** p : ptrs) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+}
+
+ed_status build_device_tables(ed_model* m) {
+    const int L = m->L;
+    ED_TRY(upload(&m->d_site, m->site));
+    ED_TRY(upload(&m->d_bond, m->bond));
+    if (L >= kTileBits) {
+        const int T = kTileBits;
+        std::vector<double2> lo(256), mid(size_t(1) << (T - 7)), hi(size_t(1) << (L - T + 1));
+        for (uint64_t j = 0; j < lo.size(); ++j) lo[j] = diag_part(m, j, 0, 8, 0, 7);
+        for (uint64_t j = 0; j < mid.size(); ++j) mid[j] = diag_part(m, j << 7, 8, T, 7, T - 1);
+        for (uint64_t j = 0; j < hi.size(); ++j) hi[j] = diag_part(m, j << (T - 1), T, L, T - 1, L - 1);
+        ED_TRY(upload(&m->d_diag_lo, lo));
+        ED_TRY(upload(&m->d_diag_mid, mid));
+        ED_TRY(upload(&m->d_diag_hi, hi));
+    }
+    return ED_OK;
+}
+
+// Fold the rule terms into per-bit operators and classify them.
+ed_status fold_model(const ed_model_desc* desc, ed_model* m) {
+    const int L = desc->L;
+    m->L = L;
+    m->site.assign(size_t(4) * L, c2(0, 0));
+    m->bond.assign(size_t(16) * (L - 1), c2(0, 0));
+    for (int z = 0; z < desc->n_site; ++z) {
+        for (int k = 1; k <= L; ++k) {
+            const double c = desc->site_coef[size_t(z) * L + (k - 1)];
+            if (c == 0.0) continue;
+            const int p = L - k;
+            for (int e = 0; e < 4; ++e) {
+                const ed_c64 o = desc->site_op[size_t(z) * 4 + e];
+                m->site[4 * p + e].x += c * o.re;
+                m->site[4 * p + e].y += c * o.im;
+            }
+        }
+    }
+    for (int z = 0; z < desc->n_bond; ++z) {
+        for (int k = 1; k <= L - 1; ++k) {
+            const double c = desc->bond_coef[size_t(z) * (L - 1) + (k - 1)];
+            if (c == 0.0) continue;
+            const int p = L - k - 1;  // bits (p, p+1) = sites (k+1, k); local index 2*i_k + i_{k+1}
+            for (int e = 0; e < 16; ++e) {
+                const ed_c64 o = desc->bond_op[size_t(z) * 16 + e];
+                m->bond[16 * p + e].x += c * o.re;
+                m->bond[16 * p + e].y += c * o.im;
+            }
+        }
+    }
+    unsigned cls = kOffReal | kDiagReal;
+    for (int p = 0; p < L; ++p) {
+        for (int e = 0; e < 4; ++e) {
+            const double2 v = m->site[4 * p + e];
+            const bool diag = (e == 0 || e == 3);
+            if (v.x == 0.0 && v.y == 0.0) continue;
+            if (!diag) cls |= kSiteOff;
+            if (v.y != 0.0) cls &= diag ? ~unsigned(kDiagReal) : ~unsigned(kOffReal);
+        }
+    }
+    for (int p = 0; p + 1 < L; ++p) {
+        for (int r = 0; r < 4; ++r) {
+            for (int cc = 0; cc < 4; ++cc) {
+                const double2 v = m->bond[16 * p + 4 * r + cc];
+                if (v.x == 0.0 && v.y == 0.0) continue;
+                const int f = r ^ cc;
+                if (f == 1 || f == 2) cls |= kBondSingle;
+                if (f == 3) cls |= kBondDouble;
+                if (v.y != 0.0) cls &= (f == 0) ? ~unsigned(kDiagReal) : ~unsigned(kOffReal);
+            }
+        }
+    }
+    m->op_class = cls;
+    plan_passes(m);
+    return ED_OK;
+}
+
+ed_status validate_desc(const ed_model_desc* desc) {
+    if (!desc) return fail(ED_ERR_ARG, "desc is null");
+    if (desc->d != 2) return fail(ED_ERR_UNSUPPORTED, "only d = 2 is supported");
+    if (desc->L < 2 || desc->L > 30) return fail(ED_ERR_UNSUPPORTED, "L must be in [2, 30]");
+    if (desc->n_site < 0 || desc->n_bond < 0) return fail(ED_ERR_ARG, "negative term count");
+    if (desc->n_site > 0 && (!desc->site_op || !desc->site_coef))
+        return fail(ED_ERR_ARG, "site_op/site_coef is null with n_site > 0");
+    if (desc->n_bond > 0 && (!desc->bond_op || !desc->bond_coef))
+        return fail(ED_ERR_ARG, "bond_op/bond_coef is null with n_bond > 0");
+    for (int z = 0; z < desc->n_site; ++z) {
+        for (int e = 0; e < 4; ++e) {
+            const ed_c64 o = desc->site_op[4 * z + e];
+            if (!std::isfinite(o.re) || !std::isfinite(o.im)) return fail(ED_ERR_NUMERIC, "non-finite site_op");
+        }
+        for (int k = 0; k < desc->L; ++k)
+            if (!std::isfinite(desc->site_coef[size_t(z) * desc->L + k])) return fail(ED_ERR_NUMERIC, "non-finite site_coef");
+    }
+    for (int z = 0; z < desc->n_bond; ++z) {
+        for (int e = 0; e < 16; ++e) {
+            const ed_c64 o = desc->bond_op[16 * z + e];
+            if (!std::isfinite(o.re) || !std::isfinite(o.im)) return fail(ED_ERR_NUMERIC, "non-finite bond_op");
+        }
+        for (int k = 0; k < desc->L - 1; ++k)
+            if (!std::isfinite(desc->bond_coef[size_t(z) * (desc->L - 1) + k])) return fail(ED_ERR_NUMERIC, "non-finite bond_coef");
+    }
+    return ED_OK;
+}
+
+ed_status create_model(const ed_model_desc* desc, ed_model** out) {
+    ED_TRY(validate_desc(desc));
+    ed_model* m = new (std::nothrow) ed_model();
+    if (!m) return fail(ED_ERR_NOMEM, "host allocation failed");
+    ed_status st = fold_model(desc, m);
+    if (st == ED_OK) st = require_device(&m->device);
+    if (st == ED_OK) st = build_device_tables(m);
+    if (st != ED_OK) {
+        free_tables(m);
+        delete m;
+        return st;
+    }
+    *out = m;
+    return ED_OK;
+}
+
+void destroy_model(ed_model* m) {
+    if (!m) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(m->device);
+    free_tables(m);
+    (void)hipSetDevice(cur);
+    delete m;
+}
+
+}  // namespace ed
+
+extern "C" {
+
+const char* ed_last_error(void) { return ed::g_last_error.c_str(); }
+
+const char* ed_version(void) { return "libed 0.1 (gfx950)"; }
+
+ed_status ed_model_create(const ed_model_desc* desc, ed_model** out) {
+    if (!out) return ed::fail(ED_ERR_ARG, "out is null");
+    *out = nullptr;
+    return ed::create_model(desc, out);
+}
+
+ed_status ed_model_destroy(ed_model* model) {
+    ed::destroy_model(model);
+    return ED_OK;
+}
+
+ed_status ed_model_dims(const ed_model* model, int* L, int64_t* D) {
+    if (!model) return ed::fail(ED_ERR_ARG, "model is null");
+    if (L) *L = model->L;
+    if (D) *D = int64_t(1) << model->L;
+    return ED_OK;
+}
+
+ed_status ed_model_passes(const ed_model* model, int* passes) {
+    if (!model || !passes) return ed::fail(ED_ERR_ARG, "null argument");
+    *passes = model->n_pass;
+    return ED_OK;
+}
+
+ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void* stream) {
+    if (!model || !psi || !out) return ed::fail(ED_ERR_ARG, "null argument");
+    const int64_t D = int64_t(1) << model->L;
+    const char* a = reinterpret_cast<const char*>(psi);
+    const char* b = reinterpret_cast<const char*>(out);
+    if (a < b + D * 16 && b < a + D * 16) return ed::fail(ED_ERR_ARG, "psi and out overlap");
+    return ed::launch_apply_H(model, reinterpret_cast<const double2*>(psi), reinterpret_cast<double2*>(out),
+                              static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

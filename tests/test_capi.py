@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every symbol that
+include/ed.h declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1802_10052_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ed.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ed_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(_lib.LIB_PATH)
+    syms = declared_symbols()
+    assert "ed_apply_H" in syms and len(syms) >= 7
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def _desc(L=4, d=2, n_site=1, n_bond=1, null_ops=False):
+    so = np.zeros((n_site, 2, 2), np.complex128)
+    sc = np.ones((n_site, L))
+    bo = np.zeros((n_bond, 4, 4), np.complex128)
+    bc = np.ones((n_bond, max(L - 1, 1)))
+    keep = (so, sc, bo, bc)
+    d_ = _lib.ModelDescC(L, d, n_site, None if null_ops else so.ctypes.data, sc.ctypes.data,
+                         n_bond, bo.ctypes.data, bc.ctypes.data)
+    return d_, keep
+
+
+def test_model_create_argument_errors():
+    lib = _lib.lib()
+    h = C.c_void_p()
+    assert lib.ed_model_create(None, C.byref(h)) == -1
+    d, keep = _desc(d=3)
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -2
+    d, keep = _desc(L=31)
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -2
+    d, keep = _desc(L=1)
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -2
+    d, keep = _desc(null_ops=True)
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -1
+    assert b"null" in lib.ed_last_error()
+    d, keep = _desc()
+    keep[1][0, 0] = np.nan
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -8
+
+
+def test_apply_rejects_null_arguments():
+    lib = _lib.lib()
+    assert lib.ed_apply_H(None, None, None, None) == -1
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU may be visible")
+def test_model_create_without_device_reports_nodevice():
+    lib = _lib.lib()
+    d, keep = _desc()
+    h = C.c_void_p()
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -3

@@ -1,0 +1,77 @@
+"""GPU parity of ed_apply_H against the oracle's explicit sparse H (Sec. III.C, Eq. ed:eq:OKrylov).
+
+Relative 2-norm error <= 1e-13: both sides sum at most 3L+1 products per entry in float64, so
+the rounding difference is a few ulp of the largest term."""
+import numpy as np
+import pytest
+import torch
+
+import edinputs as E
+import paper_1802_10052_amd as P
+from oracle import hamiltonian as OH
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def models(L):
+    return {
+        "tfim": E.tfim(L, 0.5),
+        "xxz": E.xxz(L, 1.0, 0.5, E.random_fields(L, 2)),
+        "generic": E.random_model(L, seed=40 + L, hermitian=False),
+        "xxz_decay": E.ModelDesc(L, site_ops=[E.SZ, -0.5j * E.NUP], site_coef=np.stack([E.random_fields(L, 3), np.full(L, 0.1)]),
+                                 bond_ops=[E.SXSX, E.SYSY, E.SZSZ], bond_coef=np.ones((3, L - 1))),
+    }
+
+
+def to_dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 8, 11, 12, 13, 14, 15, 17, 20, 21])
+@pytest.mark.parametrize("kind", ["tfim", "xxz", "generic", "xxz_decay"])
+def test_apply_H_parity(L, kind):
+    print(f"apply_H parity L={L} kind={kind}", flush=True)
+    desc = models(L)[kind]
+    psi = E.random_state(L, 11)
+    ref = OH.apply_H(desc, psi)
+    m = P.Model(desc)
+    out = P.apply_H(m, to_dev(psi))
+    got = out.cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 1e-13, (L, kind, err, m.passes)
+
+
+@pytest.mark.parametrize("L,kind", [(26, "tfim"), (26, "xxz"), (26, "generic")])
+def test_apply_H_sampled_entries_large(L, kind):
+    print(f"apply_H sampled L={L} kind={kind}", flush=True)
+    desc = models(L)[kind]
+    psi = E.random_state(L, 11)
+    m = P.Model(desc)
+    out = P.apply_H(m, to_dev(psi)).cpu().numpy()
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([rng.integers(0, 1 << L, 4000), [0, (1 << L) - 1, 1 << (L - 1), (1 << 12) - 1, 1 << 12]])
+    ref = OH.apply_H_entries(desc, psi, xs)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(out[xs] - ref)) < 1e-13 * scale * L
+
+
+def test_apply_H_hermitian_property_large():
+    """<phi|H psi> = conj(<psi|H phi>) for Hermitian H at L = 26 (holds at any size)."""
+    L = 26
+    desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
+    m = P.Model(desc)
+    phi = to_dev(E.random_state(L, 21))
+    psi = to_dev(E.random_state(L, 22))
+    a = torch.vdot(phi, P.apply_H(m, psi)).item()
+    b = torch.vdot(psi, P.apply_H(m, phi)).item()
+    assert abs(a - b.conjugate()) < 1e-11
+
+
+def test_apply_H_deterministic():
+    L = 20
+    m = P.Model(E.random_model(L, seed=3))
+    psi = to_dev(E.random_state(L, 1))
+    a = P.apply_H(m, psi)
+    b = P.apply_H(m, psi)
+    assert torch.equal(a, b)

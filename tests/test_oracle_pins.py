@@ -169,3 +169,11 @@ def test_philox_stream_matches_definition():
     d = PhiloxDraws(seed=0, traj_id=0)
     u = [d.uniform() for _ in range(1000)]
     assert min(u) > 0 and max(u) <= 1
+
+
+def test_apply_H_entries_matches_sparse():
+    for desc in (E.random_model(7, seed=3, hermitian=False), E.tfim(9, 0.7), E.xxz(8, 1.0, 0.5, E.random_fields(8, 1))):
+        psi = E.random_state(desc.L, 2)
+        y = OH.apply_H(desc, psi)
+        xs = np.arange(1 << desc.L)
+        assert np.max(np.abs(OH.apply_H_entries(desc, psi, xs) - y)) < 1e-13
