@@ -96,6 +96,104 @@ ed_status ed_model_passes(const ed_model* model, int* passes);
  * ---------------------------------------------------------------------------------------- */
 ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void* stream);
 
+
+/* ----------------------------------------------------------------------------------------
+ * Workspace. Iterative calls take a caller-owned device workspace (ws, ws_bytes) whose size
+ * comes from the matching *_workspace query; the library allocates nothing on these paths.
+ * A workspace smaller than the query returns ED_ERR_WORKSPACE.
+ * ---------------------------------------------------------------------------------------- */
+
+/* ----------------------------------------------------------------------------------------
+ * ed_lanczos_ground: lowest eigenpair of a Hermitian model, matrix-free. The paper obtains the
+ * ground state from the full H with eigh/eigsh (Sec. II, statics); here the same Lanczos
+ * recurrence that underlies the Krylov step (Sec. III.C) runs on H psi directly:
+ *   v_1 = v0/|v0|; w = H v_j; w is orthogonalised against every stored v_i by classical
+ *   Gram-Schmidt applied twice; beta_j = |w|; T = V^H H V is the projected matrix.
+ *   When the basis reaches max_basis vectors it is restarted thick (Wu & Simon): the n_keep
+ *   lowest Ritz vectors and the last residual vector are kept and the recurrence continues.
+ *   Convergence: beta_j |s_j| <= tol for the lowest Ritz pair (theta, s) (the residual norm
+ *   |H psi - theta psi| of the unit Ritz vector), or an invariant subspace (beta_j <= 1e-14 |theta|).
+ * v0      device, D amplitudes, any nonzero vector (not modified)
+ * E0      host, lowest Ritz value; psi0 device, D amplitudes, unit norm (global phase arbitrary)
+ * info    host (may be NULL): iterations (H psi products), restarts, explicit residual
+ *         |H psi0 - E0 psi0| recomputed at the end, converged flag
+ * Returns ED_ERR_NOCONV (with E0, psi0, info filled) if max_iter products were not enough.
+ * Workspace: ed_lanczos_workspace = (max_basis + 1 + n_keep) D complex + scratch.
+ * Limits: 2 <= max_basis <= 512, 0 <= n_keep < max_basis (0 means min(10, max_basis/2)).
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    int max_iter;
+    int max_basis;
+    int n_keep;
+    double tol;
+} ed_lanczos_params;
+
+typedef struct {
+    int iters;
+    int restarts;
+    double residual;
+    int converged;
+} ed_lanczos_info;
+
+ed_status ed_lanczos_workspace(const ed_model* model, const ed_lanczos_params* params, size_t* bytes);
+ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, const ed_lanczos_params* params,
+                            double* E0, ed_c64* psi0, ed_lanczos_info* info, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * ed_krylov_evolve: n_steps Krylov time steps psi(t+dt) = |psi| V_m exp(-i dt T_m) e_1
+ * (Sec. III.C): a new Krylov basis of the current state every step, xi_i = [exp(-i dt T_m)]_{i,1}.
+ * hermitian = 1: Lanczos, T_m real symmetric tridiagonal (closed systems);
+ * hermitian = 0: Arnoldi, T_m upper Hessenberg (non-Hermitian generators, Sec. VI.B).
+ * Stopping (the paper names a tolerance and a maximal basis size): the a-posteriori estimate
+ * |psi| beta_m |[exp(-i dt T_m)]_{m,1}| <= tol, an invariant subspace (beta_m <= 1e-14 |T_m|), or
+ * m = m_max. fixed_m > 0 forces exactly min(fixed_m, m_max) vectors unless the space is invariant.
+ * reorth = 1 orthogonalises every new vector against the whole basis (twice); reorth = 0 against
+ * the previous two (the three-term recurrence with local re-projection; Hermitian only).
+ * psi     device, D amplitudes, in place: psi(0) on entry, psi(n_steps dt) on exit; no
+ *         renormalisation (the norm drift is measured).
+ * obs     host arrays, each may be NULL: sz[(n_steps+1) * L] = <sigma^z_k>/<psi|psi> for sites
+ *         k = 1..L at t = 0, dt, ..., energy[n_steps+1] = <psi|H|psi>/<psi|psi>,
+ *         norm[n_steps+1] = |psi|.
+ * info    host (may be NULL).
+ * Workspace: ed_krylov_workspace = (m_max + 1) D complex + scratch. Limits: 1 <= m_max <= 64.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    int m_max;
+    double tol;
+    int fixed_m;
+    int reorth;
+    int hermitian;
+} ed_krylov_params;
+
+typedef struct {
+    double* sz;
+    double* energy;
+    double* norm;
+} ed_observe;
+
+typedef struct {
+    int steps;
+    int total_m;
+    int max_m;
+    double max_err;
+} ed_krylov_info;
+
+ed_status ed_krylov_workspace(const ed_model* model, const ed_krylov_params* params, size_t* bytes);
+ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double dt, int n_steps,
+                           const ed_krylov_params* params, const ed_observe* obs, ed_krylov_info* info,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * ed_measure: norm and all-site <sigma^z> of a state in one read pass (Sec. IV: the diagonal of
+ * every single-site reduced density matrix). psi device; sz host [L] (site order k = 1..L,
+ * normalised by <psi|psi>), norm host (may be NULL). Synchronises stream.
+ * Workspace: ed_measure_workspace bytes.
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_measure_workspace(int L, size_t* bytes);
+ed_status ed_measure(const ed_c64* psi, int L, double* sz, double* norm, void* ws, size_t ws_bytes,
+                     void* stream);
+
 #ifdef __cplusplus
 }
 #endif

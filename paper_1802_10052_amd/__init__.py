@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import EdError, call, lib
 
-__all__ = ["Model", "apply_H", "EdError", "lib"]
+__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "EdError", "lib"]
 
 
 def _stream_ptr(stream=None):
@@ -81,3 +81,62 @@ def apply_H(model, psi, out=None, stream=None):
     _check_state(out, model.D, "out")
     call("ed_apply_H", model.handle, _dptr(psi), _dptr(out), _stream_ptr(stream))
     return out
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def lanczos_ground(model, v0, tol=1e-10, max_iter=200, max_basis=None, n_keep=0, stream=None):
+    """Lowest eigenpair (E0, psi0, info) of a Hermitian model by matrix-free Lanczos with full
+    reorthogonalisation and thick restart (ed_lanczos_ground). info is a dict."""
+    _check_state(v0, model.D, "v0")
+    mb = max_iter + 1 if max_basis is None else max_basis
+    mb = max(2, min(mb, 512))
+    p = _lib.LanczosParams(int(max_iter), int(mb), int(n_keep), float(tol))
+    nb = C.c_size_t()
+    call("ed_lanczos_workspace", model.handle, C.byref(p), C.byref(nb))
+    ws = _workspace(nb.value, v0.device)
+    psi0 = torch.empty_like(v0)
+    e0 = C.c_double()
+    info = _lib.LanczosInfo()
+    code = lib().ed_lanczos_ground(model.handle, _dptr(v0), C.byref(p), C.byref(e0), _dptr(psi0),
+                                   C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
+    d = {"iters": info.iters, "restarts": info.restarts, "residual": info.residual,
+         "converged": bool(info.converged), "status": _lib.STATUS.get(code, code)}
+    if code not in (0, -7):
+        _lib.check("ed_lanczos_ground", code)
+    return e0.value, psi0, d
+
+
+def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reorth=0, hermitian=True,
+                  observe=True, stream=None):
+    """Krylov time evolution of psi in place (ed_krylov_evolve). Returns (psi, obs, info) with obs
+    holding numpy arrays sz [(n_steps+1), L], energy [n_steps+1], norm [n_steps+1]."""
+    _check_state(psi, model.D)
+    p = _lib.KrylovParams(int(m_max), float(tol), int(fixed_m), int(reorth if hermitian else 1), int(bool(hermitian)))
+    nb = C.c_size_t()
+    call("ed_krylov_workspace", model.handle, C.byref(p), C.byref(nb))
+    ws = _workspace(nb.value, psi.device)
+    obs = None
+    o = None
+    if observe:
+        obs = {"sz": np.zeros((n_steps + 1, model.L)), "energy": np.zeros(n_steps + 1),
+               "norm": np.zeros(n_steps + 1)}
+        o = _lib.Observe(obs["sz"].ctypes.data, obs["energy"].ctypes.data, obs["norm"].ctypes.data)
+    info = _lib.KrylovInfo()
+    call("ed_krylov_evolve", model.handle, _dptr(psi), float(dt), int(n_steps), C.byref(p),
+         C.byref(o) if o is not None else None, C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
+    return psi, obs, {"steps": info.steps, "total_m": info.total_m, "max_m": info.max_m, "max_err": info.max_err}
+
+
+def measure(psi, L, stream=None):
+    """(sz[L], norm) of a device state in one pass (ed_measure)."""
+    _check_state(psi, 1 << L)
+    nb = C.c_size_t()
+    call("ed_measure_workspace", int(L), C.byref(nb))
+    ws = _workspace(nb.value, psi.device)
+    sz = np.zeros(L)
+    nrm = C.c_double()
+    call("ed_measure", _dptr(psi), int(L), sz.ctypes.data, C.byref(nrm), _dptr(ws), nb.value, _stream_ptr(stream))
+    return sz, nrm.value

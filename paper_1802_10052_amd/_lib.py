@@ -26,6 +26,27 @@ class ModelDescC(C.Structure):
                 ("n_bond", C.c_int), ("bond_op", C.c_void_p), ("bond_coef", C.c_void_p)]
 
 
+class LanczosParams(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("max_basis", C.c_int), ("n_keep", C.c_int), ("tol", C.c_double)]
+
+
+class LanczosInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("residual", C.c_double), ("converged", C.c_int)]
+
+
+class KrylovParams(C.Structure):
+    _fields_ = [("m_max", C.c_int), ("tol", C.c_double), ("fixed_m", C.c_int), ("reorth", C.c_int),
+                ("hermitian", C.c_int)]
+
+
+class Observe(C.Structure):
+    _fields_ = [("sz", C.c_void_p), ("energy", C.c_void_p), ("norm", C.c_void_p)]
+
+
+class KrylovInfo(C.Structure):
+    _fields_ = [("steps", C.c_int), ("total_m", C.c_int), ("max_m", C.c_int), ("max_err", C.c_double)]
+
+
 ED_OK = 0
 STATUS = {0: "ED_OK", -1: "ED_ERR_ARG", -2: "ED_ERR_UNSUPPORTED", -3: "ED_ERR_NODEVICE",
           -4: "ED_ERR_NOMEM", -5: "ED_ERR_WORKSPACE", -6: "ED_ERR_HIP", -7: "ED_ERR_NOCONV",
@@ -60,6 +81,15 @@ def _declare(l):
     _fn(l, "ed_model_dims", [P, C.POINTER(C.c_int), C.POINTER(C.c_int64)])
     _fn(l, "ed_model_passes", [P, C.POINTER(C.c_int)])
     _fn(l, "ed_apply_H", [P, P, P, P])
+    S = C.POINTER(C.c_size_t)
+    _fn(l, "ed_lanczos_workspace", [P, C.POINTER(LanczosParams), S])
+    _fn(l, "ed_lanczos_ground", [P, P, C.POINTER(LanczosParams), C.POINTER(C.c_double), P,
+                                 C.POINTER(LanczosInfo), P, C.c_size_t, P])
+    _fn(l, "ed_krylov_workspace", [P, C.POINTER(KrylovParams), S])
+    _fn(l, "ed_krylov_evolve", [P, P, C.c_double, C.c_int, C.POINTER(KrylovParams), C.POINTER(Observe),
+                                C.POINTER(KrylovInfo), P, C.c_size_t, P])
+    _fn(l, "ed_measure_workspace", [C.c_int, S])
+    _fn(l, "ed_measure", [P, C.c_int, P, P, P, C.c_size_t, P])
 
 
 def check(name, code):

@@ -1,0 +1,35 @@
+// Host launchers of the vector kernels (vec.hip). All pointers are device memory; `part` is a
+// scratch area of kRedBlocks * kPartLd complex values taken from the caller's workspace.
+#pragma once
+#include "ed_internal.h"
+
+namespace ed {
+
+constexpr int kRedBlocks = 1024;  // max blocks of a partial reduction
+constexpr int kPartLd = 64;       // complex entries per block row of the partial buffer
+constexpr int kDotGroup = 16;     // basis vectors per dot/axpy launch
+constexpr int kMaxComb = 64;      // max terms of a Krylov combination
+constexpr size_t kPartBytes = size_t(kRedBlocks) * kPartLd * sizeof(double2);
+
+int reduction_blocks(int64_t D);
+// out[i] = <V_i|w>, i < n (V_i = V + i*ldv)
+hipError_t dots(const double2* V, int64_t ldv, int n, const double2* w, int64_t D, double2* out,
+                double2* part, hipStream_t s);
+// w += sign * sum_i coef[i] V_i  (coef device)
+hipError_t axpy_multi(const double2* V, int64_t ldv, int n, const double2* coef, double sign, double2* w,
+                      int64_t D, hipStream_t s);
+// out[0].x = |w|^2
+hipError_t norm2(const double2* w, int64_t D, double2* out, double2* part, hipStream_t s);
+// dst = src / sqrt(nrm2_dev[0].x)
+hipError_t normalize(const double2* src, double2* dst, const double2* nrm2_dev, int64_t D, hipStream_t s);
+// dst = a * src
+hipError_t scale(const double2* src, double2* dst, double2 a, int64_t D, hipStream_t s);
+// y = a x + b y  (complex a, b)
+hipError_t axpby(const double2* x, double2* y, double2 a, double2 b, int64_t D, hipStream_t s);
+// out = sum_i c[i] V_i  (c host; any n); out must not alias any V_i
+hipError_t combination(const double2* V, int64_t ldv, int n, const double2* c, double2* out, int64_t D,
+                       hipStream_t s);
+// out[0].x = |psi|^2, out[1+p].x = sum |psi_x|^2 (1 - 2 bit_p(x))  (p = bit, site L-p)
+hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStream_t s);
+
+}  // namespace ed

@@ -1,0 +1,413 @@
+// Krylov machinery on top of H psi (Sec. III.C): the basis recurrence shared by the Lanczos
+// ground state and the Krylov time step, the thick-restart ground-state driver, the time
+// evolution driver with per-step observables, and the one-pass measurement.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dense.h"
+#include "ed_vec.h"
+#include "krylov_core.h"
+
+namespace ed {
+
+// ------------------------------------------------------------------------ workspace layout
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t core_scratch_bytes() { return align_up(kPartBytes) + align_up(sizeof(double2) * kScalars); }
+
+ed_status carve(void* ws, size_t ws_bytes, int64_t D, int nvec, Workspace* w) {
+    const size_t need = core_scratch_bytes() + align_up(size_t(nvec) * size_t(D) * sizeof(double2));
+    if (!ws) return fail(ED_ERR_ARG, "workspace is null");
+    if (ws_bytes < need)
+        return fail(ED_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes < required " +
+                                          std::to_string(need));
+    char* p = static_cast<char*>(ws);
+    w->part = reinterpret_cast<double2*>(p);
+    p += align_up(kPartBytes);
+    w->scal = reinterpret_cast<double2*>(p);
+    p += align_up(sizeof(double2) * kScalars);
+    w->V = reinterpret_cast<double2*>(p);
+    w->nvec = nvec;
+    w->D = D;
+    return ED_OK;
+}
+
+// Pinned host staging buffer for the per-iteration scalars (allocated once per thread).
+double2* host_stage() {
+    static thread_local double2* buf = nullptr;
+    if (!buf) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&buf), sizeof(double2) * kScalars) != hipSuccess) buf = nullptr;
+    }
+    return buf;
+}
+
+ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s) {
+    double2* st = host_stage();
+    if (!st) return fail(ED_ERR_NOMEM, "pinned host buffer");
+    ED_HIP_TRY(hipMemcpyAsync(st, dev, sizeof(double2) * n, hipMemcpyDeviceToHost, s));
+    ED_HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(host, st, sizeof(double2) * n);
+    return ED_OK;
+}
+
+#define ED_K(expr)                                                                           \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess) return fail(ED_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// One step of the recurrence: w = H V_j into V_{j+1}, orthogonalised against V_lo..V_j
+// (passes = 1 or 2 classical Gram-Schmidt sweeps). Returns the projections h[0..j-lo] and the
+// norm beta of the orthogonalised w. V_{j+1} is normalised unless beta is below `tiny`.
+ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
+                      cplx* h, double* beta, bool* breakdown, hipStream_t s) {
+    const int64_t D = w.D;
+    double2* Vj = w.V + int64_t(j) * D;
+    double2* Wn = w.V + int64_t(j + 1) * D;
+    const int n = j - lo + 1;
+    if (n > kMaxProj) return fail(ED_ERR_UNSUPPORTED, "too many projections");
+    ED_TRY(launch_apply_H(m, Vj, Wn, s));
+    double2* nr = w.scal + kNrm;
+    double2* h1 = w.scal + 1;
+    double2* h2 = w.scal + 1 + n;
+    const double2* Vlo = w.V + int64_t(lo) * D;
+    ED_K(dots(Vlo, D, n, Wn, D, h1, w.part, s));
+    ED_K(axpy_multi(Vlo, D, n, h1, -1.0, Wn, D, s));
+    if (passes > 1) {
+        ED_K(dots(Vlo, D, n, Wn, D, h2, w.part, s));
+        ED_K(axpy_multi(Vlo, D, n, h2, -1.0, Wn, D, s));
+    }
+    ED_K(norm2(Wn, D, nr, w.part, s));
+    std::vector<double2> hs(1 + 2 * n);
+    ED_TRY(fetch_scalars(w.scal, passes > 1 ? 1 + 2 * n : 1 + n, hs.data(), s));
+    for (int i = 0; i < n; ++i) {
+        h[i] = cplx(hs[1 + i].x, hs[1 + i].y);
+        if (passes > 1) h[i] += cplx(hs[1 + n + i].x, hs[1 + n + i].y);
+    }
+    const double nrm2v = hs[kNrm].x;
+    if (!std::isfinite(nrm2v)) return fail(ED_ERR_NUMERIC, "non-finite value in the Krylov recurrence");
+    *beta = std::sqrt(std::max(nrm2v, 0.0));
+    double scale = 0.0;
+    for (int i = 0; i < n; ++i) scale = std::max(scale, std::abs(h[i]));
+    *breakdown = (*beta <= tiny_rel * std::max(scale, 1e-300)) || *beta == 0.0;
+    if (!*breakdown) ED_K(normalize(Wn, Wn, nr, D, s));
+    return ED_OK;
+}
+
+// V_0 = psi / |psi|; returns |psi|.
+ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s) {
+    double2* nr = w.scal + kNrm;
+    ED_K(norm2(psi, w.D, nr, w.part, s));
+    double2 hv[1];
+    ED_TRY(fetch_scalars(w.scal, 1, hv, s));
+    const double n2 = hv[kNrm].x;
+    if (!std::isfinite(n2)) return fail(ED_ERR_NUMERIC, "non-finite start vector");
+    if (n2 <= 0.0) return fail(ED_ERR_ARG, "start vector is zero");
+    *nrm = std::sqrt(n2);
+    ED_K(normalize(psi, w.V, nr, w.D, s));
+    return ED_OK;
+}
+
+}  // namespace ed
+
+using namespace ed;
+
+// ============================================================================ Lanczos ground
+extern "C" ed_status ed_lanczos_workspace(const ed_model* model, const ed_lanczos_params* p, size_t* bytes) {
+    if (!model || !p || !bytes) return fail(ED_ERR_ARG, "null argument");
+    if (p->max_basis < 2 || p->max_basis > 512) return fail(ED_ERR_ARG, "max_basis must be in [2, 512]");
+    const int keep = p->n_keep > 0 ? p->n_keep : std::min(10, p->max_basis / 2);
+    if (keep >= p->max_basis) return fail(ED_ERR_ARG, "n_keep must be < max_basis");
+    const int64_t D = int64_t(1) << model->L;
+    *bytes = core_scratch_bytes() + ((size_t(p->max_basis + 1 + keep) * size_t(D) * sizeof(double2) + 255) & ~size_t(255));
+    return ED_OK;
+}
+
+extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, const ed_lanczos_params* p,
+                                       double* E0, ed_c64* psi0, ed_lanczos_info* info, void* ws,
+                                       size_t ws_bytes, void* stream) {
+    if (!model || !v0 || !p || !E0 || !psi0) return fail(ED_ERR_ARG, "null argument");
+    if (p->max_iter < 1) return fail(ED_ERR_ARG, "max_iter must be >= 1");
+    if (!(p->tol > 0.0)) return fail(ED_ERR_ARG, "tol must be > 0");
+    size_t need = 0;
+    ED_TRY(ed_lanczos_workspace(model, p, &need));
+    const int mb = p->max_basis;
+    const int keep = p->n_keep > 0 ? p->n_keep : std::min(10, mb / 2);
+    const int64_t D = int64_t(1) << model->L;
+    Workspace w;
+    ED_TRY(carve(ws, ws_bytes, D, mb + 1 + keep, &w));
+    if (ws_bytes < need) return fail(ED_ERR_WORKSPACE, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    double nrm0 = 0.0;
+    ED_TRY(start_vector(w, reinterpret_cast<const double2*>(v0), &nrm0, s));
+
+    std::vector<double> T(size_t(mb + 1) * (mb + 1), 0.0);
+    auto Tij = [&](int i, int j) -> double& { return T[size_t(i) * (mb + 1) + j]; };
+    std::vector<cplx> h(mb + 1);
+    int j = 0, iters = 0, restarts = 0, k_locked = 0;
+    bool converged = false;
+    double theta = 0.0;
+    std::vector<double> svec;
+    int m = 0;
+    ed_status result = ED_OK;
+    while (true) {
+        double beta = 0.0;
+        bool brk = false;
+        ED_TRY(krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s));
+        ++iters;
+        for (int i = 0; i <= j; ++i) {
+            Tij(i, j) = h[i].real();
+            Tij(j, i) = h[i].real();
+        }
+        m = j + 1;
+        // lowest Ritz pair of the m x m projected matrix
+        svec.assign(m, 0.0);
+        if (restarts == 0) {
+            std::vector<double> a(m), b(std::max(m - 1, 1));
+            for (int i = 0; i < m; ++i) a[i] = Tij(i, i);
+            for (int i = 0; i + 1 < m; ++i) b[i] = Tij(i + 1, i);
+            tridiag_lowest(m, a.data(), b.data(), &theta, svec.data());
+        } else {
+            std::vector<double> A(size_t(m) * m), wv(m), Z(size_t(m) * m);
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < m; ++c) A[size_t(r) * m + c] = Tij(r, c);
+            sym_eig_jacobi(m, A.data(), wv.data(), Z.data());
+            theta = wv[0];
+            for (int r = 0; r < m; ++r) svec[r] = Z[size_t(r) * m];
+        }
+        const double res = beta * std::fabs(svec[m - 1]);
+        if (brk || res <= p->tol) {
+            converged = true;
+            break;
+        }
+        if (iters >= p->max_iter) {
+            result = fail(ED_ERR_NOCONV, "Lanczos did not reach the tolerance within max_iter products");
+            break;
+        }
+        Tij(j + 1, j) = beta;
+        Tij(j, j + 1) = beta;
+        if (m == mb) {
+            // thick restart: keep the `keep` lowest Ritz vectors plus the residual direction V_m
+            std::vector<double> A(size_t(m) * m), wv(m), Z(size_t(m) * m);
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < m; ++c) A[size_t(r) * m + c] = Tij(r, c);
+            sym_eig_jacobi(m, A.data(), wv.data(), Z.data());
+            double2* tmp = w.V + int64_t(mb + 1) * D;
+            for (int i = 0; i < keep; ++i) {
+                std::vector<double2> c(m);
+                for (int r = 0; r < m; ++r) c[r] = make_double2(Z[size_t(r) * m + i], 0.0);
+                ED_K(combination(w.V, D, m, c.data(), tmp + int64_t(i) * D, D, s));
+            }
+            ED_HIP_TRY(hipMemcpyAsync(w.V, tmp, size_t(keep) * D * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            ED_HIP_TRY(hipMemcpyAsync(w.V + int64_t(keep) * D, w.V + int64_t(m) * D, D * sizeof(double2),
+                                      hipMemcpyDeviceToDevice, s));
+            std::fill(T.begin(), T.end(), 0.0);
+            for (int i = 0; i < keep; ++i) {
+                Tij(i, i) = wv[i];
+                Tij(i, keep) = beta * Z[size_t(m - 1) * m + i];
+                Tij(keep, i) = Tij(i, keep);
+            }
+            j = keep;
+            k_locked = keep;
+            ++restarts;
+            continue;
+        }
+        ++j;
+    }
+    (void)k_locked;
+    // Ritz vector psi0 = V s (unit norm up to rounding; renormalise explicitly)
+    std::vector<double2> c(m);
+    for (int r = 0; r < m; ++r) c[r] = make_double2(svec[r], 0.0);
+    double2* out = reinterpret_cast<double2*>(psi0);
+    ED_K(combination(w.V, D, m, c.data(), out, D, s));
+    double2* nr = w.scal + kNrm;
+    ED_K(norm2(out, D, nr, w.part, s));
+    ED_K(normalize(out, out, nr, D, s));
+    // explicit residual |H psi0 - theta psi0|
+    double2* r = w.V;  // basis no longer needed
+    ED_TRY(launch_apply_H(model, out, r, s));
+    ED_K(axpby(out, r, make_double2(-theta, 0.0), make_double2(1.0, 0.0), D, s));
+    ED_K(norm2(r, D, nr, w.part, s));
+    double2 hv[1];
+    ED_TRY(fetch_scalars(w.scal, 1, hv, s));
+    *E0 = theta;
+    if (info) {
+        info->iters = iters;
+        info->restarts = restarts;
+        info->residual = std::sqrt(std::max(hv[kNrm].x, 0.0));
+        info->converged = converged ? 1 : 0;
+    }
+    return result;
+}
+
+// ============================================================================ Krylov evolve
+extern "C" ed_status ed_krylov_workspace(const ed_model* model, const ed_krylov_params* p, size_t* bytes) {
+    if (!model || !p || !bytes) return fail(ED_ERR_ARG, "null argument");
+    if (p->m_max < 1 || p->m_max > kMaxProj - 1) return fail(ED_ERR_ARG, "m_max must be in [1, 64]");
+    const int64_t D = int64_t(1) << model->L;
+    *bytes = core_scratch_bytes() + ((size_t(p->m_max + 1) * size_t(D) * sizeof(double2) + 255) & ~size_t(255));
+    return ED_OK;
+}
+
+namespace ed {
+
+// Observables of psi: sz (site order) normalised, and |psi|. sz may be null.
+ed_status measure_state(const double2* psi, int L, const Workspace& w, double* sz, double* nrm, hipStream_t s) {
+    double2* res = w.scal + kObs;
+    ED_K(sz_all(psi, L, res, w.part, s));
+    double2 hv[32];
+    ED_TRY(fetch_scalars(res, L + 1, hv, s));
+    const double n2 = hv[0].x;
+    if (nrm) *nrm = std::sqrt(std::max(n2, 0.0));
+    if (sz)
+        for (int k = 1; k <= L; ++k) sz[k - 1] = hv[1 + (L - k)].x / n2;
+    return ED_OK;
+}
+
+// One Krylov time step of psi in place: returns the dimension used, the error estimate and
+// alpha_0 = <v_0|H v_0> (the energy of the incoming state).
+ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, double dt,
+                           const ed_krylov_params* p, int* m_used, double* err_out, double* e_in,
+                           double* nrm_in, hipStream_t s) {
+    const int mmax = p->m_max;
+    double nrm0 = 0.0;
+    ED_TRY(start_vector(w, psi, &nrm0, s));
+    std::vector<cplx> T(size_t(mmax + 1) * (mmax + 1), 0.0);
+    auto Tij = [&](int i, int j) -> cplx& { return T[size_t(i) * (mmax + 1) + j]; };
+    std::vector<cplx> h(mmax + 1), u(mmax + 1);
+    const bool herm = p->hermitian != 0;
+    const int passes = (p->reorth || !herm) ? 2 : 1;
+    int mm = 0;
+    double err = 0.0;
+    for (int j = 0; j < mmax; ++j) {
+        const int lo = (herm && !p->reorth) ? std::max(j - 1, 0) : 0;
+        double beta = 0.0;
+        bool brk = false;
+        ED_TRY(krylov_step(m, w, j, lo, passes, 1e-14, h.data(), &beta, &brk, s));
+        if (herm) {
+            Tij(j, j) = h[j - lo].real();
+        } else {
+            for (int i = 0; i <= j; ++i) Tij(i, j) = h[i];
+        }
+        mm = j + 1;
+        // u = exp(-i dt T_m) e_1
+        if (herm) {
+            std::vector<double> d(mm), e(mm), Z(size_t(mm) * mm, 0.0);
+            for (int i = 0; i < mm; ++i) {
+                d[i] = Tij(i, i).real();
+                e[i] = (i + 1 < mm) ? Tij(i + 1, i).real() : 0.0;
+                Z[size_t(i) * mm + i] = 1.0;
+            }
+            if (!tridiag_ql(mm, d.data(), e.data(), Z.data())) return fail(ED_ERR_NUMERIC, "tridiagonal QL failed");
+            expm_col_sym(mm, d.data(), Z.data(), dt, u.data());
+        } else {
+            std::vector<cplx> A(size_t(mm) * mm), E(size_t(mm) * mm);
+            for (int r = 0; r < mm; ++r)
+                for (int c = 0; c < mm; ++c) A[size_t(r) * mm + c] = cplx(0.0, -dt) * Tij(r, c);
+            expm_complex(mm, A.data(), E.data());
+            for (int r = 0; r < mm; ++r) u[r] = E[size_t(r) * mm];
+        }
+        err = nrm0 * beta * std::abs(u[mm - 1]);
+        if (j == 0 && e_in) *e_in = Tij(0, 0).real();
+        bool stop;
+        if (p->fixed_m > 0) stop = brk || mm >= std::min(p->fixed_m, mmax);
+        else stop = brk || err <= p->tol || mm >= mmax;
+        if (brk) err = 0.0;
+        if (stop) break;
+        Tij(j + 1, j) = beta;
+        if (herm) Tij(j, j + 1) = beta;
+    }
+    std::vector<double2> c(mm);
+    for (int i = 0; i < mm; ++i) c[i] = make_double2(nrm0 * u[i].real(), nrm0 * u[i].imag());
+    ED_K(combination(w.V, w.D, mm, c.data(), psi, w.D, s));
+    *m_used = mm;
+    *err_out = err;
+    if (nrm_in) *nrm_in = nrm0;
+    return ED_OK;
+}
+
+// <psi|H|psi>/<psi|psi> using V_0, V_1 of the workspace as scratch
+ed_status energy_of(const ed_model* m, const Workspace& w, const double2* psi, double* e, hipStream_t s) {
+    double nrm0 = 0.0;
+    ED_TRY(start_vector(w, psi, &nrm0, s));
+    double2* Hv = w.V + w.D;
+    ED_TRY(launch_apply_H(m, w.V, Hv, s));
+    ED_K(dots(w.V, w.D, 1, Hv, w.D, w.scal + 1, w.part, s));
+    double2 hv[2];
+    ED_TRY(fetch_scalars(w.scal, 2, hv, s));
+    *e = hv[1].x;
+    return ED_OK;
+}
+
+}  // namespace ed
+
+extern "C" ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double dt, int n_steps,
+                                      const ed_krylov_params* p, const ed_observe* obs, ed_krylov_info* info,
+                                      void* ws, size_t ws_bytes, void* stream) {
+    if (!model || !psi || !p) return fail(ED_ERR_ARG, "null argument");
+    if (n_steps < 0) return fail(ED_ERR_ARG, "n_steps must be >= 0");
+    if (!std::isfinite(dt)) return fail(ED_ERR_ARG, "dt must be finite");
+    if (!(p->tol > 0.0) && p->fixed_m <= 0) return fail(ED_ERR_ARG, "tol must be > 0");
+    if (!p->hermitian && !p->reorth) return fail(ED_ERR_ARG, "Arnoldi (hermitian = 0) needs reorth = 1");
+    size_t need = 0;
+    ED_TRY(ed_krylov_workspace(model, p, &need));
+    if (ws_bytes < need) return fail(ED_ERR_WORKSPACE, "workspace too small");
+    const int L = model->L;
+    const int64_t D = int64_t(1) << L;
+    Workspace w;
+    ED_TRY(carve(ws, ws_bytes, D, p->m_max + 1, &w));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2* v = reinterpret_cast<double2*>(psi);
+    int total_m = 0, max_m = 0;
+    double max_err = 0.0;
+    const bool want_e = obs && obs->energy;
+    auto record = [&](int step) -> ed_status {
+        if (!obs || (!obs->sz && !obs->norm)) return ED_OK;
+        double nrm = 0.0;
+        ED_TRY(measure_state(v, L, w, obs->sz ? obs->sz + size_t(step) * L : nullptr, &nrm, s));
+        if (obs->norm) obs->norm[step] = nrm;
+        return ED_OK;
+    };
+    ED_TRY(record(0));
+    for (int st = 0; st < n_steps; ++st) {
+        int mu = 0;
+        double err = 0.0, e_in = 0.0, n_in = 0.0;
+        ED_TRY(krylov_time_step(model, w, v, dt, p, &mu, &err, &e_in, &n_in, s));
+        if (want_e) obs->energy[st] = e_in;
+        total_m += mu;
+        max_m = std::max(max_m, mu);
+        max_err = std::max(max_err, err);
+        ED_TRY(record(st + 1));
+    }
+    if (want_e) {
+        double e = 0.0;
+        ED_TRY(energy_of(model, w, v, &e, s));
+        obs->energy[n_steps] = e;
+    }
+    ED_HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->steps = n_steps;
+        info->total_m = total_m;
+        info->max_m = max_m;
+        info->max_err = max_err;
+    }
+    return ED_OK;
+}
+
+// ============================================================================ measurement
+extern "C" ed_status ed_measure_workspace(int L, size_t* bytes) {
+    if (!bytes || L < 1 || L > 30) return fail(ED_ERR_ARG, "bad argument");
+    *bytes = core_scratch_bytes();
+    return ED_OK;
+}
+
+extern "C" ed_status ed_measure(const ed_c64* psi, int L, double* sz, double* norm, void* ws, size_t ws_bytes,
+                                void* stream) {
+    if (!psi || !sz || L < 1 || L > 30) return fail(ED_ERR_ARG, "bad argument");
+    Workspace w;
+    ED_TRY(carve(ws, ws_bytes, int64_t(1) << L, 0, &w));
+    return measure_state(reinterpret_cast<const double2*>(psi), L, w, sz, norm, static_cast<hipStream_t>(stream));
+}

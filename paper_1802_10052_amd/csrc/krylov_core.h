@@ -1,0 +1,35 @@
+// Shared Krylov recurrence (krylov.cpp) used by the ground-state, time-evolution, trajectory and
+// adjoint drivers.
+#pragma once
+#include "dense.h"
+#include "ed_internal.h"
+
+namespace ed {
+
+constexpr int kMaxProj = 520;                  // max vectors one step projects against
+constexpr int kNrm = 0;                        // scalar area: [norm^2, h1[n], h2[n] ... | obs]
+constexpr int kObs = 1 + 2 * kMaxProj;
+constexpr int kScalars = kObs + 64;
+
+// Caller workspace carved into: partial-reduction buffer, device scalars, nvec vectors of D.
+struct Workspace {
+    double2* part = nullptr;
+    double2* scal = nullptr;
+    double2* V = nullptr;
+    int nvec = 0;
+    int64_t D = 0;
+};
+
+size_t core_scratch_bytes();
+ed_status carve(void* ws, size_t ws_bytes, int64_t D, int nvec, Workspace* w);
+ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s);
+ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
+                      cplx* h, double* beta, bool* breakdown, hipStream_t s);
+ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s);
+ed_status measure_state(const double2* psi, int L, const Workspace& w, double* sz, double* nrm, hipStream_t s);
+ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, double dt,
+                           const ed_krylov_params* p, int* m_used, double* err_out, double* e_in,
+                           double* nrm_in, hipStream_t s);
+ed_status energy_of(const ed_model* m, const Workspace& w, const double2* psi, double* e, hipStream_t s);
+
+}  // namespace ed

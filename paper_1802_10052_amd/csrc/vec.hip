@@ -1,0 +1,310 @@
+// Vector kernels of the Krylov methods (Sec. III.C and Sec. II statics, computed matrix-free):
+// deterministic dot products against several basis vectors at once, the matching multi-axpy,
+// norm + scaling, the Krylov combination psi = sum_i c_i v_i, and the all-site <sigma^z>
+// reduction of Sec. IV. Every reduction uses a fixed grid, a fixed per-thread assignment and a
+// fixed tree, so results are bitwise reproducible from run to run.
+#include "ed_vec.h"
+
+namespace ed {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block-reduce NA doubles per thread; thread i < NA of the block receives total i.
+template <int NA>
+__device__ __forceinline__ void block_sum(double (&a)[NA], double* lds /* kWaves * NA */) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        double s = wave_sum(a[i]);
+        if (lane == 0) lds[wv * NA + i] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NA) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s += lds[w * NA + threadIdx.x];
+        a[0] = s;
+    }
+    __syncthreads();
+}
+
+// Partial dots over block b's chunk: part[b][i] = sum_x conj(V_i[x]) * w[x], i < n <= kDotGroup.
+template <int NG>
+__global__ __launch_bounds__(kThreads) void dot_partial(const double2* __restrict__ V, int64_t ldv, int n,
+                                                        const double2* __restrict__ w, int64_t D,
+                                                        double2* __restrict__ part, int part_ld) {
+    __shared__ double lds[kWaves * 2 * NG];
+    double a[2 * NG];
+#pragma unroll
+    for (int i = 0; i < 2 * NG; ++i) a[i] = 0.0;
+    const int64_t chunk = (D + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = int64_t(blockIdx.x) * chunk;
+    const int64_t hi = lo + chunk < D ? lo + chunk : D;
+    for (int64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
+        const double2 y = w[x];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            if (i < n) {
+                const double2 v = V[int64_t(i) * ldv + x];
+                a[2 * i] = fma(v.x, y.x, fma(v.y, y.y, a[2 * i]));
+                a[2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, a[2 * i + 1]));
+            }
+        }
+    }
+    block_sum<2 * NG>(a, lds);
+    if (threadIdx.x < 2 * n) {
+        double* p = reinterpret_cast<double*>(part + int64_t(blockIdx.x) * part_ld);
+        p[threadIdx.x] = a[0];
+    }
+}
+
+// Sum partials in fixed order: out[i] = scale * sum_b part[b][i] (+ out[i] if accumulate).
+__global__ __launch_bounds__(kThreads) void reduce_partials(const double2* __restrict__ part, int part_ld,
+                                                            int nblk, int n, double2* __restrict__ out,
+                                                            int accumulate) {
+    __shared__ double lds[kWaves * 2];
+    for (int i = 0; i < n; ++i) {
+        double a[2] = {0.0, 0.0};
+        for (int b = threadIdx.x; b < nblk; b += kThreads) {
+            const double2 v = part[int64_t(b) * part_ld + i];
+            a[0] += v.x;
+            a[1] += v.y;
+        }
+        block_sum<2>(a, lds);
+        if (threadIdx.x < 2) {
+            double* o = reinterpret_cast<double*>(out + i);
+            o[threadIdx.x] = accumulate ? o[threadIdx.x] + a[0] : a[0];
+        }
+        __syncthreads();
+    }
+}
+
+// w[x] += sign * sum_i coef[i] * V_i[x]  (coef in device memory)
+template <int NG>
+__global__ __launch_bounds__(kThreads) void multi_axpy(const double2* __restrict__ V, int64_t ldv, int n,
+                                                       const double2* __restrict__ coef, double sign,
+                                                       double2* __restrict__ w, int64_t D) {
+    double2 c[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) c[i] = i < n ? coef[i] : make_double2(0.0, 0.0);
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < D; x += stride) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            if (i < n) {
+                const double2 v = V[int64_t(i) * ldv + x];
+                acc.x = fma(c[i].x, v.x, fma(-c[i].y, v.y, acc.x));
+                acc.y = fma(c[i].x, v.y, fma(c[i].y, v.x, acc.y));
+            }
+        }
+        double2 y = w[x];
+        y.x = fma(sign, acc.x, y.x);
+        y.y = fma(sign, acc.y, y.y);
+        w[x] = y;
+    }
+}
+
+// out[x] = sum_i c_i V_i[x] (+ out[x] when accumulate), c given by value.
+struct CombArgs {
+    double2 c[kMaxComb];
+};
+
+__global__ __launch_bounds__(kThreads) void combine(const double2* __restrict__ V, int64_t ldv, int n,
+                                                    CombArgs ca, double2* __restrict__ out, int64_t D,
+                                                    int accumulate) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < D; x += stride) {
+        double2 acc = accumulate ? out[x] : make_double2(0.0, 0.0);
+        for (int i = 0; i < n; ++i) {
+            const double2 v = V[int64_t(i) * ldv + x];
+            acc.x = fma(ca.c[i].x, v.x, fma(-ca.c[i].y, v.y, acc.x));
+            acc.y = fma(ca.c[i].x, v.y, fma(ca.c[i].y, v.x, acc.y));
+        }
+        out[x] = acc;
+    }
+}
+
+// norm^2 partials
+__global__ __launch_bounds__(kThreads) void norm2_partial(const double2* __restrict__ w, int64_t D,
+                                                          double2* __restrict__ part, int part_ld) {
+    __shared__ double lds[kWaves];
+    double a[1] = {0.0};
+    const int64_t chunk = (D + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = int64_t(blockIdx.x) * chunk;
+    const int64_t hi = lo + chunk < D ? lo + chunk : D;
+    for (int64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
+        const double2 y = w[x];
+        a[0] = fma(y.x, y.x, fma(y.y, y.y, a[0]));
+    }
+    block_sum<1>(a, lds);
+    if (threadIdx.x == 0) part[int64_t(blockIdx.x) * part_ld] = make_double2(a[0], 0.0);
+}
+
+// dst[x] = src[x] * (1/sqrt(nrm2[0].x)) ; nrm2 is device memory
+__global__ __launch_bounds__(kThreads) void scale_by_invnorm(const double2* __restrict__ src,
+                                                             double2* __restrict__ dst,
+                                                             const double2* __restrict__ nrm2, int64_t D) {
+    const double s = 1.0 / sqrt(nrm2[0].x);
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < D; x += stride) {
+        double2 y = src[x];
+        dst[x] = make_double2(y.x * s, y.y * s);
+    }
+}
+
+// dst[x] = a * src[x] (complex a by value)
+__global__ __launch_bounds__(kThreads) void scale_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                       double2 a, int64_t D) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < D; x += stride) {
+        const double2 y = src[x];
+        dst[x] = make_double2(a.x * y.x - a.y * y.y, a.x * y.y + a.y * y.x);
+    }
+}
+
+// y[x] = a * x[x] + b * y[x] (complex a, b by value)
+__global__ __launch_bounds__(kThreads) void axpby_kernel(const double2* __restrict__ xv, double2* __restrict__ y,
+                                                         double2 a, double2 b, int64_t D) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < D; x += stride) {
+        const double2 u = xv[x], v = y[x];
+        y[x] = make_double2(a.x * u.x - a.y * u.y + b.x * v.x - b.y * v.y,
+                            a.x * u.y + a.y * u.x + b.x * v.y + b.y * v.x);
+    }
+}
+
+// All-site <sigma^z> partials: part[b][0] = sum |psi|^2, part[b][1 + p] = sum |psi|^2 (1 - 2 bit_p).
+// Blocks walk whole 2^kZBits-amplitude chunks: inside a chunk, bits 0..7 are fixed per thread,
+// bits 8..11 follow the thread's loop counter and the bits above are constant.
+constexpr int kZBits = 12;
+
+__global__ __launch_bounds__(kThreads) void sz_partial(const double2* __restrict__ psi, int L,
+                                                       double2* __restrict__ part, int part_ld) {
+    __shared__ double lds[kWaves * 32];
+    const int64_t D = int64_t(1) << L;
+    const int cb = L < kZBits ? L : kZBits;
+    const int64_t csize = int64_t(1) << cb;
+    const int64_t nchunk = D >> cb;
+    const int t = threadIdx.x;
+    double acc[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = 0.0;
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        double ct = 0.0;
+        double cbits[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t i = t; i < csize; i += kThreads) {
+            const double2 y = psi[(ch << cb) + i];
+            const double q = fma(y.x, y.x, y.y * y.y);
+            ct += q;
+#pragma unroll
+            for (int p = 8; p < 12; ++p) cbits[p - 8] += ((i >> p) & 1) ? -q : q;
+        }
+        acc[0] += ct;
+#pragma unroll
+        for (int p = 8; p < 12; ++p)
+            if (p < cb) acc[1 + p] += cbits[p - 8];
+#pragma unroll
+        for (int p = 12; p < 31; ++p)
+            if (p < L) acc[1 + p] += (((ch << cb) >> p) & 1) ? -ct : ct;
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) acc[1 + p] = (p < cb) ? (((t >> p) & 1) ? -acc[0] : acc[0]) : 0.0;
+    block_sum<32>(acc, lds);
+    if (t < L + 1) part[int64_t(blockIdx.x) * part_ld + t] = make_double2(acc[0], 0.0);
+}
+
+inline int grid_for(int64_t D) {
+    int64_t g = D / (kThreads * 4);
+    if (g < 1) g = 1;
+    if (g > kRedBlocks) g = kRedBlocks;
+    return int(g);
+}
+
+}  // namespace
+
+int reduction_blocks(int64_t D) { return grid_for(D); }
+
+hipError_t dots(const double2* V, int64_t ldv, int n, const double2* w, int64_t D, double2* out,
+                double2* part, hipStream_t s) {
+    const int G = grid_for(D);
+    for (int i0 = 0; i0 < n; i0 += kDotGroup) {
+        const int nn = n - i0 < kDotGroup ? n - i0 : kDotGroup;
+        if (nn <= 4) {
+            hipLaunchKernelGGL((dot_partial<4>), dim3(G), dim3(kThreads), 0, s, V + int64_t(i0) * ldv, ldv, nn, w, D, part, kPartLd);
+        } else {
+            hipLaunchKernelGGL((dot_partial<kDotGroup>), dim3(G), dim3(kThreads), 0, s, V + int64_t(i0) * ldv, ldv, nn, w, D, part, kPartLd);
+        }
+        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, nn, out + i0, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t axpy_multi(const double2* V, int64_t ldv, int n, const double2* coef, double sign, double2* w,
+                      int64_t D, hipStream_t s) {
+    const int G = grid_for(D);
+    for (int i0 = 0; i0 < n; i0 += kDotGroup) {
+        const int nn = n - i0 < kDotGroup ? n - i0 : kDotGroup;
+        if (nn <= 4) {
+            hipLaunchKernelGGL((multi_axpy<4>), dim3(G), dim3(kThreads), 0, s, V + int64_t(i0) * ldv, ldv, nn, coef + i0, sign, w, D);
+        } else {
+            hipLaunchKernelGGL((multi_axpy<kDotGroup>), dim3(G), dim3(kThreads), 0, s, V + int64_t(i0) * ldv, ldv, nn, coef + i0, sign, w, D);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t norm2(const double2* w, int64_t D, double2* out, double2* part, hipStream_t s) {
+    const int G = grid_for(D);
+    hipLaunchKernelGGL(norm2_partial, dim3(G), dim3(kThreads), 0, s, w, D, part, kPartLd);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, 1, out, 0);
+    return hipGetLastError();
+}
+
+hipError_t normalize(const double2* src, double2* dst, const double2* nrm2_dev, int64_t D, hipStream_t s) {
+    hipLaunchKernelGGL(scale_by_invnorm, dim3(grid_for(D)), dim3(kThreads), 0, s, src, dst, nrm2_dev, D);
+    return hipGetLastError();
+}
+
+hipError_t scale(const double2* src, double2* dst, double2 a, int64_t D, hipStream_t s) {
+    hipLaunchKernelGGL(scale_copy, dim3(grid_for(D)), dim3(kThreads), 0, s, src, dst, a, D);
+    return hipGetLastError();
+}
+
+hipError_t combination(const double2* V, int64_t ldv, int n, const double2* c, double2* out, int64_t D,
+                       hipStream_t s) {
+    for (int i0 = 0; i0 < n || i0 == 0; i0 += kMaxComb) {
+        const int nn = n - i0 < kMaxComb ? n - i0 : kMaxComb;
+        CombArgs ca;
+        for (int i = 0; i < kMaxComb; ++i) ca.c[i] = i < nn ? c[i0 + i] : make_double2(0.0, 0.0);
+        hipLaunchKernelGGL(combine, dim3(grid_for(D)), dim3(kThreads), 0, s, V + int64_t(i0) * ldv, ldv, nn, ca,
+                           out, D, i0 > 0 ? 1 : 0);
+        if (n == 0) break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t axpby(const double2* x, double2* y, double2 a, double2 b, int64_t D, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(D)), dim3(kThreads), 0, s, x, y, a, b, D);
+    return hipGetLastError();
+}
+
+hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStream_t s) {
+    const int64_t D = int64_t(1) << L;
+    const int cb = L < kZBits ? L : kZBits;
+    int64_t nchunk = D >> cb;
+    int G = int(nchunk < kRedBlocks ? nchunk : kRedBlocks);
+    hipLaunchKernelGGL(sz_partial, dim3(G), dim3(kThreads), 0, s, psi, L, part, kPartLd);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, L + 1, out, 0);
+    return hipGetLastError();
+}
+
+}  // namespace ed

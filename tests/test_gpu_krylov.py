@@ -1,0 +1,148 @@
+"""GPU parity of the Lanczos ground state, the Krylov time step and the one-pass measurement
+against the oracle (energies 1e-10 relative, state overlaps 1 - |<a|b>| <= 1e-9)."""
+import numpy as np
+import pytest
+import torch
+
+import edinputs as E
+import paper_1802_10052_amd as P
+from oracle import hamiltonian as OH
+from oracle import krylov as OK
+from oracle import lanczos as OL
+from oracle import observables as OO
+from tests import closed_forms as CF
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
+
+
+def overlap_err(a, b):
+    return 1 - abs(np.vdot(a, b)) / (np.linalg.norm(a) * np.linalg.norm(b))
+
+
+def test_lanczos_tfim_L14_config():
+    """Transverse-field Ising L = 14, g = 1, seeded start, tol 1e-10, <= 200 iterations; checked
+    against the free-fermion closed form and the oracle's Lanczos ground state."""
+    L = 14
+    print("lanczos tfim L=14", flush=True)
+    desc = E.tfim(L, 1.0)
+    v0 = E.random_state(L, 1)
+    m = P.Model(desc)
+    e0, psi, info = P.lanczos_ground(m, dev(v0), tol=1e-10, max_iter=200)
+    ref = CF.tfim_bdg_ground_energy(L, 1.0, 1.0)
+    assert info["converged"] and info["residual"] < 1e-9
+    assert abs(e0 - ref) <= 1e-10 * abs(ref)
+    H = OH.hamiltonian_sparse(desc)
+    eo, po, io = OL.lanczos_ground(lambda v: H @ v, v0, tol=1e-10, max_iter=200)
+    assert abs(e0 - eo) <= 1e-10 * abs(eo)
+    assert overlap_err(psi.cpu().numpy(), po) <= 1e-9
+
+
+@pytest.mark.parametrize("L,mb,keep", [(10, 12, 4), (16, 24, 8), (18, 30, 10)])
+def test_lanczos_thick_restart_xxz(L, mb, keep):
+    print(f"lanczos restart L={L}", flush=True)
+    desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
+    v0 = E.random_state(L, 3)
+    m = P.Model(desc)
+    e0, psi, info = P.lanczos_ground(m, dev(v0), tol=1e-10, max_iter=2000, max_basis=mb, n_keep=keep)
+    assert info["converged"] and info["restarts"] >= 1, info
+    H = OH.hamiltonian_sparse(desc)
+    eo, po = OL.ground_state_eigsh(H, tol=1e-14)
+    assert abs(e0 - eo) <= 1e-10 * abs(eo)
+    assert overlap_err(psi.cpu().numpy(), po) <= 1e-9
+    assert info["residual"] < 2e-10
+
+
+def test_lanczos_breakdown_and_noconv():
+    L = 12
+    m = P.Model(E.tfim(L, 0.0))
+    e0, psi, info = P.lanczos_ground(m, dev(E.product_state(L, 0)), tol=1e-10, max_iter=50)
+    assert info["iters"] == 1 and abs(e0 + (L - 1)) < 1e-13
+    m2 = P.Model(E.tfim(L, 1.0))
+    e1, psi1, info1 = P.lanczos_ground(m2, dev(E.random_state(L, 1)), tol=1e-15, max_iter=3)
+    assert info1["status"] == "ED_ERR_NOCONV" and not info1["converged"] and info1["iters"] == 3
+
+
+@pytest.mark.parametrize("L,reorth", [(10, 0), (10, 1), (14, 0), (16, 1)])
+def test_krylov_quench_vs_oracle(L, reorth):
+    """All-up start, g = 0.5, dt = 0.05, m <= 20, tol 1e-10 (the L = 28 quench at oracle size)."""
+    print(f"krylov quench L={L} reorth={reorth}", flush=True)
+    desc = E.tfim(L, 0.5)
+    H = OH.hamiltonian_sparse(desc)
+    psi0 = E.product_state(L, 0)
+    m = P.Model(desc)
+    steps = 40
+    g = dev(psi0)
+    _, obs, info = P.krylov_evolve(m, g, 0.05, steps, m_max=20, tol=1e-10, reorth=reorth)
+    ref = psi0.copy()
+    sz_ref = [OO.sz_all(ref, L)]
+    e_ref = [OO.energy(H, ref)]
+    for _ in range(steps):
+        ref, _m = OK.krylov_step(lambda v: H @ v, ref, 0.05, m_max=20, tol=1e-10)
+        sz_ref.append(OO.sz_all(ref, L))
+        e_ref.append(OO.energy(H, ref))
+    got = g.cpu().numpy()
+    assert overlap_err(got, ref) <= 1e-9
+    assert np.max(np.abs(obs["sz"] - np.array(sz_ref))) < 1e-9
+    assert np.max(np.abs(obs["energy"] - np.array(e_ref))) <= 1e-10 * (L - 1)
+    assert abs(obs["energy"][0] + (L - 1)) < 1e-12
+    assert np.max(np.abs(obs["norm"] - 1)) < 1e-9
+    assert np.allclose(obs["sz"], obs["sz"][:, ::-1], atol=1e-9)
+    exact = OK.expm_step(H.toarray(), psi0, 0.05 * steps) if L <= 10 else None
+    if exact is not None:
+        assert overlap_err(got, exact) <= 1e-9
+
+
+def test_krylov_generic_and_arnoldi():
+    L = 9
+    for herm in (True, False):
+        desc = E.random_model(L, seed=77, hermitian=herm)
+        H = OH.hamiltonian_sparse(desc)
+        psi0 = E.random_state(L, 4)
+        m = P.Model(desc)
+        g = dev(psi0)
+        P.krylov_evolve(m, g, 0.03, 10, m_max=30, tol=1e-12, reorth=1, hermitian=herm, observe=False)
+        exact = OK.expm_step(H.toarray(), psi0, 0.3)
+        got = g.cpu().numpy()
+        assert np.linalg.norm(got - exact) <= 1e-10 * np.linalg.norm(exact), herm
+
+
+def test_krylov_fixed_m_and_eigenstate():
+    L = 12
+    m = P.Model(E.tfim(L, 0.0))
+    g = dev(E.product_state(L, 0))
+    _, obs, info = P.krylov_evolve(m, g, 0.1, 5, m_max=20, tol=1e-10)
+    assert info["max_m"] == 1
+    got = g.cpu().numpy()
+    assert abs(got[0] - np.exp(1j * 0.5 * (L - 1))) < 1e-13
+    m2 = P.Model(E.tfim(L, 0.7))
+    g2 = dev(E.random_state(L, 2))
+    _, _, info2 = P.krylov_evolve(m2, g2, 0.05, 3, m_max=20, fixed_m=7, observe=False)
+    assert info2["max_m"] == 7 and info2["total_m"] == 21
+
+
+def test_measure_matches_oracle():
+    for L in (3, 9, 13, 17):
+        psi = E.random_state(L, 5, normalise=False)
+        sz, nrm = P.measure(dev(psi), L)
+        assert np.allclose(sz, OO.sz_all(psi, L), atol=1e-13)
+        assert abs(nrm - np.linalg.norm(psi)) < 1e-12 * np.linalg.norm(psi)
+
+
+def test_krylov_invariants_L26():
+    """At L = 26 (1 GiB per vector): energy of the all-up start is -(L-1) exactly, the norm and
+    energy are conserved, and the open uniform chain keeps reflection symmetry."""
+    L = 26
+    print("krylov invariants L=26", flush=True)
+    m = P.Model(E.tfim(L, 0.5))
+    g = torch.zeros(1 << L, dtype=torch.complex128, device=DEV)
+    g[0] = 1.0
+    _, obs, info = P.krylov_evolve(m, g, 0.05, 4, m_max=20, tol=1e-10)
+    assert obs["energy"][0] == -(L - 1)
+    assert np.max(np.abs(obs["energy"] + (L - 1))) < 1e-9 * L
+    assert np.max(np.abs(obs["norm"] - 1)) < 1e-10
+    assert np.allclose(obs["sz"], obs["sz"][:, ::-1], atol=1e-10)
