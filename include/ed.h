@@ -194,6 +194,21 @@ ed_status ed_measure_workspace(int L, size_t* bytes);
 ed_status ed_measure(const ed_c64* psi, int L, double* sz, double* norm, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* ----------------------------------------------------------------------------------------
+ * ed_entropy: bond entropy S(l) = -sum_j Lambda_j log Lambda_j (natural log, 0 log 0 = 0) of the
+ * bipartition sites 1..l | l+1..L (Sec. IV, bond entropy). Lambda_j are the eigenvalues of
+ * rho_l = M M^dagger / <psi|psi>, M = psi reshaped to 2^l x 2^(L-l) row-major (no copy is made).
+ * The Gram matrix of the smaller side is formed on the FP64 matrix cores, reduced to
+ * tridiagonal form by Householder steps on the GPU, and its eigenvalues are taken on the host.
+ * psi       device, D amplitudes (any nonzero norm)
+ * S         host; spectrum host (may be NULL): min(2^l, 2^(L-l)) eigenvalues, descending.
+ * Limits: 0 <= l_cut <= L, min(l_cut, L - l_cut) <= 14. Synchronises stream.
+ * Workspace: ed_entropy_workspace (the Gram matrix, 16 * 4^min(l, L-l) bytes, plus vectors).
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_entropy_workspace(int L, int l_cut, size_t* bytes);
+ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, void* ws,
+                     size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import EdError, call, lib
 
-__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "EdError", "lib"]
+__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "EdError", "lib"]
 
 
 def _stream_ptr(stream=None):
@@ -140,3 +140,18 @@ def measure(psi, L, stream=None):
     nrm = C.c_double()
     call("ed_measure", _dptr(psi), int(L), sz.ctypes.data, C.byref(nrm), _dptr(ws), nb.value, _stream_ptr(stream))
     return sz, nrm.value
+
+
+def entropy(psi, L, l_cut=None, spectrum=False, stream=None):
+    """Bond entropy S(l_cut) (natural log) of a device state (ed_entropy); with spectrum=True
+    also the Schmidt spectrum (descending numpy array)."""
+    _check_state(psi, 1 << L)
+    l = L // 2 if l_cut is None else int(l_cut)
+    nb = C.c_size_t()
+    call("ed_entropy_workspace", int(L), l, C.byref(nb))
+    ws = _workspace(nb.value, psi.device)
+    S = C.c_double()
+    spec = np.zeros(1 << min(l, L - l)) if spectrum else None
+    call("ed_entropy", _dptr(psi), int(L), 2, l, C.byref(S), spec.ctypes.data if spectrum else None,
+         _dptr(ws), nb.value, _stream_ptr(stream))
+    return (S.value, spec) if spectrum else S.value

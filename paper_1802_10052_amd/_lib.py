@@ -89,6 +89,8 @@ def _declare(l):
     _fn(l, "ed_krylov_evolve", [P, P, C.c_double, C.c_int, C.POINTER(KrylovParams), C.POINTER(Observe),
                                 C.POINTER(KrylovInfo), P, C.c_size_t, P])
     _fn(l, "ed_measure_workspace", [C.c_int, S])
+    _fn(l, "ed_entropy_workspace", [C.c_int, C.c_int, S])
+    _fn(l, "ed_entropy", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, P, C.c_size_t, P])
     _fn(l, "ed_measure", [P, C.c_int, P, P, P, C.c_size_t, P])
 
 

@@ -1,0 +1,439 @@
+// Bond (Schmidt) entropy of a pure state (Sec. IV, bond entropy; S(l) of the convergence
+// section): rho_l = M M^dagger with M the state reshaped to d^l x d^(L-l), its eigenvalues
+// Lambda_j, and S = -sum_j Lambda_j log Lambda_j. The paper computes rho_l by a matrix product
+// and takes an eigendecomposition (noting the SVD of M gives the same spectrum).
+//
+// Here:
+//   1. rho = R R^H on the FP64 matrix cores (v_mfma_f64_16x16x4f64), with R = M when
+//      d^l <= d^(L-l) and R = M^T otherwise (same non-zero spectrum, smaller Gram matrix);
+//      R is read in place from the state, never copied.
+//   2. Householder reduction of the Hermitian rho to a real symmetric tridiagonal matrix on the
+//      GPU: each step's rank-2 update of the trailing matrix is fused with the matrix-vector
+//      product that the next step needs, so the trailing matrix streams once per step.
+//   3. Eigenvalues of the tridiagonal matrix by implicit QL on the host (O(n^2)).
+#include <cmath>
+#include <vector>
+
+#include "dense.h"
+#include "ed_internal.h"
+
+namespace ed {
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------------ Gram matrix
+// rho[a][a'] = sum_b R[a][b] conj(R[a'][b]), R[r][c] = psi[r*rs + c*cs], n x K.
+// Block tile 64 x 64 of rho per workgroup (4 waves, each 32 x 32 = 2 x 2 MFMA tiles), K consumed
+// 16 at a time through LDS. Only blocks with I >= J are computed; the mirrored block is written
+// as the conjugate transpose so rho is stored in full.
+constexpr int kGB = 64;
+constexpr int kGK = 16;
+
+template <bool ROWC>  // ROWC: R's columns are contiguous in memory (cs == 1)
+__global__ __launch_bounds__(256) void gram_mfma(const double2* __restrict__ psi, int64_t rs, int64_t cs,
+                                                 int n, int64_t K, double2* __restrict__ rho, int nb) {
+    __shared__ double Ar[kGB][kGK + 1], Ai[kGB][kGK + 1], Br[kGB][kGK + 1], Bi[kGB][kGK + 1];
+    // triangular block index -> (I, J), I >= J
+    int b = blockIdx.x, I = 0;
+    while (b > I) {
+        b -= I + 1;
+        ++I;
+    }
+    const int J = b;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+    dbl4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            accr[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
+    const int r0 = I * kGB, c0 = J * kGB;
+    for (int64_t k0 = 0; k0 < K; k0 += kGK) {
+        // load 64 x 16 of R rows r0.. and rows c0..; 1024 elements each, 4 per thread
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = t + 256 * e;
+            int rr, kk;
+            if (ROWC) {
+                rr = idx / kGK;
+                kk = idx % kGK;
+            } else {
+                rr = idx % kGB;
+                kk = idx / kGB;
+            }
+            double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+            if (k0 + kk < K) {
+                if (r0 + rr < n) va = psi[int64_t(r0 + rr) * rs + (k0 + kk) * cs];
+                if (c0 + rr < n) vb = psi[int64_t(c0 + rr) * rs + (k0 + kk) * cs];
+            }
+            Ar[rr][kk] = va.x;
+            Ai[rr][kk] = va.y;
+            Br[rr][kk] = vb.x;
+            Bi[rr][kk] = vb.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGK; kk += 4) {
+            const int ka = kk + (lane >> 4), ra = lane & 15;
+            double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ar[i] = Ar[wr + 16 * i + ra][ka];
+                ai[i] = Ai[wr + 16 * i + ra][ka];
+                br[i] = Br[wc + 16 * i + ra][ka];
+                bi[i] = Bi[wc + 16 * i + ra][ka];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], accr[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[i], bi[j], acci[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // D[row][col] of a 16x16 tile: lane holds rows 4*(lane/16) + q, column lane % 16
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = r0 + wr + 16 * i + 4 * (lane >> 4) + q;
+                const int col = c0 + wc + 16 * j + (lane & 15);
+                if (row < n && col < n) {
+                    const double re = accr[i][j][q], im = acci[i][j][q];
+                    rho[int64_t(row) * n + col] = make_double2(re, im);
+                    if (I != J) rho[int64_t(col) * n + row] = make_double2(re, -im);
+                }
+            }
+}
+
+// ------------------------------------------------------------------------------ Householder
+// State of the reduction kept in device memory:
+//   v[n]   current Householder vector (v[0] = 1) of the step, indexed from row k+1
+//   y[n]   tau * A22 v, then w = y + alpha v
+//   d[n], e[n]  tridiagonal diagonal / |sub-diagonal|
+//   part[nblk][n] partial row sums of the fused update
+//   sc[4]  tau (complex) at sc[0]
+constexpr int kFR = 16;    // rows per workgroup tile of the fused update
+constexpr int kFC = 512;   // columns per workgroup tile
+
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * b
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
+
+// Fused: for the trailing block rows/cols [s, n) (s = k + 2):
+//   A[i][j] -= v_i conj(w_j) + w_i conj(v_j)     (rank-2 update of step k, vectors indexed by
+//                                               absolute row; v, w hold entries for rows >= k+1)
+//   part[cb][i] = sum_{j in tile} A_new[i][j] * vn_j   (vn: next Householder vector, rows >= k+2)
+__global__ __launch_bounds__(256) void hh_fused(double2* __restrict__ A, int n, int s,
+                                                const double2* __restrict__ v, const double2* __restrict__ w,
+                                                const double2* __restrict__ vn, double2* __restrict__ part) {
+    const int r = n - s;
+    const int ncb = (r + kFC - 1) / kFC;
+    const int rb = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cbeg = s + cb * kFC;
+    for (int ii = 0; ii < kFR / 4; ++ii) {
+        const int i = s + rb * kFR + wv * (kFR / 4) + ii;
+        if (i >= n) break;
+        const double2 vi = v[i], wi = w[i];
+        double2 acc = make_double2(0.0, 0.0);
+        for (int jj = lane; jj < kFC; jj += 64) {
+            const int j = cbeg + jj;
+            if (j >= n) break;
+            double2 a = A[int64_t(i) * n + j];
+            const double2 vj = v[j], wj = w[j];
+            const double2 t1 = cmulc(vi, conjd(wj)), t2 = cmulc(wi, conjd(vj));
+            a.x -= t1.x + t2.x;
+            a.y -= t1.y + t2.y;
+            A[int64_t(i) * n + j] = a;
+            const double2 p = cmulc(a, vn[j]);
+            acc.x += p.x;
+            acc.y += p.y;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            acc.x += __shfl_down(acc.x, off, 64);
+            acc.y += __shfl_down(acc.y, off, 64);
+        }
+        if (lane == 0) part[int64_t(cb) * n + i] = acc;
+    }
+}
+
+// Single-workgroup step kernel (1024 threads). Given part (row sums of A22 * v for the
+// current step k, rows k+1..n-1) it: forms y = tau (A22 v); alpha = -1/2 tau (y^H v); w = y + alpha v;
+// updates column k+1 of the trailing matrix (rows k+1..n-1) with the rank-2 term; records
+// d[k+1]; builds the next Householder vector from rows k+2.. of that column, with tau, beta.
+// For k = -1 it only builds the first Householder vector from column 0.
+constexpr int kStepThreads = 1024;
+
+__device__ double block_reduce(double v, double* lds) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < kStepThreads / 64; ++i) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(kStepThreads) void hh_step(double2* __restrict__ A, int n, int k,
+                                                        double2* __restrict__ v, double2* __restrict__ y,
+                                                        double2* __restrict__ vn, const double2* __restrict__ part,
+                                                        int ncb, double* __restrict__ d, double* __restrict__ e,
+                                                        double2* __restrict__ sc) {
+    __shared__ double lds[kStepThreads / 64];
+    const int t = threadIdx.x;
+    const int c = k + 1;  // column of the trailing matrix to finish now
+    if (k >= 0) {
+        const double2 tau = sc[0];
+        // y_i = tau * sum_cb part[cb][i], i = k+1..n-1 ; also y^H v
+        double dre = 0.0, dim = 0.0;
+        for (int i = c + t; i < n; i += kStepThreads) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int cb = 0; cb < ncb; ++cb) {
+                const double2 p = part[int64_t(cb) * n + i];
+                s.x += p.x;
+                s.y += p.y;
+            }
+            // rows >= k+1 of A22 v: the fused kernel covered columns >= k+1 of rows >= k+1? (see host)
+            const double2 yi = cmulc(tau, s);
+            y[i] = yi;
+            const double2 vi = v[i];
+            // y^H v = sum conj(y_i) v_i
+            dre += yi.x * vi.x + yi.y * vi.y;
+            dim += yi.x * vi.y - yi.y * vi.x;
+        }
+        dre = block_reduce(dre, lds);
+        dim = block_reduce(dim, lds);
+        // alpha = -1/2 tau (y^H v)
+        const double2 yhv = make_double2(dre, dim);
+        const double2 tt = cmulc(tau, yhv);
+        const double2 alpha = make_double2(-0.5 * tt.x, -0.5 * tt.y);
+        for (int i = c + t; i < n; i += kStepThreads) {
+            const double2 vi = v[i], yi = y[i];
+            const double2 av = cmulc(alpha, vi);
+            y[i] = make_double2(yi.x + av.x, yi.y + av.y);  // w
+        }
+        __syncthreads();
+        // update column c (rows c..n-1): A[i][c] -= v_i conj(w_c) + w_i conj(v_c)
+        const double2 vc = v[c], wc = y[c];
+        for (int i = c + t; i < n; i += kStepThreads) {
+            double2 a = A[int64_t(i) * n + c];
+            const double2 t1 = cmulc(v[i], conjd(wc)), t2 = cmulc(y[i], conjd(vc));
+            a.x -= t1.x + t2.x;
+            a.y -= t1.y + t2.y;
+            A[int64_t(i) * n + c] = a;
+        }
+        __syncthreads();
+    }
+    // diagonal of row c and Householder vector of column c below the diagonal (rows c+1..)
+    if (t == 0) d[c] = A[int64_t(c) * n + c].x;
+    if (c + 1 >= n) return;
+    double nx = 0.0;
+    for (int i = c + 2 + t; i < n; i += kStepThreads) {
+        const double2 a = A[int64_t(i) * n + c];
+        nx += a.x * a.x + a.y * a.y;
+    }
+    nx = block_reduce(nx, lds);
+    const double2 al = A[int64_t(c + 1) * n + c];
+    double2 tau = make_double2(0.0, 0.0);
+    double beta;
+    double2 inv = make_double2(0.0, 0.0);
+    if (nx == 0.0 && al.y == 0.0) {
+        beta = al.x;  // H = I
+    } else {
+        const double nrm = sqrt(al.x * al.x + al.y * al.y + nx);
+        beta = al.x >= 0.0 ? -nrm : nrm;
+        tau = make_double2((beta - al.x) / beta, -al.y / beta);
+        // 1 / (alpha - beta)
+        const double2 den = make_double2(al.x - beta, al.y);
+        const double dd = den.x * den.x + den.y * den.y;
+        inv = make_double2(den.x / dd, -den.y / dd);
+    }
+    if (t == 0) {
+        e[c] = fabs(beta);
+        sc[0] = tau;
+        vn[c + 1] = make_double2(1.0, 0.0);
+    }
+    for (int i = c + 2 + t; i < n; i += kStepThreads) vn[i] = cmulc(A[int64_t(i) * n + c], inv);
+}
+
+// GEMV for the first step: part[cb][i] = sum_{j in tile} A[i][j] v_j over rows/cols >= s
+__global__ __launch_bounds__(256) void hh_gemv(const double2* __restrict__ A, int n, int s,
+                                               const double2* __restrict__ vn, double2* __restrict__ part) {
+    const int r = n - s;
+    const int ncb = (r + kFC - 1) / kFC;
+    const int rb = blockIdx.x / ncb, cb = blockIdx.x % ncb;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cbeg = s + cb * kFC;
+    for (int ii = 0; ii < kFR / 4; ++ii) {
+        const int i = s + rb * kFR + wv * (kFR / 4) + ii;
+        if (i >= n) break;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int jj = lane; jj < kFC; jj += 64) {
+            const int j = cbeg + jj;
+            if (j >= n) break;
+            const double2 p = cmulc(A[int64_t(i) * n + j], vn[j]);
+            acc.x += p.x;
+            acc.y += p.y;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            acc.x += __shfl_down(acc.x, off, 64);
+            acc.y += __shfl_down(acc.y, off, 64);
+        }
+        if (lane == 0) part[int64_t(cb) * n + i] = acc;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct EntWS {
+    double2* rho;
+    double2* v;
+    double2* y;
+    double2* vn;
+    double2* part;
+    double* d;
+    double* e;
+    double2* sc;
+};
+
+size_t entropy_bytes(int n) {
+    const int ncb = (n + kFC - 1) / kFC;
+    return align256(size_t(n) * n * sizeof(double2)) + 3 * align256(size_t(n) * sizeof(double2)) +
+           align256(size_t(ncb + 1) * n * sizeof(double2)) + 2 * align256(size_t(n) * sizeof(double)) +
+           align256(4 * sizeof(double2));
+}
+
+EntWS carve_ent(void* ws, int n) {
+    const int ncb = (n + kFC - 1) / kFC;
+    char* p = static_cast<char*>(ws);
+    EntWS w;
+    w.rho = reinterpret_cast<double2*>(p);
+    p += align256(size_t(n) * n * sizeof(double2));
+    w.v = reinterpret_cast<double2*>(p);
+    p += align256(size_t(n) * sizeof(double2));
+    w.y = reinterpret_cast<double2*>(p);
+    p += align256(size_t(n) * sizeof(double2));
+    w.vn = reinterpret_cast<double2*>(p);
+    p += align256(size_t(n) * sizeof(double2));
+    w.part = reinterpret_cast<double2*>(p);
+    p += align256(size_t(ncb + 1) * n * sizeof(double2));
+    w.d = reinterpret_cast<double*>(p);
+    p += align256(size_t(n) * sizeof(double));
+    w.e = reinterpret_cast<double*>(p);
+    p += align256(size_t(n) * sizeof(double));
+    w.sc = reinterpret_cast<double2*>(p);
+    return w;
+}
+
+}  // namespace
+}  // namespace ed
+
+using namespace ed;
+
+extern "C" ed_status ed_entropy_workspace(int L, int l_cut, size_t* bytes) {
+    if (!bytes || L < 1 || L > 30 || l_cut < 0 || l_cut > L) return fail(ED_ERR_ARG, "bad argument");
+    const int ls = l_cut <= L - l_cut ? l_cut : L - l_cut;
+    if (ls > 14) return fail(ED_ERR_UNSUPPORTED, "the smaller side of the cut must have <= 14 sites");
+    *bytes = entropy_bytes(1 << ls);
+    return ED_OK;
+}
+
+extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum,
+                                void* ws, size_t ws_bytes, void* stream) {
+    if (!psi || !S) return fail(ED_ERR_ARG, "null argument");
+    if (d != 2) return fail(ED_ERR_UNSUPPORTED, "only d = 2 is supported");
+    size_t need = 0;
+    ED_TRY(ed_entropy_workspace(L, l_cut, &need));
+    if (!ws) return fail(ED_ERR_ARG, "workspace is null");
+    if (ws_bytes < need) return fail(ED_ERR_WORKSPACE, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool left_small = l_cut <= L - l_cut;
+    const int ls = left_small ? l_cut : L - l_cut;
+    const int n = 1 << ls;
+    const int64_t K = int64_t(1) << (L - ls);
+    EntWS w = carve_ent(ws, n);
+    const double2* p = reinterpret_cast<const double2*>(psi);
+    // 1. Gram matrix on the matrix cores
+    const int nb = (n + kGB - 1) / kGB;
+    const int nblocks = nb * (nb + 1) / 2;
+    if (left_small) {
+        // R = M: row a of M is psi[a*K .. a*K+K)
+        hipLaunchKernelGGL((gram_mfma<true>), dim3(nblocks), dim3(256), 0, s, p, K, int64_t(1), n, K, w.rho, nb);
+    } else {
+        // R = M^T: R[b][a] = psi[a*n + b] with n = 2^(L-l) columns of M
+        hipLaunchKernelGGL((gram_mfma<false>), dim3(nblocks), dim3(256), 0, s, p, int64_t(1), int64_t(n), n, K, w.rho, nb);
+    }
+    ED_HIP_TRY(hipGetLastError());
+    // 2. Householder tridiagonalisation
+    ED_HIP_TRY(hipMemsetAsync(w.v, 0, size_t(n) * sizeof(double2), s));
+    ED_HIP_TRY(hipMemsetAsync(w.y, 0, size_t(n) * sizeof(double2), s));
+    ED_HIP_TRY(hipMemsetAsync(w.vn, 0, size_t(n) * sizeof(double2), s));
+    if (n > 1) {
+        // first Householder vector from column 0
+        hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, -1, w.v, w.y, w.vn, w.part, 0, w.d,
+                           w.e, w.sc);
+        for (int k = 0; k + 1 < n; ++k) {
+            // the current vector (rows >= k+1) becomes v; A22 v over rows/cols >= k+1
+            std::swap(w.v, w.vn);
+            const int s0 = k + 1;
+            const int r = n - s0;
+            const int ncb = (r + kFC - 1) / kFC;
+            const int nrb = (r + kFR - 1) / kFR;
+            if (k == 0) {
+                hipLaunchKernelGGL(hh_gemv, dim3(nrb * ncb), dim3(256), 0, s, w.rho, n, s0, w.v, w.part);
+            }
+            // step kernel: y, w, column k+1 update, next Householder vector into vn
+            hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.part, ncb,
+                               w.d, w.e, w.sc);
+            if (k + 2 < n) {
+                // rank-2 update of rows/cols >= k+2 fused with A_new * vn (the next step's product)
+                const int s1 = k + 2;
+                const int r1 = n - s1;
+                const int ncb1 = (r1 + kFC - 1) / kFC;
+                const int nrb1 = (r1 + kFR - 1) / kFR;
+                hipLaunchKernelGGL(hh_fused, dim3(nrb1 * ncb1), dim3(256), 0, s, w.rho, n, s1, w.v, w.y, w.vn, w.part);
+            }
+            ED_HIP_TRY(hipGetLastError());
+        }
+    }
+    // 3. tridiagonal eigenvalues on the host
+    std::vector<double> dd(n), ee(n, 0.0);
+    ED_HIP_TRY(hipMemcpyAsync(dd.data(), w.d, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    if (n > 1) ED_HIP_TRY(hipMemcpyAsync(ee.data(), w.e, sizeof(double) * (n - 1), hipMemcpyDeviceToHost, s));
+    ED_HIP_TRY(hipStreamSynchronize(s));
+    if (n == 1) {
+        // rho is the 1x1 matrix |psi|^2
+        double2 r11;
+        ED_HIP_TRY(hipMemcpy(&r11, w.rho, sizeof(double2), hipMemcpyDeviceToHost));
+        dd[0] = r11.x;
+    }
+    if (!tridiag_ql(n, dd.data(), ee.data(), nullptr)) return fail(ED_ERR_NUMERIC, "tridiagonal QL did not converge");
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += dd[i];
+    if (!(tr > 0.0) || !std::isfinite(tr)) return fail(ED_ERR_NUMERIC, "state has zero or non-finite norm");
+    double ent = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double lam = dd[i] / tr;
+        if (lam > 1e-300) ent -= lam * std::log(lam);
+    }
+    *S = ent;
+    if (spectrum)
+        for (int i = 0; i < n; ++i) spectrum[i] = dd[n - 1 - i] / tr;  // descending
+    return ED_OK;
+}
