@@ -209,6 +209,73 @@ ed_status ed_entropy_workspace(int L, int l_cut, size_t* bytes);
 ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* ----------------------------------------------------------------------------------------
+ * Quantum trajectories (Sec. VI.A) of the Lindblad equation with one jump operator per site,
+ * L_nu = sqrt(rate_nu) J on site nu, and H_eff = H - (i/2) sum_nu L_nu^dagger L_nu built inside.
+ * Per trajectory: draw r; evolve the unnormalised state under H_eff (Krylov steps of length dt,
+ * Arnoldi basis, stopping tolerance tol, at most m_max vectors) until |psi|^2 = r, the crossing
+ * time being solved exactly inside the step; draw r_kappa, pick kappa with
+ * P_{kappa-1} < r_kappa <= P_kappa, P the normalised cumulative sum of
+ * p_nu = <psi|L_nu^dagger L_nu|psi> over sites nu = 1..L; apply L_kappa, renormalise, repeat.
+ * Random numbers: trajectory t uses Philox4x64-10 with key (seed, t); draw n is word n%4 of
+ * counter block (n/4 + 1, 0, 0, 0) mapped to ((w >> 11) + 1) 2^-53 in (0, 1]; draws alternate
+ * threshold r, then (at each jump) r_kappa and the next r.
+ * desc:  models[n_models] Hermitian parts H (one per chain length, L <= 16); rates[m] host [L_m];
+ *        psi0[m] device initial states; model_of_traj host [n_traj]; jump_op host 2x2 row-major,
+ *        J^dagger J must be diagonal (lowering, raising, number, dephasing) else UNSUPPORTED.
+ * out:   sz host [n_traj][n_out][L_max] = <sigma^z_k>/<psi|psi> at t = n dt out_stride,
+ *        n = 0..n_out-1 with n_out = n_steps/out_stride + 1 (sites k = 1..L_t, zero padded);
+ *        n_jumps host [n_traj] (may be NULL); jump_t / jump_site host [n_traj][max_jumps]
+ *        (may be NULL): time and site index nu-1 of the first max_jumps jumps.
+ * ed_trajectories_batch runs every trajectory in one persistent kernel launch (replayed from a
+ * hipGraph when stream is not NULL); ed_trajectories_plain runs the same algorithm one trajectory
+ * at a time from the host (the per-instance baseline). Both synchronise stream. The effective
+ * Hamiltonians' coefficient tables are allocated at entry and freed on return.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    int n_models;
+    const ed_model* const* models;
+    const ed_c64* jump_op;
+    const double* const* rates;
+    const ed_c64* const* psi0;
+    int n_traj;
+    const int* model_of_traj;
+    double dt;
+    int n_steps;
+    int out_stride;
+    uint64_t seed;
+} ed_traj_desc;
+
+typedef struct {
+    int m_max;
+    double tol;
+    int max_jumps;
+} ed_traj_params;
+
+typedef struct {
+    double* sz;
+    int* n_jumps;
+    double* jump_t;
+    int* jump_site;
+} ed_traj_out;
+
+typedef struct {
+    long long total_jumps;
+    long long total_krylov;
+    int blocks;
+} ed_traj_info;
+
+ed_status ed_trajectories_workspace(const ed_traj_desc* desc, const ed_traj_params* params, size_t* bytes);
+ed_status ed_trajectories_batch(const ed_traj_desc* desc, const ed_traj_params* params, const ed_traj_out* out,
+                                ed_traj_info* info, void* ws, size_t ws_bytes, void* stream);
+ed_status ed_trajectories_plain_workspace(const ed_traj_desc* desc, const ed_traj_params* params, size_t* bytes);
+ed_status ed_trajectories_plain(const ed_traj_desc* desc, const ed_traj_params* params, const ed_traj_out* out,
+                                ed_traj_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Raw 64-bit words n = 0..count-1 of the trajectory random stream of key (seed, id), written to
+ * device memory out (for checking the generator against its published definition). Async. */
+ed_status ed_philox_words(uint64_t seed, uint64_t id, uint64_t* out, int64_t count, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

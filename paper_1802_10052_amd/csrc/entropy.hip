@@ -99,14 +99,14 @@ __global__ __launch_bounds__(256) void gram_mfma(const double2* __restrict__ psi
         }
         __syncthreads();
     }
-    // D[row][col] of a 16x16 tile: lane holds rows 4*(lane/16) + q, column lane % 16
+    // D[row][col] of a 16x16 f64 tile: register q of lane l holds row l/16 + 4q, column l%16
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = r0 + wr + 16 * i + 4 * (lane >> 4) + q;
+                const int row = r0 + wr + 16 * i + (lane >> 4) + 4 * q;
                 const int col = c0 + wc + 16 * j + (lane & 15);
                 if (row < n && col < n) {
                     const double re = accr[i][j][q], im = acci[i][j][q];

@@ -1,0 +1,249 @@
+// Device-side bodies of out = H psi (Sec. III.C, Eq. ed:eq:OKrylov), shared by the streaming
+// kernels (one tile per workgroup) and by the trajectory kernel (one workgroup walks every tile of
+// its own small state).
+#pragma once
+#include "ed_internal.h"
+
+namespace ed {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <bool REAL>
+__device__ __forceinline__ void cfma(double2& acc, double2 c, double2 v) {
+    if (REAL) {
+        acc.x = fma(c.x, v.x, acc.x);
+        acc.y = fma(c.x, v.y, acc.y);
+    } else {
+        acc.x = fma(c.x, v.x, acc.x);
+        acc.x = fma(-c.y, v.y, acc.x);
+        acc.y = fma(c.x, v.y, acc.y);
+        acc.y = fma(c.y, v.x, acc.y);
+    }
+}
+
+__device__ __forceinline__ double2 sel2(int b, double2 a0, double2 a1) { return b ? a1 : a0; }
+
+__device__ __forceinline__ double2 sel4(int l, double2 a0, double2 a1, double2 a2, double2 a3) {
+    double2 lo = (l & 1) ? a1 : a0;
+    double2 hi = (l & 1) ? a3 : a2;
+    return (l & 2) ? hi : lo;
+}
+
+// Tile-local index i = t + 256 k: local bits 0..7 across threads, 8..11 across 16 registers.
+constexpr int kSlots = (1 << kTileBits) / kTileThreads;  // 16
+
+struct PassArgs {
+    int c, h0, first;
+    uint32_t site_mask, bond_mask;
+    int bit_of[kTileBits];
+};
+
+// Coefficient tables of one model as the kernels see them.
+struct ModelTables {
+    const double2* site;
+    const double2* bond;
+    const double2* dlo;
+    const double2* dmid;
+    const double2* dhi;
+    int L;
+    int n_pass;
+    PassArgs pass[kMaxPasses];
+};
+
+// One tile of one pass (tile index n). s: 4096 double2 of LDS. FIRST: writes out including the
+// diagonal; otherwise accumulates into out. Caller synchronises around reuse of s.
+template <unsigned CLS, bool FIRST>
+__device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
+                                          const double2* __restrict__ site, const double2* __restrict__ bond,
+                                          const double2* __restrict__ dlo, const double2* __restrict__ dmid,
+                                          const double2* __restrict__ dhi, const PassArgs& pa, int64_t n,
+                                          double2* s) {
+    constexpr bool OFFR = CLS & kOffReal;
+    constexpr bool DIAGR = CLS & kDiagReal;
+    const int t = threadIdx.x;
+    int64_t base;
+    if (FIRST) {
+        base = n << kTileBits;
+    } else {
+        const int lo_bits = pa.h0 - pa.c;
+        const int64_t nlo = n & ((int64_t(1) << lo_bits) - 1);
+        const int64_t nhi = n >> lo_bits;
+        base = (nlo << pa.c) | (nhi << (pa.h0 + kTileBits - pa.c));
+    }
+    auto gidx = [&](int i) -> int64_t {
+        if (FIRST) return base + i;
+        const int lowmask = (1 << pa.c) - 1;
+        return base | int64_t(i & lowmask) | (int64_t(i >> pa.c) << pa.h0);
+    };
+
+    double2 v[kSlots];
+    double2 acc[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) v[k] = psi[gidx(t + kTileThreads * k)];
+    if (!FIRST) {
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) acc[k] = out[gidx(t + kTileThreads * k)];
+    }
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) s[t + kTileThreads * k] = v[k];
+
+    if (FIRST) {
+        const double2 dl = dlo[t & 255];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int i = t + kTileThreads * k;
+            const double2 dm = dmid[(i >> 7) & 31];
+            const double2 dh = dhi[(n << 1) | ((i >> 11) & 1)];
+            double2 dd = make_double2(dl.x + dm.x + dh.x, dl.y + dm.y + dh.y);
+            if (DIAGR) {
+                acc[k] = make_double2(dd.x * v[k].x, dd.x * v[k].y);
+            } else {
+                acc[k] = cmul(dd, v[k]);
+            }
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int q = 0; q < kTileBits; ++q) {
+        const int p = pa.bit_of[q];
+        if ((CLS & kSiteOff) && ((pa.site_mask >> q) & 1)) {
+            const double2 c01 = site[4 * p + 1];
+            const double2 c10 = site[4 * p + 2];
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) {
+                const int i = t + kTileThreads * k;
+                const int b = (i >> q) & 1;
+                double2 w;
+                if (q >= 8) {
+                    w = v[k ^ (1 << (q >= 8 ? q - 8 : 0))];
+                } else {
+                    w = s[i ^ (1 << q)];
+                }
+                cfma<OFFR>(acc[k], sel2(b, c01, c10), w);
+            }
+        }
+        if ((CLS & (kBondSingle | kBondDouble)) && q + 1 < kTileBits && ((pa.bond_mask >> q) & 1)) {
+            const double2* B = bond + 16 * p;
+            if (CLS & kBondSingle) {
+#pragma unroll
+                for (int m = 1; m <= 2; ++m) {
+                    const double2 b0 = B[0 * 4 + (0 ^ m)], b1 = B[1 * 4 + (1 ^ m)];
+                    const double2 b2 = B[2 * 4 + (2 ^ m)], b3 = B[3 * 4 + (3 ^ m)];
+#pragma unroll
+                    for (int k = 0; k < kSlots; ++k) {
+                        const int i = t + kTileThreads * k;
+                        const int l = (i >> q) & 3;
+                        double2 w;
+                        if (q >= 8) {
+                            w = v[k ^ (m << (q >= 8 ? q - 8 : 0))];
+                        } else {
+                            w = s[i ^ (m << q)];
+                        }
+                        cfma<OFFR>(acc[k], sel4(l, b0, b1, b2, b3), w);
+                    }
+                }
+            }
+            if (CLS & kBondDouble) {
+                const double2 b0 = B[0 * 4 + 3], b1 = B[1 * 4 + 2];
+                const double2 b2 = B[2 * 4 + 1], b3 = B[3 * 4 + 0];
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) {
+                    const int i = t + kTileThreads * k;
+                    const int l = (i >> q) & 3;
+                    double2 w;
+                    if (q >= 8) {
+                        w = v[k ^ (3 << (q >= 8 ? q - 8 : 0))];
+                    } else {
+                        w = s[i ^ (3 << q)];
+                    }
+                    cfma<OFFR>(acc[k], sel4(l, b0, b1, b2, b3), w);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) out[gidx(t + kTileThreads * k)] = acc[k];
+}
+
+// Small-L body for one amplitude x (L < kTileBits), partners read from `src` (global or LDS).
+template <unsigned CLS>
+__device__ __forceinline__ double2 small_entry(const double2* src, const double2* __restrict__ site,
+                                               const double2* __restrict__ bond, int L, int64_t x) {
+    constexpr bool OFFR = CLS & kOffReal;
+    const double2 v = src[x];
+    double2 diag = make_double2(0.0, 0.0);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int p = 0; p < L; ++p) {
+        const int b = (x >> p) & 1;
+        const double2* S = site + 4 * p;
+        diag.x += S[3 * b].x;
+        diag.y += S[3 * b].y;
+        if (CLS & kSiteOff) cfma<OFFR>(acc, S[b ? 2 : 1], src[x ^ (int64_t(1) << p)]);
+    }
+    for (int p = 0; p + 1 < L; ++p) {
+        const int l = (x >> p) & 3;
+        const double2* B = bond + 16 * p;
+        diag.x += B[5 * l].x;
+        diag.y += B[5 * l].y;
+        if (CLS & kBondSingle) {
+            cfma<OFFR>(acc, B[4 * l + (l ^ 1)], src[x ^ (int64_t(1) << p)]);
+            cfma<OFFR>(acc, B[4 * l + (l ^ 2)], src[x ^ (int64_t(2) << p)]);
+        }
+        if (CLS & kBondDouble) cfma<OFFR>(acc, B[4 * l + (l ^ 3)], src[x ^ (int64_t(3) << p)]);
+    }
+    const double2 dv = cmul(diag, v);
+    return make_double2(acc.x + dv.x, acc.y + dv.y);
+}
+
+// Kernel variants: a model runs on the first variant whose work flags cover its own and whose
+// "real" flags it satisfies.
+constexpr unsigned kWork = kSiteOff | kBondSingle | kBondDouble;
+constexpr unsigned kVariants[] = {
+    kSiteOff | kOffReal | kDiagReal,                 // transverse-field Ising
+    kBondDouble | kOffReal | kDiagReal,              // XXZ
+    kBondDouble | kOffReal,                          // XXZ with a decay term (H_eff)
+    kSiteOff | kBondDouble | kOffReal | kDiagReal,   // XXZ with transverse fields
+    kSiteOff | kBondDouble | kOffReal,
+    kSiteOff | kBondSingle | kBondDouble,            // anything
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+__host__ __device__ constexpr bool variant_fits(unsigned V, unsigned mc) {
+    return (((mc & kWork) & ~(V & kWork)) == 0) && (((V & ~kWork) & ~(mc & ~kWork)) == 0);
+}
+
+inline int pick_variant(unsigned mc) {
+    for (int i = 0; i < kNumVariants; ++i)
+        if (variant_fits(kVariants[i], mc)) return i;
+    return kNumVariants - 1;
+}
+
+inline PassArgs to_args(const PassDesc& pd) {
+    PassArgs pa;
+    pa.c = pd.c;
+    pa.h0 = pd.h0;
+    pa.first = pd.first;
+    pa.site_mask = pd.site_mask;
+    pa.bond_mask = pd.bond_mask;
+    for (int q = 0; q < kTileBits; ++q) pa.bit_of[q] = pd.bit_of[q];
+    return pa;
+}
+
+inline ModelTables tables_of(const ed_model* m) {
+    ModelTables tb;
+    tb.site = m->d_site;
+    tb.bond = m->d_bond;
+    tb.dlo = m->d_diag_lo;
+    tb.dmid = m->d_diag_mid;
+    tb.dhi = m->d_diag_hi;
+    tb.L = m->L;
+    tb.n_pass = m->n_pass;
+    for (int i = 0; i < kMaxPasses; ++i) tb.pass[i] = to_args(m->pass[i]);
+    return tb;
+}
+
+}  // namespace ed

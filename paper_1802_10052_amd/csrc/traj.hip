@@ -1,0 +1,1043 @@
+// Quantum trajectories for the Lindblad equation (Sec. VI.A). Per trajectory, with
+// H_eff = H - (i/2) sum_nu L_nu^dagger L_nu and L_nu = sqrt(rate_nu) J on site nu:
+//   1. draw r; evolve the unnormalised state under H_eff until |psi|^2 drops to r;
+//   2. draw r_kappa; p_nu = <psi|L_nu^dagger L_nu|psi>, P_nu the normalised cumulative sum;
+//   3. apply L_kappa with P_{kappa-1} < r_kappa <= P_kappa, renormalise, go back to 1.
+// The evolution uses Krylov steps (the paper notes quantum trajectories work with any of its
+// three propagators); H_eff is not Hermitian, so the basis comes from Arnoldi and the projected
+// matrix is upper Hessenberg (Sec. VI.B). The step's basis gives psi(t + tau) for every tau in the
+// step, so the time at which |psi|^2 reaches r is solved in the small space, without extra H psi.
+//
+// Batched path: one persistent launch. Each workgroup takes trajectories from a queue (longest
+// chains first), keeps the state and Krylov basis in its own slice of the workspace, runs H psi
+// tile by tile through LDS, and does every reduction, the small exponential, the root search,
+// the Philox draws and the jumps itself, so a trajectory never returns to the host.
+// Plain path: the same algorithm one trajectory at a time from the host, on the library's
+// stream-level kernels (the per-instance baseline).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dense.h"
+#include "ed_vec.h"
+#include "hpsi_device.h"
+#include "krylov_core.h"
+
+namespace ed {
+
+ed_status create_model(const ed_model_desc* desc, ed_model** out);
+void destroy_model(ed_model* m);
+
+namespace {
+
+constexpr int kTT = 256;       // threads per trajectory workgroup
+constexpr int kTMax = 24;      // max Krylov dimension per step (basis holds kTMax + 1 vectors)
+constexpr int kMaxL = 20;
+
+// ---------------------------------------------------------------------------- Philox4x64-10
+// Salmon et al. (SC'11): two 64x64 -> 128 multiplies per round, key bumped by Weyl constants.
+__device__ __host__ inline void philox4x64_10(const uint64_t c_in[4], uint64_t k0, uint64_t k1, uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t x0 = c_in[0], x1 = c_in[1], x2 = c_in[2], x3 = c_in[3];
+    for (int r = 0; r < 10; ++r) {
+#ifdef __HIP_DEVICE_COMPILE__
+        const uint64_t hi0 = __umul64hi(M0, x0), hi1 = __umul64hi(M1, x2);
+#else
+        const uint64_t hi0 = uint64_t((unsigned __int128)M0 * x0 >> 64);
+        const uint64_t hi1 = uint64_t((unsigned __int128)M1 * x2 >> 64);
+#endif
+        const uint64_t lo0 = M0 * x0, lo1 = M1 * x2;
+        const uint64_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+// Word n of the stream of key (seed, id): counter block n/4 + 1, word n%4.
+__device__ __host__ inline uint64_t philox_word(uint64_t seed, uint64_t id, uint64_t n) {
+    const uint64_t c[4] = {n / 4 + 1, 0, 0, 0};
+    uint64_t o[4];
+    philox4x64_10(c, seed, id, o);
+    return o[n % 4];
+}
+
+__device__ __host__ inline double to_unit(uint64_t w) { return double((w >> 11) + 1) * 0x1.0p-53; }
+
+// ---------------------------------------------------------------------------- descriptors
+struct TrajModel {
+    ModelTables tb;
+    const double2* psi0;
+    double rate[kMaxL];
+    int L;
+    unsigned cls;
+};
+
+struct TrajArgs {
+    const TrajModel* models;
+    const int* order;
+    const int* model_of;
+    int n_traj;
+    double dt;
+    int n_steps;
+    int out_stride;
+    int n_out;
+    uint64_t seed;
+    int m_max;
+    double tol;
+    int max_jumps;
+    double2 J[4];
+    double jdj_up, jdj_dn;
+    int Lmax;
+    double* sz_out;
+    int* n_jumps;
+    double* jump_t;
+    int* jump_site;
+    int* m_total;
+    double2* scratch;
+    int64_t scratch_stride;
+    int* counter;
+};
+
+struct Shared {
+    double2 tile[1 << kTileBits];
+    double2 H[(kTMax + 1) * (kTMax + 1)];
+    double2 u[kTMax + 1], term[kTMax + 1], acc[kTMax + 1], h[kTMax + 1];
+    double red[kTT / 64][2 * (kTMax + 1)];
+    double pop[kMaxL + 1];
+    double scal[8];
+    int iscal[4];
+};
+
+// ---------------------------------------------------------------------------- WG reductions
+// Sum NA per-thread doubles over the workgroup; every thread receives all NA totals in out[].
+template <int NA>
+__device__ void wg_sum(double (&a)[NA], Shared& sh, double* out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        double v = a[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) sh.red[wv][i] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kTT / 64; ++w) s += sh.red[w][i];
+        out[i] = s;
+    }
+    __syncthreads();
+}
+
+__device__ double wg_norm2(const double2* x, int64_t N, Shared& sh) {
+    double a[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < N; i += kTT) {
+        const double2 y = x[i];
+        a[0] = fma(y.x, y.x, fma(y.y, y.y, a[0]));
+    }
+    double o[1];
+    wg_sum<1>(a, sh, o);
+    return o[0];
+}
+
+__device__ void wg_scale(double2* x, int64_t N, double s) {
+    for (int64_t i = threadIdx.x; i < N; i += kTT) {
+        const double2 y = x[i];
+        x[i] = make_double2(y.x * s, y.y * s);
+    }
+    __syncthreads();
+}
+
+// out[i] (into sh.h) = <V_i|w>, i < n
+__device__ void wg_dots(const double2* V, int64_t ld, int n, const double2* w, int64_t N, Shared& sh) {
+    double a[2 * (kTMax + 1)];
+#pragma unroll
+    for (int i = 0; i < 2 * (kTMax + 1); ++i) a[i] = 0.0;
+    for (int64_t x = threadIdx.x; x < N; x += kTT) {
+        const double2 y = w[x];
+#pragma unroll
+        for (int i = 0; i < kTMax + 1; ++i) {
+            if (i < n) {
+                const double2 v = V[i * ld + x];
+                a[2 * i] = fma(v.x, y.x, fma(v.y, y.y, a[2 * i]));
+                a[2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, a[2 * i + 1]));
+            }
+        }
+    }
+    double o[2 * (kTMax + 1)];
+    wg_sum<2 * (kTMax + 1)>(a, sh, o);
+    if (threadIdx.x < n) sh.h[threadIdx.x] = make_double2(o[2 * threadIdx.x], o[2 * threadIdx.x + 1]);
+    __syncthreads();
+}
+
+// w -= sum_i c_i V_i with c in shared memory
+__device__ void wg_sub(const double2* V, int64_t ld, int n, const double2* c, double2* w, int64_t N) {
+    for (int64_t x = threadIdx.x; x < N; x += kTT) {
+        double2 acc = w[x];
+        for (int i = 0; i < n; ++i) {
+            const double2 v = V[i * ld + x];
+            acc.x -= c[i].x * v.x - c[i].y * v.y;
+            acc.y -= c[i].x * v.y + c[i].y * v.x;
+        }
+        w[x] = acc;
+    }
+    __syncthreads();
+}
+
+// out = scale * sum_i c_i V_i
+__device__ void wg_combine(const double2* V, int64_t ld, int n, const double2* c, double scale, double2* out,
+                           int64_t N) {
+    for (int64_t x = threadIdx.x; x < N; x += kTT) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = 0; i < n; ++i) {
+            const double2 v = V[i * ld + x];
+            acc.x += c[i].x * v.x - c[i].y * v.y;
+            acc.y += c[i].x * v.y + c[i].y * v.x;
+        }
+        out[x] = make_double2(scale * acc.x, scale * acc.y);
+    }
+    __syncthreads();
+}
+
+// Per-site populations: pop[p] = sum_{bit p of x = 0} |psi_x|^2 (p = bit), pop[L] = total.
+__device__ void wg_pops(const double2* psi, int L, Shared& sh) {
+    double a[kMaxL + 1];
+#pragma unroll
+    for (int i = 0; i <= kMaxL; ++i) a[i] = 0.0;
+    const int64_t N = int64_t(1) << L;
+    for (int64_t x = threadIdx.x; x < N; x += kTT) {
+        const double2 y = psi[x];
+        const double q = fma(y.x, y.x, y.y * y.y);
+        a[kMaxL] += q;
+#pragma unroll
+        for (int p = 0; p < kMaxL; ++p)
+            if (p < L && !((x >> p) & 1)) a[p] += q;
+    }
+    double o[kMaxL + 1];
+    wg_sum<kMaxL + 1>(a, sh, o);
+    if (threadIdx.x == 0) {
+        for (int p = 0; p < L; ++p) sh.pop[p] = o[p];
+        sh.pop[kMaxL] = o[kMaxL];
+    }
+    __syncthreads();
+}
+
+// dst = H_eff src, whole small state handled by this workgroup
+template <unsigned CLS>
+__device__ void wg_apply(const TrajModel& md, const double2* src, double2* dst, Shared& sh) {
+    const int L = md.L;
+    if (L < kTileBits) {
+        const int64_t N = int64_t(1) << L;
+        for (int64_t x = threadIdx.x; x < N; x += kTT) sh.tile[x] = src[x];
+        __syncthreads();
+        for (int64_t x = threadIdx.x; x < N; x += kTT) dst[x] = small_entry<CLS>(sh.tile, md.tb.site, md.tb.bond, L, x);
+        __syncthreads();
+        return;
+    }
+    const int64_t tiles = int64_t(1) << (L - kTileBits);
+    for (int ip = 0; ip < md.tb.n_pass; ++ip) {
+        const PassArgs& pa = md.tb.pass[ip];
+        for (int64_t n = 0; n < tiles; ++n) {
+            if (pa.first)
+                tile_body<CLS, true>(src, dst, md.tb.site, md.tb.bond, md.tb.dlo, md.tb.dmid, md.tb.dhi, pa, n, sh.tile);
+            else
+                tile_body<CLS, false>(src, dst, md.tb.site, md.tb.bond, md.tb.dlo, md.tb.dmid, md.tb.dhi, pa, n, sh.tile);
+            __syncthreads();
+        }
+    }
+}
+
+// u = exp(-i tau H_m) e_1 for the m x m Hessenberg in sh.H (leading dimension kTMax + 1), by
+// scaling the matrix to norm <= 1/2 and summing the Taylor series of the vector 2^s times.
+__device__ void wg_expv(int m, double tau, Shared& sh) {
+    constexpr int LD = kTMax + 1;
+    double nrm = 0.0;
+    for (int j = 0; j < m; ++j) {
+        double cs = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double2 h = sh.H[i * LD + j];
+            cs += sqrt(h.x * h.x + h.y * h.y);
+        }
+        nrm = fmax(nrm, cs);
+    }
+    nrm *= fabs(tau);
+    int sq = 0;
+    while (nrm > 0.5 && sq < 60) {
+        nrm *= 0.5;
+        ++sq;
+    }
+    const double sc = tau * ldexp(1.0, -sq);  // A = -i sc H
+    const int t = threadIdx.x;
+    if (t < m) sh.u[t] = make_double2(t == 0 ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    const long reps = 1L << sq;
+    for (long rep = 0; rep < reps; ++rep) {
+        if (t < m) {
+            sh.term[t] = sh.u[t];
+            sh.acc[t] = sh.u[t];
+        }
+        __syncthreads();
+        for (int k = 1; k <= 40; ++k) {
+            double2 nt = make_double2(0.0, 0.0);
+            if (t < m) {
+                for (int j = 0; j < m; ++j) {
+                    const double2 h = sh.H[t * LD + j], v = sh.term[j];
+                    nt.x += h.x * v.x - h.y * v.y;
+                    nt.y += h.x * v.y + h.y * v.x;
+                }
+                // multiply by -i sc / k
+                const double f = sc / k;
+                nt = make_double2(f * nt.y, -f * nt.x);
+            }
+            __syncthreads();
+            if (t < m) {
+                sh.term[t] = nt;
+                sh.acc[t].x += nt.x;
+                sh.acc[t].y += nt.y;
+            }
+            __syncthreads();
+            double tn = 0.0, an = 0.0;
+            for (int j = 0; j < m; ++j) {
+                tn = fmax(tn, fabs(sh.term[j].x) + fabs(sh.term[j].y));
+                an = fmax(an, fabs(sh.acc[j].x) + fabs(sh.acc[j].y));
+            }
+            __syncthreads();
+            if (tn <= 1e-18 * an) break;
+        }
+        if (t < m) sh.u[t] = sh.acc[t];
+        __syncthreads();
+    }
+}
+
+__device__ double unorm2(int m, Shared& sh) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += sh.u[i].x * sh.u[i].x + sh.u[i].y * sh.u[i].y;
+    return s;
+}
+
+template <unsigned CLS>
+__device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared& sh) {
+    constexpr int LD = kTMax + 1;
+    const TrajModel& md = a.models[a.model_of[tr]];
+    const int L = md.L;
+    const int64_t N = int64_t(1) << L;
+    const int64_t ldv = int64_t(1) << a.Lmax;
+    double2* psi = base;
+    double2* V = base + ldv;
+    const int t = threadIdx.x;
+    uint64_t ndraw = 0;
+    auto draw = [&]() -> double {
+        const double u = to_unit(philox_word(a.seed, uint64_t(tr), ndraw));
+        ++ndraw;
+        return u;
+    };
+    for (int64_t x = t; x < N; x += kTT) psi[x] = md.psi0[x];
+    __syncthreads();
+    {
+        const double n2 = wg_norm2(psi, N, sh);
+        wg_scale(psi, N, 1.0 / sqrt(n2));
+    }
+    double r = draw();
+    int njump = 0, mtot = 0;
+    double* szo = a.sz_out + int64_t(tr) * a.n_out * a.Lmax;
+    auto record = [&](int slot) {
+        wg_pops(psi, L, sh);
+        const double tot = sh.pop[kMaxL];
+        if (t < L) {
+            const int p = L - 1 - t;  // site k = t+1 sits at bit L-1-t
+            const double up = sh.pop[p];
+            szo[int64_t(slot) * a.Lmax + t] = (2.0 * up - tot) / tot;
+        }
+        __syncthreads();
+    };
+    record(0);
+    for (int step = 0; step < a.n_steps; ++step) {
+        double tau_left = a.dt;
+        while (tau_left > 0.0) {
+            // Krylov basis of the current state
+            const double n2 = wg_norm2(psi, N, sh);
+            const double nrm = sqrt(n2);
+            for (int64_t x = t; x < N; x += kTT) {
+                const double2 y = psi[x];
+                V[x] = make_double2(y.x / nrm, y.y / nrm);
+            }
+            if (t < LD * LD) {
+                for (int e = t; e < LD * LD; e += kTT) sh.H[e] = make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+            int m = 0;
+            double beta = 0.0;
+            for (int j = 0; j < a.m_max; ++j) {
+                double2* Vj = V + j * ldv;
+                double2* Wn = V + (j + 1) * ldv;
+                wg_apply<CLS>(md, Vj, Wn, sh);
+                // classical Gram-Schmidt, twice
+                wg_dots(V, ldv, j + 1, Wn, N, sh);
+                if (t <= j) sh.H[t * LD + j] = sh.h[t];
+                __syncthreads();
+                wg_sub(V, ldv, j + 1, sh.h, Wn, N);
+                wg_dots(V, ldv, j + 1, Wn, N, sh);
+                if (t <= j) {
+                    sh.H[t * LD + j].x += sh.h[t].x;
+                    sh.H[t * LD + j].y += sh.h[t].y;
+                }
+                __syncthreads();
+                wg_sub(V, ldv, j + 1, sh.h, Wn, N);
+                const double b2 = wg_norm2(Wn, N, sh);
+                beta = sqrt(b2);
+                m = j + 1;
+                double hs = 0.0;
+                for (int i = 0; i <= j; ++i) hs = fmax(hs, sqrt(sh.H[i * LD + j].x * sh.H[i * LD + j].x + sh.H[i * LD + j].y * sh.H[i * LD + j].y));
+                const bool brk = beta <= 1e-14 * fmax(hs, 1e-300) || beta == 0.0;
+                wg_expv(m, tau_left, sh);
+                const double err = brk ? 0.0 : nrm * beta * sqrt(sh.u[m - 1].x * sh.u[m - 1].x + sh.u[m - 1].y * sh.u[m - 1].y);
+                if (brk || err <= a.tol || m >= a.m_max) break;
+                if (t == 0) sh.H[(j + 1) * LD + j] = make_double2(beta, 0.0);
+                wg_scale(Wn, N, 1.0 / beta);
+            }
+            mtot += m;
+            // sh.u = exp(-i tau_left H_m) e_1
+            const double lr = log(r);
+            const double f_end = log(n2 * unorm2(m, sh)) - lr;
+            if (f_end > 0.0) {
+                if (t < m) sh.acc[t] = sh.u[t];
+                __syncthreads();
+                wg_combine(V, ldv, m, sh.acc, nrm, psi, N);
+                tau_left = 0.0;
+                break;
+            }
+            // crossing inside (0, tau_left]: f(tau) = log(|psi(tau)|^2) - log r is decreasing
+            double lo = 0.0, hi = tau_left;
+            double flo = log(n2) - lr, fhi = f_end;
+            double tau = hi;
+            if (flo <= 0.0) {
+                tau = 0.0;
+            } else {
+                int side = 0;
+                for (int it = 0; it < 200; ++it) {
+                    double c = hi - fhi * (hi - lo) / (fhi - flo);
+                    if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
+                    wg_expv(m, c, sh);
+                    const double fc = log(n2 * unorm2(m, sh)) - lr;
+                    if (fc > 0.0) {
+                        lo = c;
+                        flo = fc;
+                        if (side == -1) fhi *= 0.5;
+                        side = -1;
+                    } else {
+                        hi = c;
+                        fhi = fc;
+                        if (side == 1) flo *= 0.5;
+                        side = 1;
+                    }
+                    tau = hi;
+                    if (fc == 0.0 || hi - lo <= 1e-15 * a.dt) {
+                        tau = (fc == 0.0) ? c : hi;
+                        break;
+                    }
+                }
+            }
+            wg_expv(m, tau, sh);
+            if (t < m) sh.acc[t] = sh.u[t];
+            __syncthreads();
+            wg_combine(V, ldv, m, sh.acc, nrm, psi, N);
+            const double t_abs = step * a.dt + (a.dt - tau_left) + tau;
+            // jump probabilities p_nu = rate_nu <psi| J^dag J |psi>_nu (J^dag J diagonal)
+            wg_pops(psi, L, sh);
+            const double tot = sh.pop[kMaxL];
+            const double rk = draw();
+            int kappa = L - 1;
+            {
+                double ptot = 0.0;
+                for (int nu = 0; nu < L; ++nu) {
+                    const double up = sh.pop[L - 1 - nu];
+                    ptot += md.rate[nu] * (a.jdj_up * up + a.jdj_dn * (tot - up));
+                }
+                double cum = 0.0;
+                for (int nu = 0; nu < L; ++nu) {
+                    const double up = sh.pop[L - 1 - nu];
+                    cum += md.rate[nu] * (a.jdj_up * up + a.jdj_dn * (tot - up));
+                    if (rk <= cum / ptot) {
+                        kappa = nu;
+                        break;
+                    }
+                }
+            }
+            // psi <- J on site kappa (bit L-1-kappa), then renormalise
+            {
+                const int p = L - 1 - kappa;
+                const int64_t half = N >> 1;
+                for (int64_t q = t; q < half; q += kTT) {
+                    const int64_t lowm = (int64_t(1) << p) - 1;
+                    const int64_t x0 = ((q & ~lowm) << 1) | (q & lowm);
+                    const int64_t x1 = x0 | (int64_t(1) << p);
+                    const double2 a0 = psi[x0], a1 = psi[x1];
+                    const double2 n0 = make_double2(a.J[0].x * a0.x - a.J[0].y * a0.y + a.J[1].x * a1.x - a.J[1].y * a1.y,
+                                                    a.J[0].x * a0.y + a.J[0].y * a0.x + a.J[1].x * a1.y + a.J[1].y * a1.x);
+                    const double2 n1 = make_double2(a.J[2].x * a0.x - a.J[2].y * a0.y + a.J[3].x * a1.x - a.J[3].y * a1.y,
+                                                    a.J[2].x * a0.y + a.J[2].y * a0.x + a.J[3].x * a1.y + a.J[3].y * a1.x);
+                    psi[x0] = n0;
+                    psi[x1] = n1;
+                }
+                __syncthreads();
+                const double jn2 = wg_norm2(psi, N, sh);
+                wg_scale(psi, N, 1.0 / sqrt(jn2));
+            }
+            if (t == 0 && njump < a.max_jumps) {
+                a.jump_t[int64_t(tr) * a.max_jumps + njump] = t_abs;
+                a.jump_site[int64_t(tr) * a.max_jumps + njump] = kappa;
+            }
+            ++njump;
+            r = draw();
+            tau_left -= tau;
+            if (tau_left <= 1e-15 * a.dt) tau_left = 0.0;
+        }
+        if ((step + 1) % a.out_stride == 0) record((step + 1) / a.out_stride);
+    }
+    if (t == 0) {
+        a.n_jumps[tr] = njump;
+        a.m_total[tr] = mtot;
+    }
+    __syncthreads();
+}
+
+template <unsigned CLS>
+__global__ __launch_bounds__(kTT) void traj_kernel(TrajArgs a) {
+    extern __shared__ char smem_raw[];
+    Shared& sh = *reinterpret_cast<Shared*>(smem_raw);
+    double2* base = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
+    while (true) {
+        if (threadIdx.x == 0) sh.iscal[0] = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int q = sh.iscal[0];
+        __syncthreads();
+        if (q >= a.n_traj) break;
+        run_trajectory<CLS>(a, a.order[q], base, sh);
+    }
+}
+
+__global__ void zero_ints(int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void zero_doubles(double* p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+template <int I>
+hipError_t prepare_traj(unsigned cls, size_t shm) {
+    if constexpr (I >= kNumVariants) {
+        return hipErrorInvalidValue;
+    } else {
+        if (variant_fits(kVariants[I], cls))
+            return hipFuncSetAttribute(reinterpret_cast<const void*>(&traj_kernel<kVariants[I]>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+        return prepare_traj<I + 1>(cls, shm);
+    }
+}
+
+template <int I>
+hipError_t launch_traj(unsigned cls, dim3 grid, size_t shm, hipStream_t s, const TrajArgs& a) {
+    if constexpr (I >= kNumVariants) {
+        return hipErrorInvalidValue;
+    } else {
+        if (variant_fits(kVariants[I], cls)) {
+            hipLaunchKernelGGL((traj_kernel<kVariants[I]>), grid, dim3(kTT), shm, s, a);
+            return hipGetLastError();
+        }
+        return launch_traj<I + 1>(cls, grid, shm, s, a);
+    }
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- shared setup
+struct TrajSetup {
+    std::vector<ed_model*> heff;  // owned
+    int Lmax = 0;
+    int n_out = 0;
+    unsigned cls = 0;
+    double jdj_up = 0.0, jdj_dn = 0.0;
+    ~TrajSetup() {
+        for (ed_model* m : heff) destroy_model(m);
+    }
+};
+
+static ed_status validate_traj(const ed_traj_desc* d, const ed_traj_params* p) {
+    if (!d || !p) return fail(ED_ERR_ARG, "null argument");
+    if (d->n_models < 1 || !d->models || !d->jump_op || !d->rates || !d->psi0 || !d->model_of_traj)
+        return fail(ED_ERR_ARG, "incomplete trajectory description");
+    if (d->n_traj < 0) return fail(ED_ERR_ARG, "n_traj must be >= 0");
+    if (!(d->dt > 0.0) || d->n_steps < 0 || d->out_stride < 1) return fail(ED_ERR_ARG, "bad time grid");
+    if (p->m_max < 1 || p->m_max > kTMax) return fail(ED_ERR_ARG, "m_max must be in [1, 24]");
+    if (!(p->tol > 0.0)) return fail(ED_ERR_ARG, "tol must be > 0");
+    if (p->max_jumps < 0) return fail(ED_ERR_ARG, "max_jumps must be >= 0");
+    for (int i = 0; i < d->n_models; ++i) {
+        if (!d->models[i] || !d->rates[i] || !d->psi0[i]) return fail(ED_ERR_ARG, "null model entry");
+        if (d->models[i]->L > 16) return fail(ED_ERR_UNSUPPORTED, "trajectory chains are limited to L <= 16");
+    }
+    for (int t = 0; t < d->n_traj; ++t)
+        if (d->model_of_traj[t] < 0 || d->model_of_traj[t] >= d->n_models) return fail(ED_ERR_ARG, "model_of_traj out of range");
+    // J^dag J must be diagonal (true for lowering, raising, number and dephasing operators)
+    const ed_c64* J = d->jump_op;
+    const double o_re = J[0].re * J[1].re + J[0].im * J[1].im + J[2].re * J[3].re + J[2].im * J[3].im;
+    const double o_im = J[0].re * J[1].im - J[0].im * J[1].re + J[2].re * J[3].im - J[2].im * J[3].re;
+    if (std::fabs(o_re) > 0.0 || std::fabs(o_im) > 0.0)
+        return fail(ED_ERR_UNSUPPORTED, "jump operators with off-diagonal J^dagger J are not supported");
+    return ED_OK;
+}
+
+// H_eff = H - (i/2) sum_k rate_k J^dag J on site k, built as a copy of each model's terms plus one
+// site rule with the operator -(i/2) J^dag J and coefficients rate_k.
+static ed_status build_setup(const ed_traj_desc* d, TrajSetup* st) {
+    const ed_c64* J = d->jump_op;
+    st->jdj_up = J[0].re * J[0].re + J[0].im * J[0].im + J[2].re * J[2].re + J[2].im * J[2].im;
+    st->jdj_dn = J[1].re * J[1].re + J[1].im * J[1].im + J[3].re * J[3].re + J[3].im * J[3].im;
+    st->n_out = d->n_steps / d->out_stride + 1;
+    for (int i = 0; i < d->n_models; ++i) {
+        const ed_model* m = d->models[i];
+        const int L = m->L;
+        st->Lmax = std::max(st->Lmax, L);
+        // site ops: the folded per-site operators of H (one rule per site) + the decay rule
+        std::vector<ed_c64> sop(4 * (L + 1));
+        std::vector<double> scoef(size_t(L + 1) * L, 0.0);
+        for (int k = 1; k <= L; ++k) {
+            const int p = L - k;
+            for (int e = 0; e < 4; ++e) sop[4 * (k - 1) + e] = ed_c64{m->site[4 * p + e].x, m->site[4 * p + e].y};
+            scoef[size_t(k - 1) * L + (k - 1)] = 1.0;
+        }
+        sop[4 * L + 0] = ed_c64{0.0, -0.5 * st->jdj_up};
+        sop[4 * L + 1] = ed_c64{0.0, 0.0};
+        sop[4 * L + 2] = ed_c64{0.0, 0.0};
+        sop[4 * L + 3] = ed_c64{0.0, -0.5 * st->jdj_dn};
+        for (int k = 0; k < L; ++k) scoef[size_t(L) * L + k] = d->rates[i][k];
+        std::vector<ed_c64> bop(16 * (L - 1));
+        std::vector<double> bcoef(size_t(L - 1) * (L - 1), 0.0);
+        for (int k = 1; k <= L - 1; ++k) {
+            const int p = L - k - 1;
+            for (int e = 0; e < 16; ++e) bop[16 * (k - 1) + e] = ed_c64{m->bond[16 * p + e].x, m->bond[16 * p + e].y};
+            bcoef[size_t(k - 1) * (L - 1) + (k - 1)] = 1.0;
+        }
+        ed_model_desc md{L, 2, L + 1, sop.data(), scoef.data(), L - 1, bop.data(), bcoef.data()};
+        ed_model* h = nullptr;
+        ED_TRY(create_model(&md, &h));
+        st->heff.push_back(h);
+        st->cls |= h->op_class & kWork;
+    }
+    // real flags: only if every model has them
+    unsigned real = kOffReal | kDiagReal;
+    for (ed_model* h : st->heff) real &= h->op_class;
+    st->cls |= real;
+    return ED_OK;
+}
+
+static int persistent_blocks(int n_traj) {
+    int dev = 0, cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t pr;
+        if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cu = pr.multiProcessorCount;
+    }
+    return std::max(1, std::min(n_traj, 2 * cu));
+}
+
+static size_t traj_bytes(const ed_traj_desc* d, const ed_traj_params* p, int Lmax, int n_out, int G) {
+    const size_t per = size_t(p->m_max + 2) << Lmax;
+    return al256(size_t(G) * per * sizeof(double2)) + al256(size_t(d->n_models) * sizeof(TrajModel)) +
+           3 * al256(size_t(d->n_traj) * sizeof(int)) + al256(size_t(d->n_traj) * n_out * Lmax * sizeof(double)) +
+           al256(size_t(d->n_traj) * std::max(p->max_jumps, 1) * (sizeof(double) + sizeof(int))) + al256(sizeof(int) * 4) +
+           al256(size_t(d->n_traj) * sizeof(int));
+}
+
+}  // namespace ed
+
+using namespace ed;
+
+extern "C" ed_status ed_trajectories_workspace(const ed_traj_desc* d, const ed_traj_params* p, size_t* bytes) {
+    if (!bytes) return fail(ED_ERR_ARG, "bytes is null");
+    ED_TRY(validate_traj(d, p));
+    int Lmax = 0;
+    for (int i = 0; i < d->n_models; ++i) Lmax = std::max(Lmax, d->models[i]->L);
+    const int n_out = d->n_steps / d->out_stride + 1;
+    *bytes = traj_bytes(d, p, Lmax, n_out, persistent_blocks(std::max(d->n_traj, 1)));
+    return ED_OK;
+}
+
+extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_params* p, const ed_traj_out* out,
+                                           ed_traj_info* info, void* ws, size_t ws_bytes, void* stream) {
+    ED_TRY(validate_traj(d, p));
+    if (!out || !out->sz) return fail(ED_ERR_ARG, "output sz is null");
+    size_t need = 0;
+    ED_TRY(ed_trajectories_workspace(d, p, &need));
+    if (!ws) return fail(ED_ERR_ARG, "workspace is null");
+    if (ws_bytes < need) return fail(ED_ERR_WORKSPACE, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TrajSetup st;
+    ED_TRY(build_setup(d, &st));
+    const int G = persistent_blocks(std::max(d->n_traj, 1));
+    const int Lmax = st.Lmax, n_out = st.n_out, nt = d->n_traj;
+    // carve
+    char* c = static_cast<char*>(ws);
+    auto take = [&](size_t bytes) {
+        char* r = c;
+        c += al256(bytes);
+        return r;
+    };
+    const size_t per = size_t(p->m_max + 2) << Lmax;
+    double2* scratch = reinterpret_cast<double2*>(take(size_t(G) * per * sizeof(double2)));
+    TrajModel* dmod = reinterpret_cast<TrajModel*>(take(size_t(d->n_models) * sizeof(TrajModel)));
+    int* order = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
+    int* model_of = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
+    int* njumps = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
+    double* sz = reinterpret_cast<double*>(take(size_t(nt) * n_out * Lmax * sizeof(double)));
+    const int mj = std::max(p->max_jumps, 1);
+    char* jbuf = take(size_t(nt) * mj * (sizeof(double) + sizeof(int)));
+    double* jt = reinterpret_cast<double*>(jbuf);
+    int* js = reinterpret_cast<int*>(jbuf + size_t(nt) * mj * sizeof(double));
+    int* counter = reinterpret_cast<int*>(take(sizeof(int) * 4));
+    int* mtot = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
+    // host-side descriptors
+    std::vector<TrajModel> hm(d->n_models);
+    for (int i = 0; i < d->n_models; ++i) {
+        std::memset(&hm[i], 0, sizeof(TrajModel));
+        hm[i].tb = tables_of(st.heff[i]);
+        hm[i].psi0 = reinterpret_cast<const double2*>(d->psi0[i]);
+        hm[i].L = st.heff[i]->L;
+        hm[i].cls = st.heff[i]->op_class;
+        for (int k = 0; k < hm[i].L; ++k) hm[i].rate[k] = d->rates[i][k];
+    }
+    std::vector<int> ord(nt), mo(d->model_of_traj, d->model_of_traj + nt);
+    for (int i = 0; i < nt; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        return d->models[mo[a]]->L > d->models[mo[b]]->L;
+    });
+    ED_HIP_TRY(hipMemcpyAsync(dmod, hm.data(), sizeof(TrajModel) * hm.size(), hipMemcpyHostToDevice, s));
+    if (nt > 0) {
+        ED_HIP_TRY(hipMemcpyAsync(order, ord.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+        ED_HIP_TRY(hipMemcpyAsync(model_of, mo.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+    }
+    TrajArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.models = dmod;
+    a.order = order;
+    a.model_of = model_of;
+    a.n_traj = nt;
+    a.dt = d->dt;
+    a.n_steps = d->n_steps;
+    a.out_stride = d->out_stride;
+    a.n_out = n_out;
+    a.seed = d->seed;
+    a.m_max = p->m_max;
+    a.tol = p->tol;
+    a.max_jumps = p->max_jumps;
+    for (int e = 0; e < 4; ++e) a.J[e] = make_double2(d->jump_op[e].re, d->jump_op[e].im);
+    a.jdj_up = st.jdj_up;
+    a.jdj_dn = st.jdj_dn;
+    a.Lmax = Lmax;
+    a.sz_out = sz;
+    a.n_jumps = njumps;
+    a.jump_t = jt;
+    a.jump_site = js;
+    a.m_total = mtot;
+    a.scratch = scratch;
+    a.scratch_stride = int64_t(per);
+    a.counter = counter;
+    ED_HIP_TRY(prepare_traj<0>(st.cls, sizeof(Shared)));
+    // clear the queue counter and the outputs with fill kernels, then the persistent launch;
+    // on a non-null stream the three launches are captured and replayed as one hipGraph
+    auto enqueue = [&]() -> hipError_t {
+        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 4);
+        if (nt == 0) return hipGetLastError();
+        const int64_t nz = int64_t(nt) * n_out * Lmax;
+        hipLaunchKernelGGL(zero_doubles, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, s, sz, nz);
+        return launch_traj<0>(st.cls, dim3(G), sizeof(Shared), s, a);
+    };
+    if (s == nullptr) {
+        hipError_t e = enqueue();
+        if (e != hipSuccess) return fail(ED_ERR_HIP, std::string("trajectory launch: ") + hipGetErrorString(e));
+        ED_HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ED_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue();
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (e != hipSuccess || ce != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(ED_ERR_HIP, std::string("trajectory capture: ") + hipGetErrorString(e != hipSuccess ? e : ce));
+        }
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(ED_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        }
+        hipError_t le = hipGraphLaunch(exec, s);
+        hipError_t se = hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (le != hipSuccess) return fail(ED_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(le));
+        if (se != hipSuccess) return fail(ED_ERR_HIP, std::string("trajectory kernel: ") + hipGetErrorString(se));
+    }
+    // outputs to the host
+    std::vector<double> hsz(size_t(nt) * n_out * Lmax);
+    std::vector<int> hnj(nt), hmt(nt);
+    if (nt > 0) {
+        ED_HIP_TRY(hipMemcpy(hsz.data(), sz, sizeof(double) * hsz.size(), hipMemcpyDeviceToHost));
+        ED_HIP_TRY(hipMemcpy(hnj.data(), njumps, sizeof(int) * nt, hipMemcpyDeviceToHost));
+        ED_HIP_TRY(hipMemcpy(hmt.data(), mtot, sizeof(int) * nt, hipMemcpyDeviceToHost));
+    }
+    std::memcpy(out->sz, hsz.data(), sizeof(double) * hsz.size());
+    if (out->n_jumps) std::memcpy(out->n_jumps, hnj.data(), sizeof(int) * nt);
+    if ((out->jump_t || out->jump_site) && p->max_jumps > 0 && nt > 0) {
+        std::vector<double> hjt(size_t(nt) * mj);
+        std::vector<int> hjs(size_t(nt) * mj);
+        ED_HIP_TRY(hipMemcpy(hjt.data(), jt, sizeof(double) * hjt.size(), hipMemcpyDeviceToHost));
+        ED_HIP_TRY(hipMemcpy(hjs.data(), js, sizeof(int) * hjs.size(), hipMemcpyDeviceToHost));
+        if (out->jump_t) std::memcpy(out->jump_t, hjt.data(), sizeof(double) * hjt.size());
+        if (out->jump_site) std::memcpy(out->jump_site, hjs.data(), sizeof(int) * hjs.size());
+    }
+    if (info) {
+        long long tj = 0, tm = 0;
+        for (int i = 0; i < nt; ++i) {
+            tj += hnj[i];
+            tm += hmt[i];
+        }
+        info->total_jumps = tj;
+        info->total_krylov = tm;
+        info->blocks = G;
+    }
+    return ED_OK;
+}
+
+// ----------------------------------------------------------------------------- plain path
+// One trajectory at a time from the host: the Arnoldi basis from the stream-level kernels, the
+// small exponential, root search and jump choice on the host, the jump itself by a kernel.
+namespace ed {
+namespace {
+__global__ void apply_site_op(double2* psi, int L, int p, double2 j0, double2 j1, double2 j2, double2 j3) {
+    const int64_t half = int64_t(1) << (L - 1);
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= half) return;
+    const int64_t lowm = (int64_t(1) << p) - 1;
+    const int64_t x0 = ((q & ~lowm) << 1) | (q & lowm);
+    const int64_t x1 = x0 | (int64_t(1) << p);
+    const double2 a0 = psi[x0], a1 = psi[x1];
+    psi[x0] = make_double2(j0.x * a0.x - j0.y * a0.y + j1.x * a1.x - j1.y * a1.y, j0.x * a0.y + j0.y * a0.x + j1.x * a1.y + j1.y * a1.x);
+    psi[x1] = make_double2(j2.x * a0.x - j2.y * a0.y + j3.x * a1.x - j3.y * a1.y, j2.x * a0.y + j2.y * a0.x + j3.x * a1.y + j3.y * a1.x);
+}
+}  // namespace
+}  // namespace ed
+
+extern "C" ed_status ed_trajectories_plain_workspace(const ed_traj_desc* d, const ed_traj_params* p, size_t* bytes) {
+    if (!bytes) return fail(ED_ERR_ARG, "bytes is null");
+    ED_TRY(validate_traj(d, p));
+    int Lmax = 0;
+    for (int i = 0; i < d->n_models; ++i) Lmax = std::max(Lmax, d->models[i]->L);
+    *bytes = core_scratch_bytes() + al256(size_t(p->m_max + 2) * (size_t(1) << Lmax) * sizeof(double2));
+    return ED_OK;
+}
+
+extern "C" ed_status ed_trajectories_plain(const ed_traj_desc* d, const ed_traj_params* p, const ed_traj_out* out,
+                                           ed_traj_info* info, void* ws, size_t ws_bytes, void* stream) {
+    ED_TRY(validate_traj(d, p));
+    if (!out || !out->sz) return fail(ED_ERR_ARG, "output sz is null");
+    size_t need = 0;
+    ED_TRY(ed_trajectories_plain_workspace(d, p, &need));
+    if (!ws) return fail(ED_ERR_ARG, "workspace is null");
+    if (ws_bytes < need) return fail(ED_ERR_WORKSPACE, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TrajSetup st;
+    ED_TRY(build_setup(d, &st));
+    const int Lmax = st.Lmax, n_out = st.n_out, nt = d->n_traj;
+    const int mj = std::max(p->max_jumps, 1);
+    std::fill(out->sz, out->sz + size_t(nt) * n_out * Lmax, 0.0);
+    long long tot_j = 0, tot_m = 0;
+    for (int tr = 0; tr < nt; ++tr) {
+        const int mi = d->model_of_traj[tr];
+        const ed_model* hm = st.heff[mi];
+        const int L = hm->L;
+        const int64_t D = int64_t(1) << L;
+        Workspace w;
+        ED_TRY(carve(ws, ws_bytes, D, p->m_max + 2, &w));
+        double2* psi = w.V + int64_t(p->m_max + 1) * D;  // the state lives after the basis
+        ED_HIP_TRY(hipMemcpyAsync(psi, d->psi0[mi], sizeof(double2) * D, hipMemcpyDeviceToDevice, s));
+        double n0 = 0.0;
+        ED_TRY(start_vector(w, psi, &n0, s));
+        ED_HIP_TRY(hipMemcpyAsync(psi, w.V, sizeof(double2) * D, hipMemcpyDeviceToDevice, s));
+        uint64_t ndraw = 0;
+        auto draw = [&]() {
+            const double u = to_unit(philox_word(d->seed, uint64_t(tr), ndraw));
+            ++ndraw;
+            return u;
+        };
+        double r = draw();
+        int njump = 0;
+        double* szo = out->sz + size_t(tr) * n_out * Lmax;
+        auto record = [&](int slot) -> ed_status {
+            std::vector<double> szv(L);
+            ED_TRY(measure_state(psi, L, w, szv.data(), nullptr, s));
+            for (int k = 0; k < L; ++k) szo[size_t(slot) * Lmax + k] = szv[k];
+            return ED_OK;
+        };
+        ED_TRY(record(0));
+        for (int step = 0; step < d->n_steps; ++step) {
+            double tau_left = d->dt;
+            while (tau_left > 0.0) {
+                double nrm = 0.0;
+                ED_TRY(start_vector(w, psi, &nrm, s));
+                const double n2 = nrm * nrm;
+                const int mmax = p->m_max;
+                std::vector<cplx> T(size_t(mmax + 1) * (mmax + 1), 0.0), h(mmax + 1), u(mmax + 1);
+                int m = 0;
+                auto expv = [&](int mm, double tau, std::vector<cplx>& uu) {
+                    std::vector<cplx> A(size_t(mm) * mm), E(size_t(mm) * mm);
+                    for (int r2 = 0; r2 < mm; ++r2)
+                        for (int c2 = 0; c2 < mm; ++c2) A[size_t(r2) * mm + c2] = cplx(0.0, -tau) * T[size_t(r2) * (mmax + 1) + c2];
+                    expm_complex(mm, A.data(), E.data());
+                    for (int r2 = 0; r2 < mm; ++r2) uu[r2] = E[size_t(r2) * mm];
+                };
+                for (int j = 0; j < mmax; ++j) {
+                    double beta = 0.0;
+                    bool brk = false;
+                    ED_TRY(krylov_step(hm, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s));
+                    for (int i = 0; i <= j; ++i) T[size_t(i) * (mmax + 1) + j] = h[i];
+                    m = j + 1;
+                    expv(m, tau_left, u);
+                    const double err = brk ? 0.0 : nrm * beta * std::abs(u[m - 1]);
+                    if (brk || err <= p->tol || m >= mmax) break;
+                    T[size_t(j + 1) * (mmax + 1) + j] = beta;
+                }
+                tot_m += m;
+                auto lnorm = [&](const std::vector<cplx>& uu) {
+                    double q = 0.0;
+                    for (int i = 0; i < m; ++i) q += std::norm(uu[i]);
+                    return std::log(n2 * q);
+                };
+                const double lr = std::log(r);
+                const double f_end = lnorm(u) - lr;
+                auto combine = [&](const std::vector<cplx>& uu) -> ed_status {
+                    std::vector<double2> c(m);
+                    for (int i = 0; i < m; ++i) c[i] = make_double2(nrm * uu[i].real(), nrm * uu[i].imag());
+                    return combination(w.V, D, m, c.data(), psi, D, s) == hipSuccess ? ED_OK : fail(ED_ERR_HIP, "combination");
+                };
+                if (f_end > 0.0) {
+                    ED_TRY(combine(u));
+                    tau_left = 0.0;
+                    break;
+                }
+                double lo = 0.0, hi = tau_left, flo = std::log(n2) - lr, fhi = f_end, tau = hi;
+                if (flo <= 0.0) {
+                    tau = 0.0;
+                } else {
+                    int side = 0;
+                    for (int it = 0; it < 200; ++it) {
+                        double c = hi - fhi * (hi - lo) / (fhi - flo);
+                        if (!(c > lo && c < hi)) c = 0.5 * (lo + hi);
+                        expv(m, c, u);
+                        const double fc = lnorm(u) - lr;
+                        if (fc > 0.0) {
+                            lo = c;
+                            flo = fc;
+                            if (side == -1) fhi *= 0.5;
+                            side = -1;
+                        } else {
+                            hi = c;
+                            fhi = fc;
+                            if (side == 1) flo *= 0.5;
+                            side = 1;
+                        }
+                        tau = hi;
+                        if (fc == 0.0 || hi - lo <= 1e-15 * d->dt) {
+                            tau = (fc == 0.0) ? c : hi;
+                            break;
+                        }
+                    }
+                }
+                expv(m, tau, u);
+                ED_TRY(combine(u));
+                const double t_abs = step * d->dt + (d->dt - tau_left) + tau;
+                std::vector<double> szv(L);
+                double nn = 0.0;
+                ED_TRY(measure_state(psi, L, w, szv.data(), &nn, s));
+                const double rk = draw();
+                int kappa = L - 1;
+                double ptot = 0.0;
+                std::vector<double> pk(L);
+                for (int nu = 0; nu < L; ++nu) {
+                    const double up = 0.5 * (1.0 + szv[nu]) * nn * nn;
+                    pk[nu] = d->rates[mi][nu] * (st.jdj_up * up + st.jdj_dn * (nn * nn - up));
+                    ptot += pk[nu];
+                }
+                double cum = 0.0;
+                for (int nu = 0; nu < L; ++nu) {
+                    cum += pk[nu];
+                    if (rk <= cum / ptot) {
+                        kappa = nu;
+                        break;
+                    }
+                }
+                const ed_c64* J = d->jump_op;
+                const int64_t half = D / 2;
+                hipLaunchKernelGGL(apply_site_op, dim3(unsigned((half + 255) / 256)), dim3(256), 0, s, psi, L, L - 1 - kappa,
+                                   make_double2(J[0].re, J[0].im), make_double2(J[1].re, J[1].im),
+                                   make_double2(J[2].re, J[2].im), make_double2(J[3].re, J[3].im));
+                ED_HIP_TRY(hipGetLastError());
+                ED_TRY(start_vector(w, psi, &nn, s));
+                ED_HIP_TRY(hipMemcpyAsync(psi, w.V, sizeof(double2) * D, hipMemcpyDeviceToDevice, s));
+                if (njump < p->max_jumps) {
+                    if (out->jump_t) out->jump_t[size_t(tr) * mj + njump] = t_abs;
+                    if (out->jump_site) out->jump_site[size_t(tr) * mj + njump] = kappa;
+                }
+                ++njump;
+                r = draw();
+                tau_left -= tau;
+                if (tau_left <= 1e-15 * d->dt) tau_left = 0.0;
+            }
+            if ((step + 1) % d->out_stride == 0) ED_TRY(record((step + 1) / d->out_stride));
+        }
+        if (out->n_jumps) out->n_jumps[tr] = njump;
+        tot_j += njump;
+    }
+    ED_HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->total_jumps = tot_j;
+        info->total_krylov = tot_m;
+        info->blocks = 1;
+    }
+    return ED_OK;
+}
+
+// Raw Philox words as the trajectories draw them (for checking the generator against its
+// published definition): out[i] = word i of the stream of key (seed, id).
+namespace ed {
+namespace {
+__global__ void philox_words_kernel(uint64_t seed, uint64_t id, uint64_t* out, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = philox_word(seed, id, uint64_t(i));
+}
+}  // namespace
+}  // namespace ed
+
+extern "C" ed_status ed_philox_words(uint64_t seed, uint64_t id, uint64_t* out, int64_t n, void* stream) {
+    if (!out || n < 0) return fail(ED_ERR_ARG, "bad argument");
+    if (n == 0) return ED_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(philox_words_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, seed, id, out, n);
+    ED_HIP_TRY(hipGetLastError());
+    return ED_OK;
+}
