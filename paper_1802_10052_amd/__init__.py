@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import EdError, call, lib
 
-__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "EdError", "lib"]
+__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "trajectories", "philox_words", "EdError", "lib"]
 
 
 def _stream_ptr(stream=None):
@@ -155,3 +155,56 @@ def entropy(psi, L, l_cut=None, spectrum=False, stream=None):
     call("ed_entropy", _dptr(psi), int(L), 2, l, C.byref(S), spec.ctypes.data if spectrum else None,
          _dptr(ws), nb.value, _stream_ptr(stream))
     return (S.value, spec) if spectrum else S.value
+
+
+def trajectories(models, jump_op, rates, psi0, model_of_traj, dt, n_steps, out_stride, seed,
+                 m_max=20, tol=1e-10, max_jumps=64, plain=False, stream=None):
+    """Quantum trajectories (ed_trajectories_batch, or ed_trajectories_plain with plain=True).
+
+    models: list of Model (Hermitian parts, one per chain length); jump_op: 2x2 complex;
+    rates: list of per-site rate arrays; psi0: list of complex128 device states;
+    model_of_traj: int array. Returns dict with sz [n_traj, n_out, L_max], n_jumps, jump_t,
+    jump_site and info. Runs on a dedicated non-default stream (so the batched launch is replayed
+    from a hipGraph) and synchronises it."""
+    nm = len(models)
+    mh = (C.c_void_p * nm)(*[m.handle.value for m in models])
+    J = np.ascontiguousarray(np.asarray(jump_op, np.complex128).reshape(2, 2))
+    rk = [np.ascontiguousarray(r, np.float64) for r in rates]
+    rp = (C.c_void_p * nm)(*[r.ctypes.data for r in rk])
+    for i, p0 in enumerate(psi0):
+        _check_state(p0, models[i].D, "psi0")
+    pp = (C.c_void_p * nm)(*[p0.data_ptr() for p0 in psi0])
+    mo = np.ascontiguousarray(model_of_traj, np.int32)
+    nt = len(mo)
+    d = _lib.TrajDesc(nm, C.cast(mh, C.POINTER(C.c_void_p)), J.ctypes.data, C.cast(rp, C.POINTER(C.c_void_p)),
+                      C.cast(pp, C.POINTER(C.c_void_p)), nt, mo.ctypes.data, float(dt), int(n_steps),
+                      int(out_stride), int(seed))
+    p = _lib.TrajParams(int(m_max), float(tol), int(max_jumps))
+    nb = C.c_size_t()
+    name = "ed_trajectories_plain" if plain else "ed_trajectories_batch"
+    call(name.replace("_plain", "_plain_workspace") if plain else "ed_trajectories_workspace",
+         C.byref(d), C.byref(p), C.byref(nb))
+    dev = psi0[0].device
+    ws = _workspace(nb.value, dev)
+    Lmax = max(m.L for m in models)
+    n_out = n_steps // out_stride + 1
+    sz = np.zeros((nt, n_out, Lmax))
+    nj = np.zeros(nt, np.int32)
+    mj = max(int(max_jumps), 1)
+    jt = np.zeros((nt, mj))
+    js = np.zeros((nt, mj), np.int32)
+    o = _lib.TrajOut(sz.ctypes.data, nj.ctypes.data, jt.ctypes.data, js.ctypes.data)
+    info = _lib.TrajInfo()
+    st = stream if stream is not None else torch.cuda.Stream(device=dev)
+    st.wait_stream(torch.cuda.current_stream(dev))
+    call(name, C.byref(d), C.byref(p), C.byref(o), C.byref(info), _dptr(ws), nb.value, _stream_ptr(st))
+    return {"sz": sz, "n_jumps": nj, "jump_t": jt, "jump_site": js,
+            "info": {"total_jumps": info.total_jumps, "total_krylov": info.total_krylov, "blocks": info.blocks}}
+
+
+def philox_words(seed, ident, count, device="cuda:0", stream=None):
+    """Raw 64-bit words 0..count-1 of the trajectory random stream of key (seed, ident)."""
+    out = torch.empty(int(count), dtype=torch.int64, device=device)
+    call("ed_philox_words", int(seed), int(ident), _dptr(out), int(count), _stream_ptr(stream))
+    torch.cuda.synchronize(device)
+    return out.cpu().numpy().view(np.uint64)

@@ -47,6 +47,25 @@ class KrylovInfo(C.Structure):
     _fields_ = [("steps", C.c_int), ("total_m", C.c_int), ("max_m", C.c_int), ("max_err", C.c_double)]
 
 
+class TrajDesc(C.Structure):
+    _fields_ = [("n_models", C.c_int), ("models", C.POINTER(C.c_void_p)), ("jump_op", C.c_void_p),
+                ("rates", C.POINTER(C.c_void_p)), ("psi0", C.POINTER(C.c_void_p)), ("n_traj", C.c_int),
+                ("model_of_traj", C.c_void_p), ("dt", C.c_double), ("n_steps", C.c_int),
+                ("out_stride", C.c_int), ("seed", C.c_uint64)]
+
+
+class TrajParams(C.Structure):
+    _fields_ = [("m_max", C.c_int), ("tol", C.c_double), ("max_jumps", C.c_int)]
+
+
+class TrajOut(C.Structure):
+    _fields_ = [("sz", C.c_void_p), ("n_jumps", C.c_void_p), ("jump_t", C.c_void_p), ("jump_site", C.c_void_p)]
+
+
+class TrajInfo(C.Structure):
+    _fields_ = [("total_jumps", C.c_longlong), ("total_krylov", C.c_longlong), ("blocks", C.c_int)]
+
+
 ED_OK = 0
 STATUS = {0: "ED_OK", -1: "ED_ERR_ARG", -2: "ED_ERR_UNSUPPORTED", -3: "ED_ERR_NODEVICE",
           -4: "ED_ERR_NOMEM", -5: "ED_ERR_WORKSPACE", -6: "ED_ERR_HIP", -7: "ED_ERR_NOCONV",
@@ -90,6 +109,12 @@ def _declare(l):
                                 C.POINTER(KrylovInfo), P, C.c_size_t, P])
     _fn(l, "ed_measure_workspace", [C.c_int, S])
     _fn(l, "ed_entropy_workspace", [C.c_int, C.c_int, S])
+    TD, TP, TO, TI = C.POINTER(TrajDesc), C.POINTER(TrajParams), C.POINTER(TrajOut), C.POINTER(TrajInfo)
+    _fn(l, "ed_trajectories_workspace", [TD, TP, S])
+    _fn(l, "ed_trajectories_batch", [TD, TP, TO, TI, P, C.c_size_t, P])
+    _fn(l, "ed_trajectories_plain_workspace", [TD, TP, S])
+    _fn(l, "ed_trajectories_plain", [TD, TP, TO, TI, P, C.c_size_t, P])
+    _fn(l, "ed_philox_words", [C.c_uint64, C.c_uint64, P, C.c_int64, P])
     _fn(l, "ed_entropy", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, P, C.c_size_t, P])
     _fn(l, "ed_measure", [P, C.c_int, P, P, P, C.c_size_t, P])
 

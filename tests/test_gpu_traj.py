@@ -1,0 +1,111 @@
+"""GPU parity of the quantum-trajectory paths (Sec. VI.A) against the oracle on the same Philox
+streams, plus the closed forms that pin every trajectory of the dissipative XXZ chain:
+from the Neel state with [H, N_up] = 0 the no-jump norm is exp(-gamma n t), so jump times follow
+from the draws alone, and sum_k <sigma^z_k> = -2 (number of jumps so far) exactly."""
+import numpy as np
+import pytest
+import torch
+
+import edinputs as E
+import paper_1802_10052_amd as P
+from oracle import hamiltonian as OH
+from oracle import trajectories as OT
+from tests import closed_forms as CF
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GAMMA = 0.1
+
+
+def setup_batch(lengths, n_traj, seed=4):
+    models = [P.Model(E.xxz(L, 1.0, 1.0)) for L in lengths]
+    rates = [np.full(L, GAMMA) for L in lengths]
+    psi0 = [torch.from_numpy(E.product_state(L, E.neel_index(L))).to(DEV) for L in lengths]
+    mo = np.array([t % len(lengths) for t in range(n_traj)], np.int32)
+    return models, rates, psi0, mo
+
+
+def expected_jump_times(seed, tr, L, T):
+    d = OT.PhiloxDraws(seed, tr)
+    n, t, out = L // 2, 0.0, []
+    r = d.uniform()
+    while n > 0:
+        t = t - np.log(r) / (GAMMA * n)
+        if t > T:
+            break
+        d.uniform()
+        r = d.uniform()
+        n -= 1
+        out.append(t)
+    return out
+
+
+def test_philox_words_match_definition_and_numpy():
+    w = P.philox_words(4, 123, 1 << 20)
+    ref = np.random.Philox(key=[4, 123]).random_raw(1 << 20)
+    assert np.array_equal(w, ref)
+    first = CF.philox4x64_10([1, 0, 0, 0], [4, 123]) + CF.philox4x64_10([2, 0, 0, 0], [4, 123])
+    assert [int(x) for x in w[:8]] == first
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_trajectories_vs_oracle(plain):
+    lengths = [8, 10, 12]
+    n_traj, dt, steps, stride, seed = 6, 0.01, 300, 10, 4
+    models, rates, psi0, mo = setup_batch(lengths, n_traj, seed)
+    print(f"trajectories vs oracle plain={plain}", flush=True)
+    res = P.trajectories(models, E.SMINUS, rates, psi0, mo, dt, steps, stride, seed, m_max=20, tol=1e-12,
+                         plain=plain)
+    for tr in range(n_traj):
+        L = lengths[mo[tr]]
+        H = OH.hamiltonian_sparse(E.xxz(L, 1.0, 1.0))
+        ref = OT.trajectory(H, OT.lowering_jumps(L, GAMMA), E.product_state(L, E.neel_index(L)), dt, steps, stride,
+                            seed, tr, tol=1e-12)
+        nj = res["n_jumps"][tr]
+        assert nj == len(ref["jumps"]), (tr, nj, ref["jumps"])
+        assert np.allclose(res["jump_t"][tr, :nj], [j[0] for j in ref["jumps"]], rtol=0, atol=1e-10)
+        assert list(res["jump_site"][tr, :nj]) == [j[1] for j in ref["jumps"]]
+        assert np.max(np.abs(res["sz"][tr, :, :L] - ref["sz"])) < 1e-9
+
+
+def test_trajectory_closed_forms_mixed_lengths():
+    """Config-4 shape (mixed L = 8..16, Delta = 1, gamma = 0.1, dt = 0.01) over T = 2."""
+    lengths = [8, 10, 12, 14, 16]
+    n_traj, dt, steps, stride, seed = 60, 0.01, 200, 10, 4
+    models, rates, psi0, mo = setup_batch(lengths, n_traj, seed)
+    print("trajectory closed forms", flush=True)
+    res = P.trajectories(models, E.SMINUS, rates, psi0, mo, dt, steps, stride, seed, m_max=20, tol=1e-10)
+    n_out = steps // stride + 1
+    times = np.arange(n_out) * dt * stride
+    for tr in range(n_traj):
+        L = lengths[mo[tr]]
+        exp_t = expected_jump_times(seed, tr, L, dt * steps)
+        nj = res["n_jumps"][tr]
+        assert nj == len(exp_t), (tr, nj, exp_t)
+        assert np.allclose(res["jump_t"][tr, :nj], exp_t, rtol=0, atol=1e-8)
+        jumps_before = np.array([np.sum(np.array(exp_t) <= t) for t in times])
+        tot = res["sz"][tr, :, :L].sum(axis=1)
+        assert np.allclose(tot, -2.0 * jumps_before, atol=1e-8), tr
+        # every jump lowers a different site (each site can decay once)
+        assert len(set(res["jump_site"][tr, :nj])) == nj
+
+
+def test_batched_equals_plain():
+    lengths = [8, 12, 14]
+    n_traj, dt, steps, stride, seed = 6, 0.01, 60, 5, 9
+    models, rates, psi0, mo = setup_batch(lengths, n_traj, seed)
+    a = P.trajectories(models, E.SMINUS, rates, psi0, mo, dt, steps, stride, seed)
+    b = P.trajectories(models, E.SMINUS, rates, psi0, mo, dt, steps, stride, seed, plain=True)
+    assert np.array_equal(a["n_jumps"], b["n_jumps"])
+    assert np.max(np.abs(a["sz"] - b["sz"])) < 1e-10
+    for tr in range(n_traj):
+        nj = a["n_jumps"][tr]
+        assert np.allclose(a["jump_t"][tr, :nj], b["jump_t"][tr, :nj], atol=1e-12)
+
+
+def test_batched_deterministic():
+    lengths = [10, 16]
+    models, rates, psi0, mo = setup_batch(lengths, 8, 3)
+    a = P.trajectories(models, E.SMINUS, rates, psi0, mo, 0.01, 50, 10, 3)
+    b = P.trajectories(models, E.SMINUS, rates, psi0, mo, 0.01, 50, 10, 3)
+    assert np.array_equal(a["sz"], b["sz"]) and np.array_equal(a["jump_t"], b["jump_t"])
