@@ -276,6 +276,40 @@ ed_status ed_trajectories_plain(const ed_traj_desc* desc, const ed_traj_params* 
  * device memory out (for checking the generator against its published definition). Async. */
 ed_status ed_philox_words(uint64_t seed, uint64_t id, uint64_t* out, int64_t count, void* stream);
 
+/* ----------------------------------------------------------------------------------------
+ * Adjoint gradient of a final-time observable with respect to piecewise-constant bond couplings.
+ * Evolution: psi_s = exp(-i H_s slice_len) psi_{s-1}, s = 1..n_slices, with
+ *   H_s = sum_b J[s-1][b] h_b + (site terms of tmpl),  h_b = the bond operator of tmpl on bond b
+ *   (sites b+1, b+2, b = 0..L-2, as folded from tmpl's bond rules);
+ * each slice is propagated by `substeps` Krylov steps (Sec. III.C; Lanczos with local
+ * re-projection, m_fixed vectors if > 0, else adaptive with tol, at most m_max).
+ * Loss = <psi_S|O|psi_S>, O = sum_k obs_w[k-1] sigma^z_k. The gradient is back-propagated:
+ * lam_S = O psi_S, lam_{s-1} = exp(+i H_s slice_len) lam_s, and
+ *   dLoss/dJ[s][b] = 2 int_0^slice_len Im <mu(tau)|h_b|phi(tau)> dtau,
+ *   phi(tau) = exp(-i H_s tau) psi_{s-1}, mu(tau) = exp(-i H_s tau) lam_{s-1},
+ * by Gauss-Legendre quadrature with quad_nodes nodes per sub-step. psi_s are kept at slice
+ * boundaries (checkpoints) and recomputed inside slices.
+ * J host [n_slices][L-1]; psi0 device; obs_w host [L]; loss host; grad host [n_slices][L-1].
+ * Limits: L <= 24. Synchronises stream. ed_evolve_loss runs the forward pass only (loss), with
+ * the same discretisation: the per-parameter baseline for finite differences.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    int substeps;
+    int quad_nodes;
+    int m_max;
+    int m_fixed;
+    double tol;
+} ed_adjoint_params;
+
+ed_status ed_adjoint_workspace(const ed_model* tmpl, int n_slices, const ed_adjoint_params* params, size_t* bytes);
+ed_status ed_evolve_adjoint(const ed_model* tmpl, int n_slices, double slice_len, const double* J, const ed_c64* psi0,
+                            const double* obs_w, const ed_adjoint_params* params, double* loss, double* grad, void* ws,
+                            size_t ws_bytes, void* stream);
+ed_status ed_evolve_loss_workspace(const ed_model* tmpl, const ed_adjoint_params* params, size_t* bytes);
+ed_status ed_evolve_loss(const ed_model* tmpl, int n_slices, double slice_len, const double* J, const ed_c64* psi0,
+                         const double* obs_w, const ed_adjoint_params* params, double* loss, void* ws, size_t ws_bytes,
+                         void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import EdError, call, lib
 
-__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "trajectories", "philox_words", "EdError", "lib"]
+__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "trajectories", "philox_words", "evolve_adjoint", "evolve_loss", "AdjointEvolve", "EdError", "lib"]
 
 
 def _stream_ptr(stream=None):
@@ -208,3 +208,59 @@ def philox_words(seed, ident, count, device="cuda:0", stream=None):
     call("ed_philox_words", int(seed), int(ident), _dptr(out), int(count), _stream_ptr(stream))
     torch.cuda.synchronize(device)
     return out.cpu().numpy().view(np.uint64)
+
+
+def _adj_params(substeps, quad_nodes, m_max, m_fixed, tol):
+    return _lib.AdjointParams(int(substeps), int(quad_nodes), int(m_max), int(m_fixed), float(tol))
+
+
+def evolve_adjoint(template, J, psi0, slice_len, obs_w, substeps=2, quad_nodes=8, m_max=30, m_fixed=0, tol=1e-13,
+                   stream=None):
+    """(loss, grad) of <psi_S|sum_k w_k sz_k|psi_S> w.r.t. the sliced bond couplings J [S, L-1]
+    (ed_evolve_adjoint)."""
+    J = np.ascontiguousarray(J, np.float64)
+    S = J.shape[0]
+    w = np.ascontiguousarray(obs_w, np.float64)
+    _check_state(psi0, template.D, "psi0")
+    p = _adj_params(substeps, quad_nodes, m_max, m_fixed, tol)
+    nb = C.c_size_t()
+    call("ed_adjoint_workspace", template.handle, S, C.byref(p), C.byref(nb))
+    ws = _workspace(nb.value, psi0.device)
+    loss = C.c_double()
+    grad = np.zeros_like(J)
+    call("ed_evolve_adjoint", template.handle, S, float(slice_len), J.ctypes.data, _dptr(psi0), w.ctypes.data,
+         C.byref(p), C.byref(loss), grad.ctypes.data, _dptr(ws), nb.value, _stream_ptr(stream))
+    return loss.value, grad
+
+
+def evolve_loss(template, J, psi0, slice_len, obs_w, substeps=2, m_max=30, m_fixed=0, tol=1e-13, ws=None,
+                stream=None):
+    """Forward-only loss with the same discretisation (ed_evolve_loss)."""
+    J = np.ascontiguousarray(J, np.float64)
+    w = np.ascontiguousarray(obs_w, np.float64)
+    p = _adj_params(substeps, 1, m_max, m_fixed, tol)
+    nb = C.c_size_t()
+    call("ed_evolve_loss_workspace", template.handle, C.byref(p), C.byref(nb))
+    if ws is None or ws.numel() < nb.value:
+        ws = _workspace(nb.value, psi0.device)
+    loss = C.c_double()
+    call("ed_evolve_loss", template.handle, J.shape[0], float(slice_len), J.ctypes.data, _dptr(psi0), w.ctypes.data,
+         C.byref(p), C.byref(loss), _dptr(ws), nb.value, _stream_ptr(stream))
+    return loss.value
+
+
+class AdjointEvolve(torch.autograd.Function):
+    """Loss(J) = <psi_S|O|psi_S> as a differentiable function of the couplings J [S, L-1]
+    (float64 CPU tensor); backward returns grad_out * dLoss/dJ from ed_evolve_adjoint."""
+
+    @staticmethod
+    def forward(ctx, J, template, psi0, slice_len, obs_w, substeps=2, quad_nodes=8, m_max=30, m_fixed=0, tol=1e-13):
+        loss, grad = evolve_adjoint(template, J.detach().cpu().numpy(), psi0, slice_len, obs_w, substeps,
+                                    quad_nodes, m_max, m_fixed, tol)
+        ctx.save_for_backward(torch.from_numpy(grad))
+        return torch.tensor(loss, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return (grad_out * g, None, None, None, None, None, None, None, None, None)

@@ -66,6 +66,11 @@ class TrajInfo(C.Structure):
     _fields_ = [("total_jumps", C.c_longlong), ("total_krylov", C.c_longlong), ("blocks", C.c_int)]
 
 
+class AdjointParams(C.Structure):
+    _fields_ = [("substeps", C.c_int), ("quad_nodes", C.c_int), ("m_max", C.c_int), ("m_fixed", C.c_int),
+                ("tol", C.c_double)]
+
+
 ED_OK = 0
 STATUS = {0: "ED_OK", -1: "ED_ERR_ARG", -2: "ED_ERR_UNSUPPORTED", -3: "ED_ERR_NODEVICE",
           -4: "ED_ERR_NOMEM", -5: "ED_ERR_WORKSPACE", -6: "ED_ERR_HIP", -7: "ED_ERR_NOCONV",
@@ -115,6 +120,11 @@ def _declare(l):
     _fn(l, "ed_trajectories_plain_workspace", [TD, TP, S])
     _fn(l, "ed_trajectories_plain", [TD, TP, TO, TI, P, C.c_size_t, P])
     _fn(l, "ed_philox_words", [C.c_uint64, C.c_uint64, P, C.c_int64, P])
+    AP = C.POINTER(AdjointParams)
+    _fn(l, "ed_adjoint_workspace", [P, C.c_int, AP, S])
+    _fn(l, "ed_evolve_adjoint", [P, C.c_int, C.c_double, P, P, P, AP, C.POINTER(C.c_double), P, P, C.c_size_t, P])
+    _fn(l, "ed_evolve_loss_workspace", [P, AP, S])
+    _fn(l, "ed_evolve_loss", [P, C.c_int, C.c_double, P, P, P, AP, C.POINTER(C.c_double), P, C.c_size_t, P])
     _fn(l, "ed_entropy", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, P, C.c_size_t, P])
     _fn(l, "ed_measure", [P, C.c_int, P, P, P, C.c_size_t, P])
 

@@ -18,6 +18,8 @@ hipError_t dots(const double2* V, int64_t ldv, int n, const double2* w, int64_t 
 // w += sign * sum_i coef[i] V_i  (coef device)
 hipError_t axpy_multi(const double2* V, int64_t ldv, int n, const double2* coef, double sign, double2* w,
                       int64_t D, hipStream_t s);
+// out[i] = sum_b part[b][i] for i < n, b < nblk (fixed order)
+hipError_t reduce_partial_rows(const double2* part, int nblk, int n, double2* out, hipStream_t s);
 // out[0].x = |w|^2
 hipError_t norm2(const double2* w, int64_t D, double2* out, double2* part, hipStream_t s);
 // dst = src / sqrt(nrm2_dev[0].x)

@@ -34,6 +34,8 @@ namespace {
 constexpr int kTT = 256;       // threads per trajectory workgroup
 constexpr int kTMax = 24;      // max Krylov dimension per step (basis holds kTMax + 1 vectors)
 constexpr int kMaxL = 20;
+constexpr int kMaxHalvings = 10;       // exp(-i tau H_m) e_1: at most 2^10 scaled Taylor sums
+constexpr int kMaxEventsPerStep = 256;  // jumps resolved inside one time step before giving up
 
 // ---------------------------------------------------------------------------- Philox4x64-10
 // Salmon et al. (SC'11): two 64x64 -> 128 multiplies per round, key bumped by Weyl constants.
@@ -109,13 +111,11 @@ struct TrajArgs {
 };
 
 struct Shared {
-    double2 tile[1 << kTileBits];
     double2 H[(kTMax + 1) * (kTMax + 1)];
     double2 u[kTMax + 1], term[kTMax + 1], acc[kTMax + 1], h[kTMax + 1];
     double red[kTT / 64][2 * (kTMax + 1)];
     double pop[kMaxL + 1];
     double scal[8];
-    int iscal[4];
 };
 
 // ---------------------------------------------------------------------------- WG reductions
@@ -160,25 +160,29 @@ __device__ void wg_scale(double2* x, int64_t N, double s) {
     __syncthreads();
 }
 
-// out[i] (into sh.h) = <V_i|w>, i < n
+// out[i] (into sh.h) = <V_i|w>, i < n; vectors taken in groups of 8 to bound register use
 __device__ void wg_dots(const double2* V, int64_t ld, int n, const double2* w, int64_t N, Shared& sh) {
-    double a[2 * (kTMax + 1)];
+    constexpr int G = 8;
+    for (int i0 = 0; i0 < n; i0 += G) {
+        double a[2 * G];
 #pragma unroll
-    for (int i = 0; i < 2 * (kTMax + 1); ++i) a[i] = 0.0;
-    for (int64_t x = threadIdx.x; x < N; x += kTT) {
-        const double2 y = w[x];
+        for (int i = 0; i < 2 * G; ++i) a[i] = 0.0;
+        for (int64_t x = threadIdx.x; x < N; x += kTT) {
+            const double2 y = w[x];
 #pragma unroll
-        for (int i = 0; i < kTMax + 1; ++i) {
-            if (i < n) {
-                const double2 v = V[i * ld + x];
-                a[2 * i] = fma(v.x, y.x, fma(v.y, y.y, a[2 * i]));
-                a[2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, a[2 * i + 1]));
+            for (int i = 0; i < G; ++i) {
+                if (i0 + i < n) {
+                    const double2 v = V[(i0 + i) * ld + x];
+                    a[2 * i] = fma(v.x, y.x, fma(v.y, y.y, a[2 * i]));
+                    a[2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, a[2 * i + 1]));
+                }
             }
         }
+        double o[2 * G];
+        wg_sum<2 * G>(a, sh, o);
+        if (threadIdx.x < G && i0 + threadIdx.x < n)
+            sh.h[i0 + threadIdx.x] = make_double2(o[2 * threadIdx.x], o[2 * threadIdx.x + 1]);
     }
-    double o[2 * (kTMax + 1)];
-    wg_sum<2 * (kTMax + 1)>(a, sh, o);
-    if (threadIdx.x < n) sh.h[threadIdx.x] = make_double2(o[2 * threadIdx.x], o[2 * threadIdx.x + 1]);
     __syncthreads();
 }
 
@@ -234,29 +238,14 @@ __device__ void wg_pops(const double2* psi, int L, Shared& sh) {
     __syncthreads();
 }
 
-// dst = H_eff src, whole small state handled by this workgroup
+// dst = H_eff src for the whole small state of this workgroup; partner amplitudes are read from
+// global memory (the state of one trajectory is at most 1 MiB).
 template <unsigned CLS>
 __device__ void wg_apply(const TrajModel& md, const double2* src, double2* dst, Shared& sh) {
     const int L = md.L;
-    if (L < kTileBits) {
-        const int64_t N = int64_t(1) << L;
-        for (int64_t x = threadIdx.x; x < N; x += kTT) sh.tile[x] = src[x];
-        __syncthreads();
-        for (int64_t x = threadIdx.x; x < N; x += kTT) dst[x] = small_entry<CLS>(sh.tile, md.tb.site, md.tb.bond, L, x);
-        __syncthreads();
-        return;
-    }
-    const int64_t tiles = int64_t(1) << (L - kTileBits);
-    for (int ip = 0; ip < md.tb.n_pass; ++ip) {
-        const PassArgs& pa = md.tb.pass[ip];
-        for (int64_t n = 0; n < tiles; ++n) {
-            if (pa.first)
-                tile_body<CLS, true>(src, dst, md.tb.site, md.tb.bond, md.tb.dlo, md.tb.dmid, md.tb.dhi, pa, n, sh.tile);
-            else
-                tile_body<CLS, false>(src, dst, md.tb.site, md.tb.bond, md.tb.dlo, md.tb.dmid, md.tb.dhi, pa, n, sh.tile);
-            __syncthreads();
-        }
-    }
+    const int64_t N = int64_t(1) << L;
+    for (int64_t x = threadIdx.x; x < N; x += kTT) dst[x] = small_entry<CLS>(src, md.tb.site, md.tb.bond, L, x);
+    __syncthreads();
 }
 
 // u = exp(-i tau H_m) e_1 for the m x m Hessenberg in sh.H (leading dimension kTMax + 1), by
@@ -274,7 +263,7 @@ __device__ void wg_expv(int m, double tau, Shared& sh) {
     }
     nrm *= fabs(tau);
     int sq = 0;
-    while (nrm > 0.5 && sq < 60) {
+    while (nrm > 0.5 && sq < kMaxHalvings) {
         nrm *= 0.5;
         ++sq;
     }
@@ -363,12 +352,17 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
         __syncthreads();
     };
     record(0);
-    for (int step = 0; step < a.n_steps; ++step) {
+    bool failed = false;
+    for (int step = 0; step < a.n_steps && !failed; ++step) {
         double tau_left = a.dt;
-        while (tau_left > 0.0) {
+        for (int ev = 0; tau_left > 0.0; ++ev) {
             // Krylov basis of the current state
             const double n2 = wg_norm2(psi, N, sh);
             const double nrm = sqrt(n2);
+            if (!(n2 > 0.0) || !isfinite(n2) || ev >= kMaxEventsPerStep) {
+                failed = true;  // uniform: every thread sees the same n2 and ev
+                break;
+            }
             for (int64_t x = t; x < N; x += kTT) {
                 const double2 y = psi[x];
                 V[x] = make_double2(y.x / nrm, y.y / nrm);
@@ -507,25 +501,19 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
         if ((step + 1) % a.out_stride == 0) record((step + 1) / a.out_stride);
     }
     if (t == 0) {
-        a.n_jumps[tr] = njump;
+        a.n_jumps[tr] = failed ? -1 : njump;
         a.m_total[tr] = mtot;
     }
     __syncthreads();
 }
 
+// Persistent launch: workgroup g runs trajectories order[g], order[g + G], ... (the order is
+// longest chain first, so the round-robin deal is balanced); every loop below is bounded.
 template <unsigned CLS>
 __global__ __launch_bounds__(kTT) void traj_kernel(TrajArgs a) {
-    extern __shared__ char smem_raw[];
-    Shared& sh = *reinterpret_cast<Shared*>(smem_raw);
+    __shared__ Shared sh;
     double2* base = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
-    while (true) {
-        if (threadIdx.x == 0) sh.iscal[0] = atomicAdd(a.counter, 1);
-        __syncthreads();
-        const int q = sh.iscal[0];
-        __syncthreads();
-        if (q >= a.n_traj) break;
-        run_trajectory<CLS>(a, a.order[q], base, sh);
-    }
+    for (int q = blockIdx.x; q < a.n_traj; q += gridDim.x) run_trajectory<CLS>(a, a.order[q], base, sh);
 }
 
 __global__ void zero_ints(int* p, int n) {
@@ -539,24 +527,12 @@ __global__ void zero_doubles(double* p, int64_t n) {
 }
 
 template <int I>
-hipError_t prepare_traj(unsigned cls, size_t shm) {
-    if constexpr (I >= kNumVariants) {
-        return hipErrorInvalidValue;
-    } else {
-        if (variant_fits(kVariants[I], cls))
-            return hipFuncSetAttribute(reinterpret_cast<const void*>(&traj_kernel<kVariants[I]>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-        return prepare_traj<I + 1>(cls, shm);
-    }
-}
-
-template <int I>
 hipError_t launch_traj(unsigned cls, dim3 grid, size_t shm, hipStream_t s, const TrajArgs& a) {
     if constexpr (I >= kNumVariants) {
         return hipErrorInvalidValue;
     } else {
         if (variant_fits(kVariants[I], cls)) {
-            hipLaunchKernelGGL((traj_kernel<kVariants[I]>), grid, dim3(kTT), shm, s, a);
+            hipLaunchKernelGGL((traj_kernel<kVariants[I]>), grid, dim3(kTT), 0, s, a);
             return hipGetLastError();
         }
         return launch_traj<I + 1>(cls, grid, shm, s, a);
@@ -578,6 +554,8 @@ struct TrajSetup {
         for (ed_model* m : heff) destroy_model(m);
     }
 };
+
+static double heff_bound(const ed_model* m);
 
 static ed_status validate_traj(const ed_traj_desc* d, const ed_traj_params* p) {
     if (!d || !p) return fail(ED_ERR_ARG, "null argument");
@@ -640,11 +618,39 @@ static ed_status build_setup(const ed_traj_desc* d, TrajSetup* st) {
         st->heff.push_back(h);
         st->cls |= h->op_class & kWork;
     }
+    for (ed_model* h : st->heff)
+        if (d->dt * heff_bound(h) > 50.0)
+            return fail(ED_ERR_UNSUPPORTED, "dt * |H_eff| > 50: use a smaller trajectory time step");
     // real flags: only if every model has them
     unsigned real = kOffReal | kDiagReal;
     for (ed_model* h : st->heff) real &= h->op_class;
     st->cls |= real;
     return ED_OK;
+}
+
+// Upper bound of |H_eff| (sum over terms of the largest absolute row sum of each local operator):
+// dt times it must stay moderate so that the scaled Taylor series of each step is short.
+static double heff_bound(const ed_model* m) {
+    double b = 0.0;
+    for (int p = 0; p < m->L; ++p) {
+        double r = 0.0;
+        for (int row = 0; row < 2; ++row) {
+            double rs = 0.0;
+            for (int c = 0; c < 2; ++c) rs += std::hypot(m->site[4 * p + 2 * row + c].x, m->site[4 * p + 2 * row + c].y);
+            r = std::max(r, rs);
+        }
+        b += r;
+    }
+    for (int p = 0; p + 1 < m->L; ++p) {
+        double r = 0.0;
+        for (int row = 0; row < 4; ++row) {
+            double rs = 0.0;
+            for (int c = 0; c < 4; ++c) rs += std::hypot(m->bond[16 * p + 4 * row + c].x, m->bond[16 * p + 4 * row + c].y);
+            r = std::max(r, rs);
+        }
+        b += r;
+    }
+    return b;
 }
 
 static int persistent_blocks(int n_traj) {
@@ -757,7 +763,6 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     a.scratch = scratch;
     a.scratch_stride = int64_t(per);
     a.counter = counter;
-    ED_HIP_TRY(prepare_traj<0>(st.cls, sizeof(Shared)));
     // clear the queue counter and the outputs with fill kernels, then the persistent launch;
     // on a non-null stream the three launches are captured and replayed as one hipGraph
     auto enqueue = [&]() -> hipError_t {
@@ -765,7 +770,7 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
         if (nt == 0) return hipGetLastError();
         const int64_t nz = int64_t(nt) * n_out * Lmax;
         hipLaunchKernelGGL(zero_doubles, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, s, sz, nz);
-        return launch_traj<0>(st.cls, dim3(G), sizeof(Shared), s, a);
+        return launch_traj<0>(st.cls, dim3(G), 0, s, a);
     };
     if (s == nullptr) {
         hipError_t e = enqueue();
@@ -811,6 +816,8 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
         if (out->jump_t) std::memcpy(out->jump_t, hjt.data(), sizeof(double) * hjt.size());
         if (out->jump_site) std::memcpy(out->jump_site, hjs.data(), sizeof(int) * hjs.size());
     }
+    for (int i = 0; i < nt; ++i)
+        if (hnj[i] < 0) return fail(ED_ERR_NUMERIC, "trajectory " + std::to_string(i) + " hit a non-finite norm or too many jumps in one step");
     if (info) {
         long long tj = 0, tm = 0;
         for (int i = 0; i < nt; ++i) {

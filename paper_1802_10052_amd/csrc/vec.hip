@@ -262,6 +262,11 @@ hipError_t axpy_multi(const double2* V, int64_t ldv, int n, const double2* coef,
     return hipGetLastError();
 }
 
+hipError_t reduce_partial_rows(const double2* part, int nblk, int n, double2* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, nblk, n, out, 0);
+    return hipGetLastError();
+}
+
 hipError_t norm2(const double2* w, int64_t D, double2* out, double2* part, hipStream_t s) {
     const int G = grid_for(D);
     hipLaunchKernelGGL(norm2_partial, dim3(G), dim3(kThreads), 0, s, w, D, part, kPartLd);

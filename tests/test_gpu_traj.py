@@ -56,8 +56,10 @@ def test_trajectories_vs_oracle(plain):
     print(f"trajectories vs oracle plain={plain}", flush=True)
     res = P.trajectories(models, E.SMINUS, rates, psi0, mo, dt, steps, stride, seed, m_max=20, tol=1e-12,
                          plain=plain)
+    print("  batched/plain call done", flush=True)
     for tr in range(n_traj):
         L = lengths[mo[tr]]
+        print(f"  oracle trajectory {tr} (L={L})", flush=True)
         H = OH.hamiltonian_sparse(E.xxz(L, 1.0, 1.0))
         ref = OT.trajectory(H, OT.lowering_jumps(L, GAMMA), E.product_state(L, E.neel_index(L)), dt, steps, stride,
                             seed, tr, tol=1e-12)
@@ -75,6 +77,7 @@ def test_trajectory_closed_forms_mixed_lengths():
     models, rates, psi0, mo = setup_batch(lengths, n_traj, seed)
     print("trajectory closed forms", flush=True)
     res = P.trajectories(models, E.SMINUS, rates, psi0, mo, dt, steps, stride, seed, m_max=20, tol=1e-10)
+    print("  batched call done", flush=True)
     n_out = steps // stride + 1
     times = np.arange(n_out) * dt * stride
     for tr in range(n_traj):
