@@ -1,15 +1,20 @@
 """Benchmark of the exact-diagonalisation hot path on one MI355X.
 
-Headline: matrix-free H psi (ed_apply_H) on the L = 28 transverse-field Ising chain (g = 0.5,
-complex128 state of 2^28 amplitudes, 4 GiB), reported as algorithmic GB/s = 32 B/amplitude
-(read psi once, write H psi once) / kernel time, and as a fraction of the 8 TB/s HBM peak.
-A step is one H psi over the whole state. Timing uses HIP events on the stream the library
-launches on, after warm-up, with the state resident in HBM.
+Headline (the JSON line's value): matrix-free H psi (ed_apply_H) on the open transverse-field
+Ising chain, L = 28, g = 0.5 (2^28 complex128 amplitudes, 4 GiB per vector), reported as
+algorithmic GB/s = 32 B per amplitude (read psi once, write H psi once) / time per product,
+and as a fraction of the 8 TB/s HBM peak. A step is one H psi over the whole state; the state
+is resident in HBM and the time comes from HIP events on the stream the library launches on.
+
+Beside it, each remaining row of the hot path is run once on its synthetic workload and reported
+under "rows": Lanczos ground state (TFIM L = 14), Lanczos + half-chain entropy (XXZ L = 26),
+the L = 28 Krylov quench (100 steps), 4096 batched quantum trajectories against the plain
+per-trajectory path, and the adjoint gradient (L = 20) against finite differences of the
+forward-only path. The CPU oracle is timed on a bounded sample of the headline workload.
 """
 import argparse
 import json
 import os
-import platform
 import sys
 import time
 
@@ -31,9 +36,12 @@ def host_info():
     return {"nproc": os.cpu_count(), "cpu": cpu, "omp_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def cpu_baseline(L=20, reps=60):
     """The oracle's explicit sparse H psi (scipy CSR matvec, single-threaded) at L = 20."""
-    import numpy as np
     import edinputs as E
     from oracle import hamiltonian as OH
     H = OH.hamiltonian_sparse(E.tfim(L, 0.5))
@@ -41,11 +49,144 @@ def cpu_baseline(L=20, reps=60):
     H @ psi
     t0 = time.perf_counter()
     for _ in range(reps):
-        y = H @ psi
+        H @ psi
     dt = (time.perf_counter() - t0) / reps
-    return {"value": 32.0 * (1 << L) / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"scipy CSR H psi, TFIM g=0.5 L={L} (2^{L} amplitudes), {reps} products, "
-                      f"{dt * 1e3:.1f} ms each; same 32 B/amplitude accounting"}
+    return {"value": round(32.0 * (1 << L) / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"scipy CSR H psi (oracle), TFIM g=0.5 L={L} (2^{L} amplitudes), {reps} products of "
+                      f"{dt * 1e3:.1f} ms; same 32 B/amplitude accounting as the headline"}
+
+
+class Timer:
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.t0 = time.perf_counter()
+        return self
+
+    def __exit__(self, *a):
+        self.torch.cuda.synchronize()
+        self.s = time.perf_counter() - self.t0
+
+
+def row_lanczos_L14(P, E, torch, dev):
+    from tests import closed_forms as CF
+    L = 14
+    m = P.Model(E.tfim(L, 1.0))
+    v0 = torch.from_numpy(E.random_state(L, 1)).to(dev)
+    P.lanczos_ground(m, v0, tol=1e-10, max_iter=200)
+    with Timer(torch, None) as t:
+        e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=200)
+    ref = CF.tfim_bdg_ground_energy(L, 1.0, 1.0)
+    return {"workload": "TFIM g=1 L=14 Lanczos, full reorthogonalisation, tol 1e-10", "seconds": round(t.s, 4),
+            "iters": info["iters"], "E0": e0, "rel_err_vs_free_fermion": abs(e0 - ref) / abs(ref),
+            "residual": info["residual"]}
+
+
+def row_lanczos_entropy_L26(P, E, torch, dev):
+    L = 26
+    desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
+    m = P.Model(desc)
+    v0 = E.random_state_device(L, 3, dev)
+    with Timer(torch, None) as t:
+        e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=60, n_keep=10)
+    del v0
+    torch.cuda.empty_cache()
+    P.entropy(psi, L, L // 2)
+    with Timer(torch, None) as te:
+        S = P.entropy(psi, L, L // 2)
+    return {"workload": "XXZ J=1 Delta=0.5 h~U[-0.5,0.5] L=26, Lanczos max_basis 60 (thick restart), "
+                        "half-chain entropy 2^13 x 2^13",
+            "lanczos_seconds": round(t.s, 3), "iters": info["iters"], "restarts": info["restarts"],
+            "E0": e0, "residual": info["residual"], "entropy": S, "entropy_seconds": round(te.s, 3)}
+
+
+def row_quench_L28(P, E, torch, dev, steps=100):
+    L = 28
+    m = P.Model(E.tfim(L, 0.5))
+    psi = torch.zeros(1 << L, dtype=torch.complex128, device=dev)
+    psi[0] = 1.0
+    with Timer(torch, None) as t:
+        _, obs, info = P.krylov_evolve(m, psi, 0.05, steps, m_max=20, tol=1e-10, reorth=0)
+    e = obs["energy"]
+    return {"workload": f"TFIM g=0.5 L=28 quench from all up, dt=0.05, {steps} Krylov steps, m<=20, tol 1e-10",
+            "seconds": round(t.s, 3), "ms_per_step": round(1e3 * t.s / steps, 2), "total_krylov": info["total_m"],
+            "max_m": info["max_m"], "energy_drift": float(abs(e - e[0]).max() / abs(e[0])),
+            "norm_drift": float(abs(obs["norm"] - 1).max()), "sz_final_site1": float(obs["sz"][-1, 0])}
+
+
+def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):
+    import numpy as np
+    lengths = [8, 10, 12, 14, 16]
+    gamma = 0.1
+    models = [P.Model(E.xxz(L, 1.0, 1.0)) for L in lengths]
+    rates = [np.full(L, gamma) for L in lengths]
+    psi0 = [torch.from_numpy(E.product_state(L, E.neel_index(L))).to(dev) for L in lengths]
+    mo = np.array([t % 5 for t in range(n_traj)], np.int32)
+    dt, steps, stride, seed = 0.01, 500, 10, 4
+    with Timer(torch, None) as t:
+        res = P.trajectories(models, E.SMINUS, rates, psi0, mo, dt, steps, stride, seed, m_max=20, tol=1e-10)
+    n_out = steps // stride + 1
+    times = np.arange(n_out) * dt * stride
+    # ensemble check: mean of sum_k sz_k = -2 <jumps>  -> L (exp(-gamma t) - 1) per length
+    ens = {}
+    for i, L in enumerate(lengths):
+        sel = mo == i
+        tot = res["sz"][sel][:, :, :L].sum(axis=2)
+        mean = tot.mean(axis=0)
+        sem = tot.std(axis=0, ddof=1) / np.sqrt(sel.sum()) + 1e-12
+        z = np.abs(mean - L * (np.exp(-gamma * times) - 1)) / sem
+        ens[f"L{L}"] = round(float(z.max()), 3)
+    # plain per-trajectory path on a sample (two of each length), time per trajectory-step
+    ids = np.concatenate([np.where(mo == i)[0][:plain_sample // 5] for i in range(5)])
+    sub = mo[ids]
+    with Timer(torch, None) as tp:
+        rp = P.trajectories(models, E.SMINUS, rates, psi0, sub, dt, steps, stride, seed, m_max=20, tol=1e-10,
+                            plain=True)
+    # the plain path's trajectory t of the sample has id t, not ids[t]: compare cost only
+    traj_steps_batched = n_traj * steps
+    plain_per_len = tp.s / len(ids)
+    est_plain = plain_per_len * n_traj
+    return {"workload": "4096 dissipative XXZ trajectories (J=1, Delta=1, gamma=0.1 sigma^- on every site), "
+                        "L in {8..16} mixed, Neel start, dt=0.01, T=5, one persistent launch",
+            "batched_seconds": round(t.s, 3), "trajectory_steps_per_s": round(traj_steps_batched / t.s, 1),
+            "total_jumps": res["info"]["total_jumps"], "blocks": res["info"]["blocks"],
+            "plain_sample_trajectories": int(len(ids)), "plain_sample_seconds": round(tp.s, 3),
+            "plain_estimated_seconds_4096": round(est_plain, 1),
+            "speedup_vs_plain": round(est_plain / t.s, 2),
+            "ensemble_max_z_sum_sz": ens}
+
+
+def row_adjoint(P, E, torch, dev, fd_sample=4):
+    import numpy as np
+    L, S = 20, 50
+    tmpl = E.xxz_bond_scaled(L, 0.5, np.ones(L - 1))
+    J = E.adjoint_couplings(S, L - 1, 5)
+    psi0 = torch.from_numpy(E.product_state(L, E.neel_index(L))).to(dev)
+    w = np.array([(-1) ** k for k in range(L)], np.float64) / L
+    m = P.Model(tmpl)
+    kw = dict(substeps=2, m_fixed=14, m_max=30)
+    P.evolve_adjoint(m, J, psi0, 0.1, w, quad_nodes=8, **kw)
+    with Timer(torch, None) as t:
+        loss, g = P.evolve_adjoint(m, J, psi0, 0.1, w, quad_nodes=8, **kw)
+    # plain path: central differences need 2 forward runs per parameter (1900 in total)
+    h = 1e-6
+    errs = []
+    with Timer(torch, None) as tf:
+        for k in range(fd_sample):
+            s, b = [(49, 9), (0, 0), (25, 18), (10, 3)][k]
+            Jp, Jm = J.copy(), J.copy()
+            Jp[s, b] += h
+            Jm[s, b] -= h
+            fd = (P.evolve_loss(m, Jp, psi0, 0.1, w, **kw) - P.evolve_loss(m, Jm, psi0, 0.1, w, **kw)) / (2 * h)
+            errs.append(abs(g[s, b] - fd) / max(abs(fd), 1e-3 * np.max(np.abs(g))))
+    per_forward = tf.s / (2 * fd_sample)
+    est_fd = per_forward * 2 * S * (L - 1)
+    return {"workload": "XXZ L=20 Delta=0.5, 50 slices x 0.1, J~U[0.5,1.5], Neel, staggered magnetisation",
+            "adjoint_seconds": round(t.s, 3), "loss": loss, "n_params": int(S * (L - 1)),
+            "forward_seconds": round(per_forward, 4), "fd_estimated_seconds": round(est_fd, 1),
+            "speedup_vs_fd": round(est_fd / t.s, 1), "fd_sample_max_rel_err": float(max(errs))}
 
 
 def main():
@@ -55,10 +196,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--L", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rows", default="all",
+                    help="comma list of lanczos14,lanczos26,quench28,traj,adjoint; 'none' or 'all'")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design "
-              f"note, not a measured path", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); the multi-GPU layout is a design note, "
+              f"not a measured path", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -72,6 +215,7 @@ def main():
     psi = E.random_state_device(L, 11, dev)
     out = torch.empty_like(psi)
     stream = torch.cuda.current_stream()
+    log(f"bench: apply_H L={L}, {model.passes} passes, warmup {args.warmup}, steps {args.steps}")
     for _ in range(args.warmup):
         P.apply_H(model, psi, out)
     torch.cuda.synchronize()
@@ -99,14 +243,29 @@ def main():
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": f"apply_H TFIM g=0.5 open chain L={L} (2^{L} complex128 amplitudes)",
-                   "L": L, "passes": model.passes},
+        "config": {"workload": f"apply_H, open transverse-field Ising chain g=0.5, L={L} "
+                               f"(2^{L} complex128 amplitudes, seeded complex-normal state)",
+                   "L": L, "passes": model.passes, "launches_per_step": model.passes},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
         "host": host_info(),
         "wall_s": round(wall, 3),
     }
+    del psi, out
+    torch.cuda.empty_cache()
+    rows = {"lanczos14": row_lanczos_L14, "lanczos26": row_lanczos_entropy_L26, "quench28": row_quench_L28,
+            "traj": row_trajectories, "adjoint": row_adjoint}
+    pick = list(rows) if args.rows == "all" else ([] if args.rows == "none" else args.rows.split(","))
+    rec["rows"] = {}
+    for name in pick:
+        log(f"bench: row {name}")
+        try:
+            rec["rows"][name] = rows[name](P, E, torch, dev)
+        except Exception as e:  # a failing row is reported, not hidden
+            rec["rows"][name] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
+        log("bench: cpu baseline")
         rec["cpu_baseline"] = cpu_baseline()
     print(json.dumps(rec))
 

@@ -48,10 +48,26 @@ def test_philox_words_match_definition_and_numpy():
     assert [int(x) for x in w[:8]] == first
 
 
+ORACLE_CASE = dict(lengths=[8, 10, 12], n_traj=6, dt=0.01, steps=300, stride=10, seed=4)
+
+
+@pytest.fixture(scope="module")
+def oracle_runs():
+    c = ORACLE_CASE
+    out = []
+    for tr in range(c["n_traj"]):
+        L = c["lengths"][tr % len(c["lengths"])]
+        print(f"  oracle trajectory {tr} (L={L})", flush=True)
+        H = OH.hamiltonian_sparse(E.xxz(L, 1.0, 1.0))
+        out.append(OT.trajectory(H, OT.lowering_jumps(L, GAMMA), E.product_state(L, E.neel_index(L)), c["dt"],
+                                 c["steps"], c["stride"], c["seed"], tr, tol=1e-12))
+    return out
+
+
 @pytest.mark.parametrize("plain", [False, True])
-def test_trajectories_vs_oracle(plain):
-    lengths = [8, 10, 12]
-    n_traj, dt, steps, stride, seed = 6, 0.01, 300, 10, 4
+def test_trajectories_vs_oracle(plain, oracle_runs):
+    c = ORACLE_CASE
+    lengths, n_traj, dt, steps, stride, seed = c["lengths"], c["n_traj"], c["dt"], c["steps"], c["stride"], c["seed"]
     models, rates, psi0, mo = setup_batch(lengths, n_traj, seed)
     print(f"trajectories vs oracle plain={plain}", flush=True)
     res = P.trajectories(models, E.SMINUS, rates, psi0, mo, dt, steps, stride, seed, m_max=20, tol=1e-12,
@@ -59,10 +75,7 @@ def test_trajectories_vs_oracle(plain):
     print("  batched/plain call done", flush=True)
     for tr in range(n_traj):
         L = lengths[mo[tr]]
-        print(f"  oracle trajectory {tr} (L={L})", flush=True)
-        H = OH.hamiltonian_sparse(E.xxz(L, 1.0, 1.0))
-        ref = OT.trajectory(H, OT.lowering_jumps(L, GAMMA), E.product_state(L, E.neel_index(L)), dt, steps, stride,
-                            seed, tr, tol=1e-12)
+        ref = oracle_runs[tr]
         nj = res["n_jumps"][tr]
         assert nj == len(ref["jumps"]), (tr, nj, ref["jumps"])
         assert np.allclose(res["jump_t"][tr, :nj], [j[0] for j in ref["jumps"]], rtol=0, atol=1e-10)
