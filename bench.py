@@ -93,13 +93,17 @@ def row_lanczos_entropy_L26(P, E, torch, dev):
         e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=60, n_keep=10)
     del v0
     torch.cuda.empty_cache()
-    P.entropy(psi, L, L // 2)
-    with Timer(torch, None) as te:
-        S = P.entropy(psi, L, L // 2)
-    return {"workload": "XXZ J=1 Delta=0.5 h~U[-0.5,0.5] L=26, Lanczos max_basis 60 (thick restart), "
-                        "half-chain entropy 2^13 x 2^13",
-            "lanczos_seconds": round(t.s, 3), "iters": info["iters"], "restarts": info["restarts"],
-            "E0": e0, "residual": info["residual"], "entropy": S, "entropy_seconds": round(te.s, 3)}
+    rec = {"workload": "XXZ J=1 Delta=0.5 h~U[-0.5,0.5] L=26, Lanczos max_basis 60 (thick restart), "
+                       "half-chain entropy 2^13 x 2^13",
+           "lanczos_seconds": round(t.s, 3), "iters": info["iters"], "restarts": info["restarts"],
+           "E0": e0, "residual": info["residual"], "converged": info["converged"]}
+    try:
+        with Timer(torch, None) as te:
+            S = P.entropy(psi, L, L // 2)
+        rec.update({"entropy": S, "entropy_seconds": round(te.s, 3)})
+    except Exception as e:
+        rec["entropy_error"] = f"{type(e).__name__}: {e}"
+    return rec
 
 
 def row_quench_L28(P, E, torch, dev, steps=100):
@@ -166,7 +170,7 @@ def row_adjoint(P, E, torch, dev, fd_sample=4):
     psi0 = torch.from_numpy(E.product_state(L, E.neel_index(L))).to(dev)
     w = np.array([(-1) ** k for k in range(L)], np.float64) / L
     m = P.Model(tmpl)
-    kw = dict(substeps=2, m_fixed=14, m_max=30)
+    kw = dict(substeps=2, m_fixed=20, m_max=30)
     P.evolve_adjoint(m, J, psi0, 0.1, w, quad_nodes=8, **kw)
     with Timer(torch, None) as t:
         loss, g = P.evolve_adjoint(m, J, psi0, 0.1, w, quad_nodes=8, **kw)
@@ -196,6 +200,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--L", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of the 4 GiB state first (known bytes, for scaling "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--rows", default="all",
                     help="comma list of lanczos14,lanczos26,quench28,traj,adjoint; 'none' or 'all'")
     args = ap.parse_args()
@@ -215,6 +222,10 @@ def main():
     psi = E.random_state_device(L, 11, dev)
     out = torch.empty_like(psi)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        out.copy_(psi)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {16 * D} bytes read + {16 * D} bytes written")
     log(f"bench: apply_H L={L}, {model.passes} passes, warmup {args.warmup}, steps {args.steps}")
     for _ in range(args.warmup):
         P.apply_H(model, psi, out)

@@ -27,7 +27,10 @@ __global__ __launch_bounds__(256) void hpsi_small(const double2* __restrict__ ps
     out[x] = small_entry<CLS>(psi, site, bond, L, x);
 }
 
-template <unsigned CLS, bool FIRST>
+// One tile per workgroup. With gathered bits, consecutive workgroups of one XCD (workgroups are
+// dealt to the 8 XCDs round-robin) take the 2^G tiles that differ only in the gathered bits, so
+// the neighbouring tiles a workgroup reads are being streamed into the same L2 at the same time.
+template <unsigned CLS, bool FIRST, bool GATHER>
 __global__ __launch_bounds__(kTileThreads) void hpsi_tile(const double2* __restrict__ psi,
                                                           double2* __restrict__ out,
                                                           const double2* __restrict__ site,
@@ -37,7 +40,16 @@ __global__ __launch_bounds__(kTileThreads) void hpsi_tile(const double2* __restr
                                                           const double2* __restrict__ dhi,
                                                           PassArgs pa) {
     __shared__ double2 s[1 << kTileBits];
-    tile_body<CLS, FIRST>(psi, out, site, bond, dlo, dmid, dhi, pa, int64_t(blockIdx.x), s);
+    int64_t n = blockIdx.x;
+    if (GATHER) {
+        const int64_t b = blockIdx.x;
+        const int64_t xcd = b & 7, j = b >> 3;
+        const int64_t member = j & ((int64_t(1) << pa.G) - 1), gl = j >> pa.G;
+        const int64_t group = (gl << 3) | xcd;
+        const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
+        n = low | (member << pa.gpos) | (high << (pa.gpos + pa.G));
+    }
+    tile_body<CLS, FIRST, GATHER>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s);
 }
 
 template <unsigned CLS>
@@ -55,15 +67,17 @@ hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, h
     for (int ip = 0; ip < m->n_pass; ++ip) {
         const PassDesc& pd = m->pass[ip];
         const PassArgs pa = to_args(pd);
+#define ED_LAUNCH_TILE(F, G)                                                                             \
+    hipLaunchKernelGGL((hpsi_tile<CLS, F, G>), dim3(unsigned(tiles)), dim3(kTileThreads), 0, s, psi, out, \
+                       m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid, m->d_diag_hi, pa)
         if (pd.first) {
-            hipLaunchKernelGGL((hpsi_tile<CLS, true>), dim3(unsigned(tiles)), dim3(kTileThreads), 0, s,
-                               psi, out, m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid,
-                               m->d_diag_hi, pa);
+            if (pd.G > 0) ED_LAUNCH_TILE(true, true);
+            else ED_LAUNCH_TILE(true, false);
         } else {
-            hipLaunchKernelGGL((hpsi_tile<CLS, false>), dim3(unsigned(tiles)), dim3(kTileThreads), 0,
-                               s, psi, out, m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid,
-                               m->d_diag_hi, pa);
+            if (pd.G > 0) ED_LAUNCH_TILE(false, true);
+            else ED_LAUNCH_TILE(false, false);
         }
+#undef ED_LAUNCH_TILE
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

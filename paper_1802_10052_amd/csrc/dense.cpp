@@ -16,16 +16,24 @@ namespace ed {
 bool tridiag_ql(int n, double* d, double* e, double* Z) {
     if (n <= 0) return true;
     e[n - 1] = 0.0;
+    // An off-diagonal entry is dropped when it is negligible next to its two diagonal neighbours
+    // or next to the whole matrix: the second test matters for graded spectra (a ground-state
+    // Schmidt spectrum spans 1 .. 1e-30) whose tail sits at the rounding level of |T|, where a
+    // purely relative test never fires. Dropping |e| <= 1e-17 |T| moves eigenvalues by less than
+    // the rounding of the reduction that produced T.
+    double tnorm = 0.0;
+    for (int i = 0; i < n; ++i) tnorm = std::max(tnorm, std::fabs(d[i]) + 2.0 * std::fabs(e[i]));
+    const double abs_tol = 1e-17 * tnorm;
     for (int l = 0; l < n; ++l) {
         int iter = 0;
         while (true) {
             int m = l;
             for (; m < n - 1; ++m) {
                 const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= 1e-17 * dd || std::fabs(e[m]) < 1e-300) break;
+                if (std::fabs(e[m]) <= 1e-17 * dd || std::fabs(e[m]) <= abs_tol || std::fabs(e[m]) < 1e-300) break;
             }
             if (m == l) break;
-            if (++iter > 60) return false;
+            if (++iter > 200) return false;
             // Wilkinson-type shift from the leading 2x2 block
             double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
             double r = std::hypot(g, 1.0);

@@ -38,6 +38,8 @@ constexpr int kTileThreads = 256;  // threads per tile workgroup
 constexpr int kWindowLow = 3;      // contiguous low bits kept in window passes (128 B runs)
 constexpr int kMaxPasses = 4;
 
+constexpr int kMaxGather = 4;     // index bits above a tile whose partner tiles are read from L2
+
 struct PassDesc {
     int c;            // contiguous low bits in the tile
     int h0;           // first bit of the window
@@ -46,6 +48,14 @@ struct PassDesc {
     uint32_t site_mask;  // bit q set: the site on tile-local bit q belongs to this pass
     uint32_t bond_mask;  // bit q set: the bond on tile-local bits (q, q+1) belongs to this pass
     int bit_of[kTileBits];  // global bit of tile-local bit q
+    // gathered bits [gb, gb + G) directly above the tile's top bit: their terms read the partner
+    // amplitude from the neighbouring tile (tile index bit gpos + (g - gb)) instead of LDS
+    int G;
+    int gb;
+    int gpos;
+    int gcross;          // the bond (gb-1, gb) between the tile's top bit and the first gathered bit
+    uint32_t site_gmask;  // bit i: site on gathered bit gb + i belongs to this pass
+    uint32_t bond_gmask;  // bit i: bond (gb + i, gb + i + 1) belongs to this pass
 };
 
 enum OpClass : unsigned {

@@ -38,6 +38,8 @@ struct PassArgs {
     int c, h0, first;
     uint32_t site_mask, bond_mask;
     int bit_of[kTileBits];
+    int G, gb, gpos, gcross;
+    uint32_t site_gmask, bond_gmask;
 };
 
 // Coefficient tables of one model as the kernels see them.
@@ -52,9 +54,26 @@ struct ModelTables {
     PassArgs pass[kMaxPasses];
 };
 
+// First global index of tile n of a pass (the fixed bits of the tile).
+__device__ __forceinline__ int64_t tile_base(const PassArgs& pa, bool first, int64_t n) {
+    if (first) return n << kTileBits;
+    const int lo_bits = pa.h0 - pa.c;
+    const int64_t nlo = n & ((int64_t(1) << lo_bits) - 1);
+    const int64_t nhi = n >> lo_bits;
+    return (nlo << pa.c) | (nhi << (pa.h0 + kTileBits - pa.c));
+}
+
+__device__ __forceinline__ int64_t tile_index(const PassArgs& pa, bool first, int64_t base, int i) {
+    if (first) return base + i;
+    const int lowmask = (1 << pa.c) - 1;
+    return base | int64_t(i & lowmask) | (int64_t(i >> pa.c) << pa.h0);
+}
+
 // One tile of one pass (tile index n). s: 4096 double2 of LDS. FIRST: writes out including the
-// diagonal; otherwise accumulates into out. Caller synchronises around reuse of s.
-template <unsigned CLS, bool FIRST>
+// diagonal; otherwise accumulates into out. GATHER: also evaluates the terms on the gathered bits
+// above the tile, reading partner amplitudes from the neighbouring tiles n ^ (bit of g).
+// Caller synchronises around reuse of s.
+template <unsigned CLS, bool FIRST, bool GATHER = false>
 __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
                                           const double2* __restrict__ site, const double2* __restrict__ bond,
                                           const double2* __restrict__ dlo, const double2* __restrict__ dmid,
@@ -63,20 +82,8 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     constexpr bool OFFR = CLS & kOffReal;
     constexpr bool DIAGR = CLS & kDiagReal;
     const int t = threadIdx.x;
-    int64_t base;
-    if (FIRST) {
-        base = n << kTileBits;
-    } else {
-        const int lo_bits = pa.h0 - pa.c;
-        const int64_t nlo = n & ((int64_t(1) << lo_bits) - 1);
-        const int64_t nhi = n >> lo_bits;
-        base = (nlo << pa.c) | (nhi << (pa.h0 + kTileBits - pa.c));
-    }
-    auto gidx = [&](int i) -> int64_t {
-        if (FIRST) return base + i;
-        const int lowmask = (1 << pa.c) - 1;
-        return base | int64_t(i & lowmask) | (int64_t(i >> pa.c) << pa.h0);
-    };
+    const int64_t base = tile_base(pa, FIRST, n);
+    auto gidx = [&](int i) -> int64_t { return tile_index(pa, FIRST, base, i); };
 
     double2 v[kSlots];
     double2 acc[kSlots];
@@ -165,6 +172,77 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
         }
     }
 
+    if constexpr (GATHER) {
+        // terms on the gathered bits: every partner is a whole neighbouring tile in the same layout
+        auto tbit = [&](int gi) -> int64_t { return int64_t(1) << (pa.gpos + gi); };
+        auto gbit = [&](int gi) -> int { return int((n >> (pa.gpos + gi)) & 1); };
+        auto add_tile = [&](double2 c, int64_t n2, int lflip) {
+            if (c.x == 0.0 && c.y == 0.0) return;
+            const int64_t b2 = tile_base(pa, FIRST, n2);
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) {
+                const double2 w = psi[tile_index(pa, FIRST, b2, (t + kTileThreads * k) ^ lflip)];
+                cfma<OFFR>(acc[k], c, w);
+            }
+        };
+        if (pa.gcross) {
+            // bond (gb-1, gb): local index l = 2 bit(gb) + bit(gb-1), bit(gb-1) = local bit 11
+            const double2* B = bond + 16 * (pa.gb - 1);
+            const int hb = gbit(0);
+            constexpr int q = kTileBits - 1;
+            if (CLS & kBondSingle) {
+                // m = 1 flips only the local top bit: partner in this tile (register slot k ^ 8)
+                const double2 c0 = B[4 * (2 * hb) + (2 * hb + 1)], c1 = B[4 * (2 * hb + 1) + (2 * hb)];
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) {
+                    const int i = t + kTileThreads * k;
+                    cfma<OFFR>(acc[k], ((i >> q) & 1) ? c1 : c0, v[k ^ (kSlots >> 1)]);
+                }
+                // m = 2 flips only bit gb: partner tile, same local index
+                const double2 d0 = B[4 * (2 * hb) + (2 * (1 - hb))], d1 = B[4 * (2 * hb + 1) + (2 * (1 - hb) + 1)];
+                if (d0.x != 0.0 || d0.y != 0.0 || d1.x != 0.0 || d1.y != 0.0) {
+                    const int64_t b2 = tile_base(pa, FIRST, n ^ tbit(0));
+#pragma unroll
+                    for (int k = 0; k < kSlots; ++k) {
+                        const int i = t + kTileThreads * k;
+                        cfma<OFFR>(acc[k], ((i >> q) & 1) ? d1 : d0, psi[tile_index(pa, FIRST, b2, i)]);
+                    }
+                }
+            }
+            if (CLS & kBondDouble) {
+                // m = 3: partner tile n ^ bit(gb), local top bit flipped
+                const double2 e0 = B[4 * (2 * hb) + (3 - 2 * hb)], e1 = B[4 * (2 * hb + 1) + (2 - 2 * hb)];
+                if (e0.x != 0.0 || e0.y != 0.0 || e1.x != 0.0 || e1.y != 0.0) {
+                    const int64_t b2 = tile_base(pa, FIRST, n ^ tbit(0));
+#pragma unroll
+                    for (int k = 0; k < kSlots; ++k) {
+                        const int i = t + kTileThreads * k;
+                        cfma<OFFR>(acc[k], ((i >> q) & 1) ? e1 : e0, psi[tile_index(pa, FIRST, b2, i ^ (1 << q))]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int gi = 0; gi < kMaxGather; ++gi) {
+            if (gi < pa.G) {
+                const int g = pa.gb + gi;
+                if ((CLS & kSiteOff) && ((pa.site_gmask >> gi) & 1)) {
+                    const int b = gbit(gi);
+                    add_tile(site[4 * g + (b ? 2 : 1)], n ^ tbit(gi), 0);
+                }
+                if (gi + 1 < pa.G && ((pa.bond_gmask >> gi) & 1)) {
+                    const double2* B = bond + 16 * g;
+                    const int l = 2 * gbit(gi + 1) + gbit(gi);
+                    if (CLS & kBondSingle) {
+                        add_tile(B[4 * l + (l ^ 1)], n ^ tbit(gi), 0);
+                        add_tile(B[4 * l + (l ^ 2)], n ^ tbit(gi + 1), 0);
+                    }
+                    if (CLS & kBondDouble) add_tile(B[4 * l + (l ^ 3)], n ^ tbit(gi) ^ tbit(gi + 1), 0);
+                }
+            }
+        }
+    }
+
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) out[gidx(t + kTileThreads * k)] = acc[k];
 }
@@ -230,6 +308,12 @@ inline PassArgs to_args(const PassDesc& pd) {
     pa.site_mask = pd.site_mask;
     pa.bond_mask = pd.bond_mask;
     for (int q = 0; q < kTileBits; ++q) pa.bit_of[q] = pd.bit_of[q];
+    pa.G = pd.G;
+    pa.gb = pd.gb;
+    pa.gpos = pd.gpos;
+    pa.gcross = pd.gcross;
+    pa.site_gmask = pd.site_gmask;
+    pa.bond_gmask = pd.bond_gmask;
     return pa;
 }
 

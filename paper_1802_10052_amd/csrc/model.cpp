@@ -2,6 +2,7 @@
 // one 2x2 operator per site and one 4x4 operator per bond, classifies the non-zero pattern so the
 // H psi kernels can skip absent terms ("iterate only over non-zero elements", Sec. II), builds the
 // diagonal tables, and plans the streaming passes of H psi.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -27,6 +28,102 @@ ed_status require_device(int* device) {
     return ED_OK;
 }
 
+// Passes without gathered bits: the first pass covers bits 0..11, each later pass a 9-bit window
+// (plus the 3 low bits) overlapping the previous coverage by one bit for the crossing bond.
+static int plan_plain(int L, PassDesc* out) {
+    const int T = kTileBits;
+    int np = 0;
+    PassDesc& p0 = out[np++];
+    std::memset(&p0, 0, sizeof(PassDesc));
+    p0.c = T;
+    p0.h0 = T;
+    p0.first = 1;
+    for (int q = 0; q < T; ++q) p0.bit_of[q] = q;
+    p0.site_mask = (1u << T) - 1u;
+    p0.bond_mask = (1u << (T - 1)) - 1u;
+    int done_bits = T;  // sites on bits < done_bits and bonds on bits < done_bits-1 are assigned
+    const int wbits = T - kWindowLow;
+    while (done_bits < L) {
+        if (np >= kMaxPasses) return -1;
+        PassDesc& pd = out[np++];
+        std::memset(&pd, 0, sizeof(PassDesc));
+        int h0 = done_bits - 1;  // overlap one bit: the bond crossing into the window
+        if (h0 + wbits > L) h0 = L - wbits;
+        pd.c = kWindowLow;
+        pd.h0 = h0;
+        pd.w = wbits;
+        for (int q = 0; q < T; ++q) pd.bit_of[q] = q < kWindowLow ? q : h0 + (q - kWindowLow);
+        for (int q = kWindowLow; q < T; ++q) {
+            const int p = pd.bit_of[q];
+            if (p >= done_bits) pd.site_mask |= 1u << q;
+            if (q + 1 < T && p + 1 >= done_bits && p + 1 < L) pd.bond_mask |= 1u << q;
+        }
+        done_bits = h0 + wbits;
+    }
+    return np;
+}
+
+// Passes with up to kMaxGather gathered bits above each tile (their partner tiles come from L2),
+// so that one pass covers up to 16 bits: L = 28 needs two passes instead of three.
+static int plan_gather(int L, PassDesc* out) {
+    const int T = kTileBits;
+    const int tile_index_bits = L - T;
+    auto gathers_fit = [&](int G) { return tile_index_bits >= 3 + G; };
+    int np = 0;
+    PassDesc& p0 = out[np++];
+    std::memset(&p0, 0, sizeof(PassDesc));
+    p0.c = T;
+    p0.h0 = T;
+    p0.first = 1;
+    for (int q = 0; q < T; ++q) p0.bit_of[q] = q;
+    p0.site_mask = (1u << T) - 1u;
+    p0.bond_mask = (1u << (T - 1)) - 1u;
+    int G0 = std::min(kMaxGather, L - T);
+    if (!gathers_fit(G0)) G0 = 0;
+    if (G0 > 0) {
+        p0.G = G0;
+        p0.gb = T;
+        p0.gpos = 0;
+        p0.gcross = 1;
+        p0.site_gmask = (1u << G0) - 1u;
+        p0.bond_gmask = (1u << (G0 - 1)) - 1u;
+    }
+    int done_bits = T + G0;
+    const int wbits = T - kWindowLow;
+    while (done_bits < L) {
+        if (np >= kMaxPasses) return -1;
+        PassDesc& pd = out[np++];
+        std::memset(&pd, 0, sizeof(PassDesc));
+        int h0 = done_bits - 1;
+        int G = 0;
+        if (h0 + wbits > L) {
+            h0 = L - wbits;
+        } else {
+            G = std::min(kMaxGather, L - (h0 + wbits));
+            if (!gathers_fit(G)) G = 0;
+        }
+        pd.c = kWindowLow;
+        pd.h0 = h0;
+        pd.w = wbits;
+        for (int q = 0; q < T; ++q) pd.bit_of[q] = q < kWindowLow ? q : h0 + (q - kWindowLow);
+        for (int q = kWindowLow; q < T; ++q) {
+            const int p = pd.bit_of[q];
+            if (p >= done_bits) pd.site_mask |= 1u << q;
+            if (q + 1 < T && p + 1 >= done_bits && p + 1 < L) pd.bond_mask |= 1u << q;
+        }
+        if (G > 0) {
+            pd.G = G;
+            pd.gb = h0 + wbits;
+            pd.gpos = h0 - kWindowLow;  // the window pass's tile index: bits [c, h0) then [h0 + w, L)
+            pd.gcross = 1;
+            pd.site_gmask = (1u << G) - 1u;
+            pd.bond_gmask = G > 1 ? (1u << (G - 1)) - 1u : 0u;
+        }
+        done_bits = h0 + wbits + G;
+    }
+    return np;
+}
+
 static void plan_passes(ed_model* m) {
     const int L = m->L;
     const int T = kTileBits;
@@ -38,37 +135,57 @@ static void plan_passes(ed_model* m) {
         m->pass[0].c = L;
         return;
     }
-    int np = 0;
-    // first pass: contiguous low T bits, all terms inside them plus every diagonal
-    PassDesc& p0 = m->pass[np++];
-    std::memset(&p0, 0, sizeof(PassDesc));
-    p0.c = T;
-    p0.h0 = T;
-    p0.w = 0;
-    p0.first = 1;
-    for (int q = 0; q < T; ++q) p0.bit_of[q] = q;
-    p0.site_mask = (1u << T) - 1u;
-    p0.bond_mask = (1u << (T - 1)) - 1u;
-    int done_bits = T;  // sites on bits < done_bits and bonds on bits < done_bits-1 are assigned
-    const int wbits = T - kWindowLow;
-    while (done_bits < L) {
-        PassDesc& pd = m->pass[np++];
-        std::memset(&pd, 0, sizeof(PassDesc));
-        int h0 = done_bits - 1;  // overlap one bit: the bond crossing into the window
-        if (h0 + wbits > L) h0 = L - wbits;
-        pd.c = kWindowLow;
-        pd.h0 = h0;
-        pd.w = wbits;
-        pd.first = 0;
-        for (int q = 0; q < T; ++q) pd.bit_of[q] = q < kWindowLow ? q : h0 + (q - kWindowLow);
-        for (int q = kWindowLow; q < T; ++q) {
+    PassDesc a[kMaxPasses + 1], b[kMaxPasses + 1];
+    const int na = plan_plain(L, a);
+    const int nb = plan_gather(L, b);
+    const bool use_b = nb > 0 && (na < 0 || nb < na);
+    const PassDesc* src = use_b ? b : a;
+    m->n_pass = use_b ? nb : na;
+    for (int i = 0; i < m->n_pass; ++i) m->pass[i] = src[i];
+}
+
+// Every site and every bond must belong to exactly one pass, and every gathered bit must sit
+// where the tile-index mapping expects it; a plan that breaks this is a bug, reported as such.
+static bool plan_is_valid(const ed_model* m) {
+    const int L = m->L;
+    if (L < kTileBits) return m->n_pass == 1;
+    std::vector<int> sites(L, 0), bonds(L - 1, 0);
+    for (int ip = 0; ip < m->n_pass; ++ip) {
+        const PassDesc& pd = m->pass[ip];
+        if (pd.first != (ip == 0 ? 1 : 0)) return false;
+        for (int q = 0; q < kTileBits; ++q) {
             const int p = pd.bit_of[q];
-            if (p >= done_bits) pd.site_mask |= 1u << q;
-            if (q + 1 < T && p + 1 >= done_bits && p + 1 < L) pd.bond_mask |= 1u << q;
+            if (p < 0 || p >= L) return false;
+            if ((pd.site_mask >> q) & 1) ++sites[p];
+            if ((pd.bond_mask >> q) & 1) {
+                if (q + 1 >= kTileBits || pd.bit_of[q + 1] != p + 1 || p + 1 >= L) return false;
+                ++bonds[p];
+            }
         }
-        done_bits = h0 + wbits;
+        if (pd.G > 0) {
+            if (pd.G > kMaxGather || pd.gb + pd.G > L) return false;
+            if (pd.gpos + pd.G > L - kTileBits || L - kTileBits < 3 + pd.G) return false;
+            if (pd.bit_of[kTileBits - 1] != pd.gb - 1) return false;
+            // the tile index bit gpos + i must be global bit gb + i
+            const int expect_gpos = pd.first ? pd.gb - kTileBits : pd.h0 - pd.c;
+            if (pd.gpos != expect_gpos || (!pd.first && pd.gb != pd.h0 + kTileBits - pd.c)) return false;
+            for (int i = 0; i < pd.G; ++i) {
+                if ((pd.site_gmask >> i) & 1) ++sites[pd.gb + i];
+                if ((pd.bond_gmask >> i) & 1) {
+                    if (i + 1 >= pd.G) return false;
+                    ++bonds[pd.gb + i];
+                }
+            }
+            if (pd.gcross) ++bonds[pd.gb - 1];
+        } else if (pd.site_gmask || pd.bond_gmask || pd.gcross) {
+            return false;
+        }
     }
-    m->n_pass = np;
+    for (int c : sites)
+        if (c != 1) return false;
+    for (int c : bonds)
+        if (c != 1) return false;
+    return true;
 }
 
 static inline double2 c2(double re, double im) { return make_double2(re, im); }
@@ -178,6 +295,7 @@ ed_status fold_model(const ed_model_desc* desc, ed_model* m) {
     }
     m->op_class = cls;
     plan_passes(m);
+    if (!plan_is_valid(m)) return fail(ED_ERR_UNSUPPORTED, "internal error: invalid H psi pass plan for L = " + std::to_string(L));
     return ED_OK;
 }
 

@@ -67,3 +67,17 @@ def test_model_create_without_device_reports_nodevice():
     d, keep = _desc()
     h = C.c_void_p()
     assert lib.ed_model_create(C.byref(d), C.byref(h)) == -3
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU may be visible")
+def test_pass_plans_valid_for_every_length():
+    """Model creation checks its H psi pass plan (every site and bond in exactly one pass) before
+    looking for a device: on a CPU-only host every L must get as far as ED_ERR_NODEVICE."""
+    lib = _lib.lib()
+    for L in range(2, 31):
+        d, keep = _desc(L=L, n_site=2, n_bond=2)
+        keep[0][:] = np.array([[0, 1], [1, 0]])   # off-diagonal sites
+        keep[2][:, 0, 3] = 1.0                     # double-flip bonds
+        h = C.c_void_p()
+        assert lib.ed_model_create(C.byref(d), C.byref(h)) == -3, (L, lib.ed_last_error())

@@ -116,3 +116,20 @@ def test_expm_complex(driver):
         E = np.array([float(x[0]) + 1j * float(x[1]) for x in out]).reshape(n, n)
         ref = sla.expm(A)
         assert np.linalg.norm(E - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_tridiag_ql_graded_spectrum(driver):
+    """A Schmidt-like spectrum 1 .. 1e-30 hidden in a tridiagonal matrix with rounding-level
+    couplings: QL must converge and reproduce LAPACK to the rounding level of |T|."""
+    rng = np.random.default_rng(4)
+    n = 400
+    lam = np.exp(-np.linspace(0, 70, n))
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * lam) @ Q.T
+    from scipy.linalg import hessenberg
+    T = hessenberg(A)                       # symmetric -> tridiagonal up to rounding
+    a, b = np.diag(T).copy(), np.diag(T, -1).copy()
+    out = driver(f"0 {n} " + _fmt(a, b))
+    w = np.array([float(x[0]) for x in out[:n]])
+    ref = sla.eigvalsh_tridiagonal(a, b)
+    assert np.max(np.abs(w - ref)) < 2e-14 * np.max(np.abs(ref))

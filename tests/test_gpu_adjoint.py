@@ -60,7 +60,7 @@ def test_adjoint_vs_finite_differences_L20():
     tmpl, J, psi0, w = case(20, 50)
     m = P.Model(tmpl)
     p0 = torch.from_numpy(psi0).to(DEV)
-    kw = dict(substeps=2, m_fixed=14, m_max=30)
+    kw = dict(substeps=2, m_fixed=20, m_max=30)
     loss, g = P.evolve_adjoint(m, J, p0, 0.1, w, quad_nodes=8, **kw)
     rng = np.random.default_rng(0)
     picks = [(49, 9), (0, 0), (25, 18)] + [tuple(x) for x in zip(rng.integers(0, 50, 5), rng.integers(0, 19, 5))]

@@ -42,12 +42,16 @@ def test_apply_H_parity(L, kind):
     assert err < 1e-13, (L, kind, err, m.passes)
 
 
-@pytest.mark.parametrize("L,kind", [(26, "tfim"), (26, "xxz"), (26, "generic")])
+@pytest.mark.parametrize("L,kind", [(22, "generic"), (25, "xxz"), (25, "generic"), (26, "tfim"), (26, "xxz"),
+                                    (26, "generic"), (27, "xxz_decay"), (28, "tfim"), (28, "xxz"), (28, "generic")])
 def test_apply_H_sampled_entries_large(L, kind):
+    """Sampled entries at sizes where the pass plan uses gathered bits (L >= 25: G = L - 24 in the
+    window pass; the first pass gathers 4 bits from L = 21 on)."""
     print(f"apply_H sampled L={L} kind={kind}", flush=True)
     desc = models(L)[kind]
     psi = E.random_state(L, 11)
     m = P.Model(desc)
+    assert m.passes == (2 if L <= 28 else 3)
     out = P.apply_H(m, to_dev(psi)).cpu().numpy()
     rng = np.random.default_rng(5)
     xs = np.concatenate([rng.integers(0, 1 << L, 4000), [0, (1 << L) - 1, 1 << (L - 1), (1 << 12) - 1, 1 << 12]])
