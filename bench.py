@@ -40,6 +40,31 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+HPSI_SOURCES = ["paper_1802_10052_amd/csrc/apply_h.hip", "paper_1802_10052_amd/csrc/hpsi_device.h",
+                "paper_1802_10052_amd/csrc/model.cpp"]
+TRAFFIC_PROFILE = "profiles/hpsi_tile_L28_tfim.md"
+
+
+def measured_traffic():
+    """HBM bytes per H psi from the committed rocprofv3 counter summary, if it was taken on the
+    H psi kernels as they are now (same source hash); otherwise None."""
+    import hashlib
+    try:
+        h = hashlib.sha256()
+        for f in HPSI_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        cur = h.hexdigest()[:16]
+        rec, traffic = None, None
+        for line in open(os.path.join(ROOT, TRAFFIC_PROFILE)):
+            if line.startswith("source-hash:"):
+                rec = line.split(":", 1)[1].strip()
+            if line.startswith("traffic-bytes-per-apply:"):
+                traffic = float(line.split(":", 1)[1])
+        return traffic if rec == cur else None
+    except OSError:
+        return None
+
+
 def cpu_baseline(L=20, reps=60):
     """The oracle's explicit sparse H psi (scipy CSR matvec, single-threaded) at L = 20."""
     import edinputs as E
@@ -258,7 +283,8 @@ def main():
                                f"(2^{L} complex128 amplitudes, seeded complex-normal state)",
                    "L": L, "passes": model.passes, "launches_per_step": model.passes},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+                     "frac": round(gbs / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic() if L == 28 else None},
         "host": host_info(),
         "wall_s": round(wall, 3),
     }

@@ -218,8 +218,7 @@ ed_status eval_basis(const Basis& B, double tau, double2* out, hipStream_t s) {
     expm_col_sym(B.m, B.d.data(), B.Z.data(), tau, u.data());
     std::vector<double2> c(B.m);
     for (int i = 0; i < B.m; ++i) c[i] = make_double2(B.nrm * u[i].real(), B.nrm * u[i].imag());
-    if (combination(B.w.V, B.w.D, B.m, c.data(), out, B.w.D, s) != hipSuccess) return fail(ED_ERR_HIP, "combination");
-    return ED_OK;
+    return combine_basis(B.w, B.m, c.data(), out, s);
 }
 
 // psi <- exp(-i H dt) psi through K sub-steps

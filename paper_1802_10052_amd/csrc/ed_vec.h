@@ -34,4 +34,14 @@ hipError_t combination(const double2* V, int64_t ldv, int n, const double2* c, d
 // out[0].x = |psi|^2, out[1+p].x = sum |psi_x|^2 (1 - 2 bit_p(x))  (p = bit, site L-p)
 hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStream_t s);
 
+// Scaled-basis variants: vectors given as pointer lists.
+// out[i] = <U_i|w>, i < n
+hipError_t dots_ptr(const double2* const* U, int n, const double2* w, int64_t D, double2* out, double2* part,
+                    hipStream_t s);
+// w -= sum_i scale[i] coef[i] U_i (coef device, scale host); nrm_out[0].x = |w_new|^2
+hipError_t axpy_norm_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
+                         int64_t D, double2* nrm_out, double2* part, hipStream_t s);
+// out = sum_i c[i] U_i (c host); out may be U_0 when n <= kMaxComb
+hipError_t combination_ptr(const double2* const* U, int n, const double2* c, double2* out, int64_t D, hipStream_t s);
+
 }  // namespace ed

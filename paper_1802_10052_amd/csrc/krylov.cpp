@@ -58,46 +58,54 @@ ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s)
         if (_e != hipSuccess) return fail(ED_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
     } while (0)
 
-// One step of the recurrence: w = H V_j into V_{j+1}, orthogonalised against V_lo..V_j
-// (passes = 1 or 2 classical Gram-Schmidt sweeps). Returns the projections h[0..j-lo] and the
-// norm beta of the orthogonalised w. V_{j+1} is normalised unless beta is below `tiny`.
+// One step of the recurrence on the scaled basis: y = H u_j into slot j+1, orthogonalised against
+// u_lo..u_j (passes = 1 or 2 classical Gram-Schmidt sweeps, each one dot pass and one fused
+// axpy + norm pass). Returns the true projections h_i = <v_i|H v_j> (i = lo..j) and the norm
+// beta of the orthogonalised H v_j; the new basis vector is u_{j+1} = y with c_{j+1} = 1/|y|.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
                       cplx* h, double* beta, bool* breakdown, hipStream_t s) {
     const int64_t D = w.D;
-    double2* Vj = w.V + int64_t(j) * D;
-    double2* Wn = w.V + int64_t(j + 1) * D;
     const int n = j - lo + 1;
     if (n > kMaxProj) return fail(ED_ERR_UNSUPPORTED, "too many projections");
-    ED_TRY(launch_apply_H(m, Vj, Wn, s));
-    double2* nr = w.scal + kNrm;
-    double2* h1 = w.scal + 1;
-    double2* h2 = w.scal + 1 + n;
-    const double2* Vlo = w.V + int64_t(lo) * D;
-    ED_K(dots(Vlo, D, n, Wn, D, h1, w.part, s));
-    ED_K(axpy_multi(Vlo, D, n, h1, -1.0, Wn, D, s));
-    if (passes > 1) {
-        ED_K(dots(Vlo, D, n, Wn, D, h2, w.part, s));
-        ED_K(axpy_multi(Vlo, D, n, h2, -1.0, Wn, D, s));
+    if (int(w.u.size()) < j + 2) {
+        w.u.resize(j + 2, nullptr);
+        w.c.resize(j + 2, 0.0);
     }
-    ED_K(norm2(Wn, D, nr, w.part, s));
+    double2* y = w.slot(j + 1);
+    ED_TRY(launch_apply_H(m, w.u[j], y, s));
+    double2* nr = w.scal + kNrm;
+    double2* g1 = w.scal + 1;
+    double2* g2 = w.scal + 1 + n;
+    const double2* const* U = const_cast<const double2* const*>(w.u.data() + lo);
+    std::vector<double> sc(n);
+    for (int i = 0; i < n; ++i) sc[i] = w.c[lo + i] * w.c[lo + i];
+    ED_K(dots_ptr(U, n, y, D, g1, w.part, s));
+    ED_K(axpy_norm_ptr(U, n, g1, sc.data(), y, D, nr, w.part, s));
+    if (passes > 1) {
+        ED_K(dots_ptr(U, n, y, D, g2, w.part, s));
+        ED_K(axpy_norm_ptr(U, n, g2, sc.data(), y, D, nr, w.part, s));
+    }
     std::vector<double2> hs(1 + 2 * n);
     ED_TRY(fetch_scalars(w.scal, passes > 1 ? 1 + 2 * n : 1 + n, hs.data(), s));
+    const double cj = w.c[j];
     for (int i = 0; i < n; ++i) {
-        h[i] = cplx(hs[1 + i].x, hs[1 + i].y);
-        if (passes > 1) h[i] += cplx(hs[1 + n + i].x, hs[1 + n + i].y);
+        cplx g(hs[1 + i].x, hs[1 + i].y);
+        if (passes > 1) g += cplx(hs[1 + n + i].x, hs[1 + n + i].y);
+        h[i] = w.c[lo + i] * cj * g;
     }
     const double nrm2v = hs[kNrm].x;
     if (!std::isfinite(nrm2v)) return fail(ED_ERR_NUMERIC, "non-finite value in the Krylov recurrence");
-    *beta = std::sqrt(std::max(nrm2v, 0.0));
+    const double ny = std::sqrt(std::max(nrm2v, 0.0));
+    *beta = cj * ny;
     double scale = 0.0;
     for (int i = 0; i < n; ++i) scale = std::max(scale, std::abs(h[i]));
     *breakdown = (*beta <= tiny_rel * std::max(scale, 1e-300)) || *beta == 0.0;
-    if (!*breakdown) ED_K(normalize(Wn, Wn, nr, D, s));
+    w.u[j + 1] = y;
+    w.c[j + 1] = *breakdown ? 0.0 : 1.0 / ny;
     return ED_OK;
 }
 
-// V_0 = psi / |psi|; returns |psi|.
-ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s) {
+ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s, bool alias) {
     double2* nr = w.scal + kNrm;
     ED_K(norm2(psi, w.D, nr, w.part, s));
     double2 hv[1];
@@ -106,7 +114,26 @@ ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipS
     if (!std::isfinite(n2)) return fail(ED_ERR_NUMERIC, "non-finite start vector");
     if (n2 <= 0.0) return fail(ED_ERR_ARG, "start vector is zero");
     *nrm = std::sqrt(n2);
-    ED_K(normalize(psi, w.V, nr, w.D, s));
+    if (w.u.empty()) {
+        w.u.resize(1);
+        w.c.resize(1);
+    }
+    if (alias) {
+        w.u[0] = const_cast<double2*>(psi);
+        w.c[0] = 1.0 / *nrm;
+    } else {
+        ED_K(normalize(psi, w.V, nr, w.D, s));
+        w.u[0] = w.V;
+        w.c[0] = 1.0;
+    }
+    return ED_OK;
+}
+
+ed_status combine_basis(const Workspace& w, int m, const double2* xi, double2* out, hipStream_t s) {
+    if (m > kMaxComb && out == w.u[0]) return fail(ED_ERR_UNSUPPORTED, "in-place combination of more than 64 vectors");
+    std::vector<double2> c(m);
+    for (int i = 0; i < m; ++i) c[i] = make_double2(xi[i].x * w.c[i], xi[i].y * w.c[i]);
+    ED_K(combination_ptr(const_cast<const double2* const*>(w.u.data()), m, c.data(), out, w.D, s));
     return ED_OK;
 }
 
@@ -142,7 +169,7 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     double nrm0 = 0.0;
-    ED_TRY(start_vector(w, reinterpret_cast<const double2*>(v0), &nrm0, s));
+    ED_TRY(start_vector(w, reinterpret_cast<const double2*>(v0), &nrm0, s, true));
 
     std::vector<double> T(size_t(mb + 1) * (mb + 1), 0.0);
     auto Tij = [&](int i, int j) -> double& { return T[size_t(i) * (mb + 1) + j]; };
@@ -199,11 +226,15 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
             for (int i = 0; i < keep; ++i) {
                 std::vector<double2> c(m);
                 for (int r = 0; r < m; ++r) c[r] = make_double2(Z[size_t(r) * m + i], 0.0);
-                ED_K(combination(w.V, D, m, c.data(), tmp + int64_t(i) * D, D, s));
+                ED_TRY(combine_basis(w, m, c.data(), tmp + int64_t(i) * D, s));
             }
+            const double cm = w.c[m];
             ED_HIP_TRY(hipMemcpyAsync(w.V, tmp, size_t(keep) * D * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            ED_HIP_TRY(hipMemcpyAsync(w.V + int64_t(keep) * D, w.V + int64_t(m) * D, D * sizeof(double2),
-                                      hipMemcpyDeviceToDevice, s));
+            ED_HIP_TRY(hipMemcpyAsync(w.V + int64_t(keep) * D, w.u[m], D * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            for (int i = 0; i <= keep; ++i) {
+                w.u[i] = w.slot(i);
+                w.c[i] = (i < keep) ? 1.0 : cm;
+            }
             std::fill(T.begin(), T.end(), 0.0);
             for (int i = 0; i < keep; ++i) {
                 Tij(i, i) = wv[i];
@@ -222,7 +253,7 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
     std::vector<double2> c(m);
     for (int r = 0; r < m; ++r) c[r] = make_double2(svec[r], 0.0);
     double2* out = reinterpret_cast<double2*>(psi0);
-    ED_K(combination(w.V, D, m, c.data(), out, D, s));
+    ED_TRY(combine_basis(w, m, c.data(), out, s));
     double2* nr = w.scal + kNrm;
     ED_K(norm2(out, D, nr, w.part, s));
     ED_K(normalize(out, out, nr, D, s));
@@ -274,7 +305,7 @@ ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, 
                            double* nrm_in, hipStream_t s) {
     const int mmax = p->m_max;
     double nrm0 = 0.0;
-    ED_TRY(start_vector(w, psi, &nrm0, s));
+    ED_TRY(start_vector(w, psi, &nrm0, s, true));
     std::vector<cplx> T(size_t(mmax + 1) * (mmax + 1), 0.0);
     auto Tij = [&](int i, int j) -> cplx& { return T[size_t(i) * (mmax + 1) + j]; };
     std::vector<cplx> h(mmax + 1), u(mmax + 1);
@@ -322,7 +353,7 @@ ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, 
     }
     std::vector<double2> c(mm);
     for (int i = 0; i < mm; ++i) c[i] = make_double2(nrm0 * u[i].real(), nrm0 * u[i].imag());
-    ED_K(combination(w.V, w.D, mm, c.data(), psi, w.D, s));
+    ED_TRY(combine_basis(w, mm, c.data(), psi, s));
     *m_used = mm;
     *err_out = err;
     if (nrm_in) *nrm_in = nrm0;

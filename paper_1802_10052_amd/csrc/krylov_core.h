@@ -12,12 +12,18 @@ constexpr int kObs = 1 + 2 * kMaxProj;
 constexpr int kScalars = kObs + 64;
 
 // Caller workspace carved into: partial-reduction buffer, device scalars, nvec vectors of D.
+// The Krylov basis lives there as (u_i, c_i) with v_i = c_i u_i: u_i is slot i of V except that
+// u_0 may be the caller's state itself; c_i is a host scalar, so a new basis vector is never
+// rescaled in memory.
 struct Workspace {
     double2* part = nullptr;
     double2* scal = nullptr;
     double2* V = nullptr;
     int nvec = 0;
     int64_t D = 0;
+    mutable std::vector<double2*> u;
+    mutable std::vector<double> c;
+    double2* slot(int i) const { return V + int64_t(i) * D; }
 };
 
 size_t core_scratch_bytes();
@@ -25,7 +31,11 @@ ed_status carve(void* ws, size_t ws_bytes, int64_t D, int nvec, Workspace* w);
 ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s);
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
                       cplx* h, double* beta, bool* breakdown, hipStream_t s);
-ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s);
+// Basis vector 0 from psi: alias = true uses psi itself as u_0 (c_0 = 1/|psi|); otherwise psi/|psi|
+// is written to slot 0 (c_0 = 1).
+ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s, bool alias = false);
+// out = sum_i xi_i v_i over the first m basis vectors (xi host); out may be u_0.
+ed_status combine_basis(const Workspace& w, int m, const double2* xi, double2* out, hipStream_t s);
 ed_status measure_state(const double2* psi, int L, const Workspace& w, double* sz, double* nrm, hipStream_t s);
 ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, double dt,
                            const ed_krylov_params* p, int* m_used, double* err_out, double* e_in,

@@ -940,7 +940,7 @@ extern "C" ed_status ed_trajectories_plain(const ed_traj_desc* d, const ed_traj_
                 auto combine = [&](const std::vector<cplx>& uu) -> ed_status {
                     std::vector<double2> c(m);
                     for (int i = 0; i < m; ++i) c[i] = make_double2(nrm * uu[i].real(), nrm * uu[i].imag());
-                    return combination(w.V, D, m, c.data(), psi, D, s) == hipSuccess ? ED_OK : fail(ED_ERR_HIP, "combination");
+                    return combine_basis(w, m, c.data(), psi, s);
                 };
                 if (f_end > 0.0) {
                     ED_TRY(combine(u));

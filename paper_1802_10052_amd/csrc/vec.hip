@@ -222,6 +222,102 @@ __global__ __launch_bounds__(kThreads) void sz_partial(const double2* __restrict
     if (t < L + 1) part[int64_t(blockIdx.x) * part_ld + t] = make_double2(acc[0], 0.0);
 }
 
+// ---------------------------------------------------------------- scaled-basis kernels
+// A Krylov basis is kept as (u_i, c_i) with v_i = c_i u_i, so normalising a new vector is a host
+// scalar instead of a pass over the state. Vectors come as pointer lists (u_0 may be the caller's
+// state itself).
+struct VecPtrs {
+    const double2* p[kDotGroup];
+};
+struct Scales {
+    double s[kDotGroup];
+};
+
+// part[b][i] = sum_x conj(u_i[x]) w[x] over block b's chunk, i < n <= kDotGroup
+template <int NG>
+__global__ __launch_bounds__(kThreads) void dot_partial_ptr(VecPtrs U, int n, const double2* __restrict__ w,
+                                                            int64_t D, double2* __restrict__ part, int part_ld) {
+    __shared__ double lds[kWaves * 2 * NG];
+    double a[2 * NG];
+#pragma unroll
+    for (int i = 0; i < 2 * NG; ++i) a[i] = 0.0;
+    const int64_t chunk = (D + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = int64_t(blockIdx.x) * chunk;
+    const int64_t hi = lo + chunk < D ? lo + chunk : D;
+    for (int64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
+        const double2 y = w[x];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            if (i < n) {
+                const double2 v = U.p[i][x];
+                a[2 * i] = fma(v.x, y.x, fma(v.y, y.y, a[2 * i]));
+                a[2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, a[2 * i + 1]));
+            }
+        }
+    }
+    block_sum<2 * NG>(a, lds);
+    if (threadIdx.x < 2 * n) {
+        double* p = reinterpret_cast<double*>(part + int64_t(blockIdx.x) * part_ld);
+        p[threadIdx.x] = a[0];
+    }
+}
+
+// w[x] -= sum_i (sc_i * coef[i]) u_i[x]; when want_norm, part[b][0] = sum |w_new|^2 over the chunk
+template <int NG>
+__global__ __launch_bounds__(kThreads) void axpy_norm_partial(VecPtrs U, int n, const double2* __restrict__ coef,
+                                                              Scales sc, double2* __restrict__ w, int64_t D,
+                                                              int want_norm, double2* __restrict__ part,
+                                                              int part_ld) {
+    __shared__ double lds[kWaves];
+    double2 c[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+        const double2 k = i < n ? coef[i] : make_double2(0.0, 0.0);
+        c[i] = make_double2(sc.s[i] * k.x, sc.s[i] * k.y);
+    }
+    double a[1] = {0.0};
+    const int64_t chunk = (D + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = int64_t(blockIdx.x) * chunk;
+    const int64_t hi = lo + chunk < D ? lo + chunk : D;
+    for (int64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
+        double2 acc = w[x];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            if (i < n) {
+                const double2 v = U.p[i][x];
+                acc.x -= c[i].x * v.x - c[i].y * v.y;
+                acc.y -= c[i].x * v.y + c[i].y * v.x;
+            }
+        }
+        w[x] = acc;
+        a[0] = fma(acc.x, acc.x, fma(acc.y, acc.y, a[0]));
+    }
+    if (want_norm) {
+        block_sum<1>(a, lds);
+        if (threadIdx.x == 0) part[int64_t(blockIdx.x) * part_ld] = make_double2(a[0], 0.0);
+    }
+}
+
+// out[x] = sum_i c_i u_i[x] (+ out[x] when accumulate); in place on out == u_0 is safe (each
+// element is read before it is written by the same thread)
+struct CombPtrs {
+    const double2* p[kMaxComb];
+    double2 c[kMaxComb];
+};
+
+__global__ __launch_bounds__(kThreads) void combine_ptr(CombPtrs cp, int n, double2* out, int64_t D, int accumulate) {
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < D; x += stride) {
+        double2 acc = accumulate ? out[x] : make_double2(0.0, 0.0);
+        for (int i = 0; i < n; ++i) {
+            const double2 v = cp.p[i][x];
+            acc.x = fma(cp.c[i].x, v.x, fma(-cp.c[i].y, v.y, acc.x));
+            acc.y = fma(cp.c[i].x, v.y, fma(cp.c[i].y, v.x, acc.y));
+        }
+        out[x] = acc;
+    }
+}
+
 inline int grid_for(int64_t D) {
     int64_t g = D / (kThreads * 4);
     if (g < 1) g = 1;
@@ -309,6 +405,67 @@ hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStr
     int G = int(nchunk < kRedBlocks ? nchunk : kRedBlocks);
     hipLaunchKernelGGL(sz_partial, dim3(G), dim3(kThreads), 0, s, psi, L, part, kPartLd);
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, L + 1, out, 0);
+    return hipGetLastError();
+}
+
+}  // namespace ed
+
+namespace ed {
+
+hipError_t dots_ptr(const double2* const* U, int n, const double2* w, int64_t D, double2* out, double2* part,
+                    hipStream_t s) {
+    const int G = grid_for(D);
+    for (int i0 = 0; i0 < n; i0 += kDotGroup) {
+        const int nn = n - i0 < kDotGroup ? n - i0 : kDotGroup;
+        VecPtrs vp;
+        for (int i = 0; i < kDotGroup; ++i) vp.p[i] = i < nn ? U[i0 + i] : nullptr;
+        if (nn <= 4) {
+            hipLaunchKernelGGL((dot_partial_ptr<4>), dim3(G), dim3(kThreads), 0, s, vp, nn, w, D, part, kPartLd);
+        } else {
+            hipLaunchKernelGGL((dot_partial_ptr<kDotGroup>), dim3(G), dim3(kThreads), 0, s, vp, nn, w, D, part, kPartLd);
+        }
+        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, nn, out + i0, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t axpy_norm_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
+                         int64_t D, double2* nrm_out, double2* part, hipStream_t s) {
+    const int G = grid_for(D);
+    for (int i0 = 0; i0 < n || i0 == 0; i0 += kDotGroup) {
+        const int nn = n - i0 < kDotGroup ? n - i0 : kDotGroup;
+        const bool last = i0 + kDotGroup >= n;
+        VecPtrs vp;
+        Scales sc;
+        for (int i = 0; i < kDotGroup; ++i) {
+            vp.p[i] = i < nn ? U[i0 + i] : nullptr;
+            sc.s[i] = i < nn ? scale[i0 + i] : 0.0;
+        }
+        if (nn <= 4) {
+            hipLaunchKernelGGL((axpy_norm_partial<4>), dim3(G), dim3(kThreads), 0, s, vp, nn, coef + i0, sc, w, D,
+                               last ? 1 : 0, part, kPartLd);
+        } else {
+            hipLaunchKernelGGL((axpy_norm_partial<kDotGroup>), dim3(G), dim3(kThreads), 0, s, vp, nn, coef + i0, sc, w,
+                               D, last ? 1 : 0, part, kPartLd);
+        }
+        if (last) hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, 1, nrm_out, 0);
+        if (n == 0) break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t combination_ptr(const double2* const* U, int n, const double2* c, double2* out, int64_t D, hipStream_t s) {
+    // out may alias U[0] only when n <= kMaxComb (a single pass)
+    for (int i0 = 0; i0 < n || i0 == 0; i0 += kMaxComb) {
+        const int nn = n - i0 < kMaxComb ? n - i0 : kMaxComb;
+        CombPtrs cp;
+        for (int i = 0; i < kMaxComb; ++i) {
+            cp.p[i] = i < nn ? U[i0 + i] : nullptr;
+            cp.c[i] = i < nn ? c[i0 + i] : make_double2(0.0, 0.0);
+        }
+        hipLaunchKernelGGL(combine_ptr, dim3(grid_for(D)), dim3(kThreads), 0, s, cp, nn, out, D, i0 > 0 ? 1 : 0);
+        if (n == 0) break;
+    }
     return hipGetLastError();
 }
 
