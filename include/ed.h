@@ -89,6 +89,19 @@ ed_status ed_model_dims(const ed_model* model, int* L, int64_t* D);
 /* Number of streaming passes over the state one ed_apply_H makes (diagnostic). */
 ed_status ed_model_passes(const ed_model* model, int* passes);
 
+/* Autotuning of H psi. A model holds up to 4 candidate pass plans (which index bits each
+ * streaming pass covers, and how many bits above a tile are read from neighbouring tiles in L2).
+ * All candidates compute the same H psi (up to the order of floating-point sums). The plan with
+ * the fewest passes is selected at creation. ed_model_tune times every candidate on the caller's
+ * device buffers psi, out (D amplitudes each, `reps` products per candidate, HIP events on
+ * stream), selects the fastest and returns its index and the per-candidate times (host,
+ * may be NULL; count from ed_model_plans). Selecting or tuning a plan modifies the handle: it
+ * must not run concurrently with any other call that uses the same model. */
+ed_status ed_model_plans(const ed_model* model, int* count, int* selected);
+ed_status ed_model_select_plan(ed_model* model, int index);
+ed_status ed_model_tune(ed_model* model, const ed_c64* psi, ed_c64* out, int reps, void* stream, int* best,
+                        float* times_ms);
+
 /* ----------------------------------------------------------------------------------------
  * ed_apply_H: out = H psi (Sec. III.C, the rule set applied to the state without building H,
  * Eq. ed:eq:OKrylov). psi and out are device arrays of D amplitudes that must not overlap.

@@ -61,6 +61,28 @@ class Model:
         call("ed_model_passes", self._h, C.byref(n))
         return n.value
 
+    @property
+    def plans(self):
+        """(number of candidate H psi pass plans, selected index)."""
+        n, sel = C.c_int(), C.c_int()
+        call("ed_model_plans", self._h, C.byref(n), C.byref(sel))
+        return n.value, sel.value
+
+    def select_plan(self, index):
+        call("ed_model_select_plan", self._h, int(index))
+
+    def tune(self, psi, out=None, reps=3, stream=None):
+        """Time every candidate H psi plan on psi (ed_model_tune) and keep the fastest.
+        Returns (best index, list of ms per product)."""
+        _check_state(psi, self.D)
+        if out is None:
+            out = torch.empty_like(psi)
+        n = self.plans[0]
+        times = (C.c_float * max(n, 1))()
+        best = C.c_int()
+        call("ed_model_tune", self._h, _dptr(psi), _dptr(out), int(reps), _stream_ptr(stream), C.byref(best), times)
+        return best.value, [times[i] for i in range(n)]
+
     def close(self):
         if getattr(self, "_h", None):
             lib().ed_model_destroy(self._h)

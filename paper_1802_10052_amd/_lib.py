@@ -105,6 +105,9 @@ def _declare(l):
     _fn(l, "ed_model_dims", [P, C.POINTER(C.c_int), C.POINTER(C.c_int64)])
     _fn(l, "ed_model_passes", [P, C.POINTER(C.c_int)])
     _fn(l, "ed_apply_H", [P, P, P, P])
+    _fn(l, "ed_model_plans", [P, C.POINTER(C.c_int), C.POINTER(C.c_int)])
+    _fn(l, "ed_model_select_plan", [P, C.c_int])
+    _fn(l, "ed_model_tune", [P, P, P, C.c_int, P, C.POINTER(C.c_int), C.POINTER(C.c_float)])
     S = C.POINTER(C.c_size_t)
     _fn(l, "ed_lanczos_workspace", [P, C.POINTER(LanczosParams), S])
     _fn(l, "ed_lanczos_ground", [P, P, C.POINTER(LanczosParams), C.POINTER(C.c_double), P,

@@ -38,7 +38,8 @@ constexpr int kTileThreads = 256;  // threads per tile workgroup
 constexpr int kWindowLow = 3;      // contiguous low bits kept in window passes (128 B runs)
 constexpr int kMaxPasses = 4;
 
-constexpr int kMaxGather = 4;     // index bits above a tile whose partner tiles are read from L2
+constexpr int kMaxGather = 6;     // index bits above a tile whose partner tiles are read from L2
+constexpr int kMaxPlans = 4;      // candidate pass plans per model (chosen by ed_model_tune)
 
 struct PassDesc {
     int c;            // contiguous low bits in the tile
@@ -84,8 +85,12 @@ struct ed_model {
     double2* d_diag_mid = nullptr; // [2^(T-7)] bonds 7..T-2, sites 8..T-1
     double2* d_diag_hi = nullptr;  // [2^(L-T+1)] bonds T-1..L-2, sites T..L-1
     int tile_bits = 0;           // T = min(L, kTileBits)
-    int n_pass = 0;
+    int n_pass = 0;              // the selected plan (copied from cand[plan])
     ed::PassDesc pass[ed::kMaxPasses];
+    int n_cand = 0;              // candidate plans and their pass counts
+    int plan = 0;
+    int cand_np[ed::kMaxPlans] = {0, 0, 0, 0};
+    ed::PassDesc cand[ed::kMaxPlans][ed::kMaxPasses];
 };
 
 namespace ed {

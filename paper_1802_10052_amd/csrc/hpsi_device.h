@@ -243,8 +243,14 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
         }
     }
 
+    // streaming stores: out is not read again by this pass, so it should not evict the state tiles
+    // that neighbouring workgroups gather from L2
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) out[gidx(t + kTileThreads * k)] = acc[k];
+    for (int k = 0; k < kSlots; ++k) {
+        double* o = reinterpret_cast<double*>(out + gidx(t + kTileThreads * k));
+        __builtin_nontemporal_store(acc[k].x, o);
+        __builtin_nontemporal_store(acc[k].y, o + 1);
+    }
 }
 
 // Small-L body for one amplitude x (L < kTileBits), partners read from `src` (global or LDS).

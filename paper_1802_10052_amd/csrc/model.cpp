@@ -63,9 +63,9 @@ static int plan_plain(int L, PassDesc* out) {
     return np;
 }
 
-// Passes with up to kMaxGather gathered bits above each tile (their partner tiles come from L2),
-// so that one pass covers up to 16 bits: L = 28 needs two passes instead of three.
-static int plan_gather(int L, PassDesc* out) {
+// Passes with gathered bits above each tile (their partner tiles come from L2): up to g_first in
+// the first pass and up to 4 in window passes, so that L = 28 needs two passes instead of three.
+static int plan_gather(int L, int g_first, PassDesc* out) {
     const int T = kTileBits;
     const int tile_index_bits = L - T;
     auto gathers_fit = [&](int G) { return tile_index_bits >= 3 + G; };
@@ -78,7 +78,7 @@ static int plan_gather(int L, PassDesc* out) {
     for (int q = 0; q < T; ++q) p0.bit_of[q] = q;
     p0.site_mask = (1u << T) - 1u;
     p0.bond_mask = (1u << (T - 1)) - 1u;
-    int G0 = std::min(kMaxGather, L - T);
+    int G0 = std::min(g_first, L - T);
     if (!gathers_fit(G0)) G0 = 0;
     if (G0 > 0) {
         p0.G = G0;
@@ -99,7 +99,7 @@ static int plan_gather(int L, PassDesc* out) {
         if (h0 + wbits > L) {
             h0 = L - wbits;
         } else {
-            G = std::min(kMaxGather, L - (h0 + wbits));
+            G = std::min(4, L - (h0 + wbits));
             if (!gathers_fit(G)) G = 0;
         }
         pd.c = kWindowLow;
@@ -124,34 +124,53 @@ static int plan_gather(int L, PassDesc* out) {
     return np;
 }
 
+// Candidate plans: the fewest passes first (gathered, 4 bits in the first pass), then the other
+// gathered variants with the same pass count, then the plain plan. ed_model_tune times them.
 static void plan_passes(ed_model* m) {
     const int L = m->L;
     const int T = kTileBits;
     m->tile_bits = L < T ? L : T;
+    m->n_cand = 0;
+    m->plan = 0;
     if (L < T) {
-        m->n_pass = 1;
-        std::memset(&m->pass[0], 0, sizeof(PassDesc));
-        m->pass[0].first = 1;
-        m->pass[0].c = L;
-        return;
+        m->n_cand = 1;
+        m->cand_np[0] = 1;
+        std::memset(&m->cand[0][0], 0, sizeof(PassDesc));
+        m->cand[0][0].first = 1;
+        m->cand[0][0].c = L;
+    } else {
+        PassDesc plain[kMaxPasses + 1], g[3][kMaxPasses + 1];
+        const int np_plain = plan_plain(L, plain);
+        const int gf[3] = {4, 5, 6};
+        int np_g[3];
+        for (int i = 0; i < 3; ++i) np_g[i] = plan_gather(L, gf[i], g[i]);
+        int best = np_plain;
+        for (int i = 0; i < 3; ++i)
+            if (np_g[i] > 0 && (best < 0 || np_g[i] < best)) best = np_g[i];
+        auto add = [&](const PassDesc* src, int np) {
+            if (np <= 0 || m->n_cand >= kMaxPlans) return;
+            for (int c = 0; c < m->n_cand; ++c)  // skip duplicates
+                if (m->cand_np[c] == np && std::memcmp(m->cand[c], src, sizeof(PassDesc) * np) == 0) return;
+            m->cand_np[m->n_cand] = np;
+            for (int i = 0; i < np; ++i) m->cand[m->n_cand][i] = src[i];
+            ++m->n_cand;
+        };
+        for (int i = 0; i < 3; ++i)
+            if (np_g[i] == best) add(g[i], np_g[i]);
+        add(plain, np_plain);
     }
-    PassDesc a[kMaxPasses + 1], b[kMaxPasses + 1];
-    const int na = plan_plain(L, a);
-    const int nb = plan_gather(L, b);
-    const bool use_b = nb > 0 && (na < 0 || nb < na);
-    const PassDesc* src = use_b ? b : a;
-    m->n_pass = use_b ? nb : na;
-    for (int i = 0; i < m->n_pass; ++i) m->pass[i] = src[i];
+    m->n_pass = m->cand_np[0];
+    for (int i = 0; i < m->n_pass; ++i) m->pass[i] = m->cand[0][i];
 }
 
 // Every site and every bond must belong to exactly one pass, and every gathered bit must sit
 // where the tile-index mapping expects it; a plan that breaks this is a bug, reported as such.
-static bool plan_is_valid(const ed_model* m) {
-    const int L = m->L;
-    if (L < kTileBits) return m->n_pass == 1;
+static bool plan_is_valid(int L, const PassDesc* pass, int n_pass) {
+    if (L < kTileBits) return n_pass == 1;
+    if (n_pass < 1 || n_pass > kMaxPasses) return false;
     std::vector<int> sites(L, 0), bonds(L - 1, 0);
-    for (int ip = 0; ip < m->n_pass; ++ip) {
-        const PassDesc& pd = m->pass[ip];
+    for (int ip = 0; ip < n_pass; ++ip) {
+        const PassDesc& pd = pass[ip];
         if (pd.first != (ip == 0 ? 1 : 0)) return false;
         for (int q = 0; q < kTileBits; ++q) {
             const int p = pd.bit_of[q];
@@ -295,7 +314,10 @@ ed_status fold_model(const ed_model_desc* desc, ed_model* m) {
     }
     m->op_class = cls;
     plan_passes(m);
-    if (!plan_is_valid(m)) return fail(ED_ERR_UNSUPPORTED, "internal error: invalid H psi pass plan for L = " + std::to_string(L));
+    for (int c = 0; c < m->n_cand; ++c)
+        if (!plan_is_valid(L, m->cand[c], m->cand_np[c]))
+            return fail(ED_ERR_UNSUPPORTED, "internal error: invalid H psi pass plan " + std::to_string(c) + " for L = " +
+                                                std::to_string(L));
     return ED_OK;
 }
 
@@ -382,6 +404,58 @@ ed_status ed_model_dims(const ed_model* model, int* L, int64_t* D) {
 ed_status ed_model_passes(const ed_model* model, int* passes) {
     if (!model || !passes) return ed::fail(ED_ERR_ARG, "null argument");
     *passes = model->n_pass;
+    return ED_OK;
+}
+
+ed_status ed_model_plans(const ed_model* model, int* count, int* selected) {
+    if (!model) return ed::fail(ED_ERR_ARG, "model is null");
+    if (count) *count = model->n_cand;
+    if (selected) *selected = model->plan;
+    return ED_OK;
+}
+
+ed_status ed_model_select_plan(ed_model* model, int index) {
+    if (!model) return ed::fail(ED_ERR_ARG, "model is null");
+    if (index < 0 || index >= model->n_cand) return ed::fail(ED_ERR_ARG, "plan index out of range");
+    model->plan = index;
+    model->n_pass = model->cand_np[index];
+    for (int i = 0; i < model->n_pass; ++i) model->pass[i] = model->cand[index][i];
+    return ED_OK;
+}
+
+ed_status ed_model_tune(ed_model* model, const ed_c64* psi, ed_c64* out, int reps, void* stream, int* best,
+                        float* times_ms) {
+    if (!model || !psi || !out) return ed::fail(ED_ERR_ARG, "null argument");
+    if (reps < 1) return ed::fail(ED_ERR_ARG, "reps must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    ED_HIP_TRY(hipEventCreate(&e0));
+    ED_HIP_TRY(hipEventCreate(&e1));
+    int arg = 0;
+    float best_ms = 0.0f;
+    ed_status st = ED_OK;
+    for (int c = 0; c < model->n_cand && st == ED_OK; ++c) {
+        ed_model_select_plan(model, c);
+        st = ed_apply_H(model, psi, out, stream);  // warm-up
+        if (st != ED_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == ED_OK; ++r) st = ed_apply_H(model, psi, out, stream);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= float(reps);
+        if (times_ms) times_ms[c] = ms;
+        if (c == 0 || ms < best_ms) {
+            best_ms = ms;
+            arg = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ED_TRY(st);
+    ed_model_select_plan(model, arg);
+    if (best) *best = arg;
     return ED_OK;
 }
 

@@ -79,3 +79,33 @@ def test_apply_H_deterministic():
     a = P.apply_H(m, psi)
     b = P.apply_H(m, psi)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("L", [21, 25, 28])
+def test_apply_H_every_candidate_plan(L):
+    """Every candidate pass plan of the autotuner computes the same H psi (sampled entries against
+    the oracle; whole vectors against each other to rounding), and tuning selects one of them."""
+    print(f"apply_H plans L={L}", flush=True)
+    desc = E.random_model(L, seed=9, hermitian=False) if L < 28 else E.tfim(L, 0.5)
+    psi_h = E.random_state(L, 3)
+    psi = to_dev(psi_h)
+    m = P.Model(desc)
+    n, sel = m.plans
+    assert n >= 2 and sel == 0
+    rng = np.random.default_rng(1)
+    xs = rng.integers(0, 1 << L, 2000)
+    ref = OH.apply_H_entries(desc, psi_h, xs)
+    first = None
+    for i in range(n):
+        m.select_plan(i)
+        out = P.apply_H(m, psi)
+        got = out[torch.from_numpy(xs).to(DEV)].cpu().numpy()
+        assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref)) * L, (L, i)
+        if first is None:
+            first = out
+        else:
+            assert (torch.linalg.vector_norm(out - first) / torch.linalg.vector_norm(first)).item() < 1e-14
+        del out
+    best, times = m.tune(psi, reps=2)
+    assert 0 <= best < n and len(times) == n and all(t > 0 for t in times)
+    assert m.plans[1] == best

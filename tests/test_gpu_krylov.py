@@ -146,3 +146,25 @@ def test_krylov_invariants_L26():
     assert np.max(np.abs(obs["energy"] + (L - 1))) < 1e-9 * L
     assert np.max(np.abs(obs["norm"] - 1)) < 1e-10
     assert np.allclose(obs["sz"], obs["sz"][:, ::-1], atol=1e-10)
+
+
+def test_error_paths_from_the_host():
+    """Failure handling forced from the host: a non-finite state is reported as ED_ERR_NUMERIC,
+    a short workspace as ED_ERR_WORKSPACE, overlapping buffers as ED_ERR_ARG."""
+    import ctypes as C
+    from paper_1802_10052_amd import _lib
+    L = 10
+    m = P.Model(E.tfim(L, 0.7))
+    psi = dev(E.random_state(L, 1))
+    psi[5] = float("nan")
+    with pytest.raises(P.EdError) as ei:
+        P.krylov_evolve(m, psi, 0.05, 2)
+    assert ei.value.code == "ED_ERR_NUMERIC"
+    ok = dev(E.random_state(L, 1))
+    p = _lib.KrylovParams(10, 1e-10, 0, 0, 1)
+    ws = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    code = _lib.lib().ed_krylov_evolve(m.handle, C.c_void_p(ok.data_ptr()), 0.05, 1, C.byref(p), None, None,
+                                      C.c_void_p(ws.data_ptr()), 1024, None)
+    assert _lib.STATUS[code] == "ED_ERR_WORKSPACE"
+    code = _lib.lib().ed_apply_H(m.handle, C.c_void_p(ok.data_ptr()), C.c_void_p(ok.data_ptr() + 16), None)
+    assert _lib.STATUS[code] == "ED_ERR_ARG"
