@@ -102,6 +102,13 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     *breakdown = (*beta <= tiny_rel * std::max(scale, 1e-300)) || *beta == 0.0;
     w.u[j + 1] = y;
     w.c[j + 1] = *breakdown ? 0.0 : 1.0 / ny;
+    // |u_{j+1}| = |y| grows like the product of the betas over a run of steps; keep it inside a
+    // safe exponent range so long recurrences (and vectors carried across restarts) never
+    // overflow: rescale in memory, which is rare (one pass every few dozen steps at most).
+    if (!*breakdown && (ny > 1e100 || ny < 1e-100)) {
+        ED_K(scale(y, y, make_double2(1.0 / ny, 0.0), D, s));
+        w.c[j + 1] = 1.0;
+    }
     return ED_OK;
 }
 
@@ -183,7 +190,12 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
     while (true) {
         double beta = 0.0;
         bool brk = false;
-        ED_TRY(krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s));
+        {
+            const ed_status st = krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s);
+            if (st != ED_OK)
+                return fail(st, std::string(ed_last_error()) + " (Lanczos product " + std::to_string(iters + 1) +
+                                    ", restarts " + std::to_string(restarts) + ", basis index " + std::to_string(j) + ")");
+        }
         ++iters;
         for (int i = 0; i <= j; ++i) {
             Tij(i, j) = h[i].real();
@@ -230,10 +242,11 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
             }
             const double cm = w.c[m];
             ED_HIP_TRY(hipMemcpyAsync(w.V, tmp, size_t(keep) * D * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            ED_HIP_TRY(hipMemcpyAsync(w.V + int64_t(keep) * D, w.u[m], D * sizeof(double2), hipMemcpyDeviceToDevice, s));
+            // the residual direction v_m = c_m u_m is stored normalised in slot `keep`
+            ED_K(scale(w.u[m], w.slot(keep), make_double2(cm, 0.0), D, s));
             for (int i = 0; i <= keep; ++i) {
                 w.u[i] = w.slot(i);
-                w.c[i] = (i < keep) ? 1.0 : cm;
+                w.c[i] = 1.0;
             }
             std::fill(T.begin(), T.end(), 0.0);
             for (int i = 0; i < keep; ++i) {

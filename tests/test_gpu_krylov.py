@@ -168,3 +168,22 @@ def test_error_paths_from_the_host():
     assert _lib.STATUS[code] == "ED_ERR_WORKSPACE"
     code = _lib.lib().ed_apply_H(m.handle, C.c_void_p(ok.data_ptr()), C.c_void_p(ok.data_ptr() + 16), None)
     assert _lib.STATUS[code] == "ED_ERR_ARG"
+
+
+@pytest.mark.parametrize("L", [20, 26])
+def test_lanczos_config2_shape(L):
+    """The config-2 shape (XXZ Delta = 0.5, h ~ U[-0.5, 0.5], max_basis 60 with 10 kept Ritz
+    vectors): converged with an explicit residual below 1e-10; at L = 20 the energy agrees with a
+    run that never restarts."""
+    print(f"lanczos config-2 shape L={L}", flush=True)
+    desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
+    m = P.Model(desc)
+    v0 = E.random_state_device(L, 3, DEV)
+    e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=60, n_keep=10)
+    print(f"  E0={e0!r} info={info}", flush=True)
+    assert info["converged"] and info["residual"] < 2e-10 and info["restarts"] >= 1
+    if L == 20:
+        e1, psi1, info1 = P.lanczos_ground(m, v0, tol=1e-10, max_iter=500, max_basis=500)
+        assert info1["restarts"] == 0
+        assert abs(e0 - e1) <= 1e-10 * abs(e1)
+        assert 1 - abs(torch.vdot(psi, psi1).item()) <= 1e-9
