@@ -97,9 +97,9 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     if (!std::isfinite(nrm2v)) return fail(ED_ERR_NUMERIC, "non-finite value in the Krylov recurrence");
     const double ny = std::sqrt(std::max(nrm2v, 0.0));
     *beta = cj * ny;
-    double scale = 0.0;
-    for (int i = 0; i < n; ++i) scale = std::max(scale, std::abs(h[i]));
-    *breakdown = (*beta <= tiny_rel * std::max(scale, 1e-300)) || *beta == 0.0;
+    double hmax = 0.0;
+    for (int i = 0; i < n; ++i) hmax = std::max(hmax, std::abs(h[i]));
+    *breakdown = (*beta <= tiny_rel * std::max(hmax, 1e-300)) || *beta == 0.0;
     w.u[j + 1] = y;
     w.c[j + 1] = *breakdown ? 0.0 : 1.0 / ny;
     // |u_{j+1}| = |y| grows like the product of the betas over a run of steps; keep it inside a

@@ -161,8 +161,9 @@ __global__ __launch_bounds__(kThreads) void scale_by_invnorm(const double2* __re
     }
 }
 
-// dst[x] = a * src[x] (complex a by value)
-__global__ __launch_bounds__(kThreads) void scale_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+// dst[x] = a * src[x] (complex a by value); src == dst is allowed (each element is read before
+// the same thread writes it)
+__global__ __launch_bounds__(kThreads) void scale_copy(const double2* src, double2* dst,
                                                        double2 a, int64_t D) {
     const int64_t stride = int64_t(gridDim.x) * kThreads;
     for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < D; x += stride) {
