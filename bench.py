@@ -253,6 +253,8 @@ def main():
         log(f"bench: calibration copy of {16 * D} bytes read + {16 * D} bytes written")
     best, plan_ms = model.tune(psi, out, reps=3)
     log(f"bench: tuned H psi plan {best} of {len(plan_ms)} ({', '.join(f'{t:.3f}' for t in plan_ms)} ms)")
+    for i, t in enumerate(plan_ms):
+        log(f"bench:   plan {i:2d} {t:8.3f} ms  {model.describe_plan(i)}")
     log(f"bench: apply_H L={L}, {model.passes} passes, warmup {args.warmup}, steps {args.steps}")
     for _ in range(args.warmup):
         P.apply_H(model, psi, out)
@@ -284,7 +286,8 @@ def main():
         "config": {"workload": f"apply_H, open transverse-field Ising chain g=0.5, L={L} "
                                f"(2^{L} complex128 amplitudes, seeded complex-normal state)",
                    "L": L, "passes": model.passes, "launches_per_step": model.passes,
-                   "plan": best, "plan_ms": [round(t, 4) for t in plan_ms]},
+                   "plan": best, "plan_desc": model.describe_plan(best),
+                   "plan_ms": [round(t, 4) for t in plan_ms]},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(gbs / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic() if L == 28 else None},

@@ -89,16 +89,20 @@ ed_status ed_model_dims(const ed_model* model, int* L, int64_t* D);
 /* Number of streaming passes over the state one ed_apply_H makes (diagnostic). */
 ed_status ed_model_passes(const ed_model* model, int* passes);
 
-/* Autotuning of H psi. A model holds up to 4 candidate pass plans (which index bits each
- * streaming pass covers, and how many bits above a tile are read from neighbouring tiles in L2).
- * All candidates compute the same H psi (up to the order of floating-point sums). The plan with
- * the fewest passes is selected at creation. ed_model_tune times every candidate on the caller's
- * device buffers psi, out (D amplitudes each, `reps` products per candidate, HIP events on
- * stream), selects the fastest and returns its index and the per-candidate times (host,
- * may be NULL; count from ed_model_plans). Selecting or tuning a plan modifies the handle: it
- * must not run concurrently with any other call that uses the same model. */
+/* Autotuning of H psi. A model holds up to 16 candidate pass plans (which index bits each
+ * streaming pass covers, how many bits above a tile are read from neighbouring tiles in L2, and
+ * whether a pass runs one workgroup per CU). All candidates compute the same H psi (up to the
+ * order of floating-point sums). Candidates have the fewest passes possible for L (plus the plan
+ * without neighbour reads), ordered by an estimated cost; the first is selected at creation.
+ * ed_model_tune times every candidate on the caller's device buffers psi, out (D amplitudes each,
+ * `reps` products per candidate, HIP events on stream), selects the fastest and returns its
+ * index and the per-candidate times (host, may be NULL; count from ed_model_plans). Selecting or
+ * tuning a plan modifies the handle: it must not run concurrently with any other call that uses
+ * the same model. ed_model_plan_describe writes a one-line description of candidate `index`
+ * (NUL-terminated, truncated to buf_len bytes), e.g. "first+G5 | c3 h16 +G3", into buf. */
 ed_status ed_model_plans(const ed_model* model, int* count, int* selected);
 ed_status ed_model_select_plan(ed_model* model, int index);
+ed_status ed_model_plan_describe(const ed_model* model, int index, char* buf, int buf_len);
 ed_status ed_model_tune(ed_model* model, const ed_c64* psi, ed_c64* out, int reps, void* stream, int* best,
                         float* times_ms);
 

@@ -71,6 +71,14 @@ class Model:
     def select_plan(self, index):
         call("ed_model_select_plan", self._h, int(index))
 
+    def describe_plan(self, index=None):
+        """One-line description of candidate plan `index` (default: the selected one)."""
+        if index is None:
+            index = self.plans[1]
+        buf = C.create_string_buffer(256)
+        call("ed_model_plan_describe", self._h, int(index), buf, 256)
+        return buf.value.decode()
+
     def tune(self, psi, out=None, reps=3, stream=None):
         """Time every candidate H psi plan on psi (ed_model_tune) and keep the fastest.
         Returns (best index, list of ms per product)."""

@@ -107,6 +107,7 @@ def _declare(l):
     _fn(l, "ed_apply_H", [P, P, P, P])
     _fn(l, "ed_model_plans", [P, C.POINTER(C.c_int), C.POINTER(C.c_int)])
     _fn(l, "ed_model_select_plan", [P, C.c_int])
+    _fn(l, "ed_model_plan_describe", [P, C.c_int, C.c_char_p, C.c_int])
     _fn(l, "ed_model_tune", [P, P, P, C.c_int, P, C.POINTER(C.c_int), C.POINTER(C.c_float)])
     S = C.POINTER(C.c_size_t)
     _fn(l, "ed_lanczos_workspace", [P, C.POINTER(LanczosParams), S])

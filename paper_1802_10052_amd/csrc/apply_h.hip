@@ -4,11 +4,13 @@
 // The paper contracts each rule with the rank-L tensor (tensordot + permutation per rule and
 // site). Here the state streams through HBM in a few passes. Each pass stages a 2^12-amplitude
 // tile in LDS; the tile spans either the 12 low bits (first pass: it also adds the diagonal of
-// every term) or 3 low bits (128-byte runs) times a 9-bit window of high bits (later passes,
-// which accumulate into out). Every site and bond term is assigned to exactly one pass, so a
-// term whose bits both lie in the tile is evaluated entirely on chip: the partner amplitude
-// psi[x ^ flip] comes from LDS, or from the thread's own registers when the flipped bits map to
-// the register dimension of the tile.
+// every term) or c low bits (runs of 2^c amplitudes, c = 3 or 4) times a window of 12 - c high
+// bits (later passes, which accumulate into out). Every site and off-diagonal bond term is
+// assigned to exactly one pass, so a term whose bits both lie in the tile is evaluated entirely on
+// chip: the partner amplitude psi[x ^ flip] comes from LDS, or from the thread's own registers
+// when the flipped bits map to the register dimension of the tile. Terms on the few "gathered"
+// bits just above a tile read the partner amplitude from the neighbouring tile, which the
+// workgroups of the same group stream through the same L2 at the same time.
 #include "hpsi_device.h"
 
 namespace ed {
@@ -67,8 +69,10 @@ hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, h
     for (int ip = 0; ip < m->n_pass; ++ip) {
         const PassDesc& pd = m->pass[ip];
         const PassArgs pa = to_args(pd);
-#define ED_LAUNCH_TILE(F, G)                                                                             \
-    hipLaunchKernelGGL((hpsi_tile<CLS, F, G>), dim3(unsigned(tiles)), dim3(kTileThreads), 0, s, psi, out, \
+        // optional LDS padding: one tile workgroup per CU, so the tiles of a group fit in L2
+        const unsigned pad = pd.occ1 ? unsigned(kOccPadBytes) : 0u;
+#define ED_LAUNCH_TILE(F, G)                                                                               \
+    hipLaunchKernelGGL((hpsi_tile<CLS, F, G>), dim3(unsigned(tiles)), dim3(kTileThreads), pad, s, psi, out, \
                        m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid, m->d_diag_hi, pa)
         if (pd.first) {
             if (pd.G > 0) ED_LAUNCH_TILE(true, true);

@@ -32,17 +32,17 @@ ed_status require_device(int* device);
 
 // ---------------------------------------------------------------- H psi plan
 // Tile of one streaming pass: the low `c` bits of the index plus the window of `w` bits starting
-// at bit h0 (h0 >= c, or w == 0). Bonds and sites are assigned to exactly one pass each.
+// at bit h0 (h0 >= c, or w == 0). Sites and off-diagonal bonds are assigned to one pass each.
 constexpr int kTileBits = 12;      // amplitudes per workgroup tile = 2^12 (64 KiB of LDS)
 constexpr int kTileThreads = 256;  // threads per tile workgroup
-constexpr int kWindowLow = 3;      // contiguous low bits kept in window passes (128 B runs)
 constexpr int kMaxPasses = 4;
 
-constexpr int kMaxGather = 6;     // index bits above a tile whose partner tiles are read from L2
-constexpr int kMaxPlans = 4;      // candidate pass plans per model (chosen by ed_model_tune)
+constexpr int kMaxGather = 8;     // index bits above a tile whose partner tiles are read from L2
+constexpr int kMaxPlans = 16;     // candidate pass plans per model (chosen by ed_model_tune)
+constexpr int kOccPadBytes = 40960;  // extra LDS that leaves room for one tile workgroup per CU
 
 struct PassDesc {
-    int c;            // contiguous low bits in the tile
+    int c;            // contiguous low bits in the tile (window passes: 1..8)
     int h0;           // first bit of the window
     int w;            // window width (0 for the first pass)
     int first;        // 1: writes out (and adds the diagonal); 0: accumulates into out
@@ -57,6 +57,7 @@ struct PassDesc {
     int gcross;          // the bond (gb-1, gb) between the tile's top bit and the first gathered bit
     uint32_t site_gmask;  // bit i: site on gathered bit gb + i belongs to this pass
     uint32_t bond_gmask;  // bit i: bond (gb + i, gb + i + 1) belongs to this pass
+    int occ1;            // launch with one workgroup per CU (a group's tiles then fit in L2)
 };
 
 enum OpClass : unsigned {
@@ -89,7 +90,7 @@ struct ed_model {
     ed::PassDesc pass[ed::kMaxPasses];
     int n_cand = 0;              // candidate plans and their pass counts
     int plan = 0;
-    int cand_np[ed::kMaxPlans] = {0, 0, 0, 0};
+    int cand_np[ed::kMaxPlans] = {};
     ed::PassDesc cand[ed::kMaxPlans][ed::kMaxPasses];
 };
 

@@ -69,6 +69,13 @@ __device__ __forceinline__ int64_t tile_index(const PassArgs& pa, bool first, in
     return base | int64_t(i & lowmask) | (int64_t(i >> pa.c) << pa.h0);
 }
 
+// Tile-local index t + kTileThreads * k sits at global index tile_index(t) + k * slot_step: the
+// register slots only touch bits above the thread bits (c <= 8 in window passes), so every slot of
+// a thread is one uniform stride from the first and no per-slot 64-bit index is kept.
+__device__ __forceinline__ int64_t slot_step(const PassArgs& pa, bool first) {
+    return first ? int64_t(kTileThreads) : (int64_t(kTileThreads >> pa.c) << pa.h0);
+}
+
 // One tile of one pass (tile index n). s: 4096 double2 of LDS. FIRST: writes out including the
 // diagonal; otherwise accumulates into out. GATHER: also evaluates the terms on the gathered bits
 // above the tile, reading partner amplitudes from the neighbouring tiles n ^ (bit of g).
@@ -83,15 +90,17 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     constexpr bool DIAGR = CLS & kDiagReal;
     const int t = threadIdx.x;
     const int64_t base = tile_base(pa, FIRST, n);
-    auto gidx = [&](int i) -> int64_t { return tile_index(pa, FIRST, base, i); };
+    const int64_t i0 = tile_index(pa, FIRST, base, t);
+    const int64_t step = slot_step(pa, FIRST);
+    const double2* __restrict__ pv = psi + i0;
 
     double2 v[kSlots];
     double2 acc[kSlots];
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) v[k] = psi[gidx(t + kTileThreads * k)];
+    for (int k = 0; k < kSlots; ++k) v[k] = pv[k * step];
     if (!FIRST) {
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) acc[k] = out[gidx(t + kTileThreads * k)];
+        for (int k = 0; k < kSlots; ++k) acc[k] = out[i0 + k * step];
     }
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) s[t + kTileThreads * k] = v[k];
@@ -176,14 +185,13 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
         // terms on the gathered bits: every partner is a whole neighbouring tile in the same layout
         auto tbit = [&](int gi) -> int64_t { return int64_t(1) << (pa.gpos + gi); };
         auto gbit = [&](int gi) -> int { return int((n >> (pa.gpos + gi)) & 1); };
-        auto add_tile = [&](double2 c, int64_t n2, int lflip) {
+        // the partner tile holds the same tile-local layout, shifted by the difference of the bases
+        auto partner = [&](int64_t n2) -> const double2* { return pv + (tile_base(pa, FIRST, n2) - base); };
+        auto add_tile = [&](double2 c, int64_t n2) {
             if (c.x == 0.0 && c.y == 0.0) return;
-            const int64_t b2 = tile_base(pa, FIRST, n2);
+            const double2* __restrict__ pw = partner(n2);
 #pragma unroll
-            for (int k = 0; k < kSlots; ++k) {
-                const double2 w = psi[tile_index(pa, FIRST, b2, (t + kTileThreads * k) ^ lflip)];
-                cfma<OFFR>(acc[k], c, w);
-            }
+            for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], c, pw[k * step]);
         };
         if (pa.gcross) {
             // bond (gb-1, gb): local index l = 2 bit(gb) + bit(gb-1), bit(gb-1) = local bit 11
@@ -201,11 +209,11 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
                 // m = 2 flips only bit gb: partner tile, same local index
                 const double2 d0 = B[4 * (2 * hb) + (2 * (1 - hb))], d1 = B[4 * (2 * hb + 1) + (2 * (1 - hb) + 1)];
                 if (d0.x != 0.0 || d0.y != 0.0 || d1.x != 0.0 || d1.y != 0.0) {
-                    const int64_t b2 = tile_base(pa, FIRST, n ^ tbit(0));
+                    const double2* __restrict__ pw = partner(n ^ tbit(0));
 #pragma unroll
                     for (int k = 0; k < kSlots; ++k) {
                         const int i = t + kTileThreads * k;
-                        cfma<OFFR>(acc[k], ((i >> q) & 1) ? d1 : d0, psi[tile_index(pa, FIRST, b2, i)]);
+                        cfma<OFFR>(acc[k], ((i >> q) & 1) ? d1 : d0, pw[k * step]);
                     }
                 }
             }
@@ -213,11 +221,12 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
                 // m = 3: partner tile n ^ bit(gb), local top bit flipped
                 const double2 e0 = B[4 * (2 * hb) + (3 - 2 * hb)], e1 = B[4 * (2 * hb + 1) + (2 - 2 * hb)];
                 if (e0.x != 0.0 || e0.y != 0.0 || e1.x != 0.0 || e1.y != 0.0) {
-                    const int64_t b2 = tile_base(pa, FIRST, n ^ tbit(0));
+                    // local top bit q = 11 is register bit 3: flipping it is slot k ^ (kSlots / 2)
+                    const double2* __restrict__ pw = partner(n ^ tbit(0));
 #pragma unroll
                     for (int k = 0; k < kSlots; ++k) {
                         const int i = t + kTileThreads * k;
-                        cfma<OFFR>(acc[k], ((i >> q) & 1) ? e1 : e0, psi[tile_index(pa, FIRST, b2, i ^ (1 << q))]);
+                        cfma<OFFR>(acc[k], ((i >> q) & 1) ? e1 : e0, pw[(k ^ (kSlots >> 1)) * step]);
                     }
                 }
             }
@@ -228,16 +237,16 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
                 const int g = pa.gb + gi;
                 if ((CLS & kSiteOff) && ((pa.site_gmask >> gi) & 1)) {
                     const int b = gbit(gi);
-                    add_tile(site[4 * g + (b ? 2 : 1)], n ^ tbit(gi), 0);
+                    add_tile(site[4 * g + (b ? 2 : 1)], n ^ tbit(gi));
                 }
                 if (gi + 1 < pa.G && ((pa.bond_gmask >> gi) & 1)) {
                     const double2* B = bond + 16 * g;
                     const int l = 2 * gbit(gi + 1) + gbit(gi);
                     if (CLS & kBondSingle) {
-                        add_tile(B[4 * l + (l ^ 1)], n ^ tbit(gi), 0);
-                        add_tile(B[4 * l + (l ^ 2)], n ^ tbit(gi + 1), 0);
+                        add_tile(B[4 * l + (l ^ 1)], n ^ tbit(gi));
+                        add_tile(B[4 * l + (l ^ 2)], n ^ tbit(gi + 1));
                     }
-                    if (CLS & kBondDouble) add_tile(B[4 * l + (l ^ 3)], n ^ tbit(gi) ^ tbit(gi + 1), 0);
+                    if (CLS & kBondDouble) add_tile(B[4 * l + (l ^ 3)], n ^ tbit(gi) ^ tbit(gi + 1));
                 }
             }
         }
@@ -247,7 +256,7 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     // that neighbouring workgroups gather from L2
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) {
-        double* o = reinterpret_cast<double*>(out + gidx(t + kTileThreads * k));
+        double* o = reinterpret_cast<double*>(out + i0 + k * step);
         __builtin_nontemporal_store(acc[k].x, o);
         __builtin_nontemporal_store(acc[k].y, o + 1);
     }

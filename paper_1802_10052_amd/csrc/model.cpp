@@ -28,47 +28,18 @@ ed_status require_device(int* device) {
     return ED_OK;
 }
 
-// Passes without gathered bits: the first pass covers bits 0..11, each later pass a 9-bit window
-// (plus the 3 low bits) overlapping the previous coverage by one bit for the crossing bond.
-static int plan_plain(int L, PassDesc* out) {
-    const int T = kTileBits;
-    int np = 0;
-    PassDesc& p0 = out[np++];
-    std::memset(&p0, 0, sizeof(PassDesc));
-    p0.c = T;
-    p0.h0 = T;
-    p0.first = 1;
-    for (int q = 0; q < T; ++q) p0.bit_of[q] = q;
-    p0.site_mask = (1u << T) - 1u;
-    p0.bond_mask = (1u << (T - 1)) - 1u;
-    int done_bits = T;  // sites on bits < done_bits and bonds on bits < done_bits-1 are assigned
-    const int wbits = T - kWindowLow;
-    while (done_bits < L) {
-        if (np >= kMaxPasses) return -1;
-        PassDesc& pd = out[np++];
-        std::memset(&pd, 0, sizeof(PassDesc));
-        int h0 = done_bits - 1;  // overlap one bit: the bond crossing into the window
-        if (h0 + wbits > L) h0 = L - wbits;
-        pd.c = kWindowLow;
-        pd.h0 = h0;
-        pd.w = wbits;
-        for (int q = 0; q < T; ++q) pd.bit_of[q] = q < kWindowLow ? q : h0 + (q - kWindowLow);
-        for (int q = kWindowLow; q < T; ++q) {
-            const int p = pd.bit_of[q];
-            if (p >= done_bits) pd.site_mask |= 1u << q;
-            if (q + 1 < T && p + 1 >= done_bits && p + 1 < L) pd.bond_mask |= 1u << q;
-        }
-        done_bits = h0 + wbits;
-    }
-    return np;
-}
-
-// Passes with gathered bits above each tile (their partner tiles come from L2): up to g_first in
-// the first pass and up to 4 in window passes, so that L = 28 needs two passes instead of three.
-static int plan_gather(int L, int g_first, PassDesc* out) {
+// One pass plan. The first pass covers the 12 low bits plus `g_first` gathered bits above them;
+// each later pass covers a window of 12 - cw bits above cw contiguous low bits (runs of 2^cw
+// amplitudes), plus up to `gw_max` gathered bits above the window. With off-diagonal bond terms
+// (`bonds`) consecutive passes overlap by one bit so that the bond crossing between them lies
+// inside one tile; without them the passes tile the bits edge to edge. Returns the pass count, or
+// -1 if this combination does not give a plan for L.
+static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ1, PassDesc* out) {
     const int T = kTileBits;
     const int tile_index_bits = L - T;
-    auto gathers_fit = [&](int G) { return tile_index_bits >= 3 + G; };
+    // at least 8 groups, one per XCD
+    auto gathers_fit = [&](int G) { return G <= kMaxGather && tile_index_bits >= 3 + G; };
+    if (cw < 1 || cw > 8) return -1;
     int np = 0;
     PassDesc& p0 = out[np++];
     std::memset(&p0, 0, sizeof(PassDesc));
@@ -77,58 +48,81 @@ static int plan_gather(int L, int g_first, PassDesc* out) {
     p0.first = 1;
     for (int q = 0; q < T; ++q) p0.bit_of[q] = q;
     p0.site_mask = (1u << T) - 1u;
-    p0.bond_mask = (1u << (T - 1)) - 1u;
-    int G0 = std::min(g_first, L - T);
-    if (!gathers_fit(G0)) G0 = 0;
+    p0.bond_mask = bonds ? (1u << (T - 1)) - 1u : 0u;
+    const int G0 = std::min(g_first, L - T);
     if (G0 > 0) {
+        if (!gathers_fit(G0)) return -1;
         p0.G = G0;
         p0.gb = T;
         p0.gpos = 0;
-        p0.gcross = 1;
+        p0.gcross = bonds ? 1 : 0;
         p0.site_gmask = (1u << G0) - 1u;
-        p0.bond_gmask = (1u << (G0 - 1)) - 1u;
+        p0.bond_gmask = (bonds && G0 > 1) ? (1u << (G0 - 1)) - 1u : 0u;
+        p0.occ1 = occ1;
     }
-    int done_bits = T + G0;
-    const int wbits = T - kWindowLow;
-    while (done_bits < L) {
+    int done = T + G0;  // sites on bits < done are assigned, and bonds (p, p+1) with p + 1 < done
+    const int wb = T - cw;
+    while (done < L) {
         if (np >= kMaxPasses) return -1;
         PassDesc& pd = out[np++];
         std::memset(&pd, 0, sizeof(PassDesc));
-        int h0 = done_bits - 1;
+        int h0 = bonds ? done - 1 : done;
         int G = 0;
-        if (h0 + wbits > L) {
-            h0 = L - wbits;
+        if (h0 + wb >= L) {
+            h0 = L - wb;  // last window: flush with the top bit
         } else {
-            G = std::min(4, L - (h0 + wbits));
-            if (!gathers_fit(G)) G = 0;
+            G = std::min(gw_max, L - (h0 + wb));
+            if (G > 0 && !gathers_fit(G)) G = 0;
         }
-        pd.c = kWindowLow;
+        pd.c = cw;
         pd.h0 = h0;
-        pd.w = wbits;
-        for (int q = 0; q < T; ++q) pd.bit_of[q] = q < kWindowLow ? q : h0 + (q - kWindowLow);
-        for (int q = kWindowLow; q < T; ++q) {
+        pd.w = wb;
+        for (int q = 0; q < T; ++q) pd.bit_of[q] = q < cw ? q : h0 + (q - cw);
+        for (int q = cw; q < T; ++q) {
             const int p = pd.bit_of[q];
-            if (p >= done_bits) pd.site_mask |= 1u << q;
-            if (q + 1 < T && p + 1 >= done_bits && p + 1 < L) pd.bond_mask |= 1u << q;
+            if (p >= done) pd.site_mask |= 1u << q;
+            if (bonds && q + 1 < T && p + 1 >= done && p + 1 < L) pd.bond_mask |= 1u << q;
         }
         if (G > 0) {
             pd.G = G;
-            pd.gb = h0 + wbits;
-            pd.gpos = h0 - kWindowLow;  // the window pass's tile index: bits [c, h0) then [h0 + w, L)
-            pd.gcross = 1;
+            pd.gb = h0 + wb;
+            pd.gpos = h0 - cw;  // the window pass's tile index: bits [cw, h0) then [h0 + wb, L)
+            pd.gcross = bonds ? 1 : 0;
             pd.site_gmask = (1u << G) - 1u;
-            pd.bond_gmask = G > 1 ? (1u << (G - 1)) - 1u : 0u;
+            pd.bond_gmask = (bonds && G > 1) ? (1u << (G - 1)) - 1u : 0u;
+            pd.occ1 = occ1;
         }
-        done_bits = h0 + wbits + G;
+        done = h0 + wb + G;
     }
     return np;
 }
 
-// Candidate plans: the fewest passes first (gathered, 4 bits in the first pass), then the other
-// gathered variants with the same pass count, then the plain plan. ed_model_tune times them.
+// Rough cost of a plan in units of one full read of the state, used only to order the candidates
+// (the first one is the default before tuning): 2 state streams for the first pass, 3 for each
+// accumulating window, windows of 128-byte runs high up slower, and each gathered bit a fraction
+// of a stream (mostly L2 hits in the first pass, mostly misses in windows, whose partner lines sit
+// a power-of-two apart).
+static double plan_cost(const PassDesc* pass, int np) {
+    double cost = 0.0;
+    for (int i = 0; i < np; ++i) {
+        const PassDesc& pd = pass[i];
+        if (pd.first) {
+            cost += 2.0 + 0.35 * pd.G;
+        } else {
+            const double slow = (pd.c <= 3 && pd.h0 >= 17) ? 1.25 : (pd.c <= 3 ? 1.05 : 1.0);
+            cost += 3.0 * slow + 1.2 * pd.G;
+        }
+    }
+    return cost;
+}
+
+// Candidate plans: every combination of first-pass gathers, window run length, window gathers and
+// occupancy that reaches the fewest passes, cheapest first by plan_cost, then the plain plan (no
+// gathers) if it is not among them. ed_model_tune times them on the device.
 static void plan_passes(ed_model* m) {
     const int L = m->L;
     const int T = kTileBits;
+    const bool bonds = (m->op_class & (kBondSingle | kBondDouble)) != 0;
     m->tile_bits = L < T ? L : T;
     m->n_cand = 0;
     m->plan = 0;
@@ -138,40 +132,72 @@ static void plan_passes(ed_model* m) {
         std::memset(&m->cand[0][0], 0, sizeof(PassDesc));
         m->cand[0][0].first = 1;
         m->cand[0][0].c = L;
-    } else {
-        PassDesc plain[kMaxPasses + 1], g[3][kMaxPasses + 1];
-        const int np_plain = plan_plain(L, plain);
-        const int gf[3] = {4, 5, 6};
-        int np_g[3];
-        for (int i = 0; i < 3; ++i) np_g[i] = plan_gather(L, gf[i], g[i]);
-        int best = np_plain;
-        for (int i = 0; i < 3; ++i)
-            if (np_g[i] > 0 && (best < 0 || np_g[i] < best)) best = np_g[i];
-        auto add = [&](const PassDesc* src, int np) {
-            if (np <= 0 || m->n_cand >= kMaxPlans) return;
-            for (int c = 0; c < m->n_cand; ++c)  // skip duplicates
-                if (m->cand_np[c] == np && std::memcmp(m->cand[c], src, sizeof(PassDesc) * np) == 0) return;
-            m->cand_np[m->n_cand] = np;
-            for (int i = 0; i < np; ++i) m->cand[m->n_cand][i] = src[i];
-            ++m->n_cand;
-        };
-        for (int i = 0; i < 3; ++i)
-            if (np_g[i] == best) add(g[i], np_g[i]);
-        add(plain, np_plain);
+        m->n_pass = 1;
+        m->pass[0] = m->cand[0][0];
+        return;
     }
+    struct Cand {
+        PassDesc p[kMaxPasses];
+        int np;
+        double cost;
+    };
+    std::vector<Cand> all;
+    Cand plain{};
+    plain.np = plan_make(L, 0, 3, 0, bonds, 0, plain.p);
+    plain.cost = plain.np > 0 ? plan_cost(plain.p, plain.np) : 0.0;
+    for (int g = 0; g <= kMaxGather; ++g)
+        for (int cw = 3; cw <= 4; ++cw)
+            for (int gw : {0, 2, 4})
+                for (int occ = 0; occ <= 1; ++occ) {
+                    Cand c{};
+                    c.np = plan_make(L, g, cw, gw, bonds, occ, c.p);
+                    if (c.np <= 0) continue;
+                    bool gathered = false;
+                    for (int i = 0; i < c.np; ++i) gathered = gathered || c.p[i].G > 0;
+                    if (occ && !gathered) continue;
+                    c.cost = plan_cost(c.p, c.np);
+                    bool dup = false;
+                    for (const Cand& o : all)
+                        dup = dup || (o.np == c.np && std::memcmp(o.p, c.p, sizeof(PassDesc) * c.np) == 0);
+                    if (!dup) all.push_back(c);
+                }
+    int best_np = kMaxPasses + 1;
+    for (const Cand& c : all) best_np = std::min(best_np, c.np);
+    std::vector<Cand> keep;
+    for (const Cand& c : all)
+        if (c.np == best_np) keep.push_back(c);
+    std::stable_sort(keep.begin(), keep.end(), [](const Cand& a, const Cand& b) { return a.cost < b.cost; });
+    auto add = [&](const Cand& c) {
+        if (m->n_cand >= kMaxPlans) return;
+        for (int i = 0; i < m->n_cand; ++i)
+            if (m->cand_np[i] == c.np && std::memcmp(m->cand[i], c.p, sizeof(PassDesc) * c.np) == 0) return;
+        m->cand_np[m->n_cand] = c.np;
+        for (int i = 0; i < c.np; ++i) m->cand[m->n_cand][i] = c.p[i];
+        ++m->n_cand;
+    };
+    const int room = plain.np > 0 ? kMaxPlans - 1 : kMaxPlans;
+    for (size_t i = 0; i < keep.size() && m->n_cand < room; ++i) add(keep[i]);
+    if (plain.np > 0) add(plain);
     m->n_pass = m->cand_np[0];
     for (int i = 0; i < m->n_pass; ++i) m->pass[i] = m->cand[0][i];
 }
 
-// Every site and every bond must belong to exactly one pass, and every gathered bit must sit
-// where the tile-index mapping expects it; a plan that breaks this is a bug, reported as such.
-static bool plan_is_valid(int L, const PassDesc* pass, int n_pass) {
+// Every site must belong to exactly one pass, and so must every bond when the model has
+// off-diagonal bond terms (otherwise a bond may belong to at most one); every gathered bit must
+// sit where the tile-index mapping expects it. A plan that breaks this is a bug, reported as such.
+static bool plan_is_valid(int L, bool bonds_needed, const PassDesc* pass, int n_pass) {
     if (L < kTileBits) return n_pass == 1;
     if (n_pass < 1 || n_pass > kMaxPasses) return false;
     std::vector<int> sites(L, 0), bonds(L - 1, 0);
     for (int ip = 0; ip < n_pass; ++ip) {
         const PassDesc& pd = pass[ip];
         if (pd.first != (ip == 0 ? 1 : 0)) return false;
+        if (pd.first) {
+            if (pd.c != kTileBits || pd.h0 != kTileBits) return false;
+        } else {
+            if (pd.c < 1 || pd.c > 8 || pd.w != kTileBits - pd.c || pd.h0 < pd.c || pd.h0 + pd.w > L) return false;
+        }
+        if (pd.occ1 != 0 && pd.occ1 != 1) return false;
         for (int q = 0; q < kTileBits; ++q) {
             const int p = pd.bit_of[q];
             if (p < 0 || p >= L) return false;
@@ -196,14 +222,14 @@ static bool plan_is_valid(int L, const PassDesc* pass, int n_pass) {
                 }
             }
             if (pd.gcross) ++bonds[pd.gb - 1];
-        } else if (pd.site_gmask || pd.bond_gmask || pd.gcross) {
+        } else if (pd.site_gmask || pd.bond_gmask || pd.gcross || pd.occ1) {
             return false;
         }
     }
     for (int c : sites)
         if (c != 1) return false;
     for (int c : bonds)
-        if (c != 1) return false;
+        if (bonds_needed ? c != 1 : c > 1) return false;
     return true;
 }
 
@@ -315,7 +341,7 @@ ed_status fold_model(const ed_model_desc* desc, ed_model* m) {
     m->op_class = cls;
     plan_passes(m);
     for (int c = 0; c < m->n_cand; ++c)
-        if (!plan_is_valid(L, m->cand[c], m->cand_np[c]))
+        if (!plan_is_valid(L, (cls & (kBondSingle | kBondDouble)) != 0, m->cand[c], m->cand_np[c]))
             return fail(ED_ERR_UNSUPPORTED, "internal error: invalid H psi pass plan " + std::to_string(c) + " for L = " +
                                                 std::to_string(L));
     return ED_OK;
@@ -420,6 +446,28 @@ ed_status ed_model_select_plan(ed_model* model, int index) {
     model->plan = index;
     model->n_pass = model->cand_np[index];
     for (int i = 0; i < model->n_pass; ++i) model->pass[i] = model->cand[index][i];
+    return ED_OK;
+}
+
+ed_status ed_model_plan_describe(const ed_model* model, int index, char* buf, int buf_len) {
+    if (!model || !buf || buf_len < 1) return ed::fail(ED_ERR_ARG, "null argument");
+    if (index < 0 || index >= model->n_cand) return ed::fail(ED_ERR_ARG, "plan index out of range");
+    std::string d;
+    for (int i = 0; i < model->cand_np[index]; ++i) {
+        const ed::PassDesc& pd = model->cand[index][i];
+        if (i) d += " | ";
+        if (model->L < ed::kTileBits) {
+            d += "small";
+        } else if (pd.first) {
+            d += "first";
+        } else {
+            d += "c" + std::to_string(pd.c) + " h" + std::to_string(pd.h0);
+        }
+        if (pd.G > 0) d += " +G" + std::to_string(pd.G);
+        if (pd.occ1) d += " occ1";
+    }
+    std::strncpy(buf, d.c_str(), size_t(buf_len) - 1);
+    buf[buf_len - 1] = 0;
     return ED_OK;
 }
 

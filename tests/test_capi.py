@@ -76,8 +76,12 @@ def test_pass_plans_valid_for_every_length():
     looking for a device: on a CPU-only host every L must get as far as ED_ERR_NODEVICE."""
     lib = _lib.lib()
     for L in range(2, 31):
-        d, keep = _desc(L=L, n_site=2, n_bond=2)
-        keep[0][:] = np.array([[0, 1], [1, 0]])   # off-diagonal sites
-        keep[2][:, 0, 3] = 1.0                     # double-flip bonds
-        h = C.c_void_p()
-        assert lib.ed_model_create(C.byref(d), C.byref(h)) == -3, (L, lib.ed_last_error())
+        for flip_bonds in (True, False):
+            d, keep = _desc(L=L, n_site=2, n_bond=2)
+            keep[0][:] = np.array([[0, 1], [1, 0]])   # off-diagonal sites
+            keep[2][:] = 0.0
+            keep[2][:, 0, 0] = 1.0                     # diagonal bond part (zz-like)
+            if flip_bonds:
+                keep[2][:, 0, 3] = 1.0                 # double-flip bonds: passes must overlap
+            h = C.c_void_p()
+            assert lib.ed_model_create(C.byref(d), C.byref(h)) == -3, (L, flip_bonds, lib.ed_last_error())

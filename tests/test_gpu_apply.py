@@ -81,12 +81,28 @@ def test_apply_H_deterministic():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("L", [21, 25, 28])
-def test_apply_H_every_candidate_plan(L):
+def _plan_model(L, kind):
+    """Models for the plan tests: 'flip' has single and double bond flips (passes overlap by one
+    bit); 'rtfim' is a disordered transverse-field Ising chain (no bond flips: passes edge to
+    edge, real kernel variant); 'cfield' has complex site fields and no bond flips (edge-to-edge
+    passes on the general kernel variant, whose bond masks are then empty)."""
+    rng = np.random.default_rng(100 + L)
+    if kind == "flip":
+        return E.random_model(L, seed=9, hermitian=False)
+    if kind == "rtfim":
+        return E.ModelDesc(L, site_ops=[E.SX], site_coef=rng.uniform(-1.5, -0.5, (1, L)),
+                           bond_ops=[E.SZSZ], bond_coef=rng.uniform(-1.5, -0.5, (1, L - 1)))
+    return E.ModelDesc(L, site_ops=[E.SX, E.SY, E.SZ], site_coef=rng.uniform(-1, 1, (3, L)),
+                       bond_ops=[E.SZSZ], bond_coef=rng.uniform(-1, 1, (1, L - 1)))
+
+
+@pytest.mark.parametrize("L,kind", [(21, "flip"), (21, "rtfim"), (21, "cfield"), (25, "flip"), (25, "rtfim"),
+                                    (25, "cfield"), (28, "rtfim"), (28, "flip")])
+def test_apply_H_every_candidate_plan(L, kind):
     """Every candidate pass plan of the autotuner computes the same H psi (sampled entries against
     the oracle; whole vectors against each other to rounding), and tuning selects one of them."""
-    print(f"apply_H plans L={L}", flush=True)
-    desc = E.random_model(L, seed=9, hermitian=False) if L < 28 else E.tfim(L, 0.5)
+    print(f"apply_H plans L={L} {kind}", flush=True)
+    desc = _plan_model(L, kind)
     psi_h = E.random_state(L, 3)
     psi = to_dev(psi_h)
     m = P.Model(desc)
@@ -98,6 +114,7 @@ def test_apply_H_every_candidate_plan(L):
     first = None
     for i in range(n):
         m.select_plan(i)
+        print(f"  plan {i}: {m.describe_plan(i)}", flush=True)
         out = P.apply_H(m, psi)
         got = out[torch.from_numpy(xs).to(DEV)].cpu().numpy()
         assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref)) * L, (L, i)
