@@ -32,15 +32,15 @@ __global__ __launch_bounds__(256) void hpsi_small(const double2* __restrict__ ps
 // One tile per workgroup. With gathered bits, consecutive workgroups of one XCD (workgroups are
 // dealt to the 8 XCDs round-robin) take the 2^G tiles that differ only in the gathered bits, so
 // the neighbouring tiles a workgroup reads are being streamed into the same L2 at the same time.
-template <unsigned CLS, bool FIRST, bool GATHER>
-__global__ __launch_bounds__(kTileThreads) void hpsi_tile(const double2* __restrict__ psi,
-                                                          double2* __restrict__ out,
-                                                          const double2* __restrict__ site,
-                                                          const double2* __restrict__ bond,
-                                                          const double2* __restrict__ dlo,
-                                                          const double2* __restrict__ dmid,
-                                                          const double2* __restrict__ dhi,
-                                                          PassArgs pa) {
+// OCC1 kernels run one workgroup per CU (launched with LDS padding) and may use the whole
+// register file for batched partner loads; the others keep two workgroups per CU.
+template <unsigned CLS, bool FIRST, bool GATHER, bool OCC1>
+__device__ __forceinline__ void tile_kernel_body(const double2* __restrict__ psi, double2* __restrict__ out,
+                                                 const double2* __restrict__ site,
+                                                 const double2* __restrict__ bond,
+                                                 const double2* __restrict__ dlo,
+                                                 const double2* __restrict__ dmid,
+                                                 const double2* __restrict__ dhi, const PassArgs& pa) {
     __shared__ double2 s[1 << kTileBits];
     int64_t n = blockIdx.x;
     if (GATHER) {
@@ -51,7 +51,23 @@ __global__ __launch_bounds__(kTileThreads) void hpsi_tile(const double2* __restr
         const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
         n = low | (member << pa.gpos) | (high << (pa.gpos + pa.G));
     }
-    tile_body<CLS, FIRST, GATHER>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s);
+    tile_body<CLS, FIRST, GATHER, OCC1>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s);
+}
+
+template <unsigned CLS, bool FIRST, bool GATHER>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void hpsi_tile(const double2* __restrict__ psi, double2* __restrict__ out, const double2* __restrict__ site,
+               const double2* __restrict__ bond, const double2* __restrict__ dlo, const double2* __restrict__ dmid,
+               const double2* __restrict__ dhi, PassArgs pa) {
+    tile_kernel_body<CLS, FIRST, GATHER, false>(psi, out, site, bond, dlo, dmid, dhi, pa);
+}
+
+template <unsigned CLS, bool FIRST>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void hpsi_tile_occ1(const double2* __restrict__ psi, double2* __restrict__ out, const double2* __restrict__ site,
+                    const double2* __restrict__ bond, const double2* __restrict__ dlo,
+                    const double2* __restrict__ dmid, const double2* __restrict__ dhi, PassArgs pa) {
+    tile_kernel_body<CLS, FIRST, true, true>(psi, out, site, bond, dlo, dmid, dhi, pa);
 }
 
 template <unsigned CLS>
@@ -68,20 +84,22 @@ hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, h
     const int64_t tiles = int64_t(1) << (L - kTileBits);
     for (int ip = 0; ip < m->n_pass; ++ip) {
         const PassDesc& pd = m->pass[ip];
-        const PassArgs pa = to_args(pd);
-        // optional LDS padding: one tile workgroup per CU, so the tiles of a group fit in L2
-        const unsigned pad = pd.occ1 ? unsigned(kOccPadBytes) : 0u;
-#define ED_LAUNCH_TILE(F, G)                                                                               \
-    hipLaunchKernelGGL((hpsi_tile<CLS, F, G>), dim3(unsigned(tiles)), dim3(kTileThreads), pad, s, psi, out, \
-                       m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid, m->d_diag_hi, pa)
-        if (pd.first) {
-            if (pd.G > 0) ED_LAUNCH_TILE(true, true);
-            else ED_LAUNCH_TILE(true, false);
+        const PassArgs pa = to_args(pd, m->d_jobs + (size_t(m->plan) * kMaxPasses + ip) * kMaxJobs,
+                                    m->njobs[m->plan][ip]);
+        const dim3 grid{unsigned(tiles)}, block{unsigned(kTileThreads)};
+#define ED_TILE_ARGS psi, out, m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid, m->d_diag_hi, pa
+        if (pd.G > 0 && pd.occ1) {
+            // LDS padding leaves room for one workgroup per CU, so a group's tiles fit in L2
+            if (pd.first) hipLaunchKernelGGL((hpsi_tile_occ1<CLS, true>), grid, block, kOccPadBytes, s, ED_TILE_ARGS);
+            else hipLaunchKernelGGL((hpsi_tile_occ1<CLS, false>), grid, block, kOccPadBytes, s, ED_TILE_ARGS);
+        } else if (pd.first) {
+            if (pd.G > 0) hipLaunchKernelGGL((hpsi_tile<CLS, true, true>), grid, block, 0, s, ED_TILE_ARGS);
+            else hipLaunchKernelGGL((hpsi_tile<CLS, true, false>), grid, block, 0, s, ED_TILE_ARGS);
         } else {
-            if (pd.G > 0) ED_LAUNCH_TILE(false, true);
-            else ED_LAUNCH_TILE(false, false);
+            if (pd.G > 0) hipLaunchKernelGGL((hpsi_tile<CLS, false, true>), grid, block, 0, s, ED_TILE_ARGS);
+            else hipLaunchKernelGGL((hpsi_tile<CLS, false, false>), grid, block, 0, s, ED_TILE_ARGS);
         }
-#undef ED_LAUNCH_TILE
+#undef ED_TILE_ARGS
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

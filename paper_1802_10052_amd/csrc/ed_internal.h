@@ -35,6 +35,7 @@ ed_status require_device(int* device);
 // at bit h0 (h0 >= c, or w == 0). Sites and off-diagonal bonds are assigned to one pass each.
 constexpr int kTileBits = 12;      // amplitudes per workgroup tile = 2^12 (64 KiB of LDS)
 constexpr int kTileThreads = 256;  // threads per tile workgroup
+constexpr int kTileSlots = (1 << kTileBits) / kTileThreads;  // register slots per thread (16)
 constexpr int kMaxPasses = 4;
 
 constexpr int kMaxGather = 8;     // index bits above a tile whose partner tiles are read from L2
@@ -59,6 +60,18 @@ struct PassDesc {
     uint32_t bond_gmask;  // bit i: bond (gb + i, gb + i + 1) belongs to this pass
     int occ1;            // launch with one workgroup per CU (a group's tiles then fit in L2)
 };
+
+// One gathered term of a pass as the kernels evaluate it: out[x] += coef * psi[partner of x], the
+// partner sitting in tile n ^ txor at register slot k ^ sx of the same thread; coef depends on two
+// bits of the tile index (pattern (n >> shift) & 3) and on the tile-local top bit (the upper half
+// of the register slots). Built on the host from the plan and the folded operators.
+struct GatherJob {
+    int64_t txor;
+    int sx;
+    int shift;
+    double2 coef[4][2];  // [pattern][local top bit]
+};
+constexpr int kMaxJobs = 4 * kMaxGather;  // G sites + 3 (G - 1) bond flips + 2 crossing-bond flips
 
 enum OpClass : unsigned {
     kSiteOff = 1u,      // some site operator has off-diagonal entries
@@ -92,6 +105,10 @@ struct ed_model {
     int plan = 0;
     int cand_np[ed::kMaxPlans] = {};
     ed::PassDesc cand[ed::kMaxPlans][ed::kMaxPasses];
+    // gathered terms of every candidate pass: [plan][pass][job], counts in njobs
+    std::vector<ed::GatherJob> jobs;
+    int njobs[ed::kMaxPlans][ed::kMaxPasses] = {};
+    ed::GatherJob* d_jobs = nullptr;
 };
 
 namespace ed {

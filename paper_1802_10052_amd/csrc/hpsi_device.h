@@ -32,26 +32,22 @@ __device__ __forceinline__ double2 sel4(int l, double2 a0, double2 a1, double2 a
 }
 
 // Tile-local index i = t + 256 k: local bits 0..7 across threads, 8..11 across 16 registers.
-constexpr int kSlots = (1 << kTileBits) / kTileThreads;  // 16
+constexpr int kSlots = kTileSlots;  // 16
 
 struct PassArgs {
     int c, h0, first;
     uint32_t site_mask, bond_mask;
     int bit_of[kTileBits];
     int G, gb, gpos, gcross;
-    uint32_t site_gmask, bond_gmask;
+    const GatherJob* jobs;  // the pass's gathered terms (device), njobs of them
+    int njobs;
 };
 
-// Coefficient tables of one model as the kernels see them.
+// Operator tables of one model as the per-amplitude kernels see them.
 struct ModelTables {
     const double2* site;
     const double2* bond;
-    const double2* dlo;
-    const double2* dmid;
-    const double2* dhi;
     int L;
-    int n_pass;
-    PassArgs pass[kMaxPasses];
 };
 
 // First global index of tile n of a pass (the fixed bits of the tile).
@@ -76,11 +72,19 @@ __device__ __forceinline__ int64_t slot_step(const PassArgs& pa, bool first) {
     return first ? int64_t(kTileThreads) : (int64_t(kTileThreads >> pa.c) << pa.h0);
 }
 
+// Gathered terms are evaluated BATCH jobs at a time: the partner loads of a batch are all issued
+// before any is used, so a workgroup waits for one L2 round trip per batch, not per term.
+// (Complex coefficients need more registers for the products: batches of 3 there.)
+template <unsigned CLS, bool OCC1>
+constexpr int gather_batch() { return OCC1 ? ((CLS & kOffReal) ? 4 : 3) : 1; }
+
 // One tile of one pass (tile index n). s: 4096 double2 of LDS. FIRST: writes out including the
 // diagonal; otherwise accumulates into out. GATHER: also evaluates the terms on the gathered bits
-// above the tile, reading partner amplitudes from the neighbouring tiles n ^ (bit of g).
+// above the tile (the pass's job list), reading partner amplitudes from the neighbouring tiles.
+// OCC1: the kernel runs one workgroup per CU with the whole register file; the first batch of
+// partner loads is then issued before the LDS stage so that its latency overlaps it.
 // Caller synchronises around reuse of s.
-template <unsigned CLS, bool FIRST, bool GATHER = false>
+template <unsigned CLS, bool FIRST, bool GATHER = false, bool OCC1 = false>
 __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
                                           const double2* __restrict__ site, const double2* __restrict__ bond,
                                           const double2* __restrict__ dlo, const double2* __restrict__ dmid,
@@ -102,6 +106,35 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) acc[k] = out[i0 + k * step];
     }
+    // gathered-term batches: partner tile n ^ txor, register slot k ^ sx, coefficients by pattern
+    constexpr int NB = gather_batch<CLS, OCC1>();
+    double2 gw[NB][kSlots];
+    auto gload = [&](int j0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (j0 + b < pa.njobs) {
+                const GatherJob& jb = pa.jobs[j0 + b];
+                const double2* __restrict__ pw = pv + (tile_base(pa, FIRST, n ^ jb.txor) - base);
+                const int sx = jb.sx;
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) gw[b][k] = pw[(k ^ sx) * step];
+            }
+        }
+    };
+    auto gapply = [&](int j0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (j0 + b < pa.njobs) {
+                const GatherJob& jb = pa.jobs[j0 + b];
+                const int p = int((n >> jb.shift) & 3);
+                const double2 c0 = jb.coef[p][0], c1 = jb.coef[p][1];
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, gw[b][k]);
+            }
+        }
+    };
+    if constexpr (GATHER && OCC1) gload(0);
+
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) s[t + kTileThreads * k] = v[k];
 
@@ -182,73 +215,22 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     }
 
     if constexpr (GATHER) {
-        // terms on the gathered bits: every partner is a whole neighbouring tile in the same layout
-        auto tbit = [&](int gi) -> int64_t { return int64_t(1) << (pa.gpos + gi); };
-        auto gbit = [&](int gi) -> int { return int((n >> (pa.gpos + gi)) & 1); };
-        // the partner tile holds the same tile-local layout, shifted by the difference of the bases
-        auto partner = [&](int64_t n2) -> const double2* { return pv + (tile_base(pa, FIRST, n2) - base); };
-        auto add_tile = [&](double2 c, int64_t n2) {
-            if (c.x == 0.0 && c.y == 0.0) return;
-            const double2* __restrict__ pw = partner(n2);
-#pragma unroll
-            for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], c, pw[k * step]);
-        };
-        if (pa.gcross) {
-            // bond (gb-1, gb): local index l = 2 bit(gb) + bit(gb-1), bit(gb-1) = local bit 11
+        // the crossing bond (gb-1, gb) flipping only the tile-local top bit: partner in registers
+        if ((CLS & kBondSingle) && pa.gcross) {
             const double2* B = bond + 16 * (pa.gb - 1);
-            const int hb = gbit(0);
-            constexpr int q = kTileBits - 1;
-            if (CLS & kBondSingle) {
-                // m = 1 flips only the local top bit: partner in this tile (register slot k ^ 8)
-                const double2 c0 = B[4 * (2 * hb) + (2 * hb + 1)], c1 = B[4 * (2 * hb + 1) + (2 * hb)];
+            const int hb = int((n >> pa.gpos) & 1);
+            const double2 c0 = B[4 * (2 * hb) + (2 * hb + 1)], c1 = B[4 * (2 * hb + 1) + (2 * hb)];
 #pragma unroll
-                for (int k = 0; k < kSlots; ++k) {
-                    const int i = t + kTileThreads * k;
-                    cfma<OFFR>(acc[k], ((i >> q) & 1) ? c1 : c0, v[k ^ (kSlots >> 1)]);
-                }
-                // m = 2 flips only bit gb: partner tile, same local index
-                const double2 d0 = B[4 * (2 * hb) + (2 * (1 - hb))], d1 = B[4 * (2 * hb + 1) + (2 * (1 - hb) + 1)];
-                if (d0.x != 0.0 || d0.y != 0.0 || d1.x != 0.0 || d1.y != 0.0) {
-                    const double2* __restrict__ pw = partner(n ^ tbit(0));
-#pragma unroll
-                    for (int k = 0; k < kSlots; ++k) {
-                        const int i = t + kTileThreads * k;
-                        cfma<OFFR>(acc[k], ((i >> q) & 1) ? d1 : d0, pw[k * step]);
-                    }
-                }
-            }
-            if (CLS & kBondDouble) {
-                // m = 3: partner tile n ^ bit(gb), local top bit flipped
-                const double2 e0 = B[4 * (2 * hb) + (3 - 2 * hb)], e1 = B[4 * (2 * hb + 1) + (2 - 2 * hb)];
-                if (e0.x != 0.0 || e0.y != 0.0 || e1.x != 0.0 || e1.y != 0.0) {
-                    // local top bit q = 11 is register bit 3: flipping it is slot k ^ (kSlots / 2)
-                    const double2* __restrict__ pw = partner(n ^ tbit(0));
-#pragma unroll
-                    for (int k = 0; k < kSlots; ++k) {
-                        const int i = t + kTileThreads * k;
-                        cfma<OFFR>(acc[k], ((i >> q) & 1) ? e1 : e0, pw[(k ^ (kSlots >> 1)) * step]);
-                    }
-                }
-            }
+            for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, v[k ^ (kSlots >> 1)]);
         }
-#pragma unroll
-        for (int gi = 0; gi < kMaxGather; ++gi) {
-            if (gi < pa.G) {
-                const int g = pa.gb + gi;
-                if ((CLS & kSiteOff) && ((pa.site_gmask >> gi) & 1)) {
-                    const int b = gbit(gi);
-                    add_tile(site[4 * g + (b ? 2 : 1)], n ^ tbit(gi));
-                }
-                if (gi + 1 < pa.G && ((pa.bond_gmask >> gi) & 1)) {
-                    const double2* B = bond + 16 * g;
-                    const int l = 2 * gbit(gi + 1) + gbit(gi);
-                    if (CLS & kBondSingle) {
-                        add_tile(B[4 * l + (l ^ 1)], n ^ tbit(gi));
-                        add_tile(B[4 * l + (l ^ 2)], n ^ tbit(gi + 1));
-                    }
-                    if (CLS & kBondDouble) add_tile(B[4 * l + (l ^ 3)], n ^ tbit(gi) ^ tbit(gi + 1));
-                }
-            }
+        int j0 = 0;
+        if constexpr (OCC1) {
+            gapply(0);
+            j0 = NB;
+        }
+        for (; j0 < pa.njobs; j0 += NB) {
+            gload(j0);
+            gapply(j0);
         }
     }
 
@@ -315,7 +297,7 @@ inline int pick_variant(unsigned mc) {
     return kNumVariants - 1;
 }
 
-inline PassArgs to_args(const PassDesc& pd) {
+inline PassArgs to_args(const PassDesc& pd, const GatherJob* jobs, int njobs) {
     PassArgs pa;
     pa.c = pd.c;
     pa.h0 = pd.h0;
@@ -327,8 +309,8 @@ inline PassArgs to_args(const PassDesc& pd) {
     pa.gb = pd.gb;
     pa.gpos = pd.gpos;
     pa.gcross = pd.gcross;
-    pa.site_gmask = pd.site_gmask;
-    pa.bond_gmask = pd.bond_gmask;
+    pa.jobs = jobs;
+    pa.njobs = njobs;
     return pa;
 }
 
@@ -336,12 +318,7 @@ inline ModelTables tables_of(const ed_model* m) {
     ModelTables tb;
     tb.site = m->d_site;
     tb.bond = m->d_bond;
-    tb.dlo = m->d_diag_lo;
-    tb.dmid = m->d_diag_mid;
-    tb.dhi = m->d_diag_hi;
     tb.L = m->L;
-    tb.n_pass = m->n_pass;
-    for (int i = 0; i < kMaxPasses; ++i) tb.pass[i] = to_args(m->pass[i]);
     return tb;
 }
 

@@ -233,6 +233,55 @@ static bool plan_is_valid(int L, bool bonds_needed, const PassDesc* pass, int n_
     return true;
 }
 
+// Gathered terms of one pass (see GatherJob), skipping terms whose coefficients all vanish.
+static int build_jobs(const ed_model* m, const PassDesc& pd, GatherJob* out) {
+    if (pd.G == 0) return 0;
+    int nj = 0;
+    auto push = [&](int64_t txor, int sx, int shift, auto coef) {
+        GatherJob j{};
+        j.txor = txor;
+        j.sx = sx;
+        j.shift = shift;
+        bool nz = false;
+        for (int p = 0; p < 4; ++p)
+            for (int lt = 0; lt < 2; ++lt) {
+                j.coef[p][lt] = coef(p, lt);
+                nz = nz || j.coef[p][lt].x != 0.0 || j.coef[p][lt].y != 0.0;
+            }
+        if (nz && nj < kMaxJobs) out[nj++] = j;
+    };
+    for (int gi = 0; gi < pd.G; ++gi) {
+        const int g = pd.gb + gi;
+        const int sh = pd.gpos + gi;
+        if ((pd.site_gmask >> gi) & 1) {
+            const double2* S = m->site.data() + 4 * g;
+            push(int64_t(1) << sh, 0, sh, [&](int p, int) { return S[(p & 1) ? 2 : 1]; });
+        }
+        if ((pd.bond_gmask >> gi) & 1) {
+            // bond (g, g+1): local index l = 2 bit(g+1) + bit(g) = the pattern
+            const double2* B = m->bond.data() + 16 * g;
+            push(int64_t(1) << sh, 0, sh, [&](int p, int) { return B[4 * p + (p ^ 1)]; });
+            push(int64_t(2) << sh, 0, sh, [&](int p, int) { return B[4 * p + (p ^ 2)]; });
+            push(int64_t(3) << sh, 0, sh, [&](int p, int) { return B[4 * p + (p ^ 3)]; });
+        }
+    }
+    if (pd.gcross) {
+        // bond (gb-1, gb): local index l = 2 bit(gb) + (tile-local top bit); flipping only the local
+        // top bit stays in registers (kernel), flipping bit gb or both reads tile n ^ bit(gb)
+        const double2* B = m->bond.data() + 16 * (pd.gb - 1);
+        const int sh = pd.gpos;
+        push(int64_t(1) << sh, 0, sh, [&](int p, int lt) {
+            const int l = 2 * (p & 1) + lt;
+            return B[4 * l + (l ^ 2)];
+        });
+        push(int64_t(1) << sh, kTileSlots / 2, sh, [&](int p, int lt) {
+            const int l = 2 * (p & 1) + lt;
+            return B[4 * l + (l ^ 3)];
+        });
+    }
+    return nj;
+}
+
 static inline double2 c2(double re, double im) { return make_double2(re, im); }
 
 // diagonal contribution of the sites on bits [s_lo, s_hi) and bonds on bits [b_lo, b_hi)
@@ -267,6 +316,8 @@ static void free_tables(ed_model* m) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
+    if (m->d_jobs) (void)hipFree(m->d_jobs);
+    m->d_jobs = nullptr;
 }
 
 ed_status build_device_tables(ed_model* m) {
@@ -283,6 +334,9 @@ ed_status build_device_tables(ed_model* m) {
         ED_TRY(upload(&m->d_diag_mid, mid));
         ED_TRY(upload(&m->d_diag_hi, hi));
     }
+    const size_t jb = m->jobs.size() * sizeof(GatherJob);
+    ED_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&m->d_jobs), jb ? jb : sizeof(GatherJob)));
+    if (jb) ED_HIP_TRY(hipMemcpy(m->d_jobs, m->jobs.data(), jb, hipMemcpyHostToDevice));
     return ED_OK;
 }
 
@@ -344,6 +398,10 @@ ed_status fold_model(const ed_model_desc* desc, ed_model* m) {
         if (!plan_is_valid(L, (cls & (kBondSingle | kBondDouble)) != 0, m->cand[c], m->cand_np[c]))
             return fail(ED_ERR_UNSUPPORTED, "internal error: invalid H psi pass plan " + std::to_string(c) + " for L = " +
                                                 std::to_string(L));
+    m->jobs.assign(size_t(kMaxPlans) * kMaxPasses * kMaxJobs, GatherJob{});
+    for (int c = 0; c < m->n_cand; ++c)
+        for (int i = 0; i < m->cand_np[c]; ++i)
+            m->njobs[c][i] = build_jobs(m, m->cand[c][i], m->jobs.data() + (size_t(c) * kMaxPasses + i) * kMaxJobs);
     return ED_OK;
 }
 
