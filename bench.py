@@ -41,13 +41,15 @@ def log(msg):
 
 
 HPSI_SOURCES = ["paper_1802_10052_amd/csrc/apply_h.hip", "paper_1802_10052_amd/csrc/hpsi_device.h",
-                "paper_1802_10052_amd/csrc/model.cpp"]
+                "paper_1802_10052_amd/csrc/model.cpp", "paper_1802_10052_amd/csrc/ed_internal.h"]
 TRAFFIC_PROFILE = "profiles/hpsi_tile_L28_tfim.md"
 
 
-def measured_traffic():
-    """HBM bytes per H psi from the committed rocprofv3 counter summary, if it was taken on the
-    H psi kernels as they are now (same source hash); otherwise None."""
+def measured_traffic(plan_desc):
+    """HBM bytes (read + written) per H psi of the plan `plan_desc` from the committed rocprofv3
+    counter summary, if it was taken on the H psi kernels as they are now (same source hash) and
+    lists that plan; otherwise None. Summary lines: "source-hash: <hex>" and
+    "traffic-bytes-per-apply[<plan description>]: <bytes>"."""
     import hashlib
     try:
         h = hashlib.sha256()
@@ -55,11 +57,12 @@ def measured_traffic():
             h.update(open(os.path.join(ROOT, f), "rb").read())
         cur = h.hexdigest()[:16]
         rec, traffic = None, None
+        key = f"traffic-bytes-per-apply[{plan_desc}]:"
         for line in open(os.path.join(ROOT, TRAFFIC_PROFILE)):
             if line.startswith("source-hash:"):
                 rec = line.split(":", 1)[1].strip()
-            if line.startswith("traffic-bytes-per-apply:"):
-                traffic = float(line.split(":", 1)[1])
+            if line.startswith(key):
+                traffic = float(line[len(key):])
         return traffic if rec == cur else None
     except OSError:
         return None
@@ -228,6 +231,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of the 4 GiB state first (known bytes, for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--plan", default=None,
+                    help="use the H psi plan with this description (ed_model_plan_describe) instead of tuning")
     ap.add_argument("--rows", default="all",
                     help="comma list of lanczos14,lanczos26,quench28,traj,adjoint; 'none' or 'all'")
     args = ap.parse_args()
@@ -251,10 +256,19 @@ def main():
         out.copy_(psi)
         torch.cuda.synchronize()
         log(f"bench: calibration copy of {16 * D} bytes read + {16 * D} bytes written")
-    best, plan_ms = model.tune(psi, out, reps=3)
-    log(f"bench: tuned H psi plan {best} of {len(plan_ms)} ({', '.join(f'{t:.3f}' for t in plan_ms)} ms)")
-    for i, t in enumerate(plan_ms):
-        log(f"bench:   plan {i:2d} {t:8.3f} ms  {model.describe_plan(i)}")
+    if args.plan is None:
+        best, plan_ms = model.tune(psi, out, reps=3)
+        log(f"bench: tuned H psi plan {best} of {len(plan_ms)}")
+        for i, t in enumerate(plan_ms):
+            log(f"bench:   plan {i:2d} {t:8.3f} ms  {model.describe_plan(i)}")
+    else:
+        descs = [model.describe_plan(i) for i in range(model.plans[0])]
+        if args.plan not in descs:
+            print(f"bench.py: no H psi plan '{args.plan}' for L={L}; candidates: {descs}", file=sys.stderr)
+            sys.exit(2)
+        best, plan_ms = descs.index(args.plan), []
+        model.select_plan(best)
+        log(f"bench: H psi plan {best} ({args.plan}), not tuned")
     log(f"bench: apply_H L={L}, {model.passes} passes, warmup {args.warmup}, steps {args.steps}")
     for _ in range(args.warmup):
         P.apply_H(model, psi, out)
@@ -290,7 +304,7 @@ def main():
                    "plan_ms": [round(t, 4) for t in plan_ms]},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(gbs / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic() if L == 28 else None},
+                     "traffic": measured_traffic(model.describe_plan(best)) if L == 28 else None},
         "host": host_info(),
         "wall_s": round(wall, 3),
     }

@@ -32,15 +32,11 @@ __global__ __launch_bounds__(256) void hpsi_small(const double2* __restrict__ ps
 // One tile per workgroup. With gathered bits, consecutive workgroups of one XCD (workgroups are
 // dealt to the 8 XCDs round-robin) take the 2^G tiles that differ only in the gathered bits, so
 // the neighbouring tiles a workgroup reads are being streamed into the same L2 at the same time.
-// OCC1 kernels run one workgroup per CU (launched with LDS padding) and may use the whole
-// register file for batched partner loads; the others keep two workgroups per CU.
-template <unsigned CLS, bool FIRST, bool GATHER, bool OCC1>
-__device__ __forceinline__ void tile_kernel_body(const double2* __restrict__ psi, double2* __restrict__ out,
-                                                 const double2* __restrict__ site,
-                                                 const double2* __restrict__ bond,
-                                                 const double2* __restrict__ dlo,
-                                                 const double2* __restrict__ dmid,
-                                                 const double2* __restrict__ dhi, const PassArgs& pa) {
+template <unsigned CLS, bool FIRST, bool GATHER>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void hpsi_tile(const double2* __restrict__ psi, double2* __restrict__ out, const double2* __restrict__ site,
+               const double2* __restrict__ bond, const double2* __restrict__ dlo, const double2* __restrict__ dmid,
+               const double2* __restrict__ dhi, PassArgs pa) {
     __shared__ double2 s[1 << kTileBits];
     int64_t n = blockIdx.x;
     if (GATHER) {
@@ -51,23 +47,7 @@ __device__ __forceinline__ void tile_kernel_body(const double2* __restrict__ psi
         const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
         n = low | (member << pa.gpos) | (high << (pa.gpos + pa.G));
     }
-    tile_body<CLS, FIRST, GATHER, OCC1>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s);
-}
-
-template <unsigned CLS, bool FIRST, bool GATHER>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(2)))
-void hpsi_tile(const double2* __restrict__ psi, double2* __restrict__ out, const double2* __restrict__ site,
-               const double2* __restrict__ bond, const double2* __restrict__ dlo, const double2* __restrict__ dmid,
-               const double2* __restrict__ dhi, PassArgs pa) {
-    tile_kernel_body<CLS, FIRST, GATHER, false>(psi, out, site, bond, dlo, dmid, dhi, pa);
-}
-
-template <unsigned CLS, bool FIRST>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void hpsi_tile_occ1(const double2* __restrict__ psi, double2* __restrict__ out, const double2* __restrict__ site,
-                    const double2* __restrict__ bond, const double2* __restrict__ dlo,
-                    const double2* __restrict__ dmid, const double2* __restrict__ dhi, PassArgs pa) {
-    tile_kernel_body<CLS, FIRST, true, true>(psi, out, site, bond, dlo, dmid, dhi, pa);
+    tile_body<CLS, FIRST, GATHER>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s);
 }
 
 template <unsigned CLS>
@@ -88,15 +68,13 @@ hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, h
                                     m->njobs[m->plan][ip]);
         const dim3 grid{unsigned(tiles)}, block{unsigned(kTileThreads)};
 #define ED_TILE_ARGS psi, out, m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid, m->d_diag_hi, pa
-        if (pd.G > 0 && pd.occ1) {
-            // LDS padding leaves room for one workgroup per CU, so a group's tiles fit in L2
-            if (pd.first) hipLaunchKernelGGL((hpsi_tile_occ1<CLS, true>), grid, block, kOccPadBytes, s, ED_TILE_ARGS);
-            else hipLaunchKernelGGL((hpsi_tile_occ1<CLS, false>), grid, block, kOccPadBytes, s, ED_TILE_ARGS);
-        } else if (pd.first) {
-            if (pd.G > 0) hipLaunchKernelGGL((hpsi_tile<CLS, true, true>), grid, block, 0, s, ED_TILE_ARGS);
+        // optional LDS padding: one workgroup per CU, so that the tiles of a group fit in L2
+        const unsigned pad = (pd.G > 0 && pd.occ1) ? unsigned(kOccPadBytes) : 0u;
+        if (pd.first) {
+            if (pd.G > 0) hipLaunchKernelGGL((hpsi_tile<CLS, true, true>), grid, block, pad, s, ED_TILE_ARGS);
             else hipLaunchKernelGGL((hpsi_tile<CLS, true, false>), grid, block, 0, s, ED_TILE_ARGS);
         } else {
-            if (pd.G > 0) hipLaunchKernelGGL((hpsi_tile<CLS, false, true>), grid, block, 0, s, ED_TILE_ARGS);
+            if (pd.G > 0) hipLaunchKernelGGL((hpsi_tile<CLS, false, true>), grid, block, pad, s, ED_TILE_ARGS);
             else hipLaunchKernelGGL((hpsi_tile<CLS, false, false>), grid, block, 0, s, ED_TILE_ARGS);
         }
 #undef ED_TILE_ARGS

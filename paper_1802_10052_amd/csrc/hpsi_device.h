@@ -72,19 +72,11 @@ __device__ __forceinline__ int64_t slot_step(const PassArgs& pa, bool first) {
     return first ? int64_t(kTileThreads) : (int64_t(kTileThreads >> pa.c) << pa.h0);
 }
 
-// Gathered terms are evaluated BATCH jobs at a time: the partner loads of a batch are all issued
-// before any is used, so a workgroup waits for one L2 round trip per batch, not per term.
-// (Complex coefficients need more registers for the products: batches of 3 there.)
-template <unsigned CLS, bool OCC1>
-constexpr int gather_batch() { return OCC1 ? ((CLS & kOffReal) ? 4 : 3) : 1; }
-
 // One tile of one pass (tile index n). s: 4096 double2 of LDS. FIRST: writes out including the
 // diagonal; otherwise accumulates into out. GATHER: also evaluates the terms on the gathered bits
 // above the tile (the pass's job list), reading partner amplitudes from the neighbouring tiles.
-// OCC1: the kernel runs one workgroup per CU with the whole register file; the first batch of
-// partner loads is then issued before the LDS stage so that its latency overlaps it.
 // Caller synchronises around reuse of s.
-template <unsigned CLS, bool FIRST, bool GATHER = false, bool OCC1 = false>
+template <unsigned CLS, bool FIRST, bool GATHER = false>
 __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
                                           const double2* __restrict__ site, const double2* __restrict__ bond,
                                           const double2* __restrict__ dlo, const double2* __restrict__ dmid,
@@ -106,35 +98,6 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) acc[k] = out[i0 + k * step];
     }
-    // gathered-term batches: partner tile n ^ txor, register slot k ^ sx, coefficients by pattern
-    constexpr int NB = gather_batch<CLS, OCC1>();
-    double2 gw[NB][kSlots];
-    auto gload = [&](int j0) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            if (j0 + b < pa.njobs) {
-                const GatherJob& jb = pa.jobs[j0 + b];
-                const double2* __restrict__ pw = pv + (tile_base(pa, FIRST, n ^ jb.txor) - base);
-                const int sx = jb.sx;
-#pragma unroll
-                for (int k = 0; k < kSlots; ++k) gw[b][k] = pw[(k ^ sx) * step];
-            }
-        }
-    };
-    auto gapply = [&](int j0) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            if (j0 + b < pa.njobs) {
-                const GatherJob& jb = pa.jobs[j0 + b];
-                const int p = int((n >> jb.shift) & 3);
-                const double2 c0 = jb.coef[p][0], c1 = jb.coef[p][1];
-#pragma unroll
-                for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, gw[b][k]);
-            }
-        }
-    };
-    if constexpr (GATHER && OCC1) gload(0);
-
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) s[t + kTileThreads * k] = v[k];
 
@@ -223,14 +186,17 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
 #pragma unroll
             for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, v[k ^ (kSlots >> 1)]);
         }
-        int j0 = 0;
-        if constexpr (OCC1) {
-            gapply(0);
-            j0 = NB;
-        }
-        for (; j0 < pa.njobs; j0 += NB) {
-            gload(j0);
-            gapply(j0);
+        // gathered terms: partner tile n ^ txor, register slot k ^ sx, coefficients by pattern.
+        // (Loading several partner tiles per round trip was measured slower: the one-workgroup
+        // launches are bound by the missing overlap of load, LDS and store phases, not by it.)
+        for (int j = 0; j < pa.njobs; ++j) {
+            const GatherJob& jb = pa.jobs[j];
+            const double2* __restrict__ pw = pv + (tile_base(pa, FIRST, n ^ jb.txor) - base);
+            const int sx = jb.sx;
+            const int p = int((n >> jb.shift) & 3);
+            const double2 c0 = jb.coef[p][0], c1 = jb.coef[p][1];
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, pw[(k ^ sx) * step]);
         }
     }
 
