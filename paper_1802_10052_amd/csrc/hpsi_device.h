@@ -210,31 +210,64 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     }
 }
 
-// Small-L body for one amplitude x (L < kTileBits), partners read from `src` (global or LDS).
+// Per-amplitude body for one x (small L, or one small state per workgroup): partners read from
+// `src` (global memory or LDS). Sites are taken 4 at a time, and every load of a chunk (partner
+// amplitudes and per-lane table entries) is issued before any is used; out-of-range sites load
+// index 0 entries and add nothing. A wave so keeps a chunk's loads in flight instead of waiting
+// on one partner per term.
 template <unsigned CLS>
 __device__ __forceinline__ double2 small_entry(const double2* src, const double2* __restrict__ site,
                                                const double2* __restrict__ bond, int L, int64_t x) {
     constexpr bool OFFR = CLS & kOffReal;
+    constexpr int CH = 4;
     const double2 v = src[x];
     double2 diag = make_double2(0.0, 0.0);
     double2 acc = make_double2(0.0, 0.0);
-    for (int p = 0; p < L; ++p) {
-        const int b = (x >> p) & 1;
-        const double2* S = site + 4 * p;
-        diag.x += S[3 * b].x;
-        diag.y += S[3 * b].y;
-        if (CLS & kSiteOff) cfma<OFFR>(acc, S[b ? 2 : 1], src[x ^ (int64_t(1) << p)]);
-    }
-    for (int p = 0; p + 1 < L; ++p) {
-        const int l = (x >> p) & 3;
-        const double2* B = bond + 16 * p;
-        diag.x += B[5 * l].x;
-        diag.y += B[5 * l].y;
-        if (CLS & kBondSingle) {
-            cfma<OFFR>(acc, B[4 * l + (l ^ 1)], src[x ^ (int64_t(1) << p)]);
-            cfma<OFFR>(acc, B[4 * l + (l ^ 2)], src[x ^ (int64_t(2) << p)]);
+    for (int p0 = 0; p0 < L; p0 += CH) {
+        double2 ds[CH], db[CH], ws[CH], cs[CH], w1[CH], c1[CH], w2[CH], c2[CH], w3[CH], c3[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int p = p0 + k;
+            const bool sok = p < L, bok = p + 1 < L;
+            const int ps = sok ? p : 0, pb = bok ? p : 0;
+            const int b = int((x >> ps) & 1);
+            const int l = int((x >> pb) & 3);
+            const double2* B = bond + 16 * pb;
+            ds[k] = site[4 * ps + 3 * b];
+            db[k] = B[5 * l];
+            if (CLS & kSiteOff) {
+                ws[k] = src[x ^ (int64_t(1) << ps)];
+                cs[k] = site[4 * ps + (b ? 2 : 1)];
+            }
+            if (CLS & kBondSingle) {
+                w1[k] = src[x ^ (int64_t(1) << pb)];
+                c1[k] = B[4 * l + (l ^ 1)];
+                w2[k] = src[x ^ (int64_t(2) << pb)];
+                c2[k] = B[4 * l + (l ^ 2)];
+            }
+            if (CLS & kBondDouble) {
+                w3[k] = src[x ^ (int64_t(3) << pb)];
+                c3[k] = B[4 * l + (l ^ 3)];
+            }
         }
-        if (CLS & kBondDouble) cfma<OFFR>(acc, B[4 * l + (l ^ 3)], src[x ^ (int64_t(3) << p)]);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int p = p0 + k;
+            if (p < L) {
+                diag.x += ds[k].x;
+                diag.y += ds[k].y;
+                if (CLS & kSiteOff) cfma<OFFR>(acc, cs[k], ws[k]);
+            }
+            if (p + 1 < L) {
+                diag.x += db[k].x;
+                diag.y += db[k].y;
+                if (CLS & kBondSingle) {
+                    cfma<OFFR>(acc, c1[k], w1[k]);
+                    cfma<OFFR>(acc, c2[k], w2[k]);
+                }
+                if (CLS & kBondDouble) cfma<OFFR>(acc, c3[k], w3[k]);
+            }
+        }
     }
     const double2 dv = cmul(diag, v);
     return make_double2(acc.x + dv.x, acc.y + dv.y);

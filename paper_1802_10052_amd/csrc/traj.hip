@@ -112,7 +112,8 @@ struct TrajArgs {
 
 struct Shared {
     double2 H[(kTMax + 1) * (kTMax + 1)];
-    double2 u[kTMax + 1], term[kTMax + 1], acc[kTMax + 1], h[kTMax + 1];
+    double2 u[kTMax + 1], term[kTMax + 1], acc[kTMax + 1], h[kTMax + 1], h2[kTMax + 1], coef[kTMax + 1];
+    double cs[kTMax + 1];  // basis vector i of the step is v_i = cs[i] u_i (u_i stored)
     double red[kTT / 64][2 * (kTMax + 1)];
     double pop[kMaxL + 1];
     double scal[8];
@@ -141,11 +142,19 @@ __device__ void wg_sum(double (&a)[NA], Shared& sh, double* out) {
     __syncthreads();
 }
 
+// The loops below take 4 elements (or a group of basis vectors) per iteration and issue all of
+// their loads before using any, so every wave keeps several loads in flight; a workgroup's state
+// has N = 2^L >= 256 = kTT elements, a multiple of kTT.
 __device__ double wg_norm2(const double2* x, int64_t N, Shared& sh) {
     double a[1] = {0.0};
-    for (int64_t i = threadIdx.x; i < N; i += kTT) {
-        const double2 y = x[i];
-        a[0] = fma(y.x, y.x, fma(y.y, y.y, a[0]));
+    #pragma unroll 1
+    for (int64_t i = threadIdx.x; i < N; i += 4 * kTT) {
+        double2 y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = x[i + u * kTT < N ? i + u * kTT : i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * kTT < N) a[0] = fma(y[u].x, y[u].x, fma(y[u].y, y[u].y, a[0]));
     }
     double o[1];
     wg_sum<1>(a, sh, o);
@@ -153,9 +162,14 @@ __device__ double wg_norm2(const double2* x, int64_t N, Shared& sh) {
 }
 
 __device__ void wg_scale(double2* x, int64_t N, double s) {
-    for (int64_t i = threadIdx.x; i < N; i += kTT) {
-        const double2 y = x[i];
-        x[i] = make_double2(y.x * s, y.y * s);
+    #pragma unroll 1
+    for (int64_t i = threadIdx.x; i < N; i += 4 * kTT) {
+        double2 y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = x[i + u * kTT < N ? i + u * kTT : i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * kTT < N) x[i + u * kTT] = make_double2(y[u].x * s, y[u].y * s);
     }
     __syncthreads();
 }
@@ -167,14 +181,17 @@ __device__ void wg_dots(const double2* V, int64_t ld, int n, const double2* w, i
         double a[2 * G];
 #pragma unroll
         for (int i = 0; i < 2 * G; ++i) a[i] = 0.0;
+        #pragma unroll 1
         for (int64_t x = threadIdx.x; x < N; x += kTT) {
             const double2 y = w[x];
+            double2 v[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) v[i] = V[(i0 + i < n ? i0 + i : i0) * ld + x];
 #pragma unroll
             for (int i = 0; i < G; ++i) {
                 if (i0 + i < n) {
-                    const double2 v = V[(i0 + i) * ld + x];
-                    a[2 * i] = fma(v.x, y.x, fma(v.y, y.y, a[2 * i]));
-                    a[2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, a[2 * i + 1]));
+                    a[2 * i] = fma(v[i].x, y.x, fma(v[i].y, y.y, a[2 * i]));
+                    a[2 * i + 1] = fma(v[i].x, y.y, fma(-v[i].y, y.x, a[2 * i + 1]));
                 }
             }
         }
@@ -188,12 +205,22 @@ __device__ void wg_dots(const double2* V, int64_t ld, int n, const double2* w, i
 
 // w -= sum_i c_i V_i with c in shared memory
 __device__ void wg_sub(const double2* V, int64_t ld, int n, const double2* c, double2* w, int64_t N) {
+    constexpr int G = 8;
+    #pragma unroll 1
     for (int64_t x = threadIdx.x; x < N; x += kTT) {
         double2 acc = w[x];
-        for (int i = 0; i < n; ++i) {
-            const double2 v = V[i * ld + x];
-            acc.x -= c[i].x * v.x - c[i].y * v.y;
-            acc.y -= c[i].x * v.y + c[i].y * v.x;
+        for (int i0 = 0; i0 < n; i0 += G) {
+            double2 v[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) v[i] = V[(i0 + i < n ? i0 + i : i0) * ld + x];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                if (i0 + i < n) {
+                    const double2 ci = c[i0 + i];
+                    acc.x -= ci.x * v[i].x - ci.y * v[i].y;
+                    acc.y -= ci.x * v[i].y + ci.y * v[i].x;
+                }
+            }
         }
         w[x] = acc;
     }
@@ -203,16 +230,114 @@ __device__ void wg_sub(const double2* V, int64_t ld, int n, const double2* c, do
 // out = scale * sum_i c_i V_i
 __device__ void wg_combine(const double2* V, int64_t ld, int n, const double2* c, double scale, double2* out,
                            int64_t N) {
+    constexpr int G = 8;
+    #pragma unroll 1
     for (int64_t x = threadIdx.x; x < N; x += kTT) {
         double2 acc = make_double2(0.0, 0.0);
-        for (int i = 0; i < n; ++i) {
-            const double2 v = V[i * ld + x];
-            acc.x += c[i].x * v.x - c[i].y * v.y;
-            acc.y += c[i].x * v.y + c[i].y * v.x;
+        for (int i0 = 0; i0 < n; i0 += G) {
+            double2 v[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) v[i] = V[(i0 + i < n ? i0 + i : i0) * ld + x];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                if (i0 + i < n) {
+                    const double2 ci = c[i0 + i];
+                    acc.x += ci.x * v[i].x - ci.y * v[i].y;
+                    acc.y += ci.x * v[i].y + ci.y * v[i].x;
+                }
+            }
         }
         out[x] = make_double2(scale * acc.x, scale * acc.y);
     }
     __syncthreads();
+}
+
+// Scaled-basis Gram-Schmidt pieces (v_i = cs[i] u_i). sweep B: w -= sum_i coef_i u_i over all n
+// vectors and, in the same pass, h2[i] = cs[i] <u_i|w_new> for the first G of them (their values
+// are still in registers); dots of any further vectors take an extra pass.
+__device__ void wg_sub_dots(const double2* V, int64_t ld, int n, double2* w, int64_t N, Shared& sh) {
+    constexpr int G = 8;
+    double a[2 * G];
+#pragma unroll
+    for (int i = 0; i < 2 * G; ++i) a[i] = 0.0;
+    #pragma unroll 1
+    for (int64_t x = threadIdx.x; x < N; x += kTT) {
+        double2 acc = w[x];
+        double2 keep[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) keep[i] = V[(i < n ? i : 0) * ld + x];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (i < n) {
+                const double2 ci = sh.coef[i];
+                acc.x -= ci.x * keep[i].x - ci.y * keep[i].y;
+                acc.y -= ci.x * keep[i].y + ci.y * keep[i].x;
+            }
+        }
+        for (int i0 = G; i0 < n; i0 += G) {
+            double2 v[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) v[i] = V[(i0 + i < n ? i0 + i : i0) * ld + x];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                if (i0 + i < n) {
+                    const double2 ci = sh.coef[i0 + i];
+                    acc.x -= ci.x * v[i].x - ci.y * v[i].y;
+                    acc.y -= ci.x * v[i].y + ci.y * v[i].x;
+                }
+            }
+        }
+        w[x] = acc;
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (i < n) {
+                a[2 * i] = fma(keep[i].x, acc.x, fma(keep[i].y, acc.y, a[2 * i]));
+                a[2 * i + 1] = fma(keep[i].x, acc.y, fma(-keep[i].y, acc.x, a[2 * i + 1]));
+            }
+        }
+    }
+    double o[2 * G];
+    wg_sum<2 * G>(a, sh, o);
+    if (threadIdx.x < G && threadIdx.x < n)
+        sh.h2[threadIdx.x] = make_double2(sh.cs[threadIdx.x] * o[2 * threadIdx.x], sh.cs[threadIdx.x] * o[2 * threadIdx.x + 1]);
+    __syncthreads();
+    if (n > G) {
+        // remaining vectors: plain dots, scaled
+        wg_dots(V + G * ld, ld, n - G, w, N, sh);
+        if (threadIdx.x < n - G) {
+            const double c = sh.cs[G + threadIdx.x];
+            sh.h2[G + threadIdx.x] = make_double2(c * sh.h[threadIdx.x].x, c * sh.h[threadIdx.x].y);
+        }
+        __syncthreads();
+    }
+}
+
+// sweep C: w -= sum_i coef_i u_i; returns |w_new|^2
+__device__ double wg_sub_norm(const double2* V, int64_t ld, int n, double2* w, int64_t N, Shared& sh) {
+    constexpr int G = 8;
+    double a[1] = {0.0};
+    #pragma unroll 1
+    for (int64_t x = threadIdx.x; x < N; x += kTT) {
+        double2 acc = w[x];
+        for (int i0 = 0; i0 < n; i0 += G) {
+            double2 v[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) v[i] = V[(i0 + i < n ? i0 + i : i0) * ld + x];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                if (i0 + i < n) {
+                    const double2 ci = sh.coef[i0 + i];
+                    acc.x -= ci.x * v[i].x - ci.y * v[i].y;
+                    acc.y -= ci.x * v[i].y + ci.y * v[i].x;
+                }
+            }
+        }
+        w[x] = acc;
+        a[0] = fma(acc.x, acc.x, fma(acc.y, acc.y, a[0]));
+    }
+    double o[1];
+    wg_sum<1>(a, sh, o);
+    return o[0];
 }
 
 // Per-site populations: pop[p] = sum_{bit p of x = 0} |psi_x|^2 (p = bit), pop[L] = total.
@@ -221,6 +346,7 @@ __device__ void wg_pops(const double2* psi, int L, Shared& sh) {
 #pragma unroll
     for (int i = 0; i <= kMaxL; ++i) a[i] = 0.0;
     const int64_t N = int64_t(1) << L;
+    #pragma unroll 1
     for (int64_t x = threadIdx.x; x < N; x += kTT) {
         const double2 y = psi[x];
         const double q = fma(y.x, y.x, y.y * y.y);
@@ -241,10 +367,14 @@ __device__ void wg_pops(const double2* psi, int L, Shared& sh) {
 // dst = H_eff src for the whole small state of this workgroup; partner amplitudes are read from
 // global memory (the state of one trajectory is at most 1 MiB).
 template <unsigned CLS>
-__device__ void wg_apply(const TrajModel& md, const double2* src, double2* dst, Shared& sh) {
+__device__ void wg_apply(const TrajModel& md, const double2* src, double scale, double2* dst, Shared& sh) {
     const int L = md.L;
     const int64_t N = int64_t(1) << L;
-    for (int64_t x = threadIdx.x; x < N; x += kTT) dst[x] = small_entry<CLS>(src, md.tb.site, md.tb.bond, L, x);
+    #pragma unroll 1
+    for (int64_t x = threadIdx.x; x < N; x += kTT) {
+        const double2 y = small_entry<CLS>(src, md.tb.site, md.tb.bond, L, x);
+        dst[x] = make_double2(scale * y.x, scale * y.y);
+    }
     __syncthreads();
 }
 
@@ -323,8 +453,9 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
     const int L = md.L;
     const int64_t N = int64_t(1) << L;
     const int64_t ldv = int64_t(1) << a.Lmax;
+    // the step's basis u_0 .. u_m sits at base + i * ldv, and u_0 is the state itself
     double2* psi = base;
-    double2* V = base + ldv;
+    double2* V = base;
     const int t = threadIdx.x;
     uint64_t ndraw = 0;
     auto draw = [&]() -> double {
@@ -363,10 +494,8 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
                 failed = true;  // uniform: every thread sees the same n2 and ev
                 break;
             }
-            for (int64_t x = t; x < N; x += kTT) {
-                const double2 y = psi[x];
-                V[x] = make_double2(y.x / nrm, y.y / nrm);
-            }
+            // v_0 = psi / |psi|: u_0 is psi itself, scaled by cs[0]
+            if (t == 0) sh.cs[0] = 1.0 / nrm;
             if (t < LD * LD) {
                 for (int e = t; e < LD * LD; e += kTT) sh.H[e] = make_double2(0.0, 0.0);
             }
@@ -376,20 +505,25 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
             for (int j = 0; j < a.m_max; ++j) {
                 double2* Vj = V + j * ldv;
                 double2* Wn = V + (j + 1) * ldv;
-                wg_apply<CLS>(md, Vj, Wn, sh);
-                // classical Gram-Schmidt, twice
-                wg_dots(V, ldv, j + 1, Wn, N, sh);
-                if (t <= j) sh.H[t * LD + j] = sh.h[t];
-                __syncthreads();
-                wg_sub(V, ldv, j + 1, sh.h, Wn, N);
-                wg_dots(V, ldv, j + 1, Wn, N, sh);
+                // w = H v_j = cs[j] H u_j, then classical Gram-Schmidt twice in three sweeps
+                wg_apply<CLS>(md, Vj, sh.cs[j], Wn, sh);
+                wg_dots(V, ldv, j + 1, Wn, N, sh);  // sh.h = <u_i|w>
                 if (t <= j) {
-                    sh.H[t * LD + j].x += sh.h[t].x;
-                    sh.H[t * LD + j].y += sh.h[t].y;
+                    const double c = sh.cs[t];
+                    const double2 g = make_double2(c * sh.h[t].x, c * sh.h[t].y);  // <v_i|w>
+                    sh.H[t * LD + j] = g;
+                    sh.coef[t] = make_double2(c * g.x, c * g.y);  // w -= <v_i|w> v_i = (c_i <v_i|w>) u_i
                 }
                 __syncthreads();
-                wg_sub(V, ldv, j + 1, sh.h, Wn, N);
-                const double b2 = wg_norm2(Wn, N, sh);
+                wg_sub_dots(V, ldv, j + 1, Wn, N, sh);  // sh.h2 = <v_i|w'>
+                if (t <= j) {
+                    const double c = sh.cs[t];
+                    sh.H[t * LD + j].x += sh.h2[t].x;
+                    sh.H[t * LD + j].y += sh.h2[t].y;
+                    sh.coef[t] = make_double2(c * sh.h2[t].x, c * sh.h2[t].y);
+                }
+                __syncthreads();
+                const double b2 = wg_sub_norm(V, ldv, j + 1, Wn, N, sh);
                 beta = sqrt(b2);
                 m = j + 1;
                 double hs = 0.0;
@@ -398,17 +532,23 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
                 wg_expv(m, tau_left, sh);
                 const double err = brk ? 0.0 : nrm * beta * sqrt(sh.u[m - 1].x * sh.u[m - 1].x + sh.u[m - 1].y * sh.u[m - 1].y);
                 if (brk || err <= a.tol || m >= a.m_max) break;
-                if (t == 0) sh.H[(j + 1) * LD + j] = make_double2(beta, 0.0);
-                wg_scale(Wn, N, 1.0 / beta);
+                // u_{j+1} = w'' unnormalised, v_{j+1} = w'' / beta
+                if (t == 0) {
+                    sh.H[(j + 1) * LD + j] = make_double2(beta, 0.0);
+                    sh.cs[j + 1] = 1.0 / beta;
+                }
+                __syncthreads();
             }
             mtot += m;
             // sh.u = exp(-i tau_left H_m) e_1
             const double lr = log(r);
             const double f_end = log(n2 * unorm2(m, sh)) - lr;
+            // psi(tau) = nrm sum_i u_i(tau) v_i = sum_i (nrm cs[i] u_i(tau)) u_i, written over u_0 = psi
+            // (each thread reads its element of every u_i before writing it)
             if (f_end > 0.0) {
-                if (t < m) sh.acc[t] = sh.u[t];
+                if (t < m) sh.acc[t] = make_double2(nrm * sh.cs[t] * sh.u[t].x, nrm * sh.cs[t] * sh.u[t].y);
                 __syncthreads();
-                wg_combine(V, ldv, m, sh.acc, nrm, psi, N);
+                wg_combine(V, ldv, m, sh.acc, 1.0, psi, N);
                 tau_left = 0.0;
                 break;
             }
@@ -444,9 +584,9 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
                 }
             }
             wg_expv(m, tau, sh);
-            if (t < m) sh.acc[t] = sh.u[t];
+            if (t < m) sh.acc[t] = make_double2(nrm * sh.cs[t] * sh.u[t].x, nrm * sh.cs[t] * sh.u[t].y);
             __syncthreads();
-            wg_combine(V, ldv, m, sh.acc, nrm, psi, N);
+            wg_combine(V, ldv, m, sh.acc, 1.0, psi, N);
             const double t_abs = step * a.dt + (a.dt - tau_left) + tau;
             // jump probabilities p_nu = rate_nu <psi| J^dag J |psi>_nu (J^dag J diagonal)
             wg_pops(psi, L, sh);
@@ -510,7 +650,7 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
 // Persistent launch: workgroup g runs trajectories order[g], order[g + G], ... (the order is
 // longest chain first, so the round-robin deal is balanced); every loop below is bounded.
 template <unsigned CLS>
-__global__ __launch_bounds__(kTT) void traj_kernel(TrajArgs a) {
+__global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(2))) void traj_kernel(TrajArgs a) {
     __shared__ Shared sh;
     double2* base = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
     for (int q = blockIdx.x; q < a.n_traj; q += gridDim.x) run_trajectory<CLS>(a, a.order[q], base, sh);
@@ -653,13 +793,41 @@ static double heff_bound(const ed_model* m) {
     return b;
 }
 
-static int persistent_blocks(int n_traj) {
+// Workgroups of the persistent launch: as many as can be resident at once for the kernel variant
+// (the deal is static, so a workgroup that had to wait for a free slot would finish late), at
+// most one per trajectory, and at most what a 32 GiB scratch budget holds (each workgroup keeps a
+// state and its Krylov basis: (m_max + 2) 2^Lmax amplitudes). variant < 0: the largest count over
+// the variants (used to size the workspace).
+template <int I>
+static int resident_per_cu(int variant) {
+    if constexpr (I >= kNumVariants) {
+        return 1;
+    } else {
+        if (I == variant) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, traj_kernel<kVariants[I]>, kTT, 0) != hipSuccess)
+                nb = 1;
+            return std::max(nb, 1);
+        }
+        return resident_per_cu<I + 1>(variant);
+    }
+}
+
+static int persistent_blocks(int n_traj, int Lmax, int m_max, int variant) {
     int dev = 0, cu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t pr;
         if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cu = pr.multiProcessorCount;
     }
-    return std::max(1, std::min(n_traj, 2 * cu));
+    int per_cu = 1;
+    if (variant >= 0) {
+        per_cu = resident_per_cu<0>(variant);
+    } else {
+        for (int v = 0; v < kNumVariants; ++v) per_cu = std::max(per_cu, resident_per_cu<0>(v));
+    }
+    const double per_bytes = double(m_max + 2) * double(int64_t(1) << Lmax) * sizeof(double2);
+    const int64_t by_mem = std::max<int64_t>(1, int64_t((double(int64_t(32) << 30)) / per_bytes));
+    return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(n_traj), int64_t(per_cu) * cu, by_mem})));
 }
 
 static size_t traj_bytes(const ed_traj_desc* d, const ed_traj_params* p, int Lmax, int n_out, int G) {
@@ -680,7 +848,7 @@ extern "C" ed_status ed_trajectories_workspace(const ed_traj_desc* d, const ed_t
     int Lmax = 0;
     for (int i = 0; i < d->n_models; ++i) Lmax = std::max(Lmax, d->models[i]->L);
     const int n_out = d->n_steps / d->out_stride + 1;
-    *bytes = traj_bytes(d, p, Lmax, n_out, persistent_blocks(std::max(d->n_traj, 1)));
+    *bytes = traj_bytes(d, p, Lmax, n_out, persistent_blocks(std::max(d->n_traj, 1), Lmax, p->m_max, -1));
     return ED_OK;
 }
 
@@ -695,7 +863,7 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     hipStream_t s = static_cast<hipStream_t>(stream);
     TrajSetup st;
     ED_TRY(build_setup(d, &st));
-    const int G = persistent_blocks(std::max(d->n_traj, 1));
+    const int G = persistent_blocks(std::max(d->n_traj, 1), st.Lmax, p->m_max, pick_variant(st.cls));
     const int Lmax = st.Lmax, n_out = st.n_out, nt = d->n_traj;
     // carve
     char* c = static_cast<char*>(ws);
