@@ -190,6 +190,23 @@ def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):
             "ensemble_max_z_sum_sz": ens}
 
 
+def row_trajectories_L16(P, E, torch, dev, n_traj=512, steps=20):
+    """The L = 16 slice of the trajectory workload on its own (the chain length that dominates its
+    cost): 512 trajectories, 20 steps of dt = 0.01, one persistent launch. For profiling."""
+    import numpy as np
+    L, gamma = 16, 0.1
+    m = P.Model(E.xxz(L, 1.0, 1.0))
+    psi0 = torch.from_numpy(E.product_state(L, E.neel_index(L))).to(dev)
+    mo = np.zeros(n_traj, np.int32)
+    with Timer(torch, None) as t:
+        res = P.trajectories([m], E.SMINUS, [np.full(L, gamma)], [psi0], mo, 0.01, steps, 10, 4, m_max=20, tol=1e-10)
+    return {"workload": f"{n_traj} dissipative XXZ trajectories at L={L} (J=1, Delta=1, gamma=0.1), Neel start, "
+                        f"dt=0.01, {steps} steps, one persistent launch",
+            "seconds": round(t.s, 4), "trajectory_steps_per_s": round(n_traj * steps / t.s, 1),
+            "krylov_vectors_per_step": round(res["info"]["total_krylov"] / (n_traj * steps), 3),
+            "total_jumps": res["info"]["total_jumps"], "blocks": res["info"]["blocks"]}
+
+
 def row_adjoint(P, E, torch, dev, fd_sample=4):
     import numpy as np
     L, S = 20, 50
@@ -234,7 +251,8 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="use the H psi plan with this description (ed_model_plan_describe) instead of tuning")
     ap.add_argument("--rows", default="all",
-                    help="comma list of lanczos14,lanczos26,quench28,traj,adjoint; 'none' or 'all'")
+                    help="comma list of lanczos14,lanczos26,quench28,traj,adjoint (the 'all' set) and traj16 "
+                         "(the L=16 trajectory slice, for profiling); 'none' or 'all'")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); the multi-GPU layout is a design note, "
@@ -311,8 +329,9 @@ def main():
     del psi, out
     torch.cuda.empty_cache()
     rows = {"lanczos14": row_lanczos_L14, "lanczos26": row_lanczos_entropy_L26, "quench28": row_quench_L28,
-            "traj": row_trajectories, "adjoint": row_adjoint}
-    pick = list(rows) if args.rows == "all" else ([] if args.rows == "none" else args.rows.split(","))
+            "traj": row_trajectories, "adjoint": row_adjoint, "traj16": row_trajectories_L16}
+    default_rows = ["lanczos14", "lanczos26", "quench28", "traj", "adjoint"]
+    pick = default_rows if args.rows == "all" else ([] if args.rows == "none" else args.rows.split(","))
     rec["rows"] = {}
     for name in pick:
         log(f"bench: row {name}")
