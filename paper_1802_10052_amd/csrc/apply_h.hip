@@ -50,6 +50,27 @@ void hpsi_tile(const double2* __restrict__ psi, double2* __restrict__ out, const
     tile_body<CLS, FIRST, GATHER>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s);
 }
 
+// Two tiles per workgroup (512 threads, 128 KiB of LDS, one workgroup per CU): the tiles n and
+// n ^ (tile-index bit gpos) that differ in the first gathered bit, one per half. Block b is mapped
+// like the one-tile launch, with pairs in place of tiles, so a gather group's pairs still run
+// back to back on one XCD.
+template <unsigned CLS, bool FIRST>
+__global__ __launch_bounds__(2 * kTileThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void hpsi_tile_pair(const double2* __restrict__ psi, double2* __restrict__ out, const double2* __restrict__ site,
+                    const double2* __restrict__ bond, const double2* __restrict__ dlo,
+                    const double2* __restrict__ dmid, const double2* __restrict__ dhi, PassArgs pa) {
+    __shared__ double2 s[2][1 << kTileBits];
+    const int h = int(threadIdx.x) / kTileThreads, t = int(threadIdx.x) % kTileThreads;
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b & 7, j = b >> 3;
+    const int gp = pa.G - 1;  // gathered bits besides the paired one
+    const int64_t member = j & ((int64_t(1) << gp) - 1), gl = j >> gp;
+    const int64_t group = (gl << 3) | xcd;
+    const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
+    const int64_t n = low | (int64_t(h) << pa.gpos) | (member << (pa.gpos + 1)) | (high << (pa.gpos + pa.G));
+    tile_body<CLS, FIRST, true, true>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s[h], t, s[h ^ 1]);
+}
+
 template <unsigned CLS>
 hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, hipStream_t s) {
     const int L = m->L;
@@ -70,7 +91,11 @@ hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, h
 #define ED_TILE_ARGS psi, out, m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid, m->d_diag_hi, pa
         // optional LDS padding: one workgroup per CU, so that the tiles of a group fit in L2
         const unsigned pad = (pd.G > 0 && pd.occ1) ? unsigned(kOccPadBytes) : 0u;
-        if (pd.first) {
+        if (pd.G > 0 && pd.pair) {
+            const dim3 pgrid{unsigned(tiles / 2)}, pblock{unsigned(2 * kTileThreads)};
+            if (pd.first) hipLaunchKernelGGL((hpsi_tile_pair<CLS, true>), pgrid, pblock, 0, s, ED_TILE_ARGS);
+            else hipLaunchKernelGGL((hpsi_tile_pair<CLS, false>), pgrid, pblock, 0, s, ED_TILE_ARGS);
+        } else if (pd.first) {
             if (pd.G > 0) hipLaunchKernelGGL((hpsi_tile<CLS, true, true>), grid, block, pad, s, ED_TILE_ARGS);
             else hipLaunchKernelGGL((hpsi_tile<CLS, true, false>), grid, block, 0, s, ED_TILE_ARGS);
         } else {

@@ -75,16 +75,19 @@ __device__ __forceinline__ int64_t slot_step(const PassArgs& pa, bool first) {
 // One tile of one pass (tile index n). s: 4096 double2 of LDS. FIRST: writes out including the
 // diagonal; otherwise accumulates into out. GATHER: also evaluates the terms on the gathered bits
 // above the tile (the pass's job list), reading partner amplitudes from the neighbouring tiles.
+// PAIR: the workgroup holds two tiles, n and n ^ (tile-index bit gpos), one per half of its
+// threads (t is the thread's index in its half, s its half's LDS tile, so the other half's
+// tile); jobs whose partner is the other tile read it from LDS instead of global memory.
 // Caller synchronises around reuse of s.
-template <unsigned CLS, bool FIRST, bool GATHER = false>
+template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false>
 __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
                                           const double2* __restrict__ site, const double2* __restrict__ bond,
                                           const double2* __restrict__ dlo, const double2* __restrict__ dmid,
                                           const double2* __restrict__ dhi, const PassArgs& pa, int64_t n,
-                                          double2* s) {
+                                          double2* s, int t = 0, const double2* so = nullptr) {
     constexpr bool OFFR = CLS & kOffReal;
     constexpr bool DIAGR = CLS & kDiagReal;
-    const int t = threadIdx.x;
+    if (!PAIR) t = threadIdx.x;
     const int64_t base = tile_base(pa, FIRST, n);
     const int64_t i0 = tile_index(pa, FIRST, base, t);
     const int64_t step = slot_step(pa, FIRST);
@@ -191,12 +194,18 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
         // launches are bound by the missing overlap of load, LDS and store phases, not by it.)
         for (int j = 0; j < pa.njobs; ++j) {
             const GatherJob& jb = pa.jobs[j];
-            const double2* __restrict__ pw = pv + (tile_base(pa, FIRST, n ^ jb.txor) - base);
             const int sx = jb.sx;
             const int p = int((n >> jb.shift) & 3);
             const double2 c0 = jb.coef[p][0], c1 = jb.coef[p][1];
+            if (PAIR && jb.txor == (int64_t(1) << pa.gpos)) {
 #pragma unroll
-            for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, pw[(k ^ sx) * step]);
+                for (int k = 0; k < kSlots; ++k)
+                    cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, so[t + kTileThreads * (k ^ sx)]);
+            } else {
+                const double2* __restrict__ pw = pv + (tile_base(pa, FIRST, n ^ jb.txor) - base);
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, pw[(k ^ sx) * step]);
+            }
         }
     }
 

@@ -34,7 +34,7 @@ ed_status require_device(int* device) {
 // (`bonds`) consecutive passes overlap by one bit so that the bond crossing between them lies
 // inside one tile; without them the passes tile the bits edge to edge. Returns the pass count, or
 // -1 if this combination does not give a plan for L.
-static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ1, PassDesc* out) {
+static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ1, int pair, PassDesc* out) {
     const int T = kTileBits;
     const int tile_index_bits = L - T;
     // at least 8 groups, one per XCD
@@ -58,7 +58,8 @@ static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ
         p0.gcross = bonds ? 1 : 0;
         p0.site_gmask = (1u << G0) - 1u;
         p0.bond_gmask = (bonds && G0 > 1) ? (1u << (G0 - 1)) - 1u : 0u;
-        p0.occ1 = occ1;
+        p0.occ1 = pair ? 0 : occ1;
+        p0.pair = pair;
     }
     int done = T + G0;  // sites on bits < done are assigned, and bonds (p, p+1) with p + 1 < done
     const int wb = T - cw;
@@ -90,7 +91,8 @@ static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ
             pd.gcross = bonds ? 1 : 0;
             pd.site_gmask = (1u << G) - 1u;
             pd.bond_gmask = (bonds && G > 1) ? (1u << (G - 1)) - 1u : 0u;
-            pd.occ1 = occ1;
+            pd.occ1 = pair ? 0 : occ1;
+            pd.pair = pair;
         }
         done = h0 + wb + G;
     }
@@ -106,18 +108,20 @@ static double plan_cost(const PassDesc* pass, int np) {
     double cost = 0.0;
     for (int i = 0; i < np; ++i) {
         const PassDesc& pd = pass[i];
+        const int gl2 = pd.pair ? pd.G - 1 : pd.G;  // gathered bits read through L2
+        const double stream = pd.pair ? 0.95 : 1.0;
         if (pd.first) {
-            cost += 2.0 + 0.35 * pd.G;
+            cost += 2.0 * stream + 0.35 * gl2;
         } else {
             const double slow = (pd.c <= 3 && pd.h0 >= 17) ? 1.25 : (pd.c <= 3 ? 1.05 : 1.0);
-            cost += 3.0 * slow + 1.2 * pd.G;
+            cost += 3.0 * slow * stream + 1.2 * gl2;
         }
     }
     return cost;
 }
 
 // Candidate plans: every combination of first-pass gathers, window run length, window gathers and
-// occupancy that reaches the fewest passes, cheapest first by plan_cost, then the plain plan (no
+// launch shape (two tile workgroups per CU, one, or paired tiles) that reaches the fewest passes, cheapest first by plan_cost, then the plain plan (no
 // gathers) if it is not among them. ed_model_tune times them on the device.
 static void plan_passes(ed_model* m) {
     const int L = m->L;
@@ -143,14 +147,14 @@ static void plan_passes(ed_model* m) {
     };
     std::vector<Cand> all;
     Cand plain{};
-    plain.np = plan_make(L, 0, 3, 0, bonds, 0, plain.p);
+    plain.np = plan_make(L, 0, 3, 0, bonds, 0, 0, plain.p);
     plain.cost = plain.np > 0 ? plan_cost(plain.p, plain.np) : 0.0;
     for (int g = 0; g <= kMaxGather; ++g)
         for (int cw = 3; cw <= 4; ++cw)
             for (int gw : {0, 2, 4})
-                for (int occ = 0; occ <= 1; ++occ) {
+                for (int occ = 0; occ <= 2; ++occ) {  // 0: two workgroups per CU, 1: one, 2: paired tiles
                     Cand c{};
-                    c.np = plan_make(L, g, cw, gw, bonds, occ, c.p);
+                    c.np = plan_make(L, g, cw, gw, bonds, occ == 1 ? 1 : 0, occ == 2 ? 1 : 0, c.p);
                     if (c.np <= 0) continue;
                     bool gathered = false;
                     for (int i = 0; i < c.np; ++i) gathered = gathered || c.p[i].G > 0;
@@ -198,6 +202,7 @@ static bool plan_is_valid(int L, bool bonds_needed, const PassDesc* pass, int n_
             if (pd.c < 1 || pd.c > 8 || pd.w != kTileBits - pd.c || pd.h0 < pd.c || pd.h0 + pd.w > L) return false;
         }
         if (pd.occ1 != 0 && pd.occ1 != 1) return false;
+        if (pd.pair != 0 && (pd.pair != 1 || pd.G < 1 || pd.occ1)) return false;
         for (int q = 0; q < kTileBits; ++q) {
             const int p = pd.bit_of[q];
             if (p < 0 || p >= L) return false;
@@ -222,7 +227,7 @@ static bool plan_is_valid(int L, bool bonds_needed, const PassDesc* pass, int n_
                 }
             }
             if (pd.gcross) ++bonds[pd.gb - 1];
-        } else if (pd.site_gmask || pd.bond_gmask || pd.gcross || pd.occ1) {
+        } else if (pd.site_gmask || pd.bond_gmask || pd.gcross || pd.occ1 || pd.pair) {
             return false;
         }
     }
@@ -523,6 +528,7 @@ ed_status ed_model_plan_describe(const ed_model* model, int index, char* buf, in
         }
         if (pd.G > 0) d += " +G" + std::to_string(pd.G);
         if (pd.occ1) d += " occ1";
+        if (pd.pair) d += " pair";
     }
     std::strncpy(buf, d.c_str(), size_t(buf_len) - 1);
     buf[buf_len - 1] = 0;
