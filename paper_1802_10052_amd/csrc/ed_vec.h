@@ -9,6 +9,8 @@ constexpr int kRedBlocks = 1024;  // max blocks of a partial reduction
 constexpr int kPartLd = 64;       // complex entries per block row of the partial buffer
 constexpr int kDotGroup = 16;     // basis vectors per dot/axpy launch
 constexpr int kMaxComb = 64;      // max terms of a Krylov combination
+constexpr int kChunk = 64;        // basis vectors per subtraction sweep
+constexpr int kKeepDots = 16;     // dots of the next pass taken inside a subtraction sweep
 constexpr size_t kPartBytes = size_t(kRedBlocks) * kPartLd * sizeof(double2);
 
 int reduction_blocks(int64_t D);
@@ -38,9 +40,14 @@ hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStr
 // out[i] = <U_i|w>, i < n
 hipError_t dots_ptr(const double2* const* U, int n, const double2* w, int64_t D, double2* out, double2* part,
                     hipStream_t s);
-// w -= sum_i scale[i] coef[i] U_i (coef device, scale host); nrm_out[0].x = |w_new|^2
+// w -= sum_i scale[i] coef[i] U_i (coef device, scale host); nrm_out[0].x = |w_new|^2. One sweep
+// of w per kChunk vectors.
 hipError_t axpy_norm_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
                          int64_t D, double2* nrm_out, double2* part, hipStream_t s);
+// w -= sum_i scale[i] coef[i] U_i, then dots_out[i] = <U_i|w_new> for i < n; for n <= kChunk the
+// subtraction and the dots of the first kKeepDots vectors share one sweep.
+hipError_t axpy_dots_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
+                         int64_t D, double2* dots_out, double2* part, hipStream_t s);
 // out = sum_i c[i] U_i (c host); out may be U_0 when n <= kMaxComb
 hipError_t combination_ptr(const double2* const* U, int n, const double2* c, double2* out, int64_t D, hipStream_t s);
 

@@ -59,8 +59,8 @@ ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s)
     } while (0)
 
 // One step of the recurrence on the scaled basis: y = H u_j into slot j+1, orthogonalised against
-// u_lo..u_j (passes = 1 or 2 classical Gram-Schmidt sweeps, each one dot pass and one fused
-// axpy + norm pass). Returns the true projections h_i = <v_i|H v_j> (i = lo..j) and the norm
+// u_lo..u_j by classical Gram-Schmidt once (dots, then subtraction + norm) or twice (dots; the
+// first subtraction together with the second pass's dots; subtraction + norm). Returns the true projections h_i = <v_i|H v_j> (i = lo..j) and the norm
 // beta of the orthogonalised H v_j; the new basis vector is u_{j+1} = y with c_{j+1} = 1/|y|.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
                       cplx* h, double* beta, bool* breakdown, hipStream_t s) {
@@ -80,10 +80,12 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     std::vector<double> sc(n);
     for (int i = 0; i < n; ++i) sc[i] = w.c[lo + i] * w.c[lo + i];
     ED_K(dots_ptr(U, n, y, D, g1, w.part, s));
-    ED_K(axpy_norm_ptr(U, n, g1, sc.data(), y, D, nr, w.part, s));
     if (passes > 1) {
-        ED_K(dots_ptr(U, n, y, D, g2, w.part, s));
+        // the first subtraction and the second pass's dots share a sweep
+        ED_K(axpy_dots_ptr(U, n, g1, sc.data(), y, D, g2, w.part, s));
         ED_K(axpy_norm_ptr(U, n, g2, sc.data(), y, D, nr, w.part, s));
+    } else {
+        ED_K(axpy_norm_ptr(U, n, g1, sc.data(), y, D, nr, w.part, s));
     }
     std::vector<double2> hs(1 + 2 * n);
     ED_TRY(fetch_scalars(w.scal, passes > 1 ? 1 + 2 * n : 1 + n, hs.data(), s));

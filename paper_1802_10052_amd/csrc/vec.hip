@@ -263,37 +263,86 @@ __global__ __launch_bounds__(kThreads) void dot_partial_ptr(VecPtrs U, int n, co
     }
 }
 
-// w[x] -= sum_i (sc_i * coef[i]) u_i[x]; when want_norm, part[b][0] = sum |w_new|^2 over the chunk
-template <int NG>
-__global__ __launch_bounds__(kThreads) void axpy_norm_partial(VecPtrs U, int n, const double2* __restrict__ coef,
-                                                              Scales sc, double2* __restrict__ w, int64_t D,
-                                                              int want_norm, double2* __restrict__ part,
-                                                              int part_ld) {
-    __shared__ double lds[kWaves];
-    double2 c[NG];
-#pragma unroll
-    for (int i = 0; i < NG; ++i) {
-        const double2 k = i < n ? coef[i] : make_double2(0.0, 0.0);
-        c[i] = make_double2(sc.s[i] * k.x, sc.s[i] * k.y);
+// One sweep of w against up to kChunk basis vectors: w -= sum_i (s_i coef[i]) u_i (coef device,
+// s host). Every element of w is read and written once whatever n is; the vectors are loaded 8
+// at a time with all loads of a group issued before use. NORM: part[b][0] = sum |w_new|^2 over
+// block b's chunk. KEEP (> 0): the values of the first KEEP vectors stay in registers and
+// part[b][i] = sum conj(u_i) w_new over the chunk for i < min(n, KEEP): the dots of the next
+// Gram-Schmidt pass, taken in the same sweep.
+struct ChunkArgs {
+    const double2* p[kChunk];
+    double s[kChunk];
+};
+
+template <bool NORM, int KEEP>
+__global__ __launch_bounds__(kThreads) void sub_sweep(ChunkArgs U, int n, const double2* __restrict__ coef,
+                                                      double2* __restrict__ w, int64_t D,
+                                                      double2* __restrict__ part, int part_ld) {
+    constexpr int G = 8;
+    constexpr int NA = KEEP > 0 ? 2 * KEEP : 1;
+    __shared__ double2 cl[kChunk];
+    __shared__ double lds[kWaves * NA];
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        const double2 k = coef[i];
+        cl[i] = make_double2(U.s[i] * k.x, U.s[i] * k.y);
     }
-    double a[1] = {0.0};
+    __syncthreads();
+    double a[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) a[i] = 0.0;
     const int64_t chunk = (D + gridDim.x - 1) / gridDim.x;
     const int64_t lo = int64_t(blockIdx.x) * chunk;
     const int64_t hi = lo + chunk < D ? lo + chunk : D;
     for (int64_t x = lo + threadIdx.x; x < hi; x += kThreads) {
         double2 acc = w[x];
+        double2 keep[KEEP > 0 ? KEEP : 1];
+        int i0 = 0;
+        if constexpr (KEEP > 0) {
 #pragma unroll
-        for (int i = 0; i < NG; ++i) {
-            if (i < n) {
-                const double2 v = U.p[i][x];
-                acc.x -= c[i].x * v.x - c[i].y * v.y;
-                acc.y -= c[i].x * v.y + c[i].y * v.x;
+            for (int i = 0; i < KEEP; ++i) keep[i] = U.p[i < n ? i : 0][x];
+#pragma unroll
+            for (int i = 0; i < KEEP; ++i) {
+                if (i < n) {
+                    acc.x -= cl[i].x * keep[i].x - cl[i].y * keep[i].y;
+                    acc.y -= cl[i].x * keep[i].y + cl[i].y * keep[i].x;
+                }
+            }
+            i0 = KEEP;
+        }
+        for (; i0 < n; i0 += G) {
+            double2 v[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) v[i] = U.p[i0 + i < n ? i0 + i : i0][x];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                if (i0 + i < n) {
+                    const double2 c = cl[i0 + i];
+                    acc.x -= c.x * v[i].x - c.y * v[i].y;
+                    acc.y -= c.x * v[i].y + c.y * v[i].x;
+                }
             }
         }
         w[x] = acc;
-        a[0] = fma(acc.x, acc.x, fma(acc.y, acc.y, a[0]));
+        if constexpr (KEEP > 0) {
+#pragma unroll
+            for (int i = 0; i < KEEP; ++i) {
+                if (i < n) {
+                    a[2 * i] = fma(keep[i].x, acc.x, fma(keep[i].y, acc.y, a[2 * i]));
+                    a[2 * i + 1] = fma(keep[i].x, acc.y, fma(-keep[i].y, acc.x, a[2 * i + 1]));
+                }
+            }
+        } else if constexpr (NORM) {
+            a[0] = fma(acc.x, acc.x, fma(acc.y, acc.y, a[0]));
+        }
     }
-    if (want_norm) {
+    if constexpr (KEEP > 0) {
+        block_sum<NA>(a, lds);
+        const int nk = n < KEEP ? n : KEEP;
+        if (threadIdx.x < 2 * nk) {
+            double* p = reinterpret_cast<double*>(part + int64_t(blockIdx.x) * part_ld);
+            p[threadIdx.x] = a[0];
+        }
+    } else if constexpr (NORM) {
         block_sum<1>(a, lds);
         if (threadIdx.x == 0) part[int64_t(blockIdx.x) * part_ld] = make_double2(a[0], 0.0);
     }
@@ -433,25 +482,54 @@ hipError_t dots_ptr(const double2* const* U, int n, const double2* w, int64_t D,
 hipError_t axpy_norm_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
                          int64_t D, double2* nrm_out, double2* part, hipStream_t s) {
     const int G = grid_for(D);
-    for (int i0 = 0; i0 < n || i0 == 0; i0 += kDotGroup) {
-        const int nn = n - i0 < kDotGroup ? n - i0 : kDotGroup;
-        const bool last = i0 + kDotGroup >= n;
-        VecPtrs vp;
-        Scales sc;
-        for (int i = 0; i < kDotGroup; ++i) {
-            vp.p[i] = i < nn ? U[i0 + i] : nullptr;
-            sc.s[i] = i < nn ? scale[i0 + i] : 0.0;
+    for (int i0 = 0; i0 < n || i0 == 0; i0 += kChunk) {
+        const int nn = n - i0 < kChunk ? n - i0 : kChunk;
+        const bool last = i0 + kChunk >= n;
+        ChunkArgs ca;
+        for (int i = 0; i < kChunk; ++i) {
+            ca.p[i] = i < nn ? U[i0 + i] : nullptr;
+            ca.s[i] = i < nn ? scale[i0 + i] : 0.0;
         }
-        if (nn <= 4) {
-            hipLaunchKernelGGL((axpy_norm_partial<4>), dim3(G), dim3(kThreads), 0, s, vp, nn, coef + i0, sc, w, D,
-                               last ? 1 : 0, part, kPartLd);
+        if (last) {
+            hipLaunchKernelGGL((sub_sweep<true, 0>), dim3(G), dim3(kThreads), 0, s, ca, nn, coef + i0, w, D, part,
+                               kPartLd);
+            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, 1, nrm_out, 0);
         } else {
-            hipLaunchKernelGGL((axpy_norm_partial<kDotGroup>), dim3(G), dim3(kThreads), 0, s, vp, nn, coef + i0, sc, w,
-                               D, last ? 1 : 0, part, kPartLd);
+            hipLaunchKernelGGL((sub_sweep<false, 0>), dim3(G), dim3(kThreads), 0, s, ca, nn, coef + i0, w, D, part,
+                               kPartLd);
         }
-        if (last) hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, 1, nrm_out, 0);
         if (n == 0) break;
     }
+    return hipGetLastError();
+}
+
+hipError_t axpy_dots_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
+                         int64_t D, double2* dots_out, double2* part, hipStream_t s) {
+    if (n > kChunk) {
+        // the subtraction takes several sweeps: dots afterwards, in their own sweeps
+        for (int i0 = 0; i0 < n; i0 += kChunk) {
+            const int nn = n - i0 < kChunk ? n - i0 : kChunk;
+            ChunkArgs ca;
+            for (int i = 0; i < kChunk; ++i) {
+                ca.p[i] = i < nn ? U[i0 + i] : nullptr;
+                ca.s[i] = i < nn ? scale[i0 + i] : 0.0;
+            }
+            hipLaunchKernelGGL((sub_sweep<false, 0>), dim3(grid_for(D)), dim3(kThreads), 0, s, ca, nn, coef + i0, w,
+                               D, part, kPartLd);
+        }
+        return dots_ptr(U, n, w, D, dots_out, part, s);
+    }
+    const int G = grid_for(D);
+    ChunkArgs ca;
+    for (int i = 0; i < kChunk; ++i) {
+        ca.p[i] = i < n ? U[i] : nullptr;
+        ca.s[i] = i < n ? scale[i] : 0.0;
+    }
+    hipLaunchKernelGGL((sub_sweep<false, kKeepDots>), dim3(G), dim3(kThreads), 0, s, ca, n, coef, w, D, part,
+                       kPartLd);
+    const int nk = n < kKeepDots ? n : kKeepDots;
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, nk, dots_out, 0);
+    if (n > kKeepDots) return dots_ptr(U + kKeepDots, n - kKeepDots, w, D, dots_out + kKeepDots, part, s);
     return hipGetLastError();
 }
 
