@@ -202,6 +202,26 @@ ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double dt, int n_
                            void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
+ * ed_trotter_evolve: n_steps Suzuki-Trotter time steps (Sec. II, Method 2). H = H_o + H_e,
+ * H_o = the bond terms (k, k+1) with k odd (1-based sites), H_e = those with k even; the site
+ * terms of each site are shared by the bonds that contain it, weight 1/2 each, or 1 for a site
+ * in a single bond (sites 1 and L of the open chain).
+ *   order 2: exp(-i dt/2 H_e) exp(-i dt H_o) exp(-i dt/2 H_e)              (Eq. ed:eq:trotter2)
+ *   order 4: the eleven layers of Eq. ed:eq:trotter4, constants of Eq. ed:eq:trotter4c.
+ * A layer is the product of the commuting two-site propagators exp(-i t h_k) (formed on the host
+ * from the model's folded operators, which need not be Hermitian), applied in place.
+ * psi     device, D amplitudes, in place: psi(0) on entry, psi(n_steps dt) on exit.
+ * obs     as for ed_krylov_evolve (host arrays of n_steps + 1 entries, each may be NULL);
+ *         energy = <psi|H|psi>/<psi|psi> costs one H psi per record and needs the workspace of
+ *         ed_trotter_workspace(model, with_energy = 1, ...).
+ * Errors: ED_ERR_ARG (null model/psi/ws, order not 2 or 4, n_steps < 0, dt not finite),
+ * ED_ERR_WORKSPACE. Synchronises stream.
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_trotter_workspace(const ed_model* model, int with_energy, size_t* bytes);
+ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, double dt, int n_steps, int order,
+                            const ed_observe* obs, void* ws, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------
  * ed_measure: norm and all-site <sigma^z> of a state in one read pass (Sec. IV: the diagonal of
  * every single-site reduced density matrix). psi device; sz host [L] (site order k = 1..L,
  * normalised by <psi|psi>), norm host (may be NULL). Synchronises stream.

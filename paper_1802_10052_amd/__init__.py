@@ -160,6 +160,27 @@ def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reort
     return psi, obs, {"steps": info.steps, "total_m": info.total_m, "max_m": info.max_m, "max_err": info.max_err}
 
 
+def trotter_evolve(model, psi, dt, n_steps, order=4, observe=True, energy=False, stream=None):
+    """Suzuki-Trotter time evolution of psi in place (ed_trotter_evolve, order 2 or 4). Returns
+    (psi, obs) with obs holding numpy arrays sz [(n_steps+1), L], norm [n_steps+1] and, with
+    energy=True, energy [n_steps+1]."""
+    _check_state(psi, model.D)
+    nb = C.c_size_t()
+    call("ed_trotter_workspace", model.handle, int(bool(energy)), C.byref(nb))
+    ws = _workspace(nb.value, psi.device)
+    obs = None
+    o = None
+    if observe or energy:
+        obs = {"sz": np.zeros((n_steps + 1, model.L)), "norm": np.zeros(n_steps + 1)}
+        if energy:
+            obs["energy"] = np.zeros(n_steps + 1)
+        o = _lib.Observe(obs["sz"].ctypes.data, obs["energy"].ctypes.data if energy else None,
+                         obs["norm"].ctypes.data)
+    call("ed_trotter_evolve", model.handle, _dptr(psi), float(dt), int(n_steps), int(order),
+         C.byref(o) if o is not None else None, _dptr(ws), nb.value, _stream_ptr(stream))
+    return psi, obs
+
+
 def measure(psi, L, stream=None):
     """(sz[L], norm) of a device state in one pass (ed_measure)."""
     _check_state(psi, 1 << L)

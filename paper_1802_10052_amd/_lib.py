@@ -116,6 +116,8 @@ def _declare(l):
     _fn(l, "ed_krylov_workspace", [P, C.POINTER(KrylovParams), S])
     _fn(l, "ed_krylov_evolve", [P, P, C.c_double, C.c_int, C.POINTER(KrylovParams), C.POINTER(Observe),
                                 C.POINTER(KrylovInfo), P, C.c_size_t, P])
+    _fn(l, "ed_trotter_workspace", [P, C.c_int, S])
+    _fn(l, "ed_trotter_evolve", [P, P, C.c_double, C.c_int, C.c_int, C.POINTER(Observe), P, C.c_size_t, P])
     _fn(l, "ed_measure_workspace", [C.c_int, S])
     _fn(l, "ed_entropy_workspace", [C.c_int, C.c_int, S])
     TD, TP, TO, TI = C.POINTER(TrajDesc), C.POINTER(TrajParams), C.POINTER(TrajOut), C.POINTER(TrajInfo)
