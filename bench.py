@@ -8,9 +8,10 @@ is resident in HBM and the time comes from HIP events on the stream the library 
 
 Beside it, each remaining row of the hot path is run once on its synthetic workload and reported
 under "rows": Lanczos ground state (TFIM L = 14), Lanczos + half-chain entropy (XXZ L = 26),
-the L = 28 Krylov quench (100 steps), 4096 batched quantum trajectories against the plain
-per-trajectory path, and the adjoint gradient (L = 20) against finite differences of the
-forward-only path. The CPU oracle is timed on a bounded sample of the headline workload.
+the L = 28 Krylov quench (100 steps), the same quench with the Suzuki-Trotter propagators of order
+4 and 2, 4096 batched quantum trajectories against the plain per-trajectory path, and the
+adjoint gradient (L = 20) against finite differences of the forward-only path. The CPU oracle
+is timed on a bounded sample of the headline workload.
 """
 import argparse
 import json
@@ -142,10 +143,43 @@ def row_quench_L28(P, E, torch, dev, steps=100):
     with Timer(torch, None) as t:
         _, obs, info = P.krylov_evolve(m, psi, 0.05, steps, m_max=20, tol=1e-10, reorth=0)
     e = obs["energy"]
+    _SHARED["quench28_sz"] = obs["sz"]
     return {"workload": f"TFIM g=0.5 L=28 quench from all up, dt=0.05, {steps} Krylov steps, m<=20, tol 1e-10",
             "seconds": round(t.s, 3), "ms_per_step": round(1e3 * t.s / steps, 2), "total_krylov": info["total_m"],
             "max_m": info["max_m"], "energy_drift": float(abs(e - e[0]).max() / abs(e[0])),
             "norm_drift": float(abs(obs["norm"] - 1).max()), "sz_final_site1": float(obs["sz"][-1, 0])}
+
+
+_SHARED = {}
+
+
+def row_trotter_L28(P, E, torch, dev, steps=100):
+    """The L = 28 quench of the Krylov row with the Suzuki-Trotter propagators (Sec. II, Method 2):
+    orders 4 and 2, per-step time, the algorithmic bandwidth of the gate passes (each pass reads and
+    writes the state once: 32 B per amplitude; 3 passes per layer at L = 28) and the largest
+    difference of <sigma^z_k>(t) from the Krylov run when that row ran before."""
+    import numpy as np
+    L, dt = 28, 0.05
+    m = P.Model(E.tfim(L, 0.5))
+    out = {"workload": f"TFIM g=0.5 L=28 quench from all up, dt=0.05, {steps} Trotter steps (order 4 and 2)"}
+    layers = {4: 11, 2: 3}
+    passes_per_layer = 3
+    for order in (4, 2):
+        psi = torch.zeros(1 << L, dtype=torch.complex128, device=dev)
+        psi[0] = 1.0
+        with Timer(torch, None) as t:
+            _, obs = P.trotter_evolve(m, psi, dt, steps, order=order)
+        per_step = t.s / steps
+        nbytes = layers[order] * passes_per_layer * 32.0 * (1 << L)
+        r = {"seconds": round(t.s, 3), "ms_per_step": round(1e3 * per_step, 2),
+             "gate_pass_GBps": round(nbytes / per_step / 1e9, 1), "norm_drift": float(abs(obs["norm"] - 1).max()),
+             "sz_final_site1": float(obs["sz"][-1, 0])}
+        ref = _SHARED.get("quench28_sz")
+        if ref is not None:
+            r["max_abs_sz_diff_vs_krylov"] = float(np.abs(obs["sz"] - ref).max())
+        out[f"order{order}"] = r
+        del psi
+    return out
 
 
 def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):
@@ -251,7 +285,7 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="use the H psi plan with this description (ed_model_plan_describe) instead of tuning")
     ap.add_argument("--rows", default="all",
-                    help="comma list of lanczos14,lanczos26,quench28,traj,adjoint (the 'all' set) and traj16 "
+                    help="comma list of lanczos14,lanczos26,quench28,trotter28,traj,adjoint (the 'all' set) and traj16 "
                          "(the L=16 trajectory slice, for profiling); 'none' or 'all'")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -329,8 +363,9 @@ def main():
     del psi, out
     torch.cuda.empty_cache()
     rows = {"lanczos14": row_lanczos_L14, "lanczos26": row_lanczos_entropy_L26, "quench28": row_quench_L28,
-            "traj": row_trajectories, "adjoint": row_adjoint, "traj16": row_trajectories_L16}
-    default_rows = ["lanczos14", "lanczos26", "quench28", "traj", "adjoint"]
+            "traj": row_trajectories, "adjoint": row_adjoint, "traj16": row_trajectories_L16,
+            "trotter28": row_trotter_L28}
+    default_rows = ["lanczos14", "lanczos26", "quench28", "trotter28", "traj", "adjoint"]
     pick = default_rows if args.rows == "all" else ([] if args.rows == "none" else args.rows.split(","))
     rec["rows"] = {}
     for name in pick:
