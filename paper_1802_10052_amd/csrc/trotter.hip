@@ -5,10 +5,10 @@
 // k; each site's terms are shared by the bonds that contain it (1/2 each, 1 for a site in a single
 // bond). A layer exp(-i t H_o) (or H_e) is the product of the commuting two-site propagators
 // exp(-i t h_k); the paper contracts each with two legs of the rank-L state tensor (tensordot plus
-// a permutation). Here a layer streams the state through LDS tiles in a few in-place passes with
-// the geometry of the H psi passes (the 12 low bits, then windows of 9 high bits above 3 low bits,
-// overlapping by one bit): every gate of the layer is applied in the first pass whose tile holds
-// both of its bits. Gates of one layer act on disjoint bits, so they commute and the order of the
+// a permutation). Here a layer streams the state through LDS tiles in a few in-place passes (the
+// 12 low bits, then windows of 8 high bits above 4 contiguous low bits, each starting at the first
+// bond of the layer not yet covered): every gate of the layer is applied in the first pass whose
+// tile holds both of its bits. Gates of one layer act on disjoint bits, so they commute and the order of the
 // passes is free; a tile is read completely before it is written, and tiles of a pass are
 // disjoint, so the passes work in place.
 #include <algorithm>
@@ -26,7 +26,7 @@ namespace {
 constexpr int kGThreads = 256;
 constexpr int kGTileBits = 12;
 constexpr int kGSlots = (1 << kGTileBits) / kGThreads;  // 16
-constexpr int kGLow = 3;                                 // contiguous low bits of a window tile
+constexpr int kGLow = 4;                                 // contiguous low bits of a window tile
 constexpr int kMaxGates = kGTileBits / 2;                // gates of one parity inside a tile
 
 // One pass of one layer: tile geometry and the gates it applies. A gate on tile-local bits
@@ -83,7 +83,7 @@ __device__ __forceinline__ void reg_gate(double2 (&v)[kGSlots], const double2* _
 
 // Tile-local index of slot k of thread t: i = t + kGThreads k (bits 0..7 across threads, 8..11
 // across the 16 register slots). Gates whose two bits are both register bits are applied in
-// registers; the others read the three partner amplitudes from LDS.
+// registers while the tile is loaded; the others update groups of four amplitudes in LDS.
 __global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi, GatePass gp) {
     __shared__ double2 s[1 << kGTileBits];
     const int t = threadIdx.x;
@@ -111,59 +111,112 @@ __global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi
         if (i < N) s[i] = v[k];
     }
     __syncthreads();
-    // LDS gates (bit q is a thread bit)
+    // LDS gates (bit q is a thread bit): each thread owns whole groups of the amplitudes a gate
+    // mixes (the index with zero bits inserted at q), reads them, writes them back. Two gates on
+    // adjacent pairs (q, q+1), (q+2, q+3) share one round on groups of 16. Gates are sorted by q.
     for (int g = 0; g < gp.ngate; ++g) {
         const int q = gp.q[g];
         if (q >= 8 && (1 << (q + 2)) <= N) continue;  // done in registers
         const double2* U = gp.U[g];
-        const int mask = 3 << q;
+        const bool two = g + 1 < gp.ngate && gp.q[g + 1] == q + 2 && !(q + 2 >= 8 && (1 << (q + 4)) <= N);
+        if (two) {
+            const double2* U2 = gp.U[g + 1];
+            const int lowm = (1 << q) - 1;
+            for (int j = t; j < (N >> 4); j += kGThreads) {
+                const int b = (j & lowm) | ((j >> q) << (q + 4));
+                double2 a[16];
 #pragma unroll
-        for (int k = 0; k < kGSlots; ++k) {
-            const int i = t + kGThreads * k;
-            if (i >= N) continue;
-            const int l = (i >> q) & 3;
-            const int b = i & ~mask;
-            double2 acc = make_double2(0.0, 0.0);
+                for (int m = 0; m < 16; ++m) a[m] = s[b | (m << q)];
+                // first gate on the low pair (bits q, q+1) of every group of four
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const double2 p = cmul(U[4 * l + m], s[b | (m << q)]);
-                acc.x += p.x;
-                acc.y += p.y;
+                for (int h = 0; h < 4; ++h) {
+                    double2 o[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const double2 p = cmul(U[4 * l + m], a[4 * h + m]);
+                            acc.x += p.x;
+                            acc.y += p.y;
+                        }
+                        o[l] = acc;
+                    }
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) a[4 * h + l] = o[l];
+                }
+                // second gate on the high pair (bits q+2, q+3)
+#pragma unroll
+                for (int lo = 0; lo < 4; ++lo) {
+                    double2 o[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const double2 p = cmul(U2[4 * l + m], a[4 * m + lo]);
+                            acc.x += p.x;
+                            acc.y += p.y;
+                        }
+                        o[l] = acc;
+                    }
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) a[4 * l + lo] = o[l];
+                }
+#pragma unroll
+                for (int m = 0; m < 16; ++m) s[b | (m << q)] = a[m];
             }
-            v[k] = acc;
-        }
-        __syncthreads();
+            ++g;
+        } else {
+            const int lowm = (1 << q) - 1;
+            for (int j = t; j < (N >> 2); j += kGThreads) {
+                const int b = (j & lowm) | ((j >> q) << (q + 2));
+                double2 a[4];
 #pragma unroll
-        for (int k = 0; k < kGSlots; ++k) {
-            const int i = t + kGThreads * k;
-            if (i < N) s[i] = v[k];
+                for (int m = 0; m < 4; ++m) a[m] = s[b | (m << q)];
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const double2 p = cmul(U[4 * l + m], a[m]);
+                        acc.x += p.x;
+                        acc.y += p.y;
+                    }
+                    s[b | (l << q)] = acc;
+                }
+            }
         }
         __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < kGSlots; ++k) {
         const int i = t + kGThreads * k;
-        if (i < N) psi[gate_index(gp, n, i)] = v[k];
+        if (i < N) psi[gate_index(gp, n, i)] = s[i];
     }
 }
 
-// Tile geometries of the passes for L: the 12 low bits, then windows of 9 bits above 3
-// contiguous low bits, each overlapping the bits covered so far by one (the bond crossing into it).
+// Tile geometries of the passes of one layer: the 12 low bits, then windows of 8 bits above 4
+// contiguous low bits (256-byte runs), each starting at the lower bit of the first bond of the
+// layer not yet covered (the layer's bonds are disjoint, so windows need not overlap). `lows`
+// lists the lower bits of the layer's bonds in increasing order.
 struct Geometry {
     int first, c, h0, tbits;
 };
 
-std::vector<Geometry> pass_geometry(int L) {
+std::vector<Geometry> pass_geometry(int L, const std::vector<int>& lows) {
     std::vector<Geometry> g;
     const int T = std::min(L, kGTileBits);
     g.push_back({1, T, T, T});
-    int done = T;
     const int wb = kGTileBits - kGLow;
-    while (done < L) {
-        int h0 = done - 1;
+    for (int p : lows) {
+        if (p + 1 < T) continue;
+        const Geometry& last = g.back();
+        const bool in_last = !last.first && p >= last.h0 && p + 1 < last.h0 + wb;
+        if (in_last) continue;
+        int h0 = p;
         if (h0 + wb > L) h0 = L - wb;
         g.push_back({0, kGLow, h0, kGTileBits});
-        done = h0 + wb;
     }
     return g;
 }
@@ -195,8 +248,12 @@ void bond_hamiltonian(const ed_model* m, int p, cplx* h) {
 
 // Passes of one layer: the propagators exp(-i t h) of the bonds whose left site k has the given
 // parity (1: odd k, H_o; 0: even k, H_e), each given to the first pass that holds both its bits.
-std::vector<GatePass> build_layer(const ed_model* m, int parity, double t, const std::vector<Geometry>& geo) {
+std::vector<GatePass> build_layer(const ed_model* m, int parity, double t) {
     const int L = m->L;
+    std::vector<int> lows;
+    for (int p = 0; p + 1 < L; ++p)
+        if (((L - p - 1) & 1) == parity) lows.push_back(p);
+    const std::vector<Geometry> geo = pass_geometry(L, lows);
     std::vector<GatePass> passes(geo.size());
     for (size_t i = 0; i < geo.size(); ++i) {
         std::memset(&passes[i], 0, sizeof(GatePass));
@@ -285,7 +342,6 @@ extern "C" ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, doubl
         seq = {{0, tau3}, {1, tau4}, {0, tau4}, {1, tau4}, {0, tau2}, {1, tau1},
                {0, tau2}, {1, tau4}, {0, tau4}, {1, tau4}, {0, tau3}};
     }
-    const std::vector<Geometry> geo = pass_geometry(L);
     // one set of passes per distinct (part, fraction)
     std::vector<std::pair<int, double>> keys;
     std::vector<std::vector<GatePass>> layers;
@@ -296,7 +352,7 @@ extern "C" ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, doubl
             if (keys[j] == seq[i]) found = int(j);
         if (found < 0) {
             keys.push_back(seq[i]);
-            layers.push_back(build_layer(model, seq[i].first, seq[i].second * dt, geo));
+            layers.push_back(build_layer(model, seq[i].first, seq[i].second * dt));
             if (layers.back().empty() && L > 2 - seq[i].first)
                 return fail(ED_ERR_UNSUPPORTED, "internal error: a Trotter gate has no pass for L = " + std::to_string(L));
             found = int(keys.size()) - 1;
