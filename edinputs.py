@@ -41,11 +41,14 @@ SZSZ = np.array([[1, 0, 0, 0],
 @dataclass
 class ModelDesc:
     """Rule-set description of H = sum_sites c_k O_k + sum_bonds c'_k O_k (x) O'_{k+1}
-    (Eq. ed:eq:genericH, site and bond rules of App. A), with w*c_k folded into the
-    coefficient arrays.
+    + sum_inf sum_{k<j} c''_k f(j-k) O_k (x) O'_j (Eq. ed:eq:genericH; site, bond and
+    InfiniteFunc rules of App. A, the latter without phase operators), with w*c_k folded into
+    the coefficient arrays.
 
     site_ops  (n_site, 2, 2) complex128;  site_coef (n_site, L) float64
     bond_ops  (n_bond, 4, 4) complex128;  bond_coef (n_bond, L-1) float64
+    inf_ops, inf_ops2 (n_inf, 2, 2) complex128 (O, O');  inf_coef (n_inf, L) float64 (c''_k);
+    inf_f (n_inf, L-1) float64 (f(r) for r = 1..L-1)
     """
     L: int
     site_ops: np.ndarray
@@ -53,6 +56,10 @@ class ModelDesc:
     bond_ops: np.ndarray
     bond_coef: np.ndarray
     d: int = 2
+    inf_ops: np.ndarray = None
+    inf_ops2: np.ndarray = None
+    inf_coef: np.ndarray = None
+    inf_f: np.ndarray = None
 
     def __post_init__(self):
         self.site_ops = np.ascontiguousarray(np.asarray(self.site_ops, np.complex128).reshape(-1, 2, 2))
@@ -60,6 +67,18 @@ class ModelDesc:
         self.bond_ops = np.ascontiguousarray(np.asarray(self.bond_ops, np.complex128).reshape(-1, 4, 4))
         self.bond_coef = np.ascontiguousarray(
             np.asarray(self.bond_coef, np.float64).reshape(len(self.bond_ops), max(self.L - 1, 0)))
+        n_inf = 0 if self.inf_ops is None else len(np.asarray(self.inf_ops).reshape(-1, 2, 2))
+        self.inf_ops = np.ascontiguousarray(
+            np.zeros((0, 2, 2)) if n_inf == 0 else np.asarray(self.inf_ops, np.complex128).reshape(-1, 2, 2),
+            dtype=np.complex128)
+        self.inf_ops2 = np.ascontiguousarray(
+            np.zeros((0, 2, 2)) if n_inf == 0 else np.asarray(self.inf_ops2, np.complex128).reshape(-1, 2, 2),
+            dtype=np.complex128)
+        self.inf_coef = np.ascontiguousarray(
+            np.zeros((0, self.L)) if n_inf == 0 else np.asarray(self.inf_coef, np.float64).reshape(n_inf, self.L))
+        self.inf_f = np.ascontiguousarray(
+            np.zeros((0, max(self.L - 1, 0))) if n_inf == 0
+            else np.asarray(self.inf_f, np.float64).reshape(n_inf, max(self.L - 1, 0)))
 
     @property
     def dim(self):
@@ -89,6 +108,17 @@ def xxz_bond_scaled(L, delta, Jb):
                      site_ops=np.zeros((0, 2, 2)), site_coef=np.zeros((0, L)),
                      bond_ops=[SXSX, SYSY, SZSZ],
                      bond_coef=np.stack([Jb, Jb, delta * Jb]))
+
+
+def lrqi(L, phi, alpha):
+    """Long-range quantum Ising chain: H = -sum_{k<k'} cos(phi)/(k'-k)^alpha sz_k sz_k'
+    - sin(phi) sum_k sx_k (the H_LRQI of the thermalisation section); the zz part is one
+    InfiniteFunc rule with f(r) = r^-alpha."""
+    r = np.arange(1, L, dtype=np.float64)
+    return ModelDesc(L, site_ops=[SX], site_coef=np.full((1, L), -np.sin(phi)),
+                     bond_ops=np.zeros((0, 4, 4)), bond_coef=np.zeros((0, L - 1)),
+                     inf_ops=[SZ], inf_ops2=[SZ], inf_coef=np.full((1, L), -np.cos(phi)),
+                     inf_f=(r ** -float(alpha)).reshape(1, L - 1))
 
 
 def random_fields(L, seed, lo=-0.5, hi=0.5):
