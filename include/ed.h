@@ -63,10 +63,22 @@ const char* ed_version(void);
  *   bond_op  host, [n_bond][4][4] row-major, index i_k*2 + i_{k+1} (site k is the left
  *            Kronecker factor)
  *   site_coef host, [n_site][L];  bond_coef host, [n_bond][L-1]   (real)
+ *
+ * InfiniteFunc rules (App. A, Eq. ed:eq:appinfrs) without phase operators (Q = identity):
+ *
+ *     + sum_{z<n_inf} sum_{1<=k<j<=L} inf_coef[z][k-1] * inf_f[z][j-k-1] * O^z_k O'^z_j
+ *
+ *   inf_op, inf_op2 host, [n_inf][2][2] (O and O'); both must be diagonal (the long-range zz
+ *            couplings of the long-range Ising chain, densities, ...), else ED_ERR_UNSUPPORTED;
+ *   inf_coef host, [n_inf][L] (c_k, real); inf_f host, [n_inf][L-1] (f(r) for r = 1..L-1, real).
+ *   They enter only the diagonal of H; ed_apply_H and the Krylov calls support them, the
+ *   trajectory, adjoint and Trotter calls (which take the model apart into sites and bonds)
+ *   return ED_ERR_UNSUPPORTED for a model that has them.
+ *
  * Operators may be non-Hermitian (the effective Hamiltonian of a trajectory); Hermiticity of a
  * Hamiltonian is the caller's responsibility, as in the paper's rule sets. All host arrays are
  * copied; the handle keeps small coefficient tables in device memory of the current device.
- * Requires 2 <= L <= 30 and d == 2 (else ED_ERR_UNSUPPORTED); n_site, n_bond >= 0; a null
+ * Requires 2 <= L <= 30 and d == 2 (else ED_ERR_UNSUPPORTED); n_site, n_bond, n_inf >= 0; a null
  * array is allowed only when its count is 0.
  * ---------------------------------------------------------------------------------------- */
 typedef struct ed_model ed_model;
@@ -80,6 +92,11 @@ typedef struct {
     int n_bond;
     const ed_c64* bond_op;
     const double* bond_coef;
+    int n_inf;
+    const ed_c64* inf_op;
+    const ed_c64* inf_op2;
+    const double* inf_coef;
+    const double* inf_f;
 } ed_model_desc;
 
 ed_status ed_model_create(const ed_model_desc* desc, ed_model** out);

@@ -31,21 +31,33 @@ def _check_state(t, D, name="psi"):
 
 
 class Model:
-    """Handle on an immutable rule-set Hamiltonian (site + bond rules).
+    """Handle on an immutable rule-set Hamiltonian (site, bond and diagonal InfiniteFunc rules).
 
     desc: any object with L, site_ops (n,2,2), site_coef (n,L), bond_ops (m,4,4),
-    bond_coef (m,L-1) (e.g. edinputs.ModelDesc). The handle lives on the current device.
+    bond_coef (m,L-1) and optionally inf_ops / inf_ops2 (r,2,2), inf_coef (r,L), inf_f (r,L-1)
+    (e.g. edinputs.ModelDesc). The handle lives on the current device.
     """
 
     def __init__(self, desc):
         self.L = int(desc.L)
+        L = self.L
+        io = getattr(desc, "inf_ops", None)
+        ni = 0 if io is None else len(np.asarray(io).reshape(-1, 2, 2))
         self._keep = [np.ascontiguousarray(desc.site_ops, np.complex128),
                       np.ascontiguousarray(desc.site_coef, np.float64),
                       np.ascontiguousarray(desc.bond_ops, np.complex128),
-                      np.ascontiguousarray(desc.bond_coef, np.float64)]
-        so, sc, bo, bc = self._keep
+                      np.ascontiguousarray(desc.bond_coef, np.float64),
+                      np.ascontiguousarray(np.asarray(io if ni else np.zeros((0, 2, 2))).reshape(-1, 2, 2), np.complex128),
+                      np.ascontiguousarray(np.asarray(desc.inf_ops2 if ni else np.zeros((0, 2, 2))).reshape(-1, 2, 2),
+                                           np.complex128),
+                      np.ascontiguousarray(np.asarray(desc.inf_coef if ni else np.zeros((0, L))).reshape(ni, L),
+                                           np.float64),
+                      np.ascontiguousarray(np.asarray(desc.inf_f if ni else np.zeros((0, L - 1))).reshape(ni, L - 1),
+                                           np.float64)]
+        so, sc, bo, bc, i1, i2, ic, fr = self._keep
         d = _lib.ModelDescC(self.L, 2, len(so), so.ctypes.data, sc.ctypes.data,
-                            len(bo), bo.ctypes.data, bc.ctypes.data)
+                            len(bo), bo.ctypes.data, bc.ctypes.data,
+                            ni, i1.ctypes.data, i2.ctypes.data, ic.ctypes.data, fr.ctypes.data)
         h = C.c_void_p()
         call("ed_model_create", C.byref(d), C.byref(h))
         self._h = h

@@ -23,7 +23,9 @@ class c64(C.Structure):
 class ModelDescC(C.Structure):
     _fields_ = [("L", C.c_int), ("d", C.c_int),
                 ("n_site", C.c_int), ("site_op", C.c_void_p), ("site_coef", C.c_void_p),
-                ("n_bond", C.c_int), ("bond_op", C.c_void_p), ("bond_coef", C.c_void_p)]
+                ("n_bond", C.c_int), ("bond_op", C.c_void_p), ("bond_coef", C.c_void_p),
+                ("n_inf", C.c_int), ("inf_op", C.c_void_p), ("inf_op2", C.c_void_p), ("inf_coef", C.c_void_p),
+                ("inf_f", C.c_void_p)]
 
 
 class LanczosParams(C.Structure):

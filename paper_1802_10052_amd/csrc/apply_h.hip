@@ -22,11 +22,18 @@ template <unsigned CLS>
 __global__ __launch_bounds__(256) void hpsi_small(const double2* __restrict__ psi,
                                                   double2* __restrict__ out,
                                                   const double2* __restrict__ site,
-                                                  const double2* __restrict__ bond, int L) {
+                                                  const double2* __restrict__ bond, int L,
+                                                  const double2* __restrict__ lr_full) {
     const int64_t D = int64_t(1) << L;
     const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (x >= D) return;
-    out[x] = small_entry<CLS>(psi, site, bond, L, x);
+    double2 y = small_entry<CLS>(psi, site, bond, L, x);
+    if (lr_full) {  // long-range zz energy of basis state x
+        const double2 e = lr_full[x], v = psi[x];
+        y.x += e.x * v.x - e.y * v.y;
+        y.y += e.x * v.y + e.y * v.x;
+    }
+    out[x] = y;
 }
 
 // One tile per workgroup. With gathered bits, consecutive workgroups of one XCD (workgroups are
@@ -38,6 +45,7 @@ void hpsi_tile(const double2* __restrict__ psi, double2* __restrict__ out, const
                const double2* __restrict__ bond, const double2* __restrict__ dlo, const double2* __restrict__ dmid,
                const double2* __restrict__ dhi, PassArgs pa) {
     __shared__ double2 s[1 << kTileBits];
+    __shared__ double2 sF[kTileBits];
     int64_t n = blockIdx.x;
     if (GATHER) {
         const int64_t b = blockIdx.x;
@@ -47,7 +55,7 @@ void hpsi_tile(const double2* __restrict__ psi, double2* __restrict__ out, const
         const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
         n = low | (member << pa.gpos) | (high << (pa.gpos + pa.G));
     }
-    tile_body<CLS, FIRST, GATHER>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s);
+    tile_body<CLS, FIRST, GATHER>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s, 0, nullptr, sF);
 }
 
 // Two tiles per workgroup (512 threads, 128 KiB of LDS, one workgroup per CU): the tiles n and
@@ -60,6 +68,7 @@ void hpsi_tile_pair(const double2* __restrict__ psi, double2* __restrict__ out, 
                     const double2* __restrict__ bond, const double2* __restrict__ dlo,
                     const double2* __restrict__ dmid, const double2* __restrict__ dhi, PassArgs pa) {
     __shared__ double2 s[2][1 << kTileBits];
+    __shared__ double2 sF[2][kTileBits];
     const int h = int(threadIdx.x) / kTileThreads, t = int(threadIdx.x) % kTileThreads;
     const int64_t b = blockIdx.x;
     const int64_t xcd = b & 7, j = b >> 3;
@@ -68,7 +77,7 @@ void hpsi_tile_pair(const double2* __restrict__ psi, double2* __restrict__ out, 
     const int64_t group = (gl << 3) | xcd;
     const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
     const int64_t n = low | (int64_t(h) << pa.gpos) | (member << (pa.gpos + 1)) | (high << (pa.gpos + pa.G));
-    tile_body<CLS, FIRST, true, true>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s[h], t, s[h ^ 1]);
+    tile_body<CLS, FIRST, true, true>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s[h], t, s[h ^ 1], sF[h]);
 }
 
 template <unsigned CLS>
@@ -79,14 +88,20 @@ hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, h
         const int threads = 256;
         const int blocks = int((D + threads - 1) / threads);
         hipLaunchKernelGGL((hpsi_small<CLS>), dim3(blocks), dim3(threads), 0, s, psi, out,
-                           m->d_site, m->d_bond, L);
+                           m->d_site, m->d_bond, L, m->lr ? m->d_lr_low : nullptr);
         return hipGetLastError();
     }
     const int64_t tiles = int64_t(1) << (L - kTileBits);
     for (int ip = 0; ip < m->n_pass; ++ip) {
         const PassDesc& pd = m->pass[ip];
-        const PassArgs pa = to_args(pd, m->d_jobs + (size_t(m->plan) * kMaxPasses + ip) * kMaxJobs,
-                                    m->njobs[m->plan][ip]);
+        PassArgs pa = to_args(pd, m->d_jobs + (size_t(m->plan) * kMaxPasses + ip) * kMaxJobs,
+                              m->njobs[m->plan][ip]);
+        if (pd.first && m->lr) {
+            pa.lr = 1;
+            pa.L = L;
+            pa.lr_low = m->d_lr_low;
+            pa.lr_cross = m->d_lr_cross;
+        }
         const dim3 grid{unsigned(tiles)}, block{unsigned(kTileThreads)};
 #define ED_TILE_ARGS psi, out, m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid, m->d_diag_hi, pa
         // optional LDS padding: one workgroup per CU, so that the tiles of a group fit in L2

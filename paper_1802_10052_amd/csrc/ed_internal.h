@@ -98,7 +98,13 @@ struct ed_model {
     double2* d_bond = nullptr;   // [L-1][16]
     double2* d_diag_lo = nullptr;  // [256]   bonds 0..6, sites 0..7   (low table)
     double2* d_diag_mid = nullptr; // [2^(T-7)] bonds 7..T-2, sites 8..T-1
-    double2* d_diag_hi = nullptr;  // [2^(L-T+1)] bonds T-1..L-2, sites T..L-1
+    double2* d_diag_hi = nullptr;  // [2^(L-T+1)] bonds T-1..L-2, sites T..L-1 (+ long-range pairs
+                                   //  with both bits in T-1..L-1)
+    // long-range zz couplings (diagonal InfiniteFunc rules): H += sum_{p<q} lrz[p][q] z_p z_q (bits)
+    bool lr = false;
+    std::vector<double2> lrz;      // [L][L], upper triangle p < q
+    double2* d_lr_low = nullptr;   // [2^T] pairs with both bits in 0..T-1 (L >= T) or all pairs (L < T)
+    double2* d_lr_cross = nullptr; // [T-1][L] lrz[p][q] for p < T-1, q >= T (L >= T)
     int tile_bits = 0;           // T = min(L, kTileBits)
     int n_pass = 0;              // the selected plan (copied from cand[plan])
     ed::PassDesc pass[ed::kMaxPasses];

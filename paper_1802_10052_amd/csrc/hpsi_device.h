@@ -41,6 +41,11 @@ struct PassArgs {
     int G, gb, gpos, gcross;
     const GatherJob* jobs;  // the pass's gathered terms (device), njobs of them
     int njobs;
+    // long-range zz couplings (first pass only): lr_low[i] = pairs inside the tile's 12 bits,
+    // lr_cross[p * L + q] = coupling of low bit p < 11 with high bit q >= 12
+    int lr, L;
+    const double2* lr_low;
+    const double2* lr_cross;
 };
 
 // Operator tables of one model as the per-amplitude kernels see them.
@@ -84,7 +89,8 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
                                           const double2* __restrict__ site, const double2* __restrict__ bond,
                                           const double2* __restrict__ dlo, const double2* __restrict__ dmid,
                                           const double2* __restrict__ dhi, const PassArgs& pa, int64_t n,
-                                          double2* s, int t = 0, const double2* so = nullptr) {
+                                          double2* s, int t = 0, const double2* so = nullptr,
+                                          double2* sF = nullptr) {
     constexpr bool OFFR = CLS & kOffReal;
     constexpr bool DIAGR = CLS & kDiagReal;
     if (!PAIR) t = threadIdx.x;
@@ -104,6 +110,17 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
 #pragma unroll
     for (int k = 0; k < kSlots; ++k) s[t + kTileThreads * k] = v[k];
 
+    if (FIRST && pa.lr && t < kTileBits - 1) {
+        // long-range field on low bit t from the tile's fixed high bits (z = +1 for bit 0)
+        double2 f = make_double2(0.0, 0.0);
+        for (int q = kTileBits; q < pa.L; ++q) {
+            const double z = ((n >> (q - kTileBits)) & 1) ? -1.0 : 1.0;
+            const double2 c = pa.lr_cross[t * pa.L + q];
+            f.x += z * c.x;
+            f.y += z * c.y;
+        }
+        sF[t] = f;
+    }
     if (FIRST) {
         const double2 dl = dlo[t & 255];
 #pragma unroll
@@ -120,6 +137,38 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
         }
     }
     __syncthreads();
+    if (FIRST && pa.lr) {
+        // long-range zz: pairs inside the tile (table) + sum over low bits p < 11 of z_p F_p
+        // (bits 0..7 are the thread's, 8..10 the slot's)
+        double2 st = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const double z = ((t >> p) & 1) ? -1.0 : 1.0;
+            st.x += z * sF[p].x;
+            st.y += z * sF[p].y;
+        }
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int i = t + kTileThreads * k;
+            double2 e = pa.lr_low[i];
+            e.x += st.x;
+            e.y += st.y;
+#pragma unroll
+            for (int p = 8; p < kTileBits - 1; ++p) {
+                const double z = ((k >> (p - 8)) & 1) ? -1.0 : 1.0;
+                e.x += z * sF[p].x;
+                e.y += z * sF[p].y;
+            }
+            if (DIAGR) {
+                acc[k].x += e.x * v[k].x;
+                acc[k].y += e.x * v[k].y;
+            } else {
+                const double2 ev = cmul(e, v[k]);
+                acc[k].x += ev.x;
+                acc[k].y += ev.y;
+            }
+        }
+    }
 
 #pragma unroll
     for (int q = 0; q < kTileBits; ++q) {
@@ -319,6 +368,10 @@ inline PassArgs to_args(const PassDesc& pd, const GatherJob* jobs, int njobs) {
     pa.gcross = pd.gcross;
     pa.jobs = jobs;
     pa.njobs = njobs;
+    pa.lr = 0;
+    pa.L = 0;
+    pa.lr_low = nullptr;
+    pa.lr_cross = nullptr;
     return pa;
 }
 

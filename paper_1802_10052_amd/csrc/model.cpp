@@ -4,12 +4,15 @@
 // diagonal tables, and plans the streaming passes of H psi.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 
 #include "ed_internal.h"
 
 namespace ed {
+
+using cplx = std::complex<double>;
 
 static thread_local std::string g_last_error;
 
@@ -316,13 +319,29 @@ static ed_status upload(double2** dst, const std::vector<double2>& src) {
 }
 
 static void free_tables(ed_model* m) {
-    double2** ptrs[] = {&m->d_site, &m->d_bond, &m->d_diag_lo, &m->d_diag_mid, &m->d_diag_hi};
+    double2** ptrs[] = {&m->d_site, &m->d_bond, &m->d_diag_lo, &m->d_diag_mid, &m->d_diag_hi, &m->d_lr_low,
+                        &m->d_lr_cross};
     for (double2** p : ptrs) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     if (m->d_jobs) (void)hipFree(m->d_jobs);
     m->d_jobs = nullptr;
+}
+
+// long-range zz energy of the pairs p < q with both bits in [lo, hi), evaluated at index x
+static double2 lr_part(const ed_model* m, uint64_t x, int lo, int hi) {
+    double re = 0.0, im = 0.0;
+    const int L = m->L;
+    for (int p = lo; p < hi; ++p)
+        for (int q = p + 1; q < hi; ++q) {
+            const double2 v = m->lrz[size_t(p) * L + q];
+            if (v.x == 0.0 && v.y == 0.0) continue;
+            const double zz = (((x >> p) ^ (x >> q)) & 1) ? -1.0 : 1.0;
+            re += zz * v.x;
+            im += zz * v.y;
+        }
+    return c2(re, im);
 }
 
 ed_status build_device_tables(ed_model* m) {
@@ -334,10 +353,31 @@ ed_status build_device_tables(ed_model* m) {
         std::vector<double2> lo(256), mid(size_t(1) << (T - 7)), hi(size_t(1) << (L - T + 1));
         for (uint64_t j = 0; j < lo.size(); ++j) lo[j] = diag_part(m, j, 0, 8, 0, 7);
         for (uint64_t j = 0; j < mid.size(); ++j) mid[j] = diag_part(m, j << 7, 8, T, 7, T - 1);
-        for (uint64_t j = 0; j < hi.size(); ++j) hi[j] = diag_part(m, j << (T - 1), T, L, T - 1, L - 1);
+        for (uint64_t j = 0; j < hi.size(); ++j) {
+            hi[j] = diag_part(m, j << (T - 1), T, L, T - 1, L - 1);
+            if (m->lr) {
+                const double2 e = lr_part(m, j << (T - 1), T - 1, L);
+                hi[j].x += e.x;
+                hi[j].y += e.y;
+            }
+        }
         ED_TRY(upload(&m->d_diag_lo, lo));
         ED_TRY(upload(&m->d_diag_mid, mid));
         ED_TRY(upload(&m->d_diag_hi, hi));
+        if (m->lr) {
+            // pairs inside the 12 low bits; pairs (p < T-1, q >= T) as per-tile fields; pairs with
+            // both bits in [T-1, L) are in the high table above
+            std::vector<double2> low(size_t(1) << T), cross(size_t(T - 1) * L, c2(0, 0));
+            for (uint64_t i = 0; i < low.size(); ++i) low[i] = lr_part(m, i, 0, T);
+            for (int p = 0; p < T - 1; ++p)
+                for (int q = T; q < L; ++q) cross[size_t(p) * L + q] = m->lrz[size_t(p) * L + q];
+            ED_TRY(upload(&m->d_lr_low, low));
+            ED_TRY(upload(&m->d_lr_cross, cross));
+        }
+    } else if (m->lr) {
+        std::vector<double2> full(size_t(1) << L);
+        for (uint64_t x = 0; x < full.size(); ++x) full[x] = lr_part(m, x, 0, L);
+        ED_TRY(upload(&m->d_lr_low, full));
     }
     const size_t jb = m->jobs.size() * sizeof(GatherJob);
     ED_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&m->d_jobs), jb ? jb : sizeof(GatherJob)));
@@ -375,7 +415,39 @@ ed_status fold_model(const ed_model_desc* desc, ed_model* m) {
             }
         }
     }
+    // diagonal InfiniteFunc rules: c f(j-k) O_k O'_j with O = diag(o0, o1), O' = diag(p0, p1) is
+    // (a + b z_k)(c + d z_j) c f, a = (o0+o1)/2, b = (o0-o1)/2, c = (p0+p1)/2, d = (p0-p1)/2
+    // (z = +1 for index 0): its constant and field parts go to the site diagonals, its zz part to
+    // the long-range coupling table
+    m->lrz.assign(size_t(L) * L, c2(0, 0));
+    for (int z = 0; z < desc->n_inf; ++z) {
+        const ed_c64* O = desc->inf_op + 4 * z;
+        const ed_c64* Q = desc->inf_op2 + 4 * z;
+        const cplx o0(O[0].re, O[0].im), o1(O[3].re, O[3].im), p0(Q[0].re, Q[0].im), p1(Q[3].re, Q[3].im);
+        const cplx a = 0.5 * (o0 + o1), b = 0.5 * (o0 - o1), c = 0.5 * (p0 + p1), d = 0.5 * (p0 - p1);
+        for (int k = 1; k < L; ++k)
+            for (int j = k + 1; j <= L; ++j) {
+                const double w = desc->inf_coef[size_t(z) * L + (k - 1)] * desc->inf_f[size_t(z) * (L - 1) + (j - k - 1)];
+                if (w == 0.0) continue;
+                const int pk = L - k, pj = L - j;  // bits of sites k and j
+                auto add_site = [&](int p, cplx v0, cplx v1) {
+                    m->site[4 * p + 0].x += v0.real();
+                    m->site[4 * p + 0].y += v0.imag();
+                    m->site[4 * p + 3].x += v1.real();
+                    m->site[4 * p + 3].y += v1.imag();
+                };
+                const cplx cst = w * a * c, fk = w * b * c, fj = w * a * d, zz = w * b * d;
+                add_site(pk, cst + fk, cst - fk);
+                add_site(pj, fj, -fj);
+                double2& e = m->lrz[size_t(pj) * L + pk];  // pj < pk
+                e.x += zz.real();
+                e.y += zz.imag();
+            }
+    }
+    for (const double2& e : m->lrz) m->lr = m->lr || e.x != 0.0 || e.y != 0.0;
     unsigned cls = kOffReal | kDiagReal;
+    for (const double2& e : m->lrz)
+        if (e.y != 0.0) cls &= ~unsigned(kDiagReal);
     for (int p = 0; p < L; ++p) {
         for (int e = 0; e < 4; ++e) {
             const double2 v = m->site[4 * p + e];
@@ -426,6 +498,22 @@ ed_status validate_desc(const ed_model_desc* desc) {
         }
         for (int k = 0; k < desc->L; ++k)
             if (!std::isfinite(desc->site_coef[size_t(z) * desc->L + k])) return fail(ED_ERR_NUMERIC, "non-finite site_coef");
+    }
+    if (desc->n_inf < 0) return fail(ED_ERR_ARG, "negative term count");
+    if (desc->n_inf > 0 && (!desc->inf_op || !desc->inf_op2 || !desc->inf_coef || !desc->inf_f))
+        return fail(ED_ERR_ARG, "inf_op/inf_op2/inf_coef/inf_f is null with n_inf > 0");
+    for (int z = 0; z < desc->n_inf; ++z) {
+        for (int e = 0; e < 4; ++e) {
+            const ed_c64 o = desc->inf_op[4 * z + e], q = desc->inf_op2[4 * z + e];
+            if (!std::isfinite(o.re) || !std::isfinite(o.im) || !std::isfinite(q.re) || !std::isfinite(q.im))
+                return fail(ED_ERR_NUMERIC, "non-finite inf_op");
+            if ((e == 1 || e == 2) && (o.re != 0.0 || o.im != 0.0 || q.re != 0.0 || q.im != 0.0))
+                return fail(ED_ERR_UNSUPPORTED, "InfiniteFunc rules need diagonal operators");
+        }
+        for (int k = 0; k < desc->L; ++k)
+            if (!std::isfinite(desc->inf_coef[size_t(z) * desc->L + k])) return fail(ED_ERR_NUMERIC, "non-finite inf_coef");
+        for (int r = 0; r + 1 < desc->L; ++r)
+            if (!std::isfinite(desc->inf_f[size_t(z) * (desc->L - 1) + r])) return fail(ED_ERR_NUMERIC, "non-finite inf_f");
     }
     for (int z = 0; z < desc->n_bond; ++z) {
         for (int e = 0; e < 16; ++e) {

@@ -85,3 +85,28 @@ def test_pass_plans_valid_for_every_length():
                 keep[2][:, 0, 3] = 1.0                 # double-flip bonds: passes must overlap
             h = C.c_void_p()
             assert lib.ed_model_create(C.byref(d), C.byref(h)) == -3, (L, flip_bonds, lib.ed_last_error())
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU may be visible")
+def test_long_range_rule_validation():
+    """InfiniteFunc rules are folded and checked before the device is looked for: diagonal
+    operators reach ED_ERR_NODEVICE on a CPU-only host, off-diagonal ones ED_ERR_UNSUPPORTED, null
+    arrays with n_inf > 0 ED_ERR_ARG."""
+    lib = _lib.lib()
+    L = 14
+    d, keep = _desc(L=L, n_site=1, n_bond=1)
+    keep[0][:] = np.array([[0, 1], [1, 0]])
+    o1 = np.array([[[1, 0], [0, -1]]], np.complex128)
+    o2 = np.array([[[0.5, 0], [0, 2j]]], np.complex128)
+    ic = np.ones((1, L))
+    fr = 1.0 / np.arange(1, L, dtype=np.float64).reshape(1, L - 1) ** 1.5
+    d.n_inf, d.inf_op, d.inf_op2, d.inf_coef, d.inf_f = 1, o1.ctypes.data, o2.ctypes.data, ic.ctypes.data, fr.ctypes.data
+    h = C.c_void_p()
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -3, lib.ed_last_error()
+    hop = np.array([[[0, 1], [0, 0]]], np.complex128)
+    d.inf_op2 = hop.ctypes.data
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -2
+    assert b"diagonal" in lib.ed_last_error()
+    d.inf_op2 = None
+    assert lib.ed_model_create(C.byref(d), C.byref(h)) == -1
