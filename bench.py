@@ -9,8 +9,8 @@ is resident in HBM and the time comes from HIP events on the stream the library 
 Beside it, each remaining row of the hot path is run once on its synthetic workload and reported
 under "rows": Lanczos ground state (TFIM L = 14), Lanczos + half-chain entropy (XXZ L = 26),
 the L = 28 Krylov quench (100 steps), the same quench with the Suzuki-Trotter propagators of order
-4 and 2, 4096 batched quantum trajectories against the plain per-trajectory path, and the
-adjoint gradient (L = 20) against finite differences of the forward-only path. The CPU oracle
+4 and 2, the long-range Ising chain H_LRQI at L = 28 (H psi and a Krylov quench), 4096 batched
+quantum trajectories against the plain per-trajectory path, and the adjoint gradient (L = 20) against finite differences of the forward-only path. The CPU oracle
 is timed on a bounded sample of the headline workload.
 """
 import argparse
@@ -182,6 +182,40 @@ def row_trotter_L28(P, E, torch, dev, steps=100):
     return out
 
 
+def row_lrqi_L28(P, E, torch, dev, reps=10, steps=20):
+    """The long-range quantum Ising chain H_LRQI (App. A InfiniteFunc rule, f(r) = 1/r^alpha,
+    phi = pi/4, alpha = 1.5) at L = 28: the tuned H psi with its O(L^2) diagonal fused into the
+    first pass (same 32 B per amplitude accounting as the headline), and a Krylov quench from all
+    up, the paper's case for Krylov over Trotter (Trotter layers do not cover long-range terms)."""
+    import numpy as np
+    L = 28
+    m = P.Model(E.lrqi(L, np.pi / 4, 1.5))
+    psi = E.random_state_device(L, 11, dev)
+    out = torch.empty_like(psi)
+    best, plan_ms = m.tune(psi, out, reps=3)
+    P.apply_H(m, psi, out)
+    with Timer(torch, None) as t:
+        for _ in range(reps):
+            P.apply_H(m, psi, out)
+    ms = 1e3 * t.s / reps
+    rec = {"workload": f"H_LRQI phi=pi/4 alpha=1.5 L=28: apply_H ({reps} products) and a quench from all up, "
+                       f"dt=0.05, {steps} Krylov steps, m<=20, tol 1e-10",
+           "apply_ms": round(ms, 3), "apply_GBps": round(32.0 * (1 << L) / (ms * 1e-3) / 1e9, 1),
+           "plan": m.describe_plan(best)}
+    del psi, out
+    torch.cuda.empty_cache()
+    psi = torch.zeros(1 << L, dtype=torch.complex128, device=dev)
+    psi[0] = 1.0
+    with Timer(torch, None) as t:
+        _, obs, info = P.krylov_evolve(m, psi, 0.05, steps, m_max=20, tol=1e-10, reorth=0)
+    e = obs["energy"]
+    rec.update({"quench_seconds": round(t.s, 3), "quench_ms_per_step": round(1e3 * t.s / steps, 2),
+                "total_krylov": info["total_m"], "max_m": info["max_m"],
+                "energy_drift": float(abs(e - e[0]).max() / max(1.0, abs(e[0]))),
+                "norm_drift": float(abs(obs["norm"] - 1).max()), "sz_final_site1": float(obs["sz"][-1, 0])})
+    return rec
+
+
 def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):
     import numpy as np
     lengths = [8, 10, 12, 14, 16]
@@ -285,7 +319,7 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="use the H psi plan with this description (ed_model_plan_describe) instead of tuning")
     ap.add_argument("--rows", default="all",
-                    help="comma list of lanczos14,lanczos26,quench28,trotter28,traj,adjoint (the 'all' set) and traj16 "
+                    help="comma list of lanczos14,lanczos26,quench28,trotter28,lrqi28,traj,adjoint (the 'all' set) and traj16 "
                          "(the L=16 trajectory slice, for profiling); 'none' or 'all'")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -364,8 +398,8 @@ def main():
     torch.cuda.empty_cache()
     rows = {"lanczos14": row_lanczos_L14, "lanczos26": row_lanczos_entropy_L26, "quench28": row_quench_L28,
             "traj": row_trajectories, "adjoint": row_adjoint, "traj16": row_trajectories_L16,
-            "trotter28": row_trotter_L28}
-    default_rows = ["lanczos14", "lanczos26", "quench28", "trotter28", "traj", "adjoint"]
+            "trotter28": row_trotter_L28, "lrqi28": row_lrqi_L28}
+    default_rows = ["lanczos14", "lanczos26", "quench28", "trotter28", "lrqi28", "traj", "adjoint"]
     pick = default_rows if args.rows == "all" else ([] if args.rows == "none" else args.rows.split(","))
     rec["rows"] = {}
     for name in pick:
