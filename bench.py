@@ -144,6 +144,8 @@ def row_quench_L28(P, E, torch, dev, steps=100):
         _, obs, info = P.krylov_evolve(m, psi, 0.05, steps, m_max=20, tol=1e-10, reorth=0)
     e = obs["energy"]
     _SHARED["quench28_sz"] = obs["sz"]
+    r1, r2 = P.rdm(psi, L)
+    _SHARED["quench28_rdm"] = (r1.cpu().numpy(), r2.cpu().numpy())
     return {"workload": f"TFIM g=0.5 L=28 quench from all up, dt=0.05, {steps} Krylov steps, m<=20, tol 1e-10",
             "seconds": round(t.s, 3), "ms_per_step": round(1e3 * t.s / steps, 2), "total_krylov": info["total_m"],
             "max_m": info["max_m"], "energy_drift": float(abs(e - e[0]).max() / abs(e[0])),
@@ -177,6 +179,11 @@ def row_trotter_L28(P, E, torch, dev, steps=100):
         ref = _SHARED.get("quench28_sz")
         if ref is not None:
             r["max_abs_sz_diff_vs_krylov"] = float(np.abs(obs["sz"] - ref).max())
+        ref = _SHARED.get("quench28_rdm")
+        if ref is not None:  # the error measures of the convergence study, Krylov as the reference
+            g1, g2 = P.rdm(psi, L)
+            r["eps_local_vs_krylov"] = P.eps_local(g1, ref[0])
+            r["eps_corr_vs_krylov"] = P.eps_corr(g2, ref[1])
         out[f"order{order}"] = r
         del psi
     return out
@@ -214,6 +221,32 @@ def row_lrqi_L28(P, E, torch, dev, reps=10, steps=20):
                 "energy_drift": float(abs(e - e[0]).max() / max(1.0, abs(e[0]))),
                 "norm_drift": float(abs(obs["norm"] - 1).max()), "sz_final_site1": float(obs["sz"][-1, 0])})
     return rec
+
+
+def row_rdm_L28(P, E, torch, dev, reps=3):
+    """All single-site and all two-site reduced density matrices (Sec. IV) of a random L = 28
+    state: 378 pairs in 15 LDS-tiled passes. Algorithmic work: 64 flops per quad of amplitudes
+    and pair (4 squared moduli, 6 conjugate products), C(L,2) 2^(L-2) quads, against the FP64
+    vector peak (the products are not a dense contraction); and the single-site matrices alone
+    (the 27 bonds in 5 passes)."""
+    L = 28
+    psi = E.random_state_device(L, 12, dev)
+    P.rdm(psi, L)
+    with Timer(torch, None) as t:
+        for _ in range(reps):
+            P.rdm(psi, L)
+    ms = 1e3 * t.s / reps
+    flops = 64.0 * (L * (L - 1) // 2) * float(1 << (L - 2))
+    P.rdm(psi, L, two_site=False)
+    with Timer(torch, None) as t1:
+        for _ in range(reps):
+            P.rdm(psi, L, two_site=False)
+    ms1 = 1e3 * t1.s / reps
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"workload": "rho_k for all 28 sites and rho_{k,j} for all 378 pairs of a random L=28 state",
+            "all_pairs_ms": round(ms, 2), "all_pairs_TFLOPs": round(tf, 2),
+            "frac_fp64_vector_peak": round(tf / 78.6, 4), "passes": 15,
+            "single_site_only_ms": round(ms1, 2), "single_site_passes": 5}
 
 
 def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):
@@ -319,7 +352,7 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="use the H psi plan with this description (ed_model_plan_describe) instead of tuning")
     ap.add_argument("--rows", default="all",
-                    help="comma list of lanczos14,lanczos26,quench28,trotter28,lrqi28,traj,adjoint (the 'all' set) and traj16 "
+                    help="comma list of lanczos14,lanczos26,quench28,trotter28,lrqi28,rdm28,traj,adjoint (the 'all' set) and traj16 "
                          "(the L=16 trajectory slice, for profiling); 'none' or 'all'")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -398,8 +431,8 @@ def main():
     torch.cuda.empty_cache()
     rows = {"lanczos14": row_lanczos_L14, "lanczos26": row_lanczos_entropy_L26, "quench28": row_quench_L28,
             "traj": row_trajectories, "adjoint": row_adjoint, "traj16": row_trajectories_L16,
-            "trotter28": row_trotter_L28, "lrqi28": row_lrqi_L28}
-    default_rows = ["lanczos14", "lanczos26", "quench28", "trotter28", "lrqi28", "traj", "adjoint"]
+            "trotter28": row_trotter_L28, "lrqi28": row_lrqi_L28, "rdm28": row_rdm_L28}
+    default_rows = ["lanczos14", "lanczos26", "quench28", "trotter28", "lrqi28", "rdm28", "traj", "adjoint"]
     pick = default_rows if args.rows == "all" else ([] if args.rows == "none" else args.rows.split(","))
     rec["rows"] = {}
     for name in pick:

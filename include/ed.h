@@ -264,6 +264,42 @@ ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, doub
                      size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
+ * ed_rdm: every single-site and every two-site reduced density matrix of a pure state (Sec. IV:
+ * rho of the kept sites is the sum over the traced sites of psi psi^*, the kept legs in front,
+ * e.g. rho_1 = [[sum A A^*, sum A B^*], [sum B A^*, sum B B^*]] for psi = [A][B]). Not normalised:
+ * Tr rho = <psi|psi>.
+ * psi   device, 2^L amplitudes (site 1 = most significant bit, index 0 = up).
+ * rho1  device [L][2][2] complex row-major (rho_k for k = 1..L), or NULL.
+ * rho2  device [L(L-1)/2][4][4] complex row-major, or NULL: rho_{k,j} for every pair k < j in
+ *       lexicographic order (pair (k, j) at (k-1)L - (k-1)k/2 + j-k-1); row index 2 i_k + i_j.
+ *       Both triangles are written (the lower as the conjugate of the upper).
+ * The state is streamed in LDS tiles that hold 12 of its index bits; each pass evaluates the pairs
+ * of its tile bits (C(m, 2) passes for all pairs, m = ceil((L - 4) / 4); with rho2 NULL only the
+ * nearest-neighbour pairs are evaluated and rho_k is their partial trace).
+ * Limits: 2 <= L <= 30. Asynchronous on stream; deterministic (fixed reduction order).
+ * Workspace: ed_rdm_workspace(L) bytes (the pair table, 64 L(L-1) bytes, plus per-workgroup sums,
+ * 4 MiB).
+ * Errors: ED_ERR_ARG (psi or ws NULL, L outside 2..30), ED_ERR_WORKSPACE, ED_ERR_HIP.
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_rdm_workspace(int L, size_t* bytes);
+ed_status ed_rdm(const ed_c64* psi, int L, ed_c64* rho1, ed_c64* rho2, void* ws, size_t ws_bytes, void* stream);
+
+/* Pairs of index bits (p < q) that ed_rdm evaluates for this L, in pass order, with the pass of
+ * each; all_pairs = 0 gives the nearest-neighbour plan. Writes min(count, max_pairs) entries of
+ * pairs [2 per pair] and pass_of, and returns count (-1 for L outside 2..30). Host only. */
+int ed_rdm_plan_pairs(int L, int all_pairs, int* pairs, int max_pairs, int* pass_of);
+
+/* ----------------------------------------------------------------------------------------
+ * ed_trace_distances: D(a_m, b_m) = 1/2 Tr |a_m - b_m|, |A| = sqrt(A^dagger A) (Sec. V, the
+ * distance of the error measures eps_local and eps_corr), for count pairs of n x n matrices.
+ * a, b  host [count][n][n] complex row-major, meant Hermitian (only the Hermitian part of a - b
+ *       enters); out host [count]. D is half the sum of the absolute eigenvalues of a - b, taken
+ *       by Jacobi rotations of its real symmetric 2n x 2n form.
+ * Limits: 1 <= n <= 64. Errors: ED_ERR_ARG, ED_ERR_NUMERIC (non-finite entry), ED_ERR_NOCONV.
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_trace_distances(int n, int count, const ed_c64* a, const ed_c64* b, double* out);
+
+/* ----------------------------------------------------------------------------------------
  * Quantum trajectories (Sec. VI.A) of the Lindblad equation with one jump operator per site,
  * L_nu = sqrt(rate_nu) J on site nu, and H_eff = H - (i/2) sum_nu L_nu^dagger L_nu built inside.
  * Per trajectory: draw r; evolve the unnormalised state under H_eff (Krylov steps of length dt,

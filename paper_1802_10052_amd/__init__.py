@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import EdError, call, lib
 
-__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "trajectories", "philox_words", "evolve_adjoint", "evolve_loss", "AdjointEvolve", "EdError", "lib"]
+__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "rdm", "rdm_plan", "trace_distances", "eps_local", "eps_corr", "trajectories", "philox_words", "evolve_adjoint", "evolve_loss", "AdjointEvolve", "EdError", "lib"]
 
 
 def _stream_ptr(stream=None):
@@ -218,6 +218,60 @@ def entropy(psi, L, l_cut=None, spectrum=False, stream=None):
     call("ed_entropy", _dptr(psi), int(L), 2, l, C.byref(S), spec.ctypes.data if spectrum else None,
          _dptr(ws), nb.value, _stream_ptr(stream))
     return (S.value, spec) if spectrum else S.value
+
+
+def rdm(psi, L, two_site=True, stream=None):
+    """Reduced density matrices of a device state (ed_rdm): rho1 [L, 2, 2] (rho_k, k = 1..L) and,
+    with two_site, rho2 [L(L-1)/2, 4, 4] (rho_{k,j} for all pairs k < j, lexicographic), both
+    complex128 device tensors, not normalised (trace <psi|psi>). Asynchronous on the stream."""
+    import torch
+    _check_state(psi, 1 << L)
+    nb = C.c_size_t()
+    call("ed_rdm_workspace", int(L), C.byref(nb))
+    ws = _workspace(nb.value, psi.device)
+    rho1 = torch.empty((L, 2, 2), dtype=torch.complex128, device=psi.device)
+    rho2 = torch.empty((L * (L - 1) // 2, 4, 4), dtype=torch.complex128, device=psi.device) if two_site else None
+    call("ed_rdm", _dptr(psi), int(L), _dptr(rho1), _dptr(rho2) if two_site else None, _dptr(ws), nb.value,
+         _stream_ptr(stream))
+    return rho1, rho2
+
+
+def rdm_plan(L, all_pairs=True):
+    """The pairs of index bits ed_rdm evaluates, as (pairs [n, 2], pass index [n]) numpy arrays."""
+    n = lib().ed_rdm_plan_pairs(int(L), int(all_pairs), None, 0, None)
+    if n < 0:
+        raise EdError("ed_rdm_plan_pairs", "ED_ERR_ARG", f"L={L}")
+    pairs = np.zeros((n, 2), np.int32)
+    pass_of = np.zeros(n, np.int32)
+    lib().ed_rdm_plan_pairs(int(L), int(all_pairs), pairs.ctypes.data, n, pass_of.ctypes.data)
+    return pairs, pass_of
+
+
+def trace_distances(a, b):
+    """D = 1/2 Tr|a_m - b_m| for stacks of Hermitian n x n matrices (ed_trace_distances, host).
+    a, b: arrays or tensors of shape [count, n, n] (or [n, n]); returns a numpy array [count]."""
+    def host(x):
+        if hasattr(x, "detach"):
+            x = x.detach().cpu().numpy()
+        return np.ascontiguousarray(np.asarray(x, np.complex128))
+    A, B = host(a), host(b)
+    if A.ndim == 2:
+        A, B = A[None], B[None]
+    if A.shape != B.shape or A.ndim != 3 or A.shape[1] != A.shape[2]:
+        raise ValueError(f"shapes {A.shape} and {B.shape} are not two equal stacks of square matrices")
+    out = np.zeros(A.shape[0])
+    call("ed_trace_distances", int(A.shape[1]), int(A.shape[0]), A.ctypes.data, B.ctypes.data, out.ctypes.data)
+    return out
+
+
+def eps_local(rho1, rho1_ref):
+    """The largest single-site trace distance (the error measure eps_local of the convergence study)."""
+    return float(trace_distances(rho1, rho1_ref).max())
+
+
+def eps_corr(rho2, rho2_ref):
+    """The largest two-site trace distance over all pairs (eps_corr)."""
+    return float(trace_distances(rho2, rho2_ref).max())
 
 
 def trajectories(models, jump_op, rates, psi0, model_of_traj, dt, n_steps, out_stride, seed,

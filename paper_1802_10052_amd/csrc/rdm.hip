@@ -1,0 +1,419 @@
+// Single-site and two-site reduced density matrices of a pure state (Sec. IV: rho of the kept
+// sites is the sum over the traced indices of psi psi^*, arranged as the blocks [A][B] of the
+// state with the kept legs in front; only one triangle is needed since rho is Hermitian), and
+// the trace distance D = 1/2 Tr|rho - rho'| of the convergence study (Sec. V).
+//
+// rho_{k,j} for a pair of sites k < j (bits q = L-k > p = L-j) is, with u = bit q and v = bit p of
+// the index, rho[2u+v][2u'+v'] = sum over the other bits of psi[.. u .. v ..] psi^*[.. u' .. v' ..].
+// Every entry combines the four amplitudes of one "quad" {x, x|2^p, x|2^q, x|2^p|2^q} (x with both
+// bits clear): 4 squared moduli and 6 conjugate products per quad and pair.
+//
+// The state is streamed in tiles of 2^T amplitudes (T = 12, 64 KiB of LDS) whose index bits are
+// the 4 low bits (256-byte runs) plus 8 other bits; the quads of every pair of tile bits are then
+// on chip. The high bits are cut into groups of 4; the tile of groups (a, b) holds every pair of
+// bits inside low + G_a + G_b, so the C(m, 2) tiles cover all pairs (m = ceil((L-4)/4)). Each pair
+// is evaluated in exactly one pass, the passes are balanced, and a pass holds at most 32 pairs
+// (512 threads, 4 pairs per wave, each lane accumulating 16 doubles per pair over all of its
+// tiles: 128 registers). One workgroup per CU is persistent over the tiles of a pass and loads
+// the next tile into registers while it evaluates the current one from LDS; the reduction runs
+// in a fixed order, so results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "dense.h"
+#include "ed_internal.h"
+
+namespace ed {
+namespace {
+
+constexpr int kRdmThreads = 512;
+constexpr int kThreadBits = 9;                                  // tile-local bits 0..8 = thread
+constexpr int kSlots = 1 << (kTileBits - kThreadBits);          // amplitudes per thread (8)
+constexpr int kRdmPairsPerWave = 4;
+constexpr int kRdmMaxPairs = (kRdmThreads / 64) * kRdmPairsPerWave;  // pairs per pass
+constexpr int kRdmLowBits = 4;
+constexpr int kRdmMaxBlocks = 1024;  // workgroups per pass (one per CU)
+constexpr int kRdmVals = 16;         // 4 real diagonal + 6 complex upper entries
+
+struct RdmPass {
+    int T;                         // tile bits
+    int ncomp;                     // index bits outside the tile (L - T)
+    int npairs;
+    int pos[kTileBits];            // global bit of tile-local bit i, ascending
+    int comp[32];                  // global bits outside the tile, ascending
+    int lp[kRdmMaxPairs];          // tile-local bits of each pair, lp < lq
+    int lq[kRdmMaxPairs];
+    int slot[kRdmMaxPairs];        // position of the pair in the lexicographic list of site pairs
+};
+
+// index of the site pair (k, j), 1 <= k < j <= L, in lexicographic order
+__host__ __device__ inline int pair_slot(int k, int j, int L) { return (k - 1) * L - (k - 1) * k / 2 + (j - k - 1); }
+
+__device__ inline void quad_accumulate(double* a, double2 x0, double2 x1, double2 x2, double2 x3) {
+    const double2 v[4] = {x0, x1, x2, x3};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = fma(v[r].x, v[r].x, fma(v[r].y, v[r].y, a[r]));
+    int o = 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = r + 1; c < 4; ++c) {
+            // v_r conj(v_c)
+            a[o] = fma(v[r].x, v[c].x, fma(v[r].y, v[c].y, a[o]));
+            a[o + 1] = fma(v[r].y, v[c].x, fma(-v[r].x, v[c].y, a[o + 1]));
+            o += 2;
+        }
+}
+
+__global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restrict__ psi, RdmPass pa, int64_t ntiles,
+                                                        double* __restrict__ part) {
+    __shared__ double2 s[1 << kTileBits];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int tsize = 1 << pa.T;
+    int64_t off_t = 0;
+    for (int b = 0; b < kThreadBits && b < pa.T; ++b)
+        if ((t >> b) & 1) off_t |= int64_t(1) << pa.pos[b];
+    const int p0 = wave * kRdmPairsPerWave;
+    double acc[kRdmPairsPerWave][kRdmVals];
+#pragma unroll
+    for (int w = 0; w < kRdmPairsPerWave; ++w)
+#pragma unroll
+        for (int e = 0; e < kRdmVals; ++e) acc[w][e] = 0.0;
+
+    // the next tile is loaded into registers while the current one is evaluated from LDS
+    double2 v[kSlots];
+    auto load = [&](int64_t n) {
+        int64_t base = off_t;
+        for (int b = 0; b < pa.ncomp; ++b)
+            if ((n >> b) & 1) base |= int64_t(1) << pa.comp[b];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            if ((k << kThreadBits) + t < tsize) {  // then every set bit b of k has kThreadBits + b < T
+                int64_t off = base;
+#pragma unroll
+                for (int b = 0; b < kTileBits - kThreadBits; ++b)
+                    if ((k >> b) & 1) off |= int64_t(1) << pa.pos[kThreadBits + b];
+                v[k] = psi[off];
+            }
+        }
+    };
+    int64_t n = blockIdx.x;
+    if (n < ntiles) load(n);
+    for (; n < ntiles; n += gridDim.x) {
+        __syncthreads();  // the previous tile has been read
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+            if ((k << kThreadBits) + t < tsize) s[t + (k << kThreadBits)] = v[k];
+        __syncthreads();
+        if (n + gridDim.x < ntiles) load(n + gridDim.x);
+        const int nq = tsize >> 2;  // quads per pair in one tile
+#pragma unroll
+        for (int w = 0; w < kRdmPairsPerWave; ++w) {
+            const int pi = p0 + w;
+            if (pi < pa.npairs) {  // uniform over the wave
+                const int lp = pa.lp[pi], lq = pa.lq[pi];
+                const int P = 1 << lp, Q = 1 << lq;
+                for (int j = lane; j < nq; j += 64) {
+                    int x = ((j >> lp) << (lp + 1)) | (j & (P - 1));
+                    x = ((x >> lq) << (lq + 1)) | (x & (Q - 1));
+                    quad_accumulate(acc[w], s[x], s[x | P], s[x | Q], s[x | P | Q]);
+                }
+            }
+        }
+    }
+    // fixed-order butterfly over the wave, then one row per (pair, workgroup)
+#pragma unroll
+    for (int w = 0; w < kRdmPairsPerWave; ++w) {
+        const int pi = p0 + w;
+        if (pi >= pa.npairs) continue;
+#pragma unroll
+        for (int e = 0; e < kRdmVals; ++e) {
+            double x = acc[w][e];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            if (lane == 0) part[(size_t(pi) * gridDim.x + blockIdx.x) * kRdmVals + e] = x;
+        }
+    }
+}
+
+// sum of the per-workgroup rows of each pair, in workgroup order, into the pair table
+__global__ void rdm_reduce(const double* __restrict__ part, int nblocks, RdmPass pa, double* __restrict__ table) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= pa.npairs * kRdmVals) return;
+    const int pi = idx / kRdmVals, e = idx % kRdmVals;
+    double sum = 0.0;
+    for (int g = 0; g < nblocks; ++g) sum += part[(size_t(pi) * nblocks + g) * kRdmVals + e];
+    table[size_t(pa.slot[pi]) * kRdmVals + e] = sum;
+}
+
+__device__ inline double2 upper_entry(const double* r, int a, int b) {
+    // (a < b): position of (a, b) among (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)
+    const int o = a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+    return make_double2(r[4 + 2 * o], r[5 + 2 * o]);
+}
+
+// full 4x4 rho_{k,j} of every pair, and rho_k as the partial trace of a bond pair:
+// rho_k = Tr_{k+1} rho_{k,k+1} for k < L, rho_L = Tr_{L-1} rho_{L-1,L}
+__global__ void rdm_expand(const double* __restrict__ table, int L, int npairs, double2* __restrict__ rho1,
+                           double2* __restrict__ rho2) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rho2 && idx < npairs) {
+        const double* r = table + size_t(idx) * kRdmVals;
+        double2* o = rho2 + size_t(idx) * 16;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                double2 v;
+                if (a == b) {
+                    v = make_double2(r[a], 0.0);
+                } else if (a < b) {
+                    v = upper_entry(r, a, b);
+                } else {
+                    const double2 u = upper_entry(r, b, a);
+                    v = make_double2(u.x, -u.y);
+                }
+                o[4 * a + b] = v;
+            }
+    }
+    if (rho1 && idx < L) {
+        const int k = idx + 1;
+        double2* o = rho1 + size_t(idx) * 4;
+        double d0, d1;
+        double2 c;
+        if (k < L) {  // trace over the second site of (k, k+1): sum over v
+            const double* r = table + size_t(pair_slot(k, k + 1, L)) * kRdmVals;
+            d0 = r[0] + r[1];
+            d1 = r[2] + r[3];
+            const double2 e02 = upper_entry(r, 0, 2), e13 = upper_entry(r, 1, 3);
+            c = make_double2(e02.x + e13.x, e02.y + e13.y);
+        } else {  // trace over the first site of (L-1, L): sum over u
+            const double* r = table + size_t(pair_slot(L - 1, L, L)) * kRdmVals;
+            d0 = r[0] + r[2];
+            d1 = r[1] + r[3];
+            const double2 e01 = upper_entry(r, 0, 1), e23 = upper_entry(r, 2, 3);
+            c = make_double2(e01.x + e23.x, e01.y + e23.y);
+        }
+        o[0] = make_double2(d0, 0.0);
+        o[1] = c;
+        o[2] = make_double2(c.x, -c.y);
+        o[3] = make_double2(d1, 0.0);
+    }
+}
+
+// ---------------------------------------------------------------------------- planning
+// Tile bit sets and the pairs each pass evaluates. all_pairs: every pair of bits; otherwise the
+// bonds (p, p+1) only, which is what the single-site matrices need.
+std::vector<RdmPass> rdm_plan(int L, bool all_pairs) {
+    const int T = std::min(L, kTileBits);
+    const int c = std::min(kRdmLowBits, T);
+    const int W = T - c;
+    const int nH = L - c;
+    std::vector<std::vector<int>> sets;
+    std::vector<int> group(L, -1);
+    int m = 0;
+    const int g = W / 2;
+    if (nH <= W) {
+        std::vector<int> all(L);
+        for (int b = 0; b < L; ++b) all[b] = b;
+        sets.push_back(all);
+    } else {
+        m = (nH + g - 1) / g;
+        for (int b = c; b < L; ++b) group[b] = (b - c) / g;
+        for (int a = 0; a < m; ++a)
+            for (int b2 = a + 1; b2 < m; ++b2) {
+                std::vector<bool> in(L, false);
+                for (int b = 0; b < c; ++b) in[b] = true;
+                for (int b = c; b < L; ++b)
+                    if (group[b] == a || group[b] == b2) in[b] = true;
+                int cnt = 0;
+                for (int b = 0; b < L; ++b) cnt += in[b];
+                for (int b = c; b < L && cnt < T; ++b)  // fill a short last group with other bits
+                    if (!in[b]) {
+                        in[b] = true;
+                        ++cnt;
+                    }
+                std::vector<int> S;
+                for (int b = 0; b < L; ++b)
+                    if (in[b]) S.push_back(b);
+                sets.push_back(S);
+            }
+    }
+    const int nsets = int(sets.size());
+    auto set_index = [&](int a, int b2) {  // a < b2
+        return a * m - a * (a + 1) / 2 + (b2 - a - 1);
+    };
+    struct Req {
+        int p, q;
+        std::vector<int> cand;
+    };
+    std::vector<Req> reqs;
+    for (int p = 0; p < L; ++p)
+        for (int q = p + 1; q < L; ++q) {
+            if (!all_pairs && q != p + 1) continue;
+            Req r{p, q, {}};
+            if (nsets == 1) {
+                r.cand.push_back(0);
+            } else {
+                const int ga = group[p], gb = group[q];
+                if (ga >= 0 && gb >= 0 && ga != gb) {
+                    r.cand.push_back(set_index(std::min(ga, gb), std::max(ga, gb)));
+                } else {
+                    const int gg = ga >= 0 ? ga : gb;  // the one group involved, or -1 (both low)
+                    for (int a = 0; a < m; ++a)
+                        for (int b2 = a + 1; b2 < m; ++b2)
+                            if (gg < 0 || a == gg || b2 == gg) r.cand.push_back(set_index(a, b2));
+                }
+            }
+            reqs.push_back(r);
+        }
+    std::stable_sort(reqs.begin(), reqs.end(),
+                     [](const Req& x, const Req& y) { return x.cand.size() < y.cand.size(); });
+    std::vector<std::vector<std::pair<int, int>>> members(nsets);
+    for (const Req& r : reqs) {
+        // all pairs: the least loaded candidate (balanced passes); bonds only: a candidate that is
+        // already in use, so that as few tiles as possible are streamed
+        int best = -1;
+        for (int s : r.cand) {
+            if (best < 0) {
+                best = s;
+                continue;
+            }
+            const bool s_used = !members[s].empty(), b_used = !members[best].empty();
+            if (!all_pairs && s_used != b_used) {
+                if (s_used) best = s;
+                continue;
+            }
+            if (members[s].size() < members[best].size()) best = s;
+        }
+        members[best].push_back({r.p, r.q});
+    }
+    std::vector<RdmPass> passes;
+    for (int si = 0; si < nsets; ++si) {
+        auto& mem = members[si];
+        if (mem.empty()) continue;
+        std::sort(mem.begin(), mem.end());
+        const std::vector<int>& S = sets[si];
+        std::vector<int> local(L, -1);
+        for (int i = 0; i < int(S.size()); ++i) local[S[i]] = i;
+        const int npass = (int(mem.size()) + kRdmMaxPairs - 1) / kRdmMaxPairs;
+        for (int ps = 0; ps < npass; ++ps) {
+            const int lo = int(mem.size()) * ps / npass, hi = int(mem.size()) * (ps + 1) / npass;
+            RdmPass pa{};
+            pa.T = T;
+            for (int i = 0; i < T; ++i) pa.pos[i] = S[i];
+            pa.ncomp = 0;
+            for (int b = 0; b < L; ++b)
+                if (local[b] < 0) pa.comp[pa.ncomp++] = b;
+            pa.npairs = hi - lo;
+            for (int i = lo; i < hi; ++i) {
+                const int p = mem[i].first, q = mem[i].second;
+                pa.lp[i - lo] = local[p];
+                pa.lq[i - lo] = local[q];
+                pa.slot[i - lo] = pair_slot(L - q, L - p, L);
+            }
+            passes.push_back(pa);
+        }
+    }
+    return passes;
+}
+
+size_t table_bytes(int L) { return size_t(L) * (L - 1) / 2 * kRdmVals * sizeof(double); }
+size_t part_bytes() { return size_t(kRdmMaxPairs) * kRdmMaxBlocks * kRdmVals * sizeof(double); }
+
+int rdm_blocks(int64_t ntiles) {
+    int dev = 0, cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t pr;
+        if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cu = pr.multiProcessorCount;
+    }
+    return int(std::min<int64_t>({ntiles, int64_t(cu), int64_t(kRdmMaxBlocks)}));
+}
+
+}  // namespace
+
+}  // namespace ed
+
+using namespace ed;
+
+extern "C" int ed_rdm_plan_pairs(int L, int all_pairs, int* pairs, int max_pairs, int* pass_of) {
+    if (L < 2 || L > 30) return -1;
+    const std::vector<RdmPass> ps = rdm_plan(L, all_pairs != 0);
+    int n = 0;
+    for (int i = 0; i < int(ps.size()); ++i)
+        for (int j = 0; j < ps[i].npairs; ++j) {
+            if (n < max_pairs && pairs && pass_of) {
+                pairs[2 * n] = ps[i].pos[ps[i].lp[j]];
+                pairs[2 * n + 1] = ps[i].pos[ps[i].lq[j]];
+                pass_of[n] = i;
+            }
+            ++n;
+        }
+    return n;
+}
+
+extern "C" ed_status ed_rdm_workspace(int L, size_t* bytes) {
+    if (!bytes || L < 2 || L > 30) return fail(ED_ERR_ARG, "bad argument (2 <= L <= 30)");
+    *bytes = table_bytes(L) + part_bytes();
+    return ED_OK;
+}
+
+extern "C" ed_status ed_rdm(const ed_c64* psi, int L, ed_c64* rho1, ed_c64* rho2, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!psi || L < 2 || L > 30) return fail(ED_ERR_ARG, "bad argument (psi null or L outside 2..30)");
+    if (!rho1 && !rho2) return ED_OK;
+    size_t need = 0;
+    ED_TRY(ed_rdm_workspace(L, &need));
+    if (!ws) return fail(ED_ERR_ARG, "workspace is null");
+    if (ws_bytes < need) return fail(ED_ERR_WORKSPACE, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* table = static_cast<double*>(ws);
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + table_bytes(L));
+    const std::vector<RdmPass> passes = rdm_plan(L, rho2 != nullptr);
+    const double2* p = reinterpret_cast<const double2*>(psi);
+    for (const RdmPass& pa : passes) {
+        const int64_t ntiles = int64_t(1) << pa.ncomp;
+        const int G = rdm_blocks(ntiles);
+        hipLaunchKernelGGL(rdm_pass, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part);
+        ED_HIP_TRY(hipGetLastError());
+        const int nr = pa.npairs * kRdmVals;
+        hipLaunchKernelGGL(rdm_reduce, dim3((nr + 255) / 256), dim3(256), 0, s, part, G, pa, table);
+        ED_HIP_TRY(hipGetLastError());
+    }
+    const int npairs = L * (L - 1) / 2;
+    const int nt = std::max(npairs, L);
+    hipLaunchKernelGGL(rdm_expand, dim3((nt + 255) / 256), dim3(256), 0, s, table, L, npairs,
+                       reinterpret_cast<double2*>(rho1), reinterpret_cast<double2*>(rho2));
+    ED_HIP_TRY(hipGetLastError());
+    return ED_OK;
+}
+
+extern "C" ed_status ed_trace_distances(int n, int count, const ed_c64* a, const ed_c64* b, double* out) {
+    if (n < 1 || n > 64 || count < 0) return fail(ED_ERR_ARG, "bad argument (1 <= n <= 64, count >= 0)");
+    if (count > 0 && (!a || !b || !out)) return fail(ED_ERR_ARG, "null argument");
+    // The Hermitian difference X + iY (X symmetric, Y antisymmetric) has the eigenvalues of the
+    // real symmetric [[X, -Y], [Y, X]], each twice.
+    const int n2 = 2 * n;
+    std::vector<double> S(size_t(n2) * n2), w(n2), Z(size_t(n2) * n2);
+    for (int m = 0; m < count; ++m) {
+        const ed_c64* A = a + size_t(m) * n * n;
+        const ed_c64* B = b + size_t(m) * n * n;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const size_t ij = size_t(i) * n + j, ji = size_t(j) * n + i;
+                const double dre = A[ij].re - B[ij].re, dim = A[ij].im - B[ij].im;
+                const double tre = A[ji].re - B[ji].re, tim = A[ji].im - B[ji].im;
+                if (!std::isfinite(dre) || !std::isfinite(dim)) return fail(ED_ERR_NUMERIC, "non-finite entry");
+                const double x = 0.5 * (dre + tre), y = 0.5 * (dim - tim);  // Hermitian part
+                S[size_t(i) * n2 + j] = x;
+                S[size_t(i + n) * n2 + (j + n)] = x;
+                S[size_t(i) * n2 + (j + n)] = -y;
+                S[size_t(i + n) * n2 + j] = y;
+            }
+        if (!sym_eig_jacobi(n2, S.data(), w.data(), Z.data()))
+            return fail(ED_ERR_NOCONV, "Jacobi eigenvalue iteration did not converge");
+        double sum = 0.0;
+        for (double v : w) sum += std::fabs(v);
+        out[m] = 0.25 * sum;
+    }
+    return ED_OK;
+}

@@ -1,0 +1,143 @@
+"""GPU parity of ed_rdm (single-site and two-site reduced density matrices, Sec. IV) and of the
+trace-distance error measures (Sec. V, Eqs. ed:eq:erhoi, ed:eq:erhoij) against the oracle's
+reshape/transpose construction, and exact full-size pins.
+
+Tolerances: an entry sums 2^(L-2) products in float64 in a fixed order (per-lane sequential,
+then a butterfly and a per-workgroup sum), so its error is a few 1e-16 times the sqrt of the
+number of terms relative to <psi|psi>: 1e-13 up to L = 20, 1e-12 at L = 26 and 28."""
+import numpy as np
+import pytest
+import torch
+
+import edinputs as E
+import paper_1802_10052_amd as P
+from oracle import hamiltonian as OH
+from oracle import observables as OO
+from oracle import rdm as OR
+from oracle import trotter as OT
+from oracle import krylov as OK
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def to_dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 8, 11, 12, 13, 16, 20])
+def test_rdm_vs_oracle(L):
+    print(f"rdm L={L}", flush=True)
+    psi = 1.3 * E.random_state(L, 20 + L)   # not normalised: rho keeps <psi|psi>
+    r1, r2 = P.rdm(to_dev(psi), L)
+    n2 = np.vdot(psi, psi).real
+    assert np.abs(r1.cpu().numpy() - OR.rdm1_all(psi, L)).max() < 1e-13 * n2
+    assert np.abs(r2.cpu().numpy() - OR.rdm2_all(psi, L)).max() < 1e-13 * n2
+    o1, o2 = P.rdm(to_dev(psi), L, two_site=False)
+    assert o2 is None
+    assert np.abs(o1.cpu().numpy() - OR.rdm1_all(psi, L)).max() < 1e-13 * n2
+
+
+def test_rdm_deterministic():
+    psi = E.random_state_device(20, 4, DEV)
+    a1, a2 = P.rdm(psi, 20)
+    b1, b2 = P.rdm(psi, 20)
+    assert torch.equal(a1, b1) and torch.equal(a2, b2)
+
+
+def _product_state(L, seed):
+    rng = np.random.default_rng(seed)
+    phis = [v / np.linalg.norm(v) for v in rng.standard_normal((L, 2)) + 1j * rng.standard_normal((L, 2))]
+    psi = torch.ones(1, dtype=torch.complex128, device=DEV)
+    for v in phis:
+        psi = torch.kron(psi, to_dev(v))
+    return psi, phis
+
+
+def test_rdm_product_state_L28():
+    """Every rho_{k,j} of a product state is |phi_k phi_j><phi_k phi_j|: all 378 pairs of all
+    15 passes at the full size."""
+    L = 28
+    print("rdm product state L=28", flush=True)
+    psi, phis = _product_state(L, 8)
+    r1, r2 = P.rdm(psi, L)
+    r1, r2 = r1.cpu().numpy(), r2.cpu().numpy()
+    del psi
+    torch.cuda.empty_cache()
+    for k in range(1, L + 1):
+        assert np.abs(r1[k - 1] - np.outer(phis[k - 1], phis[k - 1].conj())).max() < 1e-12
+        for j in range(k + 1, L + 1):
+            v = np.kron(phis[k - 1], phis[j - 1])
+            assert np.abs(r2[OR.pair_index(k, j, L)] - np.outer(v, v.conj())).max() < 1e-12, (k, j)
+
+
+def test_rdm_ghz_L28():
+    L = 28
+    psi = torch.zeros(1 << L, dtype=torch.complex128, device=DEV)
+    psi[0] = psi[-1] = 2 ** -0.5
+    r1, r2 = P.rdm(psi, L)
+    assert np.abs(r1.cpu().numpy() - np.eye(2) / 2).max() < 1e-15
+    assert np.abs(r2.cpu().numpy() - np.diag([0.5, 0, 0, 0.5])).max() < 1e-15
+
+
+def test_rdm_L26_sampled_pairs():
+    """A random L = 26 state: the oracle recomputes the pairs and sites below, one from each
+    kind of pass (low bits, low x group, group x group, bonds across groups, the last group)."""
+    L = 26
+    print("rdm L=26 sampled", flush=True)
+    psi_d = E.random_state_device(L, 6, DEV)
+    r1, r2 = P.rdm(psi_d, L)
+    r1, r2 = r1.cpu().numpy(), r2.cpu().numpy()
+    psi = psi_d.cpu().numpy()
+    del psi_d
+    torch.cuda.empty_cache()
+    for (k, j) in [(25, 26), (23, 26), (1, 2), (1, 26), (12, 13), (5, 17), (9, 21), (2, 3), (13, 22)]:
+        ref = OR.rdm(psi, L, [k, j])
+        assert np.abs(r2[OR.pair_index(k, j, L)] - ref).max() < 1e-12, (k, j)
+    for k in [1, 7, 13, 22, 26]:
+        assert np.abs(r1[k - 1] - OR.rdm(psi, L, [k])).max() < 1e-12, k
+
+
+def test_rdm_L28_consistency():
+    """Random L = 28 state: Hermitian, positive, trace <psi|psi>, every partial trace of every
+    rho_{k,j} equals rho_k (pairs from different passes must agree), and the diagonal of rho_k
+    gives the <sigma^z_k> of ed_measure."""
+    L = 28
+    print("rdm L=28 consistency", flush=True)
+    psi = E.random_state_device(L, 12, DEV)
+    r1, r2 = P.rdm(psi, L)
+    sz, nrm = P.measure(psi, L)
+    r1, r2 = r1.cpu().numpy(), r2.cpu().numpy()
+    del psi
+    torch.cuda.empty_cache()
+    for r in list(r1) + list(r2):
+        assert np.abs(r - r.conj().T).max() == 0.0
+        assert np.linalg.eigvalsh(r).min() > -1e-12
+        assert abs(np.trace(r).real - 1.0) < 1e-12
+    for k in range(1, L + 1):
+        for j in range(k + 1, L + 1):
+            r = r2[OR.pair_index(k, j, L)].reshape(2, 2, 2, 2)
+            assert np.abs(np.einsum("abcb->ac", r) - r1[k - 1]).max() < 1e-12, (k, j)
+            assert np.abs(np.einsum("abad->bd", r) - r1[j - 1]).max() < 1e-12, (k, j)
+    assert np.abs((r1[:, 0, 0] - r1[:, 1, 1]).real - sz).max() < 1e-12
+
+
+def test_error_measures_trotter_vs_exact_L12():
+    """eps_local and eps_corr of the Trotter states (order 2 and 4) against the matrix
+    exponential, from the GPU matrices and ed_trace_distances, equal the oracle's."""
+    L, dt, steps = 12, 0.1, 10
+    desc = E.tfim(L, 0.9)
+    psi0 = E.random_state(L, 2)
+    H = OH.hamiltonian_dense(desc)
+    ex = OK.expm_step(H, psi0, dt * steps)
+    ex1, ex2 = P.rdm(to_dev(ex), L)
+    for order in (2, 4):
+        ref_psi, _ = OT.evolve(desc, psi0, dt, steps, order)
+        psi = to_dev(psi0)
+        P.trotter_evolve(P.Model(desc), psi, dt, steps, order=order, observe=False)
+        g1, g2 = P.rdm(psi, L)
+        el, ec = P.eps_local(g1, ex1), P.eps_corr(g2, ex2)
+        rl = OR.eps_local(OR.rdm1_all(ref_psi, L), OR.rdm1_all(ex, L))
+        rc = OR.eps_corr(OR.rdm2_all(ref_psi, L), OR.rdm2_all(ex, L))
+        assert abs(el - rl) < 1e-11 and abs(ec - rc) < 1e-11, (order, el, rl, ec, rc)
+        assert rc > 1e-8   # the splitting error is visible
