@@ -30,18 +30,21 @@ namespace {
 constexpr int kRdmThreads = 512;
 constexpr int kThreadBits = 9;                                  // tile-local bits 0..8 = thread
 constexpr int kSlots = 1 << (kTileBits - kThreadBits);          // amplitudes per thread (8)
+constexpr int kWaves = kRdmThreads / 64;
 constexpr int kRdmPairsPerWave = 4;
-constexpr int kRdmMaxPairs = (kRdmThreads / 64) * kRdmPairsPerWave;  // pairs per pass
+constexpr int kRdmMaxPairs = kWaves * kRdmPairsPerWave;  // pairs (work items) per pass
 constexpr int kRdmLowBits = 4;
 constexpr int kRdmMaxBlocks = 1024;  // workgroups per pass (one per CU)
 constexpr int kRdmVals = 16;         // 4 real diagonal + 6 complex upper entries
+constexpr int kMaxComp = 30 - kTileBits;  // index bits outside a full tile (L <= 30)
 
 struct RdmPass {
     int T;                         // tile bits
     int ncomp;                     // index bits outside the tile (L - T)
     int npairs;
+    int nsplit;                    // work items per pair (each takes every nsplit-th run of 64 quads)
     int pos[kTileBits];            // global bit of tile-local bit i, ascending
-    int comp[32];                  // global bits outside the tile, ascending
+    int comp[kMaxComp];            // global bits outside the tile, ascending
     int lp[kRdmMaxPairs];          // tile-local bits of each pair, lp < lq
     int lq[kRdmMaxPairs];
     int slot[kRdmMaxPairs];        // position of the pair in the lexicographic list of site pairs
@@ -66,84 +69,127 @@ __device__ inline void quad_accumulate(double* a, double2 x0, double2 x1, double
         }
 }
 
+// insert a zero bit at position lo and one at position hi (lo < hi) into j
+__host__ __device__ inline int insert_two(int j, int lo, int hi) {
+    int x = ((j >> lo) << (lo + 1)) | (j & ((1 << lo) - 1));
+    return ((x >> hi) << (hi + 1)) | (x & ((1 << hi) - 1));
+}
+
+// FULL: 2^12-amplitude tiles (L >= 12); otherwise the whole state (2^L < 4096) is one tile
+template <bool FULL>
 __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restrict__ psi, RdmPass pa, int64_t ntiles,
                                                         double* __restrict__ part) {
     __shared__ double2 s[1 << kTileBits];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int tsize = 1 << pa.T;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: pair data in scalar registers
+    const int tsize = FULL ? (1 << kTileBits) : (1 << pa.T);
     int64_t off_t = 0;
-    for (int b = 0; b < kThreadBits && b < pa.T; ++b)
-        if ((t >> b) & 1) off_t |= int64_t(1) << pa.pos[b];
-    const int p0 = wave * kRdmPairsPerWave;
+#pragma unroll
+    for (int b = 0; b < kThreadBits; ++b)
+        if ((FULL || b < pa.T) && ((t >> b) & 1)) off_t |= int64_t(1) << pa.pos[b];
+    static_assert(kSlots == 8, "eight slot registers below");
+    int64_t soff[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+        int64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < kTileBits - kThreadBits; ++b)
+            if ((FULL || kThreadBits + b < pa.T) && ((k >> b) & 1)) o |= int64_t(1) << pa.pos[kThreadBits + b];
+        soff[k] = o;
+    }
+    // work item i = pair (i % npairs), part (i / npairs); wave w takes items w, w + 8, ...
+    const int nitems = pa.npairs * pa.nsplit;
     double acc[kRdmPairsPerWave][kRdmVals];
 #pragma unroll
     for (int w = 0; w < kRdmPairsPerWave; ++w)
 #pragma unroll
         for (int e = 0; e < kRdmVals; ++e) acc[w][e] = 0.0;
 
-    // the next tile is loaded into registers while the current one is evaluated from LDS
-    double2 v[kSlots];
-    auto load = [&](int64_t n) {
-        int64_t base = off_t;
-        for (int b = 0; b < pa.ncomp; ++b)
-            if ((n >> b) & 1) base |= int64_t(1) << pa.comp[b];
-#pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            if ((k << kThreadBits) + t < tsize) {  // then every set bit b of k has kThreadBits + b < T
-                int64_t off = base;
-#pragma unroll
-                for (int b = 0; b < kTileBits - kThreadBits; ++b)
-                    if ((k >> b) & 1) off |= int64_t(1) << pa.pos[kThreadBits + b];
-                v[k] = psi[off];
-            }
-        }
-    };
+    // the next tile is loaded into registers while the current one is evaluated from LDS; eight
+    // named registers (an array that lives across the evaluation loop is placed in scratch memory)
+    double2 v0, v1, v2, v3, v4, v5, v6, v7;
+#define ED_SLOT(k) (k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : k == 3 ? v3 : k == 4 ? v4 : k == 5 ? v5 : k == 6 ? v6 : v7)
     int64_t n = blockIdx.x;
-    if (n < ntiles) load(n);
+    if (n < ntiles) {
+        int64_t base = off_t;
+#pragma unroll
+        for (int b = 0; b < kMaxComp; ++b)
+            if (b < pa.ncomp && ((n >> b) & 1)) base |= int64_t(1) << pa.comp[b];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+            if (FULL || (k << kThreadBits) + t < tsize) ED_SLOT(k) = psi[base + soff[k]];
+    }
     for (; n < ntiles; n += gridDim.x) {
         __syncthreads();  // the previous tile has been read
 #pragma unroll
         for (int k = 0; k < kSlots; ++k)
-            if ((k << kThreadBits) + t < tsize) s[t + (k << kThreadBits)] = v[k];
+            if (FULL || (k << kThreadBits) + t < tsize) s[t + (k << kThreadBits)] = ED_SLOT(k);
         __syncthreads();
-        if (n + gridDim.x < ntiles) load(n + gridDim.x);
-        const int nq = tsize >> 2;  // quads per pair in one tile
+        const int64_t nn = n + gridDim.x;
+        if (nn < ntiles) {
+            int64_t base = off_t;
+#pragma unroll
+            for (int b = 0; b < kMaxComp; ++b)
+                if (b < pa.ncomp && ((nn >> b) & 1)) base |= int64_t(1) << pa.comp[b];
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) ED_SLOT(k) = psi[base + soff[k]];  // FULL only: ntiles > 1
+        }
+        const int rows = FULL ? (1 << (kTileBits - 2)) / 64 : ((tsize >> 2) + 63) / 64;  // runs of 64 quads
 #pragma unroll
         for (int w = 0; w < kRdmPairsPerWave; ++w) {
-            const int pi = p0 + w;
-            if (pi < pa.npairs) {  // uniform over the wave
+            const int it = wave + kWaves * w;
+            if (it < nitems) {  // uniform over the wave
+                const int pi = it % pa.npairs, piece = it / pa.npairs;
                 const int lp = pa.lp[pi], lq = pa.lq[pi];
                 const int P = 1 << lp, Q = 1 << lq;
-                for (int j = lane; j < nq; j += 64) {
-                    int x = ((j >> lp) << (lp + 1)) | (j & (P - 1));
-                    x = ((x >> lq) << (lq + 1)) | (x & (Q - 1));
-                    quad_accumulate(acc[w], s[x], s[x | P], s[x | Q], s[x | P | Q]);
+                // quad j = lane + 64 r: its base index is insert(lane) | insert(64 r) (disjoint bits)
+                const int xl = insert_two(lane, lp, lq);
+                int r = piece;
+                if (FULL) {  // two quads per round: the second one's reads overlap the first one's FMAs
+                    for (; r + pa.nsplit < rows; r += 2 * pa.nsplit) {
+                        const double2* qa = s + (xl | insert_two(64 * r, lp, lq));
+                        const double2* qb = s + (xl | insert_two(64 * (r + pa.nsplit), lp, lq));
+                        const double2 a0 = qa[0], a1 = qa[P], a2 = qa[Q], a3 = qa[P + Q];
+                        const double2 b0 = qb[0], b1 = qb[P], b2 = qb[Q], b3 = qb[P + Q];
+                        quad_accumulate(acc[w], a0, a1, a2, a3);
+                        quad_accumulate(acc[w], b0, b1, b2, b3);
+                    }
+                }
+                for (; r < rows; r += pa.nsplit) {
+                    if (!FULL && lane + 64 * r >= (tsize >> 2)) continue;
+                    const double2* q = s + (xl | insert_two(64 * r, lp, lq));
+                    quad_accumulate(acc[w], q[0], q[P], q[Q], q[P + Q]);
                 }
             }
         }
     }
+#undef ED_SLOT
     // fixed-order butterfly over the wave, then one row per (pair, workgroup)
 #pragma unroll
     for (int w = 0; w < kRdmPairsPerWave; ++w) {
-        const int pi = p0 + w;
-        if (pi >= pa.npairs) continue;
+        const int it = wave + kWaves * w;
+        if (it >= nitems) continue;
 #pragma unroll
         for (int e = 0; e < kRdmVals; ++e) {
             double x = acc[w][e];
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-            if (lane == 0) part[(size_t(pi) * gridDim.x + blockIdx.x) * kRdmVals + e] = x;
+            if (lane == 0) part[(size_t(it) * gridDim.x + blockIdx.x) * kRdmVals + e] = x;
         }
     }
 }
 
-// sum of the per-workgroup rows of each pair, in workgroup order, into the pair table
+// sum of the per-workgroup rows of each pair (over its parts, then workgroups, in order) into the
+// pair table
 __global__ void rdm_reduce(const double* __restrict__ part, int nblocks, RdmPass pa, double* __restrict__ table) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= pa.npairs * kRdmVals) return;
     const int pi = idx / kRdmVals, e = idx % kRdmVals;
     double sum = 0.0;
-    for (int g = 0; g < nblocks; ++g) sum += part[(size_t(pi) * nblocks + g) * kRdmVals + e];
+    for (int pt = 0; pt < pa.nsplit; ++pt) {
+        const size_t it = size_t(pt) * pa.npairs + pi;
+        for (int g = 0; g < nblocks; ++g) sum += part[(it * nblocks + g) * kRdmVals + e];
+    }
     table[size_t(pa.slot[pi]) * kRdmVals + e] = sum;
 }
 
@@ -305,6 +351,8 @@ std::vector<RdmPass> rdm_plan(int L, bool all_pairs) {
             for (int b = 0; b < L; ++b)
                 if (local[b] < 0) pa.comp[pa.ncomp++] = b;
             pa.npairs = hi - lo;
+            // passes with few pairs split each pair's quads over several work items
+            pa.nsplit = std::max(1, std::min(kRdmMaxPairs / pa.npairs, std::max(1, (1 << (T - 2)) / 64)));
             for (int i = lo; i < hi; ++i) {
                 const int p = mem[i].first, q = mem[i].second;
                 pa.lp[i - lo] = local[p];
@@ -373,7 +421,11 @@ extern "C" ed_status ed_rdm(const ed_c64* psi, int L, ed_c64* rho1, ed_c64* rho2
     for (const RdmPass& pa : passes) {
         const int64_t ntiles = int64_t(1) << pa.ncomp;
         const int G = rdm_blocks(ntiles);
-        hipLaunchKernelGGL(rdm_pass, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part);
+        if (pa.T == kTileBits) {
+            hipLaunchKernelGGL(rdm_pass<true>, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part);
+        } else {
+            hipLaunchKernelGGL(rdm_pass<false>, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part);
+        }
         ED_HIP_TRY(hipGetLastError());
         const int nr = pa.npairs * kRdmVals;
         hipLaunchKernelGGL(rdm_reduce, dim3((nr + 255) / 256), dim3(256), 0, s, part, G, pa, table);
