@@ -225,18 +225,22 @@ def row_lrqi_L28(P, E, torch, dev, reps=10, steps=20):
 
 def row_rdm_L28(P, E, torch, dev, reps=3):
     """All single-site and all two-site reduced density matrices (Sec. IV) of a random L = 28
-    state: 378 pairs in 15 LDS-tiled passes. Algorithmic work: 64 flops per quad of amplitudes
-    and pair (4 squared moduli, 6 conjugate products), C(L,2) 2^(L-2) quads, against the FP64
-    vector peak (the products are not a dense contraction); and the single-site matrices alone
-    (the 27 bonds in 5 passes)."""
+    state: 378 pairs in 15 LDS-tiled passes. Algorithmic work: the 6 upper off-diagonal entries of
+    each pair's 4x4 matrix are complex multiply-adds over the 2^(L-2) quads of amplitudes (48
+    flops per quad and pair); the 4 diagonal entries are marginals of |psi|^2, summed once per
+    amplitude and pass (4 flops). The products are not a dense contraction, so the bound is the
+    FP64 vector peak (78.6 TFLOP/s). Also timed: the single-site matrices alone (27 bonds in 5
+    passes)."""
     L = 28
     psi = E.random_state_device(L, 12, dev)
+    pairs, pass_of = P.rdm_plan(L)
+    passes = int(pass_of.max()) + 1
     P.rdm(psi, L)
     with Timer(torch, None) as t:
         for _ in range(reps):
             P.rdm(psi, L)
     ms = 1e3 * t.s / reps
-    flops = 64.0 * (L * (L - 1) // 2) * float(1 << (L - 2))
+    flops = 48.0 * len(pairs) * float(1 << (L - 2)) + 4.0 * passes * float(1 << L)
     P.rdm(psi, L, two_site=False)
     with Timer(torch, None) as t1:
         for _ in range(reps):
@@ -245,8 +249,9 @@ def row_rdm_L28(P, E, torch, dev, reps=3):
     tf = flops / (ms * 1e-3) / 1e12
     return {"workload": "rho_k for all 28 sites and rho_{k,j} for all 378 pairs of a random L=28 state",
             "all_pairs_ms": round(ms, 2), "all_pairs_TFLOPs": round(tf, 2),
-            "frac_fp64_vector_peak": round(tf / 78.6, 4), "passes": 15,
-            "single_site_only_ms": round(ms1, 2), "single_site_passes": 5}
+            "frac_fp64_vector_peak": round(tf / 78.6, 4), "passes": passes,
+            "single_site_only_ms": round(ms1, 2),
+            "single_site_passes": int(P.rdm_plan(L, all_pairs=False)[1].max()) + 1}
 
 
 def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):

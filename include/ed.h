@@ -278,7 +278,7 @@ ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, doub
  * nearest-neighbour pairs are evaluated and rho_k is their partial trace).
  * Limits: 2 <= L <= 30. Asynchronous on stream; deterministic (fixed reduction order).
  * Workspace: ed_rdm_workspace(L) bytes (the pair table, 64 L(L-1) bytes, plus per-workgroup sums,
- * 4 MiB).
+ * about 35 MiB).
  * Errors: ED_ERR_ARG (psi or ws NULL, L outside 2..30), ED_ERR_WORKSPACE, ED_ERR_HIP.
  * ---------------------------------------------------------------------------------------- */
 ed_status ed_rdm_workspace(int L, size_t* bytes);

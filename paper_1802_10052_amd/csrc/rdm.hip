@@ -36,6 +36,7 @@ constexpr int kRdmMaxPairs = kWaves * kRdmPairsPerWave;  // pairs (work items) p
 constexpr int kRdmLowBits = 4;
 constexpr int kRdmMaxBlocks = 1024;  // workgroups per pass (one per CU)
 constexpr int kRdmVals = 16;         // 4 real diagonal + 6 complex upper entries
+constexpr int kRdmOff = 12;          // the 6 complex upper entries accumulated per work item
 constexpr int kMaxComp = 30 - kTileBits;  // index bits outside a full tile (L <= 30)
 
 struct RdmPass {
@@ -53,16 +54,15 @@ struct RdmPass {
 // index of the site pair (k, j), 1 <= k < j <= L, in lexicographic order
 __host__ __device__ inline int pair_slot(int k, int j, int L) { return (k - 1) * L - (k - 1) * k / 2 + (j - k - 1); }
 
+// the six upper off-diagonal entries v_r conj(v_c), r < c, of one quad; the diagonal comes from
+// the per-index probability sums
 __device__ inline void quad_accumulate(double* a, double2 x0, double2 x1, double2 x2, double2 x3) {
     const double2 v[4] = {x0, x1, x2, x3};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = fma(v[r].x, v[r].x, fma(v[r].y, v[r].y, a[r]));
-    int o = 4;
+    int o = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = r + 1; c < 4; ++c) {
-            // v_r conj(v_c)
             a[o] = fma(v[r].x, v[c].x, fma(v[r].y, v[c].y, a[o]));
             a[o + 1] = fma(v[r].y, v[c].x, fma(-v[r].x, v[c].y, a[o + 1]));
             o += 2;
@@ -78,7 +78,7 @@ __host__ __device__ inline int insert_two(int j, int lo, int hi) {
 // FULL: 2^12-amplitude tiles (L >= 12); otherwise the whole state (2^L < 4096) is one tile
 template <bool FULL>
 __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restrict__ psi, RdmPass pa, int64_t ntiles,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, double* __restrict__ hist) {
     __shared__ double2 s[1 << kTileBits];
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: pair data in scalar registers
@@ -99,16 +99,20 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
     }
     // work item i = pair (i % npairs), part (i / npairs); wave w takes items w, w + 8, ...
     const int nitems = pa.npairs * pa.nsplit;
-    double acc[kRdmPairsPerWave][kRdmVals];
+    double acc[kRdmPairsPerWave][kRdmOff];
 #pragma unroll
     for (int w = 0; w < kRdmPairsPerWave; ++w)
 #pragma unroll
-        for (int e = 0; e < kRdmVals; ++e) acc[w][e] = 0.0;
+        for (int e = 0; e < kRdmOff; ++e) acc[w][e] = 0.0;
 
     // the next tile is loaded into registers while the current one is evaluated from LDS; eight
     // named registers (an array that lives across the evaluation loop is placed in scratch memory)
+    // |psi|^2 of each of the thread's tile positions, summed over its tiles (the diagonal of every
+    // pair's matrix is a marginal of these)
     double2 v0, v1, v2, v3, v4, v5, v6, v7;
+    double h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0, h6 = 0, h7 = 0;
 #define ED_SLOT(k) (k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : k == 3 ? v3 : k == 4 ? v4 : k == 5 ? v5 : k == 6 ? v6 : v7)
+#define ED_HIST(k) (k == 0 ? h0 : k == 1 ? h1 : k == 2 ? h2 : k == 3 ? h3 : k == 4 ? h4 : k == 5 ? h5 : k == 6 ? h6 : h7)
     int64_t n = blockIdx.x;
     if (n < ntiles) {
         int64_t base = off_t;
@@ -123,7 +127,11 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
         __syncthreads();  // the previous tile has been read
 #pragma unroll
         for (int k = 0; k < kSlots; ++k)
-            if (FULL || (k << kThreadBits) + t < tsize) s[t + (k << kThreadBits)] = ED_SLOT(k);
+            if (FULL || (k << kThreadBits) + t < tsize) {
+                const double2 a = ED_SLOT(k);
+                s[t + (k << kThreadBits)] = a;
+                ED_HIST(k) = fma(a.x, a.x, fma(a.y, a.y, ED_HIST(k)));
+            }
         __syncthreads();
         const int64_t nn = n + gridDim.x;
         if (nn < ntiles) {
@@ -163,34 +171,72 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
             }
         }
     }
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k)
+        if (FULL || (k << kThreadBits) + t < tsize) hist[size_t(blockIdx.x) * (1 << kTileBits) + t + (k << kThreadBits)] = ED_HIST(k);
 #undef ED_SLOT
+#undef ED_HIST
     // fixed-order butterfly over the wave, then one row per (pair, workgroup)
 #pragma unroll
     for (int w = 0; w < kRdmPairsPerWave; ++w) {
         const int it = wave + kWaves * w;
         if (it >= nitems) continue;
 #pragma unroll
-        for (int e = 0; e < kRdmVals; ++e) {
+        for (int e = 0; e < kRdmOff; ++e) {
             double x = acc[w][e];
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-            if (lane == 0) part[(size_t(it) * gridDim.x + blockIdx.x) * kRdmVals + e] = x;
+            if (lane == 0) part[(size_t(it) * gridDim.x + blockIdx.x) * kRdmOff + e] = x;
         }
     }
 }
 
-// sum of the per-workgroup rows of each pair (over its parts, then workgroups, in order) into the
-// pair table
-__global__ void rdm_reduce(const double* __restrict__ part, int nblocks, RdmPass pa, double* __restrict__ table) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= pa.npairs * kRdmVals) return;
-    const int pi = idx / kRdmVals, e = idx % kRdmVals;
+// tile-position probabilities summed over the workgroups, in order
+__global__ void rdm_hist_reduce(const double* __restrict__ hist, int nblocks, int tsize, double* __restrict__ H) {
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= tsize) return;
     double sum = 0.0;
-    for (int pt = 0; pt < pa.nsplit; ++pt) {
-        const size_t it = size_t(pt) * pa.npairs + pi;
-        for (int g = 0; g < nblocks; ++g) sum += part[(it * nblocks + g) * kRdmVals + e];
+#pragma unroll 8
+    for (int g = 0; g < nblocks; ++g) sum += hist[size_t(g) * (1 << kTileBits) + y];
+    H[y] = sum;
+}
+
+// one workgroup per pair of the pass: the table row's diagonal is the marginal of H over the
+// pair's two tile bits (strided partial sums, then a fixed LDS tree); the upper entries are the
+// sums of the per-workgroup rows of the pair's work items (parts, then workgroups, in order)
+__global__ __launch_bounds__(256) void rdm_reduce(const double* __restrict__ part, int nblocks, RdmPass pa,
+                                                  const double* __restrict__ H, double* __restrict__ table) {
+    __shared__ double red[4][256];
+    const int pi = blockIdx.x, t = threadIdx.x;
+    const int lp = pa.lp[pi], lq = pa.lq[pi];
+    const int nq = (1 << pa.T) >> 2;
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = t; j < nq; j += 256) {
+        const int x = insert_two(j, lp, lq);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[e] += H[x | ((e >> 1) << lq) | ((e & 1) << lp)];
     }
-    table[size_t(pa.slot[pi]) * kRdmVals + e] = sum;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[e][t] = d[e];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[e][t] += red[e][t + h];
+        __syncthreads();
+    }
+    double* row = table + size_t(pa.slot[pi]) * kRdmVals;
+    if (t < 4) row[t] = red[t][0];
+    if (t >= 4 && t < kRdmVals) {
+        const int e = t - 4;
+        double sum = 0.0;
+        for (int pt = 0; pt < pa.nsplit; ++pt) {
+            const size_t it = size_t(pt) * pa.npairs + pi;
+#pragma unroll 8
+            for (int g = 0; g < nblocks; ++g) sum += part[(it * nblocks + g) * kRdmOff + e];
+        }
+        row[t] = sum;
+    }
 }
 
 __device__ inline double2 upper_entry(const double* r, int a, int b) {
@@ -366,7 +412,8 @@ std::vector<RdmPass> rdm_plan(int L, bool all_pairs) {
 }
 
 size_t table_bytes(int L) { return size_t(L) * (L - 1) / 2 * kRdmVals * sizeof(double); }
-size_t part_bytes() { return size_t(kRdmMaxPairs) * kRdmMaxBlocks * kRdmVals * sizeof(double); }
+size_t part_bytes() { return size_t(kRdmMaxPairs) * kRdmMaxBlocks * kRdmOff * sizeof(double); }
+size_t hist_bytes() { return (size_t(kRdmMaxBlocks) + 1) * (size_t(1) << kTileBits) * sizeof(double); }
 
 int rdm_blocks(int64_t ntiles) {
     int dev = 0, cu = 256;
@@ -401,7 +448,7 @@ extern "C" int ed_rdm_plan_pairs(int L, int all_pairs, int* pairs, int max_pairs
 
 extern "C" ed_status ed_rdm_workspace(int L, size_t* bytes) {
     if (!bytes || L < 2 || L > 30) return fail(ED_ERR_ARG, "bad argument (2 <= L <= 30)");
-    *bytes = table_bytes(L) + part_bytes();
+    *bytes = table_bytes(L) + part_bytes() + hist_bytes();
     return ED_OK;
 }
 
@@ -416,19 +463,23 @@ extern "C" ed_status ed_rdm(const ed_c64* psi, int L, ed_c64* rho1, ed_c64* rho2
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* table = static_cast<double*>(ws);
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + table_bytes(L));
+    double* hist = part + part_bytes() / sizeof(double);
+    double* H = hist + size_t(kRdmMaxBlocks) * (size_t(1) << kTileBits);
     const std::vector<RdmPass> passes = rdm_plan(L, rho2 != nullptr);
     const double2* p = reinterpret_cast<const double2*>(psi);
     for (const RdmPass& pa : passes) {
         const int64_t ntiles = int64_t(1) << pa.ncomp;
         const int G = rdm_blocks(ntiles);
         if (pa.T == kTileBits) {
-            hipLaunchKernelGGL(rdm_pass<true>, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part);
+            hipLaunchKernelGGL(rdm_pass<true>, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part, hist);
         } else {
-            hipLaunchKernelGGL(rdm_pass<false>, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part);
+            hipLaunchKernelGGL(rdm_pass<false>, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part, hist);
         }
         ED_HIP_TRY(hipGetLastError());
-        const int nr = pa.npairs * kRdmVals;
-        hipLaunchKernelGGL(rdm_reduce, dim3((nr + 255) / 256), dim3(256), 0, s, part, G, pa, table);
+        const int tsize = 1 << pa.T;
+        hipLaunchKernelGGL(rdm_hist_reduce, dim3((tsize + 255) / 256), dim3(256), 0, s, hist, G, tsize, H);
+        ED_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(rdm_reduce, dim3(pa.npairs), dim3(256), 0, s, part, G, pa, H, table);
         ED_HIP_TRY(hipGetLastError());
     }
     const int npairs = L * (L - 1) / 2;

@@ -35,7 +35,7 @@ def test_argument_errors():
     nb = C.c_size_t()
     assert lib.ed_rdm_workspace(1, C.byref(nb)) == -1
     assert lib.ed_rdm_workspace(31, C.byref(nb)) == -1
-    assert lib.ed_rdm_workspace(28, C.byref(nb)) == 0 and nb.value == 28 * 27 // 2 * 128 + 32 * 1024 * 128
+    assert lib.ed_rdm_workspace(28, C.byref(nb)) == 0 and nb.value == 28 * 27 // 2 * 128 + 32 * 1024 * 96 + 1025 * 4096 * 8
     assert lib.ed_rdm(None, 10, None, None, None, 0, None) == -1
     assert lib.ed_rdm_plan_pairs(1, 1, None, 0, None) == -1
     assert lib.ed_trace_distances(0, 1, None, None, None) == -1
