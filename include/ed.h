@@ -264,6 +264,40 @@ ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, doub
                      size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
+ * Liouville space (Sec. VI.B, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket, App. F). The density
+ * matrix rho (D x D, D = 2^L) of the Lindblad equation (Eq. ed:eq:lindbladme)
+ *   d rho/dt = -i [H, rho] + sum_nu (L_nu rho L_nu^dagger - 1/2 {L_nu^dagger L_nu, rho}),
+ * with L_nu = sqrt(rates[z][k-1]) J_z on site k, is stored as the superket |rho>> of D^2 entries,
+ * row-major: entry j D + k is rho_jk (the row index is the high L bits). A D x D operator product
+ * A rho B becomes (A (x) B^T)|rho>>.
+ *
+ * ed_liouville_create: a model of 2L bits for i Lcal, where d|rho>>/dt = Lcal |rho>>:
+ *   i Lcal = H_eff (x) 1 - 1 (x) H_eff^* + i sum_nu L_nu (x) L_nu^*,
+ *   H_eff = H - (i/2) sum_nu L_nu^dagger L_nu.
+ * Then ed_apply_H(model, rho, out) gives out = i Lcal |rho>>, and ed_krylov_evolve with
+ * hermitian = 0 (Arnoldi, reorth = 1) propagates |rho(t + dt)>> = exp(dt Lcal)|rho(t)>>; its
+ * observables are then those of rho: sz [n_steps+1][L] = tr(sigma^z_k rho)/tr(rho) and norm =
+ * tr(rho) (energy is not available). Lanczos, Trotter, trajectories and the adjoint return
+ * ED_ERR_UNSUPPORTED for such a model.
+ * H         host descriptor of a Hermitian H on L sites (no InfiniteFunc rules), 2 <= L <= 15.
+ * jump_op   host [n_jump][2][2] complex row-major (J_z); rates host [n_jump][L] (>= 0).
+ * The local part (H_eff on the row bits, -H_eff^* on the column bits) runs in the streaming passes
+ * of H psi; the jump sandwiches L_nu (x) L_nu^* couple row and column bits of one site, L bits
+ * apart, and are applied by one gather pass after them.
+ * Errors: ED_ERR_ARG, ED_ERR_NUMERIC, ED_ERR_UNSUPPORTED (L > 15, InfiniteFunc rules), ED_ERR_HIP.
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_liouville_create(const ed_model_desc* H, int n_jump, const ed_c64* jump_op, const double* rates,
+                              ed_model** out);
+/* L of the system whose superket the model acts on (0 for a Hamiltonian model). */
+ed_status ed_model_liouville_sites(const ed_model* model, int* L);
+
+/* ed_liouville_measure: tr(rho) and <sigma^z_k> = tr(sigma^z_k rho)/tr(rho), k = 1..L, of a
+ * superket rho (device, 4^L entries); sz host [L], trace host (may be NULL). Synchronises stream.
+ * Workspace: ed_measure_workspace bytes (any L). */
+ed_status ed_liouville_measure(const ed_c64* rho, int L, double* sz, double* trace, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* ----------------------------------------------------------------------------------------
  * ed_rdm: every single-site and every two-site reduced density matrix of a pure state (Sec. IV:
  * rho of the kept sites is the sum over the traced sites of psi psi^*, the kept legs in front,
  * e.g. rho_1 = [[sum A A^*, sum A B^*], [sum B A^*, sum B B^*]] for psi = [A][B]). Not normalised:

@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import EdError, call, lib
 
-__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "rdm", "rdm_plan", "trace_distances", "eps_local", "eps_corr", "trajectories", "philox_words", "evolve_adjoint", "evolve_loss", "AdjointEvolve", "EdError", "lib"]
+__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "Liouville", "superket", "liouville_measure", "rdm", "rdm_plan", "trace_distances", "eps_local", "eps_corr", "trajectories", "philox_words", "evolve_adjoint", "evolve_loss", "AdjointEvolve", "EdError", "lib"]
 
 
 def _stream_ptr(stream=None):
@@ -115,6 +115,55 @@ class Model:
             pass
 
 
+class Liouville(Model):
+    """Handle on the Liouvillian of a Lindblad equation (ed_liouville_create): a model of 2L bits
+    whose apply_H gives i Lcal |rho>> for the row-major superket |rho>> (entry j 2^L + k = rho_jk),
+    and whose krylov_evolve (Arnoldi) propagates exp(dt Lcal). desc: the Hermitian H on L sites;
+    jump_ops: list of 2x2 operators J_z; rates: [n_jump, L] array of gamma (L_nu = sqrt(gamma) J on
+    site k). `sites` is L; `L` is the superket's bit count 2L."""
+
+    def __init__(self, desc, jump_ops, rates):
+        self.sites = int(desc.L)
+        Ls = self.sites
+        self._keep = [np.ascontiguousarray(desc.site_ops, np.complex128),
+                      np.ascontiguousarray(desc.site_coef, np.float64),
+                      np.ascontiguousarray(desc.bond_ops, np.complex128),
+                      np.ascontiguousarray(desc.bond_coef, np.float64),
+                      np.ascontiguousarray(np.asarray(jump_ops, np.complex128).reshape(-1, 2, 2)),
+                      np.ascontiguousarray(np.asarray(rates, np.float64).reshape(-1, Ls))]
+        so, sc, bo, bc, jo, rt = self._keep
+        if len(jo) != len(rt):
+            raise ValueError("one rate row per jump operator")
+        d = _lib.ModelDescC(Ls, 2, len(so), so.ctypes.data, sc.ctypes.data, len(bo), bo.ctypes.data, bc.ctypes.data,
+                            0, None, None, None, None)
+        h = C.c_void_p()
+        call("ed_liouville_create", C.byref(d), len(jo), jo.ctypes.data if len(jo) else None,
+             rt.ctypes.data if len(jo) else None, C.byref(h))
+        self._h = h
+        self.L = 2 * Ls
+        self.D = 1 << self.L
+
+
+def superket(rho):
+    """|rho>> of a [D, D] density matrix (tensor or array): the row-major flattening."""
+    if not hasattr(rho, "reshape"):
+        rho = np.asarray(rho)
+    return rho.reshape(-1)
+
+
+def liouville_measure(rho, L, stream=None):
+    """(sz[L] = tr(sigma^z_k rho)/tr(rho), tr(rho)) of a device superket (ed_liouville_measure)."""
+    _check_state(rho, 1 << (2 * L), "rho")
+    nb = C.c_size_t()
+    call("ed_measure_workspace", int(L), C.byref(nb))
+    ws = _workspace(nb.value, rho.device)
+    sz = np.zeros(L)
+    tr = C.c_double()
+    call("ed_liouville_measure", _dptr(rho), int(L), sz.ctypes.data, C.byref(tr), _dptr(ws), nb.value,
+         _stream_ptr(stream))
+    return sz, tr.value
+
+
 def apply_H(model, psi, out=None, stream=None):
     """out = H psi (asynchronous on the current torch stream)."""
     _check_state(psi, model.D)
@@ -154,8 +203,24 @@ def lanczos_ground(model, v0, tol=1e-10, max_iter=200, max_basis=None, n_keep=0,
 def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reorth=0, hermitian=True,
                   observe=True, stream=None):
     """Krylov time evolution of psi in place (ed_krylov_evolve). Returns (psi, obs, info) with obs
-    holding numpy arrays sz [(n_steps+1), L], energy [n_steps+1], norm [n_steps+1]."""
+    holding numpy arrays sz [(n_steps+1), L], energy [n_steps+1], norm [n_steps+1]. For a
+    Liouville model (hermitian=False): sz [(n_steps+1), sites] of rho, norm = tr(rho), no energy."""
     _check_state(psi, model.D)
+    if isinstance(model, Liouville):
+        p = _lib.KrylovParams(int(m_max), float(tol), int(fixed_m), 1, 0)
+        if hermitian:
+            raise ValueError("a Liouville model evolves with hermitian=False (Arnoldi)")
+        nb = C.c_size_t()
+        call("ed_krylov_workspace", model.handle, C.byref(p), C.byref(nb))
+        ws = _workspace(nb.value, psi.device)
+        obs, o = None, None
+        if observe:
+            obs = {"sz": np.zeros((n_steps + 1, model.sites)), "norm": np.zeros(n_steps + 1)}
+            o = _lib.Observe(obs["sz"].ctypes.data, None, obs["norm"].ctypes.data)
+        info = _lib.KrylovInfo()
+        call("ed_krylov_evolve", model.handle, _dptr(psi), float(dt), int(n_steps), C.byref(p),
+             C.byref(o) if o is not None else None, C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
+        return psi, obs, {"steps": info.steps, "total_m": info.total_m, "max_m": info.max_m, "max_err": info.max_err}
     p = _lib.KrylovParams(int(m_max), float(tol), int(fixed_m), int(reorth if hermitian else 1), int(bool(hermitian)))
     nb = C.c_size_t()
     call("ed_krylov_workspace", model.handle, C.byref(p), C.byref(nb))

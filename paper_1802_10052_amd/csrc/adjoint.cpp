@@ -236,6 +236,7 @@ size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 ed_status check_params(const ed_model* tmpl, int S, double Delta, const double* J, const ed_c64* psi0, const double* w,
                        const ed_adjoint_params* p) {
     if (tmpl && tmpl->lr) return fail(ED_ERR_UNSUPPORTED, "the adjoint does not take long-range (InfiniteFunc) terms");
+    if (tmpl && tmpl->lv_L > 0) return fail(ED_ERR_UNSUPPORTED, "the adjoint does not take Liouvillian models");
     if (!tmpl || !J || !psi0 || !w || !p) return fail(ED_ERR_ARG, "null argument");
     if (S < 1 || !(Delta > 0.0)) return fail(ED_ERR_ARG, "n_slices >= 1 and slice_len > 0 required");
     if (tmpl->L > 24) return fail(ED_ERR_UNSUPPORTED, "the adjoint path supports L <= 24");

@@ -139,6 +139,7 @@ hipError_t dispatch(const ed_model* m, const double2* psi, double2* out, hipStre
 ed_status launch_apply_H(const ed_model* m, const double2* psi, double2* out, hipStream_t s) {
     hipError_t e = dispatch<0>(m, psi, out, s);
     if (e != hipSuccess) return fail(ED_ERR_HIP, std::string("apply_H launch: ") + hipGetErrorString(e));
+    if (!m->far.empty()) return launch_far_terms(m, psi, out, s);
     return ED_OK;
 }
 

@@ -86,6 +86,18 @@ enum OpClass : unsigned {
 
 // Device-side coefficient tables of a model. All indices are by BIT position p (site at bit p is
 // site k = L - p; the bond at bit p couples bits p and p+1, i.e. sites L-p-1 and L-p).
+namespace ed {
+// A two-site operator on the bit pair (p, q), q > p, at any distance: K[4 r + c] is the entry of
+// row r = 2 bit(q) + bit(p) and column c; bit 4 r + c of mask is set where K is nonzero. Applied by
+// a gather pass after the streaming passes of H psi (the jump terms of a Liouvillian).
+struct FarTerm {
+    int p, q;
+    uint32_t mask;
+    int pad;
+    double2 K[16];
+};
+}  // namespace ed
+
 struct ed_model {
     int L = 0;
     int device = 0;
@@ -116,9 +128,19 @@ struct ed_model {
     std::vector<ed::GatherJob> jobs;
     int njobs[ed::kMaxPlans][ed::kMaxPasses] = {};
     ed::GatherJob* d_jobs = nullptr;
+    // Liouvillian models (ed_liouville_create): L = 2 lv_L bits of a superket, far terms = jump
+    // sandwiches; 0 / empty for Hamiltonians
+    int lv_L = 0;
+    std::vector<ed::FarTerm> far;
+    ed::FarTerm* d_far = nullptr;
 };
 
 namespace ed {
-// Launch the passes of out = H psi (apply_h.hip).
+// Launch the passes of out = H psi (apply_h.hip), then the far terms if the model has any.
 ed_status launch_apply_H(const ed_model* m, const double2* psi, double2* out, hipStream_t s);
+// out += sum of the far terms applied to psi (liouville.hip)
+ed_status launch_far_terms(const ed_model* m, const double2* psi, double2* out, hipStream_t s);
+// trace and sum_j rho_jj z_k(j), k = 1..Ls (site order), of a superket of an Ls-site system,
+// into res[0] and res[1..Ls] (device, real parts) (liouville.hip)
+ed_status superket_diag(const double2* rho, int Ls, double2* res, hipStream_t s);
 }  // namespace ed

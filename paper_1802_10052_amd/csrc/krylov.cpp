@@ -167,6 +167,7 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
     if (!model || !v0 || !p || !E0 || !psi0) return fail(ED_ERR_ARG, "null argument");
     if (p->max_iter < 1) return fail(ED_ERR_ARG, "max_iter must be >= 1");
     if (!(p->tol > 0.0)) return fail(ED_ERR_ARG, "tol must be > 0");
+    if (model->lv_L > 0) return fail(ED_ERR_UNSUPPORTED, "Lanczos needs a Hermitian model, not a Liouvillian");
     size_t need = 0;
     ED_TRY(ed_lanczos_workspace(model, p, &need));
     const int mb = p->max_basis;
@@ -313,6 +314,18 @@ ed_status measure_state(const double2* psi, int L, const Workspace& w, double* s
     return ED_OK;
 }
 
+// tr(rho) and tr(sigma^z_k rho)/tr(rho) of a superket of an Ls-site system
+ed_status measure_superket(const double2* rho, int Ls, const Workspace& w, double* sz, double* tr, hipStream_t s) {
+    double2* res = w.scal + kObs;
+    ED_TRY(superket_diag(rho, Ls, res, s));
+    double2 hv[32];
+    ED_TRY(fetch_scalars(res, Ls + 1, hv, s));
+    if (tr) *tr = hv[0].x;
+    if (sz)
+        for (int k = 1; k <= Ls; ++k) sz[k - 1] = hv[k].x / hv[0].x;
+    return ED_OK;
+}
+
 // One Krylov time step of psi in place: returns the dimension used, the error estimate and
 // alpha_0 = <v_0|H v_0> (the energy of the incoming state).
 ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, double dt,
@@ -398,6 +411,9 @@ extern "C" ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double
     if (!std::isfinite(dt)) return fail(ED_ERR_ARG, "dt must be finite");
     if (!(p->tol > 0.0) && p->fixed_m <= 0) return fail(ED_ERR_ARG, "tol must be > 0");
     if (!p->hermitian && !p->reorth) return fail(ED_ERR_ARG, "Arnoldi (hermitian = 0) needs reorth = 1");
+    const int lvL = model->lv_L;
+    if (lvL > 0 && p->hermitian) return fail(ED_ERR_ARG, "a Liouvillian model needs hermitian = 0 (Arnoldi)");
+    if (lvL > 0 && obs && obs->energy) return fail(ED_ERR_UNSUPPORTED, "no energy observable for a Liouvillian model");
     size_t need = 0;
     ED_TRY(ed_krylov_workspace(model, p, &need));
     if (ws_bytes < need) return fail(ED_ERR_WORKSPACE, "workspace too small");
@@ -412,6 +428,12 @@ extern "C" ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double
     const bool want_e = obs && obs->energy;
     auto record = [&](int step) -> ed_status {
         if (!obs || (!obs->sz && !obs->norm)) return ED_OK;
+        if (lvL > 0) {  // observables of rho: tr(sigma^z_k rho)/tr(rho) and tr(rho)
+            double tr = 0.0;
+            ED_TRY(measure_superket(v, lvL, w, obs->sz ? obs->sz + size_t(step) * lvL : nullptr, &tr, s));
+            if (obs->norm) obs->norm[step] = tr;
+            return ED_OK;
+        }
         double nrm = 0.0;
         ED_TRY(measure_state(v, L, w, obs->sz ? obs->sz + size_t(step) * L : nullptr, &nrm, s));
         if (obs->norm) obs->norm[step] = nrm;
@@ -448,6 +470,14 @@ extern "C" ed_status ed_measure_workspace(int L, size_t* bytes) {
     if (!bytes || L < 1 || L > 30) return fail(ED_ERR_ARG, "bad argument");
     *bytes = core_scratch_bytes();
     return ED_OK;
+}
+
+extern "C" ed_status ed_liouville_measure(const ed_c64* rho, int L, double* sz, double* trace, void* ws,
+                                          size_t ws_bytes, void* stream) {
+    if (!rho || !sz || L < 1 || L > 15) return fail(ED_ERR_ARG, "bad argument (rho or sz null, L outside 1..15)");
+    Workspace w;
+    ED_TRY(carve(ws, ws_bytes, int64_t(1) << (2 * L), 0, &w));
+    return measure_superket(reinterpret_cast<const double2*>(rho), L, w, sz, trace, static_cast<hipStream_t>(stream));
 }
 
 extern "C" ed_status ed_measure(const ed_c64* psi, int L, double* sz, double* norm, void* ws, size_t ws_bytes,

@@ -327,6 +327,8 @@ static void free_tables(ed_model* m) {
     }
     if (m->d_jobs) (void)hipFree(m->d_jobs);
     m->d_jobs = nullptr;
+    if (m->d_far) (void)hipFree(m->d_far);
+    m->d_far = nullptr;
 }
 
 // long-range zz energy of the pairs p < q with both bits in [lo, hi), evaluated at index x
@@ -542,6 +544,127 @@ ed_status create_model(const ed_model_desc* desc, ed_model** out) {
     return ED_OK;
 }
 
+void destroy_model(ed_model* m);
+
+// The Liouvillian of H (Hermitian, no InfiniteFunc rules) with jump operators J_nu on every site
+// at rates gamma_nu[k], as a model on the 2L-bit superket: i Lcal = H_eff (x) 1 - 1 (x) H_eff^*
+// + i sum gamma J (x) J^* (see liouville.hip). Doubled chain: sites 1..L are the row digits
+// (bits 2L-1 .. L), sites L+1..2L the column digits (bits L-1 .. 0).
+ed_status create_liouville(const ed_model_desc* H, int n_jump, const ed_c64* jump_op, const double* rates,
+                           ed_model** out) {
+    ED_TRY(validate_desc(H));
+    const int L = H->L;
+    if (2 * L > 30) return fail(ED_ERR_UNSUPPORTED, "the superket of L sites has 2L bits: L <= 15");
+    if (H->n_inf > 0) return fail(ED_ERR_UNSUPPORTED, "Liouvillians do not take InfiniteFunc rules");
+    if (n_jump < 0) return fail(ED_ERR_ARG, "n_jump must be >= 0");
+    if (n_jump > 0 && (!jump_op || !rates)) return fail(ED_ERR_ARG, "jump_op/rates is null with n_jump > 0");
+    for (int z = 0; z < n_jump; ++z) {
+        for (int e = 0; e < 4; ++e)
+            if (!std::isfinite(jump_op[4 * z + e].re) || !std::isfinite(jump_op[4 * z + e].im))
+                return fail(ED_ERR_NUMERIC, "non-finite jump_op");
+        for (int k = 0; k < L; ++k)
+            if (!std::isfinite(rates[size_t(z) * L + k]) || rates[size_t(z) * L + k] < 0.0)
+                return fail(ED_ERR_ARG, "rates must be finite and >= 0");
+    }
+    const int L2 = 2 * L;
+    auto c64 = [](cplx v) { return ed_c64{v.real(), v.imag()}; };
+    auto cx = [](const ed_c64& v) { return cplx(v.re, v.im); };
+    std::vector<ed_c64> sop;
+    std::vector<double> scoef;
+    std::vector<ed_c64> bop;
+    std::vector<double> bcoef;
+    // site rules: O on the row digits, -O^* on the column digits
+    for (int z = 0; z < H->n_site; ++z) {
+        for (int half = 0; half < 2; ++half) {
+            for (int e = 0; e < 4; ++e) {
+                const cplx o = cx(H->site_op[4 * z + e]);
+                sop.push_back(c64(half == 0 ? o : -std::conj(o)));
+            }
+            for (int k = 0; k < L2; ++k) scoef.push_back((k < L) == (half == 0) ? H->site_coef[size_t(z) * L + (k % L)] : 0.0);
+        }
+    }
+    // -(i/2) gamma J^dagger J in H_eff: on the rows as is, on the columns -(its conjugate)
+    for (int z = 0; z < n_jump; ++z) {
+        cplx J[2][2], JdJ[2][2];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) J[a][b] = cx(jump_op[4 * z + 2 * a + b]);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) JdJ[a][b] = std::conj(J[0][a]) * J[0][b] + std::conj(J[1][a]) * J[1][b];
+        for (int half = 0; half < 2; ++half) {
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const cplx o = cplx(0.0, -0.5) * JdJ[a][b];
+                    sop.push_back(c64(half == 0 ? o : -std::conj(o)));
+                }
+            for (int k = 0; k < L2; ++k) scoef.push_back((k < L) == (half == 0) ? rates[size_t(z) * L + (k % L)] : 0.0);
+        }
+    }
+    // bond rules: B on the row bonds, -B^* on the column bonds, nothing on the middle bond
+    for (int z = 0; z < H->n_bond; ++z) {
+        for (int half = 0; half < 2; ++half) {
+            for (int e = 0; e < 16; ++e) {
+                const cplx o = cx(H->bond_op[16 * z + e]);
+                bop.push_back(c64(half == 0 ? o : -std::conj(o)));
+            }
+            for (int k = 0; k < L2 - 1; ++k) {
+                double c = 0.0;
+                if (half == 0 && k < L - 1) c = H->bond_coef[size_t(z) * (L - 1) + k];
+                if (half == 1 && k >= L) c = H->bond_coef[size_t(z) * (L - 1) + (k - L)];
+                bcoef.push_back(c);
+            }
+        }
+    }
+    ed_model_desc d{};
+    d.L = L2;
+    d.d = 2;
+    d.n_site = int(scoef.size()) / L2;
+    d.site_op = sop.data();
+    d.site_coef = scoef.data();
+    d.n_bond = int(bcoef.size()) / (L2 - 1);
+    d.bond_op = bop.data();
+    d.bond_coef = bcoef.data();
+    d.n_inf = 0;
+    ed_model* m = nullptr;
+    ED_TRY(create_model(&d, &m));
+    m->lv_L = L;
+    // jump sandwiches i gamma J (x) J^*, row bit q = 2L - k, column bit p = L - k of site k
+    for (int k = 1; k <= L; ++k) {
+        FarTerm ft{};
+        ft.p = L - k;
+        ft.q = L2 - k;
+        bool any = false;
+        for (int z = 0; z < n_jump; ++z) {
+            const double g = rates[size_t(z) * L + (k - 1)];
+            if (g == 0.0) continue;
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    const cplx Ja = cx(jump_op[4 * z + 2 * (r >> 1) + (c >> 1)]);
+                    const cplx Jb = cx(jump_op[4 * z + 2 * (r & 1) + (c & 1)]);
+                    const cplx v = cplx(0.0, g) * Ja * std::conj(Jb);
+                    ft.K[4 * r + c].x += v.real();
+                    ft.K[4 * r + c].y += v.imag();
+                }
+        }
+        for (int e = 0; e < 16; ++e)
+            if (ft.K[e].x != 0.0 || ft.K[e].y != 0.0) {
+                ft.mask |= 1u << e;
+                any = true;
+            }
+        if (any) m->far.push_back(ft);
+    }
+    if (!m->far.empty()) {
+        const size_t bytes = m->far.size() * sizeof(FarTerm);
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&m->d_far), bytes);
+        if (e == hipSuccess) e = hipMemcpy(m->d_far, m->far.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            destroy_model(m);
+            return fail(ED_ERR_HIP, std::string("far-term upload: ") + hipGetErrorString(e));
+        }
+    }
+    *out = m;
+    return ED_OK;
+}
+
 void destroy_model(ed_model* m) {
     if (!m) return;
     int cur = 0;
@@ -564,6 +687,19 @@ ed_status ed_model_create(const ed_model_desc* desc, ed_model** out) {
     if (!out) return ed::fail(ED_ERR_ARG, "out is null");
     *out = nullptr;
     return ed::create_model(desc, out);
+}
+
+ed_status ed_liouville_create(const ed_model_desc* H, int n_jump, const ed_c64* jump_op, const double* rates,
+                              ed_model** out) {
+    if (!out) return ed::fail(ED_ERR_ARG, "out is null");
+    *out = nullptr;
+    return ed::create_liouville(H, n_jump, jump_op, rates, out);
+}
+
+ed_status ed_model_liouville_sites(const ed_model* model, int* L) {
+    if (!model || !L) return ed::fail(ED_ERR_ARG, "null argument");
+    *L = model->lv_L;
+    return ED_OK;
 }
 
 ed_status ed_model_destroy(ed_model* model) {

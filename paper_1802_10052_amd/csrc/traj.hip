@@ -710,6 +710,7 @@ static ed_status validate_traj(const ed_traj_desc* d, const ed_traj_params* p) {
         if (!d->models[i] || !d->rates[i] || !d->psi0[i]) return fail(ED_ERR_ARG, "null model entry");
         if (d->models[i]->L > 16) return fail(ED_ERR_UNSUPPORTED, "trajectory chains are limited to L <= 16");
         if (d->models[i]->lr) return fail(ED_ERR_UNSUPPORTED, "trajectories do not take long-range (InfiniteFunc) terms");
+        if (d->models[i]->lv_L > 0) return fail(ED_ERR_UNSUPPORTED, "trajectories take Hamiltonians, not Liouvillians");
     }
     for (int t = 0; t < d->n_traj; ++t)
         if (d->model_of_traj[t] < 0 || d->model_of_traj[t] >= d->n_models) return fail(ED_ERR_ARG, "model_of_traj out of range");

@@ -317,7 +317,7 @@ extern "C" ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, doubl
     using namespace ed;
     if (!model || !psi) return fail(ED_ERR_ARG, "null argument");
     if (order != 2 && order != 4) return fail(ED_ERR_ARG, "order must be 2 or 4");
-    if (model->lr) return fail(ED_ERR_UNSUPPORTED, "the Trotter layers take site and bond rules only");
+    if (model->lr || model->lv_L > 0) return fail(ED_ERR_UNSUPPORTED, "the Trotter layers take site and bond rules only");
     if (n_steps < 0) return fail(ED_ERR_ARG, "n_steps must be >= 0");
     if (!std::isfinite(dt)) return fail(ED_ERR_ARG, "dt must be finite");
     const bool want_e = obs && obs->energy;

@@ -110,3 +110,23 @@ def test_long_range_rule_validation():
     assert b"diagonal" in lib.ed_last_error()
     d.inf_op2 = None
     assert lib.ed_model_create(C.byref(d), C.byref(h)) == -1
+
+
+def test_liouville_create_validation():
+    """ed_liouville_create checks its arguments before touching a device."""
+    lib = C.CDLL(_lib.LIB_PATH)
+    lib.ed_liouville_create.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    sm = np.array([[0, 0], [1, 0]], np.complex128)
+
+    def call(L, rates, n_jump=1, jump=sm):
+        d, keep = _desc(L=L)
+        r = np.ascontiguousarray(rates, np.float64)
+        h = C.c_void_p()
+        return lib.ed_liouville_create(C.byref(d), n_jump, jump.ctypes.data if jump is not None else None,
+                                       r.ctypes.data, C.byref(h))
+    assert call(16, np.full((1, 16), 0.1)) == -2          # the superket would have 32 bits
+    assert call(4, np.array([[0.1, -0.1, 0.1, 0.1]])) == -1
+    assert call(4, np.full((1, 4), np.nan)) == -1
+    assert call(4, np.full((1, 4), 0.1), jump=None) == -1
+    assert call(4, np.full((1, 4), 0.1), n_jump=-1) == -1
+    assert call(4, np.full((1, 4), 0.1)) in (0, -3)       # valid: fails only for want of a device
