@@ -10,7 +10,8 @@ Beside it, each remaining row of the hot path is run once on its synthetic workl
 under "rows": Lanczos ground state (TFIM L = 14), Lanczos + half-chain entropy (XXZ L = 26),
 the L = 28 Krylov quench (100 steps), the same quench with the Suzuki-Trotter propagators of order
 4 and 2, the long-range Ising chain H_LRQI at L = 28 (H psi and a Krylov quench), 4096 batched
-quantum trajectories against the plain per-trajectory path, and the adjoint gradient (L = 20) against finite differences of the forward-only path. The CPU oracle
+quantum trajectories against the plain per-trajectory path, the reduced density matrices at
+L = 28, the L = 14 Liouville-space evolution (2^28 superket), and the adjoint gradient (L = 20) against finite differences of the forward-only path. The CPU oracle
 is timed on a bounded sample of the headline workload.
 """
 import argparse
@@ -254,6 +255,43 @@ def row_rdm_L28(P, E, torch, dev, reps=3):
             "single_site_passes": int(P.rdm_plan(L, all_pairs=False)[1].max()) + 1}
 
 
+def row_liouville_L14(P, E, torch, dev, reps=5, steps=10):
+    """Liouville-space evolution (Sec. VI.B) of the dissipative XXZ chain of the trajectory row
+    (J = 1, Delta = 1, gamma = 0.1 sigma^- on every site) at L = 14: the density matrix as a 2^28
+    superket (4 GiB). Reported: one product i Lcal |rho>> (the tuned streaming passes of the local
+    part plus the jump gather pass; GB/s on the headline's 32 B per amplitude), and Arnoldi time
+    steps from the Neel state with the exact decay identity sum_k <sigma^z_k>(t) = L (e^{-gamma t} - 1)
+    and the trace as checks."""
+    import numpy as np
+    L, gamma, dt = 14, 0.1, 0.05
+    sm = np.array([[0, 0], [1, 0]], np.complex128)
+    m = P.Liouville(E.xxz(L, 1.0, 1.0), [sm], np.full((1, L), gamma))
+    D2 = 1 << (2 * L)
+    x = E.random_state_device(2 * L, 3, dev)
+    out = torch.empty_like(x)
+    best, _ = m.tune(x, out, reps=2)
+    P.apply_H(m, x, out)
+    with Timer(torch, None) as t:
+        for _ in range(reps):
+            P.apply_H(m, x, out)
+    ms = 1e3 * t.s / reps
+    del x, out
+    torch.cuda.empty_cache()
+    rho = torch.zeros(D2, dtype=torch.complex128, device=dev)
+    n = E.neel_index(L)
+    rho[n * (1 << L) + n] = 1.0
+    with Timer(torch, None) as te:
+        _, obs, info = P.krylov_evolve(m, rho, dt, steps, m_max=30, tol=1e-10, hermitian=False)
+    tt = dt * np.arange(steps + 1)
+    ident = float(np.abs(obs["sz"].sum(axis=1) - L * (np.exp(-gamma * tt) - 1)).max())
+    return {"workload": f"dissipative XXZ (Delta=1, gamma=0.1 sigma^-) L=14 as a 2^28 superket: i Lcal |rho>> "
+                        f"({reps} products) and {steps} Arnoldi steps of dt={dt} from the Neel state (m<=30, tol 1e-10)",
+            "apply_ms": round(ms, 3), "apply_GBps": round(32.0 * D2 / (ms * 1e-3) / 1e9, 1),
+            "plan": m.describe_plan(best), "evolve_seconds": round(te.s, 3),
+            "ms_per_step": round(1e3 * te.s / steps, 1), "total_krylov": info["total_m"], "max_m": info["max_m"],
+            "decay_identity_max_err": ident, "trace_drift": float(np.abs(obs["norm"] - 1).max())}
+
+
 def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):
     import numpy as np
     lengths = [8, 10, 12, 14, 16]
@@ -357,7 +395,7 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="use the H psi plan with this description (ed_model_plan_describe) instead of tuning")
     ap.add_argument("--rows", default="all",
-                    help="comma list of lanczos14,lanczos26,quench28,trotter28,lrqi28,rdm28,traj,adjoint (the 'all' set) and traj16 "
+                    help="comma list of lanczos14,lanczos26,quench28,trotter28,lrqi28,rdm28,liouville14,traj,adjoint (the 'all' set) and traj16 "
                          "(the L=16 trajectory slice, for profiling); 'none' or 'all'")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -436,8 +474,9 @@ def main():
     torch.cuda.empty_cache()
     rows = {"lanczos14": row_lanczos_L14, "lanczos26": row_lanczos_entropy_L26, "quench28": row_quench_L28,
             "traj": row_trajectories, "adjoint": row_adjoint, "traj16": row_trajectories_L16,
-            "trotter28": row_trotter_L28, "lrqi28": row_lrqi_L28, "rdm28": row_rdm_L28}
-    default_rows = ["lanczos14", "lanczos26", "quench28", "trotter28", "lrqi28", "rdm28", "traj", "adjoint"]
+            "trotter28": row_trotter_L28, "lrqi28": row_lrqi_L28, "rdm28": row_rdm_L28, "liouville14": row_liouville_L14}
+    default_rows = ["lanczos14", "lanczos26", "quench28", "trotter28", "lrqi28", "rdm28", "liouville14", "traj",
+                    "adjoint"]
     pick = default_rows if args.rows == "all" else ([] if args.rows == "none" else args.rows.split(","))
     rec["rows"] = {}
     for name in pick:
