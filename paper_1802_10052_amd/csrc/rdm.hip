@@ -418,8 +418,8 @@ size_t hist_bytes() { return (size_t(kRdmMaxBlocks) + 1) * (size_t(1) << kTileBi
 int rdm_blocks(int64_t ntiles) {
     int dev = 0, cu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t pr;
-        if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cu = pr.multiProcessorCount;
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cu = v;
     }
     return int(std::min<int64_t>({ntiles, int64_t(cu), int64_t(kRdmMaxBlocks)}));
 }

@@ -148,6 +148,22 @@ def test_krylov_invariants_L26():
     assert np.allclose(obs["sz"], obs["sz"][:, ::-1], atol=1e-10)
 
 
+def test_krylov_invariants_L28():
+    """The quench of the benchmark at its full size and launch configuration (L = 28, g = 0.5,
+    dt = 0.05, m <= 20, tol 1e-10), 3 steps: exact start energy, norm and energy conservation,
+    reflection symmetry of <sigma^z_k>."""
+    L = 28
+    print("krylov invariants L=28", flush=True)
+    m = P.Model(E.tfim(L, 0.5))
+    g = torch.zeros(1 << L, dtype=torch.complex128, device=DEV)
+    g[0] = 1.0
+    _, obs, info = P.krylov_evolve(m, g, 0.05, 3, m_max=20, tol=1e-10)
+    assert obs["energy"][0] == -(L - 1)
+    assert np.max(np.abs(obs["energy"] + (L - 1))) < 1e-9 * L
+    assert np.max(np.abs(obs["norm"] - 1)) < 1e-10
+    assert np.allclose(obs["sz"], obs["sz"][:, ::-1], atol=1e-10)
+
+
 def test_error_paths_from_the_host():
     """Failure handling forced from the host: a non-finite state is reported as ED_ERR_NUMERIC,
     a short workspace as ED_ERR_WORKSPACE, overlapping buffers as ED_ERR_ARG."""

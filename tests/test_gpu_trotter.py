@@ -81,6 +81,25 @@ def test_trotter_exact_precession_L26(order):
     assert np.max(np.abs(obs["norm"] - 1.0)) < 1e-12
 
 
+@pytest.mark.parametrize("order", [2, 4])
+def test_trotter_L28_against_krylov(order):
+    """The benchmark's L = 28 quench (TFIM g = 0.5 from all up, dt = 0.05) for 3 steps: Trotter
+    keeps the norm and the reflection symmetry of <sigma^z_k>, and stays within its splitting
+    error of the Krylov states (order 4: 1e-7, order 2: 1e-4 in <sigma^z_k>)."""
+    L, dt, steps = 28, 0.05, 3
+    print(f"trotter vs krylov L=28 order={order}", flush=True)
+    m = P.Model(E.tfim(L, 0.5))
+    psi = torch.zeros(1 << L, dtype=torch.complex128, device=DEV)
+    psi[0] = 1.0
+    _, obs = P.trotter_evolve(m, psi, dt, steps, order=order)
+    psi[:] = 0
+    psi[0] = 1.0
+    _, kobs, _ = P.krylov_evolve(m, psi, dt, steps, m_max=20, tol=1e-10)
+    assert np.max(np.abs(obs["norm"] - 1.0)) < 1e-12
+    assert np.allclose(obs["sz"], obs["sz"][:, ::-1], atol=1e-12)
+    assert np.max(np.abs(obs["sz"] - kobs["sz"])) < (1e-7 if order == 4 else 1e-4)
+
+
 def test_trotter_unitary_L26():
     L = 26
     print(f"trotter unitarity L={L}", flush=True)
