@@ -6,13 +6,18 @@ algorithmic GB/s = 32 B per amplitude (read psi once, write H psi once) / time p
 and as a fraction of the 8 TB/s HBM peak. A step is one H psi over the whole state; the state
 is resident in HBM and the time comes from HIP events on the stream the library launches on.
 
+The JSON line also carries the bytes the counters saw per H psi over the same time and the rate of
+a plain 4 GiB device copy on the box ("hbm_measured").
+
 Beside it, each remaining row of the hot path is run once on its synthetic workload and reported
-under "rows": Lanczos ground state (TFIM L = 14), Lanczos + half-chain entropy (XXZ L = 26),
+under "rows": an H psi sweep over L = 20..28 (TFIM and XXZ), Lanczos ground state (TFIM L = 14,
+with the oracle's textbook Lanczos timed beside it), Lanczos + half-chain entropy (XXZ L = 26),
 the L = 28 Krylov quench (100 steps), the same quench with the Suzuki-Trotter propagators of order
 4 and 2, the long-range Ising chain H_LRQI at L = 28 (H psi and a Krylov quench), 4096 batched
 quantum trajectories against the plain per-trajectory path, the reduced density matrices at
-L = 28, the L = 14 Liouville-space evolution (2^28 superket), and the adjoint gradient (L = 20) against finite differences of the forward-only path. The CPU oracle
-is timed on a bounded sample of the headline workload.
+L = 28, the L = 14 Liouville-space evolution (2^28 superket), and the adjoint gradient (L = 20)
+against finite differences of the forward-only path. The CPU oracle is timed on a bounded sample
+of the headline workload (its CSR product at L = 22 for about 10 s).
 """
 import argparse
 import json
@@ -70,20 +75,24 @@ def measured_traffic(plan_desc):
         return None
 
 
-def cpu_baseline(L=20, reps=60):
-    """The oracle's explicit sparse H psi (scipy CSR matvec, single-threaded) at L = 20."""
+def cpu_baseline(L=22, budget_s=10.0, max_reps=200):
+    """The oracle's explicit sparse H psi (scipy CSR matvec, single-threaded) at L = 22, repeated
+    for about budget_s seconds (the CSR build is not timed)."""
     import edinputs as E
     from oracle import hamiltonian as OH
     H = OH.hamiltonian_sparse(E.tfim(L, 0.5))
     psi = E.random_state(L, 11)
     H @ psi
+    reps = 0
     t0 = time.perf_counter()
-    for _ in range(reps):
+    while reps < max_reps and (reps == 0 or time.perf_counter() - t0 < budget_s):
         H @ psi
+        reps += 1
     dt = (time.perf_counter() - t0) / reps
     return {"value": round(32.0 * (1 << L) / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"scipy CSR H psi (oracle), TFIM g=0.5 L={L} (2^{L} amplitudes), {reps} products of "
-                      f"{dt * 1e3:.1f} ms; same 32 B/amplitude accounting as the headline"}
+            "sample": f"scipy CSR H psi (oracle, {H.nnz} nonzeros), TFIM g=0.5 L={L} (2^{L} amplitudes), {reps} "
+                      f"products of {dt * 1e3:.1f} ms ({reps * dt:.1f} s); same 32 B/amplitude accounting as the "
+                      f"headline; the L=28 product would need a ~190 GB CSR matrix"}
 
 
 class Timer:
@@ -100,6 +109,28 @@ class Timer:
         self.s = time.perf_counter() - self.t0
 
 
+def row_hpsi_sweep(P, E, torch, dev, reps=10):
+    """H psi over L = 20..28 for the transverse-field Ising chain (g = 0.5) and the XXZ chain
+    (Delta = 0.5, h ~ U[-0.5, 0.5]): tuned plan, passes, ms per product and algorithmic GB/s."""
+    out = {"workload": "apply_H, TFIM g=0.5 and XXZ Delta=0.5 h~U[-0.5,0.5], L=20..28, tuned plans"}
+    for L in (20, 22, 24, 26, 28):
+        for name, desc in (("tfim", E.tfim(L, 0.5)), ("xxz", E.xxz(L, 1.0, 0.5, E.random_fields(L, 2)))):
+            m = P.Model(desc)
+            psi = E.random_state_device(L, 11, dev)
+            o = torch.empty_like(psi)
+            best, _ = m.tune(psi, o, reps=2)
+            P.apply_H(m, psi, o)
+            with Timer(torch, None) as t:
+                for _ in range(reps):
+                    P.apply_H(m, psi, o)
+            ms = 1e3 * t.s / reps
+            out[f"{name}{L}"] = {"ms": round(ms, 4), "GBps": round(32.0 * (1 << L) / (ms * 1e-3) / 1e9, 1),
+                                 "passes": m.passes, "plan": m.describe_plan(best)}
+            del psi, o, m
+            torch.cuda.empty_cache()
+    return out
+
+
 def row_lanczos_L14(P, E, torch, dev):
     from tests import closed_forms as CF
     L = 14
@@ -109,9 +140,18 @@ def row_lanczos_L14(P, E, torch, dev):
     with Timer(torch, None) as t:
         e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=200)
     ref = CF.tfim_bdg_ground_energy(L, 1.0, 1.0)
+    # the oracle beside it: textbook Lanczos on the explicit CSR matrix (one core for the matvecs)
+    import edinputs
+    from oracle import hamiltonian as OH
+    from oracle import lanczos as OL
+    H = OH.hamiltonian_sparse(edinputs.tfim(L, 1.0))
+    t0 = time.perf_counter()
+    e_or = OL.lanczos_ground(lambda v: H @ v, edinputs.random_state(L, 1), tol=1e-10, max_iter=200)[0]
+    t_or = time.perf_counter() - t0
     return {"workload": "TFIM g=1 L=14 Lanczos, full reorthogonalisation, tol 1e-10", "seconds": round(t.s, 4),
             "iters": info["iters"], "E0": e0, "rel_err_vs_free_fermion": abs(e0 - ref) / abs(ref),
-            "residual": info["residual"]}
+            "residual": info["residual"], "oracle_seconds": round(t_or, 3),
+            "oracle_E0_rel_diff": abs(e_or - e0) / abs(e0)}
 
 
 def row_lanczos_entropy_L26(P, E, torch, dev):
@@ -395,7 +435,7 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="use the H psi plan with this description (ed_model_plan_describe) instead of tuning")
     ap.add_argument("--rows", default="all",
-                    help="comma list of lanczos14,lanczos26,quench28,trotter28,lrqi28,rdm28,liouville14,traj,adjoint (the 'all' set) and traj16 "
+                    help="comma list of hpsi_sweep,lanczos14,lanczos26,quench28,trotter28,lrqi28,rdm28,liouville14,traj,adjoint (the 'all' set) and traj16 "
                          "(the L=16 trajectory slice, for profiling); 'none' or 'all'")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -414,6 +454,17 @@ def main():
     psi = E.random_state_device(L, 11, dev)
     out = torch.empty_like(psi)
     stream = torch.cuda.current_stream()
+    # the practical HBM rate on this machine: a plain device copy of the state (reads and writes 4 GiB)
+    out.copy_(psi)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        out.copy_(psi)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 5
+    copy_gbs = 32.0 * D / (copy_ms * 1e-3) / 1e9
     if args.copy_calibration:
         out.copy_(psi)
         torch.cuda.synchronize()
@@ -446,6 +497,7 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / args.steps
     gbs = 32.0 * D / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(model.describe_plan(best)) if L == 28 else None
     rec = {
         "metric": "H·ψ GB/s (% HBM peak) at L=28",
         "value": round(gbs, 2),
@@ -465,8 +517,11 @@ def main():
                    "plan": best, "plan_desc": model.describe_plan(best),
                    "plan_ms": [round(t, 4) for t in plan_ms]},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(gbs / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(model.describe_plan(best)) if L == 28 else None},
+                     "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic},
+        # bytes actually moved (rocprofv3 counters of the same plan) per time, and a plain copy
+        "hbm_measured": {"GBps": round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
+                         "frac": round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if traffic else None,
+                         "copy_GBps": round(copy_gbs, 1), "copy_frac": round(copy_gbs / PEAK_HBM_GBS, 4)},
         "host": host_info(),
         "wall_s": round(wall, 3),
     }
@@ -474,8 +529,9 @@ def main():
     torch.cuda.empty_cache()
     rows = {"lanczos14": row_lanczos_L14, "lanczos26": row_lanczos_entropy_L26, "quench28": row_quench_L28,
             "traj": row_trajectories, "adjoint": row_adjoint, "traj16": row_trajectories_L16,
-            "trotter28": row_trotter_L28, "lrqi28": row_lrqi_L28, "rdm28": row_rdm_L28, "liouville14": row_liouville_L14}
-    default_rows = ["lanczos14", "lanczos26", "quench28", "trotter28", "lrqi28", "rdm28", "liouville14", "traj",
+            "trotter28": row_trotter_L28, "lrqi28": row_lrqi_L28, "rdm28": row_rdm_L28, "liouville14": row_liouville_L14,
+            "hpsi_sweep": row_hpsi_sweep}
+    default_rows = ["hpsi_sweep", "lanczos14", "lanczos26", "quench28", "trotter28", "lrqi28", "rdm28", "liouville14", "traj",
                     "adjoint"]
     pick = default_rows if args.rows == "all" else ([] if args.rows == "none" else args.rows.split(","))
     rec["rows"] = {}
