@@ -107,9 +107,9 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
 
     // the next tile is loaded into registers while the current one is evaluated from LDS; eight
     // named registers (an array that lives across the evaluation loop is placed in scratch memory)
+    double2 v0, v1, v2, v3, v4, v5, v6, v7;
     // |psi|^2 of each of the thread's tile positions, summed over its tiles (the diagonal of every
     // pair's matrix is a marginal of these)
-    double2 v0, v1, v2, v3, v4, v5, v6, v7;
     double h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0, h6 = 0, h7 = 0;
 #define ED_SLOT(k) (k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : k == 3 ? v3 : k == 4 ? v4 : k == 5 ? v5 : k == 6 ? v6 : v7)
 #define ED_HIST(k) (k == 0 ? h0 : k == 1 ? h1 : k == 2 ? h2 : k == 3 ? h3 : k == 4 ? h4 : k == 5 ? h5 : k == 6 ? h6 : h7)
