@@ -186,18 +186,27 @@ def test_error_paths_from_the_host():
     assert _lib.STATUS[code] == "ED_ERR_ARG"
 
 
-@pytest.mark.parametrize("L", [20, 26])
-def test_lanczos_config2_shape(L):
-    """The config-2 shape (XXZ Delta = 0.5, h ~ U[-0.5, 0.5], max_basis 60 with 10 kept Ritz
-    vectors): converged with an explicit residual below 1e-10; at L = 20 the energy agrees with a
-    run that never restarts."""
-    print(f"lanczos config-2 shape L={L}", flush=True)
+_CONFIG2 = {}
+
+
+@pytest.mark.parametrize("L,basis,keep", [(20, 60, 10), (20, 16, 5), (26, 60, 10), (26, 16, 5)])
+def test_lanczos_config2_shape(L, basis, keep):
+    """The config-2 shape (XXZ Delta = 0.5, h ~ U[-0.5, 0.5]) with at most 60 stored vectors: thick
+    restart with 60 (10 kept Ritz vectors) and with 16 (5 kept; the benchmark's choice): converged
+    with an explicit residual below 1e-10; at L = 20 the energy and the state agree with a run
+    that never restarts, at L = 26 the two restart sizes agree with each other."""
+    print(f"lanczos config-2 shape L={L} basis={basis}", flush=True)
     desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
     m = P.Model(desc)
     v0 = E.random_state_device(L, 3, DEV)
-    e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=60, n_keep=10)
+    e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=basis, n_keep=keep)
     print(f"  E0={e0!r} info={info}", flush=True)
     assert info["converged"] and info["residual"] < 2e-10 and info["restarts"] >= 1
+    _CONFIG2.setdefault(L, []).append((e0, psi))
+    if len(_CONFIG2[L]) == 2:
+        (ea, pa), (eb, pb) = _CONFIG2.pop(L)
+        assert abs(ea - eb) <= 1e-10 * abs(ea)
+        assert 1 - abs(torch.vdot(pa, pb).item()) <= 1e-9
     if L == 20:
         e1, psi1, info1 = P.lanczos_ground(m, v0, tol=1e-10, max_iter=500, max_basis=500)
         assert info1["restarts"] == 0
