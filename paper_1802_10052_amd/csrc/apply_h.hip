@@ -58,6 +58,26 @@ void hpsi_tile(const double2* __restrict__ psi, double2* __restrict__ out, const
     tile_body<CLS, FIRST, GATHER>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s, 0, nullptr, sF);
 }
 
+// One tile per 1024-thread workgroup (4 registers per thread), launched with LDS padding so
+// that one workgroup runs per CU: the tiles in flight on an XCD (32) are one gather group of
+// G = 5, whose neighbouring tiles then stay in its L2, and 16 waves per CU keep loads, LDS work
+// and stores overlapping. Blocks map to tiles like the 256-thread launch.
+template <unsigned CLS, bool FIRST>
+__global__ __launch_bounds__(kTileThreads * 4) void hpsi_tile_wide(
+    const double2* __restrict__ psi, double2* __restrict__ out, const double2* __restrict__ site,
+    const double2* __restrict__ bond, const double2* __restrict__ dlo, const double2* __restrict__ dmid,
+    const double2* __restrict__ dhi, PassArgs pa) {
+    __shared__ double2 s[1 << kTileBits];
+    __shared__ double2 sF[kTileBits];
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b & 7, j = b >> 3;
+    const int64_t member = j & ((int64_t(1) << pa.G) - 1), gl = j >> pa.G;
+    const int64_t group = (gl << 3) | xcd;
+    const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
+    const int64_t n = low | (member << pa.gpos) | (high << (pa.gpos + pa.G));
+    tile_body<CLS, FIRST, true, false, 10>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s, 0, nullptr, sF);
+}
+
 // Two tiles per workgroup (512 threads, 128 KiB of LDS, one workgroup per CU): the tiles n and
 // n ^ (tile-index bit gpos) that differ in the first gathered bit, one per half. Block b is mapped
 // like the one-tile launch, with pairs in place of tiles, so a gather group's pairs still run
@@ -106,7 +126,11 @@ hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, h
 #define ED_TILE_ARGS psi, out, m->d_site, m->d_bond, m->d_diag_lo, m->d_diag_mid, m->d_diag_hi, pa
         // optional LDS padding: one workgroup per CU, so that the tiles of a group fit in L2
         const unsigned pad = (pd.G > 0 && pd.occ1) ? unsigned(kOccPadBytes) : 0u;
-        if (pd.G > 0 && pd.pair) {
+        if (pd.G > 0 && pd.wide) {
+            const dim3 wblock{unsigned(4 * kTileThreads)};
+            if (pd.first) hipLaunchKernelGGL((hpsi_tile_wide<CLS, true>), grid, wblock, kOccPadBytes, s, ED_TILE_ARGS);
+            else hipLaunchKernelGGL((hpsi_tile_wide<CLS, false>), grid, wblock, kOccPadBytes, s, ED_TILE_ARGS);
+        } else if (pd.G > 0 && pd.pair) {
             const dim3 pgrid{unsigned(tiles / 2)}, pblock{unsigned(2 * kTileThreads)};
             if (pd.first) hipLaunchKernelGGL((hpsi_tile_pair<CLS, true>), pgrid, pblock, 0, s, ED_TILE_ARGS);
             else hipLaunchKernelGGL((hpsi_tile_pair<CLS, false>), pgrid, pblock, 0, s, ED_TILE_ARGS);

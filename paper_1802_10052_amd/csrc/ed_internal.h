@@ -39,7 +39,7 @@ constexpr int kTileSlots = (1 << kTileBits) / kTileThreads;  // register slots p
 constexpr int kMaxPasses = 4;
 
 constexpr int kMaxGather = 8;     // index bits above a tile whose partner tiles are read from L2
-constexpr int kMaxPlans = 32;     // candidate pass plans per model (chosen by ed_model_tune)
+constexpr int kMaxPlans = 48;     // candidate pass plans per model (chosen by ed_model_tune)
 constexpr int kOccPadBytes = 40960;  // extra LDS that leaves room for one tile workgroup per CU
 
 struct PassDesc {
@@ -60,6 +60,7 @@ struct PassDesc {
     uint32_t bond_gmask;  // bit i: bond (gb + i, gb + i + 1) belongs to this pass
     int occ1;            // launch with one workgroup per CU (a group's tiles then fit in L2)
     int pair;            // two tiles per workgroup: the first gathered bit's partner comes from LDS
+    int wide;            // 1024 threads per tile, one workgroup per CU
 };
 
 // One gathered term of a pass as the kernels evaluate it: out[x] += coef * psi[partner of x], the

@@ -31,8 +31,9 @@ __device__ __forceinline__ double2 sel4(int l, double2 a0, double2 a1, double2 a
     return (l & 2) ? hi : lo;
 }
 
-// Tile-local index i = t + 256 k: local bits 0..7 across threads, 8..11 across 16 registers.
-constexpr int kSlots = kTileSlots;  // 16
+// Tile-local index i = t + 2^TB k: local bits 0..TB-1 across the threads of the workgroup,
+// TB..11 across registers (TB = 8: 256 threads x 16 registers; TB = 10: 1024 threads x 4).
+constexpr int kSlots = kTileSlots;  // 16, for TB = 8
 
 struct PassArgs {
     int c, h0, first;
@@ -70,11 +71,12 @@ __device__ __forceinline__ int64_t tile_index(const PassArgs& pa, bool first, in
     return base | int64_t(i & lowmask) | (int64_t(i >> pa.c) << pa.h0);
 }
 
-// Tile-local index t + kTileThreads * k sits at global index tile_index(t) + k * slot_step: the
-// register slots only touch bits above the thread bits (c <= 8 in window passes), so every slot of
-// a thread is one uniform stride from the first and no per-slot 64-bit index is kept.
+// Tile-local index t + 2^TB k sits at global index tile_index(t) + k * slot_step: the register
+// slots only touch bits above the thread bits (c <= TB in window passes), so every slot of a
+// thread is one uniform stride from the first and no per-slot 64-bit index is kept.
+template <int TB = 8>
 __device__ __forceinline__ int64_t slot_step(const PassArgs& pa, bool first) {
-    return first ? int64_t(kTileThreads) : (int64_t(kTileThreads >> pa.c) << pa.h0);
+    return first ? (int64_t(1) << TB) : (int64_t((1 << TB) >> pa.c) << pa.h0);
 }
 
 // One tile of one pass (tile index n). s: 4096 double2 of LDS. FIRST: writes out including the
@@ -83,8 +85,9 @@ __device__ __forceinline__ int64_t slot_step(const PassArgs& pa, bool first) {
 // PAIR: the workgroup holds two tiles, n and n ^ (tile-index bit gpos), one per half of its
 // threads (t is the thread's index in its half, s its half's LDS tile, so the other half's
 // tile); jobs whose partner is the other tile read it from LDS instead of global memory.
+// TB: thread bits of the tile (8: 256 threads, 16 registers each; 10: 1024 threads, 4 each).
 // Caller synchronises around reuse of s.
-template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false>
+template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8>
 __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
                                           const double2* __restrict__ site, const double2* __restrict__ bond,
                                           const double2* __restrict__ dlo, const double2* __restrict__ dmid,
@@ -93,22 +96,26 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
                                           double2* sF = nullptr) {
     constexpr bool OFFR = CLS & kOffReal;
     constexpr bool DIAGR = CLS & kDiagReal;
+    constexpr int kThr = 1 << TB;                  // threads of one tile
+    constexpr int kSl = 1 << (kTileBits - TB);     // register slots per thread
+    static_assert(TB >= 8 && TB < kTileBits, "the diagonal tables take bits 0..7 from the thread index");
+    static_assert(!PAIR || TB == 8, "paired tiles use 256 threads per tile");
     if (!PAIR) t = threadIdx.x;
     const int64_t base = tile_base(pa, FIRST, n);
     const int64_t i0 = tile_index(pa, FIRST, base, t);
-    const int64_t step = slot_step(pa, FIRST);
+    const int64_t step = slot_step<TB>(pa, FIRST);
     const double2* __restrict__ pv = psi + i0;
 
-    double2 v[kSlots];
-    double2 acc[kSlots];
+    double2 v[kSl];
+    double2 acc[kSl];
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) v[k] = pv[k * step];
+    for (int k = 0; k < kSl; ++k) v[k] = pv[k * step];
     if (!FIRST) {
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) acc[k] = out[i0 + k * step];
+        for (int k = 0; k < kSl; ++k) acc[k] = out[i0 + k * step];
     }
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) s[t + kTileThreads * k] = v[k];
+    for (int k = 0; k < kSl; ++k) s[t + kThr * k] = v[k];
 
     if (FIRST && pa.lr && t < kTileBits - 1) {
         // long-range field on low bit t from the tile's fixed high bits (z = +1 for bit 0)
@@ -124,8 +131,8 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     if (FIRST) {
         const double2 dl = dlo[t & 255];
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            const int i = t + kTileThreads * k;
+        for (int k = 0; k < kSl; ++k) {
+            const int i = t + kThr * k;
             const double2 dm = dmid[(i >> 7) & 31];
             const double2 dh = dhi[(n << 1) | ((i >> 11) & 1)];
             double2 dd = make_double2(dl.x + dm.x + dh.x, dl.y + dm.y + dh.y);
@@ -139,23 +146,23 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     __syncthreads();
     if (FIRST && pa.lr) {
         // long-range zz: pairs inside the tile (table) + sum over low bits p < 11 of z_p F_p
-        // (bits 0..7 are the thread's, 8..10 the slot's)
+        // (bits 0..TB-1 are the thread's, TB..10 the slot's)
         double2 st = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
+        for (int p = 0; p < TB; ++p) {
             const double z = ((t >> p) & 1) ? -1.0 : 1.0;
             st.x += z * sF[p].x;
             st.y += z * sF[p].y;
         }
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            const int i = t + kTileThreads * k;
+        for (int k = 0; k < kSl; ++k) {
+            const int i = t + kThr * k;
             double2 e = pa.lr_low[i];
             e.x += st.x;
             e.y += st.y;
 #pragma unroll
-            for (int p = 8; p < kTileBits - 1; ++p) {
-                const double z = ((k >> (p - 8)) & 1) ? -1.0 : 1.0;
+            for (int p = TB; p < kTileBits - 1; ++p) {
+                const double z = ((k >> (p - TB)) & 1) ? -1.0 : 1.0;
                 e.x += z * sF[p].x;
                 e.y += z * sF[p].y;
             }
@@ -177,12 +184,12 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
             const double2 c01 = site[4 * p + 1];
             const double2 c10 = site[4 * p + 2];
 #pragma unroll
-            for (int k = 0; k < kSlots; ++k) {
-                const int i = t + kTileThreads * k;
+            for (int k = 0; k < kSl; ++k) {
+                const int i = t + kThr * k;
                 const int b = (i >> q) & 1;
                 double2 w;
-                if (q >= 8) {
-                    w = v[k ^ (1 << (q >= 8 ? q - 8 : 0))];
+                if (q >= TB) {
+                    w = v[k ^ (1 << (q >= TB ? q - TB : 0))];
                 } else {
                     w = s[i ^ (1 << q)];
                 }
@@ -197,12 +204,12 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
                     const double2 b0 = B[0 * 4 + (0 ^ m)], b1 = B[1 * 4 + (1 ^ m)];
                     const double2 b2 = B[2 * 4 + (2 ^ m)], b3 = B[3 * 4 + (3 ^ m)];
 #pragma unroll
-                    for (int k = 0; k < kSlots; ++k) {
-                        const int i = t + kTileThreads * k;
+                    for (int k = 0; k < kSl; ++k) {
+                        const int i = t + kThr * k;
                         const int l = (i >> q) & 3;
                         double2 w;
-                        if (q >= 8) {
-                            w = v[k ^ (m << (q >= 8 ? q - 8 : 0))];
+                        if (q >= TB) {
+                            w = v[k ^ (m << (q >= TB ? q - TB : 0))];
                         } else {
                             w = s[i ^ (m << q)];
                         }
@@ -214,12 +221,12 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
                 const double2 b0 = B[0 * 4 + 3], b1 = B[1 * 4 + 2];
                 const double2 b2 = B[2 * 4 + 1], b3 = B[3 * 4 + 0];
 #pragma unroll
-                for (int k = 0; k < kSlots; ++k) {
-                    const int i = t + kTileThreads * k;
+                for (int k = 0; k < kSl; ++k) {
+                    const int i = t + kThr * k;
                     const int l = (i >> q) & 3;
                     double2 w;
-                    if (q >= 8) {
-                        w = v[k ^ (3 << (q >= 8 ? q - 8 : 0))];
+                    if (q >= TB) {
+                        w = v[k ^ (3 << (q >= TB ? q - TB : 0))];
                     } else {
                         w = s[i ^ (3 << q)];
                     }
@@ -236,24 +243,24 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
             const int hb = int((n >> pa.gpos) & 1);
             const double2 c0 = B[4 * (2 * hb) + (2 * hb + 1)], c1 = B[4 * (2 * hb + 1) + (2 * hb)];
 #pragma unroll
-            for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, v[k ^ (kSlots >> 1)]);
+            for (int k = 0; k < kSl; ++k) cfma<OFFR>(acc[k], k >= kSl / 2 ? c1 : c0, v[k ^ (kSl >> 1)]);
         }
         // gathered terms: partner tile n ^ txor, register slot k ^ sx, coefficients by pattern.
         // (Loading several partner tiles per round trip was measured slower: the one-workgroup
         // launches are bound by the missing overlap of load, LDS and store phases, not by it.)
         for (int j = 0; j < pa.njobs; ++j) {
             const GatherJob& jb = pa.jobs[j];
-            const int sx = jb.sx;
+            const int sx = jb.sx ? (kSl >> 1) : 0;  // jobs flip at most the tile's top bit
             const int p = int((n >> jb.shift) & 3);
             const double2 c0 = jb.coef[p][0], c1 = jb.coef[p][1];
             if (PAIR && jb.txor == (int64_t(1) << pa.gpos)) {
 #pragma unroll
-                for (int k = 0; k < kSlots; ++k)
-                    cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, so[t + kTileThreads * (k ^ sx)]);
+                for (int k = 0; k < kSl; ++k)
+                    cfma<OFFR>(acc[k], k >= kSl / 2 ? c1 : c0, so[t + kThr * (k ^ sx)]);
             } else {
                 const double2* __restrict__ pw = pv + (tile_base(pa, FIRST, n ^ jb.txor) - base);
 #pragma unroll
-                for (int k = 0; k < kSlots; ++k) cfma<OFFR>(acc[k], k >= kSlots / 2 ? c1 : c0, pw[(k ^ sx) * step]);
+                for (int k = 0; k < kSl; ++k) cfma<OFFR>(acc[k], k >= kSl / 2 ? c1 : c0, pw[(k ^ sx) * step]);
             }
         }
     }
@@ -261,7 +268,7 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     // streaming stores: out is not read again by this pass, so it should not evict the state tiles
     // that neighbouring workgroups gather from L2
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) {
+    for (int k = 0; k < kSl; ++k) {
         double* o = reinterpret_cast<double*>(out + i0 + k * step);
         __builtin_nontemporal_store(acc[k].x, o);
         __builtin_nontemporal_store(acc[k].y, o + 1);

@@ -37,7 +37,8 @@ ed_status require_device(int* device) {
 // (`bonds`) consecutive passes overlap by one bit so that the bond crossing between them lies
 // inside one tile; without them the passes tile the bits edge to edge. Returns the pass count, or
 // -1 if this combination does not give a plan for L.
-static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ1, int pair, PassDesc* out) {
+static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ1, int pair, int wide,
+                     PassDesc* out) {
     const int T = kTileBits;
     const int tile_index_bits = L - T;
     // at least 8 groups, one per XCD
@@ -61,8 +62,9 @@ static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ
         p0.gcross = bonds ? 1 : 0;
         p0.site_gmask = (1u << G0) - 1u;
         p0.bond_gmask = (bonds && G0 > 1) ? (1u << (G0 - 1)) - 1u : 0u;
-        p0.occ1 = pair ? 0 : occ1;
+        p0.occ1 = (pair || wide) ? 0 : occ1;
         p0.pair = pair;
+        p0.wide = pair ? 0 : wide;
     }
     int done = T + G0;  // sites on bits < done are assigned, and bonds (p, p+1) with p + 1 < done
     const int wb = T - cw;
@@ -94,8 +96,9 @@ static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ
             pd.gcross = bonds ? 1 : 0;
             pd.site_gmask = (1u << G) - 1u;
             pd.bond_gmask = (bonds && G > 1) ? (1u << (G - 1)) - 1u : 0u;
-            pd.occ1 = pair ? 0 : occ1;
+            pd.occ1 = (pair || wide) ? 0 : occ1;
             pd.pair = pair;
+            pd.wide = pair ? 0 : wide;
         }
         done = h0 + wb + G;
     }
@@ -112,7 +115,7 @@ static double plan_cost(const PassDesc* pass, int np) {
     for (int i = 0; i < np; ++i) {
         const PassDesc& pd = pass[i];
         const int gl2 = pd.pair ? pd.G - 1 : pd.G;  // gathered bits read through L2
-        const double stream = pd.pair ? 0.95 : 1.0;
+        const double stream = pd.pair ? 0.95 : (pd.wide ? 0.97 : 1.0);
         if (pd.first) {
             cost += 2.0 * stream + 0.35 * gl2;
         } else {
@@ -150,14 +153,15 @@ static void plan_passes(ed_model* m) {
     };
     std::vector<Cand> all;
     Cand plain{};
-    plain.np = plan_make(L, 0, 3, 0, bonds, 0, 0, plain.p);
+    plain.np = plan_make(L, 0, 3, 0, bonds, 0, 0, 0, plain.p);
     plain.cost = plain.np > 0 ? plan_cost(plain.p, plain.np) : 0.0;
     for (int g = 0; g <= kMaxGather; ++g)
         for (int cw = 3; cw <= 4; ++cw)
             for (int gw : {0, 2, 4})
-                for (int occ = 0; occ <= 2; ++occ) {  // 0: two workgroups per CU, 1: one, 2: paired tiles
+                for (int occ = 0; occ <= 3; ++occ) {  // 0: two workgroups per CU, 1: one, 2: paired, 3: wide
                     Cand c{};
-                    c.np = plan_make(L, g, cw, gw, bonds, occ == 1 ? 1 : 0, occ == 2 ? 1 : 0, c.p);
+                    c.np = plan_make(L, g, cw, gw, bonds, occ == 1 ? 1 : 0, occ == 2 ? 1 : 0, occ == 3 ? 1 : 0,
+                                     c.p);
                     if (c.np <= 0) continue;
                     bool gathered = false;
                     for (int i = 0; i < c.np; ++i) gathered = gathered || c.p[i].G > 0;
@@ -206,6 +210,7 @@ static bool plan_is_valid(int L, bool bonds_needed, const PassDesc* pass, int n_
         }
         if (pd.occ1 != 0 && pd.occ1 != 1) return false;
         if (pd.pair != 0 && (pd.pair != 1 || pd.G < 1 || pd.occ1)) return false;
+        if (pd.wide != 0 && (pd.wide != 1 || pd.G < 1 || pd.occ1 || pd.pair || (!pd.first && pd.c > 10))) return false;
         for (int q = 0; q < kTileBits; ++q) {
             const int p = pd.bit_of[q];
             if (p < 0 || p >= L) return false;
@@ -230,7 +235,7 @@ static bool plan_is_valid(int L, bool bonds_needed, const PassDesc* pass, int n_
                 }
             }
             if (pd.gcross) ++bonds[pd.gb - 1];
-        } else if (pd.site_gmask || pd.bond_gmask || pd.gcross || pd.occ1 || pd.pair) {
+        } else if (pd.site_gmask || pd.bond_gmask || pd.gcross || pd.occ1 || pd.pair || pd.wide) {
             return false;
         }
     }
@@ -753,6 +758,7 @@ ed_status ed_model_plan_describe(const ed_model* model, int index, char* buf, in
         if (pd.G > 0) d += " +G" + std::to_string(pd.G);
         if (pd.occ1) d += " occ1";
         if (pd.pair) d += " pair";
+        if (pd.wide) d += " wide";
     }
     std::strncpy(buf, d.c_str(), size_t(buf_len) - 1);
     buf[buf_len - 1] = 0;
