@@ -106,7 +106,7 @@ ed_status ed_model_dims(const ed_model* model, int* L, int64_t* D);
 /* Number of streaming passes over the state one ed_apply_H makes (diagnostic). */
 ed_status ed_model_passes(const ed_model* model, int* passes);
 
-/* Autotuning of H psi. A model holds up to 48 candidate pass plans (which index bits each
+/* Autotuning of H psi. A model holds up to 96 candidate pass plans (which index bits each
  * streaming pass covers, how many bits above a tile are read from neighbouring tiles in L2, and
  * whether a pass runs one workgroup per CU, two tiles per workgroup, or one tile per 1024-thread
  * workgroup). All candidates compute the same H psi (up to the order of floating-point sums). Candidates have the fewest passes possible for L (plus the plan

@@ -39,7 +39,7 @@ constexpr int kTileSlots = (1 << kTileBits) / kTileThreads;  // register slots p
 constexpr int kMaxPasses = 4;
 
 constexpr int kMaxGather = 8;     // index bits above a tile whose partner tiles are read from L2
-constexpr int kMaxPlans = 48;     // candidate pass plans per model (chosen by ed_model_tune)
+constexpr int kMaxPlans = 96;     // candidate pass plans per model (chosen by ed_model_tune)
 constexpr int kOccPadBytes = 40960;  // extra LDS that leaves room for one tile workgroup per CU
 
 struct PassDesc {

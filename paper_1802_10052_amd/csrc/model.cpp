@@ -37,7 +37,15 @@ ed_status require_device(int* device) {
 // (`bonds`) consecutive passes overlap by one bit so that the bond crossing between them lies
 // inside one tile; without them the passes tile the bits edge to edge. Returns the pass count, or
 // -1 if this combination does not give a plan for L.
-static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ1, int pair, int wide,
+// Launch shape of a gathered pass: 0 two tile workgroups per CU, 1 one (LDS padding), 2 paired
+// tiles, 3 one 1024-thread tile per CU.
+static void set_shape(PassDesc& pd, int shape) {
+    pd.occ1 = shape == 1 ? 1 : 0;
+    pd.pair = shape == 2 ? 1 : 0;
+    pd.wide = shape == 3 ? 1 : 0;
+}
+
+static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int shape_first, int shape_win,
                      PassDesc* out) {
     const int T = kTileBits;
     const int tile_index_bits = L - T;
@@ -62,9 +70,7 @@ static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ
         p0.gcross = bonds ? 1 : 0;
         p0.site_gmask = (1u << G0) - 1u;
         p0.bond_gmask = (bonds && G0 > 1) ? (1u << (G0 - 1)) - 1u : 0u;
-        p0.occ1 = (pair || wide) ? 0 : occ1;
-        p0.pair = pair;
-        p0.wide = pair ? 0 : wide;
+        set_shape(p0, shape_first);
     }
     int done = T + G0;  // sites on bits < done are assigned, and bonds (p, p+1) with p + 1 < done
     const int wb = T - cw;
@@ -96,9 +102,7 @@ static int plan_make(int L, int g_first, int cw, int gw_max, bool bonds, int occ
             pd.gcross = bonds ? 1 : 0;
             pd.site_gmask = (1u << G) - 1u;
             pd.bond_gmask = (bonds && G > 1) ? (1u << (G - 1)) - 1u : 0u;
-            pd.occ1 = (pair || wide) ? 0 : occ1;
-            pd.pair = pair;
-            pd.wide = pair ? 0 : wide;
+            set_shape(pd, shape_win);
         }
         done = h0 + wb + G;
     }
@@ -116,19 +120,22 @@ static double plan_cost(const PassDesc* pass, int np) {
         const PassDesc& pd = pass[i];
         const int gl2 = pd.pair ? pd.G - 1 : pd.G;  // gathered bits read through L2
         const double stream = pd.pair ? 0.95 : (pd.wide ? 0.97 : 1.0);
+        // one tile per CU keeps more of a gather group's neighbours in L2
+        const double per_bit = pd.wide ? 0.8 : 1.0;
         if (pd.first) {
-            cost += 2.0 * stream + 0.35 * gl2;
+            cost += 2.0 * stream + 0.35 * per_bit * gl2;
         } else {
             const double slow = (pd.c <= 3 && pd.h0 >= 17) ? 1.25 : (pd.c <= 3 ? 1.05 : 1.0);
-            cost += 3.0 * slow * stream + 1.2 * gl2;
+            cost += 3.0 * slow * stream + 1.2 * per_bit * gl2;
         }
     }
     return cost;
 }
 
 // Candidate plans: every combination of first-pass gathers, window run length, window gathers and
-// launch shape (two tile workgroups per CU, one, or paired tiles) that reaches the fewest passes, cheapest first by plan_cost, then the plain plan (no
-// gathers) if it is not among them. ed_model_tune times them on the device.
+// the launch shapes of the first and the window passes that reaches the fewest passes, cheapest
+// first by plan_cost, then the plain plan (no gathers) if it is not among them. ed_model_tune
+// times them on the device.
 static void plan_passes(ed_model* m) {
     const int L = m->L;
     const int T = kTileBits;
@@ -153,19 +160,18 @@ static void plan_passes(ed_model* m) {
     };
     std::vector<Cand> all;
     Cand plain{};
-    plain.np = plan_make(L, 0, 3, 0, bonds, 0, 0, 0, plain.p);
+    plain.np = plan_make(L, 0, 3, 0, bonds, 0, 0, plain.p);
     plain.cost = plain.np > 0 ? plan_cost(plain.p, plain.np) : 0.0;
     for (int g = 0; g <= kMaxGather; ++g)
         for (int cw = 3; cw <= 4; ++cw)
             for (int gw : {0, 2, 4})
-                for (int occ = 0; occ <= 3; ++occ) {  // 0: two workgroups per CU, 1: one, 2: paired, 3: wide
+                for (int shape = 0; shape < 9; ++shape) {  // launch shapes of the first and window passes
+                    // normal, paired or wide each (the one-workgroup-per-CU shape of 256 threads is
+                    // never faster than the wide one with the same L2 footprint)
+                    static const int kShapes[3] = {0, 2, 3};
                     Cand c{};
-                    c.np = plan_make(L, g, cw, gw, bonds, occ == 1 ? 1 : 0, occ == 2 ? 1 : 0, occ == 3 ? 1 : 0,
-                                     c.p);
-                    if (c.np <= 0) continue;
-                    bool gathered = false;
-                    for (int i = 0; i < c.np; ++i) gathered = gathered || c.p[i].G > 0;
-                    if (occ && !gathered) continue;
+                    c.np = plan_make(L, g, cw, gw, bonds, kShapes[shape % 3], kShapes[shape / 3], c.p);
+                    if (c.np <= 0) continue;  // (a shape on passes without gathers gives a duplicate)
                     c.cost = plan_cost(c.p, c.np);
                     bool dup = false;
                     for (const Cand& o : all)
