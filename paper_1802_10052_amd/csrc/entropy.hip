@@ -9,9 +9,12 @@
 //      R is read in place from the state, never copied.
 //   2. Householder reduction of the Hermitian rho to a real symmetric tridiagonal matrix on the
 //      GPU: each step's rank-2 update of the trailing matrix is fused with the matrix-vector
-//      product that the next step needs, so the trailing matrix streams once per step.
+//      product that the next step needs, on the lower triangle only (the product takes the upper
+//      part as the conjugate of the lower), so half the trailing matrix streams once per step.
 //   3. Eigenvalues of the tridiagonal matrix by implicit QL on the host (O(n^2)).
+#include <algorithm>
 #include <cmath>
+#include <utility>
 #include <vector>
 
 #include "dense.h"
@@ -131,47 +134,96 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * b
 }
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 
-// Fused: for the trailing block rows/cols [s, n) (s = k + 2):
-//   A[i][j] -= v_i conj(w_j) + w_i conj(v_j)     (rank-2 update of step k, vectors indexed by
-//                                               absolute row; v, w hold entries for rows >= k+1)
-//   part[cb][i] = sum_{j in tile} A_new[i][j] * vn_j   (vn: next Householder vector, rows >= k+2)
-__global__ __launch_bounds__(256) void hh_fused(double2* __restrict__ A, int n, int s,
-                                                const double2* __restrict__ v, const double2* __restrict__ w,
-                                                const double2* __restrict__ vn, double2* __restrict__ part) {
-    const int r = n - s;
-    const int ncb = (r + kFC - 1) / kFC;
-    const int rb = blockIdx.x / ncb, cb = blockIdx.x % ncb;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int cbeg = s + cb * kFC;
-    for (int ii = 0; ii < kFR / 4; ++ii) {
-        const int i = s + rb * kFR + wv * (kFR / 4) + ii;
-        if (i >= n) break;
-        const double2 vi = v[i], wi = w[i];
-        double2 acc = make_double2(0.0, 0.0);
-        for (int jj = lane; jj < kFC; jj += 64) {
-            const int j = cbeg + jj;
-            if (j >= n) break;
+// Fused rank-2 update and next product, lower triangle only: for the trailing block [s, n)
+// (s = k + 2), A[i][j] -= v_i conj(w_j) + w_i conj(v_j) (the update of step k; v, w hold entries for
+// rows >= k+1) and the partial sums of A_new vn (vn: the next Householder vector, rows >= k+2).
+// rho is Hermitian, so only entries with j <= i of the trailing block are
+// kept up to date (the upper triangle is never read again). The trailing block [s, n) is cut into
+// 64 x 64 tiles (R, C), C <= R; each workgroup updates one tile and writes, for the next product
+// y = A_new vn, the row sums of its rows (slot C) and the conjugate column sums of its strictly
+// lower entries (slot R, y_j += conj(A_ij) vn_i). In a diagonal tile both go to slot R of the same
+// index. Index i of block B thus gets slot b from tile (B, b) for b < B, (B, B) for b = B and
+// (b, B) for b > B: every slot exactly once, summed in slot order by hh_reduce.
+constexpr int kSB = 64;
+
+__global__ __launch_bounds__(256) void hh_fused_sym(double2* __restrict__ A, int n, int s,
+                                                    const double2* __restrict__ v, const double2* __restrict__ w,
+                                                    const double2* __restrict__ vn, double2* __restrict__ part) {
+    __shared__ double2 colred[4][kSB];
+    __shared__ double2 rowred[kSB];
+    int b = blockIdx.x, R = 0;
+    while (b > R) {
+        b -= R + 1;
+        ++R;
+    }
+    const int C = b;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int j = s + C * kSB + lane;
+    const bool jok = j < n;
+    const double2 zero = make_double2(0.0, 0.0);
+    const double2 vj = jok ? v[j] : zero, wj = jok ? w[j] : zero, vnj = jok ? vn[j] : zero;
+    double2 colacc = zero;
+    for (int rr = 0; rr < kSB / 4; ++rr) {
+        const int li = wv * (kSB / 4) + rr;
+        const int i = s + R * kSB + li;
+        if (i >= n) break;  // uniform over the wave
+        const double2 vi = v[i], wi = w[i], vni = vn[i];
+        double2 rp = zero;
+        if (jok && j <= i) {
             double2 a = A[int64_t(i) * n + j];
-            const double2 vj = v[j], wj = w[j];
             const double2 t1 = cmulc(vi, conjd(wj)), t2 = cmulc(wi, conjd(vj));
             a.x -= t1.x + t2.x;
             a.y -= t1.y + t2.y;
             A[int64_t(i) * n + j] = a;
-            const double2 p = cmulc(a, vn[j]);
-            acc.x += p.x;
-            acc.y += p.y;
+            rp = cmulc(a, vnj);
+            if (j < i) {
+                const double2 q = cmulc(conjd(a), vni);
+                colacc.x += q.x;
+                colacc.y += q.y;
+            }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            acc.x += __shfl_down(acc.x, off, 64);
-            acc.y += __shfl_down(acc.y, off, 64);
+            rp.x += __shfl_down(rp.x, off, 64);
+            rp.y += __shfl_down(rp.y, off, 64);
         }
-        if (lane == 0) part[int64_t(cb) * n + i] = acc;
+        if (lane == 0) {
+            if (R == C) rowred[li] = rp;
+            else part[int64_t(C) * n + i] = rp;
+        }
+    }
+    colred[wv][lane] = colacc;
+    __syncthreads();
+    if (wv == 0 && jok) {
+        double2 cs = colred[0][lane];
+        for (int q = 1; q < 4; ++q) {
+            cs.x += colred[q][lane].x;
+            cs.y += colred[q][lane].y;
+        }
+        if (R == C) {
+            cs.x += rowred[lane].x;
+            cs.y += rowred[lane].y;
+        }
+        part[int64_t(R) * n + j] = cs;
     }
 }
 
-// Single-workgroup step kernel (1024 threads). Given part (row sums of A22 * v for the
-// current step k, rows k+1..n-1) it: forms y = tau (A22 v); alpha = -1/2 tau (y^H v); w = y + alpha v;
+// ys[i] = sum over the nslots partial sums of row i, in slot order (i in [c, n))
+__global__ __launch_bounds__(256) void hh_reduce(const double2* __restrict__ part, int nslots, int c, int n,
+                                                 double2* __restrict__ ys) {
+    const int i = c + int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (i >= n) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int b = 0; b < nslots; ++b) {
+        const double2 p = part[int64_t(b) * n + i];
+        acc.x += p.x;
+        acc.y += p.y;
+    }
+    ys[i] = acc;
+}
+
+// Single-workgroup step kernel (1024 threads). Given ys = A22 v for the current step k (rows
+// k+1..n-1, from hh_reduce) it: forms y = tau (A22 v); alpha = -1/2 tau (y^H v); w = y + alpha v;
 // updates column k+1 of the trailing matrix (rows k+1..n-1) with the rank-2 term; records
 // d[k+1]; builds the next Householder vector from rows k+2.. of that column, with tau, beta.
 // For k = -1 it only builds the first Householder vector from column 0.
@@ -191,25 +243,18 @@ __device__ double block_reduce(double v, double* lds) {
 
 __global__ __launch_bounds__(kStepThreads) void hh_step(double2* __restrict__ A, int n, int k,
                                                         double2* __restrict__ v, double2* __restrict__ y,
-                                                        double2* __restrict__ vn, const double2* __restrict__ part,
-                                                        int ncb, double* __restrict__ d, double* __restrict__ e,
+                                                        double2* __restrict__ vn, const double2* __restrict__ ys,
+                                                        double* __restrict__ d, double* __restrict__ e,
                                                         double2* __restrict__ sc) {
     __shared__ double lds[kStepThreads / 64];
     const int t = threadIdx.x;
     const int c = k + 1;  // column of the trailing matrix to finish now
     if (k >= 0) {
         const double2 tau = sc[0];
-        // y_i = tau * sum_cb part[cb][i], i = k+1..n-1 ; also y^H v
+        // y_i = tau * (A22 v)_i, i = k+1..n-1 (the sums from hh_reduce); also y^H v
         double dre = 0.0, dim = 0.0;
         for (int i = c + t; i < n; i += kStepThreads) {
-            double2 s = make_double2(0.0, 0.0);
-            for (int cb = 0; cb < ncb; ++cb) {
-                const double2 p = part[int64_t(cb) * n + i];
-                s.x += p.x;
-                s.y += p.y;
-            }
-            // rows >= k+1 of A22 v: the fused kernel covered columns >= k+1 of rows >= k+1? (see host)
-            const double2 yi = cmulc(tau, s);
+            const double2 yi = cmulc(tau, ys[i]);
             y[i] = yi;
             const double2 vi = v[i];
             // y^H v = sum conj(y_i) v_i
@@ -306,21 +351,23 @@ struct EntWS {
     double2* v;
     double2* y;
     double2* vn;
+    double2* ys;
     double2* part;
     double* d;
     double* e;
     double2* sc;
 };
 
+// partial-sum slots: the first product's column blocks, or the symmetric tiles' block count
+int part_slots(int n) { return std::max((n + kFC - 1) / kFC, (n + kSB - 1) / kSB) + 1; }
+
 size_t entropy_bytes(int n) {
-    const int ncb = (n + kFC - 1) / kFC;
-    return align256(size_t(n) * n * sizeof(double2)) + 3 * align256(size_t(n) * sizeof(double2)) +
-           align256(size_t(ncb + 1) * n * sizeof(double2)) + 2 * align256(size_t(n) * sizeof(double)) +
+    return align256(size_t(n) * n * sizeof(double2)) + 4 * align256(size_t(n) * sizeof(double2)) +
+           align256(size_t(part_slots(n)) * n * sizeof(double2)) + 2 * align256(size_t(n) * sizeof(double)) +
            align256(4 * sizeof(double2));
 }
 
 EntWS carve_ent(void* ws, int n) {
-    const int ncb = (n + kFC - 1) / kFC;
     char* p = static_cast<char*>(ws);
     EntWS w;
     w.rho = reinterpret_cast<double2*>(p);
@@ -331,8 +378,10 @@ EntWS carve_ent(void* ws, int n) {
     p += align256(size_t(n) * sizeof(double2));
     w.vn = reinterpret_cast<double2*>(p);
     p += align256(size_t(n) * sizeof(double2));
+    w.ys = reinterpret_cast<double2*>(p);
+    p += align256(size_t(n) * sizeof(double2));
     w.part = reinterpret_cast<double2*>(p);
-    p += align256(size_t(ncb + 1) * n * sizeof(double2));
+    p += align256(size_t(part_slots(n)) * n * sizeof(double2));
     w.d = reinterpret_cast<double*>(p);
     p += align256(size_t(n) * sizeof(double));
     w.e = reinterpret_cast<double*>(p);
@@ -384,30 +433,35 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
     ED_HIP_TRY(hipMemsetAsync(w.v, 0, size_t(n) * sizeof(double2), s));
     ED_HIP_TRY(hipMemsetAsync(w.y, 0, size_t(n) * sizeof(double2), s));
     ED_HIP_TRY(hipMemsetAsync(w.vn, 0, size_t(n) * sizeof(double2), s));
+    ED_HIP_TRY(hipMemsetAsync(w.ys, 0, size_t(n) * sizeof(double2), s));
     if (n > 1) {
         // first Householder vector from column 0
-        hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, -1, w.v, w.y, w.vn, w.part, 0, w.d,
+        hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, -1, w.v, w.y, w.vn, w.ys, w.d,
                            w.e, w.sc);
+        int nslots = 0;  // partial-sum slots of the current product
         for (int k = 0; k + 1 < n; ++k) {
             // the current vector (rows >= k+1) becomes v; A22 v over rows/cols >= k+1
             std::swap(w.v, w.vn);
             const int s0 = k + 1;
             const int r = n - s0;
-            const int ncb = (r + kFC - 1) / kFC;
-            const int nrb = (r + kFR - 1) / kFR;
             if (k == 0) {
+                // nothing updated yet: full-row products of the Gram matrix, column blocks of kFC
+                const int ncb = (r + kFC - 1) / kFC;
+                const int nrb = (r + kFR - 1) / kFR;
                 hipLaunchKernelGGL(hh_gemv, dim3(nrb * ncb), dim3(256), 0, s, w.rho, n, s0, w.v, w.part);
+                nslots = ncb;
             }
+            hipLaunchKernelGGL(hh_reduce, dim3((r + 255) / 256), dim3(256), 0, s, w.part, nslots, s0, n, w.ys);
             // step kernel: y, w, column k+1 update, next Householder vector into vn
-            hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.part, ncb,
-                               w.d, w.e, w.sc);
+            hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.ys, w.d,
+                               w.e, w.sc);
             if (k + 2 < n) {
-                // rank-2 update of rows/cols >= k+2 fused with A_new * vn (the next step's product)
+                // rank-2 update of the lower triangle of rows/cols >= k+2 fused with A_new * vn
                 const int s1 = k + 2;
-                const int r1 = n - s1;
-                const int ncb1 = (r1 + kFC - 1) / kFC;
-                const int nrb1 = (r1 + kFR - 1) / kFR;
-                hipLaunchKernelGGL(hh_fused, dim3(nrb1 * ncb1), dim3(256), 0, s, w.rho, n, s1, w.v, w.y, w.vn, w.part);
+                const int nb = (n - s1 + kSB - 1) / kSB;
+                hipLaunchKernelGGL(hh_fused_sym, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, w.rho, n, s1, w.v, w.y,
+                                   w.vn, w.part);
+                nslots = nb;
             }
             ED_HIP_TRY(hipGetLastError());
         }
