@@ -63,7 +63,7 @@ ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s)
 // first subtraction together with the second pass's dots; subtraction + norm). Returns the true projections h_i = <v_i|H v_j> (i = lo..j) and the norm
 // beta of the orthogonalised H v_j; the new basis vector is u_{j+1} = y with c_{j+1} = 1/|y|.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
-                      cplx* h, double* beta, bool* breakdown, hipStream_t s) {
+                      cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo) {
     const int64_t D = w.D;
     const int n = j - lo + 1;
     if (n > kMaxProj) return fail(ED_ERR_UNSUPPORTED, "too many projections");
@@ -79,7 +79,14 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     const double2* const* U = const_cast<const double2* const*>(w.u.data() + lo);
     std::vector<double> sc(n);
     for (int i = 0; i < n; ++i) sc[i] = w.c[lo + i] * w.c[lo + i];
-    ED_K(dots_ptr(U, n, y, D, g1, w.part, s));
+    if (passes > 1 && first_lo > lo) {
+        // the recurrence's own vectors first; the other coefficients of the first pass are zero
+        const int nf = j - first_lo + 1;
+        ED_HIP_TRY(hipMemsetAsync(g1, 0, sizeof(double2) * size_t(n - nf), s));
+        ED_K(dots_ptr(U + (n - nf), nf, y, D, g1 + (n - nf), w.part, s));
+    } else {
+        ED_K(dots_ptr(U, n, y, D, g1, w.part, s));
+    }
     if (passes > 1) {
         // the first subtraction and the second pass's dots share a sweep
         ED_K(axpy_dots_ptr(U, n, g1, sc.data(), y, D, g2, w.part, s));
@@ -194,7 +201,10 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
         double beta = 0.0;
         bool brk = false;
         {
-            const ed_status st = krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s);
+            // past the first step of a cycle the recurrence is three-term: the first Gram-Schmidt
+            // pass needs only v_{j-1}, v_j (the second one takes the whole basis)
+            const int first_lo = (j >= 1 && j > k_locked) ? j - 1 : -1;
+            const ed_status st = krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s, first_lo);
             if (st != ED_OK)
                 return fail(st, std::string(ed_last_error()) + " (Lanczos product " + std::to_string(iters + 1) +
                                     ", restarts " + std::to_string(restarts) + ", basis index " + std::to_string(j) + ")");
@@ -264,7 +274,6 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
         }
         ++j;
     }
-    (void)k_locked;
     // Ritz vector psi0 = V s (unit norm up to rounding; renormalise explicitly)
     std::vector<double2> c(m);
     for (int r = 0; r < m; ++r) c[r] = make_double2(svec[r], 0.0);
