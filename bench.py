@@ -270,8 +270,8 @@ def row_rdm_L28(P, E, torch, dev, reps=3):
     each pair's 4x4 matrix are complex multiply-adds over the 2^(L-2) quads of amplitudes (48
     flops per quad and pair); the 4 diagonal entries are marginals of |psi|^2, summed once per
     amplitude and pass (4 flops). The products are not a dense contraction, so the bound is the
-    FP64 vector peak (78.6 TFLOP/s). Also timed: the single-site matrices alone (27 bonds in 5
-    passes)."""
+    FP64 vector peak (78.6 TFLOP/s). Also timed: the single-site matrices alone (every site's 2x2
+    matrix directly, 3 passes over the state, each reading it once: HBM-bound)."""
     L = 28
     psi = E.random_state_device(L, 12, dev)
     pairs, pass_of = P.rdm_plan(L)
@@ -287,12 +287,14 @@ def row_rdm_L28(P, E, torch, dev, reps=3):
         for _ in range(reps):
             P.rdm(psi, L, two_site=False)
     ms1 = 1e3 * t1.s / reps
+    passes1 = int(P.rdm_plan_sites(L)[1].max()) + 1
+    gbs1 = passes1 * 16.0 * float(1 << L) / (ms1 * 1e-3) / 1e9  # each pass streams the state once
     tf = flops / (ms * 1e-3) / 1e12
     return {"workload": "rho_k for all 28 sites and rho_{k,j} for all 378 pairs of a random L=28 state",
             "all_pairs_ms": round(ms, 2), "all_pairs_TFLOPs": round(tf, 2),
             "frac_fp64_vector_peak": round(tf / 78.6, 4), "passes": passes,
-            "single_site_only_ms": round(ms1, 2),
-            "single_site_passes": int(P.rdm_plan(L, all_pairs=False)[1].max()) + 1}
+            "single_site_only_ms": round(ms1, 2), "single_site_passes": passes1,
+            "single_site_GBps": round(gbs1, 1), "single_site_frac_hbm_peak": round(gbs1 / 8000.0, 4)}
 
 
 def row_liouville_L14(P, E, torch, dev, reps=5, steps=10):

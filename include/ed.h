@@ -308,20 +308,26 @@ ed_status ed_liouville_measure(const ed_c64* rho, int L, double* sz, double* tra
  *       lexicographic order (pair (k, j) at (k-1)L - (k-1)k/2 + j-k-1); row index 2 i_k + i_j.
  *       Both triangles are written (the lower as the conjugate of the upper).
  * The state is streamed in LDS tiles that hold 12 of its index bits; each pass evaluates the pairs
- * of its tile bits (C(m, 2) passes for all pairs, m = ceil((L - 4) / 4); with rho2 NULL only the
- * nearest-neighbour pairs are evaluated and rho_k is their partial trace).
+ * of its tile bits (C(m, 2) passes for all pairs, m = ceil((L - 4) / 4); then rho_k is the partial
+ * trace of a nearest-neighbour pair). With rho2 NULL, rho_k is evaluated directly, every site of
+ * a tile at once (ceil((L - 4) / 8) passes).
  * Limits: 2 <= L <= 30. Asynchronous on stream; deterministic (fixed reduction order).
  * Workspace: ed_rdm_workspace(L) bytes (the pair table, 64 L(L-1) bytes, plus per-workgroup sums,
- * about 35 MiB).
+ * about 35 MiB; the single-site path uses part of it).
  * Errors: ED_ERR_ARG (psi or ws NULL, L outside 2..30), ED_ERR_WORKSPACE, ED_ERR_HIP.
  * ---------------------------------------------------------------------------------------- */
 ed_status ed_rdm_workspace(int L, size_t* bytes);
 ed_status ed_rdm(const ed_c64* psi, int L, ed_c64* rho1, ed_c64* rho2, void* ws, size_t ws_bytes, void* stream);
 
-/* Pairs of index bits (p < q) that ed_rdm evaluates for this L, in pass order, with the pass of
- * each; all_pairs = 0 gives the nearest-neighbour plan. Writes min(count, max_pairs) entries of
- * pairs [2 per pair] and pass_of, and returns count (-1 for L outside 2..30). Host only. */
-int ed_rdm_plan_pairs(int L, int all_pairs, int* pairs, int max_pairs, int* pass_of);
+/* Pairs of index bits (p < q) that ed_rdm evaluates for this L when rho2 is requested, in pass
+ * order, with the pass of each. Writes min(count, max_pairs) entries of pairs [2 per pair] and
+ * pass_of, and returns count (-1 for L outside 2..30). Host only. */
+int ed_rdm_plan_pairs(int L, int* pairs, int max_pairs, int* pass_of);
+
+/* Index bits that ed_rdm evaluates for this L when only rho1 is requested, in pass order, with
+ * the pass of each (bit b is site L - b). Writes min(count, max_bits) entries of bits and pass_of
+ * and returns count (= L; -1 for L outside 2..30). Host only. */
+int ed_rdm_plan_sites(int L, int* bits, int max_bits, int* pass_of);
 
 /* ----------------------------------------------------------------------------------------
  * ed_trace_distances: D(a_m, b_m) = 1/2 Tr |a_m - b_m|, |A| = sqrt(A^dagger A) (Sec. V, the

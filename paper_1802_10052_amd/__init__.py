@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import EdError, call, lib
 
-__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "Liouville", "superket", "liouville_measure", "rdm", "rdm_plan", "trace_distances", "eps_local", "eps_corr", "trajectories", "philox_words", "evolve_adjoint", "evolve_loss", "AdjointEvolve", "EdError", "lib"]
+__all__ = ["Model", "apply_H", "lanczos_ground", "krylov_evolve", "measure", "entropy", "Liouville", "superket", "liouville_measure", "rdm", "rdm_plan", "rdm_plan_sites", "trace_distances", "eps_local", "eps_corr", "trajectories", "philox_words", "evolve_adjoint", "evolve_loss", "AdjointEvolve", "EdError", "lib"]
 
 
 def _stream_ptr(stream=None):
@@ -301,15 +301,28 @@ def rdm(psi, L, two_site=True, stream=None):
     return rho1, rho2
 
 
-def rdm_plan(L, all_pairs=True):
-    """The pairs of index bits ed_rdm evaluates, as (pairs [n, 2], pass index [n]) numpy arrays."""
-    n = lib().ed_rdm_plan_pairs(int(L), int(all_pairs), None, 0, None)
+def rdm_plan(L):
+    """The pairs of index bits ed_rdm evaluates for the two-site matrices, as (pairs [n, 2],
+    pass index [n]) numpy arrays."""
+    n = lib().ed_rdm_plan_pairs(int(L), None, 0, None)
     if n < 0:
         raise EdError("ed_rdm_plan_pairs", "ED_ERR_ARG", f"L={L}")
     pairs = np.zeros((n, 2), np.int32)
     pass_of = np.zeros(n, np.int32)
-    lib().ed_rdm_plan_pairs(int(L), int(all_pairs), pairs.ctypes.data, n, pass_of.ctypes.data)
+    lib().ed_rdm_plan_pairs(int(L), pairs.ctypes.data, n, pass_of.ctypes.data)
     return pairs, pass_of
+
+
+def rdm_plan_sites(L):
+    """The index bits ed_rdm evaluates for the single-site matrices alone, as (bits [L],
+    pass index [L]) numpy arrays (bit b is site L - b)."""
+    n = lib().ed_rdm_plan_sites(int(L), None, 0, None)
+    if n < 0:
+        raise EdError("ed_rdm_plan_sites", "ED_ERR_ARG", f"L={L}")
+    bits = np.zeros(n, np.int32)
+    pass_of = np.zeros(n, np.int32)
+    lib().ed_rdm_plan_sites(int(L), bits.ctypes.data, n, pass_of.ctypes.data)
+    return bits, pass_of
 
 
 def trace_distances(a, b):

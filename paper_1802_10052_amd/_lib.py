@@ -140,7 +140,8 @@ def _declare(l):
     _fn(l, "ed_liouville_measure", [P, C.c_int, P, C.POINTER(C.c_double), P, C.c_size_t, P])
     _fn(l, "ed_rdm_workspace", [C.c_int, S])
     _fn(l, "ed_rdm", [P, C.c_int, P, P, P, C.c_size_t, P])
-    _fn(l, "ed_rdm_plan_pairs", [C.c_int, C.c_int, P, C.c_int, P])
+    _fn(l, "ed_rdm_plan_pairs", [C.c_int, P, C.c_int, P])
+    _fn(l, "ed_rdm_plan_sites", [C.c_int, P, C.c_int, P])
     _fn(l, "ed_trace_distances", [C.c_int, C.c_int, P, P, P])
 
 

@@ -13,8 +13,13 @@
 // on chip. The high bits are cut into groups of 4; the tile of groups (a, b) holds every pair of
 // bits inside low + G_a + G_b, so the C(m, 2) tiles cover all pairs (m = ceil((L-4)/4)). Each pair
 // is evaluated in exactly one pass, the passes are balanced, and a pass holds at most 32 pairs
-// (512 threads, 4 pairs per wave, each lane accumulating 16 doubles per pair over all of its
-// tiles: 128 registers). One workgroup per CU is persistent over the tiles of a pass and loads
+// (512 threads, 4 pairs per wave, each lane accumulating the 12 doubles of a pair's upper entries
+// over all of its tiles). Pairs that share bits are evaluated together: the 8 amplitudes of three
+// bits hold two quads of each of the three pairs among them, so a "triangle" of pairs reads 8
+// amplitudes for 6 quads and a "star" of two pairs 8 for 4, where single pairs read 4 per quad.
+// The single-site matrices alone take a path of their own (one 2x2 matrix per bit, every bit of the
+// tile evaluated on chip, ceil((L-4)/8) passes).
+// One workgroup per CU is persistent over the tiles of a pass and loads
 // the next tile into registers while it evaluates the current one from LDS; the reduction runs
 // in a fixed order, so results are bitwise reproducible.
 #include <algorithm>
@@ -39,16 +44,31 @@ constexpr int kRdmVals = 16;         // 4 real diagonal + 6 complex upper entrie
 constexpr int kRdmOff = 12;          // the 6 complex upper entries accumulated per work item
 constexpr int kMaxComp = 30 - kTileBits;  // index bits outside a full tile (L <= 30)
 
+// Wave programs. A wave keeps 4 accumulator slots (12 doubles each) and runs one of these
+// layouts of items over the quads of its tile:
+//   a "cube" item holds three tile bits (a, b, c) and the pairs (a,b), (a,c) (a "star") or also
+//   (b,c) (a "triangle"): each base x (those bits clear) gives 8 amplitudes and 2 quads per pair,
+//   8 LDS reads for up to 6 quads. A pair's quad is accumulated in the order (none, first bit of
+//   the item, second, both); where the first bit is the higher one, the slot is marked swapped
+//   and the reduction exchanges basis states 1 and 2;
+//   a "one" item is a single pair: 4 LDS reads per quad.
+enum RdmLayout { kLayNone = 0, kLayTriOne = 1, kLayCubeCube = 2, kLayCubeOneOne = 3, kLayOnes = 4 };
+
 struct RdmPass {
     int T;                         // tile bits
     int ncomp;                     // index bits outside the tile (L - T)
     int npairs;
-    int nsplit;                    // work items per pair (each takes every nsplit-th run of 64 quads)
     int pos[kTileBits];            // global bit of tile-local bit i, ascending
     int comp[kMaxComp];            // global bits outside the tile, ascending
     int lp[kRdmMaxPairs];          // tile-local bits of each pair, lp < lq
     int lq[kRdmMaxPairs];
     int slot[kRdmMaxPairs];        // position of the pair in the lexicographic list of site pairs
+    int layout[kWaves];            // RdmLayout of each wave
+    int piece[kWaves];             // the wave takes runs r = piece, piece + nsplit, ... of its bases
+    int nsplit[kWaves];
+    int ib[kWaves][4][3];          // tile bits of the wave's items (cube: a, b, c; one: lp, lq)
+    int wpair[kWaves][4];          // pair index held by each accumulator slot, -1 if none
+    int wswap[kWaves][4];          // 1 if the slot's quads list the pair's higher bit first
 };
 
 // index of the site pair (k, j), 1 <= k < j <= L, in lexicographic order
@@ -75,11 +95,71 @@ __host__ __device__ inline int insert_two(int j, int lo, int hi) {
     return ((x >> hi) << (hi + 1)) | (x & ((1 << hi) - 1));
 }
 
+// insert zero bits at positions a < b < c
+__host__ __device__ inline int insert_three(int j, int a, int b, int c) {
+    const int x = insert_two(j, a, b);
+    return ((x >> c) << (c + 1)) | (x & ((1 << c) - 1));
+}
+
+// One pair (bits lp < lq) into accumulator slot S over the quads of rows r = piece, piece + ns, ...
+// (quad j = lane + 64 r; its base is insert(lane) | insert(64 r), disjoint bits).
+template <int S, bool FULL>
+__device__ __forceinline__ void run_one(double (&acc)[kRdmPairsPerWave][kRdmOff], const double2* s, int lane,
+                                        int lp, int lq, int piece, int ns, int nq) {
+    const int P = 1 << lp, Q = 1 << lq;
+    const int rows = FULL ? (1 << (kTileBits - 2)) / 64 : (nq + 63) / 64;
+    const int xl = insert_two(lane, lp, lq);
+    int r = piece;
+    if (FULL) {  // two quads per round: the second one's reads overlap the first one's FMAs
+        for (; r + ns < rows; r += 2 * ns) {
+            const double2* qa = s + (xl | insert_two(64 * r, lp, lq));
+            const double2* qb = s + (xl | insert_two(64 * (r + ns), lp, lq));
+            const double2 a0 = qa[0], a1 = qa[P], a2 = qa[Q], a3 = qa[P + Q];
+            const double2 b0 = qb[0], b1 = qb[P], b2 = qb[Q], b3 = qb[P + Q];
+            quad_accumulate(acc[S], a0, a1, a2, a3);
+            quad_accumulate(acc[S], b0, b1, b2, b3);
+        }
+    }
+    for (; r < rows; r += ns) {
+        if (!FULL && lane + 64 * r >= nq) continue;
+        const double2* q = s + (xl | insert_two(64 * r, lp, lq));
+        quad_accumulate(acc[S], q[0], q[P], q[Q], q[P + Q]);
+    }
+}
+
+// The pairs (a,b), (a,c) and, if TRI, (b,c) of the item bits a, b, c (distinct, in any order) into
+// slots S0, S0 + 1, S0 + 2 (full tiles: 512 bases, 8 rows of 64). y[k] = amplitude at
+// base + (k & 1) A + ((k >> 1) & 1) B + (k >> 2) C.
+template <bool TRI, int S0>
+__device__ __forceinline__ void run_cube(double (&acc)[kRdmPairsPerWave][kRdmOff], const double2* s, int lane,
+                                         const int* bits, int piece, int ns) {
+    const int a = bits[0], b = bits[1], c = bits[2];
+    const int lo = min(a, min(b, c)), hi = max(a, max(b, c)), mid = a + b + c - lo - hi;
+    const int A = 1 << a, B = 1 << b, C = 1 << c;
+    const int xl = insert_three(lane, lo, mid, hi);
+    for (int r = piece; r < (1 << (kTileBits - 3)) / 64; r += ns) {
+        const double2* q = s + (xl | insert_three(64 * r, lo, mid, hi));
+        const double2 y0 = q[0], y1 = q[A], y2 = q[B], y3 = q[A + B];
+        const double2 y4 = q[C], y5 = q[A + C], y6 = q[B + C], y7 = q[A + B + C];
+        quad_accumulate(acc[S0], y0, y1, y2, y3);
+        quad_accumulate(acc[S0], y4, y5, y6, y7);
+        quad_accumulate(acc[S0 + 1], y0, y1, y4, y5);
+        quad_accumulate(acc[S0 + 1], y2, y3, y6, y7);
+        if (TRI) {
+            quad_accumulate(acc[S0 + 2], y0, y2, y4, y6);
+            quad_accumulate(acc[S0 + 2], y1, y3, y5, y7);
+        }
+    }
+}
+
 // FULL: 2^12-amplitude tiles (L >= 12); otherwise the whole state (2^L < 4096) is one tile
 template <bool FULL>
 __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restrict__ psi, RdmPass pa, int64_t ntiles,
                                                         double* __restrict__ part, double* __restrict__ hist) {
     __shared__ double2 s[1 << kTileBits];
+    // |psi|^2 of each tile position, summed over the workgroup's tiles (the diagonal of every pair's
+    // matrix is a marginal of these); position y is owned by thread y mod 512
+    __shared__ double sh[1 << kTileBits];
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: pair data in scalar registers
     const int tsize = FULL ? (1 << kTileBits) : (1 << pa.T);
@@ -97,8 +177,7 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
             if ((FULL || kThreadBits + b < pa.T) && ((k >> b) & 1)) o |= int64_t(1) << pa.pos[kThreadBits + b];
         soff[k] = o;
     }
-    // work item i = pair (i % npairs), part (i / npairs); wave w takes items w, w + 8, ...
-    const int nitems = pa.npairs * pa.nsplit;
+    const int layout = pa.layout[wave], piece = pa.piece[wave], ns = pa.nsplit[wave];
     double acc[kRdmPairsPerWave][kRdmOff];
 #pragma unroll
     for (int w = 0; w < kRdmPairsPerWave; ++w)
@@ -108,11 +187,9 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
     // the next tile is loaded into registers while the current one is evaluated from LDS; eight
     // named registers (an array that lives across the evaluation loop is placed in scratch memory)
     double2 v0, v1, v2, v3, v4, v5, v6, v7;
-    // |psi|^2 of each of the thread's tile positions, summed over its tiles (the diagonal of every
-    // pair's matrix is a marginal of these)
-    double h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0, h6 = 0, h7 = 0;
 #define ED_SLOT(k) (k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : k == 3 ? v3 : k == 4 ? v4 : k == 5 ? v5 : k == 6 ? v6 : v7)
-#define ED_HIST(k) (k == 0 ? h0 : k == 1 ? h1 : k == 2 ? h2 : k == 3 ? h3 : k == 4 ? h4 : k == 5 ? h5 : k == 6 ? h6 : h7)
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) sh[t + (k << kThreadBits)] = 0.0;
     int64_t n = blockIdx.x;
     if (n < ntiles) {
         int64_t base = off_t;
@@ -130,7 +207,8 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
             if (FULL || (k << kThreadBits) + t < tsize) {
                 const double2 a = ED_SLOT(k);
                 s[t + (k << kThreadBits)] = a;
-                ED_HIST(k) = fma(a.x, a.x, fma(a.y, a.y, ED_HIST(k)));
+                double& h = sh[t + (k << kThreadBits)];
+                h = fma(a.x, a.x, fma(a.y, a.y, h));
             }
         __syncthreads();
         const int64_t nn = n + gridDim.x;
@@ -142,45 +220,35 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
 #pragma unroll
             for (int k = 0; k < kSlots; ++k) ED_SLOT(k) = psi[base + soff[k]];  // FULL only: ntiles > 1
         }
-        const int rows = FULL ? (1 << (kTileBits - 2)) / 64 : ((tsize >> 2) + 63) / 64;  // runs of 64 quads
-#pragma unroll
-        for (int w = 0; w < kRdmPairsPerWave; ++w) {
-            const int it = wave + kWaves * w;
-            if (it < nitems) {  // uniform over the wave
-                const int pi = it % pa.npairs, piece = it / pa.npairs;
-                const int lp = pa.lp[pi], lq = pa.lq[pi];
-                const int P = 1 << lp, Q = 1 << lq;
-                // quad j = lane + 64 r: its base index is insert(lane) | insert(64 r) (disjoint bits)
-                const int xl = insert_two(lane, lp, lq);
-                int r = piece;
-                if (FULL) {  // two quads per round: the second one's reads overlap the first one's FMAs
-                    for (; r + pa.nsplit < rows; r += 2 * pa.nsplit) {
-                        const double2* qa = s + (xl | insert_two(64 * r, lp, lq));
-                        const double2* qb = s + (xl | insert_two(64 * (r + pa.nsplit), lp, lq));
-                        const double2 a0 = qa[0], a1 = qa[P], a2 = qa[Q], a3 = qa[P + Q];
-                        const double2 b0 = qb[0], b1 = qb[P], b2 = qb[Q], b3 = qb[P + Q];
-                        quad_accumulate(acc[w], a0, a1, a2, a3);
-                        quad_accumulate(acc[w], b0, b1, b2, b3);
-                    }
-                }
-                for (; r < rows; r += pa.nsplit) {
-                    if (!FULL && lane + 64 * r >= (tsize >> 2)) continue;
-                    const double2* q = s + (xl | insert_two(64 * r, lp, lq));
-                    quad_accumulate(acc[w], q[0], q[P], q[Q], q[P + Q]);
-                }
-            }
+        const int nq = tsize >> 2;  // quads of one pair in one tile
+        const int(*ib)[3] = pa.ib[wave];
+        if (FULL && layout == kLayTriOne) {  // uniform over the wave
+            run_cube<true, 0>(acc, s, lane, ib[0], piece, ns);
+            if (pa.wpair[wave][3] >= 0) run_one<3, FULL>(acc, s, lane, ib[1][0], ib[1][1], piece, ns, nq);
+        } else if (FULL && layout == kLayCubeCube) {
+            run_cube<false, 0>(acc, s, lane, ib[0], piece, ns);
+            if (pa.wpair[wave][2] >= 0) run_cube<false, 2>(acc, s, lane, ib[1], piece, ns);
+        } else if (FULL && layout == kLayCubeOneOne) {
+            run_cube<false, 0>(acc, s, lane, ib[0], piece, ns);
+            if (pa.wpair[wave][2] >= 0) run_one<2, FULL>(acc, s, lane, ib[1][0], ib[1][1], piece, ns, nq);
+            if (pa.wpair[wave][3] >= 0) run_one<3, FULL>(acc, s, lane, ib[2][0], ib[2][1], piece, ns, nq);
+        } else if (layout == kLayOnes) {
+            if (pa.wpair[wave][0] >= 0) run_one<0, FULL>(acc, s, lane, ib[0][0], ib[0][1], piece, ns, nq);
+            if (pa.wpair[wave][1] >= 0) run_one<1, FULL>(acc, s, lane, ib[1][0], ib[1][1], piece, ns, nq);
+            if (pa.wpair[wave][2] >= 0) run_one<2, FULL>(acc, s, lane, ib[2][0], ib[2][1], piece, ns, nq);
+            if (pa.wpair[wave][3] >= 0) run_one<3, FULL>(acc, s, lane, ib[3][0], ib[3][1], piece, ns, nq);
         }
     }
 #pragma unroll
     for (int k = 0; k < kSlots; ++k)
-        if (FULL || (k << kThreadBits) + t < tsize) hist[size_t(blockIdx.x) * (1 << kTileBits) + t + (k << kThreadBits)] = ED_HIST(k);
+        if (FULL || (k << kThreadBits) + t < tsize)
+            hist[size_t(blockIdx.x) * (1 << kTileBits) + t + (k << kThreadBits)] = sh[t + (k << kThreadBits)];
 #undef ED_SLOT
-#undef ED_HIST
     // fixed-order butterfly over the wave, then one row per (pair, workgroup)
 #pragma unroll
     for (int w = 0; w < kRdmPairsPerWave; ++w) {
-        const int it = wave + kWaves * w;
-        if (it >= nitems) continue;
+        if (pa.wpair[wave][w] < 0) continue;
+        const int it = wave * kRdmPairsPerWave + w;
 #pragma unroll
         for (int e = 0; e < kRdmOff; ++e) {
             double x = acc[w][e];
@@ -203,7 +271,8 @@ __global__ void rdm_hist_reduce(const double* __restrict__ hist, int nblocks, in
 
 // one workgroup per pair of the pass: the table row's diagonal is the marginal of H over the
 // pair's two tile bits (strided partial sums, then a fixed LDS tree); the upper entries are the
-// sums of the per-workgroup rows of the pair's work items (parts, then workgroups, in order)
+// sums of the per-workgroup rows of the accumulator slots holding the pair (slots, then
+// workgroups, in order)
 __global__ __launch_bounds__(256) void rdm_reduce(const double* __restrict__ part, int nblocks, RdmPass pa,
                                                   const double* __restrict__ H, double* __restrict__ table) {
     __shared__ double red[4][256];
@@ -228,14 +297,178 @@ __global__ __launch_bounds__(256) void rdm_reduce(const double* __restrict__ par
     double* row = table + size_t(pa.slot[pi]) * kRdmVals;
     if (t < 4) row[t] = red[t][0];
     if (t >= 4 && t < kRdmVals) {
-        const int e = t - 4;
+        const int e = t - 4, o = e >> 1;
+        // a swapped slot holds the entries in the basis with states 1 and 2 exchanged: entry
+        // (0,1) is at (0,2), (0,2) at (0,1), (1,3) at (2,3), (2,3) at (1,3), and (1,2) is the
+        // conjugate of the stored one
+        constexpr int kSwapFrom[6] = {1, 0, 2, 3, 5, 4};
+        const int e_sw = 2 * kSwapFrom[o] + (e & 1);
+        const double sign_sw = (o == 3 && (e & 1)) ? -1.0 : 1.0;
         double sum = 0.0;
-        for (int pt = 0; pt < pa.nsplit; ++pt) {
-            const size_t it = size_t(pt) * pa.npairs + pi;
+        for (int it = 0; it < kWaves * kRdmPairsPerWave; ++it) {  // the slots holding this pair, in order
+            const int w = it / kRdmPairsPerWave, k = it % kRdmPairsPerWave;
+            if (pa.wpair[w][k] != pi) continue;
+            const bool sw = pa.wswap[w][k] != 0;
+            const int src = sw ? e_sw : e;
+            double acc = 0.0;
 #pragma unroll 8
-            for (int g = 0; g < nblocks; ++g) sum += part[(it * nblocks + g) * kRdmOff + e];
+            for (int g = 0; g < nblocks; ++g) acc += part[(size_t(it) * nblocks + g) * kRdmOff + src];
+            sum += sw ? sign_sw * acc : acc;
         }
         row[t] = sum;
+    }
+}
+
+// ---------------------------------------------------------------------------- single sites
+// rho_k alone: for the site at bit b, rho_k[0][0] = sum |psi(x)|^2, rho_k[1][1] = sum |psi(x|B)|^2
+// and rho_k[0][1] = sum psi(x) psi^*(x|B) over the x with bit b clear (Sec. IV, one kept site).
+// A pass evaluates the bits of its tile that no earlier pass has: the 4 low bits and 8 others in
+// the first pass, 8 others in each later one (ceil((L - 4) / 8) passes).
+constexpr int kRdm1Vals = 4;  // d0, d1, Re c, Im c
+
+struct Rdm1Pass {
+    int T, ncomp, nbits;
+    int pos[kTileBits];
+    int comp[kMaxComp];
+    int lb[kTileBits];  // tile-local bits evaluated by the pass
+    int gb[kTileBits];  // their global bits
+};
+
+__device__ __forceinline__ void site_accumulate(double* a, double2 x, double2 y) {
+    a[0] = fma(x.x, x.x, fma(x.y, x.y, a[0]));
+    a[1] = fma(y.x, y.x, fma(y.y, y.y, a[1]));
+    a[2] = fma(x.x, y.x, fma(x.y, y.y, a[2]));
+    a[3] = fma(x.y, y.x, fma(-x.x, y.y, a[3]));
+}
+
+// Thread t owns tile positions t + 512 k (k = 0..7). For a bit b >= 9 both amplitudes of a pair
+// are the thread's own; for b < 9 the thread with bit b clear takes slots 0..3 and its partner
+// thread slots 4..7, each reading the other amplitude from LDS. Smaller tiles (L < 12) take every
+// pair from LDS in the thread that owns x.
+template <bool FULL>
+__global__ __launch_bounds__(kRdmThreads) void rdm1_pass(const double2* __restrict__ psi, Rdm1Pass pa, int64_t ntiles,
+                                                         double* __restrict__ part) {
+    __shared__ double2 s[1 << kTileBits];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int tsize = FULL ? (1 << kTileBits) : (1 << pa.T);
+    int64_t off_t = 0;
+#pragma unroll
+    for (int b = 0; b < kThreadBits; ++b)
+        if ((FULL || b < pa.T) && ((t >> b) & 1)) off_t |= int64_t(1) << pa.pos[b];
+    int64_t soff[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+        int64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < kTileBits - kThreadBits; ++b)
+            if ((FULL || kThreadBits + b < pa.T) && ((k >> b) & 1)) o |= int64_t(1) << pa.pos[kThreadBits + b];
+        soff[k] = o;
+    }
+    double acc[kTileBits][kRdm1Vals];
+#pragma unroll
+    for (int i = 0; i < kTileBits; ++i)
+#pragma unroll
+        for (int e = 0; e < kRdm1Vals; ++e) acc[i][e] = 0.0;
+    double2 v0, v1, v2, v3, v4, v5, v6, v7;
+#define ED_SLOT(k) (k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : k == 3 ? v3 : k == 4 ? v4 : k == 5 ? v5 : k == 6 ? v6 : v7)
+    int64_t n = blockIdx.x;
+    if (n < ntiles) {
+        int64_t base = off_t;
+#pragma unroll
+        for (int b = 0; b < kMaxComp; ++b)
+            if (b < pa.ncomp && ((n >> b) & 1)) base |= int64_t(1) << pa.comp[b];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+            if (FULL || (k << kThreadBits) + t < tsize) ED_SLOT(k) = psi[base + soff[k]];
+    }
+    for (; n < ntiles; n += gridDim.x) {
+        __syncthreads();  // the previous tile has been read
+        double2 own[kSlots];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+            if (FULL || (k << kThreadBits) + t < tsize) {
+                own[k] = ED_SLOT(k);
+                s[t + (k << kThreadBits)] = own[k];
+            }
+        __syncthreads();
+        const int64_t nn = n + gridDim.x;
+        if (nn < ntiles) {
+            int64_t base = off_t;
+#pragma unroll
+            for (int b = 0; b < kMaxComp; ++b)
+                if (b < pa.ncomp && ((nn >> b) & 1)) base |= int64_t(1) << pa.comp[b];
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) ED_SLOT(k) = psi[base + soff[k]];  // FULL only: ntiles > 1
+        }
+#pragma unroll
+        for (int i = 0; i < kTileBits; ++i) {
+            if (i >= pa.nbits) continue;  // uniform; no break, so that acc stays in registers
+            const int b = pa.lb[i], B = 1 << b;
+            if (!FULL) {
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) {
+                    const int y = t + (k << kThreadBits);
+                    if (y < tsize && !(y & B)) site_accumulate(acc[i], s[y], s[y | B]);
+                }
+            } else if (b >= kThreadBits) {  // both amplitudes in the thread's registers
+                const int kb = b - kThreadBits;
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) {
+                    if (kb == 0 && !(k & 1)) site_accumulate(acc[i], own[k], own[k | 1]);
+                    if (kb == 1 && !(k & 2)) site_accumulate(acc[i], own[k], own[k | 2]);
+                    if (kb == 2 && !(k & 4)) site_accumulate(acc[i], own[k], own[k | 4]);
+                }
+            } else if (!(t & B)) {  // x is ours: slots 0..3
+#pragma unroll
+                for (int k = 0; k < kSlots / 2; ++k)
+                    site_accumulate(acc[i], own[k], s[(t | B) + (k << kThreadBits)]);
+            } else {  // x|B is ours: slots 4..7
+#pragma unroll
+                for (int k = kSlots / 2; k < kSlots; ++k)
+                    site_accumulate(acc[i], s[(t ^ B) + (k << kThreadBits)], own[k]);
+            }
+        }
+    }
+#undef ED_SLOT
+    // fixed-order butterfly over the wave, one row per (workgroup, wave, bit)
+#pragma unroll
+    for (int i = 0; i < kTileBits; ++i) {
+        if (i >= pa.nbits) continue;
+#pragma unroll
+        for (int e = 0; e < kRdm1Vals; ++e) {
+            double x = acc[i][e];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            if (lane == 0) part[((size_t(blockIdx.x) * kWaves + wave) * kTileBits + i) * kRdm1Vals + e] = x;
+        }
+    }
+}
+
+// one workgroup per evaluated bit: strided partial sums over (workgroup, wave) rows and a fixed
+// LDS tree, then rho_k of the bit's site k = L - b
+__global__ __launch_bounds__(256) void rdm1_reduce(const double* __restrict__ part, int nrows, Rdm1Pass pa, int L,
+                                                   double2* __restrict__ rho1) {
+    __shared__ double red[kRdm1Vals][256];
+    const int i = blockIdx.x, t = threadIdx.x;
+    double d[kRdm1Vals] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = t; r < nrows; r += 256)
+#pragma unroll
+        for (int e = 0; e < kRdm1Vals; ++e) d[e] += part[(size_t(r) * kTileBits + i) * kRdm1Vals + e];
+#pragma unroll
+    for (int e = 0; e < kRdm1Vals; ++e) red[e][t] = d[e];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+#pragma unroll
+            for (int e = 0; e < kRdm1Vals; ++e) red[e][t] += red[e][t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double2* o = rho1 + size_t(L - 1 - pa.gb[i]) * 4;
+        o[0] = make_double2(red[0][0], 0.0);
+        o[1] = make_double2(red[2][0], red[3][0]);
+        o[2] = make_double2(red[2][0], -red[3][0]);
+        o[3] = make_double2(red[1][0], 0.0);
     }
 }
 
@@ -293,9 +526,178 @@ __global__ void rdm_expand(const double* __restrict__ table, int L, int npairs, 
 }
 
 // ---------------------------------------------------------------------------- planning
-// Tile bit sets and the pairs each pass evaluates. all_pairs: every pair of bits; otherwise the
-// bonds (p, p+1) only, which is what the single-site matrices need.
-std::vector<RdmPass> rdm_plan(int L, bool all_pairs) {
+// Items of one pass (pairs pa.lp/pa.lq): with full tiles, up to max_tri triangles (three pairs on
+// three bits), then stars (two pairs sharing a bit, as a cube item with two pairs), then single
+// pairs; packed into wave layouts, at most 4 accumulator slots per wave. A pass with few waves
+// repeats them with the bases split between the copies. Returns false if more than kWaves waves
+// would be needed.
+bool pack_waves(RdmPass& pa, bool full, int max_tri) {
+    const int n = pa.npairs;
+    struct Item {
+        int kind;     // 3 cube, 1 one
+        int bits[3];  // cube: a, b, c (pairs (a,b), (a,c), (b,c)); one: lp, lq
+        int pairs[3]; // pair indices in slot order
+        int swap[3];  // slot lists the pair's higher bit first
+        int npair;
+    };
+    auto find = [&](int a, int b, const std::vector<bool>& used) {
+        if (a > b) std::swap(a, b);
+        for (int i = 0; i < n; ++i)
+            if (!used[i] && pa.lp[i] == a && pa.lq[i] == b) return i;
+        return -1;
+    };
+    std::vector<bool> used(n, false);
+    std::vector<Item> tris, stars, ones;
+    // the pairs of a cube item on bits (x, y, z): (x,y), (x,z) and, for a triangle, (y,z)
+    auto cube_of = [&](int x, int y, int z, const std::vector<int>& members) {
+        Item it{};
+        it.kind = 3;
+        it.bits[0] = x;
+        it.bits[1] = y;
+        it.bits[2] = z;
+        const int pr[3][2] = {{x, y}, {x, z}, {y, z}};
+        for (int k = 0; k < int(members.size()); ++k) {
+            const int u = pr[k][0], v = pr[k][1];
+            int found = -1;
+            for (int m : members)
+                if (pa.lp[m] == std::min(u, v) && pa.lq[m] == std::max(u, v)) found = m;
+            it.pairs[it.npair] = found;
+            it.swap[it.npair++] = u > v;
+        }
+        return it;
+    };
+    if (full) {
+        for (int i = 0; i < n && int(tris.size()) < max_tri; ++i) {
+            if (used[i]) continue;
+            for (int r = 0; r < pa.T; ++r) {
+                if (r == pa.lp[i] || r == pa.lq[i]) continue;
+                const int j = find(pa.lp[i], r, used), k = find(pa.lq[i], r, used);
+                if (j < 0 || k < 0 || j == i || k == i) continue;
+                used[i] = used[j] = used[k] = true;
+                tris.push_back(cube_of(pa.lp[i], pa.lq[i], r, {i, j, k}));
+                break;
+            }
+        }
+    }
+    if (full) {
+        for (int i = 0; i < n; ++i) {
+            if (used[i]) continue;
+            for (int j = i + 1; j < n; ++j) {
+                if (used[j]) continue;
+                const int a = pa.lp[i], b = pa.lq[i], c = pa.lp[j], d = pa.lq[j];
+                const int shared = (a == c) + (a == d) + (b == c) + (b == d);
+                if (shared != 1) continue;
+                const int shared_bit = (a == c || a == d) ? a : b;
+                const int u = shared_bit == a ? b : a, v = (c == shared_bit) ? d : c;
+                used[i] = used[j] = true;
+                stars.push_back(cube_of(shared_bit, u, v, {i, j}));
+                break;
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (!used[i]) {
+            Item it{};
+            it.kind = 1;
+            it.bits[0] = pa.lp[i];
+            it.bits[1] = pa.lq[i];
+            it.pairs[0] = i;
+            it.npair = 1;
+            ones.push_back(it);
+        }
+    struct Wave {
+        int layout;
+        std::vector<Item> items;
+    };
+    std::vector<Wave> waves;
+    for (const Item& t : tris) waves.push_back({kLayTriOne, {t}});
+    for (size_t i = 0; i + 1 < stars.size(); i += 2) waves.push_back({kLayCubeCube, {stars[i], stars[i + 1]}});
+    if (stars.size() % 2) waves.push_back({kLayCubeOneOne, {stars.back()}});
+    size_t next = 0;
+    for (Wave& w : waves) {
+        const size_t room = w.layout == kLayTriOne ? 1 : (w.layout == kLayCubeOneOne ? 2 : 0);
+        for (size_t k = 0; k < room && next < ones.size(); ++k) w.items.push_back(ones[next++]);
+    }
+    while (next < ones.size()) {
+        Wave w{kLayOnes, {}};
+        for (int k = 0; k < 4 && next < ones.size(); ++k) w.items.push_back(ones[next++]);
+        waves.push_back(w);
+    }
+    if (int(waves.size()) > kWaves) return false;
+    const int W = int(waves.size());
+    const int copies = W > 0 ? std::max(1, kWaves / W) : 1;
+    for (int w = 0; w < kWaves; ++w) {
+        pa.layout[w] = kLayNone;
+        for (int k = 0; k < 4; ++k) {
+            pa.wpair[w][k] = -1;
+            pa.wswap[w][k] = 0;
+        }
+    }
+    for (int c = 0; c < copies; ++c)
+        for (int w = 0; w < W; ++w) {
+            const int dst = w + c * W;
+            const Wave& src = waves[w];
+            pa.layout[dst] = src.layout;
+            pa.piece[dst] = c;
+            pa.nsplit[dst] = copies;
+            int slot = 0;
+            for (size_t k = 0; k < src.items.size(); ++k) {
+                const Item& it = src.items[k];
+                for (int b = 0; b < 3; ++b) pa.ib[dst][k][b] = it.bits[b];
+                // slots: a triangle takes 0-2 and its single 3; stars take 0-1 and 2-3
+                if (src.layout == kLayTriOne && it.kind == 1) slot = 3;
+                for (int m = 0; m < it.npair; ++m) {
+                    pa.wswap[dst][slot] = it.swap[m];
+                    pa.wpair[dst][slot++] = it.pairs[m];
+                }
+            }
+        }
+    return true;
+}
+
+
+// Single-site passes: the 4 low bits in every tile, the other bits in chunks of 8 (a short last
+// chunk is filled up with bits evaluated before).
+std::vector<Rdm1Pass> rdm1_plan(int L) {
+    const int T = std::min(L, kTileBits);
+    const int c = std::min(kRdmLowBits, T);
+    const int W = T - c;
+    std::vector<Rdm1Pass> passes;
+    for (int first = c; first < L || passes.empty(); first += std::max(W, 1)) {
+        Rdm1Pass pa{};
+        pa.T = T;
+        std::vector<bool> in(L, false), eval(L, false);
+        for (int b = 0; b < c; ++b) {
+            in[b] = true;
+            eval[b] = passes.empty();
+        }
+        for (int b = first; b < std::min(L, first + W); ++b) in[b] = eval[b] = true;
+        int cnt = 0;
+        for (int b = 0; b < L; ++b) cnt += in[b];
+        for (int b = c; b < L && cnt < T; ++b)
+            if (!in[b]) {
+                in[b] = true;
+                ++cnt;
+            }
+        int i = 0;
+        for (int b = 0; b < L; ++b)
+            if (in[b]) {
+                if (eval[b]) {
+                    pa.lb[pa.nbits] = i;
+                    pa.gb[pa.nbits++] = b;
+                }
+                pa.pos[i++] = b;
+            } else {
+                pa.comp[pa.ncomp++] = b;
+            }
+        passes.push_back(pa);
+        if (W == 0) break;
+    }
+    return passes;
+}
+
+// Tile bit sets and the pairs each pass evaluates (every pair of bits).
+std::vector<RdmPass> rdm_plan(int L) {
     const int T = std::min(L, kTileBits);
     const int c = std::min(kRdmLowBits, T);
     const int W = T - c;
@@ -341,7 +743,6 @@ std::vector<RdmPass> rdm_plan(int L, bool all_pairs) {
     std::vector<Req> reqs;
     for (int p = 0; p < L; ++p)
         for (int q = p + 1; q < L; ++q) {
-            if (!all_pairs && q != p + 1) continue;
             Req r{p, q, {}};
             if (nsets == 1) {
                 r.cand.push_back(0);
@@ -362,21 +763,9 @@ std::vector<RdmPass> rdm_plan(int L, bool all_pairs) {
                      [](const Req& x, const Req& y) { return x.cand.size() < y.cand.size(); });
     std::vector<std::vector<std::pair<int, int>>> members(nsets);
     for (const Req& r : reqs) {
-        // all pairs: the least loaded candidate (balanced passes); bonds only: a candidate that is
-        // already in use, so that as few tiles as possible are streamed
-        int best = -1;
-        for (int s : r.cand) {
-            if (best < 0) {
-                best = s;
-                continue;
-            }
-            const bool s_used = !members[s].empty(), b_used = !members[best].empty();
-            if (!all_pairs && s_used != b_used) {
-                if (s_used) best = s;
-                continue;
-            }
-            if (members[s].size() < members[best].size()) best = s;
-        }
+        int best = -1;  // the least loaded candidate: balanced passes
+        for (int s : r.cand)
+            if (best < 0 || members[s].size() < members[best].size()) best = s;
         members[best].push_back({r.p, r.q});
     }
     std::vector<RdmPass> passes;
@@ -397,14 +786,16 @@ std::vector<RdmPass> rdm_plan(int L, bool all_pairs) {
             for (int b = 0; b < L; ++b)
                 if (local[b] < 0) pa.comp[pa.ncomp++] = b;
             pa.npairs = hi - lo;
-            // passes with few pairs split each pair's quads over several work items
-            pa.nsplit = std::max(1, std::min(kRdmMaxPairs / pa.npairs, std::max(1, (1 << (T - 2)) / 64)));
             for (int i = lo; i < hi; ++i) {
                 const int p = mem[i].first, q = mem[i].second;
                 pa.lp[i - lo] = local[p];
                 pa.lq[i - lo] = local[q];
                 pa.slot[i - lo] = pair_slot(L - q, L - p, L);
             }
+            // as many triangles as still fit in the waves; pairs one by one always fit
+            bool packed = false;
+            for (int mt = kRdmMaxPairs / 3; mt >= 0 && !packed; --mt) packed = pack_waves(pa, T == kTileBits, mt);
+            if (!packed) pack_waves(pa, false, 0);
             passes.push_back(pa);
         }
     }
@@ -430,15 +821,30 @@ int rdm_blocks(int64_t ntiles) {
 
 using namespace ed;
 
-extern "C" int ed_rdm_plan_pairs(int L, int all_pairs, int* pairs, int max_pairs, int* pass_of) {
+extern "C" int ed_rdm_plan_pairs(int L, int* pairs, int max_pairs, int* pass_of) {
     if (L < 2 || L > 30) return -1;
-    const std::vector<RdmPass> ps = rdm_plan(L, all_pairs != 0);
+    const std::vector<RdmPass> ps = rdm_plan(L);
     int n = 0;
     for (int i = 0; i < int(ps.size()); ++i)
         for (int j = 0; j < ps[i].npairs; ++j) {
             if (n < max_pairs && pairs && pass_of) {
                 pairs[2 * n] = ps[i].pos[ps[i].lp[j]];
                 pairs[2 * n + 1] = ps[i].pos[ps[i].lq[j]];
+                pass_of[n] = i;
+            }
+            ++n;
+        }
+    return n;
+}
+
+extern "C" int ed_rdm_plan_sites(int L, int* bits, int max_bits, int* pass_of) {
+    if (L < 2 || L > 30) return -1;
+    const std::vector<Rdm1Pass> ps = rdm1_plan(L);
+    int n = 0;
+    for (int i = 0; i < int(ps.size()); ++i)
+        for (int j = 0; j < ps[i].nbits; ++j) {
+            if (n < max_bits && bits && pass_of) {
+                bits[n] = ps[i].gb[j];
                 pass_of[n] = i;
             }
             ++n;
@@ -465,8 +871,26 @@ extern "C" ed_status ed_rdm(const ed_c64* psi, int L, ed_c64* rho1, ed_c64* rho2
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + table_bytes(L));
     double* hist = part + part_bytes() / sizeof(double);
     double* H = hist + size_t(kRdmMaxBlocks) * (size_t(1) << kTileBits);
-    const std::vector<RdmPass> passes = rdm_plan(L, rho2 != nullptr);
     const double2* p = reinterpret_cast<const double2*>(psi);
+    if (!rho2) {
+        static_assert(size_t(kRdmMaxBlocks) * kWaves * kTileBits * kRdm1Vals <= size_t(kRdmMaxPairs) * kRdmMaxBlocks * kRdmOff,
+                      "single-site rows fit the pair accumulator area");
+        for (const Rdm1Pass& pa : rdm1_plan(L)) {
+            const int64_t ntiles = int64_t(1) << pa.ncomp;
+            const int G = rdm_blocks(ntiles);
+            if (pa.T == kTileBits) {
+                hipLaunchKernelGGL(rdm1_pass<true>, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part);
+            } else {
+                hipLaunchKernelGGL(rdm1_pass<false>, dim3(G), dim3(kRdmThreads), 0, s, p, pa, ntiles, part);
+            }
+            ED_HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL(rdm1_reduce, dim3(pa.nbits), dim3(256), 0, s, part, G * kWaves, pa, L,
+                               reinterpret_cast<double2*>(rho1));
+            ED_HIP_TRY(hipGetLastError());
+        }
+        return ED_OK;
+    }
+    const std::vector<RdmPass> passes = rdm_plan(L);
     for (const RdmPass& pa : passes) {
         const int64_t ntiles = int64_t(1) << pa.ncomp;
         const int G = rdm_blocks(ntiles);

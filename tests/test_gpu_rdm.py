@@ -62,10 +62,12 @@ def test_rdm_product_state_L28():
     psi, phis = _product_state(L, 8)
     r1, r2 = P.rdm(psi, L)
     r1, r2 = r1.cpu().numpy(), r2.cpu().numpy()
+    s1 = P.rdm(psi, L, two_site=False)[0].cpu().numpy()   # the single-site path: 3 passes
     del psi
     torch.cuda.empty_cache()
     for k in range(1, L + 1):
         assert np.abs(r1[k - 1] - np.outer(phis[k - 1], phis[k - 1].conj())).max() < 1e-12
+        assert np.abs(s1[k - 1] - np.outer(phis[k - 1], phis[k - 1].conj())).max() < 1e-12
         for j in range(k + 1, L + 1):
             v = np.kron(phis[k - 1], phis[j - 1])
             assert np.abs(r2[OR.pair_index(k, j, L)] - np.outer(v, v.conj())).max() < 1e-12, (k, j)
@@ -88,26 +90,32 @@ def test_rdm_L26_sampled_pairs():
     psi_d = E.random_state_device(L, 6, DEV)
     r1, r2 = P.rdm(psi_d, L)
     r1, r2 = r1.cpu().numpy(), r2.cpu().numpy()
+    s1 = P.rdm(psi_d, L, two_site=False)[0].cpu().numpy()
     psi = psi_d.cpu().numpy()
     del psi_d
     torch.cuda.empty_cache()
     for (k, j) in [(25, 26), (23, 26), (1, 2), (1, 26), (12, 13), (5, 17), (9, 21), (2, 3), (13, 22)]:
         ref = OR.rdm(psi, L, [k, j])
         assert np.abs(r2[OR.pair_index(k, j, L)] - ref).max() < 1e-12, (k, j)
-    for k in [1, 7, 13, 22, 26]:
-        assert np.abs(r1[k - 1] - OR.rdm(psi, L, [k])).max() < 1e-12, k
+    for k in [1, 7, 13, 22, 26]:   # sites of all three single-site passes
+        ref = OR.rdm(psi, L, [k])
+        assert np.abs(r1[k - 1] - ref).max() < 1e-12, k
+        assert np.abs(s1[k - 1] - ref).max() < 1e-12, k
 
 
 def test_rdm_L28_consistency():
     """Random L = 28 state: Hermitian, positive, trace <psi|psi>, every partial trace of every
-    rho_{k,j} equals rho_k (pairs from different passes must agree), and the diagonal of rho_k
-    gives the <sigma^z_k> of ed_measure."""
+    rho_{k,j} equals rho_k (pairs from different passes must agree), the direct single-site
+    matrices equal those partial traces, and the diagonal of rho_k gives the <sigma^z_k> of
+    ed_measure."""
     L = 28
     print("rdm L=28 consistency", flush=True)
     psi = E.random_state_device(L, 12, DEV)
     r1, r2 = P.rdm(psi, L)
     sz, nrm = P.measure(psi, L)
     r1, r2 = r1.cpu().numpy(), r2.cpu().numpy()
+    s1 = P.rdm(psi, L, two_site=False)[0].cpu().numpy()
+    assert np.abs(s1 - r1).max() < 1e-12   # the direct single-site path agrees with the pair path
     del psi
     torch.cuda.empty_cache()
     for r in list(r1) + list(r2):

@@ -1,6 +1,6 @@
 """Host-side checks of the reduced-density-matrix path (no GPU): the pass plan of ed_rdm
-evaluates every pair of index bits exactly once (and the nearest-neighbour plan every bond once)
-with at most 32 pairs per pass, the argument checks, and ed_trace_distances against numpy's
+evaluates every pair of index bits exactly once with at most 32 pairs per pass (and the
+single-site plan every bit once, at most 12 per pass), the argument checks, and ed_trace_distances against numpy's
 Hermitian eigenvalues and the oracle's trace distance."""
 import ctypes as C
 
@@ -18,15 +18,17 @@ def test_plan_covers_every_pair_once(L):
     got = sorted(map(tuple, pairs.tolist()))
     assert got == [(p, q) for p in range(L) for q in range(p + 1, L)]
     assert np.bincount(pass_of).max() <= 32
-    bonds, bpass = P.rdm_plan(L, all_pairs=False)
-    assert sorted(map(tuple, bonds.tolist())) == [(p, p + 1) for p in range(L - 1)]
-    assert np.bincount(bpass).max() <= 32
+    bits, bpass = P.rdm_plan_sites(L)
+    assert sorted(bits.tolist()) == list(range(L))
+    assert np.bincount(bpass).max() <= 12
+    assert bpass.max() + 1 == max(1, -(-(L - 4) // 8))
 
 
 def test_pass_counts():
-    """C(m, 2) tiles of 4 low bits + two groups of 4 high bits cover all pairs: m = 6 at L = 28."""
+    """C(m, 2) tiles of 4 low bits + two groups of 4 high bits cover all pairs: m = 6 at L = 28;
+    tiles of 4 low bits + 8 others cover every single site in ceil(24 / 8) = 3 passes."""
     assert P.rdm_plan(28)[1].max() + 1 == 15
-    assert P.rdm_plan(28, all_pairs=False)[1].max() + 1 == 5
+    assert P.rdm_plan_sites(28)[1].max() + 1 == 3
     assert P.rdm_plan(12)[1].max() + 1 == 3   # one tile, 66 pairs in 3 passes
 
 
@@ -37,7 +39,8 @@ def test_argument_errors():
     assert lib.ed_rdm_workspace(31, C.byref(nb)) == -1
     assert lib.ed_rdm_workspace(28, C.byref(nb)) == 0 and nb.value == 28 * 27 // 2 * 128 + 32 * 1024 * 96 + 1025 * 4096 * 8
     assert lib.ed_rdm(None, 10, None, None, None, 0, None) == -1
-    assert lib.ed_rdm_plan_pairs(1, 1, None, 0, None) == -1
+    assert lib.ed_rdm_plan_pairs(1, None, 0, None) == -1
+    assert lib.ed_rdm_plan_sites(31, None, 0, None) == -1
     assert lib.ed_trace_distances(0, 1, None, None, None) == -1
     assert lib.ed_trace_distances(2, 1, None, None, None) == -1
     assert lib.ed_trace_distances(2, 0, None, None, None) == 0
