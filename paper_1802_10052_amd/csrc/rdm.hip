@@ -152,44 +152,19 @@ __device__ __forceinline__ void run_cube(double (&acc)[kRdmPairsPerWave][kRdmOff
     }
 }
 
-// FULL: 2^12-amplitude tiles (L >= 12); otherwise the whole state (2^L < 4096) is one tile
-template <bool FULL>
-__global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restrict__ psi, RdmPass pa, int64_t ntiles,
-                                                        double* __restrict__ part, double* __restrict__ hist) {
-    __shared__ double2 s[1 << kTileBits];
-    // |psi|^2 of each tile position, summed over the workgroup's tiles (the diagonal of every pair's
-    // matrix is a marginal of these); position y is owned by thread y mod 512
-    __shared__ double sh[1 << kTileBits];
-    const int t = threadIdx.x, lane = t & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: pair data in scalar registers
+// The tile loop of one wave program. All waves stream the same tiles and meet at the same
+// barriers; each runs the copy of the loop specialised to its layout, so that the registers of the
+// other layouts are not held through it.
+template <bool FULL, int LAY>
+__device__ __forceinline__ void tile_loop(const double2* __restrict__ psi, const RdmPass& pa, int64_t ntiles,
+                                          double2* s, double* sh, int t, int lane, int wave, int64_t off_t,
+                                          const int64_t (&soff)[kSlots], double (&acc)[kRdmPairsPerWave][kRdmOff]) {
     const int tsize = FULL ? (1 << kTileBits) : (1 << pa.T);
-    int64_t off_t = 0;
-#pragma unroll
-    for (int b = 0; b < kThreadBits; ++b)
-        if ((FULL || b < pa.T) && ((t >> b) & 1)) off_t |= int64_t(1) << pa.pos[b];
-    static_assert(kSlots == 8, "eight slot registers below");
-    int64_t soff[kSlots];
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) {
-        int64_t o = 0;
-#pragma unroll
-        for (int b = 0; b < kTileBits - kThreadBits; ++b)
-            if ((FULL || kThreadBits + b < pa.T) && ((k >> b) & 1)) o |= int64_t(1) << pa.pos[kThreadBits + b];
-        soff[k] = o;
-    }
-    const int layout = pa.layout[wave], piece = pa.piece[wave], ns = pa.nsplit[wave];
-    double acc[kRdmPairsPerWave][kRdmOff];
-#pragma unroll
-    for (int w = 0; w < kRdmPairsPerWave; ++w)
-#pragma unroll
-        for (int e = 0; e < kRdmOff; ++e) acc[w][e] = 0.0;
-
+    const int piece = pa.piece[wave], ns = pa.nsplit[wave];
     // the next tile is loaded into registers while the current one is evaluated from LDS; eight
     // named registers (an array that lives across the evaluation loop is placed in scratch memory)
     double2 v0, v1, v2, v3, v4, v5, v6, v7;
 #define ED_SLOT(k) (k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : k == 3 ? v3 : k == 4 ? v4 : k == 5 ? v5 : k == 6 ? v6 : v7)
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) sh[t + (k << kThreadBits)] = 0.0;
     int64_t n = blockIdx.x;
     if (n < ntiles) {
         int64_t base = off_t;
@@ -222,28 +197,75 @@ __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restric
         }
         const int nq = tsize >> 2;  // quads of one pair in one tile
         const int(*ib)[3] = pa.ib[wave];
-        if (FULL && layout == kLayTriOne) {  // uniform over the wave
+        if (LAY == kLayTriOne) {
             run_cube<true, 0>(acc, s, lane, ib[0], piece, ns);
             if (pa.wpair[wave][3] >= 0) run_one<3, FULL>(acc, s, lane, ib[1][0], ib[1][1], piece, ns, nq);
-        } else if (FULL && layout == kLayCubeCube) {
+        } else if (LAY == kLayCubeCube) {
             run_cube<false, 0>(acc, s, lane, ib[0], piece, ns);
             if (pa.wpair[wave][2] >= 0) run_cube<false, 2>(acc, s, lane, ib[1], piece, ns);
-        } else if (FULL && layout == kLayCubeOneOne) {
+        } else if (LAY == kLayCubeOneOne) {
             run_cube<false, 0>(acc, s, lane, ib[0], piece, ns);
             if (pa.wpair[wave][2] >= 0) run_one<2, FULL>(acc, s, lane, ib[1][0], ib[1][1], piece, ns, nq);
             if (pa.wpair[wave][3] >= 0) run_one<3, FULL>(acc, s, lane, ib[2][0], ib[2][1], piece, ns, nq);
-        } else if (layout == kLayOnes) {
+        } else if (LAY == kLayOnes) {
             if (pa.wpair[wave][0] >= 0) run_one<0, FULL>(acc, s, lane, ib[0][0], ib[0][1], piece, ns, nq);
             if (pa.wpair[wave][1] >= 0) run_one<1, FULL>(acc, s, lane, ib[1][0], ib[1][1], piece, ns, nq);
             if (pa.wpair[wave][2] >= 0) run_one<2, FULL>(acc, s, lane, ib[2][0], ib[2][1], piece, ns, nq);
             if (pa.wpair[wave][3] >= 0) run_one<3, FULL>(acc, s, lane, ib[3][0], ib[3][1], piece, ns, nq);
         }
     }
+#undef ED_SLOT
+}
+
+// FULL: 2^12-amplitude tiles (L >= 12); otherwise the whole state (2^L < 4096) is one tile
+template <bool FULL>
+__global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restrict__ psi, RdmPass pa, int64_t ntiles,
+                                                        double* __restrict__ part, double* __restrict__ hist) {
+    __shared__ double2 s[1 << kTileBits];
+    // |psi|^2 of each tile position, summed over the workgroup's tiles (the diagonal of every pair's
+    // matrix is a marginal of these); position y is owned by thread y mod 512
+    __shared__ double sh[1 << kTileBits];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: pair data in scalar registers
+    const int tsize = FULL ? (1 << kTileBits) : (1 << pa.T);
+    int64_t off_t = 0;
+#pragma unroll
+    for (int b = 0; b < kThreadBits; ++b)
+        if ((FULL || b < pa.T) && ((t >> b) & 1)) off_t |= int64_t(1) << pa.pos[b];
+    static_assert(kSlots == 8, "eight slot registers in the tile loop");
+    int64_t soff[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+        int64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < kTileBits - kThreadBits; ++b)
+            if ((FULL || kThreadBits + b < pa.T) && ((k >> b) & 1)) o |= int64_t(1) << pa.pos[kThreadBits + b];
+        soff[k] = o;
+    }
+    double acc[kRdmPairsPerWave][kRdmOff];
+#pragma unroll
+    for (int w = 0; w < kRdmPairsPerWave; ++w)
+#pragma unroll
+        for (int e = 0; e < kRdmOff; ++e) acc[w][e] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) sh[t + (k << kThreadBits)] = 0.0;
+
+    const int layout = pa.layout[wave];  // uniform over the wave
+    if (FULL && layout == kLayTriOne)
+        tile_loop<FULL, kLayTriOne>(psi, pa, ntiles, s, sh, t, lane, wave, off_t, soff, acc);
+    else if (FULL && layout == kLayCubeCube)
+        tile_loop<FULL, kLayCubeCube>(psi, pa, ntiles, s, sh, t, lane, wave, off_t, soff, acc);
+    else if (FULL && layout == kLayCubeOneOne)
+        tile_loop<FULL, kLayCubeOneOne>(psi, pa, ntiles, s, sh, t, lane, wave, off_t, soff, acc);
+    else if (layout == kLayOnes)
+        tile_loop<FULL, kLayOnes>(psi, pa, ntiles, s, sh, t, lane, wave, off_t, soff, acc);
+    else
+        tile_loop<FULL, kLayNone>(psi, pa, ntiles, s, sh, t, lane, wave, off_t, soff, acc);
+    __syncthreads();  // every thread's histogram entries are complete
 #pragma unroll
     for (int k = 0; k < kSlots; ++k)
         if (FULL || (k << kThreadBits) + t < tsize)
             hist[size_t(blockIdx.x) * (1 << kTileBits) + t + (k << kThreadBits)] = sh[t + (k << kThreadBits)];
-#undef ED_SLOT
     // fixed-order butterfly over the wave, then one row per (pair, workgroup)
 #pragma unroll
     for (int w = 0; w < kRdmPairsPerWave; ++w) {
