@@ -646,34 +646,71 @@ bool pack_waves(RdmPass& pa, bool full, int max_tri) {
         waves.push_back(w);
     }
     if (int(waves.size()) > kWaves) return false;
+    // wave programs: (wave, piece, nsplit). Few waves are repeated with their bases split between
+    // the copies; otherwise the heaviest waves are split in two while waves are idle. The programs
+    // are then placed so that the two waves of each SIMD (waves w and w + 4) carry similar loads.
     const int W = int(waves.size());
-    const int copies = W > 0 ? std::max(1, kWaves / W) : 1;
+    auto load_of = [](const Wave& w) {
+        int l = 0;
+        for (const Item& it : w.items) l += it.kind == 1 ? 16 : 16 * it.npair;  // quads per lane and tile
+        return l;
+    };
+    struct Prog {
+        int w, piece, nsplit;
+        double load;
+    };
+    std::vector<Prog> progs;
+    if (W > 0 && W <= kWaves / 2) {
+        const int copies = kWaves / W;
+        for (int c = 0; c < copies; ++c)
+            for (int w = 0; w < W; ++w) progs.push_back({w, c, copies, double(load_of(waves[w])) / copies});
+    } else {
+        for (int w = 0; w < W; ++w) progs.push_back({w, 0, 1, double(load_of(waves[w]))});
+        while (int(progs.size()) < kWaves) {
+            int h = -1;
+            for (int i = 0; i < int(progs.size()); ++i)
+                if (progs[i].nsplit == 1 && (h < 0 || progs[i].load > progs[h].load)) h = i;
+            if (h < 0) break;
+            progs[h].nsplit = 2;
+            progs[h].load /= 2;
+            progs.push_back({progs[h].w, 1, 2, progs[h].load});
+        }
+    }
+    std::stable_sort(progs.begin(), progs.end(), [](const Prog& x, const Prog& y) { return x.load > y.load; });
+    constexpr int kSimds = 4;
+    double simd_load[kSimds] = {0, 0, 0, 0};
+    int simd_used[kSimds] = {0, 0, 0, 0};
     for (int w = 0; w < kWaves; ++w) {
         pa.layout[w] = kLayNone;
+        pa.piece[w] = 0;
+        pa.nsplit[w] = 1;
         for (int k = 0; k < 4; ++k) {
             pa.wpair[w][k] = -1;
             pa.wswap[w][k] = 0;
         }
     }
-    for (int c = 0; c < copies; ++c)
-        for (int w = 0; w < W; ++w) {
-            const int dst = w + c * W;
-            const Wave& src = waves[w];
-            pa.layout[dst] = src.layout;
-            pa.piece[dst] = c;
-            pa.nsplit[dst] = copies;
-            int slot = 0;
-            for (size_t k = 0; k < src.items.size(); ++k) {
-                const Item& it = src.items[k];
-                for (int b = 0; b < 3; ++b) pa.ib[dst][k][b] = it.bits[b];
-                // slots: a triangle takes 0-2 and its single 3; stars take 0-1 and 2-3
-                if (src.layout == kLayTriOne && it.kind == 1) slot = 3;
-                for (int m = 0; m < it.npair; ++m) {
-                    pa.wswap[dst][slot] = it.swap[m];
-                    pa.wpair[dst][slot++] = it.pairs[m];
-                }
+    for (const Prog& pr : progs) {
+        int sm = -1;
+        for (int q = 0; q < kSimds; ++q)
+            if (simd_used[q] < kWaves / kSimds && (sm < 0 || simd_load[q] < simd_load[sm])) sm = q;
+        const int dst = sm + kSimds * simd_used[sm]++;
+        simd_load[sm] += pr.load;
+        const Wave& src = waves[pr.w];
+        pa.layout[dst] = src.layout;
+        pa.piece[dst] = pr.piece;
+        pa.nsplit[dst] = pr.nsplit;
+        int slot = 0;
+        for (size_t k = 0; k < src.items.size(); ++k) {
+            const Item& it = src.items[k];
+            for (int b = 0; b < 3; ++b) pa.ib[dst][k][b] = it.bits[b];
+            // slots: a triangle takes 0-2 and its single 3; stars take 0-1 and 2-3
+            if (src.layout == kLayTriOne && it.kind == 1) slot = 3;
+            for (int m = 0; m < it.npair; ++m) {
+                pa.wswap[dst][slot] = it.swap[m];
+                pa.wpair[dst][slot++] = it.pairs[m];
             }
         }
+    }
     return true;
 }
 
