@@ -36,6 +36,9 @@ hipError_t combination(const double2* V, int64_t ldv, int n, const double2* c, d
 // out[0].x = |psi|^2, out[1+p].x = sum |psi_x|^2 (1 - 2 bit_p(x))  (p = bit, site L-p)
 hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStream_t s);
 
+// *dst = v, ordered on the stream like a kernel
+hipError_t set_scalar(double2* dst, double2 v, hipStream_t s);
+
 // Scaled-basis variants: vectors given as pointer lists.
 // out[i] = <U_i|w>, i < n
 hipError_t dots_ptr(const double2* const* U, int n, const double2* w, int64_t D, double2* out, double2* part,

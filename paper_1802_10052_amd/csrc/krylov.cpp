@@ -63,7 +63,7 @@ ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s)
 // first subtraction together with the second pass's dots; subtraction + norm). Returns the true projections h_i = <v_i|H v_j> (i = lo..j) and the norm
 // beta of the orthogonalised H v_j; the new basis vector is u_{j+1} = y with c_{j+1} = 1/|y|.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
-                      cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo) {
+                      cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo, double beta_prev) {
     const int64_t D = w.D;
     const int n = j - lo + 1;
     if (n > kMaxProj) return fail(ED_ERR_UNSUPPORTED, "too many projections");
@@ -79,7 +79,11 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     const double2* const* U = const_cast<const double2* const*>(w.u.data() + lo);
     std::vector<double> sc(n);
     for (int i = 0; i < n; ++i) sc[i] = w.c[lo + i] * w.c[lo + i];
-    if (passes > 1 && first_lo > lo) {
+    if (passes == 1 && beta_prev >= 0.0 && n == 2 && lo == j - 1) {
+        // <u_{j-1}|y> = beta_{j-1} / (c_{j-1} c_j) for a Hermitian H: one dot only
+        ED_K(set_scalar(g1, make_double2(beta_prev / (w.c[lo] * w.c[j]), 0.0), s));
+        ED_K(dots_ptr(U + 1, 1, y, D, g1 + 1, w.part, s));
+    } else if (passes > 1 && first_lo > lo) {
         // the recurrence's own vectors first; the other coefficients of the first pass are zero
         const int nf = j - first_lo + 1;
         ED_HIP_TRY(hipMemsetAsync(g1, 0, sizeof(double2) * size_t(n - nf), s));
@@ -351,10 +355,12 @@ ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, 
     int mm = 0;
     double err = 0.0;
     for (int j = 0; j < mmax; ++j) {
-        const int lo = (herm && !p->reorth) ? std::max(j - 1, 0) : 0;
+        const bool three_term = herm && !p->reorth;
+        const int lo = three_term ? std::max(j - 1, 0) : 0;
         double beta = 0.0;
         bool brk = false;
-        ED_TRY(krylov_step(m, w, j, lo, passes, 1e-14, h.data(), &beta, &brk, s));
+        const double beta_prev = (three_term && j >= 1) ? Tij(j, j - 1).real() : -1.0;
+        ED_TRY(krylov_step(m, w, j, lo, passes, 1e-14, h.data(), &beta, &brk, s, -1, beta_prev));
         if (herm) {
             Tij(j, j) = h[j - lo].real();
         } else {

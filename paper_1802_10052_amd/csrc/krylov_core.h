@@ -31,8 +31,12 @@ ed_status carve(void* ws, size_t ws_bytes, int64_t D, int nvec, Workspace* w);
 ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s);
 // first_lo > lo (with passes = 2): the first Gram-Schmidt pass takes only vectors first_lo..j (the
 // ones a three-term recurrence couples), the second pass all of lo..j.
+// beta_prev >= 0 (Hermitian three-term recurrence: passes = 1, lo = j - 1): the projection of
+// H v_j on v_{j-1} is taken as beta_prev, the previous step's norm (they are equal for a Hermitian
+// H), so that only <v_j|H v_j> is swept for.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
-                      cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo = -1);
+                      cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo = -1,
+                      double beta_prev = -1.0);
 // Basis vector 0 from psi: alias = true uses psi itself as u_0 (c_0 = 1/|psi|); otherwise psi/|psi|
 // is written to slot 0 (c_0 = 1).
 ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s, bool alias = false);

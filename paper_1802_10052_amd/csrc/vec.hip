@@ -172,6 +172,11 @@ __global__ __launch_bounds__(kThreads) void scale_copy(const double2* src, doubl
     }
 }
 
+// *dst = v (one scalar set on the stream, in order with the sweeps around it)
+__global__ void set_value(double2* dst, double2 v) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
 // y[x] = a * x[x] + b * y[x] (complex a, b by value)
 __global__ __launch_bounds__(kThreads) void axpby_kernel(const double2* __restrict__ xv, double2* __restrict__ y,
                                                          double2 a, double2 b, int64_t D) {
@@ -461,6 +466,11 @@ hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStr
 }  // namespace ed
 
 namespace ed {
+
+hipError_t set_scalar(double2* dst, double2 v, hipStream_t s) {
+    hipLaunchKernelGGL(set_value, dim3(1), dim3(64), 0, s, dst, v);
+    return hipGetLastError();
+}
 
 hipError_t dots_ptr(const double2* const* U, int n, const double2* w, int64_t D, double2* out, double2* part,
                     hipStream_t s) {
