@@ -184,7 +184,9 @@ ed_status build_basis(const ed_model* mod, const double2* psi, double dt_err, co
         const int lo = std::max(j - 1, 0);
         double beta = 0.0;
         bool brk = false;
-        ED_TRY(krylov_step(mod, B->w, j, lo, 1, 1e-14, h.data(), &beta, &brk, s, -1, j >= 1 ? b[j - 1] : -1.0));
+        // both projections swept (local re-projection): the bases run at a fixed dimension well
+        // past convergence, where the gradient check needs the more orthogonal basis
+        ED_TRY(krylov_step(mod, B->w, j, lo, 1, 1e-14, h.data(), &beta, &brk, s));
         a[j] = h[j - lo].real();
         m = j + 1;
         bool stop = brk || m >= mmax;

@@ -139,6 +139,11 @@ struct ed_model {
 namespace ed {
 // Launch the passes of out = H psi (apply_h.hip), then the far terms if the model has any.
 ed_status launch_apply_H(const ed_model* m, const double2* psi, double2* out, hipStream_t s);
+// H psi whose last pass also leaves, per tile n, dot_part[n] = sum over the tile of conj(psi) out
+// (*nparts = the number of tiles), when the plan ends with a window pass, there are no far terms
+// and the tiles fit max_parts entries; otherwise a plain product with *nparts = 0.
+ed_status launch_apply_H_dot(const ed_model* m, const double2* psi, double2* out, double2* dot_part,
+                             int64_t max_parts, int64_t* nparts, hipStream_t s);
 // out += sum of the far terms applied to psi (liouville.hip)
 ed_status launch_far_terms(const ed_model* m, const double2* psi, double2* out, hipStream_t s);
 // trace and sum_j rho_jj z_k(j), k = 1..Ls (site order), of a superket of an Ls-site system,

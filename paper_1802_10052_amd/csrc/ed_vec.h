@@ -36,6 +36,8 @@ hipError_t combination(const double2* V, int64_t ldv, int n, const double2* c, d
 // out[0].x = |psi|^2, out[1+p].x = sum |psi_x|^2 (1 - 2 bit_p(x))  (p = bit, site L-p)
 hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStream_t s);
 
+// out[0] = sum of part[0..n) in a fixed order
+hipError_t sum_partials(const double2* part, int64_t n, double2* out, hipStream_t s);
 // *dst = v, ordered on the stream like a kernel
 hipError_t set_scalar(double2* dst, double2 v, hipStream_t s);
 

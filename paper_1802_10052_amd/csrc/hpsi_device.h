@@ -47,6 +47,9 @@ struct PassArgs {
     int lr, L;
     const double2* lr_low;
     const double2* lr_cross;
+    // last window pass with the product's projection on the input: dot_part[n] = the sum over
+    // tile n of conj(psi[x]) out[x] (only the fused launch reads it)
+    double2* dot_part;
 };
 
 // Operator tables of one model as the per-amplitude kernels see them.
@@ -87,13 +90,16 @@ __device__ __forceinline__ int64_t slot_step(const PassArgs& pa, bool first) {
 // tile); jobs whose partner is the other tile read it from LDS instead of global memory.
 // TB: thread bits of the tile (8: 256 threads, 16 registers each; 10: 1024 threads, 4 each).
 // Caller synchronises around reuse of s.
-template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8>
+// DOT (last pass of the product, every thread of the workgroup calls with the same n layout):
+// also writes pa.dot_part[n] = sum over the tile of conj(psi[x]) out[x], out being final here;
+// sD holds one entry per wave of the tile. Contains a workgroup barrier.
+template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8, bool DOT = false>
 __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
                                           const double2* __restrict__ site, const double2* __restrict__ bond,
                                           const double2* __restrict__ dlo, const double2* __restrict__ dmid,
                                           const double2* __restrict__ dhi, const PassArgs& pa, int64_t n,
                                           double2* s, int t = 0, const double2* so = nullptr,
-                                          double2* sF = nullptr) {
+                                          double2* sF = nullptr, double2* sD = nullptr) {
     constexpr bool OFFR = CLS & kOffReal;
     constexpr bool DIAGR = CLS & kDiagReal;
     constexpr int kThr = 1 << TB;                  // threads of one tile
@@ -273,6 +279,32 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
         __builtin_nontemporal_store(acc[k].x, o);
         __builtin_nontemporal_store(acc[k].y, o + 1);
     }
+    if constexpr (DOT) {
+        // the tile of psi is still in LDS; fixed order: slots, wave butterfly, waves
+        double dx = 0.0, dy = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSl; ++k) {
+            const double2 p = s[t + kThr * k];
+            dx = fma(p.x, acc[k].x, fma(p.y, acc[k].y, dx));
+            dy = fma(p.x, acc[k].y, fma(-p.y, acc[k].x, dy));
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            dx += __shfl_xor(dx, o);
+            dy += __shfl_xor(dy, o);
+        }
+        if ((t & 63) == 0) sD[t >> 6] = make_double2(dx, dy);
+        __syncthreads();
+        if (t == 0) {
+            double2 sum = sD[0];
+#pragma unroll
+            for (int w = 1; w < kThr / 64; ++w) {
+                sum.x += sD[w].x;
+                sum.y += sD[w].y;
+            }
+            pa.dot_part[n] = sum;
+        }
+    }
 }
 
 // Per-amplitude body for one x (small L, or one small state per workgroup): partners read from
@@ -379,6 +411,7 @@ inline PassArgs to_args(const PassDesc& pd, const GatherJob* jobs, int njobs) {
     pa.L = 0;
     pa.lr_low = nullptr;
     pa.lr_cross = nullptr;
+    pa.dot_part = nullptr;
     return pa;
 }
 

@@ -72,17 +72,26 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
         w.c.resize(j + 2, 0.0);
     }
     double2* y = w.slot(j + 1);
-    ED_TRY(launch_apply_H(m, w.u[j], y, s));
+    const bool three_term = passes == 1 && beta_prev >= 0.0 && n == 2 && lo == j - 1;
+    int64_t nparts = 0;
+    if (three_term) {
+        // the product's last pass also leaves per-tile partials of <u_j|y> in the partial buffer
+        ED_TRY(launch_apply_H_dot(m, w.u[j], y, w.part, int64_t(kPartBytes / sizeof(double2)), &nparts, s));
+    } else {
+        ED_TRY(launch_apply_H(m, w.u[j], y, s));
+    }
     double2* nr = w.scal + kNrm;
     double2* g1 = w.scal + 1;
     double2* g2 = w.scal + 1 + n;
     const double2* const* U = const_cast<const double2* const*>(w.u.data() + lo);
     std::vector<double> sc(n);
     for (int i = 0; i < n; ++i) sc[i] = w.c[lo + i] * w.c[lo + i];
-    if (passes == 1 && beta_prev >= 0.0 && n == 2 && lo == j - 1) {
-        // <u_{j-1}|y> = beta_{j-1} / (c_{j-1} c_j) for a Hermitian H: one dot only
+    if (three_term) {
+        // <u_{j-1}|y> = beta_{j-1} / (c_{j-1} c_j) for a Hermitian H; <u_j|y> from the product's
+        // partials, or one dot sweep
         ED_K(set_scalar(g1, make_double2(beta_prev / (w.c[lo] * w.c[j]), 0.0), s));
-        ED_K(dots_ptr(U + 1, 1, y, D, g1 + 1, w.part, s));
+        if (nparts > 0) ED_K(sum_partials(w.part, nparts, g1 + 1, s));
+        else ED_K(dots_ptr(U + 1, 1, y, D, g1 + 1, w.part, s));
     } else if (passes > 1 && first_lo > lo) {
         // the recurrence's own vectors first; the other coefficients of the first pass are zero
         const int nf = j - first_lo + 1;

@@ -467,6 +467,11 @@ hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStr
 
 namespace ed {
 
+hipError_t sum_partials(const double2* part, int64_t n, double2* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, 1, int(n), 1, out, 0);
+    return hipGetLastError();
+}
+
 hipError_t set_scalar(double2* dst, double2 v, hipStream_t s) {
     hipLaunchKernelGGL(set_value, dim3(1), dim3(64), 0, s, dst, v);
     return hipGetLastError();

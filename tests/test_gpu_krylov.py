@@ -97,6 +97,72 @@ def test_krylov_quench_vs_oracle(L, reorth):
         assert overlap_err(got, exact) <= 1e-9
 
 
+def test_krylov_three_term_fused_projection():
+    """The Hermitian three-term recurrence (reorth = 0) takes <v_j|H v_j> from the product's last
+    pass (per-tile sums of conj(psi) H psi, in a fixed order) when the plan ends with a window
+    pass. Every launch shape of that last pass the L = 18 plans offer (256-thread tiles with and
+    without gathered bits, paired tiles, 1024-thread tiles) against the oracle's Krylov steps
+    from a random start."""
+    L, steps = 18, 6
+    print(f"krylov fused projection L={L}", flush=True)
+    desc = E.tfim(L, 0.5)
+    H = OH.hamiltonian_sparse(desc)
+    psi0 = E.random_state(L, 31)
+    ref = psi0.copy()
+    sz_ref = [OO.sz_all(ref, L)]
+    for _ in range(steps):
+        ref, _m = OK.krylov_step(lambda v: H @ v, ref, 0.05, m_max=20, tol=1e-10)
+        sz_ref.append(OO.sz_all(ref, L))
+    m = P.Model(desc)
+    shapes = {}
+    for i in range(m.plans[0]):
+        d = m.describe_plan(i)
+        if "|" not in d:
+            continue
+        last = d.split("|")[-1]
+        kind = ("wide" if "wide" in last else "pair" if "pair" in last else "plain") + ("+G" if "+G" in last else "")
+        shapes.setdefault(kind, i)
+    assert "plain" in shapes or "plain+G" in shapes, shapes
+    for kind, i in sorted(shapes.items()):
+        print(f"  plan {i} ({kind}): {m.describe_plan(i)}", flush=True)
+        m.select_plan(i)
+        g = dev(psi0)
+        _, obs, info = P.krylov_evolve(m, g, 0.05, steps, m_max=20, tol=1e-10, reorth=0)
+        assert overlap_err(g.cpu().numpy(), ref) <= 1e-9, kind
+        assert np.max(np.abs(obs["sz"] - np.array(sz_ref))) < 1e-9, kind
+        assert np.max(np.abs(obs["norm"] - obs["norm"][0])) < 1e-9, kind
+
+
+def test_krylov_three_term_fused_projection_shapes_L21():
+    """At L = 21 the candidate plans end with every launch shape of a window pass: 256-thread
+    tiles with and without gathered bits, paired tiles and 1024-thread tiles. With each one as
+    the last pass, the three-term recurrence (projection from the product's last pass) agrees with
+    the fully reorthogonalised recurrence (separate dot sweeps) from the same random start."""
+    L, steps = 21, 4
+    print(f"krylov fused projection shapes L={L}", flush=True)
+    m = P.Model(E.tfim(L, 0.5))
+    psi0 = E.random_state(L, 32)
+    g = dev(psi0)
+    _, ref_obs, _ = P.krylov_evolve(m, g, 0.05, steps, m_max=20, tol=1e-12, reorth=1)
+    ref = g.cpu().numpy()
+    shapes = {}
+    for i in range(m.plans[0]):
+        d = m.describe_plan(i)
+        last = d.split("|")[-1]
+        if "|" not in d:
+            continue
+        kind = ("wide" if "wide" in last else "pair" if "pair" in last else "plain") + ("+G" if "+G" in last else "")
+        shapes.setdefault(kind, i)
+    assert {"plain", "plain+G", "wide+G", "pair+G"} <= set(shapes), shapes
+    for kind, i in sorted(shapes.items()):
+        print(f"  plan {i} ({kind}): {m.describe_plan(i)}", flush=True)
+        m.select_plan(i)
+        g = dev(psi0)
+        _, obs, _ = P.krylov_evolve(m, g, 0.05, steps, m_max=20, tol=1e-12, reorth=0)
+        assert overlap_err(g.cpu().numpy(), ref) <= 1e-9, kind
+        assert np.max(np.abs(obs["sz"] - ref_obs["sz"])) < 1e-9, kind
+
+
 def test_krylov_generic_and_arnoldi():
     L = 9
     for herm in (True, False):
