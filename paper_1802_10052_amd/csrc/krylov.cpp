@@ -73,8 +73,11 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     }
     double2* y = w.slot(j + 1);
     const bool three_term = passes == 1 && beta_prev >= 0.0 && n == 2 && lo == j - 1;
+    // CGS2 whose first pass takes only v_{j-1}, v_j: that pass's projections are beta_{j-1} and
+    // <v_j|H v_j> as well (the second pass takes the whole basis)
+    const bool local_first = passes > 1 && first_lo == j - 1 && first_lo > lo && beta_prev >= 0.0;
     int64_t nparts = 0;
-    if (three_term) {
+    if (three_term || local_first) {
         // the product's last pass also leaves per-tile partials of <u_j|y> in the partial buffer
         ED_TRY(launch_apply_H_dot(m, w.u[j], y, w.part, int64_t(kPartBytes / sizeof(double2)), &nparts, s));
     } else {
@@ -92,6 +95,11 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
         ED_K(set_scalar(g1, make_double2(beta_prev / (w.c[lo] * w.c[j]), 0.0), s));
         if (nparts > 0) ED_K(sum_partials(w.part, nparts, g1 + 1, s));
         else ED_K(dots_ptr(U + 1, 1, y, D, g1 + 1, w.part, s));
+    } else if (local_first) {
+        ED_HIP_TRY(hipMemsetAsync(g1, 0, sizeof(double2) * size_t(n - 2), s));
+        ED_K(set_scalar(g1 + (n - 2), make_double2(beta_prev / (w.c[j - 1] * w.c[j]), 0.0), s));
+        if (nparts > 0) ED_K(sum_partials(w.part, nparts, g1 + (n - 1), s));
+        else ED_K(dots_ptr(U + (n - 1), 1, y, D, g1 + (n - 1), w.part, s));
     } else if (passes > 1 && first_lo > lo) {
         // the recurrence's own vectors first; the other coefficients of the first pass are zero
         const int nf = j - first_lo + 1;
@@ -217,7 +225,9 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
             // past the first step of a cycle the recurrence is three-term: the first Gram-Schmidt
             // pass needs only v_{j-1}, v_j (the second one takes the whole basis)
             const int first_lo = (j >= 1 && j > k_locked) ? j - 1 : -1;
-            const ed_status st = krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s, first_lo);
+            const double beta_prev = first_lo >= 0 ? Tij(j, j - 1) : -1.0;
+            const ed_status st =
+                krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s, first_lo, beta_prev);
             if (st != ED_OK)
                 return fail(st, std::string(ed_last_error()) + " (Lanczos product " + std::to_string(iters + 1) +
                                     ", restarts " + std::to_string(restarts) + ", basis index " + std::to_string(j) + ")");
