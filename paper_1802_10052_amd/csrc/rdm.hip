@@ -440,18 +440,14 @@ __global__ __launch_bounds__(kRdmThreads) void rdm1_pass(const double2* __restri
                     if (kb == 1 && !(k & 2)) site_accumulate(acc[i], own[k], own[k | 2]);
                     if (kb == 2 && !(k & 4)) site_accumulate(acc[i], own[k], own[k | 4]);
                 }
-            } else {
-                // the thread with bit b clear owns x and takes slots 0..3, its partner owns x|B and
-                // takes slots 4..7; operands are selected, not branched on, since for b < 6 both
-                // kinds of thread share a wave
-                const bool hi = (t & B) != 0;
-                const int kofs = hi ? kSlots / 2 : 0;
+            } else if (!(t & B)) {  // x is ours: slots 0..3
 #pragma unroll
-                for (int j = 0; j < kSlots / 2; ++j) {
-                    const double2 mine = hi ? own[j + kSlots / 2] : own[j];
-                    const double2 other = s[(t ^ B) + ((j + kofs) << kThreadBits)];
-                    site_accumulate(acc[i], hi ? other : mine, hi ? mine : other);
-                }
+                for (int k = 0; k < kSlots / 2; ++k)
+                    site_accumulate(acc[i], own[k], s[(t | B) + (k << kThreadBits)]);
+            } else {  // x|B is ours: slots 4..7
+#pragma unroll
+                for (int k = kSlots / 2; k < kSlots; ++k)
+                    site_accumulate(acc[i], s[(t ^ B) + (k << kThreadBits)], own[k]);
             }
         }
     }
