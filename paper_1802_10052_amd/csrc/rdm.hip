@@ -154,19 +154,21 @@ __device__ __forceinline__ void run_cube(double (&acc)[kRdmPairsPerWave][kRdmOff
 
 // The tile loop of one wave program. All waves stream the same tiles and meet at the same
 // barriers; each runs the copy of the loop specialised to its layout, so that the registers of the
-// other layouts are not held through it.
+// other layouts are not held through it. Two LDS buffers: while tile n is evaluated from one, the
+// thread stores tile n + G (already in its registers) into the other and loads tile n + 2G into
+// registers (G = gridDim.x); one barrier per tile.
 template <bool FULL, int LAY>
 __device__ __forceinline__ void tile_loop(const double2* __restrict__ psi, const RdmPass& pa, int64_t ntiles,
-                                          double2* s, double* sh, int t, int lane, int wave, int64_t off_t,
-                                          const int64_t (&soff)[kSlots], double (&acc)[kRdmPairsPerWave][kRdmOff]) {
+                                          double2 (*sb)[1 << kTileBits], double* sh, int t, int lane, int wave,
+                                          int64_t off_t, const int64_t (&soff)[kSlots],
+                                          double (&acc)[kRdmPairsPerWave][kRdmOff]) {
     const int tsize = FULL ? (1 << kTileBits) : (1 << pa.T);
     const int piece = pa.piece[wave], ns = pa.nsplit[wave];
-    // the next tile is loaded into registers while the current one is evaluated from LDS; eight
-    // named registers (an array that lives across the evaluation loop is placed in scratch memory)
+    const int64_t G = gridDim.x;
+    // eight named registers (an array that lives across the evaluation loop is placed in scratch)
     double2 v0, v1, v2, v3, v4, v5, v6, v7;
 #define ED_SLOT(k) (k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : k == 3 ? v3 : k == 4 ? v4 : k == 5 ? v5 : k == 6 ? v6 : v7)
-    int64_t n = blockIdx.x;
-    if (n < ntiles) {
+    auto load = [&](int64_t n) {
         int64_t base = off_t;
 #pragma unroll
         for (int b = 0; b < kMaxComp; ++b)
@@ -174,9 +176,8 @@ __device__ __forceinline__ void tile_loop(const double2* __restrict__ psi, const
 #pragma unroll
         for (int k = 0; k < kSlots; ++k)
             if (FULL || (k << kThreadBits) + t < tsize) ED_SLOT(k) = psi[base + soff[k]];
-    }
-    for (; n < ntiles; n += gridDim.x) {
-        __syncthreads();  // the previous tile has been read
+    };
+    auto store = [&](double2* s) {  // the registers' tile into s, and its |psi|^2 into the histogram
 #pragma unroll
         for (int k = 0; k < kSlots; ++k)
             if (FULL || (k << kThreadBits) + t < tsize) {
@@ -185,15 +186,19 @@ __device__ __forceinline__ void tile_loop(const double2* __restrict__ psi, const
                 double& h = sh[t + (k << kThreadBits)];
                 h = fma(a.x, a.x, fma(a.y, a.y, h));
             }
-        __syncthreads();
-        const int64_t nn = n + gridDim.x;
-        if (nn < ntiles) {
-            int64_t base = off_t;
-#pragma unroll
-            for (int b = 0; b < kMaxComp; ++b)
-                if (b < pa.ncomp && ((nn >> b) & 1)) base |= int64_t(1) << pa.comp[b];
-#pragma unroll
-            for (int k = 0; k < kSlots; ++k) ED_SLOT(k) = psi[base + soff[k]];  // FULL only: ntiles > 1
+    };
+    int64_t n = blockIdx.x;
+    if (n < ntiles) {
+        load(n);
+        store(sb[0]);
+        if (n + G < ntiles) load(n + G);
+    }
+    __syncthreads();
+    for (int it = 0; n < ntiles; n += G, ++it) {  // n, G, ntiles uniform: every wave takes the same steps
+        const double2* s = sb[it & 1];
+        if (n + G < ntiles) {
+            store(sb[(it + 1) & 1]);  // read by every wave in the previous step, before its barrier
+            if (n + 2 * G < ntiles) load(n + 2 * G);
         }
         const int nq = tsize >> 2;  // quads of one pair in one tile
         const int(*ib)[3] = pa.ib[wave];
@@ -213,6 +218,7 @@ __device__ __forceinline__ void tile_loop(const double2* __restrict__ psi, const
             if (pa.wpair[wave][2] >= 0) run_one<2, FULL>(acc, s, lane, ib[2][0], ib[2][1], piece, ns, nq);
             if (pa.wpair[wave][3] >= 0) run_one<3, FULL>(acc, s, lane, ib[3][0], ib[3][1], piece, ns, nq);
         }
+        __syncthreads();  // tile n has been read and tile n + G stored
     }
 #undef ED_SLOT
 }
@@ -221,9 +227,10 @@ __device__ __forceinline__ void tile_loop(const double2* __restrict__ psi, const
 template <bool FULL>
 __global__ __launch_bounds__(kRdmThreads) void rdm_pass(const double2* __restrict__ psi, RdmPass pa, int64_t ntiles,
                                                         double* __restrict__ part, double* __restrict__ hist) {
-    __shared__ double2 s[1 << kTileBits];
+    __shared__ double2 s[2][1 << kTileBits];  // two tile buffers: 128 KiB
     // |psi|^2 of each tile position, summed over the workgroup's tiles (the diagonal of every pair's
-    // matrix is a marginal of these); position y is owned by thread y mod 512
+    // matrix is a marginal of these); position y is owned by thread y mod 512. 32 KiB: with the
+    // tiles, the 160 KiB of LDS of a CU
     __shared__ double sh[1 << kTileBits];
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: pair data in scalar registers
