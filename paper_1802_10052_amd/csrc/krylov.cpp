@@ -60,8 +60,11 @@ ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s)
 
 // One step of the recurrence on the scaled basis: y = H u_j into slot j+1, orthogonalised against
 // u_lo..u_j by classical Gram-Schmidt once (dots, then subtraction + norm) or twice (dots; the
-// first subtraction together with the second pass's dots; subtraction + norm). Returns the true projections h_i = <v_i|H v_j> (i = lo..j) and the norm
-// beta of the orthogonalised H v_j; the new basis vector is u_{j+1} = y with c_{j+1} = 1/|y|.
+// first subtraction together with the second pass's dots; subtraction + norm). With beta_prev
+// (Hermitian H), the first pass's projections on v_{j-1} and v_j are beta_{j-1} and the sum the
+// product's last pass leaves per tile, so that pass needs no dot sweep. Returns the true
+// projections h_i = <v_i|H v_j> (i = lo..j) and the norm beta of the orthogonalised H v_j; the new
+// basis vector is u_{j+1} = y with c_{j+1} = 1/|y|.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
                       cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo, double beta_prev) {
     const int64_t D = w.D;
