@@ -100,12 +100,12 @@ def test_krylov_quench_vs_oracle(L, reorth):
 def test_krylov_three_term_fused_projection():
     """The Hermitian three-term recurrence (reorth = 0) takes <v_j|H v_j> from the product's last
     pass (per-tile sums of conj(psi) H psi, in a fixed order) when the plan ends with a window
-    pass. Every launch shape of that last pass the L = 18 plans offer (256-thread tiles with and
-    without gathered bits, paired tiles, 1024-thread tiles) against the oracle's Krylov steps
-    from a random start."""
+    pass (at L = 18 a 256-thread one). A random Hermitian model with complex site and bond
+    operators, so the sums are complex, against the oracle's Krylov steps from a random start,
+    on every candidate plan kind."""
     L, steps = 18, 6
     print(f"krylov fused projection L={L}", flush=True)
-    desc = E.tfim(L, 0.5)
+    desc = E.random_model(L, 5, hermitian=True)
     H = OH.hamiltonian_sparse(desc)
     psi0 = E.random_state(L, 31)
     ref = psi0.copy()
