@@ -75,7 +75,8 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
         w.c.resize(j + 2, 0.0);
     }
     double2* y = w.slot(j + 1);
-    const bool three_term = passes == 1 && beta_prev >= 0.0 && n == 2 && lo == j - 1;
+    // Hermitian three-term recurrence (n = 2), or its first step (j = 0, n = 1: <v_0|H v_0> only)
+    const bool three_term = passes == 1 && beta_prev >= 0.0 && ((n == 2 && lo == j - 1) || (n == 1 && j == 0));
     // CGS2 whose first pass takes only v_{j-1}, v_j: that pass's projections are beta_{j-1} and
     // <v_j|H v_j> as well (the second pass takes the whole basis)
     const bool local_first = passes > 1 && first_lo == j - 1 && first_lo > lo && beta_prev >= 0.0;
@@ -95,9 +96,9 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     if (three_term) {
         // <u_{j-1}|y> = beta_{j-1} / (c_{j-1} c_j) for a Hermitian H; <u_j|y> from the product's
         // partials, or one dot sweep
-        ED_K(set_scalar(g1, make_double2(beta_prev / (w.c[lo] * w.c[j]), 0.0), s));
-        if (nparts > 0) ED_K(sum_partials(w.part, nparts, g1 + 1, s));
-        else ED_K(dots_ptr(U + 1, 1, y, D, g1 + 1, w.part, s));
+        if (n == 2) ED_K(set_scalar(g1, make_double2(beta_prev / (w.c[lo] * w.c[j]), 0.0), s));
+        if (nparts > 0) ED_K(sum_partials(w.part, nparts, g1 + (n - 1), s));
+        else ED_K(dots_ptr(U + (n - 1), 1, y, D, g1 + (n - 1), w.part, s));
     } else if (local_first) {
         ED_HIP_TRY(hipMemsetAsync(g1, 0, sizeof(double2) * size_t(n - 2), s));
         ED_K(set_scalar(g1 + (n - 2), make_double2(beta_prev / (w.c[j - 1] * w.c[j]), 0.0), s));
@@ -381,7 +382,8 @@ ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, 
         const int lo = three_term ? std::max(j - 1, 0) : 0;
         double beta = 0.0;
         bool brk = false;
-        const double beta_prev = (three_term && j >= 1) ? Tij(j, j - 1).real() : -1.0;
+        // the first step has no previous norm: 0 marks the recurrence as three-term
+        const double beta_prev = three_term ? (j >= 1 ? Tij(j, j - 1).real() : 0.0) : -1.0;
         ED_TRY(krylov_step(m, w, j, lo, passes, 1e-14, h.data(), &beta, &brk, s, -1, beta_prev));
         if (herm) {
             Tij(j, j) = h[j - lo].real();

@@ -31,10 +31,10 @@ ed_status carve(void* ws, size_t ws_bytes, int64_t D, int nvec, Workspace* w);
 ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s);
 // first_lo > lo (with passes = 2): the first Gram-Schmidt pass takes only vectors first_lo..j (the
 // ones a three-term recurrence couples), the second pass all of lo..j.
-// beta_prev >= 0 (Hermitian H; passes = 1 with lo = j - 1, or passes = 2 with first_lo = j - 1):
-// the projection of H v_j on v_{j-1} (in the first pass) is taken as beta_prev, the previous
-// step's norm (they are equal for a Hermitian H), and <v_j|H v_j> comes from the product's last
-// pass where the plan allows, else from one dot sweep.
+// beta_prev >= 0 (Hermitian H; passes = 1 with lo = j - 1 or j = lo = 0, or passes = 2 with
+// first_lo = j - 1): the projection of H v_j on v_{j-1} (in the first pass) is taken as
+// beta_prev, the previous step's norm (they are equal for a Hermitian H), and <v_j|H v_j> comes
+// from the product's last pass where the plan allows, else from one dot sweep.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
                       cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo = -1,
                       double beta_prev = -1.0);
