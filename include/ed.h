@@ -36,7 +36,7 @@ typedef struct { double re, im; } ed_c64;
 typedef enum {
     ED_OK = 0,
     ED_ERR_ARG = -1,          /* invalid argument (null pointer, size, range)          */
-    ED_ERR_UNSUPPORTED = -2,  /* valid request outside this build (d != 2, L > 30 ...)  */
+    ED_ERR_UNSUPPORTED = -2,  /* valid request outside what the library supports (d != 2, L > 30 ...) */
     ED_ERR_NODEVICE = -3,     /* no HIP device visible                                  */
     ED_ERR_NOMEM = -4,        /* a small internal device/host allocation failed         */
     ED_ERR_WORKSPACE = -5,    /* caller workspace smaller than the size query returned  */

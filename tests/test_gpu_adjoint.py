@@ -31,7 +31,7 @@ def test_adjoint_vs_dense_oracle_small(L, S):
     assert np.max(np.abs(g - gr)) <= 1e-9 * max(np.max(np.abs(gr)), 1e-3)
 
 
-def test_adjoint_vs_dense_oracle_L10_config():
+def test_adjoint_vs_dense_oracle_L10():
     """L = 10, 50 slices of 0.1, J ~ U[0.5, 1.5] (seed 5), Neel start, staggered magnetisation."""
     print("adjoint L=10 vs dense oracle", flush=True)
     tmpl, J, psi0, w = case(10, 50)

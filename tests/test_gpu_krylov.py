@@ -24,7 +24,7 @@ def overlap_err(a, b):
     return 1 - abs(np.vdot(a, b)) / (np.linalg.norm(a) * np.linalg.norm(b))
 
 
-def test_lanczos_tfim_L14_config():
+def test_lanczos_tfim_L14_g1():
     """Transverse-field Ising L = 14, g = 1, seeded start, tol 1e-10, <= 200 iterations; checked
     against the free-fermion closed form and the oracle's Lanczos ground state."""
     L = 14
@@ -252,25 +252,25 @@ def test_error_paths_from_the_host():
     assert _lib.STATUS[code] == "ED_ERR_ARG"
 
 
-_CONFIG2 = {}
+_XXZ_GROUND = {}
 
 
 @pytest.mark.parametrize("L,basis,keep", [(20, 60, 10), (20, 16, 5), (26, 60, 10), (26, 16, 5)])
-def test_lanczos_config2_shape(L, basis, keep):
-    """The config-2 shape (XXZ Delta = 0.5, h ~ U[-0.5, 0.5]) with at most 60 stored vectors: thick
+def test_lanczos_xxz_random_fields_restart_sizes(L, basis, keep):
+    """The XXZ ground-state workload (Delta = 0.5, h ~ U[-0.5, 0.5]) with at most 60 stored vectors: thick
     restart with 60 (10 kept Ritz vectors) and with 16 (5 kept; the benchmark's choice): converged
     with an explicit residual below 1e-10; at L = 20 the energy and the state agree with a run
     that never restarts, at L = 26 the two restart sizes agree with each other."""
-    print(f"lanczos config-2 shape L={L} basis={basis}", flush=True)
+    print(f"lanczos xxz random fields L={L} basis={basis}", flush=True)
     desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
     m = P.Model(desc)
     v0 = E.random_state_device(L, 3, DEV)
     e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=basis, n_keep=keep)
     print(f"  E0={e0!r} info={info}", flush=True)
     assert info["converged"] and info["residual"] < 2e-10 and info["restarts"] >= 1
-    _CONFIG2.setdefault(L, []).append((e0, psi))
-    if len(_CONFIG2[L]) == 2:
-        (ea, pa), (eb, pb) = _CONFIG2.pop(L)
+    _XXZ_GROUND.setdefault(L, []).append((e0, psi))
+    if len(_XXZ_GROUND[L]) == 2:
+        (ea, pa), (eb, pb) = _XXZ_GROUND.pop(L)
         assert abs(ea - eb) <= 1e-10 * abs(ea)
         assert 1 - abs(torch.vdot(pa, pb).item()) <= 1e-9
     if L == 20:

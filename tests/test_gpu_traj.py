@@ -84,7 +84,7 @@ def test_trajectories_vs_oracle(plain, oracle_runs):
 
 
 def test_trajectory_closed_forms_mixed_lengths():
-    """Config-4 shape (mixed L = 8..16, Delta = 1, gamma = 0.1, dt = 0.01) over T = 2."""
+    """The batched-trajectory workload (mixed L = 8..16, Delta = 1, gamma = 0.1, dt = 0.01) over T = 2."""
     lengths = [8, 10, 12, 14, 16]
     n_traj, dt, steps, stride, seed = 60, 0.01, 200, 10, 4
     models, rates, psi0, mo = setup_batch(lengths, n_traj, seed)
