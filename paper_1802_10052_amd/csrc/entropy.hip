@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void hh_reduce(const double2* __restrict__ par
 
 // Single-workgroup step kernel (1024 threads). Given ys = A22 v for the current step k (rows
 // k+1..n-1, from hh_reduce) it: forms y = tau (A22 v); alpha = -1/2 tau (y^H v); w = y + alpha v;
-// updates column k+1 of the trailing matrix (rows k+1..n-1) with the rank-2 term; records
+// updates column k+1 of the trailing matrix (rows k+1..n-1) with the rank-2 term, into ys; records
 // d[k+1]; builds the next Householder vector from rows k+2.. of that column, with tau, beta.
 // For k = -1 it only builds the first Householder vector from column 0.
 constexpr int kStepThreads = 1024;
@@ -241,11 +241,12 @@ __device__ double block_reduce(double v, double* lds) {
     return s;
 }
 
-__global__ __launch_bounds__(kStepThreads) void hh_step(double2* __restrict__ A, int n, int k,
+__global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restrict__ A, int n, int k,
                                                         double2* __restrict__ v, double2* __restrict__ y,
-                                                        double2* __restrict__ vn, const double2* __restrict__ ys,
+                                                        double2* __restrict__ vn, double2* __restrict__ ys,
                                                         double* __restrict__ d, double* __restrict__ e,
                                                         double2* __restrict__ sc) {
+    double2* const col = ys;  // column c of the trailing matrix after this step's update
     __shared__ double lds[kStepThreads / 64];
     const int t = threadIdx.x;
     const int c = k + 1;  // column of the trailing matrix to finish now
@@ -273,27 +274,32 @@ __global__ __launch_bounds__(kStepThreads) void hh_step(double2* __restrict__ A,
             y[i] = make_double2(yi.x + av.x, yi.y + av.y);  // w
         }
         __syncthreads();
-        // update column c (rows c..n-1): A[i][c] -= v_i conj(w_c) + w_i conj(v_c)
+        // update column c (rows c..n-1): A[i][c] -= v_i conj(w_c) + w_i conj(v_c). Column c is
+        // finished by this step (later steps take rows and columns > c), so the updated column
+        // goes to col = ys (free once y is formed; same rows per thread) instead of back into A:
+        // one strided read of the column, then contiguous reads
         const double2 vc = v[c], wc = y[c];
         for (int i = c + t; i < n; i += kStepThreads) {
             double2 a = A[int64_t(i) * n + c];
             const double2 t1 = cmulc(v[i], conjd(wc)), t2 = cmulc(y[i], conjd(vc));
             a.x -= t1.x + t2.x;
             a.y -= t1.y + t2.y;
-            A[int64_t(i) * n + c] = a;
+            col[i] = a;
         }
-        __syncthreads();
+    } else {
+        for (int i = c + t; i < n; i += kStepThreads) col[i] = A[int64_t(i) * n + c];
     }
+    __syncthreads();
     // diagonal of row c and Householder vector of column c below the diagonal (rows c+1..)
-    if (t == 0) d[c] = A[int64_t(c) * n + c].x;
+    if (t == 0) d[c] = col[c].x;
     if (c + 1 >= n) return;
     double nx = 0.0;
     for (int i = c + 2 + t; i < n; i += kStepThreads) {
-        const double2 a = A[int64_t(i) * n + c];
+        const double2 a = col[i];
         nx += a.x * a.x + a.y * a.y;
     }
     nx = block_reduce(nx, lds);
-    const double2 al = A[int64_t(c + 1) * n + c];
+    const double2 al = col[c + 1];
     double2 tau = make_double2(0.0, 0.0);
     double beta;
     double2 inv = make_double2(0.0, 0.0);
@@ -313,7 +319,7 @@ __global__ __launch_bounds__(kStepThreads) void hh_step(double2* __restrict__ A,
         sc[0] = tau;
         vn[c + 1] = make_double2(1.0, 0.0);
     }
-    for (int i = c + 2 + t; i < n; i += kStepThreads) vn[i] = cmulc(A[int64_t(i) * n + c], inv);
+    for (int i = c + 2 + t; i < n; i += kStepThreads) vn[i] = cmulc(col[i], inv);
 }
 
 // GEMV for the first step: part[cb][i] = sum_{j in tile} A[i][j] v_j over rows/cols >= s
