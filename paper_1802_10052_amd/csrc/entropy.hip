@@ -143,7 +143,7 @@ __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -
 // y = A_new vn, the row sums of its rows (slot C) and the conjugate column sums of its strictly
 // lower entries (slot R, y_j += conj(A_ij) vn_i). In a diagonal tile both go to slot R of the same
 // index. Index i of block B thus gets slot b from tile (B, b) for b < B, (B, B) for b = B and
-// (b, B) for b > B: every slot exactly once, summed in slot order by hh_reduce.
+// (b, B) for b > B: every slot exactly once, summed in a fixed order by hh_reduce.
 constexpr int kSB = 64;
 
 __global__ __launch_bounds__(256) void hh_fused_sym(double2* __restrict__ A, int n, int s,
@@ -208,18 +208,34 @@ __global__ __launch_bounds__(256) void hh_fused_sym(double2* __restrict__ A, int
     }
 }
 
-// ys[i] = sum over the nslots partial sums of row i, in slot order (i in [c, n))
-__global__ __launch_bounds__(256) void hh_reduce(const double2* __restrict__ part, int nslots, int c, int n,
-                                                 double2* __restrict__ ys) {
-    const int i = c + int(blockIdx.x) * 256 + int(threadIdx.x);
-    if (i >= n) return;
+// ys[i] = sum over the nslots partial sums of row i (i in [c, n)). A workgroup takes 32 rows; its
+// 8 groups of 32 threads sum the slots g, g + 8, g + 16, ... of each row, and the 8 group sums are
+// added in group order (a fixed order, so results are reproducible).
+constexpr int kRedRows = 32, kRedGroups = 8;
+
+__global__ __launch_bounds__(kRedRows * kRedGroups) void hh_reduce(const double2* __restrict__ part, int nslots,
+                                                                   int c, int n, double2* __restrict__ ys) {
+    __shared__ double2 red[kRedGroups][kRedRows];
+    const int r = int(threadIdx.x) % kRedRows, g = int(threadIdx.x) / kRedRows;
+    const int i = c + int(blockIdx.x) * kRedRows + r;
     double2 acc = make_double2(0.0, 0.0);
-    for (int b = 0; b < nslots; ++b) {
-        const double2 p = part[int64_t(b) * n + i];
-        acc.x += p.x;
-        acc.y += p.y;
+    if (i < n)
+        for (int b = g; b < nslots; b += kRedGroups) {
+            const double2 p = part[int64_t(b) * n + i];
+            acc.x += p.x;
+            acc.y += p.y;
+        }
+    red[g][r] = acc;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        double2 sum = red[0][r];
+#pragma unroll
+        for (int q = 1; q < kRedGroups; ++q) {
+            sum.x += red[q][r].x;
+            sum.y += red[q][r].y;
+        }
+        ys[i] = sum;
     }
-    ys[i] = acc;
 }
 
 // Single-workgroup step kernel (1024 threads). Given ys = A22 v for the current step k (rows
@@ -457,7 +473,8 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
                 hipLaunchKernelGGL(hh_gemv, dim3(nrb * ncb), dim3(256), 0, s, w.rho, n, s0, w.v, w.part);
                 nslots = ncb;
             }
-            hipLaunchKernelGGL(hh_reduce, dim3((r + 255) / 256), dim3(256), 0, s, w.part, nslots, s0, n, w.ys);
+            hipLaunchKernelGGL(hh_reduce, dim3((r + kRedRows - 1) / kRedRows), dim3(kRedRows * kRedGroups), 0, s, w.part,
+                               nslots, s0, n, w.ys);
             // step kernel: y, w, column k+1 update, next Householder vector into vn
             hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.ys, w.d,
                                w.e, w.sc);
