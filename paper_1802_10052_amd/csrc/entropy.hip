@@ -143,12 +143,15 @@ __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -
 // y = A_new vn, the row sums of its rows (slot C) and the conjugate column sums of its strictly
 // lower entries (slot R, y_j += conj(A_ij) vn_i). In a diagonal tile both go to slot R of the same
 // index. Index i of block B thus gets slot b from tile (B, b) for b < B, (B, B) for b = B and
-// (b, B) for b > B: every slot exactly once, summed in a fixed order by hh_reduce.
+// (b, B) for b > B: every slot exactly once, summed in a fixed order by hh_reduce. Column s, the
+// one the next step finishes, is also written to cn (rows >= s), so that step reads it
+// contiguously.
 constexpr int kSB = 64;
 
 __global__ __launch_bounds__(256) void hh_fused_sym(double2* __restrict__ A, int n, int s,
                                                     const double2* __restrict__ v, const double2* __restrict__ w,
-                                                    const double2* __restrict__ vn, double2* __restrict__ part) {
+                                                    const double2* __restrict__ vn, double2* __restrict__ part,
+                                                    double2* __restrict__ cn) {
     __shared__ double2 colred[4][kSB];
     __shared__ double2 rowred[kSB];
     int b = blockIdx.x, R = 0;
@@ -175,6 +178,7 @@ __global__ __launch_bounds__(256) void hh_fused_sym(double2* __restrict__ A, int
             a.x -= t1.x + t2.x;
             a.y -= t1.y + t2.y;
             A[int64_t(i) * n + j] = a;
+            if (C == 0 && lane == 0) cn[i] = a;  // j == s
             rp = cmulc(a, vnj);
             if (j < i) {
                 const double2 q = cmulc(conjd(a), vni);
@@ -257,11 +261,13 @@ __device__ double block_reduce(double v, double* lds) {
     return s;
 }
 
+// cin: column k+1 as the previous fused update left it, contiguous (rows >= k+1), or null to read
+// it from the matrix.
 __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restrict__ A, int n, int k,
                                                         double2* __restrict__ v, double2* __restrict__ y,
                                                         double2* __restrict__ vn, double2* __restrict__ ys,
                                                         double* __restrict__ d, double* __restrict__ e,
-                                                        double2* __restrict__ sc) {
+                                                        double2* __restrict__ sc, const double2* __restrict__ cin) {
     double2* const col = ys;  // column c of the trailing matrix after this step's update
     __shared__ double lds[kStepThreads / 64];
     const int t = threadIdx.x;
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restric
         // one strided read of the column, then contiguous reads
         const double2 vc = v[c], wc = y[c];
         for (int i = c + t; i < n; i += kStepThreads) {
-            double2 a = A[int64_t(i) * n + c];
+            double2 a = cin ? cin[i] : A[int64_t(i) * n + c];
             const double2 t1 = cmulc(v[i], conjd(wc)), t2 = cmulc(y[i], conjd(vc));
             a.x -= t1.x + t2.x;
             a.y -= t1.y + t2.y;
@@ -374,6 +380,7 @@ struct EntWS {
     double2* y;
     double2* vn;
     double2* ys;
+    double2* cn;  // the next step's column, written contiguously by the fused update
     double2* part;
     double* d;
     double* e;
@@ -384,7 +391,7 @@ struct EntWS {
 int part_slots(int n) { return std::max((n + kFC - 1) / kFC, (n + kSB - 1) / kSB) + 1; }
 
 size_t entropy_bytes(int n) {
-    return align256(size_t(n) * n * sizeof(double2)) + 4 * align256(size_t(n) * sizeof(double2)) +
+    return align256(size_t(n) * n * sizeof(double2)) + 5 * align256(size_t(n) * sizeof(double2)) +
            align256(size_t(part_slots(n)) * n * sizeof(double2)) + 2 * align256(size_t(n) * sizeof(double)) +
            align256(4 * sizeof(double2));
 }
@@ -401,6 +408,8 @@ EntWS carve_ent(void* ws, int n) {
     w.vn = reinterpret_cast<double2*>(p);
     p += align256(size_t(n) * sizeof(double2));
     w.ys = reinterpret_cast<double2*>(p);
+    p += align256(size_t(n) * sizeof(double2));
+    w.cn = reinterpret_cast<double2*>(p);
     p += align256(size_t(n) * sizeof(double2));
     w.part = reinterpret_cast<double2*>(p);
     p += align256(size_t(part_slots(n)) * n * sizeof(double2));
@@ -459,7 +468,7 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
     if (n > 1) {
         // first Householder vector from column 0
         hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, -1, w.v, w.y, w.vn, w.ys, w.d,
-                           w.e, w.sc);
+                           w.e, w.sc, static_cast<const double2*>(nullptr));
         int nslots = 0;  // partial-sum slots of the current product
         for (int k = 0; k + 1 < n; ++k) {
             // the current vector (rows >= k+1) becomes v; A22 v over rows/cols >= k+1
@@ -476,14 +485,16 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
             hipLaunchKernelGGL(hh_reduce, dim3((r + kRedRows - 1) / kRedRows), dim3(kRedRows * kRedGroups), 0, s, w.part,
                                nslots, s0, n, w.ys);
             // step kernel: y, w, column k+1 update, next Householder vector into vn
+            // column k+1 from the previous step's fused update (k >= 1), else from the matrix
+            const double2* cin = k >= 1 ? w.cn : nullptr;
             hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.ys, w.d,
-                               w.e, w.sc);
+                               w.e, w.sc, cin);
             if (k + 2 < n) {
                 // rank-2 update of the lower triangle of rows/cols >= k+2 fused with A_new * vn
                 const int s1 = k + 2;
                 const int nb = (n - s1 + kSB - 1) / kSB;
                 hipLaunchKernelGGL(hh_fused_sym, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, w.rho, n, s1, w.v, w.y,
-                                   w.vn, w.part);
+                                   w.vn, w.part, w.cn);
                 nslots = nb;
             }
             ED_HIP_TRY(hipGetLastError());
