@@ -261,8 +261,28 @@ __device__ double block_reduce(double v, double* lds) {
     return s;
 }
 
+// the same for a complex value: both parts reduced together, in a fixed order
+__device__ double2 block_reduce2(double2 v, double2* lds) {
+    for (int off = 32; off > 0; off >>= 1) {
+        v.x += __shfl_down(v.x, off, 64);
+        v.y += __shfl_down(v.y, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double2 s = make_double2(0.0, 0.0);
+    for (int i = 0; i < kStepThreads / 64; ++i) {
+        s.x += lds[i].x;
+        s.y += lds[i].y;
+    }
+    __syncthreads();
+    return s;
+}
+
 // cin: column k+1 as the previous fused update left it, contiguous (rows >= k+1), or null to read
-// it from the matrix.
+// it from the matrix. Every thread keeps the same rows i = k+1+t, k+1+t+1024, ... through the
+// passes, so a value it wrote is read back by the same thread.
 __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restrict__ A, int n, int k,
                                                         double2* __restrict__ v, double2* __restrict__ y,
                                                         double2* __restrict__ vn, double2* __restrict__ ys,
@@ -270,57 +290,56 @@ __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restric
                                                         double2* __restrict__ sc, const double2* __restrict__ cin) {
     double2* const col = ys;  // column c of the trailing matrix after this step's update
     __shared__ double lds[kStepThreads / 64];
+    __shared__ double2 lds2[kStepThreads / 64];
+    __shared__ double2 syc;
     const int t = threadIdx.x;
     const int c = k + 1;  // column of the trailing matrix to finish now
+    double nx = 0.0;      // |column c|^2 over rows c+2..n-1
     if (k >= 0) {
         const double2 tau = sc[0];
         // y_i = tau * (A22 v)_i, i = k+1..n-1 (the sums from hh_reduce); also y^H v
-        double dre = 0.0, dim = 0.0;
+        double2 yhv = make_double2(0.0, 0.0);
         for (int i = c + t; i < n; i += kStepThreads) {
             const double2 yi = cmulc(tau, ys[i]);
             y[i] = yi;
+            if (i == c) syc = yi;
             const double2 vi = v[i];
             // y^H v = sum conj(y_i) v_i
-            dre += yi.x * vi.x + yi.y * vi.y;
-            dim += yi.x * vi.y - yi.y * vi.x;
+            yhv.x += yi.x * vi.x + yi.y * vi.y;
+            yhv.y += yi.x * vi.y - yi.y * vi.x;
         }
-        dre = block_reduce(dre, lds);
-        dim = block_reduce(dim, lds);
-        // alpha = -1/2 tau (y^H v)
-        const double2 yhv = make_double2(dre, dim);
+        yhv = block_reduce2(yhv, lds2);
+        // alpha = -1/2 tau (y^H v); w = y + alpha v
         const double2 tt = cmulc(tau, yhv);
         const double2 alpha = make_double2(-0.5 * tt.x, -0.5 * tt.y);
+        const double2 vc = v[c], avc = cmulc(alpha, vc);
+        const double2 wc = make_double2(syc.x + avc.x, syc.y + avc.y);
+        // w, and the update of column c (rows c..n-1): A[i][c] -= v_i conj(w_c) + w_i conj(v_c).
+        // Column c is finished by this step (later steps take rows and columns > c), so the
+        // updated column goes to col = ys (free once y is formed) instead of back into A
         for (int i = c + t; i < n; i += kStepThreads) {
             const double2 vi = v[i], yi = y[i];
             const double2 av = cmulc(alpha, vi);
-            y[i] = make_double2(yi.x + av.x, yi.y + av.y);  // w
-        }
-        __syncthreads();
-        // update column c (rows c..n-1): A[i][c] -= v_i conj(w_c) + w_i conj(v_c). Column c is
-        // finished by this step (later steps take rows and columns > c), so the updated column
-        // goes to col = ys (free once y is formed; same rows per thread) instead of back into A:
-        // one strided read of the column, then contiguous reads
-        const double2 vc = v[c], wc = y[c];
-        for (int i = c + t; i < n; i += kStepThreads) {
+            const double2 wi = make_double2(yi.x + av.x, yi.y + av.y);
+            y[i] = wi;
             double2 a = cin ? cin[i] : A[int64_t(i) * n + c];
-            const double2 t1 = cmulc(v[i], conjd(wc)), t2 = cmulc(y[i], conjd(vc));
+            const double2 t1 = cmulc(vi, conjd(wc)), t2 = cmulc(wi, conjd(vc));
             a.x -= t1.x + t2.x;
             a.y -= t1.y + t2.y;
             col[i] = a;
+            if (i >= c + 2) nx += a.x * a.x + a.y * a.y;
         }
     } else {
-        for (int i = c + t; i < n; i += kStepThreads) col[i] = A[int64_t(i) * n + c];
+        for (int i = c + t; i < n; i += kStepThreads) {
+            const double2 a = A[int64_t(i) * n + c];
+            col[i] = a;
+            if (i >= c + 2) nx += a.x * a.x + a.y * a.y;
+        }
     }
-    __syncthreads();
+    nx = block_reduce(nx, lds);  // its barriers also publish col
     // diagonal of row c and Householder vector of column c below the diagonal (rows c+1..)
     if (t == 0) d[c] = col[c].x;
     if (c + 1 >= n) return;
-    double nx = 0.0;
-    for (int i = c + 2 + t; i < n; i += kStepThreads) {
-        const double2 a = col[i];
-        nx += a.x * a.x + a.y * a.y;
-    }
-    nx = block_reduce(nx, lds);
     const double2 al = col[c + 1];
     double2 tau = make_double2(0.0, 0.0);
     double beta;
