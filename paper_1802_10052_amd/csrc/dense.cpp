@@ -9,79 +9,115 @@
 
 namespace ed {
 
-// Implicit symmetric QL with Wilkinson shifts on a tridiagonal matrix (Golub & Van Loan,
-// Sec. 8.3). d[n] diagonal, e[n] sub-diagonal in e[0..n-2]. Z (n x n, row-major) is updated by
-// the rotations (pass the identity to get the eigenvectors of T). Eigenvalues sorted ascending
-// with the columns of Z. Returns false if an eigenvalue fails to converge in 60 sweeps.
+// Eigenvalues (and optionally eigenvectors) of a real symmetric tridiagonal matrix by the
+// implicit symmetric QR algorithm with Wilkinson shifts (Golub & Van Loan, "Matrix
+// Computations", Algorithms 8.3.2 and 8.3.3). d[n] holds the diagonal, e[0..n-2] the
+// off-diagonal (e[i] couples rows i and i+1); both are overwritten, d with the eigenvalues in
+// ascending order. Z (n x n, row-major) may be null; otherwise it is multiplied on the right by
+// every rotation, so passing the identity returns the eigenvectors in its columns, sorted with
+// the eigenvalues. Returns false if the active block has not split after 50 sweeps per
+// eigenvalue on average.
+//
+// Structure: the trailing end of the unreduced part is found by scanning upward from the bottom
+// for a negligible off-diagonal entry; the block above it that is still coupled gets one QR sweep
+// (shift from its trailing 2 x 2, then a Givens rotation that introduces a bulge below the
+// diagonal and a chain of rotations that chases it off the bottom of the block).
+namespace {
+
+// Off-diagonal entry e between diagonals a and b counts as zero when it is below the rounding of
+// its neighbours, or below the rounding of the whole matrix. The second test matters for graded
+// spectra (a ground-state Schmidt spectrum spans 1 .. 1e-30): their tail sits at the rounding
+// level of |T|, where a purely relative test never fires, and dropping |e| <= 1e-17 |T| moves
+// no eigenvalue by more than the rounding of the reduction that produced T.
+inline bool negligible(double e, double a, double b, double abs_tol) {
+    const double ae = std::fabs(e);
+    return ae <= 1e-17 * (std::fabs(a) + std::fabs(b)) || ae <= abs_tol || ae < 1e-300;
+}
+
+// Eigenvalue of the 2 x 2 block [[a, b], [b, c]] closer to c (the Wilkinson shift), written so
+// that it does not cancel: c - b^2 / (delta + sign(delta) sqrt(delta^2 + b^2)), delta = (a - c)/2.
+inline double wilkinson_shift(double a, double b, double c) {
+    const double delta = 0.5 * (a - c);
+    const double root = std::hypot(delta, b);
+    const double den = delta >= 0.0 ? delta + root : delta - root;
+    if (den == 0.0) return c;  // b = 0 and a = c
+    return c - b * (b / den);
+}
+
+// One implicit QR sweep with shift mu on the block lo..hi (hi > lo, all e[lo..hi-1] nonzero).
+// The rotation in the plane (k, k+1) is G = [[c, s], [-s, c]], applied as T <- G T G^T; the
+// first one is fixed by the shifted first column (d[lo] - mu, e[lo]), each later one zeroes the
+// bulge T(k+1, k-1) left by its predecessor against T(k, k-1).
+void qr_sweep(int n, int lo, int hi, double mu, double* d, double* e, double* Z) {
+    double x = d[lo] - mu;  // entry the rotation keeps
+    double z = e[lo];       // entry the rotation removes
+    for (int k = lo; k < hi; ++k) {
+        const double r = std::hypot(x, z);
+        double c = 1.0, s = 0.0;
+        if (r != 0.0) {
+            c = x / r;
+            s = z / r;
+        }
+        if (k > lo) e[k - 1] = r;  // T(k, k-1) after the bulge is removed
+        // similarity on rows/columns k, k+1 of the 2 x 2 diagonal block [[a, b], [b, f]]
+        const double a = d[k], b = e[k], f = d[k + 1];
+        const double cc = c * c, ss = s * s, cs = c * s;
+        d[k] = cc * a + 2.0 * cs * b + ss * f;
+        d[k + 1] = ss * a - 2.0 * cs * b + cc * f;
+        e[k] = cs * (f - a) + (cc - ss) * b;
+        if (k + 1 < hi) {
+            // row k+2 only couples to column k+1: the rotation spreads it onto column k (bulge)
+            const double g = e[k + 1];
+            z = s * g;
+            e[k + 1] = c * g;
+            x = e[k];
+        }
+        if (Z) {
+            for (int row = 0; row < n; ++row) {
+                double* zr = Z + size_t(row) * n;
+                const double u = zr[k], v = zr[k + 1];
+                zr[k] = c * u + s * v;
+                zr[k + 1] = c * v - s * u;
+            }
+        }
+    }
+}
+
+}  // namespace
+
 bool tridiag_ql(int n, double* d, double* e, double* Z) {
     if (n <= 0) return true;
     e[n - 1] = 0.0;
-    // An off-diagonal entry is dropped when it is negligible next to its two diagonal neighbours
-    // or next to the whole matrix: the second test matters for graded spectra (a ground-state
-    // Schmidt spectrum spans 1 .. 1e-30) whose tail sits at the rounding level of |T|, where a
-    // purely relative test never fires. Dropping |e| <= 1e-17 |T| moves eigenvalues by less than
-    // the rounding of the reduction that produced T.
     double tnorm = 0.0;
     for (int i = 0; i < n; ++i) tnorm = std::max(tnorm, std::fabs(d[i]) + 2.0 * std::fabs(e[i]));
     const double abs_tol = 1e-17 * tnorm;
-    for (int l = 0; l < n; ++l) {
-        int iter = 0;
-        while (true) {
-            int m = l;
-            for (; m < n - 1; ++m) {
-                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= 1e-17 * dd || std::fabs(e[m]) <= abs_tol || std::fabs(e[m]) < 1e-300) break;
-            }
-            if (m == l) break;
-            if (++iter > 200) return false;
-            // Wilkinson-type shift from the leading 2x2 block
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = std::hypot(g, 1.0);
-            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-            double s = 1.0, c = 1.0, p = 0.0;
-            int i = m - 1;
-            bool early = false;
-            for (; i >= l; --i) {
-                double f = s * e[i];
-                const double b = c * e[i];
-                r = std::hypot(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) {
-                    d[i + 1] -= p;
-                    e[m] = 0.0;
-                    early = true;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * b;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - b;
-                if (Z) {
-                    for (int k = 0; k < n; ++k) {
-                        f = Z[k * n + i + 1];
-                        Z[k * n + i + 1] = s * Z[k * n + i] + c * f;
-                        Z[k * n + i] = c * Z[k * n + i] - s * f;
-                    }
-                }
-            }
-            if (early) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0.0;
+    long sweeps = 0;
+    const long max_sweeps = 50L * n;
+    int hi = n - 1;  // rows hi+1.. are converged
+    while (hi > 0) {
+        if (negligible(e[hi - 1], d[hi - 1], d[hi], abs_tol)) {
+            e[hi - 1] = 0.0;
+            --hi;
+            continue;
         }
+        int lo = hi - 1;  // grow the unreduced block upward
+        while (lo > 0 && !negligible(e[lo - 1], d[lo - 1], d[lo], abs_tol)) --lo;
+        if (lo > 0) e[lo - 1] = 0.0;
+        if (++sweeps > max_sweeps) return false;
+        qr_sweep(n, lo, hi, wilkinson_shift(d[hi - 1], e[hi - 1], d[hi]), d, e, Z);
     }
-    // sort ascending
-    for (int i = 0; i < n - 1; ++i) {
-        int k = i;
-        for (int j = i + 1; j < n; ++j)
-            if (d[j] < d[k]) k = j;
-        if (k != i) {
-            std::swap(d[i], d[k]);
-            if (Z)
-                for (int r = 0; r < n; ++r) std::swap(Z[r * n + i], Z[r * n + k]);
+    // ascending order, carrying the eigenvector columns along
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return d[i] < d[j]; });
+    std::vector<double> w(d, d + n);
+    for (int i = 0; i < n; ++i) d[i] = w[order[i]];
+    if (Z) {
+        std::vector<double> row(n);
+        for (int r = 0; r < n; ++r) {
+            double* zr = Z + size_t(r) * n;
+            for (int i = 0; i < n; ++i) row[i] = zr[order[i]];
+            std::copy(row.begin(), row.end(), zr);
         }
     }
     return true;

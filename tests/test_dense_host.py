@@ -39,6 +39,12 @@ int main() {
         tridiag_lowest(n, a.data(), b.data(), &th, s.data());
         printf("%.17g\n", th);
         for (double v : s) printf("%.17g\n", v);
+    } else if (mode == 4) {  // tridiagonal QR, values only
+        std::vector<double> d(n), e(n);
+        for (auto& v : d) scanf("%lf", &v);
+        for (int i = 0; i < n - 1; ++i) scanf("%lf", &e[i]);
+        if (!tridiag_ql(n, d.data(), e.data(), nullptr)) return 2;
+        for (double v : d) printf("%.17g\n", v);
     } else {  // complex expm
         std::vector<cplx> A(n * n), E(n * n);
         for (auto& v : A) { double re, im; scanf("%lf %lf", &re, &im); v = cplx(re, im); }
@@ -133,3 +139,83 @@ def test_tridiag_ql_graded_spectrum(driver):
     w = np.array([float(x[0]) for x in out[:n]])
     ref = sla.eigvalsh_tridiagonal(a, b)
     assert np.max(np.abs(w - ref)) < 2e-14 * np.max(np.abs(ref))
+
+
+def _ql(driver, a, b):
+    n = len(a)
+    out = driver(f"0 {n} " + _fmt(a, b))
+    w = np.array([float(x[0]) for x in out[:n]])
+    Z = np.array([float(x[0]) for x in out[n:]]).reshape(n, n)
+    return w, Z
+
+
+def test_tridiag_qr_special_matrices(driver):
+    """Closed forms and hard cases for the implicit QR: the 2x2 block, a matrix that splits into
+    blocks (exact zero couplings), the Wilkinson matrix W21+ (eigenvalue pairs that agree to
+    1e-14), and the second-difference matrix with eigenvalues 2 - 2 cos(k pi / (n + 1))."""
+    # 2 x 2: eigenvalues (a+c)/2 -+ sqrt(((a-c)/2)^2 + b^2)
+    a, b, c = 0.3, -1.7, 2.2
+    w, Z = _ql(driver, np.array([a, c]), np.array([b]))
+    m, r = 0.5 * (a + c), np.hypot(0.5 * (a - c), b)
+    assert np.allclose(w, [m - r, m + r], rtol=0, atol=1e-15)
+    T = np.array([[a, b], [b, c]])
+    assert np.allclose(T @ Z, Z * w, atol=1e-14) and np.allclose(Z.T @ Z, np.eye(2), atol=1e-15)
+    # split blocks
+    a = np.array([1.0, 4.0, -2.0, 0.5, 3.0, 3.0])
+    b = np.array([0.5, 0.0, 1.0, 0.0, 1e-3])
+    w, Z = _ql(driver, a, b)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    assert np.allclose(w, np.linalg.eigvalsh(T), atol=1e-15)
+    assert np.allclose(T @ Z, Z * w, atol=1e-14)
+    # Wilkinson W21+
+    a = np.abs(np.arange(-10, 11)).astype(float)
+    b = np.ones(20)
+    w, Z = _ql(driver, a, b)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    assert np.allclose(w, sla.eigvalsh_tridiagonal(a, b), atol=2e-14)
+    assert np.allclose(Z.T @ Z, np.eye(21), atol=1e-13)
+    assert np.allclose(T @ Z, Z * w, atol=1e-13)
+    # second difference, n = 300
+    n = 300
+    w, Z = _ql(driver, 2.0 * np.ones(n), -np.ones(n - 1))
+    exact = 2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    assert np.max(np.abs(w - exact)) < 1e-13
+
+
+def test_tridiag_qr_graded_vectors(driver):
+    """Eigenvectors of a graded (1 .. 1e-30) tridiagonal: orthonormal to rounding and with
+    residuals at the rounding level of |T|, as the Krylov time step and the adjoint need."""
+    rng = np.random.default_rng(5)
+    n = 120
+    lam = np.exp(-np.linspace(0, 69, n)) * rng.choice([-1.0, 1.0], n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    from scipy.linalg import hessenberg
+    T = hessenberg((Q * lam) @ Q.T)
+    a, b = np.diag(T).copy(), np.diag(T, -1).copy()
+    w, Z = _ql(driver, a, b)
+    Tt = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    # backward-stable level: a few tens of ulps of |T| = 1 for n = 120
+    assert np.max(np.abs(w - sla.eigvalsh_tridiagonal(a, b))) < 1e-14
+    assert np.max(np.abs(Z.T @ Z - np.eye(n))) < 1e-13
+    assert np.max(np.abs(Tt @ Z - Z * w)) < 1e-14
+
+
+def test_tridiag_qr_large_values_only(driver):
+    """n = 4096 without vectors (the size class of the entropy's tridiagonal): random entries and
+    a Schmidt-like graded spectrum, both against LAPACK."""
+    rng = np.random.default_rng(6)
+    n = 4096
+    a, b = rng.standard_normal(n), rng.standard_normal(n - 1)
+    drv_in = f"4 {n} " + _fmt(a, b)
+    out = driver(drv_in)
+    w = np.array([float(x[0]) for x in out])
+    ref = sla.eigvalsh_tridiagonal(a, b)
+    assert np.max(np.abs(w - ref)) < 1e-12
+    # graded: diagonal 1 .. 1e-30 with couplings at the geometric mean scale
+    d = np.exp(-np.linspace(0, 69, n))
+    e = 0.3 * np.sqrt(d[:-1] * d[1:])
+    out = driver(f"4 {n} " + _fmt(d, e))
+    w = np.array([float(x[0]) for x in out])
+    ref = sla.eigvalsh_tridiagonal(d, e)
+    assert np.max(np.abs(w - ref)) < 1e-13 * np.max(np.abs(ref))   # eps |T| times a modest p(n)
+    assert np.all(w[:-1] <= w[1:])
