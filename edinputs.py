@@ -188,3 +188,17 @@ def random_state_device(L, seed, device):
     v = torch.randn(1 << L, dtype=torch.complex128, device=device, generator=g)
     v /= torch.linalg.vector_norm(v)
     return v
+
+
+def graded_schmidt_state(L, l, rank, decay, seed):
+    """State of length 2^L whose matrix view M (2^l rows = sites 1..l) is A diag(s) B^dagger,
+    with complex-normal A (2^l x rank) and B (2^(L-l) x rank) and s_k = exp(-k / decay): a
+    Schmidt spectrum that falls off geometrically like a ground state's, of rank <= rank.
+    Normalised. Seeded."""
+    rng = np.random.default_rng(seed)
+    n, K = 1 << l, 1 << (L - l)
+    A = rng.standard_normal((n, rank)) + 1j * rng.standard_normal((n, rank))
+    B = rng.standard_normal((K, rank)) + 1j * rng.standard_normal((K, rank))
+    s = np.exp(-np.arange(rank) / float(decay))
+    v = ((A * s) @ B.conj().T).reshape(-1)
+    return v / np.linalg.norm(v)

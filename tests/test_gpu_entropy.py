@@ -12,6 +12,7 @@ import paper_1802_10052_amd as P
 from oracle import hamiltonian as OH
 from oracle import lanczos as OL
 from oracle import observables as OO
+from tests import oracle_cache as OC
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -50,9 +51,39 @@ def test_entropy_ground_state_L20():
     the oracle's SVD of the oracle's own ground state."""
     L = 20
     print("entropy ground state L=20", flush=True)
-    desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
-    H = OH.hamiltonian_sparse(desc)
-    e0, psi = OL.ground_state_eigsh(H, tol=1e-14)
+    desc, H, e0, psi = OC.xxz_fields_ground(L)
     S = P.entropy(dev(psi), L, L // 2)
     Sref = OO.bond_entropy(psi, L, L // 2)
     assert abs(S - Sref) <= 1e-10 * abs(Sref)
+
+
+def _host_threads():
+    import os
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.mark.parametrize("kind", ["random", "graded"])
+def test_entropy_half_cut_n4096(kind):
+    """The half cut at L = 24 (M is 4096 x 4096, the size class of the L = 26 workload's 8192):
+    a complex-normal state (flat, Page-like spectrum) and a state whose Schmidt spectrum falls off
+    geometrically over 40 decades with 3584 exact zeros (rank 512), against the oracle's SVD of
+    the same state. The Gram route resolves eigenvalues to about 1e-16 of the largest; those below
+    that floor add at most n 1e-16 |ln 1e-16| ~ 1.5e-11 to S, inside the 1e-10 relative bound."""
+    from threadpoolctl import threadpool_limits
+    L, l = 24, 12
+    print(f"entropy L={L} l={l} {kind}", flush=True)
+    if kind == "random":
+        psi = E.random_state(L, 24)
+    else:
+        psi = E.graded_schmidt_state(L, l, 512, 6.0, 25)
+    S, spec = P.entropy(dev(psi), L, l, spectrum=True)
+    print(f"  GPU S = {S!r}", flush=True)
+    with threadpool_limits(limits=_host_threads()):
+        ref = OO.schmidt_spectrum(psi, L, l)
+    lam = ref[ref > 1e-300]
+    Sref = float(-(lam * np.log(lam)).sum())
+    print(f"  oracle S = {Sref!r}", flush=True)
+    assert abs(S - Sref) <= 1e-10 * abs(Sref)
+    # the spectrum itself, to the Gram route's absolute resolution
+    assert np.max(np.abs(np.sort(spec)[::-1] - ref)) < 1e-13
+    assert abs(np.sum(spec) - 1.0) < 1e-12

@@ -11,6 +11,7 @@ from oracle import krylov as OK
 from oracle import lanczos as OL
 from oracle import observables as OO
 from tests import closed_forms as CF
+from tests import oracle_cache as OC
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -278,3 +279,9 @@ def test_lanczos_xxz_random_fields_restart_sizes(L, basis, keep):
         assert info1["restarts"] == 0
         assert abs(e0 - e1) <= 1e-10 * abs(e1)
         assert 1 - abs(torch.vdot(psi, psi1).item()) <= 1e-9
+        # the oracle: ARPACK on the oracle's sparse H (the paper's statics)
+        print("  oracle eigsh L=20", flush=True)
+        _, _, eo, po = OC.xxz_fields_ground(L)
+        print(f"  oracle E0={eo!r}", flush=True)
+        assert abs(e0 - eo) <= 1e-10 * abs(eo)
+        assert overlap_err(psi.cpu().numpy(), po) <= 1e-9

@@ -83,6 +83,57 @@ def test_trajectories_vs_oracle(plain, oracle_runs):
         assert np.max(np.abs(res["sz"][tr, :, :L] - ref["sz"])) < 1e-9
 
 
+CONFIG_LENGTHS = [8, 10, 12, 14, 16]
+LARGE_CASE = dict(n_traj=60, dt=0.01, steps=200, stride=10, seed=4, per_length=2)
+
+
+def _ids_with_most_jumps(L, c):
+    """Trajectory ids of length L in the config's mix (L = lengths[t mod 5]) whose closed-form
+    jump times put the most jumps inside T (so the compared runs cross thresholds and jump)."""
+    ids = [t for t in range(c["n_traj"]) if CONFIG_LENGTHS[t % 5] == L]
+    T = c["dt"] * c["steps"]
+    ids.sort(key=lambda t: (-len(expected_jump_times(c["seed"], t, L, T)), t))
+    return ids[:c["per_length"]]
+
+
+@pytest.fixture(scope="module")
+def large_oracle_runs():
+    c = LARGE_CASE
+    out = {}
+    for L in (14, 16):
+        H = OH.hamiltonian_sparse(E.xxz(L, 1.0, 1.0))
+        for tr in _ids_with_most_jumps(L, c):
+            print(f"  oracle trajectory {tr} (L={L})", flush=True)
+            out[tr] = OT.trajectory(H, OT.lowering_jumps(L, GAMMA), E.product_state(L, E.neel_index(L)), c["dt"],
+                                    c["steps"], c["stride"], c["seed"], tr, tol=1e-12)
+    return out
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_trajectories_vs_oracle_L14_L16(plain, large_oracle_runs):
+    """Per-trajectory parity at the two longest chains of the batched workload, where a state
+    spans several tiles of the trajectory kernel (4 at L = 14, 16 at L = 16): the config's mix of
+    lengths in one call (60 trajectories, Delta = 1, gamma = 0.1, dt = 0.01, T = 2), and for two
+    trajectories of each of L = 14 and 16 the jump count, times (1e-10), sites and per-site
+    <sigma^z_k>(t) (1e-9) against the oracle on the same Philox streams."""
+    c = LARGE_CASE
+    models, rates, psi0, mo = setup_batch(CONFIG_LENGTHS, c["n_traj"], c["seed"])
+    print(f"trajectories L=14/16 vs oracle plain={plain}", flush=True)
+    res = P.trajectories(models, E.SMINUS, rates, psi0, mo, c["dt"], c["steps"], c["stride"], c["seed"], m_max=20,
+                         tol=1e-12, plain=plain)
+    print("  batched/plain call done", flush=True)
+    checked_jumps = 0
+    for tr, ref in large_oracle_runs.items():
+        L = CONFIG_LENGTHS[mo[tr]]
+        nj = res["n_jumps"][tr]
+        assert nj == len(ref["jumps"]), (tr, nj, ref["jumps"])
+        assert np.allclose(res["jump_t"][tr, :nj], [j[0] for j in ref["jumps"]], rtol=0, atol=1e-10)
+        assert list(res["jump_site"][tr, :nj]) == [j[1] for j in ref["jumps"]]
+        assert np.max(np.abs(res["sz"][tr, :, :L] - ref["sz"])) < 1e-9
+        checked_jumps += nj
+    assert checked_jumps >= 4
+
+
 def test_trajectory_closed_forms_mixed_lengths():
     """The batched-trajectory workload (mixed L = 8..16, Delta = 1, gamma = 0.1, dt = 0.01) over T = 2."""
     lengths = [8, 10, 12, 14, 16]
