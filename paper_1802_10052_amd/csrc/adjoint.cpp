@@ -167,7 +167,7 @@ ed_status slice_models(const ed_model* tmpl, int S, const double* J, ModelSet* m
 
 struct Basis {
     Workspace w;
-    std::vector<double> d, Z;  // eigenpairs of the tridiagonal T
+    std::vector<xreal> d, Z;  // eigenpairs of the tridiagonal T (extended precision)
     int m = 0;
     double nrm = 0.0;
 };
@@ -193,12 +193,13 @@ ed_status build_basis(const ed_model* mod, const double2* psi, double dt_err, co
         if (p->m_fixed > 0) {
             stop = brk || m >= std::min(p->m_fixed, mmax);
         } else if (!stop) {
-            std::vector<double> dd(a.begin(), a.begin() + m), ee(m, 0.0), Z(size_t(m) * m, 0.0);
+            std::vector<xreal> dd(a.begin(), a.begin() + m), ee(m, 0.0L), Z(size_t(m) * m, 0.0L);
             for (int i = 0; i + 1 < m; ++i) ee[i] = b[i];
-            for (int i = 0; i < m; ++i) Z[size_t(i) * m + i] = 1.0;
-            tridiag_ql(m, dd.data(), ee.data(), Z.data());
+            for (int i = 0; i < m; ++i) Z[size_t(i) * m + i] = 1.0L;
+            if (!tridiag_ql_ext(m, dd.data(), ee.data(), Z.data()))
+                return fail(ED_ERR_NUMERIC, "tridiagonal eigensolver did not converge");
             std::vector<cplx> u(m);
-            expm_col_sym(m, dd.data(), Z.data(), std::fabs(dt_err), u.data());
+            expm_col_sym_ext(m, dd.data(), Z.data(), std::fabs(dt_err), u.data());
             stop = B->nrm * beta * std::abs(u[m - 1]) <= p->tol;
         }
         if (stop) break;
@@ -206,18 +207,19 @@ ed_status build_basis(const ed_model* mod, const double2* psi, double dt_err, co
     }
     B->m = m;
     B->d.assign(a.begin(), a.begin() + m);
-    std::vector<double> ee(m, 0.0);
+    std::vector<xreal> ee(m, 0.0L);
     for (int i = 0; i + 1 < m; ++i) ee[i] = b[i];
-    B->Z.assign(size_t(m) * m, 0.0);
-    for (int i = 0; i < m; ++i) B->Z[size_t(i) * m + i] = 1.0;
-    if (!tridiag_ql(m, B->d.data(), ee.data(), B->Z.data())) return fail(ED_ERR_NUMERIC, "tridiagonal QL failed");
+    B->Z.assign(size_t(m) * m, 0.0L);
+    for (int i = 0; i < m; ++i) B->Z[size_t(i) * m + i] = 1.0L;
+    if (!tridiag_ql_ext(m, B->d.data(), ee.data(), B->Z.data()))
+        return fail(ED_ERR_NUMERIC, "tridiagonal eigensolver did not converge");
     return ED_OK;
 }
 
 // out = nrm V exp(-i tau T) e_1
 ed_status eval_basis(const Basis& B, double tau, double2* out, hipStream_t s) {
     std::vector<cplx> u(B.m);
-    expm_col_sym(B.m, B.d.data(), B.Z.data(), tau, u.data());
+    expm_col_sym_ext(B.m, B.d.data(), B.Z.data(), tau, u.data());
     std::vector<double2> c(B.m);
     for (int i = 0; i < B.m; ++i) c[i] = make_double2(B.nrm * u[i].real(), B.nrm * u[i].imag());
     return combine_basis(B.w, B.m, c.data(), out, s);

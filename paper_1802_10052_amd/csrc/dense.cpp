@@ -1,11 +1,16 @@
-// Small dense FP64 solvers for the m x m projected matrices of the Krylov methods (m <= a few
+// Small dense solvers for the m x m projected matrices of the Krylov methods (m <= a few
 // hundred): eigenpairs of real symmetric / tridiagonal matrices and the complex matrix
 // exponential. These are the "exponential transformed to the Krylov basis" of Sec. III.C; they
-// run on the host because m is tiny next to D.
+// run on the host because m is tiny next to D. The tridiagonal eigensolver also has an x87
+// extended-precision instance: the Krylov time step and the adjoint's bases form
+// exp(-i tau T) e_1 with it, so that the coefficients carry FP64 rounding only (not the
+// eigensolver's backward error, a few ulps of |T|) and the propagation is a smooth function of
+// the couplings at the level of FP64 rounding.
 #include "dense.h"
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 
 namespace ed {
 
@@ -29,18 +34,20 @@ namespace {
 // spectra (a ground-state Schmidt spectrum spans 1 .. 1e-30): their tail sits at the rounding
 // level of |T|, where a purely relative test never fires, and dropping |e| <= 1e-17 |T| moves
 // no eigenvalue by more than the rounding of the reduction that produced T.
-inline bool negligible(double e, double a, double b, double abs_tol) {
-    const double ae = std::fabs(e);
-    return ae <= 1e-17 * (std::fabs(a) + std::fabs(b)) || ae <= abs_tol || ae < 1e-300;
+template <typename R>
+inline bool negligible(R e, R a, R b, R rel_tol, R abs_tol) {
+    const R ae = std::fabs(e);
+    return ae <= rel_tol * (std::fabs(a) + std::fabs(b)) || ae <= abs_tol || ae < R(1e-300);
 }
 
 // Eigenvalue of the 2 x 2 block [[a, b], [b, c]] closer to c (the Wilkinson shift), written so
 // that it does not cancel: c - b^2 / (delta + sign(delta) sqrt(delta^2 + b^2)), delta = (a - c)/2.
-inline double wilkinson_shift(double a, double b, double c) {
-    const double delta = 0.5 * (a - c);
-    const double root = std::hypot(delta, b);
-    const double den = delta >= 0.0 ? delta + root : delta - root;
-    if (den == 0.0) return c;  // b = 0 and a = c
+template <typename R>
+inline R wilkinson_shift(R a, R b, R c) {
+    const R delta = R(0.5) * (a - c);
+    const R root = std::hypot(delta, b);
+    const R den = delta >= R(0) ? delta + root : delta - root;
+    if (den == R(0)) return c;  // b = 0 and a = c
     return c - b * (b / den);
 }
 
@@ -48,34 +55,35 @@ inline double wilkinson_shift(double a, double b, double c) {
 // The rotation in the plane (k, k+1) is G = [[c, s], [-s, c]], applied as T <- G T G^T; the
 // first one is fixed by the shifted first column (d[lo] - mu, e[lo]), each later one zeroes the
 // bulge T(k+1, k-1) left by its predecessor against T(k, k-1).
-void qr_sweep(int n, int lo, int hi, double mu, double* d, double* e, double* Z) {
-    double x = d[lo] - mu;  // entry the rotation keeps
-    double z = e[lo];       // entry the rotation removes
+template <typename R>
+void qr_sweep(int n, int lo, int hi, R mu, R* d, R* e, R* Z) {
+    R x = d[lo] - mu;  // entry the rotation keeps
+    R z = e[lo];       // entry the rotation removes
     for (int k = lo; k < hi; ++k) {
-        const double r = std::hypot(x, z);
-        double c = 1.0, s = 0.0;
-        if (r != 0.0) {
+        const R r = std::hypot(x, z);
+        R c = 1, s = 0;
+        if (r != R(0)) {
             c = x / r;
             s = z / r;
         }
         if (k > lo) e[k - 1] = r;  // T(k, k-1) after the bulge is removed
         // similarity on rows/columns k, k+1 of the 2 x 2 diagonal block [[a, b], [b, f]]
-        const double a = d[k], b = e[k], f = d[k + 1];
-        const double cc = c * c, ss = s * s, cs = c * s;
-        d[k] = cc * a + 2.0 * cs * b + ss * f;
-        d[k + 1] = ss * a - 2.0 * cs * b + cc * f;
+        const R a = d[k], b = e[k], f = d[k + 1];
+        const R cc = c * c, ss = s * s, cs = c * s;
+        d[k] = cc * a + R(2) * cs * b + ss * f;
+        d[k + 1] = ss * a - R(2) * cs * b + cc * f;
         e[k] = cs * (f - a) + (cc - ss) * b;
         if (k + 1 < hi) {
             // row k+2 only couples to column k+1: the rotation spreads it onto column k (bulge)
-            const double g = e[k + 1];
+            const R g = e[k + 1];
             z = s * g;
             e[k + 1] = c * g;
             x = e[k];
         }
         if (Z) {
             for (int row = 0; row < n; ++row) {
-                double* zr = Z + size_t(row) * n;
-                const double u = zr[k], v = zr[k + 1];
+                R* zr = Z + size_t(row) * n;
+                const R u = zr[k], v = zr[k + 1];
                 zr[k] = c * u + s * v;
                 zr[k + 1] = c * v - s * u;
             }
@@ -83,26 +91,28 @@ void qr_sweep(int n, int lo, int hi, double mu, double* d, double* e, double* Z)
     }
 }
 
-}  // namespace
-
-bool tridiag_ql(int n, double* d, double* e, double* Z) {
+// The whole algorithm for one real type. Rounding-level tolerances scale with the type's epsilon
+// (eps / 22, about 1e-17 for double).
+template <typename R>
+bool tridiag_qr(int n, R* d, R* e, R* Z) {
     if (n <= 0) return true;
-    e[n - 1] = 0.0;
-    double tnorm = 0.0;
-    for (int i = 0; i < n; ++i) tnorm = std::max(tnorm, std::fabs(d[i]) + 2.0 * std::fabs(e[i]));
-    const double abs_tol = 1e-17 * tnorm;
+    e[n - 1] = 0;
+    const R rel_tol = std::numeric_limits<R>::epsilon() / R(22);
+    R tnorm = 0;
+    for (int i = 0; i < n; ++i) tnorm = std::max(tnorm, std::fabs(d[i]) + R(2) * std::fabs(e[i]));
+    const R abs_tol = rel_tol * tnorm;
     long sweeps = 0;
     const long max_sweeps = 50L * n;
     int hi = n - 1;  // rows hi+1.. are converged
     while (hi > 0) {
-        if (negligible(e[hi - 1], d[hi - 1], d[hi], abs_tol)) {
-            e[hi - 1] = 0.0;
+        if (negligible(e[hi - 1], d[hi - 1], d[hi], rel_tol, abs_tol)) {
+            e[hi - 1] = 0;
             --hi;
             continue;
         }
         int lo = hi - 1;  // grow the unreduced block upward
-        while (lo > 0 && !negligible(e[lo - 1], d[lo - 1], d[lo], abs_tol)) --lo;
-        if (lo > 0) e[lo - 1] = 0.0;
+        while (lo > 0 && !negligible(e[lo - 1], d[lo - 1], d[lo], rel_tol, abs_tol)) --lo;
+        if (lo > 0) e[lo - 1] = 0;
         if (++sweeps > max_sweeps) return false;
         qr_sweep(n, lo, hi, wilkinson_shift(d[hi - 1], e[hi - 1], d[hi]), d, e, Z);
     }
@@ -110,18 +120,24 @@ bool tridiag_ql(int n, double* d, double* e, double* Z) {
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return d[i] < d[j]; });
-    std::vector<double> w(d, d + n);
+    std::vector<R> w(d, d + n);
     for (int i = 0; i < n; ++i) d[i] = w[order[i]];
     if (Z) {
-        std::vector<double> row(n);
+        std::vector<R> row(n);
         for (int r = 0; r < n; ++r) {
-            double* zr = Z + size_t(r) * n;
+            R* zr = Z + size_t(r) * n;
             for (int i = 0; i < n; ++i) row[i] = zr[order[i]];
             std::copy(row.begin(), row.end(), zr);
         }
     }
     return true;
 }
+
+}  // namespace
+
+bool tridiag_ql(int n, double* d, double* e, double* Z) { return tridiag_qr<double>(n, d, e, Z); }
+
+bool tridiag_ql_ext(int n, xreal* d, xreal* e, xreal* Z) { return tridiag_qr<xreal>(n, d, e, Z); }
 
 // Cyclic Jacobi for a dense real symmetric matrix A (row-major, destroyed). Eigenvalues
 // ascending in w, eigenvectors in the columns of Z.
@@ -317,6 +333,25 @@ void expm_col_sym(int n, const double* w, const double* Z, double tau, cplx* u) 
         cplx acc = 0.0;
         for (int k = 0; k < n; ++k) acc += Z[i * n + k] * std::exp(cplx(0.0, -tau * w[k])) * Z[0 * n + k];
         u[i] = acc;
+    }
+}
+
+// The same column from eigenpairs held in extended precision; the sums run in extended precision
+// and only the result is rounded to double.
+void expm_col_sym_ext(int n, const xreal* w, const xreal* Z, double tau, cplx* u) {
+    std::vector<xreal> cr(n), ci(n);
+    for (int k = 0; k < n; ++k) {
+        const xreal ph = xreal(tau) * w[k];
+        cr[k] = std::cos(ph) * Z[k];  // Z[0 * n + k]
+        ci[k] = -std::sin(ph) * Z[k];
+    }
+    for (int i = 0; i < n; ++i) {
+        xreal re = 0, im = 0;
+        for (int k = 0; k < n; ++k) {
+            re += Z[size_t(i) * n + k] * cr[k];
+            im += Z[size_t(i) * n + k] * ci[k];
+        }
+        u[i] = cplx(double(re), double(im));
     }
 }
 

@@ -393,14 +393,15 @@ ed_status krylov_time_step(const ed_model* m, const Workspace& w, double2* psi, 
         mm = j + 1;
         // u = exp(-i dt T_m) e_1
         if (herm) {
-            std::vector<double> d(mm), e(mm), Z(size_t(mm) * mm, 0.0);
+            std::vector<xreal> d(mm), e(mm), Z(size_t(mm) * mm, 0.0L);
             for (int i = 0; i < mm; ++i) {
                 d[i] = Tij(i, i).real();
                 e[i] = (i + 1 < mm) ? Tij(i + 1, i).real() : 0.0;
-                Z[size_t(i) * mm + i] = 1.0;
+                Z[size_t(i) * mm + i] = 1.0L;
             }
-            if (!tridiag_ql(mm, d.data(), e.data(), Z.data())) return fail(ED_ERR_NUMERIC, "tridiagonal QL failed");
-            expm_col_sym(mm, d.data(), Z.data(), dt, u.data());
+            if (!tridiag_ql_ext(mm, d.data(), e.data(), Z.data()))
+                return fail(ED_ERR_NUMERIC, "tridiagonal eigensolver did not converge");
+            expm_col_sym_ext(mm, d.data(), Z.data(), dt, u.data());
         } else {
             std::vector<cplx> A(size_t(mm) * mm), E(size_t(mm) * mm);
             for (int r = 0; r < mm; ++r)
@@ -526,3 +527,4 @@ extern "C" ed_status ed_measure(const ed_c64* psi, int L, double* sz, double* no
     ED_TRY(carve(ws, ws_bytes, int64_t(1) << L, 0, &w));
     return measure_state(reinterpret_cast<const double2*>(psi), L, w, sz, norm, static_cast<hipStream_t>(stream));
 }
+

@@ -45,6 +45,17 @@ int main() {
         for (int i = 0; i < n - 1; ++i) scanf("%lf", &e[i]);
         if (!tridiag_ql(n, d.data(), e.data(), nullptr)) return 2;
         for (double v : d) printf("%.17g\n", v);
+    } else if (mode == 5) {  // exp(-i tau T) e_1 from the extended-precision eigenpairs
+        double tau; if (scanf("%lf", &tau) != 1) return 1;
+        std::vector<xreal> d(n), e(n, 0.0L), Z(n * n, 0.0L);
+        for (auto& v : d) { double x; scanf("%lf", &x); v = x; }
+        for (int i = 0; i < n - 1; ++i) { double x; scanf("%lf", &x); e[i] = x; }
+        for (int i = 0; i < n; ++i) Z[i * n + i] = 1.0L;
+        if (!tridiag_ql_ext(n, d.data(), e.data(), Z.data())) return 2;
+        std::vector<cplx> u(n);
+        expm_col_sym_ext(n, d.data(), Z.data(), tau, u.data());
+        for (int i = 0; i < n; ++i) printf("%.17g\n", double(d[i]));
+        for (auto v : u) printf("%.17g %.17g\n", v.real(), v.imag());
     } else {  // complex expm
         std::vector<cplx> A(n * n), E(n * n);
         for (auto& v : A) { double re, im; scanf("%lf %lf", &re, &im); v = cplx(re, im); }
@@ -219,3 +230,18 @@ def test_tridiag_qr_large_values_only(driver):
     ref = sla.eigvalsh_tridiagonal(d, e)
     assert np.max(np.abs(w - ref)) < 1e-13 * np.max(np.abs(ref))   # eps |T| times a modest p(n)
     assert np.all(w[:-1] <= w[1:])
+
+
+def test_tridiag_ext_expm_column(driver):
+    """The extended-precision instance: eigenvalues against LAPACK and exp(-i tau T) e_1 against
+    scipy's expm of the same tridiagonal, to FP64 rounding."""
+    rng = np.random.default_rng(7)
+    for n, tau in ((1, 0.3), (2, 0.05), (20, 0.05), (40, 0.5)):
+        a, b = 5 * rng.standard_normal(n), 5 * rng.standard_normal(max(n - 1, 0))
+        out = driver(f"5 {n} {tau!r} " + _fmt(a, b))
+        w = np.array([float(x[0]) for x in out[:n]])
+        u = np.array([float(x[0]) + 1j * float(x[1]) for x in out[n:]])
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        assert np.allclose(w, np.linalg.eigvalsh(T), rtol=0, atol=1e-13 * max(1, np.max(np.abs(a))))
+        ref = sla.expm(-1j * tau * T)[:, 0]
+        assert np.max(np.abs(u - ref)) < 1e-14
