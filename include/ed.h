@@ -249,6 +249,21 @@ ed_status ed_measure(const ed_c64* psi, int L, double* sz, double* norm, void* w
                      void* stream);
 
 /* ----------------------------------------------------------------------------------------
+ * ed_measure_noalloc: the same measurement as ed_measure, for callers that cannot allocate
+ * device memory or pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Its partial sums live in a fixed 1 MiB + 4 KiB array of
+ * device memory inside the library, one copy per GPU, resolved on the first call on each device
+ * and kept until the process ends; the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).
+ * psi device, D = 2^L amplitudes; sz host [L]; norm host (may be NULL). Synchronises stream.
+ * Results equal those of ed_measure bit for bit (same kernels, grid and summation order).
+ * Limits: 1 <= L <= 30, else ED_ERR_ARG with a message naming the limit.
+ * Concurrency: every call on one GPU shares that GPU's array; calls that overlap in time on the
+ * same GPU (other threads, other streams) race and must be serialised by the caller.
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_measure_noalloc(const ed_c64* psi, int L, double* sz, double* norm, void* stream);
+
+/* ----------------------------------------------------------------------------------------
  * ed_entropy: bond entropy S(l) = -sum_j Lambda_j log Lambda_j (natural log, 0 log 0 = 0) of the
  * bipartition sites 1..l | l+1..L (Sec. IV, bond entropy). Lambda_j are the eigenvalues of
  * rho_l = M M^dagger / <psi|psi>, M = psi reshaped to 2^l x 2^(L-l) row-major (no copy is made).

@@ -270,6 +270,15 @@ def measure(psi, L, stream=None):
     return sz, nrm.value
 
 
+def measure_noalloc(psi, L, stream=None):
+    """(sz[L], norm) of a device state (ed_measure_noalloc: no workspace, nothing allocated)."""
+    _check_state(psi, 1 << L)
+    sz = np.zeros(L)
+    nrm = C.c_double()
+    call("ed_measure_noalloc", _dptr(psi), int(L), sz.ctypes.data, C.byref(nrm), _stream_ptr(stream))
+    return sz, nrm.value
+
+
 def entropy(psi, L, l_cut=None, spectrum=False, stream=None):
     """Bond entropy S(l_cut) (natural log) of a device state (ed_entropy); with spectrum=True
     also the Schmidt spectrum (descending numpy array)."""

@@ -135,6 +135,7 @@ def _declare(l):
     _fn(l, "ed_evolve_loss", [P, C.c_int, C.c_double, P, P, P, AP, C.POINTER(C.c_double), P, C.c_size_t, P])
     _fn(l, "ed_entropy", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, P, C.c_size_t, P])
     _fn(l, "ed_measure", [P, C.c_int, P, P, P, C.c_size_t, P])
+    _fn(l, "ed_measure_noalloc", [P, C.c_int, P, P, P])
     _fn(l, "ed_liouville_create", [C.POINTER(ModelDescC), C.c_int, P, P, C.POINTER(P)])
     _fn(l, "ed_model_liouville_sites", [P, C.POINTER(C.c_int)])
     _fn(l, "ed_liouville_measure", [P, C.c_int, P, C.POINTER(C.c_double), P, C.c_size_t, P])

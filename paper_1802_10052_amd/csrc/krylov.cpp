@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "dense.h"
@@ -526,5 +527,70 @@ extern "C" ed_status ed_measure(const ed_c64* psi, int L, double* sz, double* no
     Workspace w;
     ED_TRY(carve(ws, ws_bytes, int64_t(1) << L, 0, &w));
     return measure_state(reinterpret_cast<const double2*>(psi), L, w, sz, norm, static_cast<hipStream_t>(stream));
+}
+
+// ============================================================================ measurement, no allocation
+// ed_measure_noalloc runs the kernels of ed_measure on a file-scope device array instead of a
+// caller workspace: the per-block partial sums of the one-pass reduction (at most kRedBlocks
+// rows of kPartLd complex values) and the L + 1 reduced sums. Each device that the library runs
+// on holds its own copy of the array until the process ends; host code uses the address that
+// hipGetSymbolAddress returns for the current device, never the array's name.
+namespace ed {
+namespace {
+
+constexpr size_t kNoAllocPartBytes = (kPartBytes + 255) & ~size_t(255);
+constexpr size_t kNoAllocResultBytes = 256 * sizeof(double2);  // >= (L + 1) entries for L <= 30
+constexpr size_t kNoAllocScratchBytes = kNoAllocPartBytes + kNoAllocResultBytes;
+constexpr int kNoAllocMaxL = 30;
+constexpr int kNoAllocMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per device.
+ed_status noalloc_scratch(void** out) {
+    int dev = -1;
+    ED_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return fail(ED_ERR_UNSUPPORTED, "device index " + std::to_string(dev) + " outside the no-allocation table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ED_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ED_OK;
+}
+
+}  // namespace
+}  // namespace ed
+
+extern "C" ed_status ed_measure_noalloc(const ed_c64* psi, int L, double* sz, double* norm, void* stream) {
+    if (!psi || !sz) return fail(ED_ERR_ARG, "bad argument (psi or sz null)");
+    if (L < 1 || L > kNoAllocMaxL)
+        return fail(ED_ERR_ARG, "L = " + std::to_string(L) + " outside 1.." + std::to_string(kNoAllocMaxL) +
+                                    " (the no-allocation scratch holds the reduction of at most 2^30 amplitudes)");
+    static_assert(size_t(kRedBlocks) * kPartLd * sizeof(double2) <= kNoAllocPartBytes, "partial rows exceed scratch");
+    static_assert(size_t(kNoAllocMaxL + 1) * sizeof(double2) <= kNoAllocResultBytes, "results exceed scratch");
+    void* base = nullptr;
+    ED_TRY(noalloc_scratch(&base));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2* part = static_cast<double2*>(base);
+    double2* res = reinterpret_cast<double2*>(static_cast<char*>(base) + kNoAllocPartBytes);
+    // Every partial row and every result that the reduction reads is written earlier on the same
+    // stream by this call, so nothing has to be cleared first.
+    ED_K(sz_all(reinterpret_cast<const double2*>(psi), L, res, part, s));
+    double2 hv[kNoAllocMaxL + 1];
+    ED_HIP_TRY(hipMemcpyAsync(hv, res, sizeof(double2) * (L + 1), hipMemcpyDeviceToHost, s));
+    ED_HIP_TRY(hipStreamSynchronize(s));
+    const double n2 = hv[0].x;
+    if (norm) *norm = std::sqrt(std::max(n2, 0.0));
+    for (int k = 1; k <= L; ++k) sz[k - 1] = hv[1 + (L - k)].x / n2;
+    return ED_OK;
 }
 
