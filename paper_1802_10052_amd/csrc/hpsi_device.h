@@ -93,33 +93,48 @@ __device__ __forceinline__ int64_t slot_step(const PassArgs& pa, bool first) {
 // DOT (last pass of the product, every thread of the workgroup calls with the same n layout):
 // also writes pa.dot_part[n] = sum over the tile of conj(psi[x]) out[x], out being final here;
 // sD holds one entry per wave of the tile. Contains a workgroup barrier.
+// The load phase of a tile: thread t's amplitudes of psi (and, in later passes, of out, which is
+// read once and not again by this pass: non-temporal, so that it does not evict the state tiles
+// that neighbouring workgroups gather from L2).
+template <bool FIRST, int TB>
+__device__ __forceinline__ void tile_load(const double2* __restrict__ psi, const double2* __restrict__ out,
+                                          const PassArgs& pa, int64_t n, int t, double2* v, double2* acc) {
+    constexpr int kSl = 1 << (kTileBits - TB);
+    const int64_t base = tile_base(pa, FIRST, n);
+    const int64_t i0 = tile_index(pa, FIRST, base, t);
+    const int64_t step = slot_step<TB>(pa, FIRST);
+    const double2* __restrict__ pv = psi + i0;
+#pragma unroll
+    for (int k = 0; k < kSl; ++k) v[k] = pv[k * step];
+    if (!FIRST) {
+#pragma unroll
+        for (int k = 0; k < kSl; ++k) {
+            const double* o = reinterpret_cast<const double*>(out + i0 + k * step);
+            acc[k].x = __builtin_nontemporal_load(o);
+            acc[k].y = __builtin_nontemporal_load(o + 1);
+        }
+    }
+}
+
+// The rest of a tile, once tile_load has filled v (and acc in later passes): stage the tile in
+// LDS, evaluate every term of the pass, store out. Contains a workgroup barrier (two with DOT).
 template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8, bool DOT = false>
-__device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
-                                          const double2* __restrict__ site, const double2* __restrict__ bond,
-                                          const double2* __restrict__ dlo, const double2* __restrict__ dmid,
-                                          const double2* __restrict__ dhi, const PassArgs& pa, int64_t n,
-                                          double2* s, int t = 0, const double2* so = nullptr,
-                                          double2* sF = nullptr, double2* sD = nullptr) {
+__device__ __forceinline__ void tile_finish(double2* __restrict__ out,
+                                            const double2* __restrict__ site, const double2* __restrict__ bond,
+                                            const double2* __restrict__ dlo, const double2* __restrict__ dmid,
+                                            const double2* __restrict__ dhi, const PassArgs& pa, int64_t n,
+                                            double2* s, int t, const double2* so, double2* sF, double2* sD,
+                                            const double2* __restrict__ psi, double2* v, double2* acc) {
     constexpr bool OFFR = CLS & kOffReal;
     constexpr bool DIAGR = CLS & kDiagReal;
     constexpr int kThr = 1 << TB;                  // threads of one tile
     constexpr int kSl = 1 << (kTileBits - TB);     // register slots per thread
     static_assert(TB >= 8 && TB < kTileBits, "the diagonal tables take bits 0..7 from the thread index");
     static_assert(!PAIR || TB == 8, "paired tiles use 256 threads per tile");
-    if (!PAIR) t = threadIdx.x;
     const int64_t base = tile_base(pa, FIRST, n);
     const int64_t i0 = tile_index(pa, FIRST, base, t);
     const int64_t step = slot_step<TB>(pa, FIRST);
     const double2* __restrict__ pv = psi + i0;
-
-    double2 v[kSl];
-    double2 acc[kSl];
-#pragma unroll
-    for (int k = 0; k < kSl; ++k) v[k] = pv[k * step];
-    if (!FIRST) {
-#pragma unroll
-        for (int k = 0; k < kSl; ++k) acc[k] = out[i0 + k * step];
-    }
 #pragma unroll
     for (int k = 0; k < kSl; ++k) s[t + kThr * k] = v[k];
 
@@ -305,6 +320,23 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
             pa.dot_part[n] = sum;
         }
     }
+}
+
+// One tile of one pass (tile index n): tile_load, then tile_finish (see there).
+template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8, bool DOT = false>
+__device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
+                                          const double2* __restrict__ site, const double2* __restrict__ bond,
+                                          const double2* __restrict__ dlo, const double2* __restrict__ dmid,
+                                          const double2* __restrict__ dhi, const PassArgs& pa, int64_t n,
+                                          double2* s, int t = 0, const double2* so = nullptr,
+                                          double2* sF = nullptr, double2* sD = nullptr) {
+    constexpr int kSl = 1 << (kTileBits - TB);
+    if (!PAIR) t = threadIdx.x;
+    double2 v[kSl];
+    double2 acc[kSl];
+    tile_load<FIRST, TB>(psi, out, pa, n, t, v, acc);
+    tile_finish<CLS, FIRST, GATHER, PAIR, TB, DOT>(out, site, bond, dlo, dmid, dhi, pa, n, s, t, so, sF, sD, psi, v,
+                                                   acc);
 }
 
 // Per-amplitude body for one x (small L, or one small state per workgroup): partners read from
