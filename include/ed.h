@@ -141,8 +141,16 @@ ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void
  * ed_lanczos_ground: lowest eigenpair of a Hermitian model, matrix-free. The paper obtains the
  * ground state from the full H with eigh/eigsh (Sec. II, statics); here the same Lanczos
  * recurrence that underlies the Krylov step (Sec. III.C) runs on H psi directly:
- *   v_1 = v0/|v0|; w = H v_j; w is orthogonalised against every stored v_i by classical
- *   Gram-Schmidt applied twice; beta_j = |w|; T = V^H H V is the projected matrix.
+ *   v_1 = v0/|v0|; w = H v_j; beta_j = |w| after orthogonalisation; T = V^H H V is the projected
+ *   matrix. reorth selects how w is orthogonalised:
+ *   ED_REORTH_FULL: against every stored v_i by classical Gram-Schmidt applied twice (past the
+ *     first step of a cycle the first pass takes only v_{j-1}, v_j, whose projections the
+ *     three-term recurrence supplies, and the second pass the whole basis);
+ *   ED_REORTH_PARTIAL: against v_{j-1}, v_j and, by one Gram-Schmidt pass, the kept Ritz vectors
+ *     of the last restart; estimates of the overlaps with the other vectors follow Simon's
+ *     recurrence (on the full projected matrix), and a vector whose estimate exceeds 1e-12 is
+ *     re-orthogonalised, with its successor, against the vectors concerned. The first step of a
+ *     cycle stays full (its projections on the kept vectors are the restarted matrix's arrow).
  *   When the basis reaches max_basis vectors it is restarted thick (Wu & Simon): the n_keep
  *   lowest Ritz vectors and the last residual vector are kept and the recurrence continues.
  *   Convergence: beta_j |s_j| <= tol for the lowest Ritz pair (theta, s) (the residual norm
@@ -155,11 +163,14 @@ ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void
  * Workspace: ed_lanczos_workspace = (max_basis + 1 + n_keep) D complex + scratch.
  * Limits: 2 <= max_basis <= 512, 0 <= n_keep < max_basis (0 means min(10, max_basis/2)).
  * ---------------------------------------------------------------------------------------- */
+typedef enum { ED_REORTH_FULL = 0, ED_REORTH_PARTIAL = 1 } ed_reorth;
+
 typedef struct {
     int max_iter;
     int max_basis;
     int n_keep;
     double tol;
+    int reorth;  /* ed_reorth */
 } ed_lanczos_params;
 
 typedef struct {
@@ -167,6 +178,7 @@ typedef struct {
     int restarts;
     double residual;
     int converged;
+    int extra_reorth;  /* re-orthogonalisations triggered by the estimates (reorth = PARTIAL) */
 } ed_lanczos_info;
 
 ed_status ed_lanczos_workspace(const ed_model* model, const ed_lanczos_params* params, size_t* bytes);

@@ -178,13 +178,18 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def lanczos_ground(model, v0, tol=1e-10, max_iter=200, max_basis=None, n_keep=0, stream=None):
-    """Lowest eigenpair (E0, psi0, info) of a Hermitian model by matrix-free Lanczos with full
-    reorthogonalisation and thick restart (ed_lanczos_ground). info is a dict."""
+REORTH = {"full": 0, "partial": 1}
+
+
+def lanczos_ground(model, v0, tol=1e-10, max_iter=200, max_basis=None, n_keep=0, reorth="full", stream=None):
+    """Lowest eigenpair (E0, psi0, info) of a Hermitian model by matrix-free Lanczos with thick
+    restart (ed_lanczos_ground); reorth "full" (classical Gram-Schmidt twice against the whole basis
+    every step) or "partial" (three-term recurrence, the kept Ritz vectors every step, the rest when
+    the orthogonality estimates ask for it). info is a dict."""
     _check_state(v0, model.D, "v0")
     mb = max_iter + 1 if max_basis is None else max_basis
     mb = max(2, min(mb, 512))
-    p = _lib.LanczosParams(int(max_iter), int(mb), int(n_keep), float(tol))
+    p = _lib.LanczosParams(int(max_iter), int(mb), int(n_keep), float(tol), REORTH[reorth])
     nb = C.c_size_t()
     call("ed_lanczos_workspace", model.handle, C.byref(p), C.byref(nb))
     ws = _workspace(nb.value, v0.device)
@@ -194,7 +199,7 @@ def lanczos_ground(model, v0, tol=1e-10, max_iter=200, max_basis=None, n_keep=0,
     code = lib().ed_lanczos_ground(model.handle, _dptr(v0), C.byref(p), C.byref(e0), _dptr(psi0),
                                    C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
     d = {"iters": info.iters, "restarts": info.restarts, "residual": info.residual,
-         "converged": bool(info.converged), "status": _lib.STATUS.get(code, code)}
+         "converged": bool(info.converged), "extra_reorth": info.extra_reorth, "status": _lib.STATUS.get(code, code)}
     if code not in (0, -7):
         _lib.check("ed_lanczos_ground", code)
     return e0.value, psi0, d

@@ -29,11 +29,13 @@ class ModelDescC(C.Structure):
 
 
 class LanczosParams(C.Structure):
-    _fields_ = [("max_iter", C.c_int), ("max_basis", C.c_int), ("n_keep", C.c_int), ("tol", C.c_double)]
+    _fields_ = [("max_iter", C.c_int), ("max_basis", C.c_int), ("n_keep", C.c_int), ("tol", C.c_double),
+                ("reorth", C.c_int)]
 
 
 class LanczosInfo(C.Structure):
-    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("residual", C.c_double), ("converged", C.c_int)]
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("residual", C.c_double), ("converged", C.c_int),
+                ("extra_reorth", C.c_int)]
 
 
 class KrylovParams(C.Structure):

@@ -1,16 +1,20 @@
 // Host launchers of the vector kernels (vec.hip). All pointers are device memory; `part` is a
-// scratch area of kRedBlocks * kPartLd complex values taken from the caller's workspace.
+// scratch area of kRedBlocks * kPartLd complex values taken from the caller's workspace (the
+// sigma^z reduction uses at most kSzBlocks rows of it).
 #pragma once
 #include "ed_internal.h"
 
 namespace ed {
 
-constexpr int kRedBlocks = 1024;  // max blocks of a partial reduction
+constexpr int kRedBlocks = 4096;  // max blocks of a partial reduction (and of a vector sweep)
+constexpr int kSzBlocks = 1024;   // max blocks of the all-site sigma^z reduction
 constexpr int kPartLd = 64;       // complex entries per block row of the partial buffer
 constexpr int kDotGroup = 16;     // basis vectors per dot/axpy launch
 constexpr int kMaxComb = 64;      // max terms of a Krylov combination
 constexpr int kChunk = 64;        // basis vectors per subtraction sweep
 constexpr int kKeepDots = 16;     // dots of the next pass taken inside a subtraction sweep
+constexpr int kMultiIn = 96;      // inputs of one multi-output combination
+constexpr int kMultiOut = 8;      // outputs of one multi-output combination
 constexpr size_t kPartBytes = size_t(kRedBlocks) * kPartLd * sizeof(double2);
 
 int reduction_blocks(int64_t D);
@@ -53,6 +57,10 @@ hipError_t axpy_norm_ptr(const double2* const* U, int n, const double2* coef, co
 // subtraction and the dots of the first kKeepDots vectors share one sweep.
 hipError_t axpy_dots_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
                          int64_t D, double2* dots_out, double2* part, hipStream_t s);
+// out_o = sum_i C[i * n_out + o] U_i for o < n_out (C device, real, n_in x n_out row-major), in one
+// sweep; outputs may alias inputs. n_in <= kMultiIn, n_out <= kMultiOut.
+hipError_t combination_multi(const double2* const* U, int n_in, const double* C, double2* const* out, int n_out,
+                             int64_t D, hipStream_t s);
 // out = sum_i c[i] U_i (c host); out may be U_0 when n <= kMaxComb
 hipError_t combination_ptr(const double2* const* U, int n, const double2* c, double2* out, int64_t D, hipStream_t s);
 

@@ -67,7 +67,8 @@ ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s)
 // projections h_i = <v_i|H v_j> (i = lo..j) and the norm beta of the orthogonalised H v_j; the new
 // basis vector is u_{j+1} = y with c_{j+1} = 1/|y|.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
-                      cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo, double beta_prev) {
+                      cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo, double beta_prev,
+                      const double* known) {
     const int64_t D = w.D;
     const int n = j - lo + 1;
     if (n > kMaxProj) return fail(ED_ERR_UNSUPPORTED, "too many projections");
@@ -81,8 +82,9 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     // CGS2 whose first pass takes only v_{j-1}, v_j: that pass's projections are beta_{j-1} and
     // <v_j|H v_j> as well (the second pass takes the whole basis)
     const bool local_first = passes > 1 && first_lo == j - 1 && first_lo > lo && beta_prev >= 0.0;
+    const bool known_first = known && passes > 1 && lo == 0 && first_lo < 0;
     int64_t nparts = 0;
-    if (three_term || local_first) {
+    if (three_term || local_first || known_first) {
         // the product's last pass also leaves per-tile partials of <u_j|y> in the partial buffer
         ED_TRY(launch_apply_H_dot(m, w.u[j], y, w.part, int64_t(kPartBytes / sizeof(double2)), &nparts, s));
     } else {
@@ -98,6 +100,13 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
         // <u_{j-1}|y> = beta_{j-1} / (c_{j-1} c_j) for a Hermitian H; <u_j|y> from the product's
         // partials, or one dot sweep
         if (n == 2) ED_K(set_scalar(g1, make_double2(beta_prev / (w.c[lo] * w.c[j]), 0.0), s));
+        if (nparts > 0) ED_K(sum_partials(w.part, nparts, g1 + (n - 1), s));
+        else ED_K(dots_ptr(U + (n - 1), 1, y, D, g1 + (n - 1), w.part, s));
+    } else if (known_first) {
+        // <u_i|y> = h_i / (c_i c_j) for the known projections; <u_j|y> from the product
+        std::vector<double2> gk(n - 1);
+        for (int i = 0; i + 1 < n; ++i) gk[i] = make_double2(known[i] / (w.c[i] * w.c[j]), 0.0);
+        for (int i = 0; i + 1 < n; ++i) ED_K(set_scalar(g1 + i, gk[i], s));
         if (nparts > 0) ED_K(sum_partials(w.part, nparts, g1 + (n - 1), s));
         else ED_K(dots_ptr(U + (n - 1), 1, y, D, g1 + (n - 1), w.part, s));
     } else if (local_first) {
@@ -171,6 +180,84 @@ ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipS
     return ED_OK;
 }
 
+// One step of the Lanczos recurrence with partial reorthogonalisation: y = H u_j into slot j+1,
+// projected on v_{j-1} and v_j (the three-term recurrence: beta_{j-1} is known and <v_j|H v_j> comes
+// from the product's last pass) and, by one classical Gram-Schmidt pass computed from the same y, on
+// the nk kept Ritz vectors u_0..u_{nk-1} of a thick restart (the directions in which new vectors
+// lose orthogonality fastest). Returns alpha_j = <v_j|H v_j> and beta_j = |orthogonalised H v_j|.
+ed_status lanczos_local_step(const ed_model* m, const Workspace& w, int j, int nk, double beta_prev, double* alpha,
+                             double* beta, bool* breakdown, hipStream_t s) {
+    const int64_t D = w.D;
+    if (nk + 2 > kMaxProj) return fail(ED_ERR_UNSUPPORTED, "too many kept vectors");
+    if (int(w.u.size()) < j + 2) {
+        w.u.resize(j + 2, nullptr);
+        w.c.resize(j + 2, 0.0);
+    }
+    double2* y = w.slot(j + 1);
+    int64_t nparts = 0;
+    ED_TRY(launch_apply_H_dot(m, w.u[j], y, w.part, int64_t(kPartBytes / sizeof(double2)), &nparts, s));
+    const int n = nk + 2;
+    std::vector<const double2*> U(n);
+    std::vector<double> sc(n);
+    for (int i = 0; i < nk; ++i) U[i] = w.u[i];
+    U[nk] = w.u[j - 1];
+    U[nk + 1] = w.u[j];
+    for (int i = 0; i < nk; ++i) sc[i] = w.c[i] * w.c[i];
+    sc[nk] = w.c[j - 1] * w.c[j - 1];
+    sc[nk + 1] = w.c[j] * w.c[j];
+    double2* nr = w.scal + kNrm;
+    double2* g = w.scal + 1;
+    // <u_j|y> from the product's partials first (the dots below reuse the partial buffer)
+    if (nparts > 0) ED_K(sum_partials(w.part, nparts, g + nk + 1, s));
+    else ED_K(dots_ptr(U.data() + nk + 1, 1, y, D, g + nk + 1, w.part, s));
+    ED_K(set_scalar(g + nk, make_double2(beta_prev / (w.c[j - 1] * w.c[j]), 0.0), s));
+    if (nk > 0) ED_K(dots_ptr(U.data(), nk, y, D, g, w.part, s));
+    ED_K(axpy_norm_ptr(U.data(), n, g, sc.data(), y, D, nr, w.part, s));
+    std::vector<double2> hs(1 + n);
+    ED_TRY(fetch_scalars(w.scal, 1 + n, hs.data(), s));
+    const double cj = w.c[j];
+    *alpha = cj * cj * hs[1 + nk + 1].x;
+    const double nrm2v = hs[kNrm].x;
+    if (!std::isfinite(nrm2v) || !std::isfinite(*alpha))
+        return fail(ED_ERR_NUMERIC, "non-finite value in the Lanczos recurrence");
+    const double ny = std::sqrt(std::max(nrm2v, 0.0));
+    *beta = cj * ny;
+    *breakdown = (*beta <= 1e-14 * std::max(std::max(std::fabs(*alpha), beta_prev), 1e-300)) || *beta == 0.0;
+    w.u[j + 1] = y;
+    w.c[j + 1] = *breakdown ? 0.0 : 1.0 / ny;
+    if (!*breakdown && (ny > 1e100 || ny < 1e-100)) {
+        ED_K(scale(y, y, make_double2(1.0 / ny, 0.0), D, s));
+        w.c[j + 1] = 1.0;
+    }
+    return ED_OK;
+}
+
+// Re-orthogonalise basis vector jn against the vectors listed in sel (one classical Gram-Schmidt
+// pass: its components there are small, at most the trigger level of the orthogonality estimates).
+// Returns the projections <v_i|v_jn before> in proj (real parts, in sel order) and the new |u_jn|.
+ed_status reorth_selected(const Workspace& w, int jn, const std::vector<int>& sel, std::vector<double>* proj,
+                          double* ny_new, hipStream_t s) {
+    const int n = int(sel.size());
+    if (n + 1 > kScalars) return fail(ED_ERR_UNSUPPORTED, "too many vectors to re-orthogonalise against");
+    std::vector<const double2*> U(n);
+    std::vector<double> sc(n);
+    for (int k = 0; k < n; ++k) {
+        U[k] = w.u[sel[k]];
+        sc[k] = w.c[sel[k]] * w.c[sel[k]];
+    }
+    double2* y = w.u[jn];
+    double2* nr = w.scal + kNrm;
+    double2* g = w.scal + 1;
+    ED_K(dots_ptr(U.data(), n, y, w.D, g, w.part, s));
+    ED_K(axpy_norm_ptr(U.data(), n, g, sc.data(), y, w.D, nr, w.part, s));
+    std::vector<double2> hs(1 + n);
+    ED_TRY(fetch_scalars(w.scal, 1 + n, hs.data(), s));
+    proj->resize(n);
+    for (int k = 0; k < n; ++k) (*proj)[k] = w.c[sel[k]] * w.c[jn] * hs[1 + k].x;
+    *ny_new = std::sqrt(std::max(hs[kNrm].x, 0.0));
+    return ED_OK;
+}
+
 ed_status combine_basis(const Workspace& w, int m, const double2* xi, double2* out, hipStream_t s) {
     if (m > kMaxComb && out == w.u[0]) return fail(ED_ERR_UNSUPPORTED, "in-place combination of more than 64 vectors");
     std::vector<double2> c(m);
@@ -201,6 +288,8 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
     if (p->max_iter < 1) return fail(ED_ERR_ARG, "max_iter must be >= 1");
     if (!(p->tol > 0.0)) return fail(ED_ERR_ARG, "tol must be > 0");
     if (model->lv_L > 0) return fail(ED_ERR_UNSUPPORTED, "Lanczos needs a Hermitian model, not a Liouvillian");
+    if (p->reorth != ED_REORTH_FULL && p->reorth != ED_REORTH_PARTIAL)
+        return fail(ED_ERR_ARG, "reorth must be ED_REORTH_FULL or ED_REORTH_PARTIAL");
     size_t need = 0;
     ED_TRY(ed_lanczos_workspace(model, p, &need));
     const int mb = p->max_basis;
@@ -216,32 +305,106 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
 
     std::vector<double> T(size_t(mb + 1) * (mb + 1), 0.0);
     auto Tij = [&](int i, int j) -> double& { return T[size_t(i) * (mb + 1) + j]; };
+    // partial reorthogonalisation: W(i, l) estimates <v_i|v_l> (Simon's recurrence, here on the
+    // whole projected matrix, so that it also holds across the arrow of a thick restart)
+    const bool partial = p->reorth == ED_REORTH_PARTIAL;
+    std::vector<double> Wv(partial ? size_t(mb + 2) * (mb + 2) : 0, 0.0);
+    auto Wij = [&](int i, int l) -> double& { return Wv[size_t(i) * (mb + 2) + l]; };
+    if (partial) Wij(0, 0) = 1.0;
+    double anorm = 0.0;
+    bool reorth_pending = false;
+    std::vector<int> sel;
+    std::vector<double> proj, restart_coef;
     std::vector<cplx> h(mb + 1);
-    int j = 0, iters = 0, restarts = 0, k_locked = 0;
+    int j = 0, iters = 0, restarts = 0, k_locked = 0, extra = 0;
     bool converged = false;
     double theta = 0.0;
     std::vector<double> svec;
     int m = 0;
     ed_status result = ED_OK;
+    auto step_fail = [&](ed_status st) {
+        return fail(st, std::string(ed_last_error()) + " (Lanczos product " + std::to_string(iters + 1) + ", restarts " +
+                            std::to_string(restarts) + ", basis index " + std::to_string(j) + ")");
+    };
     while (true) {
         double beta = 0.0;
         bool brk = false;
-        {
+        // Full steps: every step with reorth = FULL; with PARTIAL only the first step of a cycle (its
+        // projections on the kept Ritz vectors are the arrow of the restarted matrix).
+        const bool full = !partial || j == 0 || j == k_locked;
+        if (full) {
             // past the first step of a cycle the recurrence is three-term: the first Gram-Schmidt
-            // pass needs only v_{j-1}, v_j (the second one takes the whole basis)
+            // pass needs only v_{j-1}, v_j (the second one takes the whole basis); at the first step
+            // after a restart the first pass's projections on the kept vectors are the arrow
             const int first_lo = (j >= 1 && j > k_locked) ? j - 1 : -1;
             const double beta_prev = first_lo >= 0 ? Tij(j, j - 1) : -1.0;
-            const ed_status st =
-                krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s, first_lo, beta_prev);
-            if (st != ED_OK)
-                return fail(st, std::string(ed_last_error()) + " (Lanczos product " + std::to_string(iters + 1) +
-                                    ", restarts " + std::to_string(restarts) + ", basis index " + std::to_string(j) + ")");
+            std::vector<double> arrow;
+            if (restarts > 0 && j == k_locked) {
+                arrow.resize(j);
+                for (int i = 0; i < j; ++i) arrow[i] = Tij(i, j);
+            }
+            const ed_status st = krylov_step(model, w, j, 0, 2, 1e-14, h.data(), &beta, &brk, s, first_lo, beta_prev,
+                                             arrow.empty() ? nullptr : arrow.data());
+            if (st != ED_OK) return step_fail(st);
+            for (int i = 0; i <= j; ++i) {
+                Tij(i, j) = h[i].real();
+                Tij(j, i) = h[i].real();
+            }
+            if (partial) {
+                for (int i = 0; i <= j; ++i) Wij(j + 1, i) = Wij(i, j + 1) = kOrthEps;
+            }
+        } else {
+            double alpha = 0.0;
+            const double beta_prev = Tij(j, j - 1);
+            const ed_status st = lanczos_local_step(model, w, j, k_locked, beta_prev, &alpha, &beta, &brk, s);
+            if (st != ED_OK) return step_fail(st);
+            Tij(j, j) = alpha;
+            if (!brk) {
+                // estimates for the new vector j+1: beta_j W(j+1, i) = sum_l T(l, i) W(l, j) - sum_l T(l, j) W(i, l)
+                // + a rounding term, for the vectors it was not explicitly projected on
+                anorm = std::max(anorm, std::fabs(alpha) + beta + beta_prev);
+                const double noise = kOrthEps * anorm / beta;
+                double wmax = 0.0;
+                for (int i = k_locked; i + 1 < j; ++i) {
+                    double t1 = 0.0, t2 = 0.0;
+                    for (int l = 0; l <= j; ++l) {
+                        t1 += Tij(l, i) * Wij(l, j);
+                        t2 += Tij(l, j) * Wij(i, l);
+                    }
+                    double wn = (t1 - t2) / beta;
+                    wn += std::copysign(noise, wn);
+                    Wij(j + 1, i) = Wij(i, j + 1) = wn;
+                    wmax = std::max(wmax, std::fabs(wn));
+                }
+                for (int i = 0; i < k_locked; ++i) Wij(j + 1, i) = Wij(i, j + 1) = kOrthEps;
+                Wij(j + 1, j) = Wij(j, j + 1) = Wij(j + 1, j - 1) = Wij(j - 1, j + 1) = kOrthEps;
+                if (reorth_pending || wmax > kOrthTrigger) {
+                    // the vector and its successor are re-orthogonalised against the vectors whose
+                    // estimate exceeds kOrthSelect (both, since the recurrence carries the component
+                    // of v_j into v_{j+2})
+                    sel.clear();
+                    for (int i = k_locked; i + 1 < j; ++i)
+                        if (std::fabs(Wij(j + 1, i)) > kOrthSelect) sel.push_back(i);
+                    if (!sel.empty()) {
+                        double ny = 0.0;
+                        const ed_status st2 = reorth_selected(w, j + 1, sel, &proj, &ny, s);
+                        if (st2 != ED_OK) return step_fail(st2);
+                        for (size_t k = 0; k < sel.size(); ++k) {
+                            Tij(sel[k], j) += beta * proj[k];
+                            Tij(j, sel[k]) = Tij(sel[k], j);
+                            Wij(j + 1, sel[k]) = Wij(sel[k], j + 1) = kOrthEps;
+                        }
+                        beta = w.c[j] * ny;
+                        w.c[j + 1] = 1.0 / ny;
+                        ++extra;
+                    }
+                    reorth_pending = !reorth_pending;
+                }
+            }
+            Tij(j - 1, j) = beta_prev;
         }
+        if (partial) Wij(j + 1, j + 1) = 1.0;
         ++iters;
-        for (int i = 0; i <= j; ++i) {
-            Tij(i, j) = h[i].real();
-            Tij(j, i) = h[i].real();
-        }
         m = j + 1;
         // lowest Ritz pair of the m x m projected matrix
         svec.assign(m, 0.0);
@@ -275,16 +438,34 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
             for (int r = 0; r < m; ++r)
                 for (int c = 0; c < m; ++c) A[size_t(r) * m + c] = Tij(r, c);
             sym_eig_jacobi(m, A.data(), wv.data(), Z.data());
-            double2* tmp = w.V + int64_t(mb + 1) * D;
-            for (int i = 0; i < keep; ++i) {
-                std::vector<double2> c(m);
-                for (int r = 0; r < m; ++r) c[r] = make_double2(Z[size_t(r) * m + i], 0.0);
-                ED_TRY(combine_basis(w, m, c.data(), tmp + int64_t(i) * D, s));
-            }
             const double cm = w.c[m];
-            ED_HIP_TRY(hipMemcpyAsync(w.V, tmp, size_t(keep) * D * sizeof(double2), hipMemcpyDeviceToDevice, s));
-            // the residual direction v_m = c_m u_m is stored normalised in slot `keep`
-            ED_K(scale(w.u[m], w.slot(keep), make_double2(cm, 0.0), D, s));
+            if (m + 1 <= kMultiIn && keep + 1 <= kMultiOut) {
+                // one sweep over the basis writes the Ritz vectors y_i = sum_r Z(r, i) v_r and the
+                // normalised residual direction into slots 0..keep, in place
+                restart_coef.assign(size_t(m + 1) * (keep + 1), 0.0);
+                for (int r = 0; r < m; ++r)
+                    for (int i = 0; i < keep; ++i) restart_coef[size_t(r) * (keep + 1) + i] = Z[size_t(r) * m + i] * w.c[r];
+                restart_coef[size_t(m) * (keep + 1) + keep] = cm;
+                double* cdev = reinterpret_cast<double*>(w.part);
+                ED_HIP_TRY(hipMemcpyAsync(cdev, restart_coef.data(), restart_coef.size() * sizeof(double),
+                                          hipMemcpyHostToDevice, s));
+                std::vector<double2*> outs(keep + 1);
+                for (int i = 0; i <= keep; ++i) outs[i] = w.slot(i);
+                ED_K(combination_multi(const_cast<const double2* const*>(w.u.data()), m + 1, cdev, outs.data(), keep + 1,
+                                       D, s));
+                // the coefficient upload must be complete before restart_coef is touched again
+                ED_HIP_TRY(hipStreamSynchronize(s));
+            } else {
+                double2* tmp = w.V + int64_t(mb + 1) * D;
+                for (int i = 0; i < keep; ++i) {
+                    std::vector<double2> c(m);
+                    for (int r = 0; r < m; ++r) c[r] = make_double2(Z[size_t(r) * m + i], 0.0);
+                    ED_TRY(combine_basis(w, m, c.data(), tmp + int64_t(i) * D, s));
+                }
+                ED_HIP_TRY(hipMemcpyAsync(w.V, tmp, size_t(keep) * D * sizeof(double2), hipMemcpyDeviceToDevice, s));
+                // the residual direction v_m = c_m u_m is stored normalised in slot `keep`
+                ED_K(scale(w.u[m], w.slot(keep), make_double2(cm, 0.0), D, s));
+            }
             for (int i = 0; i <= keep; ++i) {
                 w.u[i] = w.slot(i);
                 w.c[i] = 1.0;
@@ -294,6 +475,12 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
                 Tij(i, i) = wv[i];
                 Tij(i, keep) = beta * Z[size_t(m - 1) * m + i];
                 Tij(keep, i) = Tij(i, keep);
+            }
+            if (partial) {
+                std::fill(Wv.begin(), Wv.end(), 0.0);
+                for (int i = 0; i <= keep; ++i)
+                    for (int l = 0; l <= keep; ++l) Wij(i, l) = i == l ? 1.0 : kOrthEps;
+                reorth_pending = false;
             }
             j = keep;
             k_locked = keep;
@@ -323,6 +510,7 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
         info->restarts = restarts;
         info->residual = std::sqrt(std::max(hv[kNrm].x, 0.0));
         info->converged = converged ? 1 : 0;
+        info->extra_reorth = extra;
     }
     return result;
 }
@@ -531,14 +719,14 @@ extern "C" ed_status ed_measure(const ed_c64* psi, int L, double* sz, double* no
 
 // ============================================================================ measurement, no allocation
 // ed_measure_noalloc runs the kernels of ed_measure on a file-scope device array instead of a
-// caller workspace: the per-block partial sums of the one-pass reduction (at most kRedBlocks
+// caller workspace: the per-block partial sums of the one-pass reduction (at most kSzBlocks
 // rows of kPartLd complex values) and the L + 1 reduced sums. Each device that the library runs
 // on holds its own copy of the array until the process ends; host code uses the address that
 // hipGetSymbolAddress returns for the current device, never the array's name.
 namespace ed {
 namespace {
 
-constexpr size_t kNoAllocPartBytes = (kPartBytes + 255) & ~size_t(255);
+constexpr size_t kNoAllocPartBytes = (size_t(kSzBlocks) * kPartLd * sizeof(double2) + 255) & ~size_t(255);
 constexpr size_t kNoAllocResultBytes = 256 * sizeof(double2);  // >= (L + 1) entries for L <= 30
 constexpr size_t kNoAllocScratchBytes = kNoAllocPartBytes + kNoAllocResultBytes;
 constexpr int kNoAllocMaxL = 30;
@@ -575,7 +763,7 @@ extern "C" ed_status ed_measure_noalloc(const ed_c64* psi, int L, double* sz, do
     if (L < 1 || L > kNoAllocMaxL)
         return fail(ED_ERR_ARG, "L = " + std::to_string(L) + " outside 1.." + std::to_string(kNoAllocMaxL) +
                                     " (the no-allocation scratch holds the reduction of at most 2^30 amplitudes)");
-    static_assert(size_t(kRedBlocks) * kPartLd * sizeof(double2) <= kNoAllocPartBytes, "partial rows exceed scratch");
+    static_assert(size_t(kSzBlocks) * kPartLd * sizeof(double2) <= kNoAllocPartBytes, "partial rows exceed scratch");
     static_assert(size_t(kNoAllocMaxL + 1) * sizeof(double2) <= kNoAllocResultBytes, "results exceed scratch");
     void* base = nullptr;
     ED_TRY(noalloc_scratch(&base));

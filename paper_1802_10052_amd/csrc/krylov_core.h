@@ -10,6 +10,14 @@ constexpr int kMaxProj = 520;                  // max vectors one step projects 
 constexpr int kNrm = 0;                        // scalar area: [norm^2, h1[n], h2[n] ... | obs]
 constexpr int kObs = 1 + 2 * kMaxProj;
 constexpr int kScalars = kObs + 64;
+// Partial reorthogonalisation of the Lanczos ground state: a new vector whose estimated overlap with
+// an earlier one exceeds kOrthTrigger is re-orthogonalised (with its successor) against the vectors
+// whose estimate exceeds kOrthSelect; vectors projected explicitly start at kOrthEps (the unit
+// roundoff). The trigger sits well below sqrt(eps): semi-orthogonality alone keeps the Ritz values
+// exact but not the Ritz vector's residual at the 1e-10 level.
+constexpr double kOrthEps = 1.1102230246251565e-16;
+constexpr double kOrthTrigger = 1e-12;
+constexpr double kOrthSelect = 1e-14;
 
 // Caller workspace carved into: partial-reduction buffer, device scalars, nvec vectors of D.
 // The Krylov basis lives there as (u_i, c_i) with v_i = c_i u_i: u_i is slot i of V except that
@@ -35,9 +43,12 @@ ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s)
 // first_lo = j - 1): the projection of H v_j on v_{j-1} (in the first pass) is taken as
 // beta_prev, the previous step's norm (they are equal for a Hermitian H), and <v_j|H v_j> comes
 // from the product's last pass where the plan allows, else from one dot sweep.
+// known (host, passes = 2, lo = 0, first_lo < 0): the first pass's projections <v_i|H v_j> for
+// i = 0..j-1 are known in advance (the first step after a thick restart: the restarted matrix's
+// arrow), so that pass needs only <v_j|H v_j>, from the product.
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
                       cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo = -1,
-                      double beta_prev = -1.0);
+                      double beta_prev = -1.0, const double* known = nullptr);
 // Basis vector 0 from psi: alias = true uses psi itself as u_0 (c_0 = 1/|psi|); otherwise psi/|psi|
 // is written to slot 0 (c_0 = 1).
 ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s, bool alias = false);

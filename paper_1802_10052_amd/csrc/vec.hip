@@ -373,6 +373,41 @@ __global__ __launch_bounds__(kThreads) void combine_ptr(CombPtrs cp, int n, doub
     }
 }
 
+// out_o[x] = sum_i C[i * n_out + o] u_i[x] for o < n_out (real coefficients in device memory, staged
+// in LDS). Every thread reads all inputs at its x before it writes its outputs at x, so the
+// outputs may be any of the inputs (the pointers carry no restrict).
+struct MultiPtrs {
+    const double2* in[kMultiIn];
+    double2* out[kMultiOut];
+};
+
+__global__ __launch_bounds__(kThreads) void combine_multi_kernel(MultiPtrs P, int n_in, int n_out,
+                                                                 const double* __restrict__ C, int64_t D) {
+    __shared__ double cs[kMultiIn * kMultiOut];
+    for (int i = threadIdx.x; i < n_in * n_out; i += kThreads) cs[i] = C[i];
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * kThreads;
+    for (int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x; x < D; x += stride) {
+        double2 acc[kMultiOut];
+#pragma unroll
+        for (int o = 0; o < kMultiOut; ++o) acc[o] = make_double2(0.0, 0.0);
+        for (int i = 0; i < n_in; ++i) {
+            const double2 v = P.in[i][x];
+#pragma unroll
+            for (int o = 0; o < kMultiOut; ++o) {
+                if (o < n_out) {
+                    const double c = cs[i * n_out + o];
+                    acc[o].x = fma(c, v.x, acc[o].x);
+                    acc[o].y = fma(c, v.y, acc[o].y);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < kMultiOut; ++o)
+            if (o < n_out) P.out[o][x] = acc[o];
+    }
+}
+
 inline int grid_for(int64_t D) {
     int64_t g = D / (kThreads * 4);
     if (g < 1) g = 1;
@@ -457,7 +492,7 @@ hipError_t sz_all(const double2* psi, int L, double2* out, double2* part, hipStr
     const int64_t D = int64_t(1) << L;
     const int cb = L < kZBits ? L : kZBits;
     int64_t nchunk = D >> cb;
-    int G = int(nchunk < kRedBlocks ? nchunk : kRedBlocks);
+    int G = int(nchunk < kSzBlocks ? nchunk : kSzBlocks);
     hipLaunchKernelGGL(sz_partial, dim3(G), dim3(kThreads), 0, s, psi, L, part, kPartLd);
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, L + 1, out, 0);
     return hipGetLastError();
@@ -545,6 +580,16 @@ hipError_t axpy_dots_ptr(const double2* const* U, int n, const double2* coef, co
     const int nk = n < kKeepDots ? n : kKeepDots;
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, nk, dots_out, 0);
     if (n > kKeepDots) return dots_ptr(U + kKeepDots, n - kKeepDots, w, D, dots_out + kKeepDots, part, s);
+    return hipGetLastError();
+}
+
+hipError_t combination_multi(const double2* const* U, int n_in, const double* C, double2* const* out, int n_out,
+                             int64_t D, hipStream_t s) {
+    if (n_in < 1 || n_in > kMultiIn || n_out < 1 || n_out > kMultiOut) return hipErrorInvalidValue;
+    MultiPtrs P;
+    for (int i = 0; i < kMultiIn; ++i) P.in[i] = i < n_in ? U[i] : nullptr;
+    for (int o = 0; o < kMultiOut; ++o) P.out[o] = o < n_out ? out[o] : nullptr;
+    hipLaunchKernelGGL(combine_multi_kernel, dim3(grid_for(D)), dim3(kThreads), 0, s, P, n_in, n_out, C, D);
     return hipGetLastError();
 }
 
