@@ -124,6 +124,27 @@ ed_status ed_model_tune(ed_model* model, const ed_c64* psi, ed_c64* out, int rep
                         float* times_ms);
 
 /* ----------------------------------------------------------------------------------------
+ * Tuned-plan cache (host memory, process-wide). An entry maps a model's plan key to the
+ * description of its fastest plan. The key names the GPU architecture, L, the operator class
+ * (kernel variant), the Liouville and long-range flags and a hash of the model's whole candidate
+ * list, so it applies only to models whose planner proposes the same candidates.
+ *   ed_model_create / ed_liouville_create select the cached plan when the key has an entry whose
+ *     plan is among the candidates (else the planner's first candidate, as without a cache);
+ *   ed_model_tune stores its choice under the model's key;
+ *   ed_plan_cache_load merges "<key> TAB <plan>" lines from a text file ('#' starts a comment)
+ *     and returns the number of entries read; ed_plan_cache_save writes every entry (replacing the
+ *     file through a temporary in the same directory);
+ *   ed_plan_cache_get / _put / _clear read, set and empty entries (host only, no GPU needed);
+ *   ed_model_plan_key writes the model's key (NUL-terminated; ED_ERR_ARG if buf_len is too small).
+ * Keys and plans must not contain tabs or newlines. The cache is guarded by a mutex. */
+ed_status ed_model_plan_key(const ed_model* model, char* buf, int buf_len);
+ed_status ed_plan_cache_load(const char* path, int* entries);
+ed_status ed_plan_cache_save(const char* path);
+ed_status ed_plan_cache_get(const char* key, char* buf, int buf_len);
+ed_status ed_plan_cache_put(const char* key, const char* plan);
+ed_status ed_plan_cache_clear(void);
+
+/* ----------------------------------------------------------------------------------------
  * ed_apply_H: out = H psi (Sec. III.C, the rule set applied to the state without building H,
  * Eq. ed:eq:OKrylov). psi and out are device arrays of D amplitudes that must not overlap.
  * Asynchronous on stream.

@@ -91,6 +91,13 @@ class Model:
         call("ed_model_plan_describe", self._h, int(index), buf, 256)
         return buf.value.decode()
 
+    @property
+    def plan_key(self):
+        """The model's key in the tuned-plan cache (ed_model_plan_key)."""
+        buf = C.create_string_buffer(512)
+        call("ed_model_plan_key", self._h, buf, 512)
+        return buf.value.decode()
+
     def tune(self, psi, out=None, reps=3, stream=None):
         """Time every candidate H psi plan on psi (ed_model_tune) and keep the fastest.
         Returns (best index, list of ms per product)."""
@@ -176,6 +183,32 @@ def apply_H(model, psi, out=None, stream=None):
 
 def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def plan_cache_load(path):
+    """Merge a tuned-plan file into the process's plan cache; returns the number of entries."""
+    n = C.c_int()
+    call("ed_plan_cache_load", str(path).encode(), C.byref(n))
+    return n.value
+
+
+def plan_cache_save(path):
+    call("ed_plan_cache_save", str(path).encode())
+
+
+def plan_cache_get(key):
+    """The cached plan description for key, or None."""
+    buf = C.create_string_buffer(512)
+    code = lib().ed_plan_cache_get(key.encode(), buf, 512)
+    return buf.value.decode() if code == 0 else None
+
+
+def plan_cache_put(key, plan):
+    call("ed_plan_cache_put", key.encode(), plan.encode())
+
+
+def plan_cache_clear():
+    call("ed_plan_cache_clear")
 
 
 REORTH = {"full": 0, "partial": 1}

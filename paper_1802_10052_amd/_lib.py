@@ -90,7 +90,22 @@ def lib():
             raise ImportError(f"libed.so is not built ({LIB_PATH}); run paper_1802_10052_amd/build.py")
         _lib = C.CDLL(LIB_PATH)
         _declare(_lib)
+        _load_default_plans(_lib)
     return _lib
+
+
+# Tuned H psi plans shipped with the package (written by tune_plans.py on the target GPU); the
+# environment variable ED_PLAN_CACHE names another file, or "none" to start with an empty cache.
+DEFAULT_PLANS = os.path.join(HERE, "plan_cache.tsv")
+
+
+def _load_default_plans(l):
+    path = os.environ.get("ED_PLAN_CACHE", DEFAULT_PLANS)
+    if path and path != "none" and os.path.exists(path):
+        n = C.c_int()
+        code = l.ed_plan_cache_load(path.encode(), C.byref(n))
+        if code != 0:
+            raise RuntimeError(f"plan cache {path}: {l.ed_last_error().decode(errors='replace')}")
 
 
 def _fn(l, name, argtypes, restype=C.c_int):
@@ -138,6 +153,12 @@ def _declare(l):
     _fn(l, "ed_entropy", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, P, C.c_size_t, P])
     _fn(l, "ed_measure", [P, C.c_int, P, P, P, C.c_size_t, P])
     _fn(l, "ed_measure_noalloc", [P, C.c_int, P, P, P])
+    _fn(l, "ed_model_plan_key", [P, C.c_char_p, C.c_int])
+    _fn(l, "ed_plan_cache_load", [C.c_char_p, C.POINTER(C.c_int)])
+    _fn(l, "ed_plan_cache_save", [C.c_char_p])
+    _fn(l, "ed_plan_cache_get", [C.c_char_p, C.c_char_p, C.c_int])
+    _fn(l, "ed_plan_cache_put", [C.c_char_p, C.c_char_p])
+    _fn(l, "ed_plan_cache_clear", [])
     _fn(l, "ed_liouville_create", [C.POINTER(ModelDescC), C.c_int, P, P, C.POINTER(P)])
     _fn(l, "ed_model_liouville_sites", [P, C.POINTER(C.c_int)])
     _fn(l, "ed_liouville_measure", [P, C.c_int, P, C.POINTER(C.c_double), P, C.c_size_t, P])

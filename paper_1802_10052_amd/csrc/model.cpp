@@ -5,8 +5,13 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 
 #include "ed_internal.h"
 
@@ -539,6 +544,8 @@ ed_status validate_desc(const ed_model_desc* desc) {
     return ED_OK;
 }
 
+void apply_cached_plan(ed_model* m);
+
 ed_status create_model(const ed_model_desc* desc, ed_model** out) {
     ED_TRY(validate_desc(desc));
     ed_model* m = new (std::nothrow) ed_model();
@@ -551,6 +558,7 @@ ed_status create_model(const ed_model_desc* desc, ed_model** out) {
         delete m;
         return st;
     }
+    apply_cached_plan(m);
     *out = m;
     return ED_OK;
 }
@@ -672,8 +680,104 @@ ed_status create_liouville(const ed_model_desc* H, int n_jump, const ed_c64* jum
             return fail(ED_ERR_HIP, std::string("far-term upload: ") + hipGetErrorString(e));
         }
     }
+    apply_cached_plan(m);
     *out = m;
     return ED_OK;
+}
+
+// One-line description of candidate plan `index`, e.g. "first +G5 wide | c4 h17 +G3".
+std::string describe_plan(const ed_model* m, int index) {
+    std::string d;
+    for (int i = 0; i < m->cand_np[index]; ++i) {
+        const PassDesc& pd = m->cand[index][i];
+        if (i) d += " | ";
+        if (m->L < kTileBits) {
+            d += "small";
+        } else if (pd.first) {
+            d += "first";
+        } else {
+            d += "c" + std::to_string(pd.c) + " h" + std::to_string(pd.h0);
+        }
+        if (pd.G > 0) d += " +G" + std::to_string(pd.G);
+        if (pd.occ1) d += " occ1";
+        if (pd.pair) d += " pair";
+        if (pd.wide) d += " wide";
+    }
+    return d;
+}
+
+// ------------------------------------------------------------------------ tuned-plan cache
+// Key -> description of the fastest plan. The key names the GPU architecture, L, the operator
+// class (the kernel variant), the Liouville and long-range flags and a hash of the whole candidate
+// list, so an entry applies only to a model whose planner proposes exactly the same candidates.
+namespace {
+struct PlanCache {
+    std::mutex mu;
+    std::map<std::string, std::string> map;
+};
+PlanCache& plan_cache() {
+    static PlanCache c;
+    return c;
+}
+
+std::string arch_name(int device) {
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = names.find(device);
+    if (it != names.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string a = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        a = prop.gcnArchName;
+        const size_t colon = a.find(':');
+        if (colon != std::string::npos) a = a.substr(0, colon);
+    }
+    names[device] = a;
+    return a;
+}
+}  // namespace
+
+std::string plan_key(const ed_model* m) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the candidate descriptions
+    for (int c = 0; c < m->n_cand; ++c) {
+        for (char ch : describe_plan(m, c) + ";") {
+            h ^= uint64_t(uint8_t(ch));
+            h *= 1099511628211ull;
+        }
+    }
+    char hex[17];
+    std::snprintf(hex, sizeof hex, "%016llx", static_cast<unsigned long long>(h));
+    return arch_name(m->device) + " L=" + std::to_string(m->L) + " class=" + std::to_string(m->op_class) +
+           " liouville=" + std::to_string(m->lv_L) + " lr=" + std::to_string(m->lr ? 1 : 0) +
+           " far=" + std::to_string(m->far.size()) + " cands=" + hex;
+}
+
+// Select the cached plan of m, if the cache holds one for its key (no-op otherwise).
+void apply_cached_plan(ed_model* m) {
+    std::string want;
+    {
+        PlanCache& pc = plan_cache();
+        std::lock_guard<std::mutex> lock(pc.mu);
+        auto it = pc.map.find(plan_key(m));
+        if (it == pc.map.end()) return;
+        want = it->second;
+    }
+    for (int c = 0; c < m->n_cand; ++c) {
+        if (describe_plan(m, c) == want) {
+            m->plan = c;
+            m->n_pass = m->cand_np[c];
+            for (int i = 0; i < m->n_pass; ++i) m->pass[i] = m->cand[c][i];
+            return;
+        }
+    }
+}
+
+void remember_plan(const ed_model* m) {
+    PlanCache& pc = plan_cache();
+    const std::string key = plan_key(m), val = describe_plan(m, m->plan);
+    std::lock_guard<std::mutex> lock(pc.mu);
+    pc.map[key] = val;
 }
 
 void destroy_model(ed_model* m) {
@@ -750,24 +854,88 @@ ed_status ed_model_select_plan(ed_model* model, int index) {
 ed_status ed_model_plan_describe(const ed_model* model, int index, char* buf, int buf_len) {
     if (!model || !buf || buf_len < 1) return ed::fail(ED_ERR_ARG, "null argument");
     if (index < 0 || index >= model->n_cand) return ed::fail(ED_ERR_ARG, "plan index out of range");
-    std::string d;
-    for (int i = 0; i < model->cand_np[index]; ++i) {
-        const ed::PassDesc& pd = model->cand[index][i];
-        if (i) d += " | ";
-        if (model->L < ed::kTileBits) {
-            d += "small";
-        } else if (pd.first) {
-            d += "first";
-        } else {
-            d += "c" + std::to_string(pd.c) + " h" + std::to_string(pd.h0);
-        }
-        if (pd.G > 0) d += " +G" + std::to_string(pd.G);
-        if (pd.occ1) d += " occ1";
-        if (pd.pair) d += " pair";
-        if (pd.wide) d += " wide";
-    }
+    const std::string d = ed::describe_plan(model, index);
     std::strncpy(buf, d.c_str(), size_t(buf_len) - 1);
     buf[buf_len - 1] = 0;
+    return ED_OK;
+}
+
+ed_status ed_model_plan_key(const ed_model* model, char* buf, int buf_len) {
+    if (!model || !buf || buf_len < 1) return ed::fail(ED_ERR_ARG, "null argument");
+    const std::string k = ed::plan_key(model);
+    if (int(k.size()) >= buf_len) return ed::fail(ED_ERR_ARG, "buffer too small for the plan key");
+    std::memcpy(buf, k.c_str(), k.size() + 1);
+    return ED_OK;
+}
+
+ed_status ed_plan_cache_put(const char* key, const char* plan) {
+    if (!key || !plan || !*key || !*plan) return ed::fail(ED_ERR_ARG, "empty key or plan");
+    if (std::strpbrk(key, "\t\n") || std::strpbrk(plan, "\t\n"))
+        return ed::fail(ED_ERR_ARG, "key and plan may not contain tabs or newlines");
+    ed::PlanCache& pc = ed::plan_cache();
+    std::lock_guard<std::mutex> lock(pc.mu);
+    pc.map[key] = plan;
+    return ED_OK;
+}
+
+ed_status ed_plan_cache_get(const char* key, char* buf, int buf_len) {
+    if (!key || !buf || buf_len < 1) return ed::fail(ED_ERR_ARG, "null argument");
+    ed::PlanCache& pc = ed::plan_cache();
+    std::lock_guard<std::mutex> lock(pc.mu);
+    auto it = pc.map.find(key);
+    if (it == pc.map.end()) return ed::fail(ED_ERR_ARG, std::string("no cached plan for key '") + key + "'");
+    if (int(it->second.size()) >= buf_len) return ed::fail(ED_ERR_ARG, "buffer too small for the plan");
+    std::memcpy(buf, it->second.c_str(), it->second.size() + 1);
+    return ED_OK;
+}
+
+ed_status ed_plan_cache_clear(void) {
+    ed::PlanCache& pc = ed::plan_cache();
+    std::lock_guard<std::mutex> lock(pc.mu);
+    pc.map.clear();
+    return ED_OK;
+}
+
+ed_status ed_plan_cache_load(const char* path, int* entries) {
+    if (!path) return ed::fail(ED_ERR_ARG, "path is null");
+    std::ifstream f(path);
+    if (!f) return ed::fail(ED_ERR_ARG, std::string("cannot read plan cache ") + path);
+    std::string line;
+    int n = 0, lineno = 0;
+    std::map<std::string, std::string> add;
+    while (std::getline(f, line)) {
+        ++lineno;
+        if (line.empty() || line[0] == '#') continue;
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos || tab == 0 || tab + 1 >= line.size())
+            return ed::fail(ED_ERR_ARG, std::string(path) + ":" + std::to_string(lineno) + ": expected <key>\\t<plan>");
+        add[line.substr(0, tab)] = line.substr(tab + 1);
+        ++n;
+    }
+    ed::PlanCache& pc = ed::plan_cache();
+    std::lock_guard<std::mutex> lock(pc.mu);
+    for (auto& kv : add) pc.map[kv.first] = kv.second;
+    if (entries) *entries = n;
+    return ED_OK;
+}
+
+ed_status ed_plan_cache_save(const char* path) {
+    if (!path) return ed::fail(ED_ERR_ARG, "path is null");
+    std::ostringstream o;
+    o << "# libed tuned H psi plans: <GPU arch, L, operator class, flags, candidate-list hash> TAB <plan>\n";
+    {
+        ed::PlanCache& pc = ed::plan_cache();
+        std::lock_guard<std::mutex> lock(pc.mu);
+        for (auto& kv : pc.map) o << kv.first << '\t' << kv.second << '\n';
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return ed::fail(ED_ERR_ARG, std::string("cannot write ") + tmp);
+        f << o.str();
+        if (!f) return ed::fail(ED_ERR_ARG, std::string("write failed: ") + tmp);
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return ed::fail(ED_ERR_ARG, std::string("cannot replace ") + path);
     return ED_OK;
 }
 
@@ -803,6 +971,7 @@ ed_status ed_model_tune(ed_model* model, const ed_c64* psi, ed_c64* out, int rep
     (void)hipEventDestroy(e1);
     ED_TRY(st);
     ed_model_select_plan(model, arg);
+    ed::remember_plan(model);
     if (best) *best = arg;
     return ED_OK;
 }

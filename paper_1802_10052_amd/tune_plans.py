@@ -1,0 +1,59 @@
+"""Tune the H psi pass plans of the standard workloads on this GPU and write the plan cache.
+
+    python -m paper_1802_10052_amd.tune_plans --out paper_1802_10052_amd/plan_cache.tsv
+
+Every candidate plan of each model is timed on a seeded state (ed_model_tune) and the fastest is
+stored under the model's key (GPU architecture, L, operator class, flags, candidate-list hash);
+the package loads the file when the library is first used, and model creation then selects the
+stored plan. Workloads: transverse-field Ising (g = 0.5) and XXZ (Delta = 0.5, random fields) chains
+at L = 12..28, the dissipative XXZ chain's effective Hamiltonian, the long-range Ising chain at
+L = 28, and the L = 14 Liouvillian of the dissipative XXZ chain.
+"""
+import argparse
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--max-L", type=int, default=28)
+    args = ap.parse_args()
+    os.environ["ED_PLAN_CACHE"] = "none"   # tune from scratch
+    import numpy as np
+    import torch
+    import edinputs as E
+    import paper_1802_10052_amd as P
+
+    dev = "cuda:0"
+    models = []
+    for L in range(12, args.max_L + 1, 2):
+        models.append((f"tfim{L}", lambda L=L: P.Model(E.tfim(L, 0.5))))
+        models.append((f"xxz{L}", lambda L=L: P.Model(E.xxz(L, 1.0, 0.5, E.random_fields(L, 2)))))
+        models.append((f"tfim{L}g1", lambda L=L: P.Model(E.tfim(L, 1.0))))
+    for L in (25, 27):
+        models.append((f"tfim{L}", lambda L=L: P.Model(E.tfim(L, 0.5))))
+        models.append((f"xxz{L}", lambda L=L: P.Model(E.xxz(L, 1.0, 0.5, E.random_fields(L, 2)))))
+    if args.max_L >= 28:
+        models.append(("lrqi28", lambda: P.Model(E.lrqi(28, np.pi / 4, 1.5))))
+    models.append(("liouville14", lambda: P.Liouville(E.xxz(14, 1.0, 1.0), [E.SMINUS], np.full((1, 14), 0.1))))
+    for name, make in models:
+        m = make()
+        psi = E.random_state_device(m.L, 11, dev)
+        out = torch.empty_like(psi)
+        best, ms = m.tune(psi, out, reps=args.reps)
+        print(f"{name}: {m.describe_plan(best)} {ms[best]:.3f} ms (of {len(ms)} plans)", flush=True)
+        del psi, out, m
+        torch.cuda.empty_cache()
+    P.plan_cache_save(args.out)
+    print(f"wrote {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -2,6 +2,8 @@
 
 Relative 2-norm error <= 1e-13: both sides sum at most 3L+1 products per entry in float64, so
 the rounding difference is a few ulp of the largest term."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -126,3 +128,26 @@ def test_apply_H_every_candidate_plan(L, kind):
     best, times = m.tune(psi, reps=2)
     assert 0 <= best < n and len(times) == n and all(t > 0 for t in times)
     assert m.plans[1] == best
+
+
+def test_tuned_plan_cache_selects_at_creation(tmp_path):
+    """ed_model_tune stores its choice; a new model of the same kind created after the cache is
+    saved, cleared and reloaded starts on that plan; a model of another L does not match it."""
+    L = 22
+    P.plan_cache_clear()
+    m = P.Model(E.tfim(L, 0.5))
+    psi = E.random_state_device(L, 11, DEV)
+    best, ms = m.tune(psi, reps=1)
+    key, desc = m.plan_key, m.describe_plan(best)
+    assert key.startswith("gfx") and f" L={L} " in key
+    assert P.plan_cache_get(key) == desc
+    path = tmp_path / "plans.tsv"
+    P.plan_cache_save(path)
+    P.plan_cache_clear()
+    assert P.Model(E.tfim(L, 0.5)).plans[1] == 0        # no entry: the planner's first candidate
+    assert P.plan_cache_load(path) == 1
+    m2 = P.Model(E.tfim(L, 0.5))
+    assert m2.describe_plan() == desc and m2.plans[1] == best
+    assert P.Model(E.tfim(L + 2, 0.5)).plan_key != key
+    P.plan_cache_clear()
+    P.plan_cache_load(P._lib.DEFAULT_PLANS) if os.path.exists(P._lib.DEFAULT_PLANS) else None
