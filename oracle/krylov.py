@@ -25,16 +25,17 @@ def krylov_basis(matvec, psi, m_max, dt, tol, hermitian=True, fixed_m=0):
     all projections kept in T).
     """
     beta0 = np.linalg.norm(psi)
-    V = [psi / beta0]
+    Vr = np.zeros((m_max + 1, psi.shape[0]), np.complex128)   # basis vectors as rows
+    Vr[0] = psi / beta0
     T = np.zeros((m_max + 1, m_max + 1), np.complex128)
     m = 0
     for j in range(m_max):
-        w = matvec(V[j])
-        Vm = np.stack(V, axis=1)
-        h = Vm.conj().T @ w
-        w = w - Vm @ h
-        h2 = Vm.conj().T @ w
-        w = w - Vm @ h2
+        w = matvec(Vr[j])
+        Vj = Vr[:j + 1]
+        h = np.conj(Vj @ np.conj(w))           # V^H w
+        w = w - Vj.T @ h
+        h2 = np.conj(Vj @ np.conj(w))
+        w = w - Vj.T @ h2
         h = h + h2
         if hermitian:
             T[j, j] = h[j].real
@@ -54,8 +55,8 @@ def krylov_basis(matvec, psi, m_max, dt, tol, hermitian=True, fixed_m=0):
         elif err <= tol or b <= 1e-14 * max(tnorm, 1.0):
             break
         T[j + 1, j] = b
-        V.append(w / b)
-    return np.stack(V[:m], axis=1), T[:m, :m].copy(), beta0, m
+        Vr[j + 1] = w / b
+    return Vr[:m].T.copy(), T[:m, :m].copy(), beta0, m
 
 
 def krylov_step(matvec, psi, dt, m_max=20, tol=1e-10, hermitian=True, fixed_m=0):

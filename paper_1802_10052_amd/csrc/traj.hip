@@ -8,8 +8,11 @@
 // matrix is upper Hessenberg (Sec. VI.B). The step's basis gives psi(t + tau) for every tau in the
 // step, so the time at which |psi|^2 reaches r is solved in the small space, without extra H psi.
 //
-// Batched path: one persistent launch. Each workgroup takes trajectories from a queue (longest
-// chains first), keeps the state and Krylov basis in its own slice of the workspace, runs H psi
+// Batched path: one persistent launch. Each workgroup runs its own list of trajectories, dealt on
+// the host by longest processing time first (each trajectory, heaviest first, goes to the
+// workgroup with the least work so far; the work of a trajectory is taken proportional to its
+// state size plus a fixed per-step overhead), keeps the state and Krylov basis in its own slice of
+// the workspace, runs H psi
 // tile by tile through LDS, and does every reduction, the small exponential, the root search,
 // the Philox draws and the jumps itself, so a trajectory never returns to the host.
 // Plain path: the same algorithm one trajectory at a time from the host, on the library's
@@ -17,6 +20,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <queue>
+#include <utility>
 #include <vector>
 
 #include "dense.h"
@@ -86,7 +91,8 @@ struct TrajModel {
 
 struct TrajArgs {
     const TrajModel* models;
-    const int* order;
+    const int* order;        // trajectories grouped by workgroup: workgroup g runs order[start[g] .. start[g+1])
+    const int* start;        // [gridDim.x + 1]
     const int* model_of;
     int n_traj;
     double dt;
@@ -647,13 +653,14 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
     __syncthreads();
 }
 
-// Persistent launch: workgroup g runs trajectories order[g], order[g + G], ... (the order is
-// longest chain first, so the round-robin deal is balanced); every loop below is bounded.
+// Persistent launch: workgroup g runs the trajectories order[start[g]] .. order[start[g+1] - 1],
+// a list the host deals by longest processing time first; every loop below is bounded.
 template <unsigned CLS>
 __global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(2))) void traj_kernel(TrajArgs a) {
     __shared__ Shared sh;
     double2* base = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
-    for (int q = blockIdx.x; q < a.n_traj; q += gridDim.x) run_trajectory<CLS>(a, a.order[q], base, sh);
+    const int q0 = a.start[blockIdx.x], q1 = a.start[blockIdx.x + 1];
+    for (int q = q0; q < q1; ++q) run_trajectory<CLS>(a, a.order[q], base, sh);
 }
 
 __global__ void zero_ints(int* p, int n) {
@@ -832,10 +839,43 @@ static int persistent_blocks(int n_traj, int Lmax, int m_max, int variant) {
     return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(n_traj), int64_t(per_cu) * cu, by_mem})));
 }
 
+// Longest-processing-time deal of the trajectories over G workgroups: heaviest first, each to the
+// workgroup with the least work so far (ties to the lower index). A trajectory's work is taken as
+// 2^L + kStepOverhead amplitude-equivalents per step (its products and sweeps stream the state; a
+// step also has a fixed cost of barriers and small serial work). Returns the trajectories grouped
+// by workgroup in ord and the group offsets in start[0..G].
+static void deal_trajectories(const ed_traj_desc* d, int G, std::vector<int>* ord, std::vector<int>* start) {
+    constexpr double kStepOverhead = 2048.0;
+    const int nt = d->n_traj;
+    std::vector<int> by_cost(nt);
+    for (int i = 0; i < nt; ++i) by_cost[i] = i;
+    auto cost = [&](int t) { return double(int64_t(1) << d->models[d->model_of_traj[t]]->L) + kStepOverhead; };
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    using Load = std::pair<double, int>;  // (work so far, workgroup)
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int g = 0; g < G; ++g) heap.push({0.0, g});
+    std::vector<std::vector<int>> lists(G);
+    for (int t : by_cost) {
+        Load l = heap.top();
+        heap.pop();
+        lists[l.second].push_back(t);
+        l.first += cost(t);
+        heap.push(l);
+    }
+    ord->clear();
+    start->assign(G + 1, 0);
+    for (int g = 0; g < G; ++g) {
+        (*start)[g] = int(ord->size());
+        ord->insert(ord->end(), lists[g].begin(), lists[g].end());
+    }
+    (*start)[G] = int(ord->size());
+}
+
 static size_t traj_bytes(const ed_traj_desc* d, const ed_traj_params* p, int Lmax, int n_out, int G) {
     const size_t per = size_t(p->m_max + 2) << Lmax;
     return al256(size_t(G) * per * sizeof(double2)) + al256(size_t(d->n_models) * sizeof(TrajModel)) +
-           3 * al256(size_t(d->n_traj) * sizeof(int)) + al256(size_t(d->n_traj) * n_out * Lmax * sizeof(double)) +
+           3 * al256(size_t(d->n_traj) * sizeof(int)) + al256(size_t(G + 1) * sizeof(int)) +
+           al256(size_t(d->n_traj) * n_out * Lmax * sizeof(double)) +
            al256(size_t(d->n_traj) * std::max(p->max_jumps, 1) * (sizeof(double) + sizeof(int))) + al256(sizeof(int) * 4) +
            al256(size_t(d->n_traj) * sizeof(int));
 }
@@ -878,6 +918,7 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     double2* scratch = reinterpret_cast<double2*>(take(size_t(G) * per * sizeof(double2)));
     TrajModel* dmod = reinterpret_cast<TrajModel*>(take(size_t(d->n_models) * sizeof(TrajModel)));
     int* order = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
+    int* start = reinterpret_cast<int*>(take(size_t(G + 1) * sizeof(int)));
     int* model_of = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
     int* njumps = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
     double* sz = reinterpret_cast<double*>(take(size_t(nt) * n_out * Lmax * sizeof(double)));
@@ -897,12 +938,11 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
         hm[i].cls = st.heff[i]->op_class;
         for (int k = 0; k < hm[i].L; ++k) hm[i].rate[k] = d->rates[i][k];
     }
-    std::vector<int> ord(nt), mo(d->model_of_traj, d->model_of_traj + nt);
-    for (int i = 0; i < nt; ++i) ord[i] = i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-        return d->models[mo[a]]->L > d->models[mo[b]]->L;
-    });
+    std::vector<int> mo(d->model_of_traj, d->model_of_traj + nt);
+    std::vector<int> ord, wg_start;
+    deal_trajectories(d, G, &ord, &wg_start);
     ED_HIP_TRY(hipMemcpyAsync(dmod, hm.data(), sizeof(TrajModel) * hm.size(), hipMemcpyHostToDevice, s));
+    ED_HIP_TRY(hipMemcpyAsync(start, wg_start.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice, s));
     if (nt > 0) {
         ED_HIP_TRY(hipMemcpyAsync(order, ord.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
         ED_HIP_TRY(hipMemcpyAsync(model_of, mo.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
@@ -911,6 +951,7 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     std::memset(&a, 0, sizeof(a));
     a.models = dmod;
     a.order = order;
+    a.start = start;
     a.model_of = model_of;
     a.n_traj = nt;
     a.dt = d->dt;

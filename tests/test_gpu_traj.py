@@ -84,7 +84,7 @@ def test_trajectories_vs_oracle(plain, oracle_runs):
 
 
 CONFIG_LENGTHS = [8, 10, 12, 14, 16]
-LARGE_CASE = dict(n_traj=60, dt=0.01, steps=200, stride=10, seed=4, per_length=2)
+LARGE_CASE = dict(n_traj=60, dt=0.01, steps=150, stride=10, seed=4, per_length=2)
 
 
 def _ids_with_most_jumps(L, c):
@@ -113,7 +113,7 @@ def large_oracle_runs():
 def test_trajectories_vs_oracle_L14_L16(plain, large_oracle_runs):
     """Per-trajectory parity at the two longest chains of the batched workload, where a state
     spans several tiles of the trajectory kernel (4 at L = 14, 16 at L = 16): the config's mix of
-    lengths in one call (60 trajectories, Delta = 1, gamma = 0.1, dt = 0.01, T = 2), and for two
+    lengths in one call (60 trajectories, Delta = 1, gamma = 0.1, dt = 0.01, T = 1.5), and for two
     trajectories of each of L = 14 and 16 the jump count, times (1e-10), sites and per-site
     <sigma^z_k>(t) (1e-9) against the oracle on the same Philox streams."""
     c = LARGE_CASE
