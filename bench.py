@@ -95,6 +95,132 @@ def cpu_baseline(L=22, budget_s=10.0, max_reps=200):
                       f"headline; the L=28 product would need a ~190 GB CSR matrix"}
 
 
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max((i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"), default=None)
+    except ImportError:
+        return None
+
+
+def _oracle_traj_task(args):
+    """One worker of the trajectory oracle timing: n trajectories of one length, `steps` steps."""
+    L, ids, steps = args
+    try:  # one core per worker: the products are small, threads would only contend
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except ImportError:
+        pass
+    import edinputs as E
+    from oracle import hamiltonian as OH
+    from oracle import trajectories as OT
+    H = OH.hamiltonian_sparse(E.xxz(L, 1.0, 1.0))
+    jumps = OT.lowering_jumps(L, 0.1)
+    psi0 = E.product_state(L, E.neel_index(L))
+    t0 = time.perf_counter()
+    for tr in ids:
+        OT.trajectory(H, jumps, psi0, 0.01, steps, 10, 4, tr, m_max=20, tol=1e-10)
+    return L, len(ids) * steps, time.perf_counter() - t0
+
+
+def oracle_trajectories():
+    """Quantum trajectories of every chain length on the host, one worker process (one BLAS thread)
+    per length. Runs before the process touches the GPU, so the workers start from a process
+    without GPU state."""
+    import multiprocessing as mp
+    tasks = [(L, [2 * k, 2 * k + 1], 10) for k, L in enumerate((8, 10, 12, 14, 16))]
+    workers = max(1, min(16, os.cpu_count() or 1, len(tasks)))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_traj_task, tasks)
+    wall = time.perf_counter() - t0
+    return {"oracle_cores": workers, "oracle_wall_s": round(wall, 3),
+            "oracle_ms_per_trajectory_step": {f"L{L}": round(1e3 * sec / n, 2) for L, n, sec in res},
+            "sample": "2 trajectories per length, 10 steps of dt = 0.01, one process (one BLAS thread) per length"}
+
+
+def oracle_rows(P, E, torch, dev, traj_oracle=None):
+    """The oracle timed on the host beside the workloads it can finish in seconds, each next to the
+    GPU path at the same size: XXZ ground state (ARPACK on the explicit sparse H, the paper's
+    statics) and its half-chain entropy (SVD) at L = 18; the transverse-field Ising quench (textbook
+    Krylov steps on the sparse H) at L = 18; quantum trajectories of every chain length over a
+    process pool; the adjoint gradient from the dense eigendecomposition at L = 10 (5 slices)."""
+    import numpy as np
+    from oracle import adjoint as OA
+    from oracle import hamiltonian as OH
+    from oracle import krylov as OK
+    from oracle import lanczos as OL
+    from oracle import observables as OO
+    info = {"nproc": os.cpu_count(), "blas_threads": _blas_threads()}
+    out = {"host": info}
+    # ground state + entropy, L = 18
+    L = 18
+    desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
+    t0 = time.perf_counter()
+    H = OH.hamiltonian_sparse(desc)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e_or, psi_or = OL.ground_state_eigsh(H, tol=1e-14)
+    t_eigsh = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s_or = OO.bond_entropy(psi_or, L, L // 2)
+    t_svd = time.perf_counter() - t0
+    m = P.Model(desc)
+    v0 = E.random_state_device(L, 3, dev)
+    P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=24, n_keep=5, reorth="partial")
+    with Timer(torch, None) as tg:
+        e_g, psi_g, _ = P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=24, n_keep=5, reorth="partial")
+    with Timer(torch, None) as te:
+        s_g = P.entropy(psi_g, L, L // 2)
+    out["xxz_ground_entropy_L18"] = {
+        "oracle_build_s": round(t_build, 3), "oracle_eigsh_s": round(t_eigsh, 3), "oracle_svd_entropy_s": round(t_svd, 4),
+        "oracle_cores": "eigsh: 1 (sparse matvec) + BLAS", "gpu_lanczos_s": round(tg.s, 4), "gpu_entropy_s": round(te.s, 4),
+        "E0_rel_diff": abs(e_g - e_or) / abs(e_or), "S_rel_diff": abs(s_g - s_or) / abs(s_or)}
+    del m, v0, psi_g, H
+    # quench, L = 18, 10 steps
+    L, steps = 18, 10
+    desc = E.tfim(L, 0.5)
+    H = OH.hamiltonian_sparse(desc)
+    psi = E.product_state(L, 0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        psi, _m = OK.krylov_step(lambda v: H @ v, psi, 0.05, m_max=20, tol=1e-10)
+    t_or = (time.perf_counter() - t0) / steps
+    m = P.Model(desc)
+    g = torch.zeros(1 << L, dtype=torch.complex128, device=dev)
+    g[0] = 1.0
+    P.krylov_evolve(m, g.clone(), 0.05, 2, m_max=20, tol=1e-10)
+    with Timer(torch, None) as tq:
+        P.krylov_evolve(m, g, 0.05, steps, m_max=20, tol=1e-10)
+    out["tfim_quench_L18"] = {"steps": steps, "oracle_ms_per_step": round(1e3 * t_or, 2), "oracle_cores": 1,
+                              "gpu_ms_per_step": round(1e3 * tq.s / steps, 3),
+                              "final_state_overlap_err": float(1 - abs(np.vdot(psi, g.cpu().numpy())) /
+                                                               (np.linalg.norm(psi) * torch.linalg.vector_norm(g).item()))}
+    del m, g, H
+    if traj_oracle is not None:
+        out["trajectories"] = traj_oracle
+    # adjoint gradient, L = 10: the oracle's dense eigendecomposition gradient on the first 5 of the
+    # 50 slices (its cost is per slice), the GPU on the same 5 slices
+    L, S = 10, 5
+    tmpl = E.xxz_bond_scaled(L, 0.5, np.ones(L - 1))
+    J = E.adjoint_couplings(50, L - 1, 5)[:S]
+    psi0 = E.product_state(L, E.neel_index(L))
+    w = np.array([(-1) ** k for k in range(L)], np.float64) / L
+    t0 = time.perf_counter()
+    lo, go = OA.gradient_eig(tmpl, J, psi0, 0.1, w)
+    t_or = time.perf_counter() - t0
+    m = P.Model(tmpl)
+    p0 = torch.from_numpy(psi0).to(dev)
+    P.evolve_adjoint(m, J, p0, 0.1, w, substeps=2, quad_nodes=8)
+    with Timer(torch, None) as ta:
+        lg, gg = P.evolve_adjoint(m, J, p0, 0.1, w, substeps=2, quad_nodes=8)
+    out["adjoint_L10"] = {"slices": S, "n_params": int(S * (L - 1)), "oracle_s": round(t_or, 3),
+                          "oracle_s_per_slice": round(t_or / S, 3), "oracle_cores": info["blas_threads"],
+                          "gpu_s": round(ta.s, 4),
+                          "grad_max_abs_diff_over_max": float(np.max(np.abs(gg - go)) / np.max(np.abs(go)))}
+    return out
+
+
 class Timer:
     def __init__(self, torch, stream):
         self.torch, self.stream = torch, stream
@@ -199,7 +325,7 @@ _SHARED = {}
 
 
 def row_trotter_L28(P, E, torch, dev, steps=100):
-    """The L = 28 quench of the Krylov row with the Suzuki-Trotter propagators (Sec. II, Method 2):
+    """The L = 28 quench of the Krylov row with the Suzuki-Trotter propagators (Sec. ed:sec:trotter):
     orders 4 and 2, per-step time, the algorithmic bandwidth of the gate passes (each pass reads and
     writes the state once: 32 B per amplitude; 3 passes per layer at L = 28) and the largest
     difference of <sigma^z_k>(t) from the Krylov run when that row ran before."""
@@ -447,6 +573,14 @@ def main():
               f"not a measured path", file=sys.stderr)
         sys.exit(2)
 
+    traj_oracle = None
+    if not args.no_cpu_baseline and args.rows != "none":
+        log("bench: oracle trajectories (host, before the GPU is used)")
+        try:
+            traj_oracle = oracle_trajectories()
+        except Exception as e:  # reported, not hidden
+            traj_oracle = {"error": f"{type(e).__name__}: {e}"}
+
     import torch
     import edinputs as E
     import paper_1802_10052_amd as P
@@ -549,6 +683,12 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")
         rec["cpu_baseline"] = cpu_baseline()
+        if args.rows != "none":
+            log("bench: oracle rows")
+            try:
+                rec["oracle_rows"] = oracle_rows(P, E, torch, dev, traj_oracle)
+            except Exception as e:  # reported, not hidden
+                rec["oracle_rows"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(rec))
 
 

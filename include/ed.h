@@ -2,9 +2,9 @@
  * ed.h -- C ABI of the MI355X exact-diagonalisation hot path (libed.so).
  *
  * The library applies a local 1-D lattice Hamiltonian to a dense complex128 state without ever
- * storing H (the "rule set x psi" product of Sec. III.C, Eq. ed:eq:OKrylov), and builds on that
+ * storing H (the "rule set x psi" product of Sec. ed:sec:krylov, Eq. ed:eq:OKrylov), and builds on that
  * product: Lanczos ground states (Sec. II statics, computed matrix-free), Krylov time steps
- * (Sec. III.C), quantum trajectories (Sec. VI.A), a bond-coupling adjoint gradient and the
+ * (Sec. ed:sec:krylov), quantum trajectories (Sec. VI.A), a bond-coupling adjoint gradient and the
  * half-chain bond entropy (Sec. IV).
  *
  * Conventions shared by every call
@@ -145,7 +145,7 @@ ed_status ed_plan_cache_put(const char* key, const char* plan);
 ed_status ed_plan_cache_clear(void);
 
 /* ----------------------------------------------------------------------------------------
- * ed_apply_H: out = H psi (Sec. III.C, the rule set applied to the state without building H,
+ * ed_apply_H: out = H psi (Sec. ed:sec:krylov, the rule set applied to the state without building H,
  * Eq. ed:eq:OKrylov). psi and out are device arrays of D amplitudes that must not overlap.
  * Asynchronous on stream.
  * ---------------------------------------------------------------------------------------- */
@@ -161,7 +161,7 @@ ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void
 /* ----------------------------------------------------------------------------------------
  * ed_lanczos_ground: lowest eigenpair of a Hermitian model, matrix-free. The paper obtains the
  * ground state from the full H with eigh/eigsh (Sec. II, statics); here the same Lanczos
- * recurrence that underlies the Krylov step (Sec. III.C) runs on H psi directly:
+ * recurrence that underlies the Krylov step (Sec. ed:sec:krylov) runs on H psi directly:
  *   v_1 = v0/|v0|; w = H v_j; beta_j = |w| after orthogonalisation; T = V^H H V is the projected
  *   matrix. reorth selects how w is orthogonalised:
  *   ED_REORTH_FULL: against every stored v_i by classical Gram-Schmidt applied twice (past the
@@ -209,7 +209,7 @@ ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, const ed_la
 
 /* ----------------------------------------------------------------------------------------
  * ed_krylov_evolve: n_steps Krylov time steps psi(t+dt) = |psi| V_m exp(-i dt T_m) e_1
- * (Sec. III.C): a new Krylov basis of the current state every step, xi_i = [exp(-i dt T_m)]_{i,1}.
+ * (Sec. ed:sec:krylov): a new Krylov basis of the current state every step, xi_i = [exp(-i dt T_m)]_{i,1}.
  * hermitian = 1: Lanczos, T_m real symmetric tridiagonal (closed systems);
  * hermitian = 0: Arnoldi, T_m upper Hessenberg (non-Hermitian generators, Sec. VI.B).
  * Stopping (the paper names a tolerance and a maximal basis size): the a-posteriori estimate
@@ -252,7 +252,7 @@ ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double dt, int n_
                            void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
- * ed_trotter_evolve: n_steps Suzuki-Trotter time steps (Sec. II, Method 2). H = H_o + H_e,
+ * ed_trotter_evolve: n_steps Suzuki-Trotter time steps (Sec. ed:sec:trotter). H = H_o + H_e,
  * H_o = the bond terms (k, k+1) with k odd (1-based sites), H_e = those with k even; the site
  * terms of each site are shared by the bonds that contain it, weight 1/2 each, or 1 for a site
  * in a single bond (sites 1 and L of the open chain).
@@ -441,6 +441,8 @@ typedef struct {
     long long total_jumps;
     long long total_krylov;
     int blocks;
+    long long unconverged_steps;  /* Krylov steps that stopped at m_max with the error estimate above tol */
+    int graph_replayed;           /* 1 if the batched launch replayed the stream's executable graph */
 } ed_traj_info;
 
 ed_status ed_trajectories_workspace(const ed_traj_desc* desc, const ed_traj_params* params, size_t* bytes);
@@ -459,7 +461,7 @@ ed_status ed_philox_words(uint64_t seed, uint64_t id, uint64_t* out, int64_t cou
  * Evolution: psi_s = exp(-i H_s slice_len) psi_{s-1}, s = 1..n_slices, with
  *   H_s = sum_b J[s-1][b] h_b + (site terms of tmpl),  h_b = the bond operator of tmpl on bond b
  *   (sites b+1, b+2, b = 0..L-2, as folded from tmpl's bond rules);
- * each slice is propagated by `substeps` Krylov steps (Sec. III.C; Lanczos with local
+ * each slice is propagated by `substeps` Krylov steps (Sec. ed:sec:krylov; Lanczos with local
  * re-projection, m_fixed vectors if > 0, else adaptive with tol, at most m_max).
  * Loss = <psi_S|O|psi_S>, O = sum_k obs_w[k-1] sigma^z_k. The gradient is back-propagated:
  * lam_S = O psi_S, lam_{s-1} = exp(+i H_s slice_len) lam_s, and

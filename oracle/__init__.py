@@ -7,11 +7,11 @@ complex128 numpy + scipy, written from the paper's definitions:
 
   hamiltonian  H from Kronecker products of the rule sets (Sec. II, Eq. ed:eq:genericH, App. A)
   lanczos      ground state: eigsh as the paper does (Sec. II statics) and textbook Lanczos
-  krylov       Krylov time step (Sec. III.C) and the exact propagator (Sec. III.A)
+  krylov       Krylov time step (Sec. ed:sec:krylov) and the exact propagator (Sec. ed:sec:expm)
   observables  <sigma^z_k>, energy, norm (Sec. IV), bond entropy (Sec. IV, S(l))
   rdm          single-site and two-site reduced density matrices (Sec. IV), trace distance and
                the error measures of the convergence study (Sec. V)
-  trotter      Suzuki-Trotter layers of order 2 and 4 (Sec. II, Method 2)
+  trotter      Suzuki-Trotter layers of order 2 and 4 (Sec. ed:sec:trotter)
   philox       (none: the oracle draws with numpy's Philox4x64-10 bit generator)
   trajectories quantum trajectories (Sec. VI.A)
   liouville    Liouville-space superket evolution (Sec. VI.B, App. F, corrected form)

@@ -93,7 +93,7 @@ def hamiltonian_dense(desc):
 
 
 def apply_H(desc, psi, H=None):
-    """y = H psi with the explicit sparse H (Krylov mode 1 of Sec. III.C)."""
+    """y = H psi with the explicit sparse H (Krylov mode 1 of Sec. ed:sec:krylov)."""
     if H is None:
         H = hamiltonian_sparse(desc)
     return H @ psi

@@ -1,8 +1,8 @@
-"""Time evolution of a pure state (Sec. III).
+"""Time evolution of a pure state (Sec. ed:sec:dynamics).
 
-expm_step     method 1: psi(t+dt) = exp(-i H dt) psi(t) with the full propagator (Sec. III.A).
+expm_step     method 1: psi(t+dt) = exp(-i H dt) psi(t) with the full propagator (Sec. ed:sec:expm).
 krylov_step   method 3: psi(t+dt) ~ sum_i xi_i v_i with xi = |psi| [exp(-i dt T_m)]_{:,1} on the
-              Krylov basis of psi (Sec. III.C). Hermitian H: Lanczos with full
+              Krylov basis of psi (Sec. ed:sec:krylov). Hermitian H: Lanczos with full
               reorthogonalisation, T_m tridiagonal; non-Hermitian H: Arnoldi, upper Hessenberg
               T_m (Sec. VI.B, last paragraph).
 Stopping rule (the paper only names a tolerance): the a-posteriori estimate

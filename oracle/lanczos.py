@@ -1,4 +1,4 @@
-"""Ground state (Sec. II, statics; the Krylov basis of Sec. III.C).
+"""Ground state (Sec. II, statics; the Krylov basis of Sec. ed:sec:krylov).
 
 ground_state_eigsh follows the paper's statics (scipy.sparse.linalg.eigsh on the full sparse H,
 Sec. II). lanczos_ground is the textbook Lanczos recurrence with full reorthogonalisation

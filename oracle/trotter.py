@@ -1,4 +1,4 @@
-"""Suzuki-Trotter time evolution of a pure state (Sec. II, Method 2: Eqs. ed:eq:trotter1,
+"""Suzuki-Trotter time evolution of a pure state (Sec. ed:sec:trotter: Eqs. ed:eq:trotter1,
 ed:eq:trotter2, ed:eq:trotter4 and the constants of Eq. ed:eq:trotter4c).
 
 Test infrastructure: imported only by the tests, the smoke check and the CPU baseline of the

@@ -399,6 +399,18 @@ def eps_corr(rho2, rho2_ref):
     return float(trace_distances(rho2, rho2_ref).max())
 
 
+_TRAJ_STREAMS = {}
+
+
+def _traj_stream(dev):
+    """One stream per device for the batched trajectories, so that consecutive calls replay the
+    stream's executable graph."""
+    key = torch.device(dev)
+    if key not in _TRAJ_STREAMS:
+        _TRAJ_STREAMS[key] = torch.cuda.Stream(device=key)
+    return _TRAJ_STREAMS[key]
+
+
 def trajectories(models, jump_op, rates, psi0, model_of_traj, dt, n_steps, out_stride, seed,
                  m_max=20, tol=1e-10, max_jumps=64, plain=False, stream=None):
     """Quantum trajectories (ed_trajectories_batch, or ed_trajectories_plain with plain=True).
@@ -437,11 +449,12 @@ def trajectories(models, jump_op, rates, psi0, model_of_traj, dt, n_steps, out_s
     js = np.zeros((nt, mj), np.int32)
     o = _lib.TrajOut(sz.ctypes.data, nj.ctypes.data, jt.ctypes.data, js.ctypes.data)
     info = _lib.TrajInfo()
-    st = stream if stream is not None else torch.cuda.Stream(device=dev)
+    st = stream if stream is not None else _traj_stream(dev)
     st.wait_stream(torch.cuda.current_stream(dev))
     call(name, C.byref(d), C.byref(p), C.byref(o), C.byref(info), _dptr(ws), nb.value, _stream_ptr(st))
     return {"sz": sz, "n_jumps": nj, "jump_t": jt, "jump_site": js,
-            "info": {"total_jumps": info.total_jumps, "total_krylov": info.total_krylov, "blocks": info.blocks}}
+            "info": {"total_jumps": info.total_jumps, "total_krylov": info.total_krylov, "blocks": info.blocks,
+                     "unconverged_steps": info.unconverged_steps, "graph_replayed": bool(info.graph_replayed)}}
 
 
 def philox_words(seed, ident, count, device="cuda:0", stream=None):
@@ -493,16 +506,22 @@ def evolve_loss(template, J, psi0, slice_len, obs_w, substeps=2, m_max=30, m_fix
 
 class AdjointEvolve(torch.autograd.Function):
     """Loss(J) = <psi_S|O|psi_S> as a differentiable function of the couplings J [S, L-1]
-    (float64 CPU tensor); backward returns grad_out * dLoss/dJ from ed_evolve_adjoint."""
+    (float64 CPU tensor). forward runs the forward propagation only (ed_evolve_loss); backward runs
+    ed_evolve_adjoint (forward with slice-boundary checkpoints, then the costate sweep) and returns
+    grad_out * dLoss/dJ, so a caller that needs only the loss never pays for the gradient."""
 
     @staticmethod
     def forward(ctx, J, template, psi0, slice_len, obs_w, substeps=2, quad_nodes=8, m_max=30, m_fixed=0, tol=1e-13):
-        loss, grad = evolve_adjoint(template, J.detach().cpu().numpy(), psi0, slice_len, obs_w, substeps,
-                                    quad_nodes, m_max, m_fixed, tol)
-        ctx.save_for_backward(torch.from_numpy(grad))
+        Jn = J.detach().cpu().numpy()
+        loss = evolve_loss(template, Jn, psi0, slice_len, obs_w, substeps, m_max, m_fixed, tol)
+        ctx.save_for_backward(J.detach().cpu())
+        ctx.args = (template, psi0, slice_len, obs_w, substeps, quad_nodes, m_max, m_fixed, tol)
         return torch.tensor(loss, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, grad_out):
-        (g,) = ctx.saved_tensors
-        return (grad_out * g, None, None, None, None, None, None, None, None, None)
+        (J,) = ctx.saved_tensors
+        template, psi0, slice_len, obs_w, substeps, quad_nodes, m_max, m_fixed, tol = ctx.args
+        _, grad = evolve_adjoint(template, J.numpy(), psi0, slice_len, obs_w, substeps, quad_nodes, m_max, m_fixed,
+                                 tol)
+        return (grad_out * torch.from_numpy(grad), None, None, None, None, None, None, None, None, None)

@@ -67,7 +67,8 @@ class TrajOut(C.Structure):
 
 
 class TrajInfo(C.Structure):
-    _fields_ = [("total_jumps", C.c_longlong), ("total_krylov", C.c_longlong), ("blocks", C.c_int)]
+    _fields_ = [("total_jumps", C.c_longlong), ("total_krylov", C.c_longlong), ("blocks", C.c_int),
+                ("unconverged_steps", C.c_longlong), ("graph_replayed", C.c_int)]
 
 
 class AdjointParams(C.Structure):

@@ -1,5 +1,5 @@
 // Gradient of a final-time observable with respect to piecewise-constant bond couplings, by
-// costate (adjoint) back-propagation through the Krylov time evolution of Sec. III.C.
+// costate (adjoint) back-propagation through the Krylov time evolution of Sec. ed:sec:krylov.
 //
 //   H_s = sum_b J[s][b] h_b + H_site    (h_b: the template's bond operator on bond b)
 //   psi_s = exp(-i H_s Delta) psi_{s-1},  Loss = <psi_S|O|psi_S>,  O = sum_k w_k sigma^z_k

@@ -1,4 +1,4 @@
-// out = H psi for a site + bond rule set on a dense complex128 state (Sec. III.C: the rule set
+// out = H psi for a site + bond rule set on a dense complex128 state (Sec. ed:sec:krylov: the rule set
 // applied to the state without storing H, cost L(2 n_b + n_s) O(d^(L+1)), Eq. ed:eq:OKrylov).
 //
 // The paper contracts each rule with the rank-L tensor (tensordot + permutation per rule and

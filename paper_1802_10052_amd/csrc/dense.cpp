@@ -1,6 +1,6 @@
 // Small dense solvers for the m x m projected matrices of the Krylov methods (m <= a few
 // hundred): eigenpairs of real symmetric / tridiagonal matrices and the complex matrix
-// exponential. These are the "exponential transformed to the Krylov basis" of Sec. III.C; they
+// exponential. These are the "exponential transformed to the Krylov basis" of Sec. ed:sec:krylov; they
 // run on the host because m is tiny next to D. The tridiagonal eigensolver also has an x87
 // extended-precision instance: the Krylov time step and the adjoint's bases form
 // exp(-i tau T) e_1 with it, so that the coefficients carry FP64 rounding only (not the

@@ -1,4 +1,4 @@
-// Device-side bodies of out = H psi (Sec. III.C, Eq. ed:eq:OKrylov), shared by the streaming
+// Device-side bodies of out = H psi (Sec. ed:sec:krylov, Eq. ed:eq:OKrylov), shared by the streaming
 // kernels (one tile per workgroup) and by the trajectory kernel (one workgroup walks every tile of
 // its own small state).
 #pragma once

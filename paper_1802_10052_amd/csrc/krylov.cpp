@@ -1,4 +1,4 @@
-// Krylov machinery on top of H psi (Sec. III.C): the basis recurrence shared by the Lanczos
+// Krylov machinery on top of H psi (Sec. ed:sec:krylov): the basis recurrence shared by the Lanczos
 // ground state and the Krylov time step, the thick-restart ground-state driver, the time
 // evolution driver with per-step observables, and the one-pass measurement.
 #include <algorithm>
@@ -35,13 +35,24 @@ ed_status carve(void* ws, size_t ws_bytes, int64_t D, int nvec, Workspace* w) {
     return ED_OK;
 }
 
-// Pinned host staging buffer for the per-iteration scalars (allocated once per thread).
-double2* host_stage() {
-    static thread_local double2* buf = nullptr;
-    if (!buf) {
-        if (hipHostMalloc(reinterpret_cast<void**>(&buf), sizeof(double2) * kScalars) != hipSuccess) buf = nullptr;
+// Pinned host staging buffer for the per-iteration scalars: allocated on a thread's first use and
+// freed when that thread ends (thread-local objects of the main thread are destroyed before the
+// runtime's static state).
+namespace {
+struct HostStage {
+    double2* buf = nullptr;
+    ~HostStage() {
+        if (buf) (void)hipHostFree(buf);
     }
-    return buf;
+};
+}  // namespace
+
+double2* host_stage() {
+    static thread_local HostStage st;
+    if (!st.buf) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&st.buf), sizeof(double2) * kScalars) != hipSuccess) st.buf = nullptr;
+    }
+    return st.buf;
 }
 
 ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s) {

@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <queue>
 #include <utility>
 #include <vector>
@@ -111,6 +113,7 @@ struct TrajArgs {
     double* jump_t;
     int* jump_site;
     int* m_total;
+    int* unconverged;    // per trajectory: Krylov steps that stopped at m_max with the error above tol
     double2* scratch;
     int64_t scratch_stride;
     int* counter;
@@ -476,7 +479,7 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
         wg_scale(psi, N, 1.0 / sqrt(n2));
     }
     double r = draw();
-    int njump = 0, mtot = 0;
+    int njump = 0, mtot = 0, nunconv = 0;
     double* szo = a.sz_out + int64_t(tr) * a.n_out * a.Lmax;
     auto record = [&](int slot) {
         wg_pops(psi, L, sh);
@@ -508,6 +511,7 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
             __syncthreads();
             int m = 0;
             double beta = 0.0;
+            bool unconv = false;
             for (int j = 0; j < a.m_max; ++j) {
                 double2* Vj = V + j * ldv;
                 double2* Wn = V + (j + 1) * ldv;
@@ -537,7 +541,10 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
                 const bool brk = beta <= 1e-14 * fmax(hs, 1e-300) || beta == 0.0;
                 wg_expv(m, tau_left, sh);
                 const double err = brk ? 0.0 : nrm * beta * sqrt(sh.u[m - 1].x * sh.u[m - 1].x + sh.u[m - 1].y * sh.u[m - 1].y);
-                if (brk || err <= a.tol || m >= a.m_max) break;
+                if (brk || err <= a.tol || m >= a.m_max) {
+                    unconv = !brk && err > a.tol;
+                    break;
+                }
                 // u_{j+1} = w'' unnormalised, v_{j+1} = w'' / beta
                 if (t == 0) {
                     sh.H[(j + 1) * LD + j] = make_double2(beta, 0.0);
@@ -546,6 +553,7 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
                 __syncthreads();
             }
             mtot += m;
+            nunconv += unconv ? 1 : 0;
             // sh.u = exp(-i tau_left H_m) e_1
             const double lr = log(r);
             const double f_end = log(n2 * unorm2(m, sh)) - lr;
@@ -649,6 +657,7 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
     if (t == 0) {
         a.n_jumps[tr] = failed ? -1 : njump;
         a.m_total[tr] = mtot;
+        a.unconverged[tr] = nunconv;
     }
     __syncthreads();
 }
@@ -839,6 +848,11 @@ static int persistent_blocks(int n_traj, int Lmax, int m_max, int variant) {
     return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(n_traj), int64_t(per_cu) * cu, by_mem})));
 }
 
+// Executable graph of the batched launch, one per (device, stream); kept until the process ends
+// (a stream's graph is reused by the next call on that stream).
+static std::mutex g_traj_graph_mu;
+static std::map<std::pair<int, hipStream_t>, hipGraphExec_t> g_traj_graph;
+
 // Longest-processing-time deal of the trajectories over G workgroups: heaviest first, each to the
 // workgroup with the least work so far (ties to the lower index). A trajectory's work is taken as
 // 2^L + kStepOverhead amplitude-equivalents per step (its products and sweeps stream the state; a
@@ -877,7 +891,7 @@ static size_t traj_bytes(const ed_traj_desc* d, const ed_traj_params* p, int Lma
            3 * al256(size_t(d->n_traj) * sizeof(int)) + al256(size_t(G + 1) * sizeof(int)) +
            al256(size_t(d->n_traj) * n_out * Lmax * sizeof(double)) +
            al256(size_t(d->n_traj) * std::max(p->max_jumps, 1) * (sizeof(double) + sizeof(int))) + al256(sizeof(int) * 4) +
-           al256(size_t(d->n_traj) * sizeof(int));
+           2 * al256(size_t(d->n_traj) * sizeof(int));
 }
 
 }  // namespace ed
@@ -928,6 +942,7 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     int* js = reinterpret_cast<int*>(jbuf + size_t(nt) * mj * sizeof(double));
     int* counter = reinterpret_cast<int*>(take(sizeof(int) * 4));
     int* mtot = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
+    int* unconv = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
     // host-side descriptors
     std::vector<TrajModel> hm(d->n_models);
     for (int i = 0; i < d->n_models; ++i) {
@@ -971,11 +986,14 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     a.jump_t = jt;
     a.jump_site = js;
     a.m_total = mtot;
+    a.unconverged = unconv;
     a.scratch = scratch;
     a.scratch_stride = int64_t(per);
     a.counter = counter;
-    // clear the queue counter and the outputs with fill kernels, then the persistent launch;
-    // on a non-null stream the three launches are captured and replayed as one hipGraph
+    // clear the counters and the outputs with fill kernels, then the persistent launch; on a
+    // non-null stream the three launches are captured as a hipGraph and run through the stream's
+    // executable graph, which a later call updates in place (new arguments, same topology) and
+    // replays instead of instantiating again
     auto enqueue = [&]() -> hipError_t {
         hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 4);
         if (nt == 0) return hipGetLastError();
@@ -989,7 +1007,6 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
         ED_HIP_TRY(hipStreamSynchronize(s));
     } else {
         hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
         ED_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipError_t e = enqueue();
         hipError_t ce = hipStreamEndCapture(s, &graph);
@@ -997,25 +1014,44 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
             if (graph) (void)hipGraphDestroy(graph);
             return fail(ED_ERR_HIP, std::string("trajectory capture: ") + hipGetErrorString(e != hipSuccess ? e : ce));
         }
-        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (ie != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return fail(ED_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        std::lock_guard<std::mutex> lock(g_traj_graph_mu);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        hipGraphExec_t& exec = g_traj_graph[{dev, s}];
+        bool updated = false;
+        if (exec) {
+            hipGraphNode_t err_node = nullptr;
+            hipGraphExecUpdateResult ur = hipGraphExecUpdateError;
+            updated = hipGraphExecUpdate(exec, graph, &err_node, &ur) == hipSuccess && ur == hipGraphExecUpdateSuccess;
+            if (!updated) {
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(exec);
+                exec = nullptr;
+            }
         }
+        if (!exec) {
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                exec = nullptr;
+                (void)hipGraphDestroy(graph);
+                return fail(ED_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+            }
+        }
+        (void)hipGraphDestroy(graph);
         hipError_t le = hipGraphLaunch(exec, s);
         hipError_t se = hipStreamSynchronize(s);
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
         if (le != hipSuccess) return fail(ED_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(le));
         if (se != hipSuccess) return fail(ED_ERR_HIP, std::string("trajectory kernel: ") + hipGetErrorString(se));
+        if (info) info->graph_replayed = updated ? 1 : 0;
     }
     // outputs to the host
     std::vector<double> hsz(size_t(nt) * n_out * Lmax);
-    std::vector<int> hnj(nt), hmt(nt);
+    std::vector<int> hnj(nt), hmt(nt), hun(nt);
     if (nt > 0) {
         ED_HIP_TRY(hipMemcpy(hsz.data(), sz, sizeof(double) * hsz.size(), hipMemcpyDeviceToHost));
         ED_HIP_TRY(hipMemcpy(hnj.data(), njumps, sizeof(int) * nt, hipMemcpyDeviceToHost));
         ED_HIP_TRY(hipMemcpy(hmt.data(), mtot, sizeof(int) * nt, hipMemcpyDeviceToHost));
+        ED_HIP_TRY(hipMemcpy(hun.data(), unconv, sizeof(int) * nt, hipMemcpyDeviceToHost));
     }
     std::memcpy(out->sz, hsz.data(), sizeof(double) * hsz.size());
     if (out->n_jumps) std::memcpy(out->n_jumps, hnj.data(), sizeof(int) * nt);
@@ -1030,14 +1066,17 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     for (int i = 0; i < nt; ++i)
         if (hnj[i] < 0) return fail(ED_ERR_NUMERIC, "trajectory " + std::to_string(i) + " hit a non-finite norm or too many jumps in one step");
     if (info) {
-        long long tj = 0, tm = 0;
+        long long tj = 0, tm = 0, tu = 0;
         for (int i = 0; i < nt; ++i) {
             tj += hnj[i];
             tm += hmt[i];
+            tu += hun[i];
         }
         info->total_jumps = tj;
         info->total_krylov = tm;
         info->blocks = G;
+        info->unconverged_steps = tu;
+        if (s == nullptr) info->graph_replayed = 0;
     }
     return ED_OK;
 }
@@ -1084,7 +1123,7 @@ extern "C" ed_status ed_trajectories_plain(const ed_traj_desc* d, const ed_traj_
     const int Lmax = st.Lmax, n_out = st.n_out, nt = d->n_traj;
     const int mj = std::max(p->max_jumps, 1);
     std::fill(out->sz, out->sz + size_t(nt) * n_out * Lmax, 0.0);
-    long long tot_j = 0, tot_m = 0;
+    long long tot_j = 0, tot_m = 0, tot_unconv = 0;
     for (int tr = 0; tr < nt; ++tr) {
         const int mi = d->model_of_traj[tr];
         const ed_model* hm = st.heff[mi];
@@ -1137,7 +1176,10 @@ extern "C" ed_status ed_trajectories_plain(const ed_traj_desc* d, const ed_traj_
                     m = j + 1;
                     expv(m, tau_left, u);
                     const double err = brk ? 0.0 : nrm * beta * std::abs(u[m - 1]);
-                    if (brk || err <= p->tol || m >= mmax) break;
+                    if (brk || err <= p->tol || m >= mmax) {
+                        if (!brk && err > p->tol) ++tot_unconv;
+                        break;
+                    }
                     T[size_t(j + 1) * (mmax + 1) + j] = beta;
                 }
                 tot_m += m;
@@ -1236,6 +1278,8 @@ extern "C" ed_status ed_trajectories_plain(const ed_traj_desc* d, const ed_traj_
         info->total_jumps = tot_j;
         info->total_krylov = tot_m;
         info->blocks = 1;
+        info->unconverged_steps = tot_unconv;
+        info->graph_replayed = 0;
     }
     return ED_OK;
 }

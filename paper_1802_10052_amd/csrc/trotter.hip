@@ -1,4 +1,4 @@
-// Suzuki-Trotter time evolution (Sec. II, Method 2: Eqs. ed:eq:trotter1, ed:eq:trotter2,
+// Suzuki-Trotter time evolution (Sec. ed:sec:trotter: Eqs. ed:eq:trotter1, ed:eq:trotter2,
 // ed:eq:trotter4, constants Eq. ed:eq:trotter4c).
 //
 // H = H_o + H_e with H_o the bond terms (k, k+1) for odd k (1-based sites) and H_e those for even

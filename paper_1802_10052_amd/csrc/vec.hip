@@ -1,4 +1,4 @@
-// Vector kernels of the Krylov methods (Sec. III.C and Sec. II statics, computed matrix-free):
+// Vector kernels of the Krylov methods (Sec. ed:sec:krylov and Sec. II statics, computed matrix-free):
 // deterministic dot products against several basis vectors at once, the matching multi-axpy,
 // norm + scaling, the Krylov combination psi = sum_i c_i v_i, and the all-site <sigma^z>
 // reduction of Sec. IV. Every reduction uses a fixed grid, a fixed per-thread assignment and a

@@ -1,4 +1,4 @@
-"""GPU parity of ed_apply_H against the oracle's explicit sparse H (Sec. III.C, Eq. ed:eq:OKrylov).
+"""GPU parity of ed_apply_H against the oracle's explicit sparse H (Sec. ed:sec:krylov, Eq. ed:eq:OKrylov).
 
 Relative 2-norm error <= 1e-13: both sides sum at most 3L+1 products per entry in float64, so
 the rounding difference is a few ulp of the largest term."""

@@ -1,4 +1,4 @@
-"""GPU parity of ed_trotter_evolve (Sec. II, Method 2; Eqs. ed:eq:trotter2, ed:eq:trotter4,
+"""GPU parity of ed_trotter_evolve (Sec. ed:sec:trotter; Eqs. ed:eq:trotter2, ed:eq:trotter4,
 ed:eq:trotter4c) against the oracle's layer-by-layer contraction, and exact large-L pins.
 
 Tolerance: both sides apply the same 4x4 propagators, formed by two different exponential

@@ -68,7 +68,7 @@ def test_liouville_reduces_to_pure_state_at_zero_rate():
 
 def test_trajectory_ensemble_vs_liouville():
     """Ensemble mean of <sigma^z_k>(t) over trajectories agrees with the exact Lindblad
-    solution within 4 standard errors (law of large numbers, Sec. VI.C)."""
+    solution within 4 standard errors (law of large numbers, Sec. ed:sec:opencavities)."""
     L, gamma, dt, steps, stride, N = 4, 0.1, 0.05, 40, 10, 160
     H, jumps = _xxz_open(L, gamma)
     psi0 = E.product_state(L, E.neel_index(L))

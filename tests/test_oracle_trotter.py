@@ -1,4 +1,4 @@
-"""Pins of the Trotter oracle (Sec. II, Method 2; Eqs. ed:eq:trotter2, ed:eq:trotter4,
+"""Pins of the Trotter oracle (Sec. ed:sec:trotter; Eqs. ed:eq:trotter2, ed:eq:trotter4,
 ed:eq:trotter4c) against facts that do not come from its own code: exactness when all terms
 commute, exactness for a single bond, the dense layer products at L = 3 built from the
 independently pinned Kronecker Hamiltonian, the convergence orders 2 and 4 against the exact
