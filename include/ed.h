@@ -452,6 +452,11 @@ ed_status ed_trajectories_plain_workspace(const ed_traj_desc* desc, const ed_tra
 ed_status ed_trajectories_plain(const ed_traj_desc* desc, const ed_traj_params* params, const ed_traj_out* out,
                                 ed_traj_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ed_stream_copy: dst[i] = src[i] for n amplitudes (device arrays, not overlapping), one amplitude
+ * per thread with streaming stores: a plain device copy that measures the practical HBM streaming
+ * rate against which the benchmarks' kernels are compared. Asynchronous on stream. */
+ed_status ed_stream_copy(const ed_c64* src, ed_c64* dst, int64_t n, void* stream);
+
 /* Raw 64-bit words n = 0..count-1 of the trajectory random stream of key (seed, id), written to
  * device memory out (for checking the generator against its published definition). Async. */
 ed_status ed_philox_words(uint64_t seed, uint64_t id, uint64_t* out, int64_t count, void* stream);

@@ -308,6 +308,13 @@ def measure(psi, L, stream=None):
     return sz, nrm.value
 
 
+def stream_copy(src, dst, stream=None):
+    """dst = src for two device complex128 tensors of equal size (ed_stream_copy)."""
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in size")
+    call("ed_stream_copy", _dptr(src), _dptr(dst), int(src.numel()), _stream_ptr(stream))
+
+
 def measure_noalloc(psi, L, stream=None):
     """(sz[L], norm) of a device state (ed_measure_noalloc: no workspace, nothing allocated)."""
     _check_state(psi, 1 << L)

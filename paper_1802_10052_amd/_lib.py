@@ -154,6 +154,7 @@ def _declare(l):
     _fn(l, "ed_entropy", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, P, C.c_size_t, P])
     _fn(l, "ed_measure", [P, C.c_int, P, P, P, C.c_size_t, P])
     _fn(l, "ed_measure_noalloc", [P, C.c_int, P, P, P])
+    _fn(l, "ed_stream_copy", [P, P, C.c_int64, P])
     _fn(l, "ed_model_plan_key", [P, C.c_char_p, C.c_int])
     _fn(l, "ed_plan_cache_load", [C.c_char_p, C.POINTER(C.c_int)])
     _fn(l, "ed_plan_cache_save", [C.c_char_p])

@@ -408,6 +408,19 @@ __global__ __launch_bounds__(kThreads) void combine_multi_kernel(MultiPtrs P, in
     }
 }
 
+// dst[x] = src[x], one amplitude per thread, with streaming (non-temporal) stores: the plain device
+// copy that sets the box's practical HBM streaming rate for the calibration of the benchmarks.
+__global__ __launch_bounds__(kThreads) void stream_copy_kernel(const double2* __restrict__ src,
+                                                               double2* __restrict__ dst, int64_t n) {
+    const int64_t x = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (x < n) {
+        const double2 v = src[x];
+        double* o = reinterpret_cast<double*>(dst + x);
+        __builtin_nontemporal_store(v.x, o);
+        __builtin_nontemporal_store(v.y, o + 1);
+    }
+}
+
 inline int grid_for(int64_t D) {
     int64_t g = D / (kThreads * 4);
     if (g < 1) g = 1;
@@ -609,3 +622,15 @@ hipError_t combination_ptr(const double2* const* U, int n, const double2* c, dou
 }
 
 }  // namespace ed
+
+extern "C" ed_status ed_stream_copy(const ed_c64* src, ed_c64* dst, int64_t n, void* stream) {
+    if (!src || !dst || n < 0) return ed::fail(ED_ERR_ARG, "bad argument (null pointer or n < 0)");
+    if (n == 0) return ED_OK;
+    const int64_t blocks = (n + ed::kThreads - 1) / ed::kThreads;
+    if (blocks > int64_t(0x7fffffff)) return ed::fail(ED_ERR_ARG, "n too large for one launch");
+    hipLaunchKernelGGL(ed::stream_copy_kernel, dim3(unsigned(blocks)), dim3(ed::kThreads), 0,
+                       static_cast<hipStream_t>(stream), reinterpret_cast<const double2*>(src),
+                       reinterpret_cast<double2*>(dst), n);
+    ED_HIP_TRY(hipGetLastError());
+    return ED_OK;
+}
