@@ -301,7 +301,8 @@ ed_status ed_measure_noalloc(const ed_c64* psi, int L, double* sz, double* norm,
  * bipartition sites 1..l | l+1..L (Sec. IV, bond entropy). Lambda_j are the eigenvalues of
  * rho_l = M M^dagger / <psi|psi>, M = psi reshaped to 2^l x 2^(L-l) row-major (no copy is made).
  * The Gram matrix of the smaller side is formed on the FP64 matrix cores, reduced to
- * tridiagonal form by Householder steps on the GPU, and its eigenvalues are taken on the host.
+ * tridiagonal form by Householder steps on the GPU, and its eigenvalues are found by bisection
+ * on Sturm counts on the GPU (absolute accuracy a few eps |rho|).
  * psi       device, D amplitudes (any nonzero norm)
  * S         host; spectrum host (may be NULL): min(2^l, 2^(L-l)) eigenvalues, descending.
  * Limits: 0 <= l_cut <= L, min(l_cut, L - l_cut) <= 14. Synchronises stream.

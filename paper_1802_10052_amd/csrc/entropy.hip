@@ -11,13 +11,14 @@
 //      GPU: each step's rank-2 update of the trailing matrix is fused with the matrix-vector
 //      product that the next step needs, on the lower triangle only (the product takes the upper
 //      part as the conjugate of the lower), so half the trailing matrix streams once per step.
-//   3. Eigenvalues of the tridiagonal matrix by implicit QL on the host (O(n^2)).
+//   3. Eigenvalues of the tridiagonal matrix by bisection on Sturm counts on the GPU, one thread
+//      per eigenvalue.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <utility>
 #include <vector>
 
-#include "dense.h"
 #include "ed_internal.h"
 
 namespace ed {
@@ -391,6 +392,91 @@ __global__ __launch_bounds__(256) void hh_gemv(const double2* __restrict__ A, in
     }
 }
 
+// ------------------------------------------------------------------------------ tridiagonal eigenvalues
+// Every eigenvalue of the real symmetric tridiagonal T (diagonal d, off-diagonal e >= 0) by
+// bisection on Sturm counts: the pivots of the LDL^T factorisation of T - x I have as many
+// negative entries as T has eigenvalues below x (Sylvester's law of inertia), and the pivots
+// obey q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1}. A pivot smaller in magnitude than
+// pivmin is replaced by -pivmin (a perturbation of T of at most pivmin per entry), so no pivot
+// is zero. Thread k finds the k-th smallest eigenvalue on its own, from the Gershgorin interval
+// down to a width of eps |T|: its result depends on d, e and k only, not on the launch shape.
+constexpr int kBisThreads = 256;
+constexpr int kBndThreads = 1024;
+
+// One workgroup: e2[i] = e[i]^2 (i < n-1); bnd = {lower, upper bound of the spectrum, pivmin,
+// absolute tolerance}.
+__global__ __launch_bounds__(kBndThreads) void tri_bounds(const double* __restrict__ d, const double* __restrict__ e,
+                                                          int n, double* __restrict__ e2, double* __restrict__ bnd) {
+    __shared__ double rlo[kBndThreads / 64], rhi[kBndThreads / 64], rem[kBndThreads / 64];
+    const int t = threadIdx.x;
+    double lo = HUGE_VAL, hi = -HUGE_VAL, em = 0.0;
+    for (int i = t; i < n; i += kBndThreads) {
+        const double el = i > 0 ? e[i - 1] : 0.0, er = i + 1 < n ? e[i] : 0.0;
+        lo = fmin(lo, d[i] - el - er);
+        hi = fmax(hi, d[i] + el + er);
+        if (i + 1 < n) {
+            e2[i] = er * er;
+            em = fmax(em, er * er);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_down(lo, off, 64));
+        hi = fmax(hi, __shfl_down(hi, off, 64));
+        em = fmax(em, __shfl_down(em, off, 64));
+    }
+    if ((t & 63) == 0) {
+        rlo[t >> 6] = lo;
+        rhi[t >> 6] = hi;
+        rem[t >> 6] = em;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < kBndThreads / 64; ++w) {
+            lo = fmin(lo, rlo[w]);
+            hi = fmax(hi, rhi[w]);
+            em = fmax(em, rem[w]);
+        }
+        const double tnorm = fmax(fabs(lo), fabs(hi));
+        const double pivmin = DBL_MIN * fmax(1.0, em);
+        // widen by the rounding of the counts themselves, so that count(lower) = 0 and
+        // count(upper) = n hold in floating point
+        const double pad = 2.1 * DBL_EPSILON * tnorm * n + 4.2 * pivmin;
+        bnd[0] = lo - pad;
+        bnd[1] = hi + pad;
+        bnd[2] = pivmin;
+        bnd[3] = DBL_EPSILON * fmax(tnorm, DBL_MIN);
+    }
+}
+
+__device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n, double x,
+                                           double pivmin) {
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+        q = (d[i] - x) - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+// lam[k] = the k-th smallest eigenvalue, k < n. Invariant: count(lo) <= k < count(hi).
+__global__ __launch_bounds__(kBisThreads) void tri_bisect(const double* __restrict__ d, const double* __restrict__ e2,
+                                                          int n, const double* __restrict__ bnd, double* __restrict__ lam) {
+    const int k = int(blockIdx.x) * kBisThreads + int(threadIdx.x);
+    if (k >= n) return;
+    double lo = bnd[0], hi = bnd[1];
+    const double pivmin = bnd[2], tol = bnd[3];
+    for (int it = 0; it < 2100 && hi - lo > tol; ++it) {
+        const double mid = lo + 0.5 * (hi - lo);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(d, e2, n, mid, pivmin) <= k) lo = mid;
+        else hi = mid;
+    }
+    lam[k] = lo + 0.5 * (hi - lo);
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct EntWS {
@@ -519,18 +605,27 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
             ED_HIP_TRY(hipGetLastError());
         }
     }
-    // 3. tridiagonal eigenvalues on the host
-    std::vector<double> dd(n), ee(n, 0.0);
-    ED_HIP_TRY(hipMemcpyAsync(dd.data(), w.d, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    if (n > 1) ED_HIP_TRY(hipMemcpyAsync(ee.data(), w.e, sizeof(double) * (n - 1), hipMemcpyDeviceToHost, s));
-    ED_HIP_TRY(hipStreamSynchronize(s));
+    // 3. eigenvalues of the tridiagonal matrix by bisection on the GPU (the partial-sum area is
+    // free now: n eigenvalues, n squared off-diagonals, 4 bounds), sorted on the host
+    std::vector<double> dd(n);
     if (n == 1) {
         // rho is the 1x1 matrix |psi|^2
         double2 r11;
-        ED_HIP_TRY(hipMemcpy(&r11, w.rho, sizeof(double2), hipMemcpyDeviceToHost));
+        ED_HIP_TRY(hipMemcpyAsync(&r11, w.rho, sizeof(double2), hipMemcpyDeviceToHost, s));
+        ED_HIP_TRY(hipStreamSynchronize(s));
         dd[0] = r11.x;
+    } else {
+        double* lam = reinterpret_cast<double*>(w.part);
+        double* e2 = lam + n;
+        double* bnd = e2 + n;
+        hipLaunchKernelGGL(tri_bounds, dim3(1), dim3(kBndThreads), 0, s, w.d, w.e, n, e2, bnd);
+        hipLaunchKernelGGL(tri_bisect, dim3((n + kBisThreads - 1) / kBisThreads), dim3(kBisThreads), 0, s, w.d, e2, n,
+                           bnd, lam);
+        ED_HIP_TRY(hipGetLastError());
+        ED_HIP_TRY(hipMemcpyAsync(dd.data(), lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        ED_HIP_TRY(hipStreamSynchronize(s));
+        std::sort(dd.begin(), dd.end());
     }
-    if (!tridiag_ql(n, dd.data(), ee.data(), nullptr)) return fail(ED_ERR_NUMERIC, "tridiagonal QL did not converge");
     double tr = 0.0;
     for (int i = 0; i < n; ++i) tr += dd[i];
     if (!(tr > 0.0) || !std::isfinite(tr)) return fail(ED_ERR_NUMERIC, "state has zero or non-finite norm");
