@@ -11,7 +11,7 @@
 //      GPU: each step's rank-2 update of the trailing matrix is fused with the matrix-vector
 //      product that the next step needs, on the lower triangle only (the product takes the upper
 //      part as the conjugate of the lower), so half the trailing matrix streams once per step.
-//   3. Eigenvalues of the tridiagonal matrix by bisection on Sturm counts on the GPU, one thread
+//   3. Eigenvalues of the tridiagonal matrix by multisection on Sturm counts on the GPU, 16 lanes
 //      per eigenvalue.
 #include <algorithm>
 #include <cfloat>
@@ -121,80 +121,154 @@ __global__ __launch_bounds__(256) void gram_mfma(const double2* __restrict__ psi
 }
 
 // ------------------------------------------------------------------------------ Householder
-// State of the reduction kept in device memory:
-//   v[n]   current Householder vector (v[0] = 1) of the step, indexed from row k+1
-//   y[n]   tau * A22 v, then w = y + alpha v
-//   d[n], e[n]  tridiagonal diagonal / |sub-diagonal|
-//   part[nblk][n] partial row sums of the fused update
-//   sc[4]  tau (complex) at sc[0]
-constexpr int kFR = 16;    // rows per workgroup tile of the fused update
-constexpr int kFC = 512;   // columns per workgroup tile
+// Reduction of the Hermitian rho to a real symmetric tridiagonal matrix by n - 2 Householder
+// steps. Step k takes the reflector I - tau v v^H (v_{k+1} = 1) that zeroes column k below row
+// k + 1, forms y = tau A v, w = y - 1/2 tau (y^H v) v, and the rank-2 update
+// A <- A - v w^H - w v^H of the trailing block (rows and columns > k).
+//
+// The updates are applied lazily, as in the blocked form of the reduction: the last np <= kPanel
+// pairs (v_j, w_j) stay in a panel P (column j holds v_j, column kPanel + j holds w_j), and the
+// trailing matrix is A_s - sum_j (v_j w_j^H + w_j v_j^H), with A_s the stored matrix (lower
+// triangle kept). A step reads A_s once (hh_sweep: the product A_s v, read-only) and corrects
+// that product and the column it finishes with the panel (hh_reduce_panel). Every kPanel steps
+// the panel is folded into A_s by one rank-2 kPanel update on the matrix cores (hh_flush). The
+// trailing matrix thus streams once per step instead of being read and written.
+//
+// Device state:
+//   v[n]   the step's Householder vector (rows >= k+1); vn the next one
+//   y[n]   tau A v, then w (rows >= k+1)
+//   ys[n]  the product A v (rows >= k+1), then the finished column
+//   cn[n]  column k+1 of the trailing matrix (rows >= k+1)
+//   part[slots][n]  partial row sums of the sweep; dpart[chunks][2 kPanel] partial panel dots
+//   P[2 kPanel][n]  the panel
+//   d[n], e[n]  tridiagonal diagonal / |sub-diagonal|;  sc[0] = tau
+constexpr int kSB = 64;          // tile edge of the sweep and of the flush
+constexpr int kPanel = 32;       // pending rank-2 updates before a flush
+constexpr int kPW = 2 * kPanel;  // panel columns
+constexpr int kDotRows = 256;    // rows per panel-dot workgroup of the sweep
 
 __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * b
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 
-// Fused rank-2 update and next product, lower triangle only: for the trailing block [s, n)
-// (s = k + 2), A[i][j] -= v_i conj(w_j) + w_i conj(v_j) (the update of step k; v, w hold entries for
-// rows >= k+1) and the partial sums of A_new vn (vn: the next Householder vector, rows >= k+2).
-// rho is Hermitian, so only entries with j <= i of the trailing block are
-// kept up to date (the upper triangle is never read again). The trailing block [s, n) is cut into
-// 64 x 64 tiles (R, C), C <= R; each workgroup updates one tile and writes, for the next product
-// y = A_new vn, the row sums of its rows (slot C) and the conjugate column sums of its strictly
-// lower entries (slot R, y_j += conj(A_ij) vn_i). In a diagonal tile both go to slot R of the same
-// index. Index i of block B thus gets slot b from tile (B, b) for b < B, (B, B) for b = B and
-// (b, B) for b > B: every slot exactly once, summed in a fixed order by hh_reduce. Column s, the
-// one the next step finishes, is also written to cn (rows >= s), so that step reads it
-// contiguously.
-constexpr int kSB = 64;
-
-__global__ __launch_bounds__(256) void hh_fused_sym(double2* __restrict__ A, int n, int s,
-                                                    const double2* __restrict__ v, const double2* __restrict__ w,
-                                                    const double2* __restrict__ vn, double2* __restrict__ part,
-                                                    double2* __restrict__ cn) {
+// Workgroups 0..ndot-1 (only when np > 0; two per chunk of kDotRows rows from s, one per half of
+// the panel columns): dpart[chunk][m] = the sum over the chunk's rows i of conj(P_m[i]) v[i], for
+// the panel columns m in use (m mod kPanel < np); wave w of half h takes columns
+// kPanel h + 8 w .. kPanel h + 8 w + 7, its lanes consecutive rows.
+// Workgroups ndot..: one 64 x 64 tile (R, C), C <= R, of the lower triangle of A_s over [s, n).
+// The row sums of A_s v over its rows go to slot C, the conjugate column sums of its strictly
+// lower entries (y_j += conj(A_ij) v_i) to slot R; a diagonal tile sends both to slot R. Row i of
+// block B so gets slot b from tile (B, b) for b < B, (B, B) for b = B and (b, B) for b > B: every
+// slot exactly once, summed in a fixed order by hh_reduce_panel. The tiles (R, 0) also copy
+// column s of A_s to cn (rows >= s).
+__global__ __launch_bounds__(256) void hh_sweep(const double2* __restrict__ A, int n, int s,
+                                                const double2* __restrict__ v, double2* __restrict__ part,
+                                                double2* __restrict__ cn, const double2* __restrict__ P, int np,
+                                                int ndot, double2* __restrict__ dpart) {
     __shared__ double2 colred[4][kSB];
     __shared__ double2 rowred[kSB];
-    int b = blockIdx.x, R = 0;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const double2 zero = make_double2(0.0, 0.0);
+    if (int(blockIdx.x) < ndot) {
+        constexpr int kM = kPanel / 4;  // panel columns per wave
+        const int g = int(blockIdx.x) >> 1, m0 = kPanel * (int(blockIdx.x) & 1) + kM * wv;
+        const int i0 = s + g * kDotRows;
+        double2 acc[kM];
+#pragma unroll
+        for (int mm = 0; mm < kM; ++mm) acc[mm] = zero;
+        for (int q = 0; q < kDotRows / 64; ++q) {
+            const int i = i0 + 64 * q + lane;
+            if (i >= n) break;
+            const double2 vi = v[i];
+#pragma unroll
+            for (int mm = 0; mm < kM; ++mm) {
+                const int m = m0 + mm;
+                if ((m % kPanel) < np) {  // uniform over the wave
+                    const double2 a = P[int64_t(m) * n + i];
+                    acc[mm].x += a.x * vi.x + a.y * vi.y;
+                    acc[mm].y += a.x * vi.y - a.y * vi.x;
+                }
+            }
+        }
+#pragma unroll
+        for (int mm = 0; mm < kM; ++mm) {
+            double2 a = acc[mm];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                a.x += __shfl_down(a.x, off, 64);
+                a.y += __shfl_down(a.y, off, 64);
+            }
+            if (lane == 0) dpart[int64_t(g) * kPW + m0 + mm] = a;
+        }
+        return;
+    }
+    int b = int(blockIdx.x) - ndot, R = 0;
     while (b > R) {
         b -= R + 1;
         ++R;
     }
     const int C = b;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int j = s + C * kSB + lane;
     const bool jok = j < n;
-    const double2 zero = make_double2(0.0, 0.0);
-    const double2 vj = jok ? v[j] : zero, wj = jok ? w[j] : zero, vnj = jok ? vn[j] : zero;
+    double2 vj = make_double2(0.0, 0.0);
+    if (jok) vj = v[j];
+    // the wave's 16 rows, all loads issued before any use
+    constexpr int kRW = kSB / 4;
+    const int i0 = __builtin_amdgcn_readfirstlane(s + R * kSB + wv * kRW);  // the same on every lane
+    double2 a[kRW];
+#pragma unroll
+    for (int rr = 0; rr < kRW; ++rr) {
+        const int i = i0 + rr;
+        a[rr] = make_double2(0.0, 0.0);
+        if (jok && i < n && j <= i) a[rr] = A[int64_t(i) * n + j];
+    }
+    if (C == 0 && lane == 0) {  // j == s
+#pragma unroll
+        for (int rr = 0; rr < kRW; ++rr)
+            if (i0 + rr < n) cn[i0 + rr] = a[rr];
+    }
+    // column sums of the strictly lower entries; then a[rr] becomes the row product A_ij v_j
     double2 colacc = zero;
-    for (int rr = 0; rr < kSB / 4; ++rr) {
-        const int li = wv * (kSB / 4) + rr;
-        const int i = s + R * kSB + li;
-        if (i >= n) break;  // uniform over the wave
-        const double2 vi = v[i], wi = w[i], vni = vn[i];
-        double2 rp = zero;
-        if (jok && j <= i) {
-            double2 a = A[int64_t(i) * n + j];
-            const double2 t1 = cmulc(vi, conjd(wj)), t2 = cmulc(wi, conjd(vj));
-            a.x -= t1.x + t2.x;
-            a.y -= t1.y + t2.y;
-            A[int64_t(i) * n + j] = a;
-            if (C == 0 && lane == 0) cn[i] = a;  // j == s
-            rp = cmulc(a, vnj);
+#pragma unroll
+    for (int rr = 0; rr < kRW; ++rr) {
+        const int i = i0 + rr;
+        if (i < n) {
+            const double2 q = cmulc(conjd(a[rr]), v[i]);
             if (j < i) {
-                const double2 q = cmulc(conjd(a), vni);
                 colacc.x += q.x;
                 colacc.y += q.y;
             }
         }
+        a[rr] = cmulc(a[rr], vj);
+    }
+    double2* const rp = a;
+    // row sums over the 64 lanes, all 16 rows at once: at each of the exchanges 32, 16, 8, 4 a lane
+    // keeps the half of its rows selected by that lane bit and adds the partner's values of them;
+    // after 4 exchanges lane l holds row (l >> 2) & 15 summed over its group of 4 lanes, which the
+    // exchanges 2 and 1 complete
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            rp.x += __shfl_down(rp.x, off, 64);
-            rp.y += __shfl_down(rp.y, off, 64);
+    for (int h = kRW / 2, o = 32; h >= 1; h >>= 1, o >>= 1) {
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+            const double2 keep = up ? rp[q + h] : rp[q];
+            const double2 send = up ? rp[q] : rp[q + h];
+            rp[q].x = keep.x + __shfl_xor(send.x, o, 64);
+            rp[q].y = keep.y + __shfl_xor(send.y, o, 64);
         }
-        if (lane == 0) {
-            if (R == C) rowred[li] = rp;
-            else part[int64_t(C) * n + i] = rp;
+    }
+#pragma unroll
+    for (int o = 2; o >= 1; o >>= 1) {
+        rp[0].x += __shfl_xor(rp[0].x, o, 64);
+        rp[0].y += __shfl_xor(rp[0].y, o, 64);
+    }
+    if ((lane & 3) == 0) {
+        const int li = wv * kRW + (lane >> 2);
+        const int i = s + R * kSB + li;
+        if (i < n) {
+            if (R == C) rowred[li] = rp[0];
+            else part[int64_t(C) * n + i] = rp[0];
         }
     }
     colred[wv][lane] = colacc;
@@ -213,41 +287,96 @@ __global__ __launch_bounds__(256) void hh_fused_sym(double2* __restrict__ A, int
     }
 }
 
-// ys[i] = sum over the nslots partial sums of row i (i in [c, n)). A workgroup takes 32 rows; its
-// 8 groups of 32 threads sum the slots g, g + 8, g + 16, ... of each row, and the 8 group sums are
-// added in group order (a fixed order, so results are reproducible).
+// For rows i in [c, n), 32 per workgroup: ys[i] = the sum of the nslots partial sums of row i
+// minus the panel's share of the product, sum_j v_j[i] (w_j^H v) + w_j[i] (v_j^H v); and column c
+// of A_s in cn becomes column c of the trailing matrix: cn[i] -= sum_j v_j[i] conj(w_j[c]) +
+// w_j[i] conj(v_j[c]). The panel dots are the sums over the sweep's nchunk row chunks. The 8 groups of 32
+// threads take slots g, g + 8, ... and panel pairs g, g + 8, ...; their sums are added in group
+// order (a fixed order, so results are reproducible).
 constexpr int kRedRows = 32, kRedGroups = 8;
 
-__global__ __launch_bounds__(kRedRows * kRedGroups) void hh_reduce(const double2* __restrict__ part, int nslots,
-                                                                   int c, int n, double2* __restrict__ ys) {
+__global__ __launch_bounds__(kRedRows * kRedGroups) void hh_reduce_panel(
+    const double2* __restrict__ part, int nslots, int c, int n, double2* __restrict__ ys, double2* __restrict__ cn,
+    const double2* __restrict__ P, int np, const double2* __restrict__ dpart, int nchunk) {
     __shared__ double2 red[kRedGroups][kRedRows];
-    const int r = int(threadIdx.x) % kRedRows, g = int(threadIdx.x) / kRedRows;
+    __shared__ double2 redc[kRedGroups][kRedRows];
+    __shared__ double2 dq[4][kPW];  // dot sums over chunks q = 4 u + quarter
+    __shared__ double2 dsum[kPW];   // v_j^H v at j, w_j^H v at kPanel + j
+    __shared__ double2 pc[kPW];     // v_j[c] at j, w_j[c] at kPanel + j
+    const int tid = int(threadIdx.x), r = tid % kRedRows, g = tid / kRedRows;
+    if (np > 0) {
+        // thread (quarter u, column m) sums chunks u, u + 4, ...; the quarters are then added in order
+        const int m = tid % kPW, u = tid / kPW;
+        double2 a = make_double2(0.0, 0.0);
+        if ((m % kPanel) < np) {
+#pragma unroll 4
+            for (int q = u; q < nchunk; q += 4) {
+                const double2 p = dpart[int64_t(q) * kPW + m];
+                a.x += p.x;
+                a.y += p.y;
+            }
+            if (u == 0) pc[m] = P[int64_t(m) * n + c];
+        }
+        dq[u][m] = a;
+        __syncthreads();
+        if (tid < kPW) {
+            double2 t4 = dq[0][tid];
+            for (int q = 1; q < 4; ++q) {
+                t4.x += dq[q][tid].x;
+                t4.y += dq[q][tid].y;
+            }
+            dsum[tid] = t4;
+        }
+        __syncthreads();
+    }
     const int i = c + int(blockIdx.x) * kRedRows + r;
-    double2 acc = make_double2(0.0, 0.0);
-    if (i < n)
+    double2 acc = make_double2(0.0, 0.0), cc = make_double2(0.0, 0.0);
+    if (i < n) {
+#pragma unroll 4
         for (int b = g; b < nslots; b += kRedGroups) {
             const double2 p = part[int64_t(b) * n + i];
             acc.x += p.x;
             acc.y += p.y;
         }
+#pragma unroll 2
+        for (int jj = g; jj < np; jj += kRedGroups) {
+            const double2 vj = P[int64_t(jj) * n + i], wj = P[int64_t(kPanel + jj) * n + i];
+            const double2 a1 = cmulc(vj, dsum[kPanel + jj]), a2 = cmulc(wj, dsum[jj]);
+            acc.x -= a1.x + a2.x;
+            acc.y -= a1.y + a2.y;
+            const double2 c1 = cmulc(vj, conjd(pc[kPanel + jj])), c2 = cmulc(wj, conjd(pc[jj]));
+            cc.x += c1.x + c2.x;
+            cc.y += c1.y + c2.y;
+        }
+    }
     red[g][r] = acc;
+    redc[g][r] = cc;
     __syncthreads();
     if (g == 0 && i < n) {
-        double2 sum = red[0][r];
+        double2 sum = red[0][r], csum = redc[0][r];
 #pragma unroll
         for (int q = 1; q < kRedGroups; ++q) {
             sum.x += red[q][r].x;
             sum.y += red[q][r].y;
+            csum.x += redc[q][r].x;
+            csum.y += redc[q][r].y;
         }
         ys[i] = sum;
+        if (np > 0) {
+            double2 a = cn[i];
+            a.x -= csum.x;
+            a.y -= csum.y;
+            cn[i] = a;
+        }
     }
 }
 
-// Single-workgroup step kernel (1024 threads). Given ys = A22 v for the current step k (rows
-// k+1..n-1, from hh_reduce) it: forms y = tau (A22 v); alpha = -1/2 tau (y^H v); w = y + alpha v;
-// updates column k+1 of the trailing matrix (rows k+1..n-1) with the rank-2 term, into ys; records
-// d[k+1]; builds the next Householder vector from rows k+2.. of that column, with tau, beta.
-// For k = -1 it only builds the first Householder vector from column 0.
+// Single-workgroup step kernel (1024 threads). Given ys = A v for the current step k (rows
+// k+1..n-1, from hh_reduce_panel) it: forms y = tau (A v); alpha = -1/2 tau (y^H v); w = y + alpha v;
+// finishes column k+1 of the trailing matrix (rows k+1..n-1) with the step's own rank-2 term,
+// into ys; records d[k+1]; builds the next Householder vector from rows k+2.. of that column,
+// with tau, beta. v and w also go to the panel columns pv, pw (rows k+1..). For k = -1 it only
+// builds the first Householder vector from column 0.
 constexpr int kStepThreads = 1024;
 
 __device__ double block_reduce(double v, double* lds) {
@@ -281,14 +410,15 @@ __device__ double2 block_reduce2(double2 v, double2* lds) {
     return s;
 }
 
-// cin: column k+1 as the previous fused update left it, contiguous (rows >= k+1), or null to read
-// it from the matrix. Every thread keeps the same rows i = k+1+t, k+1+t+1024, ... through the
-// passes, so a value it wrote is read back by the same thread.
+// cin: column k+1 of the trailing matrix before the step's own update, contiguous (rows >= k+1),
+// or null to read it from the matrix (k = -1). Every thread keeps the same rows
+// i = k+1+t, k+1+t+1024, ... through the passes, so a value it wrote is read back by the same thread.
 __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restrict__ A, int n, int k,
                                                         double2* __restrict__ v, double2* __restrict__ y,
                                                         double2* __restrict__ vn, double2* __restrict__ ys,
                                                         double* __restrict__ d, double* __restrict__ e,
-                                                        double2* __restrict__ sc, const double2* __restrict__ cin) {
+                                                        double2* __restrict__ sc, const double2* __restrict__ cin,
+                                                        double2* __restrict__ pv, double2* __restrict__ pw) {
     double2* const col = ys;  // column c of the trailing matrix after this step's update
     __shared__ double lds[kStepThreads / 64];
     __shared__ double2 lds2[kStepThreads / 64];
@@ -298,7 +428,7 @@ __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restric
     double nx = 0.0;      // |column c|^2 over rows c+2..n-1
     if (k >= 0) {
         const double2 tau = sc[0];
-        // y_i = tau * (A22 v)_i, i = k+1..n-1 (the sums from hh_reduce); also y^H v
+        // y_i = tau * (A v)_i, i = k+1..n-1; also y^H v
         double2 yhv = make_double2(0.0, 0.0);
         for (int i = c + t; i < n; i += kStepThreads) {
             const double2 yi = cmulc(tau, ys[i]);
@@ -323,7 +453,9 @@ __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restric
             const double2 av = cmulc(alpha, vi);
             const double2 wi = make_double2(yi.x + av.x, yi.y + av.y);
             y[i] = wi;
-            double2 a = cin ? cin[i] : A[int64_t(i) * n + c];
+            pv[i] = vi;
+            pw[i] = wi;
+            double2 a = cin[i];
             const double2 t1 = cmulc(vi, conjd(wc)), t2 = cmulc(wi, conjd(vc));
             a.x -= t1.x + t2.x;
             a.y -= t1.y + t2.y;
@@ -364,32 +496,88 @@ __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restric
     for (int i = c + 2 + t; i < n; i += kStepThreads) vn[i] = cmulc(col[i], inv);
 }
 
-// GEMV for the first step: part[cb][i] = sum_{j in tile} A[i][j] v_j over rows/cols >= s
-__global__ __launch_bounds__(256) void hh_gemv(const double2* __restrict__ A, int n, int s,
-                                               const double2* __restrict__ vn, double2* __restrict__ part) {
-    const int r = n - s;
-    const int ncb = (r + kFC - 1) / kFC;
-    const int rb = blockIdx.x / ncb, cb = blockIdx.x % ncb;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int cbeg = s + cb * kFC;
-    for (int ii = 0; ii < kFR / 4; ++ii) {
-        const int i = s + rb * kFR + wv * (kFR / 4) + ii;
-        if (i >= n) break;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int jj = lane; jj < kFC; jj += 64) {
-            const int j = cbeg + jj;
-            if (j >= n) break;
-            const double2 p = cmulc(A[int64_t(i) * n + j], vn[j]);
-            acc.x += p.x;
-            acc.y += p.y;
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            acc.x += __shfl_down(acc.x, off, 64);
-            acc.y += __shfl_down(acc.y, off, 64);
-        }
-        if (lane == 0) part[int64_t(cb) * n + i] = acc;
+// The panel folded into A_s: A_s[i][j] -= sum_m U[i][m] conj(Z[j][m]) for s <= j <= i < n, with
+// U = [v_0 .. v_{kPanel-1} | w_0 .. w_{kPanel-1}] and Z = [w | v] (columns swapped by halves), that
+// is sum_j (v_j w_j^H + w_j v_j^H) over the np pairs in use. 64 x 64 tiles (I >= J) of the
+// trailing block, 4 waves of 2 x 2 FP64 MFMA tiles each (the Gram kernel's layout), the 2 kPanel
+// panel columns through LDS 16 at a time.
+__global__ __launch_bounds__(256) void hh_flush(double2* __restrict__ A, int n, int s, const double2* __restrict__ P,
+                                                int np) {
+    __shared__ double Ar[kGB][kGK + 1], Ai[kGB][kGK + 1], Br[kGB][kGK + 1], Bi[kGB][kGK + 1];
+    int b = blockIdx.x, I = 0;
+    while (b > I) {
+        b -= I + 1;
+        ++I;
     }
+    const int J = b;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+    dbl4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            accr[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
+    const int r0 = s + I * kGB, c0 = s + J * kGB;
+    for (int k0 = 0; k0 < kPW; k0 += kGK) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = t + 256 * e;
+            const int rr = idx % kGB, kk = idx / kGB;
+            const int m = k0 + kk;
+            const int mz = (m + kPanel) % kPW;
+            double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+            if ((m % kPanel) < np) {
+                if (r0 + rr < n) va = P[int64_t(m) * n + r0 + rr];
+                if (c0 + rr < n) vb = P[int64_t(mz) * n + c0 + rr];
+            }
+            Ar[rr][kk] = va.x;
+            Ai[rr][kk] = va.y;
+            Br[rr][kk] = vb.x;
+            Bi[rr][kk] = vb.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGK; kk += 4) {
+            const int ka = kk + (lane >> 4), ra = lane & 15;
+            double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ar[i] = Ar[wr + 16 * i + ra][ka];
+                ai[i] = Ai[wr + 16 * i + ra][ka];
+                br[i] = Br[wc + 16 * i + ra][ka];
+                bi[i] = Bi[wc + 16 * i + ra][ka];
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], accr[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[i], bi[j], acci[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // D[row][col] of a 16x16 f64 tile: register q of lane l holds row l/16 + 4q, column l%16
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = r0 + wr + 16 * i + (lane >> 4) + 4 * q;
+                const int col = c0 + wc + 16 * j + (lane & 15);
+                if (row < n && col <= row) {
+                    double2 a = A[int64_t(row) * n + col];
+                    a.x -= accr[i][j][q];
+                    a.y -= acci[i][j][q];
+                    A[int64_t(row) * n + col] = a;
+                }
+            }
 }
 
 // ------------------------------------------------------------------------------ tridiagonal eigenvalues
@@ -398,9 +586,12 @@ __global__ __launch_bounds__(256) void hh_gemv(const double2* __restrict__ A, in
 // negative entries as T has eigenvalues below x (Sylvester's law of inertia), and the pivots
 // obey q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1}. A pivot smaller in magnitude than
 // pivmin is replaced by -pivmin (a perturbation of T of at most pivmin per entry), so no pivot
-// is zero. Thread k finds the k-th smallest eigenvalue on its own, from the Gershgorin interval
-// down to a width of eps |T|: its result depends on d, e and k only, not on the launch shape.
+// is zero. A group of kMS lanes finds the k-th smallest eigenvalue on its own, from the
+// Gershgorin interval down to a width of eps |T|, by multisection: each round the lanes count at
+// kMS equally spaced interior points and the interval shrinks to the gap where the count first
+// exceeds k (log2(kMS + 1) bits per round instead of one). The result depends on d, e and k only.
 constexpr int kBisThreads = 256;
+constexpr int kMS = 16;  // lanes per eigenvalue
 constexpr int kBndThreads = 1024;
 
 // One workgroup: e2[i] = e[i]^2 (i < n-1); bnd = {lower, upper bound of the spectrum, pivmin,
@@ -461,20 +652,30 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const d
     return cnt;
 }
 
-// lam[k] = the k-th smallest eigenvalue, k < n. Invariant: count(lo) <= k < count(hi).
+// lam[k] = the k-th smallest eigenvalue, k < n; group k of kMS lanes. Invariant: count(lo) <= k <
+// count(hi). Every lane of a group computes the same lo, hi and step, so the points are shared
+// exactly: point l is lo + (l + 1) h, and the new bounds are points of the round.
 __global__ __launch_bounds__(kBisThreads) void tri_bisect(const double* __restrict__ d, const double* __restrict__ e2,
                                                           int n, const double* __restrict__ bnd, double* __restrict__ lam) {
-    const int k = int(blockIdx.x) * kBisThreads + int(threadIdx.x);
-    if (k >= n) return;
+    const int gid = int(blockIdx.x) * kBisThreads + int(threadIdx.x);
+    const int k0 = gid / kMS, l = gid % kMS;
+    const int k = k0 < n ? k0 : n - 1;  // surplus lanes repeat the last eigenvalue and write nothing
+    const int g0 = (int(threadIdx.x) & 63) & ~(kMS - 1);  // the group's first lane in the wave
     double lo = bnd[0], hi = bnd[1];
     const double pivmin = bnd[2], tol = bnd[3];
-    for (int it = 0; it < 2100 && hi - lo > tol; ++it) {
-        const double mid = lo + 0.5 * (hi - lo);
-        if (mid <= lo || mid >= hi) break;
-        if (sturm_count(d, e2, n, mid, pivmin) <= k) lo = mid;
-        else hi = mid;
+    for (int it = 0; it < 200 && hi - lo > tol; ++it) {
+        const double h = (hi - lo) / (kMS + 1);
+        const double x = lo + (l + 1) * h;
+        const unsigned long long above = __ballot(sturm_count(d, e2, n, x, pivmin) > k);
+        const unsigned gm = unsigned(above >> g0) & ((1u << kMS) - 1);
+        const int f = gm ? __builtin_ctz(gm) : kMS;  // first point whose count exceeds k
+        const double nlo = f == 0 ? lo : lo + f * h;
+        const double nhi = f == kMS ? hi : lo + (f + 1) * h;
+        if (!(nlo > lo || nhi < hi)) break;  // no point strictly inside: the interval cannot shrink
+        lo = nlo;
+        hi = nhi;
     }
-    lam[k] = lo + 0.5 * (hi - lo);
+    if (k0 < n && l == 0) lam[k0] = lo + 0.5 * (hi - lo);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -485,20 +686,25 @@ struct EntWS {
     double2* y;
     double2* vn;
     double2* ys;
-    double2* cn;  // the next step's column, written contiguously by the fused update
+    double2* cn;  // the step's column of the trailing matrix, contiguous
     double2* part;
+    double2* dpart;
+    double2* panel;
     double* d;
     double* e;
     double2* sc;
 };
 
-// partial-sum slots: the first product's column blocks, or the symmetric tiles' block count
-int part_slots(int n) { return std::max((n + kFC - 1) / kFC, (n + kSB - 1) / kSB) + 1; }
+// partial-sum slots of the sweep (its block count), at least 2 (the bisection reuses the area for
+// 2n + 4 doubles)
+int part_slots(int n) { return (n + kSB - 1) / kSB + 1; }
+int dot_chunks(int n) { return (n + kDotRows - 1) / kDotRows; }
 
 size_t entropy_bytes(int n) {
     return align256(size_t(n) * n * sizeof(double2)) + 5 * align256(size_t(n) * sizeof(double2)) +
-           align256(size_t(part_slots(n)) * n * sizeof(double2)) + 2 * align256(size_t(n) * sizeof(double)) +
-           align256(4 * sizeof(double2));
+           align256(size_t(part_slots(n)) * n * sizeof(double2)) +
+           align256(size_t(dot_chunks(n)) * kPW * sizeof(double2)) + align256(size_t(kPW) * n * sizeof(double2)) +
+           2 * align256(size_t(n) * sizeof(double)) + align256(4 * sizeof(double2));
 }
 
 EntWS carve_ent(void* ws, int n) {
@@ -518,6 +724,10 @@ EntWS carve_ent(void* ws, int n) {
     p += align256(size_t(n) * sizeof(double2));
     w.part = reinterpret_cast<double2*>(p);
     p += align256(size_t(part_slots(n)) * n * sizeof(double2));
+    w.dpart = reinterpret_cast<double2*>(p);
+    p += align256(size_t(dot_chunks(n)) * kPW * sizeof(double2));
+    w.panel = reinterpret_cast<double2*>(p);
+    p += align256(size_t(kPW) * n * sizeof(double2));
     w.d = reinterpret_cast<double*>(p);
     p += align256(size_t(n) * sizeof(double));
     w.e = reinterpret_cast<double*>(p);
@@ -573,34 +783,33 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
     if (n > 1) {
         // first Householder vector from column 0
         hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, -1, w.v, w.y, w.vn, w.ys, w.d,
-                           w.e, w.sc, static_cast<const double2*>(nullptr));
-        int nslots = 0;  // partial-sum slots of the current product
+                           w.e, w.sc, static_cast<const double2*>(nullptr), static_cast<double2*>(nullptr),
+                           static_cast<double2*>(nullptr));
+        int np = 0;  // pending pairs in the panel
         for (int k = 0; k + 1 < n; ++k) {
-            // the current vector (rows >= k+1) becomes v; A22 v over rows/cols >= k+1
+            // the current vector (rows >= k+1) becomes v; the trailing block is rows/cols >= k+1
             std::swap(w.v, w.vn);
             const int s0 = k + 1;
             const int r = n - s0;
-            if (k == 0) {
-                // nothing updated yet: full-row products of the Gram matrix, column blocks of kFC
-                const int ncb = (r + kFC - 1) / kFC;
-                const int nrb = (r + kFR - 1) / kFR;
-                hipLaunchKernelGGL(hh_gemv, dim3(nrb * ncb), dim3(256), 0, s, w.rho, n, s0, w.v, w.part);
-                nslots = ncb;
-            }
-            hipLaunchKernelGGL(hh_reduce, dim3((r + kRedRows - 1) / kRedRows), dim3(kRedRows * kRedGroups), 0, s, w.part,
-                               nslots, s0, n, w.ys);
-            // step kernel: y, w, column k+1 update, next Householder vector into vn
-            // column k+1 from the previous step's fused update (k >= 1), else from the matrix
-            const double2* cin = k >= 1 ? w.cn : nullptr;
+            const int nbs = (r + kSB - 1) / kSB;
+            const int nchunk = np > 0 ? (r + kDotRows - 1) / kDotRows : 0;
+            const int ndot = 2 * nchunk;
+            // A_s v (read-only sweep of the lower triangle), column k+1 of A_s, panel dots
+            hipLaunchKernelGGL(hh_sweep, dim3(ndot + nbs * (nbs + 1) / 2), dim3(256), 0, s, w.rho, n, s0, w.v, w.part,
+                               w.cn, w.panel, np, ndot, w.dpart);
+            // A v and column k+1 of the trailing matrix, with the panel's share
+            hipLaunchKernelGGL(hh_reduce_panel, dim3((r + kRedRows - 1) / kRedRows), dim3(kRedRows * kRedGroups), 0, s,
+                               w.part, nbs, s0, n, w.ys, w.cn, w.panel, np, w.dpart, nchunk);
+            // step kernel: y, w, column k+1 finished, next Householder vector into vn; (v, w) to the panel
             hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.ys, w.d,
-                               w.e, w.sc, cin);
-            if (k + 2 < n) {
-                // rank-2 update of the lower triangle of rows/cols >= k+2 fused with A_new * vn
-                const int s1 = k + 2;
-                const int nb = (n - s1 + kSB - 1) / kSB;
-                hipLaunchKernelGGL(hh_fused_sym, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, w.rho, n, s1, w.v, w.y,
-                                   w.vn, w.part, w.cn);
-                nslots = nb;
+                               w.e, w.sc, static_cast<const double2*>(w.cn), w.panel + size_t(np) * n,
+                               w.panel + size_t(kPanel + np) * n);
+            ++np;
+            if (np == kPanel && k + 2 < n) {
+                // fold the panel into the lower triangle of rows/cols >= k+2
+                const int nbf = (n - (k + 2) + kGB - 1) / kGB;
+                hipLaunchKernelGGL(hh_flush, dim3(nbf * (nbf + 1) / 2), dim3(256), 0, s, w.rho, n, k + 2, w.panel, np);
+                np = 0;
             }
             ED_HIP_TRY(hipGetLastError());
         }
@@ -619,8 +828,8 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
         double* e2 = lam + n;
         double* bnd = e2 + n;
         hipLaunchKernelGGL(tri_bounds, dim3(1), dim3(kBndThreads), 0, s, w.d, w.e, n, e2, bnd);
-        hipLaunchKernelGGL(tri_bisect, dim3((n + kBisThreads - 1) / kBisThreads), dim3(kBisThreads), 0, s, w.d, e2, n,
-                           bnd, lam);
+        hipLaunchKernelGGL(tri_bisect, dim3((n * kMS + kBisThreads - 1) / kBisThreads), dim3(kBisThreads), 0, s, w.d,
+                           e2, n, bnd, lam);
         ED_HIP_TRY(hipGetLastError());
         ED_HIP_TRY(hipMemcpyAsync(dd.data(), lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         ED_HIP_TRY(hipStreamSynchronize(s));
