@@ -496,6 +496,99 @@ __global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restric
     for (int i = c + 2 + t; i < n; i += kStepThreads) vn[i] = cmulc(col[i], inv);
 }
 
+// The step kernel for k >= 0 with every row of the column held in registers (thread t owns rows
+// c + t + 1024 q, q < RPT, as in hh_step): ys, v and the column are read once, and only the panel
+// columns and the next Householder vector are written. Covers n - k - 1 <= 1024 RPT rows.
+template <int RPT>
+__global__ __launch_bounds__(kStepThreads) void hh_step_reg(int n, int k, const double2* __restrict__ v,
+                                                            double2* __restrict__ vn, const double2* __restrict__ ys,
+                                                            double* __restrict__ d, double* __restrict__ e,
+                                                            double2* __restrict__ sc, const double2* __restrict__ cin,
+                                                            double2* __restrict__ pv, double2* __restrict__ pw) {
+    __shared__ double lds[kStepThreads / 64];
+    __shared__ double2 lds2[kStepThreads / 64];
+    __shared__ double2 sh_yc, sh_vc, sh_col[2];
+    const int t = threadIdx.x;
+    const int c = k + 1;
+    const double2 tau = sc[0];
+    const double2 zero = make_double2(0.0, 0.0);
+    double2 yv[RPT], vv[RPT], cv[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = c + t + kStepThreads * q;
+        yv[q] = zero;
+        vv[q] = zero;
+        cv[q] = zero;
+        if (i < n) {
+            yv[q] = ys[i];
+            vv[q] = v[i];
+            cv[q] = cin[i];
+        }
+    }
+    // y = tau (A v) and y^H v
+    double2 yhv = zero;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        yv[q] = cmulc(tau, yv[q]);
+        yhv.x += yv[q].x * vv[q].x + yv[q].y * vv[q].y;
+        yhv.y += yv[q].x * vv[q].y - yv[q].y * vv[q].x;
+    }
+    if (t == 0) {  // row c
+        sh_yc = yv[0];
+        sh_vc = vv[0];
+    }
+    yhv = block_reduce2(yhv, lds2);  // its barriers also publish sh_yc, sh_vc
+    const double2 tt = cmulc(tau, yhv);
+    const double2 alpha = make_double2(-0.5 * tt.x, -0.5 * tt.y);
+    const double2 vc = sh_vc, avc = cmulc(alpha, vc);
+    const double2 wc = make_double2(sh_yc.x + avc.x, sh_yc.y + avc.y);
+    // w = y + alpha v to the panel with v; column c finished with the step's own rank-2 term
+    double nx = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = c + t + kStepThreads * q;
+        if (i < n) {
+            const double2 av = cmulc(alpha, vv[q]);
+            const double2 wi = make_double2(yv[q].x + av.x, yv[q].y + av.y);
+            pv[i] = vv[q];
+            pw[i] = wi;
+            const double2 t1 = cmulc(vv[q], conjd(wc)), t2 = cmulc(wi, conjd(vc));
+            cv[q].x -= t1.x + t2.x;
+            cv[q].y -= t1.y + t2.y;
+            if (i >= c + 2) nx += cv[q].x * cv[q].x + cv[q].y * cv[q].y;
+        }
+    }
+    if (t < 2) sh_col[t] = cv[0];  // rows c and c + 1
+    nx = block_reduce(nx, lds);    // its barriers also publish sh_col
+    if (t == 0) d[c] = sh_col[0].x;
+    if (c + 1 >= n) return;
+    const double2 al = sh_col[1];
+    double2 tau_n = zero;
+    double beta;
+    double2 inv = zero;
+    if (nx == 0.0 && al.y == 0.0) {
+        beta = al.x;  // H = I
+    } else {
+        const double nrm = sqrt(al.x * al.x + al.y * al.y + nx);
+        beta = al.x >= 0.0 ? -nrm : nrm;
+        tau_n = make_double2((beta - al.x) / beta, -al.y / beta);
+        const double2 den = make_double2(al.x - beta, al.y);
+        const double dd = den.x * den.x + den.y * den.y;
+        inv = make_double2(den.x / dd, -den.y / dd);
+    }
+    if (t == 0) {
+        e[c] = fabs(beta);
+        sc[0] = tau_n;
+        vn[c + 1] = make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = c + t + kStepThreads * q;
+        if (i >= c + 2 && i < n) vn[i] = cmulc(cv[q], inv);
+    }
+}
+constexpr int kStepRegRows = 8;  // rows per thread of hh_step_reg
+
 // The panel folded into A_s: A_s[i][j] -= sum_m U[i][m] conj(Z[j][m]) for s <= j <= i < n, with
 // U = [v_0 .. v_{kPanel-1} | w_0 .. w_{kPanel-1}] and Z = [w | v] (columns swapped by halves), that
 // is sum_j (v_j w_j^H + w_j v_j^H) over the np pairs in use. 64 x 64 tiles (I >= J) of the
@@ -801,9 +894,15 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
             hipLaunchKernelGGL(hh_reduce_panel, dim3((r + kRedRows - 1) / kRedRows), dim3(kRedRows * kRedGroups), 0, s,
                                w.part, nbs, s0, n, w.ys, w.cn, w.panel, np, w.dpart, nchunk);
             // step kernel: y, w, column k+1 finished, next Householder vector into vn; (v, w) to the panel
-            hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.ys, w.d,
-                               w.e, w.sc, static_cast<const double2*>(w.cn), w.panel + size_t(np) * n,
-                               w.panel + size_t(kPanel + np) * n);
+            if (r <= kStepThreads * kStepRegRows)
+                hipLaunchKernelGGL(hh_step_reg<kStepRegRows>, dim3(1), dim3(kStepThreads), 0, s, n, k,
+                                   static_cast<const double2*>(w.v), w.vn, static_cast<const double2*>(w.ys), w.d, w.e,
+                                   w.sc, static_cast<const double2*>(w.cn), w.panel + size_t(np) * n,
+                                   w.panel + size_t(kPanel + np) * n);
+            else
+                hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.ys,
+                                   w.d, w.e, w.sc, static_cast<const double2*>(w.cn), w.panel + size_t(np) * n,
+                                   w.panel + size_t(kPanel + np) * n);
             ++np;
             if (np == kPanel && k + 2 < n) {
                 // fold the panel into the lower triangle of rows/cols >= k+2
