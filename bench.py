@@ -459,6 +459,7 @@ def row_liouville_L14(P, E, torch, dev, reps=5, steps=10):
             "apply_ms": round(ms, 3), "apply_GBps": round(32.0 * D2 / (ms * 1e-3) / 1e9, 1),
             "plan": m.describe_plan(best), "evolve_seconds": round(te.s, 3),
             "ms_per_step": round(1e3 * te.s / steps, 1), "total_krylov": info["total_m"], "max_m": info["max_m"],
+            "second_gs_passes_skipped": info["reorth_skipped"],
             "decay_identity_max_err": ident, "trace_drift": float(np.abs(obs["norm"] - 1).max())}
 
 

@@ -215,8 +215,11 @@ ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, const ed_la
  * Stopping (the paper names a tolerance and a maximal basis size): the a-posteriori estimate
  * |psi| beta_m |[exp(-i dt T_m)]_{m,1}| <= tol, an invariant subspace (beta_m <= 1e-14 |T_m|), or
  * m = m_max. fixed_m > 0 forces exactly min(fixed_m, m_max) vectors unless the space is invariant.
- * reorth = 1 orthogonalises every new vector against the whole basis (twice); reorth = 0 against
- * the previous two (the three-term recurrence with local re-projection; Hermitian only).
+ * reorth = 1 orthogonalises every new vector against the whole basis by classical Gram-Schmidt,
+ * with a second pass when the first removed more than half of the squared norm (the DGKS test
+ * with eta = 1/sqrt(2); info->reorth_skipped counts the second passes found unnecessary);
+ * reorth = 0 against the previous two (the three-term recurrence with local re-projection;
+ * Hermitian only). Arnoldi (hermitian = 0) needs reorth = 1.
  * psi     device, D amplitudes, in place: psi(0) on entry, psi(n_steps dt) on exit; no
  *         renormalisation (the norm drift is measured).
  * obs     host arrays, each may be NULL: sz[(n_steps+1) * L] = <sigma^z_k>/<psi|psi> for sites
@@ -244,6 +247,7 @@ typedef struct {
     int total_m;
     int max_m;
     double max_err;
+    int reorth_skipped;  /* second Gram-Schmidt passes skipped by the DGKS test (reorth = 1) */
 } ed_krylov_info;
 
 ed_status ed_krylov_workspace(const ed_model* model, const ed_krylov_params* params, size_t* bytes);

@@ -258,7 +258,8 @@ def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reort
         info = _lib.KrylovInfo()
         call("ed_krylov_evolve", model.handle, _dptr(psi), float(dt), int(n_steps), C.byref(p),
              C.byref(o) if o is not None else None, C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
-        return psi, obs, {"steps": info.steps, "total_m": info.total_m, "max_m": info.max_m, "max_err": info.max_err}
+        return psi, obs, {"steps": info.steps, "total_m": info.total_m, "max_m": info.max_m, "max_err": info.max_err,
+                          "reorth_skipped": info.reorth_skipped}
     p = _lib.KrylovParams(int(m_max), float(tol), int(fixed_m), int(reorth if hermitian else 1), int(bool(hermitian)))
     nb = C.c_size_t()
     call("ed_krylov_workspace", model.handle, C.byref(p), C.byref(nb))
@@ -272,7 +273,8 @@ def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reort
     info = _lib.KrylovInfo()
     call("ed_krylov_evolve", model.handle, _dptr(psi), float(dt), int(n_steps), C.byref(p),
          C.byref(o) if o is not None else None, C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
-    return psi, obs, {"steps": info.steps, "total_m": info.total_m, "max_m": info.max_m, "max_err": info.max_err}
+    return psi, obs, {"steps": info.steps, "total_m": info.total_m, "max_m": info.max_m, "max_err": info.max_err,
+                      "reorth_skipped": info.reorth_skipped}
 
 
 def trotter_evolve(model, psi, dt, n_steps, order=4, observe=True, energy=False, stream=None):

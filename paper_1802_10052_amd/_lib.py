@@ -48,7 +48,8 @@ class Observe(C.Structure):
 
 
 class KrylovInfo(C.Structure):
-    _fields_ = [("steps", C.c_int), ("total_m", C.c_int), ("max_m", C.c_int), ("max_err", C.c_double)]
+    _fields_ = [("steps", C.c_int), ("total_m", C.c_int), ("max_m", C.c_int), ("max_err", C.c_double),
+                ("reorth_skipped", C.c_int)]
 
 
 class TrajDesc(C.Structure):

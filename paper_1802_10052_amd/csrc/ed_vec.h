@@ -57,6 +57,12 @@ hipError_t axpy_norm_ptr(const double2* const* U, int n, const double2* coef, co
 // subtraction and the dots of the first kKeepDots vectors share one sweep.
 hipError_t axpy_dots_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
                          int64_t D, double2* dots_out, double2* part, hipStream_t s);
+// w -= sum_i scale[i] coef[i] U_i in one sweep (n <= kChunk) that also gives dots_out[i] = <U_i|w_new>
+// for i < *ndots = min(n, kKeepDots) and nrm_out[0].x = |w_new|^2; for n > kChunk only the
+// subtraction and the norm (*ndots = 0).
+hipError_t axpy_dots_norm_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
+                              int64_t D, double2* dots_out, double2* nrm_out, int* ndots, double2* part,
+                              hipStream_t s);
 // out_o = sum_i C[i * n_out + o] U_i for o < n_out (C device, real, n_in x n_out row-major), in one
 // sweep; outputs may alias inputs. n_in <= kMultiIn, n_out <= kMultiOut.
 hipError_t combination_multi(const double2* const* U, int n_in, const double* C, double2* const* out, int n_out,

@@ -133,7 +133,27 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
     } else {
         ED_K(dots_ptr(U, n, y, D, g1, w.part, s));
     }
-    if (passes > 1) {
+    // Plain CGS2 (both passes over lo..j): the second pass runs only when the first removed more
+    // than half of the squared norm (the DGKS test |y'| < |y| / sqrt(2), with |y|^2 = |y'|^2 +
+    // sum_i |<v_i|y>|^2 taken from the first pass's projections). Otherwise y' is orthogonal to the
+    // basis to working precision already.
+    const bool plain2 = passes > 1 && !local_first && !known_first && first_lo <= lo;
+    bool second = passes > 1;
+    if (plain2) {
+        int nd = 0;
+        ED_K(axpy_dots_norm_ptr(U, n, g1, sc.data(), y, D, g2, nr, &nd, w.part, s));
+        std::vector<double2> h1(1 + n);
+        ED_TRY(fetch_scalars(w.scal, 1 + n, h1.data(), s));
+        double removed = 0.0;
+        for (int i = 0; i < n; ++i) removed += sc[i] * (h1[1 + i].x * h1[1 + i].x + h1[1 + i].y * h1[1 + i].y);
+        second = !(h1[kNrm].x >= removed);
+        if (second) {
+            if (nd < n) ED_K(dots_ptr(U + nd, n - nd, y, D, g2 + nd, w.part, s));
+            ED_K(axpy_norm_ptr(U, n, g2, sc.data(), y, D, nr, w.part, s));
+        } else if (w.cgs_skipped) {
+            ++*w.cgs_skipped;
+        }
+    } else if (passes > 1) {
         // the first subtraction and the second pass's dots share a sweep
         ED_K(axpy_dots_ptr(U, n, g1, sc.data(), y, D, g2, w.part, s));
         ED_K(axpy_norm_ptr(U, n, g2, sc.data(), y, D, nr, w.part, s));
@@ -141,11 +161,11 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
         ED_K(axpy_norm_ptr(U, n, g1, sc.data(), y, D, nr, w.part, s));
     }
     std::vector<double2> hs(1 + 2 * n);
-    ED_TRY(fetch_scalars(w.scal, passes > 1 ? 1 + 2 * n : 1 + n, hs.data(), s));
+    ED_TRY(fetch_scalars(w.scal, second ? 1 + 2 * n : 1 + n, hs.data(), s));
     const double cj = w.c[j];
     for (int i = 0; i < n; ++i) {
         cplx g(hs[1 + i].x, hs[1 + i].y);
-        if (passes > 1) g += cplx(hs[1 + n + i].x, hs[1 + n + i].y);
+        if (second) g += cplx(hs[1 + n + i].x, hs[1 + n + i].y);
         h[i] = w.c[lo + i] * cj * g;
     }
     const double nrm2v = hs[kNrm].x;
@@ -661,6 +681,8 @@ extern "C" ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double
     const int64_t D = int64_t(1) << L;
     Workspace w;
     ED_TRY(carve(ws, ws_bytes, D, p->m_max + 1, &w));
+    int skipped = 0;
+    w.cgs_skipped = &skipped;
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* v = reinterpret_cast<double2*>(psi);
     int total_m = 0, max_m = 0;
@@ -701,6 +723,7 @@ extern "C" ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double
         info->total_m = total_m;
         info->max_m = max_m;
         info->max_err = max_err;
+        info->reorth_skipped = skipped;
     }
     return ED_OK;
 }

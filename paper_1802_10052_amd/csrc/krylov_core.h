@@ -31,12 +31,15 @@ struct Workspace {
     int64_t D = 0;
     mutable std::vector<double2*> u;
     mutable std::vector<double> c;
+    int* cgs_skipped = nullptr;  // when set, counts the second Gram-Schmidt passes skipped
     double2* slot(int i) const { return V + int64_t(i) * D; }
 };
 
 size_t core_scratch_bytes();
 ed_status carve(void* ws, size_t ws_bytes, int64_t D, int nvec, Workspace* w);
 ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s);
+// passes = 2 with both passes over lo..j (no first_lo, beta_prev or known): the second pass runs
+// only when the first removed more than half of the squared norm of H v_j.
 // first_lo > lo (with passes = 2): the first Gram-Schmidt pass takes only vectors first_lo..j (the
 // ones a three-term recurrence couples), the second pass all of lo..j.
 // beta_prev >= 0 (Hermitian H; passes = 1 with lo = j - 1 or j = lo = 0, or passes = 2 with

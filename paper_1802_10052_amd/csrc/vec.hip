@@ -284,7 +284,8 @@ __global__ __launch_bounds__(kThreads) void sub_sweep(ChunkArgs U, int n, const 
                                                       double2* __restrict__ w, int64_t D,
                                                       double2* __restrict__ part, int part_ld) {
     constexpr int G = 8;
-    constexpr int NA = KEEP > 0 ? 2 * KEEP : 1;
+    constexpr int ND = 2 * KEEP;                       // dot components, then the norm
+    constexpr int NA = ND + (NORM ? 1 : 0) > 0 ? ND + (NORM ? 1 : 0) : 1;
     __shared__ double2 cl[kChunk];
     __shared__ double lds[kWaves * NA];
     for (int i = threadIdx.x; i < n; i += kThreads) {
@@ -336,20 +337,19 @@ __global__ __launch_bounds__(kThreads) void sub_sweep(ChunkArgs U, int n, const 
                     a[2 * i + 1] = fma(keep[i].x, acc.y, fma(-keep[i].y, acc.x, a[2 * i + 1]));
                 }
             }
-        } else if constexpr (NORM) {
-            a[0] = fma(acc.x, acc.x, fma(acc.y, acc.y, a[0]));
         }
+        if constexpr (NORM) a[ND] = fma(acc.x, acc.x, fma(acc.y, acc.y, a[ND]));
     }
-    if constexpr (KEEP > 0) {
+    // block row: the dots of the first min(n, KEEP) vectors at entries 0.., the norm at entry KEEP
+    if constexpr (KEEP > 0 || NORM) {
         block_sum<NA>(a, lds);
         const int nk = n < KEEP ? n : KEEP;
-        if (threadIdx.x < 2 * nk) {
-            double* p = reinterpret_cast<double*>(part + int64_t(blockIdx.x) * part_ld);
-            p[threadIdx.x] = a[0];
+        double* p = reinterpret_cast<double*>(part + int64_t(blockIdx.x) * part_ld);
+        if (threadIdx.x < 2 * nk) p[threadIdx.x] = a[0];
+        if (NORM && threadIdx.x == ND) {
+            p[ND] = a[0];
+            p[ND + 1] = 0.0;
         }
-    } else if constexpr (NORM) {
-        block_sum<1>(a, lds);
-        if (threadIdx.x == 0) part[int64_t(blockIdx.x) * part_ld] = make_double2(a[0], 0.0);
     }
 }
 
@@ -593,6 +593,27 @@ hipError_t axpy_dots_ptr(const double2* const* U, int n, const double2* coef, co
     const int nk = n < kKeepDots ? n : kKeepDots;
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, nk, dots_out, 0);
     if (n > kKeepDots) return dots_ptr(U + kKeepDots, n - kKeepDots, w, D, dots_out + kKeepDots, part, s);
+    return hipGetLastError();
+}
+
+hipError_t axpy_dots_norm_ptr(const double2* const* U, int n, const double2* coef, const double* scale, double2* w,
+                              int64_t D, double2* dots_out, double2* nrm_out, int* ndots, double2* part,
+                              hipStream_t s) {
+    if (n > kChunk) {
+        *ndots = 0;
+        return axpy_norm_ptr(U, n, coef, scale, w, D, nrm_out, part, s);
+    }
+    const int G = grid_for(D);
+    ChunkArgs ca;
+    for (int i = 0; i < kChunk; ++i) {
+        ca.p[i] = i < n ? U[i] : nullptr;
+        ca.s[i] = i < n ? scale[i] : 0.0;
+    }
+    hipLaunchKernelGGL((sub_sweep<true, kKeepDots>), dim3(G), dim3(kThreads), 0, s, ca, n, coef, w, D, part, kPartLd);
+    const int nk = n < kKeepDots ? n : kKeepDots;
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part, kPartLd, G, nk, dots_out, 0);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s, part + kKeepDots, kPartLd, G, 1, nrm_out, 0);
+    *ndots = nk;
     return hipGetLastError();
 }
 
