@@ -499,6 +499,7 @@ def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):
                         "L in {8..16} mixed, Neel start, dt=0.01, T=5, one persistent launch",
             "batched_seconds": round(t.s, 3), "trajectory_steps_per_s": round(traj_steps_batched / t.s, 1),
             "total_jumps": res["info"]["total_jumps"], "blocks": res["info"]["blocks"],
+            "unconverged_krylov_steps": res["info"]["unconverged_steps"],
             "plain_sample_trajectories": int(len(ids)), "plain_sample_seconds": round(tp.s, 3),
             "plain_estimated_seconds_4096": round(est_plain, 1),
             "speedup_vs_plain": round(est_plain / t.s, 2),
@@ -519,6 +520,7 @@ def row_trajectories_L16(P, E, torch, dev, n_traj=512, steps=20):
                         f"dt=0.01, {steps} steps, one persistent launch",
             "seconds": round(t.s, 4), "trajectory_steps_per_s": round(n_traj * steps / t.s, 1),
             "krylov_vectors_per_step": round(res["info"]["total_krylov"] / (n_traj * steps), 3),
+            "unconverged_krylov_steps": res["info"]["unconverged_steps"],
             "total_jumps": res["info"]["total_jumps"], "blocks": res["info"]["blocks"]}
 
 

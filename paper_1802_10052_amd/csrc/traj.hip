@@ -262,13 +262,15 @@ __device__ void wg_combine(const double2* V, int64_t ld, int n, const double2* c
 }
 
 // Scaled-basis Gram-Schmidt pieces (v_i = cs[i] u_i). sweep B: w -= sum_i coef_i u_i over all n
-// vectors and, in the same pass, h2[i] = cs[i] <u_i|w_new> for the first G of them (their values
-// are still in registers); dots of any further vectors take an extra pass.
-__device__ void wg_sub_dots(const double2* V, int64_t ld, int n, double2* w, int64_t N, Shared& sh) {
-    constexpr int G = 8;
-    double a[2 * G];
+// vectors and, in the same pass, h2[i] = cs[i] <u_i|w_new> for the first kSubKeep of them (their
+// values are still in registers) and |w_new|^2, which it returns; wg_more_dots takes the dots of
+// any further vectors, in an extra pass.
+constexpr int kSubKeep = 8;
+__device__ double wg_sub_dots(const double2* V, int64_t ld, int n, double2* w, int64_t N, Shared& sh) {
+    constexpr int G = kSubKeep;
+    double a[2 * G + 1];
 #pragma unroll
-    for (int i = 0; i < 2 * G; ++i) a[i] = 0.0;
+    for (int i = 0; i < 2 * G + 1; ++i) a[i] = 0.0;
     #pragma unroll 1
     for (int64_t x = threadIdx.x; x < N; x += kTT) {
         double2 acc = w[x];
@@ -304,21 +306,26 @@ __device__ void wg_sub_dots(const double2* V, int64_t ld, int n, double2* w, int
                 a[2 * i + 1] = fma(keep[i].x, acc.y, fma(-keep[i].y, acc.x, a[2 * i + 1]));
             }
         }
+        a[2 * G] = fma(acc.x, acc.x, fma(acc.y, acc.y, a[2 * G]));
     }
-    double o[2 * G];
-    wg_sum<2 * G>(a, sh, o);
+    double o[2 * G + 1];
+    wg_sum<2 * G + 1>(a, sh, o);
     if (threadIdx.x < G && threadIdx.x < n)
         sh.h2[threadIdx.x] = make_double2(sh.cs[threadIdx.x] * o[2 * threadIdx.x], sh.cs[threadIdx.x] * o[2 * threadIdx.x + 1]);
     __syncthreads();
-    if (n > G) {
-        // remaining vectors: plain dots, scaled
-        wg_dots(V + G * ld, ld, n - G, w, N, sh);
-        if (threadIdx.x < n - G) {
-            const double c = sh.cs[G + threadIdx.x];
-            sh.h2[G + threadIdx.x] = make_double2(c * sh.h[threadIdx.x].x, c * sh.h[threadIdx.x].y);
-        }
-        __syncthreads();
+    return o[2 * G];
+}
+
+// h2[i] = cs[i] <u_i|w> for kSubKeep <= i < n (the second pass's dots beyond those of sweep B)
+__device__ void wg_more_dots(const double2* V, int64_t ld, int n, const double2* w, int64_t N, Shared& sh) {
+    constexpr int G = kSubKeep;
+    if (n <= G) return;
+    wg_dots(V + G * ld, ld, n - G, w, N, sh);
+    if (threadIdx.x < n - G) {
+        const double c = sh.cs[G + threadIdx.x];
+        sh.h2[G + threadIdx.x] = make_double2(c * sh.h[threadIdx.x].x, c * sh.h[threadIdx.x].y);
     }
+    __syncthreads();
 }
 
 // sweep C: w -= sum_i coef_i u_i; returns |w_new|^2
@@ -515,7 +522,9 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
             for (int j = 0; j < a.m_max; ++j) {
                 double2* Vj = V + j * ldv;
                 double2* Wn = V + (j + 1) * ldv;
-                // w = H v_j = cs[j] H u_j, then classical Gram-Schmidt twice in three sweeps
+                // w = H v_j = cs[j] H u_j, then classical Gram-Schmidt: dots, subtraction (with the
+                // second pass's dots and the new norm), and the second subtraction only when the first
+                // removed more than half of the squared norm (the DGKS test, eta = 1/sqrt(2))
                 wg_apply<CLS>(md, Vj, sh.cs[j], Wn, sh);
                 wg_dots(V, ldv, j + 1, Wn, N, sh);  // sh.h = <u_i|w>
                 if (t <= j) {
@@ -525,15 +534,23 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
                     sh.coef[t] = make_double2(c * g.x, c * g.y);  // w -= <v_i|w> v_i = (c_i <v_i|w>) u_i
                 }
                 __syncthreads();
-                wg_sub_dots(V, ldv, j + 1, Wn, N, sh);  // sh.h2 = <v_i|w'>
-                if (t <= j) {
-                    const double c = sh.cs[t];
-                    sh.H[t * LD + j].x += sh.h2[t].x;
-                    sh.H[t * LD + j].y += sh.h2[t].y;
-                    sh.coef[t] = make_double2(c * sh.h2[t].x, c * sh.h2[t].y);
+                const double nw2 = wg_sub_dots(V, ldv, j + 1, Wn, N, sh);  // sh.h2 = <v_i|w'>, |w'|^2
+                // |w|^2 = |w'|^2 + sum_i |<v_i|w>|^2: the same sum on every thread, in the same order
+                double removed = 0.0;
+                for (int i = 0; i <= j; ++i)
+                    removed += sh.H[i * LD + j].x * sh.H[i * LD + j].x + sh.H[i * LD + j].y * sh.H[i * LD + j].y;
+                double b2 = nw2;
+                if (!(nw2 >= removed)) {
+                    wg_more_dots(V, ldv, j + 1, Wn, N, sh);
+                    if (t <= j) {
+                        const double c = sh.cs[t];
+                        sh.H[t * LD + j].x += sh.h2[t].x;
+                        sh.H[t * LD + j].y += sh.h2[t].y;
+                        sh.coef[t] = make_double2(c * sh.h2[t].x, c * sh.h2[t].y);
+                    }
+                    __syncthreads();
+                    b2 = wg_sub_norm(V, ldv, j + 1, Wn, N, sh);
                 }
-                __syncthreads();
-                const double b2 = wg_sub_norm(V, ldv, j + 1, Wn, N, sh);
                 beta = sqrt(b2);
                 m = j + 1;
                 double hs = 0.0;
