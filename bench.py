@@ -500,6 +500,7 @@ def row_trajectories(P, E, torch, dev, n_traj=4096, plain_sample=10):
             "batched_seconds": round(t.s, 3), "trajectory_steps_per_s": round(traj_steps_batched / t.s, 1),
             "total_jumps": res["info"]["total_jumps"], "blocks": res["info"]["blocks"],
             "unconverged_krylov_steps": res["info"]["unconverged_steps"],
+            "workgroup_busy_ms": {k: round(v, 1) for k, v in res["info"]["busy_ms"].items()},
             "plain_sample_trajectories": int(len(ids)), "plain_sample_seconds": round(tp.s, 3),
             "plain_estimated_seconds_4096": round(est_plain, 1),
             "speedup_vs_plain": round(est_plain / t.s, 2),

@@ -448,6 +448,9 @@ typedef struct {
     int blocks;
     long long unconverged_steps;  /* Krylov steps that stopped at m_max with the error estimate above tol */
     int graph_replayed;           /* 1 if the batched launch replayed the stream's executable graph */
+    double busy_max_ms;           /* batched launch: the longest, shortest and mean time a workgroup */
+    double busy_min_ms;           /* spent on its list of trajectories (wall clock); 0 for the plain */
+    double busy_mean_ms;          /* path */
 } ed_traj_info;
 
 ed_status ed_trajectories_workspace(const ed_traj_desc* desc, const ed_traj_params* params, size_t* bytes);

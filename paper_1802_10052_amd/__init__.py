@@ -463,7 +463,8 @@ def trajectories(models, jump_op, rates, psi0, model_of_traj, dt, n_steps, out_s
     call(name, C.byref(d), C.byref(p), C.byref(o), C.byref(info), _dptr(ws), nb.value, _stream_ptr(st))
     return {"sz": sz, "n_jumps": nj, "jump_t": jt, "jump_site": js,
             "info": {"total_jumps": info.total_jumps, "total_krylov": info.total_krylov, "blocks": info.blocks,
-                     "unconverged_steps": info.unconverged_steps, "graph_replayed": bool(info.graph_replayed)}}
+                     "unconverged_steps": info.unconverged_steps, "graph_replayed": bool(info.graph_replayed),
+                     "busy_ms": {"max": info.busy_max_ms, "min": info.busy_min_ms, "mean": info.busy_mean_ms}}}
 
 
 def philox_words(seed, ident, count, device="cuda:0", stream=None):

@@ -69,7 +69,8 @@ class TrajOut(C.Structure):
 
 class TrajInfo(C.Structure):
     _fields_ = [("total_jumps", C.c_longlong), ("total_krylov", C.c_longlong), ("blocks", C.c_int),
-                ("unconverged_steps", C.c_longlong), ("graph_replayed", C.c_int)]
+                ("unconverged_steps", C.c_longlong), ("graph_replayed", C.c_int), ("busy_max_ms", C.c_double),
+                ("busy_min_ms", C.c_double), ("busy_mean_ms", C.c_double)]
 
 
 class AdjointParams(C.Structure):

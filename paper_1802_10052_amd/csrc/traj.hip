@@ -22,7 +22,6 @@
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <queue>
 #include <utility>
 #include <vector>
 
@@ -93,8 +92,7 @@ struct TrajModel {
 
 struct TrajArgs {
     const TrajModel* models;
-    const int* order;        // trajectories grouped by workgroup: workgroup g runs order[start[g] .. start[g+1])
-    const int* start;        // [gridDim.x + 1]
+    const int* order;        // trajectories, heaviest first: the queue the workgroups take them from
     const int* model_of;
     int n_traj;
     double dt;
@@ -116,7 +114,8 @@ struct TrajArgs {
     int* unconverged;    // per trajectory: Krylov steps that stopped at m_max with the error above tol
     double2* scratch;
     int64_t scratch_stride;
-    int* counter;
+    int* counter;     // counter[0]: the queue's next position (zero at launch)
+    long long* busy;  // per workgroup: wall-clock ticks from its start to the end of its last trajectory
 };
 
 struct Shared {
@@ -679,14 +678,25 @@ __device__ void run_trajectory(const TrajArgs& a, int tr, double2* base, Shared&
     __syncthreads();
 }
 
-// Persistent launch: workgroup g runs the trajectories order[start[g]] .. order[start[g+1] - 1],
-// a list the host deals by longest processing time first; every loop below is bounded.
+// Persistent launch: the workgroups take the trajectories of order[] (heaviest first) one at a
+// time from a queue (an atomic counter); every loop below is bounded.
 template <unsigned CLS>
 __global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(2))) void traj_kernel(TrajArgs a) {
     __shared__ Shared sh;
     double2* base = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
-    const int q0 = a.start[blockIdx.x], q1 = a.start[blockIdx.x + 1];
-    for (int q = q0; q < q1; ++q) run_trajectory<CLS>(a, a.order[q], base, sh);
+    __shared__ int qnext;
+    const unsigned long long t0 = wall_clock64();
+    // each workgroup takes the next trajectory of the queue until it is empty (no workgroup waits
+    // for another; the results do not depend on which workgroup runs a trajectory)
+    for (;;) {
+        if (threadIdx.x == 0) qnext = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int q = qnext;
+        __syncthreads();
+        if (q >= a.n_traj) break;
+        run_trajectory<CLS>(a, a.order[q], base, sh);
+    }
+    if (threadIdx.x == 0) a.busy[blockIdx.x] = static_cast<long long>(wall_clock64() - t0);
 }
 
 __global__ void zero_ints(int* p, int n) {
@@ -870,45 +880,27 @@ static int persistent_blocks(int n_traj, int Lmax, int m_max, int variant) {
 static std::mutex g_traj_graph_mu;
 static std::map<std::pair<int, hipStream_t>, hipGraphExec_t> g_traj_graph;
 
-// Longest-processing-time deal of the trajectories over G workgroups: heaviest first, each to the
-// workgroup with the least work so far (ties to the lower index). A trajectory's work is taken as
+// The queue of the batched launch: trajectories by decreasing cost, a trajectory's cost being
 // 2^L + kStepOverhead amplitude-equivalents per step (its products and sweeps stream the state; a
-// step also has a fixed cost of barriers and small serial work). Returns the trajectories grouped
-// by workgroup in ord and the group offsets in start[0..G].
-static void deal_trajectories(const ed_traj_desc* d, int G, std::vector<int>* ord, std::vector<int>* start) {
+// step also has a fixed cost of reductions and barriers). Workgroups take them in this order as
+// they finish (longest processing time first, list scheduling), so the heavy ones start early
+// and the light ones fill the end.
+static void queue_order(const ed_traj_desc* d, std::vector<int>* ord) {
     constexpr double kStepOverhead = 2048.0;
     const int nt = d->n_traj;
-    std::vector<int> by_cost(nt);
-    for (int i = 0; i < nt; ++i) by_cost[i] = i;
+    ord->resize(nt);
+    for (int i = 0; i < nt; ++i) (*ord)[i] = i;
     auto cost = [&](int t) { return double(int64_t(1) << d->models[d->model_of_traj[t]]->L) + kStepOverhead; };
-    std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    using Load = std::pair<double, int>;  // (work so far, workgroup)
-    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-    for (int g = 0; g < G; ++g) heap.push({0.0, g});
-    std::vector<std::vector<int>> lists(G);
-    for (int t : by_cost) {
-        Load l = heap.top();
-        heap.pop();
-        lists[l.second].push_back(t);
-        l.first += cost(t);
-        heap.push(l);
-    }
-    ord->clear();
-    start->assign(G + 1, 0);
-    for (int g = 0; g < G; ++g) {
-        (*start)[g] = int(ord->size());
-        ord->insert(ord->end(), lists[g].begin(), lists[g].end());
-    }
-    (*start)[G] = int(ord->size());
+    std::stable_sort(ord->begin(), ord->end(), [&](int x, int y) { return cost(x) > cost(y); });
 }
 
 static size_t traj_bytes(const ed_traj_desc* d, const ed_traj_params* p, int Lmax, int n_out, int G) {
     const size_t per = size_t(p->m_max + 2) << Lmax;
     return al256(size_t(G) * per * sizeof(double2)) + al256(size_t(d->n_models) * sizeof(TrajModel)) +
-           3 * al256(size_t(d->n_traj) * sizeof(int)) + al256(size_t(G + 1) * sizeof(int)) +
+           3 * al256(size_t(d->n_traj) * sizeof(int)) +
            al256(size_t(d->n_traj) * n_out * Lmax * sizeof(double)) +
            al256(size_t(d->n_traj) * std::max(p->max_jumps, 1) * (sizeof(double) + sizeof(int))) + al256(sizeof(int) * 4) +
-           2 * al256(size_t(d->n_traj) * sizeof(int));
+           2 * al256(size_t(d->n_traj) * sizeof(int)) + al256(size_t(G) * sizeof(long long));
 }
 
 }  // namespace ed
@@ -949,7 +941,6 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     double2* scratch = reinterpret_cast<double2*>(take(size_t(G) * per * sizeof(double2)));
     TrajModel* dmod = reinterpret_cast<TrajModel*>(take(size_t(d->n_models) * sizeof(TrajModel)));
     int* order = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
-    int* start = reinterpret_cast<int*>(take(size_t(G + 1) * sizeof(int)));
     int* model_of = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
     int* njumps = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
     double* sz = reinterpret_cast<double*>(take(size_t(nt) * n_out * Lmax * sizeof(double)));
@@ -960,6 +951,7 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     int* counter = reinterpret_cast<int*>(take(sizeof(int) * 4));
     int* mtot = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
     int* unconv = reinterpret_cast<int*>(take(size_t(nt) * sizeof(int)));
+    long long* busy = reinterpret_cast<long long*>(take(size_t(G) * sizeof(long long)));
     // host-side descriptors
     std::vector<TrajModel> hm(d->n_models);
     for (int i = 0; i < d->n_models; ++i) {
@@ -971,10 +963,9 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
         for (int k = 0; k < hm[i].L; ++k) hm[i].rate[k] = d->rates[i][k];
     }
     std::vector<int> mo(d->model_of_traj, d->model_of_traj + nt);
-    std::vector<int> ord, wg_start;
-    deal_trajectories(d, G, &ord, &wg_start);
+    std::vector<int> ord;
+    queue_order(d, &ord);
     ED_HIP_TRY(hipMemcpyAsync(dmod, hm.data(), sizeof(TrajModel) * hm.size(), hipMemcpyHostToDevice, s));
-    ED_HIP_TRY(hipMemcpyAsync(start, wg_start.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice, s));
     if (nt > 0) {
         ED_HIP_TRY(hipMemcpyAsync(order, ord.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
         ED_HIP_TRY(hipMemcpyAsync(model_of, mo.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
@@ -983,7 +974,6 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     std::memset(&a, 0, sizeof(a));
     a.models = dmod;
     a.order = order;
-    a.start = start;
     a.model_of = model_of;
     a.n_traj = nt;
     a.dt = d->dt;
@@ -1007,6 +997,7 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     a.scratch = scratch;
     a.scratch_stride = int64_t(per);
     a.counter = counter;
+    a.busy = busy;
     // clear the counters and the outputs with fill kernels, then the persistent launch; on a
     // non-null stream the three launches are captured as a hipGraph and run through the stream's
     // executable graph, which a later call updates in place (new arguments, same topology) and
@@ -1094,6 +1085,22 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
         info->blocks = G;
         info->unconverged_steps = tu;
         if (s == nullptr) info->graph_replayed = 0;
+        // per-workgroup busy time (the balance of the dealt lists)
+        std::vector<long long> hb(G);
+        ED_HIP_TRY(hipMemcpy(hb.data(), busy, sizeof(long long) * G, hipMemcpyDeviceToHost));
+        int dev = 0, khz = 0;
+        ED_HIP_TRY(hipGetDevice(&dev));
+        ED_HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        double mx = 0.0, mn = 0.0, sum = 0.0;
+        for (int g = 0; g < G; ++g) {
+            const double ms = khz > 0 ? double(hb[g]) / double(khz) : 0.0;
+            mx = g == 0 ? ms : std::max(mx, ms);
+            mn = g == 0 ? ms : std::min(mn, ms);
+            sum += ms;
+        }
+        info->busy_max_ms = mx;
+        info->busy_min_ms = mn;
+        info->busy_mean_ms = G > 0 ? sum / G : 0.0;
     }
     return ED_OK;
 }
@@ -1297,6 +1304,7 @@ extern "C" ed_status ed_trajectories_plain(const ed_traj_desc* d, const ed_traj_
         info->blocks = 1;
         info->unconverged_steps = tot_unconv;
         info->graph_replayed = 0;
+        info->busy_max_ms = info->busy_min_ms = info->busy_mean_ms = 0.0;
     }
     return ED_OK;
 }

@@ -186,3 +186,6 @@ def test_batched_deterministic():
     assert np.array_equal(a["sz"], b["sz"]) and np.array_equal(a["jump_t"], b["jump_t"])
     c = P.trajectories(models, E.SMINUS, rates, psi0, mo, 0.01, 50, 10, 3)
     assert c["info"]["graph_replayed"] and np.array_equal(a["sz"], c["sz"])
+    # every workgroup reports its busy time; the plain path reports none
+    bz = c["info"]["busy_ms"]
+    assert 0.0 < bz["min"] <= bz["mean"] <= bz["max"], bz
