@@ -7,7 +7,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libed.so")
+# ED_LIB names another build of the library (the sanitized one, for the host boundary tests)
+LIB_PATH = os.environ.get("ED_LIB") or os.path.join(HERE, "libed.so")
 
 
 class EdError(RuntimeError):

@@ -1,4 +1,9 @@
-"""Build libed.so (the HIP/C++ sources under csrc/) for gfx950 with hipcc, in-tree."""
+"""Build libed.so (the HIP/C++ sources under csrc/) for gfx950 with hipcc, in-tree.
+
+build(sanitize=True) builds libed_san.so instead: the same sources with AddressSanitizer and
+UndefinedBehaviorSanitizer on the host code only (device code is compiled as usual), for the
+CPU-side boundary tests. It needs the sanitizer runtime preloaded into the loading process
+(asan_runtime() names it)."""
 import concurrent.futures as cf
 import glob
 import os
@@ -10,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libed.so")
+SAN_BUILD = os.path.join(HERE, "_build_san")
+SAN_LIB = os.path.join(HERE, "libed_san.so")
 
 COMMON = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -23,14 +30,33 @@ def _hipcc():
     return h
 
 
-def build(verbose=False, jobs=8):
+# host-only sanitizers: each -fsanitize= directly follows -Xarch_host
+HOST_SANITIZE = ["-O1", "-g", "-Xarch_host", "-fno-omit-frame-pointer",
+                 "-Xarch_host", "-fsanitize=address",
+                 "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def asan_runtime():
+    """Path of the clang AddressSanitizer runtime that libed_san.so needs preloaded."""
+    r = subprocess.run([_hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("the clang AddressSanitizer runtime was not found")
+    return path
+
+
+def build(verbose=False, jobs=8, sanitize=False):
     hipcc = _hipcc()
-    os.makedirs(BUILD, exist_ok=True)
+    build_dir = SAN_BUILD if sanitize else BUILD
+    out_lib = SAN_LIB if sanitize else LIB
+    flags = COMMON + (HOST_SANITIZE if sanitize else [])
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
     def compile_one(src):
-        obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        cmd = [hipcc, *COMMON, "-x", "hip", "-c", src, "-o", obj]
+        obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+        cmd = [hipcc, *flags, "-x", "hip", "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -40,13 +66,14 @@ def build(verbose=False, jobs=8):
 
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    tmp = out_lib + ".tmp"
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *(HOST_SANITIZE[2:] if sanitize else []), *objs,
+           "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out_lib)
+    return out_lib
 
 
 if __name__ == "__main__":

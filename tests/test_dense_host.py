@@ -1,5 +1,6 @@
 """Host checks of the library's small dense solvers (dense.cpp), compiled with g++ on the CPU
-and compared with LAPACK/scipy on the same matrices."""
+(with AddressSanitizer and UndefinedBehaviorSanitizer) and compared with LAPACK/scipy on the same
+matrices."""
 import os
 import shutil
 import subprocess
@@ -76,10 +77,15 @@ def driver(tmp_path_factory):
     src = d / "drv.cpp"
     src.write_text(DRIVER)
     exe = d / "drv"
-    subprocess.run([gxx, "-O2", "-std=c++17", f"-I{CSRC}", str(src), os.path.join(CSRC, "dense.cpp"), "-o", str(exe)],
-                   check=True)
+    # built with AddressSanitizer and UndefinedBehaviorSanitizer: any out-of-bounds access or
+    # undefined operation in the solvers ends the driver with an error, which fails the test
+    subprocess.run([gxx, "-O2", "-g", "-std=c++17", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined", f"-I{CSRC}", str(src), os.path.join(CSRC, "dense.cpp"),
+                    "-o", str(exe)], check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
+
     def run(inp):
-        r = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True)
+        r = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True, env=env)
         return np.array([list(map(float, l.split())) for l in r.stdout.strip().splitlines()], dtype=object)
     return run
 
