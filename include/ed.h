@@ -413,7 +413,9 @@ ed_status ed_trace_distances(int n, int count, const ed_c64* a, const ed_c64* b,
  * ed_trajectories_batch runs every trajectory in one persistent kernel launch (replayed from a
  * hipGraph when stream is not NULL); ed_trajectories_plain runs the same algorithm one trajectory
  * at a time from the host (the per-instance baseline). Both synchronise stream. The effective
- * Hamiltonians' coefficient tables are allocated at entry and freed on return.
+ * Hamiltonians' tables are built on the first call with a given H, rates and jump operator (on
+ * the current device) and kept for later calls, which then allocate nothing (at most 64 are kept;
+ * the oldest is dropped first).
  * ---------------------------------------------------------------------------------------- */
 typedef struct {
     int n_models;

@@ -20,8 +20,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -728,15 +731,62 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ----------------------------------------------------------------------------- shared setup
 struct TrajSetup {
-    std::vector<ed_model*> heff;  // owned
+    std::vector<std::shared_ptr<ed_model>> heff;  // from the cache below
     int Lmax = 0;
     int n_out = 0;
     unsigned cls = 0;
     double jdj_up = 0.0, jdj_dn = 0.0;
-    ~TrajSetup() {
-        for (ed_model* m : heff) destroy_model(m);
-    }
 };
+
+// Effective Hamiltonians are kept between calls, keyed by their full description and the device:
+// a call with descriptions seen before allocates nothing, a new one builds (and allocates) once.
+// At most kHeffCacheMax are kept (the oldest is dropped, and freed once no call holds it). The
+// cache lives until the process ends and is never destroyed, so no device memory is freed after
+// the runtime has shut down.
+constexpr size_t kHeffCacheMax = 64;
+struct HeffCache {
+    std::mutex mu;
+    std::deque<std::pair<std::string, std::shared_ptr<ed_model>>> entries;  // oldest first
+};
+static HeffCache& heff_cache() {
+    static HeffCache* c = new HeffCache;
+    return *c;
+}
+
+static std::string heff_key(const ed_model_desc& md, int dev) {
+    std::string k;
+    auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+    put(&dev, sizeof(dev));
+    put(&md.L, sizeof(md.L));
+    put(&md.d, sizeof(md.d));
+    put(&md.n_site, sizeof(md.n_site));
+    put(&md.n_bond, sizeof(md.n_bond));
+    put(md.site_op, sizeof(ed_c64) * 4 * size_t(md.n_site));
+    put(md.site_coef, sizeof(double) * size_t(md.n_site) * md.L);
+    put(md.bond_op, sizeof(ed_c64) * 16 * size_t(md.n_bond));
+    put(md.bond_coef, sizeof(double) * size_t(md.n_bond) * (md.L - 1));
+    return k;  // (no long-range rules: H_eff descriptions never carry any)
+}
+
+static ed_status heff_model(const ed_model_desc& md, std::shared_ptr<ed_model>* out) {
+    int dev = 0;
+    ED_HIP_TRY(hipGetDevice(&dev));
+    const std::string key = heff_key(md, dev);
+    HeffCache& c = heff_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    for (const auto& e : c.entries)
+        if (e.first == key) {
+            *out = e.second;
+            return ED_OK;
+        }
+    ed_model* h = nullptr;
+    ED_TRY(create_model(&md, &h));
+    std::shared_ptr<ed_model> sp(h, destroy_model);
+    c.entries.emplace_back(key, sp);
+    if (c.entries.size() > kHeffCacheMax) c.entries.pop_front();
+    *out = sp;
+    return ED_OK;
+}
 
 static double heff_bound(const ed_model* m);
 
@@ -798,17 +848,17 @@ static ed_status build_setup(const ed_traj_desc* d, TrajSetup* st) {
             bcoef[size_t(k - 1) * (L - 1) + (k - 1)] = 1.0;
         }
         ed_model_desc md{L, 2, L + 1, sop.data(), scoef.data(), L - 1, bop.data(), bcoef.data()};
-        ed_model* h = nullptr;
-        ED_TRY(create_model(&md, &h));
-        st->heff.push_back(h);
+        std::shared_ptr<ed_model> h;
+        ED_TRY(heff_model(md, &h));
         st->cls |= h->op_class & kWork;
+        st->heff.push_back(std::move(h));
     }
-    for (ed_model* h : st->heff)
-        if (d->dt * heff_bound(h) > 50.0)
+    for (const auto& h : st->heff)
+        if (d->dt * heff_bound(h.get()) > 50.0)
             return fail(ED_ERR_UNSUPPORTED, "dt * |H_eff| > 50: use a smaller trajectory time step");
     // real flags: only if every model has them
     unsigned real = kOffReal | kDiagReal;
-    for (ed_model* h : st->heff) real &= h->op_class;
+    for (const auto& h : st->heff) real &= h->op_class;
     st->cls |= real;
     return ED_OK;
 }
@@ -956,7 +1006,7 @@ extern "C" ed_status ed_trajectories_batch(const ed_traj_desc* d, const ed_traj_
     std::vector<TrajModel> hm(d->n_models);
     for (int i = 0; i < d->n_models; ++i) {
         std::memset(&hm[i], 0, sizeof(TrajModel));
-        hm[i].tb = tables_of(st.heff[i]);
+        hm[i].tb = tables_of(st.heff[i].get());
         hm[i].psi0 = reinterpret_cast<const double2*>(d->psi0[i]);
         hm[i].L = st.heff[i]->L;
         hm[i].cls = st.heff[i]->op_class;
@@ -1150,7 +1200,7 @@ extern "C" ed_status ed_trajectories_plain(const ed_traj_desc* d, const ed_traj_
     long long tot_j = 0, tot_m = 0, tot_unconv = 0;
     for (int tr = 0; tr < nt; ++tr) {
         const int mi = d->model_of_traj[tr];
-        const ed_model* hm = st.heff[mi];
+        const ed_model* hm = st.heff[mi].get();
         const int L = hm->L;
         const int64_t D = int64_t(1) << L;
         Workspace w;
