@@ -176,6 +176,11 @@ ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void
  *   lowest Ritz vectors and the last residual vector are kept and the recurrence continues.
  *   Convergence: beta_j |s_j| <= tol for the lowest Ritz pair (theta, s) (the residual norm
  *   |H psi - theta psi| of the unit Ritz vector), or an invariant subspace (beta_j <= 1e-14 |theta|).
+ *   With ED_REORTH_FULL, max_basis > max_iter (no restart possible), L <= 16, no long-range rules
+ *   and max_iter <= 511, the recurrence runs device-resident: one cooperative launch performs
+ *   every product and both Gram-Schmidt passes (grid barriers between the phases) and tests
+ *   convergence on the device every 4 products, so it may take up to 3 products more than the
+ *   per-product test; info->device_resident reports it.
  * v0      device, D amplitudes, any nonzero vector (not modified)
  * E0      host, lowest Ritz value; psi0 device, D amplitudes, unit norm (global phase arbitrary)
  * info    host (may be NULL): iterations (H psi products), restarts, explicit residual
@@ -200,6 +205,7 @@ typedef struct {
     double residual;
     int converged;
     int extra_reorth;  /* re-orthogonalisations triggered by the estimates (reorth = PARTIAL) */
+    int device_resident; /* 1 if the recurrence ran in one device-resident launch (see above) */
 } ed_lanczos_info;
 
 ed_status ed_lanczos_workspace(const ed_model* model, const ed_lanczos_params* params, size_t* bytes);

@@ -232,7 +232,8 @@ def lanczos_ground(model, v0, tol=1e-10, max_iter=200, max_basis=None, n_keep=0,
     code = lib().ed_lanczos_ground(model.handle, _dptr(v0), C.byref(p), C.byref(e0), _dptr(psi0),
                                    C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
     d = {"iters": info.iters, "restarts": info.restarts, "residual": info.residual,
-         "converged": bool(info.converged), "extra_reorth": info.extra_reorth, "status": _lib.STATUS.get(code, code)}
+         "converged": bool(info.converged), "extra_reorth": info.extra_reorth,
+         "device_resident": bool(info.device_resident), "status": _lib.STATUS.get(code, code)}
     if code not in (0, -7):
         _lib.check("ed_lanczos_ground", code)
     return e0.value, psi0, d

@@ -36,7 +36,7 @@ class LanczosParams(C.Structure):
 
 class LanczosInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("residual", C.c_double), ("converged", C.c_int),
-                ("extra_reorth", C.c_int)]
+                ("extra_reorth", C.c_int), ("device_resident", C.c_int)]
 
 
 class KrylovParams(C.Structure):

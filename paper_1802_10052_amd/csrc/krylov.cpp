@@ -331,7 +331,57 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
     if (ws_bytes < need) return fail(ED_ERR_WORKSPACE, "workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
 
+    // Ritz vector psi0 = V s of the first m basis vectors, renormalised, and the explicit residual
+    auto finish = [&](int m, double theta, const std::vector<double>& svec, int iters, int restarts, int extra,
+                      bool converged, bool device, ed_status result) -> ed_status {
+        std::vector<double2> c(m);
+        for (int r = 0; r < m; ++r) c[r] = make_double2(svec[r], 0.0);
+        double2* out = reinterpret_cast<double2*>(psi0);
+        ED_TRY(combine_basis(w, m, c.data(), out, s));
+        double2* nr = w.scal + kNrm;
+        ED_K(norm2(out, D, nr, w.part, s));
+        ED_K(normalize(out, out, nr, D, s));
+        // explicit residual |H psi0 - theta psi0|
+        double2* r = w.V;  // basis no longer needed
+        ED_TRY(launch_apply_H(model, out, r, s));
+        ED_K(axpby(out, r, make_double2(-theta, 0.0), make_double2(1.0, 0.0), D, s));
+        ED_K(norm2(r, D, nr, w.part, s));
+        double2 hv[1];
+        ED_TRY(fetch_scalars(w.scal, 1, hv, s));
+        *E0 = theta;
+        if (info) {
+            info->iters = iters;
+            info->restarts = restarts;
+            info->residual = std::sqrt(std::max(hv[kNrm].x, 0.0));
+            info->converged = converged ? 1 : 0;
+            info->extra_reorth = extra;
+            info->device_resident = device ? 1 : 0;
+        }
+        return result;
+    };
+
     double nrm0 = 0.0;
+    // Full reorthogonalisation on a basis that never restarts, for a short chain: the whole
+    // recurrence on the device in one launch
+    if (p->reorth == ED_REORTH_FULL && mb >= p->max_iter + 1 && lanczos_device_fits(model, p->max_iter)) {
+        ED_TRY(start_vector(w, reinterpret_cast<const double2*>(v0), &nrm0, s, false));
+        int m = 0, prods = 0;
+        bool conv = false;
+        std::vector<double> al, be;
+        ED_TRY(lanczos_device(model, w, p->max_iter, p->tol, &m, &prods, &conv, &al, &be, s));
+        std::vector<double> svec(m, 0.0);
+        double theta = 0.0;
+        tridiag_lowest(m, al.data(), be.data(), &theta, svec.data());
+        w.u.resize(m);
+        w.c.resize(m);
+        for (int i = 0; i < m; ++i) {
+            w.u[i] = w.slot(i);
+            w.c[i] = 1.0;
+        }
+        const ed_status res =
+            conv ? ED_OK : fail(ED_ERR_NOCONV, "Lanczos did not reach the tolerance within max_iter products");
+        return finish(m, theta, svec, prods, 0, 0, conv, true, res);
+    }
     ED_TRY(start_vector(w, reinterpret_cast<const double2*>(v0), &nrm0, s, true));
 
     std::vector<double> T(size_t(mb + 1) * (mb + 1), 0.0);
@@ -520,30 +570,7 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
         }
         ++j;
     }
-    // Ritz vector psi0 = V s (unit norm up to rounding; renormalise explicitly)
-    std::vector<double2> c(m);
-    for (int r = 0; r < m; ++r) c[r] = make_double2(svec[r], 0.0);
-    double2* out = reinterpret_cast<double2*>(psi0);
-    ED_TRY(combine_basis(w, m, c.data(), out, s));
-    double2* nr = w.scal + kNrm;
-    ED_K(norm2(out, D, nr, w.part, s));
-    ED_K(normalize(out, out, nr, D, s));
-    // explicit residual |H psi0 - theta psi0|
-    double2* r = w.V;  // basis no longer needed
-    ED_TRY(launch_apply_H(model, out, r, s));
-    ED_K(axpby(out, r, make_double2(-theta, 0.0), make_double2(1.0, 0.0), D, s));
-    ED_K(norm2(r, D, nr, w.part, s));
-    double2 hv[1];
-    ED_TRY(fetch_scalars(w.scal, 1, hv, s));
-    *E0 = theta;
-    if (info) {
-        info->iters = iters;
-        info->restarts = restarts;
-        info->residual = std::sqrt(std::max(hv[kNrm].x, 0.0));
-        info->converged = converged ? 1 : 0;
-        info->extra_reorth = extra;
-    }
-    return result;
+    return finish(m, theta, svec, iters, restarts, extra, converged, false, result);
 }
 
 // ============================================================================ Krylov evolve

@@ -1,6 +1,8 @@
 // Shared Krylov recurrence (krylov.cpp) used by the ground-state, time-evolution, trajectory and
 // adjoint drivers.
 #pragma once
+#include <vector>
+
 #include "dense.h"
 #include "ed_internal.h"
 
@@ -52,6 +54,17 @@ ed_status fetch_scalars(const double2* dev, int n, double2* host, hipStream_t s)
 ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int passes, double tiny_rel,
                       cplx* h, double* beta, bool* breakdown, hipStream_t s, int first_lo = -1,
                       double beta_prev = -1.0, const double* known = nullptr);
+// Device-resident Lanczos (lanczos_dev.hip): full reorthogonalisation with no restart, the whole
+// recurrence in one cooperative launch. Fits chains of L <= kDevLanczosMaxL without long-range
+// rules or far terms and max_iter <= 511 products (within the partial-sum area). On return the
+// first m basis slots hold v_0..v_{m-1} (slot 0 must hold the unit start vector at entry),
+// alpha/beta the m diagonal and off-diagonal entries of T, products the H psi count and converged
+// whether beta_{m-1} |s_{m-1}| <= tol (tested every 4 products) or the space became invariant.
+constexpr int kDevLanczosMaxL = 16;
+bool lanczos_device_fits(const ed_model* m, int max_iter);
+ed_status lanczos_device(const ed_model* m, const Workspace& w, int max_iter, double tol, int* m_out,
+                         int* products, bool* converged, std::vector<double>* alpha, std::vector<double>* beta,
+                         hipStream_t s);
 // Basis vector 0 from psi: alias = true uses psi itself as u_0 (c_0 = 1/|psi|); otherwise psi/|psi|
 // is written to slot 0 (c_0 = 1).
 ed_status start_vector(const Workspace& w, const double2* psi, double* nrm, hipStream_t s, bool alias = false);

@@ -35,7 +35,7 @@ def test_lanczos_tfim_L14_g1():
     m = P.Model(desc)
     e0, psi, info = P.lanczos_ground(m, dev(v0), tol=1e-10, max_iter=200)
     ref = CF.tfim_bdg_ground_energy(L, 1.0, 1.0)
-    assert info["converged"] and info["residual"] < 1e-9
+    assert info["converged"] and info["residual"] < 1e-9 and info["device_resident"]
     assert abs(e0 - ref) <= 1e-10 * abs(ref)
     H = OH.hamiltonian_sparse(desc)
     eo, po, io = OL.lanczos_ground(lambda v: H @ v, v0, tol=1e-10, max_iter=200)
@@ -60,6 +60,30 @@ def test_lanczos_thick_restart_xxz(L, mb, keep, reorth):
     assert abs(e0 - eo) <= 1e-10 * abs(eo)
     assert overlap_err(psi.cpu().numpy(), po) <= 1e-9
     assert info["residual"] < 2e-10
+
+
+@pytest.mark.parametrize("L", [6, 12, 14, 16])
+def test_lanczos_device_resident(L):
+    """Full reorthogonalisation on a basis that cannot restart runs device-resident (one cooperative
+    launch); the same call with a basis that could restart runs the host-driven recurrence. Both
+    give the same ground state, and for L <= 14 the oracle's eigsh does too."""
+    print(f"lanczos device-resident L={L}", flush=True)
+    desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
+    v0 = dev(E.random_state(L, 3))
+    m = P.Model(desc)
+    e_d, psi_d, info_d = P.lanczos_ground(m, v0, tol=1e-10, max_iter=300)
+    e_h, psi_h, info_h = P.lanczos_ground(m, v0, tol=1e-10, max_iter=300, max_basis=300)
+    print(f"  device {info_d}  host {info_h}", flush=True)
+    assert info_d["device_resident"] and not info_h["device_resident"]
+    assert info_d["converged"] and info_d["residual"] < 2e-10 and info_d["restarts"] == 0
+    # the device path tests convergence every 4 products
+    assert info_h["iters"] <= info_d["iters"] <= info_h["iters"] + 3
+    assert abs(e_d - e_h) <= 1e-10 * abs(e_h)
+    assert 1 - abs(torch.vdot(psi_d, psi_h).item()) <= 1e-9
+    if L <= 14:
+        eo, po = OL.ground_state_eigsh(OH.hamiltonian_sparse(desc), tol=1e-14)
+        assert abs(e_d - eo) <= 1e-10 * abs(eo)
+        assert overlap_err(psi_d.cpu().numpy(), po) <= 1e-9
 
 
 def test_lanczos_breakdown_and_noconv():
