@@ -179,7 +179,7 @@ ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void
  *   With ED_REORTH_FULL, max_basis > max_iter (no restart possible), L <= 16, no long-range rules
  *   and max_iter <= 511, the recurrence runs device-resident: one cooperative launch performs
  *   every product and both Gram-Schmidt passes (grid barriers between the phases) and tests
- *   convergence on the device every 4 products, so it may take up to 3 products more than the
+ *   convergence on the device every 8 products, so it may take up to 7 products more than the
  *   per-product test; info->device_resident reports it.
  * v0      device, D amplitudes, any nonzero vector (not modified)
  * E0      host, lowest Ritz value; psi0 device, D amplitudes, unit norm (global phase arbitrary)

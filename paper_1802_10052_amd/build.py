@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libed.so")
 SAN_BUILD = os.path.join(HERE, "_build_san")
-SAN_LIB = os.path.join(HERE, "libed_san.so")
+SAN_LIB = os.path.join(SAN_BUILD, "libed_san.so")
 
 COMMON = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -25,7 +25,7 @@ namespace ed {
 namespace {
 
 constexpr int kLT = 256;                    // threads per workgroup
-constexpr int kLCheck = 4;                  // products between convergence tests
+constexpr int kLCheck = 8;                  // products between convergence tests
 constexpr unsigned kSpinLimit = 1u << 26;   // barrier polls before giving up
 constexpr int kDevMaxVec = 512;             // basis vectors the kernel's LDS coefficients hold
 
@@ -171,44 +171,49 @@ __device__ void subtract(const double2* V, int64_t D, int n, int64_t x, const do
     }
 }
 
-// Number of eigenvalues of the tridiagonal (d, e) below x: negative pivots of LDL^T(T - x I), a
-// pivot smaller in magnitude than pivmin taken as -pivmin.
-__device__ int sturm_below(const double* d, const double* e, int m, double x, double pivmin) {
+// Number of eigenvalues of the tridiagonal (d, e2 = squared off-diagonal) below x: negative
+// pivots of LDL^T(T - x I), a pivot smaller in magnitude than pivmin taken as -pivmin.
+__device__ int sturm_below(const double* d, const double* e2, int m, double x, double pivmin) {
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     int c = q < 0.0;
+#pragma unroll 4
     for (int i = 1; i < m; ++i) {
-        q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+        q = (d[i] - x) - e2[i - 1] / q;
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
     }
     return c;
 }
 
-// Workgroup 0's convergence test on T_m (diagonal al, off-diagonal be): theta = the lowest
-// eigenvalue by multisection (kLT points per round), then y = (T - theta I)^{-1} applied twice to
-// ones by elimination with partial pivoting (one thread), s_last = y[m-1] / |y|. Returns
-// |s_last| (the residual estimate is beta_{m-1} |s_last|).
-__device__ double ritz_last(const double* al, const double* be, int m, double* sd, double* se, double* lu, int* first) {
+// Workgroup 0's convergence test on T_m (diagonal al, off-diagonal be), the lowest Ritz value
+// being at most hi0 (the previous test's, by interlacing; +inf at the first). theta = the lowest
+// eigenvalue by multisection (kLT points per round); then y = (T - theta I)^{-1} applied twice to
+// ones by elimination with partial pivoting (one thread), s_last = y[m-1] / |y|. Returns |s_last|
+// (the residual estimate is beta_{m-1} |s_last|) and theta in *theta.
+__device__ double ritz_last(const double* al, const double* be, int m, double hi0, double* sd, double* se,
+                            double* se2, double* lu, int* first, double* theta) {
     const int t = threadIdx.x;
     for (int i = t; i < m; i += kLT) {
         sd[i] = al[i];
         se[i] = i + 1 < m ? be[i] : 0.0;
+        se2[i] = se[i] * se[i];
     }
     __syncthreads();
-    __shared__ double lo, hi, pivmin;
+    __shared__ double lo, hi, pivmin, slast;
     if (t == 0) {
         double l = HUGE_VAL, h = -HUGE_VAL, emax = 0.0;
         for (int i = 0; i < m; ++i) {
             const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i + 1 < m ? fabs(se[i]) : 0.0);
             l = fmin(l, sd[i] - r);
             h = fmax(h, sd[i] + r);
-            if (i + 1 < m) emax = fmax(emax, se[i] * se[i]);
+            if (i + 1 < m) emax = fmax(emax, se2[i]);
         }
         const double tn = fmax(fabs(l), fabs(h));
         pivmin = DBL_MIN * fmax(1.0, emax);
-        lo = l - 2.1 * DBL_EPSILON * tn * m - 4.2 * pivmin;
-        hi = h + 2.1 * DBL_EPSILON * tn * m + 4.2 * pivmin;
+        const double pad = 2.1 * DBL_EPSILON * tn * m + 4.2 * pivmin;
+        lo = l - pad;
+        hi = fmin(h, hi0) + pad;
     }
     __syncthreads();
     for (int round = 0; round < 12; ++round) {
@@ -217,7 +222,7 @@ __device__ double ritz_last(const double* al, const double* be, int m, double* s
         const double step = (h0 - l0) / (kLT + 1);
         if (t == 0) *first = kLT;
         __syncthreads();
-        if (sturm_below(sd, se, m, l0 + (t + 1) * step, pivmin) >= 1) atomicMin(first, t);
+        if (sturm_below(sd, se2, m, l0 + (t + 1) * step, pivmin) >= 1) atomicMin(first, t);
         __syncthreads();
         if (t == 0) {
             const int f = *first;
@@ -226,11 +231,10 @@ __device__ double ritz_last(const double* al, const double* be, int m, double* s
         }
         __syncthreads();
     }
-    __shared__ double slast;
     if (t == 0) {
-        const double theta = lo + 0.5 * (hi - lo);
-        // rows of T - theta I: sub b_i (i >= 1), diag c_i, super u_i; elimination with row swaps
-        // keeps at most two super-diagonals (c, u, u2), multipliers in lu[3m..4m)
+        const double th = lo + 0.5 * (hi - lo);
+        // rows of T - theta I: sub-diagonal se[i-1], diagonal c[i], super-diagonal u[i]; with row
+        // swaps the eliminated rows keep at most two super-diagonals (u, u2)
         double* c = lu;
         double* u = lu + m;
         double* u2 = lu + 2 * m;
@@ -239,15 +243,14 @@ __device__ double ritz_last(const double* al, const double* be, int m, double* s
         for (int i = 0; i < m; ++i) y[i] = 1.0;
         for (int it = 0; it < 2; ++it) {
             for (int i = 0; i < m; ++i) {
-                c[i] = sd[i] - theta;
-                u[i] = i + 1 < m ? se[i] : 0.0;
+                c[i] = sd[i] - th;
+                u[i] = se[i];
                 u2[i] = 0.0;
             }
-            // forward elimination of the sub-diagonal se[i-1] below c[i-1], with partial pivoting
             for (int i = 0; i + 1 < m; ++i) {
                 const double b = se[i];  // entry (i+1, i)
                 if (fabs(b) > fabs(c[i])) {
-                    // swap rows i and i+1: row i becomes (b, c[i+1], u[i+1]), row i+1 (c[i], u[i], u2[i] = 0)
+                    // swap rows i and i+1, then eliminate the old row i below the new pivot
                     const double ci = c[i], ui = u[i];
                     c[i] = b;
                     u[i] = c[i + 1];
@@ -268,7 +271,6 @@ __device__ double ritz_last(const double* al, const double* be, int m, double* s
                 }
             }
             if (c[m - 1] == 0.0) c[m - 1] = tiny;
-            // back substitution
             for (int i = m - 1; i >= 0; --i) {
                 double r = y[i];
                 if (i + 1 < m) r -= u[i] * y[i + 1];
@@ -282,6 +284,7 @@ __device__ double ritz_last(const double* al, const double* be, int m, double* s
         double n2 = 0.0;
         for (int i = 0; i < m; ++i) n2 += y[i] * y[i];
         slast = fabs(y[m - 1]) / sqrt(n2);
+        *theta = th;
     }
     __syncthreads();
     return slast;
@@ -292,9 +295,11 @@ __global__ __launch_bounds__(kLT) void lanczos_dev_kernel(DevLzArgs a) {
     __shared__ double2 h1[kDevMaxVec], h2[kDevMaxVec];
     __shared__ double2 red[kLT / 64][16];
     __shared__ double nred[kLT / 64];
-    __shared__ double sd[kDevMaxVec], se[kDevMaxVec], lu[4 * kDevMaxVec];
+    __shared__ double sd[kDevMaxVec], se[kDevMaxVec], se2[kDevMaxVec], lu[4 * kDevMaxVec];
     __shared__ int bad, first;
+    __shared__ double theta_prev;  // workgroup 0: the last test's lowest Ritz value
     const int t = threadIdx.x, g = blockIdx.x, G = gridDim.x;
+    if (t == 0) theta_prev = HUGE_VAL;  // read after the first grid barrier
     const int64_t x = int64_t(g) * kLT + t;
     const bool xok = x < a.D;
     unsigned gen = 0;
@@ -347,7 +352,9 @@ __global__ __launch_bounds__(kLT) void lanczos_dev_kernel(DevLzArgs a) {
             bool done = brk;
             if (!done && (n % kLCheck == 0 || n == a.nmax)) {
                 __syncthreads();  // alpha[j] and beta[j] written by thread 0
-                done = beta * ritz_last(a.alpha, a.beta, n, sd, se, lu, &first) <= a.tol;
+                double th = 0.0;
+                done = beta * ritz_last(a.alpha, a.beta, n, theta_prev, sd, se, se2, lu, &first, &th) <= a.tol;
+                if (t == 0) theta_prev = th;
             }
             if (t == 0 && done) a.ctl[1] = n;
         }

@@ -76,8 +76,8 @@ def test_lanczos_device_resident(L):
     print(f"  device {info_d}  host {info_h}", flush=True)
     assert info_d["device_resident"] and not info_h["device_resident"]
     assert info_d["converged"] and info_d["residual"] < 2e-10 and info_d["restarts"] == 0
-    # the device path tests convergence every 4 products
-    assert info_h["iters"] <= info_d["iters"] <= info_h["iters"] + 3
+    # the device path tests convergence every 8 products
+    assert info_h["iters"] <= info_d["iters"] <= info_h["iters"] + 7
     assert abs(e_d - e_h) <= 1e-10 * abs(e_h)
     assert 1 - abs(torch.vdot(psi_d, psi_h).item()) <= 1e-9
     if L <= 14:
