@@ -368,7 +368,9 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
         int m = 0, prods = 0;
         bool conv = false;
         std::vector<double> al, be;
-        ED_TRY(lanczos_device(model, w, p->max_iter, p->tol, &m, &prods, &conv, &al, &be, s));
+        const ed_status ds = lanczos_device(model, w, p->max_iter, p->tol, &m, &prods, &conv, &al, &be, s);
+        if (ds == ED_ERR_UNSUPPORTED) goto host_path;  // not co-resident now: the host-driven recurrence
+        if (ds != ED_OK) return ds;
         std::vector<double> svec(m, 0.0);
         double theta = 0.0;
         tridiag_lowest(m, al.data(), be.data(), &theta, svec.data());
@@ -382,6 +384,7 @@ extern "C" ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, 
             conv ? ED_OK : fail(ED_ERR_NOCONV, "Lanczos did not reach the tolerance within max_iter products");
         return finish(m, theta, svec, prods, 0, 0, conv, true, res);
     }
+host_path:
     ED_TRY(start_vector(w, reinterpret_cast<const double2*>(v0), &nrm0, s, true));
 
     std::vector<double> T(size_t(mb + 1) * (mb + 1), 0.0);

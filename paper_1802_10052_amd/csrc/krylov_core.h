@@ -60,6 +60,8 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
 // first m basis slots hold v_0..v_{m-1} (slot 0 must hold the unit start vector at entry),
 // alpha/beta the m diagonal and off-diagonal entries of T, products the H psi count and converged
 // whether beta_{m-1} |s_{m-1}| <= tol (tested every 8 products) or the space became invariant.
+// Returns ED_ERR_UNSUPPORTED without touching the basis when the cooperative launch cannot have all
+// its workgroups resident (the caller then runs the host-driven recurrence).
 constexpr int kDevLanczosMaxL = 16;
 bool lanczos_device_fits(const ed_model* m, int max_iter);
 ed_status lanczos_device(const ed_model* m, const Workspace& w, int max_iter, double tol, int* m_out,

@@ -426,6 +426,12 @@ ed_status lanczos_device(const ed_model* m, const Workspace& w, int max_iter, do
         return fail(ED_ERR_UNSUPPORTED, "device Lanczos: too many scalars");
     hipLaunchKernelGGL(clear_ints, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(sc), 8);
     hipError_t e = dispatch_dev<0>(m->op_class, a, G, s);
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        // the workgroups cannot all be resident now: the caller runs the host-driven recurrence
+        (void)hipGetLastError();
+        *products = 0;
+        return ED_ERR_UNSUPPORTED;
+    }
     if (e != hipSuccess) return fail(ED_ERR_HIP, std::string("device Lanczos launch: ") + hipGetErrorString(e));
     int ctl[3] = {0, 0, 0};
     ED_HIP_TRY(hipMemcpyAsync(ctl, a.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
