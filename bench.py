@@ -281,24 +281,33 @@ def row_lanczos_L14(P, E, torch, dev):
 
 
 def row_lanczos_entropy_L26(P, E, torch, dev):
+    import numpy as np
     L = 26
     desc = E.xxz(L, 1.0, 0.5, E.random_fields(L, 2))
     m = P.Model(desc)
-    v0 = E.random_state_device(L, 3, dev)
+    # a real start vector: the Hamiltonian is real, so every Lanczos vector and the ground state
+    # stay exactly real, and the entropy takes the real-arithmetic reduction
+    v0 = E.random_state_device(L, 3, dev, real=True)
     with Timer(torch, None) as t:
         e0, psi, info = P.lanczos_ground(m, v0, tol=1e-10, max_iter=1000, max_basis=24, n_keep=5, reorth="partial")
     del v0
     torch.cuda.empty_cache()
-    rec = {"workload": "XXZ J=1 Delta=0.5 h~U[-0.5,0.5] L=26, Lanczos with at most 24 stored vectors (thick "
-                       "restart keeping 5 Ritz vectors, partial reorthogonalisation), tol 1e-10, half-chain "
-                       "entropy 2^13 x 2^13",
+    rec = {"workload": "XXZ J=1 Delta=0.5 h~U[-0.5,0.5] L=26, Lanczos from a real random vector with at most 24 "
+                       "stored vectors (thick restart keeping 5 Ritz vectors, partial reorthogonalisation), tol "
+                       "1e-10, half-chain entropy 2^13 x 2^13",
            "lanczos_seconds": round(t.s, 3), "iters": info["iters"], "restarts": info["restarts"],
            "extra_reorth": info["extra_reorth"], "E0": e0, "residual": info["residual"],
            "converged": info["converged"]}
     try:
         with Timer(torch, None) as te:
-            S = P.entropy(psi, L, L // 2)
-        rec.update({"entropy": S, "entropy_seconds": round(te.s, 3)})
+            S, inf = P.entropy(psi, L, L // 2, info=True)
+        rec.update({"entropy": S, "entropy_seconds": round(te.s, 3), "entropy_real_arith": inf["real_arith"]})
+        # the same state times a global phase: same entropy, complex arithmetic
+        psi *= complex(np.cos(0.7), np.sin(0.7))
+        with Timer(torch, None) as tc:
+            Sc, infc = P.entropy(psi, L, L // 2, info=True)
+        rec.update({"entropy_seconds_complex_arith": round(tc.s, 3),
+                    "entropy_complex_arith_rel_diff": abs(Sc - S) / abs(S), "complex_real_arith": infc["real_arith"]})
     except Exception as e:
         rec["entropy_error"] = f"{type(e).__name__}: {e}"
     return rec

@@ -138,11 +138,12 @@ def random_model(L, seed, n_site=2, n_bond=3, hermitian=True):
                      bond_ops=rnd((n_bond, 4, 4)), bond_coef=rng.uniform(-1, 1, (n_bond, L - 1)))
 
 
-def random_state(L, seed, normalise=True):
-    """Complex-normal state of length 2^L (seeded)."""
+def random_state(L, seed, normalise=True, real=False):
+    """Complex-normal state of length 2^L (seeded); with real=True a real-normal one (complex
+    dtype, every imaginary part exactly zero)."""
     rng = np.random.default_rng(seed)
     D = 1 << L
-    v = rng.standard_normal(D) + 1j * rng.standard_normal(D)
+    v = rng.standard_normal(D) + (0j if real else 1j * rng.standard_normal(D))
     if normalise:
         v /= np.linalg.norm(v)
     return v
@@ -179,26 +180,31 @@ def trajectory_lengths(n_traj, lengths=(8, 10, 12, 14, 16)):
     return np.array([lengths[t % len(lengths)] for t in range(n_traj)], dtype=np.int32)
 
 
-def random_state_device(L, seed, device):
+def random_state_device(L, seed, device, real=False):
     """Complex-normal normalised state of length 2^L generated directly on a torch device
-    (seeded torch generator), for sizes where a host copy would only cost time."""
+    (seeded torch generator), for sizes where a host copy would only cost time; with real=True
+    a real-normal one (complex dtype, every imaginary part exactly zero)."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
-    v = torch.randn(1 << L, dtype=torch.complex128, device=device, generator=g)
+    if real:
+        v = torch.randn(1 << L, dtype=torch.float64, device=device, generator=g).to(torch.complex128)
+    else:
+        v = torch.randn(1 << L, dtype=torch.complex128, device=device, generator=g)
     v /= torch.linalg.vector_norm(v)
     return v
 
 
-def graded_schmidt_state(L, l, rank, decay, seed):
+def graded_schmidt_state(L, l, rank, decay, seed, real=False):
     """State of length 2^L whose matrix view M (2^l rows = sites 1..l) is A diag(s) B^dagger,
     with complex-normal A (2^l x rank) and B (2^(L-l) x rank) and s_k = exp(-k / decay): a
     Schmidt spectrum that falls off geometrically like a ground state's, of rank <= rank.
-    Normalised. Seeded."""
+    Normalised. Seeded. With real=True, A and B are real-normal (complex dtype, zero imaginary
+    parts)."""
     rng = np.random.default_rng(seed)
     n, K = 1 << l, 1 << (L - l)
-    A = rng.standard_normal((n, rank)) + 1j * rng.standard_normal((n, rank))
-    B = rng.standard_normal((K, rank)) + 1j * rng.standard_normal((K, rank))
+    A = rng.standard_normal((n, rank)) + (0j if real else 1j * rng.standard_normal((n, rank)))
+    B = rng.standard_normal((K, rank)) + (0j if real else 1j * rng.standard_normal((K, rank)))
     s = np.exp(-np.arange(rank) / float(decay))
     v = ((A * s) @ B.conj().T).reshape(-1)
     return v / np.linalg.norm(v)

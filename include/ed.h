@@ -312,15 +312,20 @@ ed_status ed_measure_noalloc(const ed_c64* psi, int L, double* sz, double* norm,
  * rho_l = M M^dagger / <psi|psi>, M = psi reshaped to 2^l x 2^(L-l) row-major (no copy is made).
  * The Gram matrix of the smaller side is formed on the FP64 matrix cores, reduced to
  * tridiagonal form by Householder steps on the GPU, and its eigenvalues are found by bisection
- * on Sturm counts on the GPU (absolute accuracy a few eps |rho|).
- * psi       device, D amplitudes (any nonzero norm)
- * S         host; spectrum host (may be NULL): min(2^l, 2^(L-l)) eigenvalues, descending.
+ * on Sturm counts on the GPU (absolute accuracy a few eps |rho|). When every amplitude has a zero
+ * imaginary part (a real state), rho is real symmetric and the Gram matrix and the reduction run
+ * in real arithmetic: the same steps without their zero imaginary parts (half the bytes per
+ * Householder sweep, a quarter of the matrix-core products). A NaN imaginary part counts as
+ * nonzero.
+ * psi        device, D amplitudes (any nonzero norm)
+ * S          host; spectrum host (may be NULL): min(2^l, 2^(L-l)) eigenvalues, descending.
+ * real_arith host (may be NULL): set to 1 when the real arithmetic ran, else 0.
  * Limits: 0 <= l_cut <= L, min(l_cut, L - l_cut) <= 14. Synchronises stream.
  * Workspace: ed_entropy_workspace (the Gram matrix, 16 * 4^min(l, L-l) bytes, plus vectors).
  * ---------------------------------------------------------------------------------------- */
 ed_status ed_entropy_workspace(int L, int l_cut, size_t* bytes);
-ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, void* ws,
-                     size_t ws_bytes, void* stream);
+ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, int* real_arith,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
  * Liouville space (Sec. VI.B, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket, App. F). The density

@@ -327,19 +327,24 @@ def measure_noalloc(psi, L, stream=None):
     return sz, nrm.value
 
 
-def entropy(psi, L, l_cut=None, spectrum=False, stream=None):
+def entropy(psi, L, l_cut=None, spectrum=False, stream=None, info=False):
     """Bond entropy S(l_cut) (natural log) of a device state (ed_entropy); with spectrum=True
-    also the Schmidt spectrum (descending numpy array)."""
+    also the Schmidt spectrum (descending numpy array); with info=True also a dict whose
+    "real_arith" tells whether the state was real and the reduction ran in real arithmetic."""
     _check_state(psi, 1 << L)
     l = L // 2 if l_cut is None else int(l_cut)
     nb = C.c_size_t()
     call("ed_entropy_workspace", int(L), l, C.byref(nb))
     ws = _workspace(nb.value, psi.device)
     S = C.c_double()
+    real = C.c_int(0)
     spec = np.zeros(1 << min(l, L - l)) if spectrum else None
     call("ed_entropy", _dptr(psi), int(L), 2, l, C.byref(S), spec.ctypes.data if spectrum else None,
-         _dptr(ws), nb.value, _stream_ptr(stream))
-    return (S.value, spec) if spectrum else S.value
+         C.byref(real), _dptr(ws), nb.value, _stream_ptr(stream))
+    out = (S.value, spec) if spectrum else (S.value,)
+    if info:
+        out = out + ({"real_arith": bool(real.value)},)
+    return out if len(out) > 1 else out[0]
 
 
 def rdm(psi, L, two_site=True, stream=None):

@@ -6,13 +6,18 @@
 // Here:
 //   1. rho = R R^H on the FP64 matrix cores (v_mfma_f64_16x16x4f64), with R = M when
 //      d^l <= d^(L-l) and R = M^T otherwise (same non-zero spectrum, smaller Gram matrix);
-//      R is read in place from the state, never copied.
+//      R is read in place from the state, never copied. Only the lower triangle is stored.
 //   2. Householder reduction of the Hermitian rho to a real symmetric tridiagonal matrix on the
-//      GPU: each step's rank-2 update of the trailing matrix is fused with the matrix-vector
-//      product that the next step needs, on the lower triangle only (the product takes the upper
-//      part as the conjugate of the lower), so half the trailing matrix streams once per step.
+//      GPU, in blocked form: a read-only matrix-vector sweep of the stored lower triangle per
+//      step, the last kPanel rank-2 updates kept pending in a panel and folded into the matrix
+//      every kPanel steps by one product on the matrix cores.
 //   3. Eigenvalues of the tridiagonal matrix by multisection on Sturm counts on the GPU, 16 lanes
 //      per eigenvalue.
+// When every amplitude of the state has a zero imaginary part (a real state, such as the ground
+// state of a real Hamiltonian started from a real vector), R and rho are real, and so are every
+// Householder vector, tau and panel column: steps 1 and 2 then run in real arithmetic (kernels
+// templated on T = double instead of T = double2), the same operations without their zero
+// imaginary parts.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -26,18 +31,70 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// ------------------------------------------------------------------------------ scalars
+// T = double2: a complex entry; T = double: a real one. The helpers give both the same spelling.
+template <typename T>
+constexpr bool kCx = sizeof(T) == sizeof(double2);
+
+__device__ __forceinline__ double2 mul(double2 a, double2 b) {  // a * b
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double mul(double a, double b) { return a * b; }
+__device__ __forceinline__ double2 cj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double cj(double a) { return a; }
+__device__ __forceinline__ double2 add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double add(double a, double b) { return a + b; }
+__device__ __forceinline__ double2 sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double sub(double a, double b) { return a - b; }
+__device__ __forceinline__ double2 scale(double2 a, double f) { return make_double2(f * a.x, f * a.y); }
+__device__ __forceinline__ double scale(double a, double f) { return f * a; }
+__device__ __forceinline__ double re(double2 a) { return a.x; }
+__device__ __forceinline__ double re(double a) { return a; }
+__device__ __forceinline__ double im(double2 a) { return a.y; }
+__device__ __forceinline__ double im(double) { return 0.0; }
+__device__ __forceinline__ double abs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double abs2(double a) { return a * a; }
+template <typename T>
+__device__ __forceinline__ T mk(double r, double i);
+template <>
+__device__ __forceinline__ double2 mk<double2>(double r, double i) {
+    return make_double2(r, i);
+}
+template <>
+__device__ __forceinline__ double mk<double>(double r, double) {
+    return r;
+}
+__device__ __forceinline__ double2 shfl_dn(double2 v, int o) {
+    return make_double2(__shfl_down(v.x, o, 64), __shfl_down(v.y, o, 64));
+}
+__device__ __forceinline__ double shfl_dn(double v, int o) { return __shfl_down(v, o, 64); }
+__device__ __forceinline__ double2 shfl_x(double2 v, int o) {
+    return make_double2(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64));
+}
+__device__ __forceinline__ double shfl_x(double v, int o) { return __shfl_xor(v, o, 64); }
+
+// flag = 1 when some amplitude has a nonzero (or NaN) imaginary part
+__global__ __launch_bounds__(256) void imag_any(const double2* __restrict__ psi, int64_t D, int* __restrict__ flag) {
+    bool nz = false;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < D; i += int64_t(gridDim.x) * 256)
+        nz |= !(psi[i].y == 0.0);
+    if (__ballot(nz) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 // ------------------------------------------------------------------------------ Gram matrix
 // rho[a][a'] = sum_b R[a][b] conj(R[a'][b]), R[r][c] = psi[r*rs + c*cs], n x K.
 // Block tile 64 x 64 of rho per workgroup (4 waves, each 32 x 32 = 2 x 2 MFMA tiles), K consumed
-// 16 at a time through LDS. Only blocks with I >= J are computed; the mirrored block is written
-// as the conjugate transpose so rho is stored in full.
+// 16 at a time through LDS. Only blocks with I >= J are computed and stored (the Householder
+// kernels read the lower triangle only). A complex product takes four real MFMAs, a real one one.
 constexpr int kGB = 64;
 constexpr int kGK = 16;
 
-template <bool ROWC>  // ROWC: R's columns are contiguous in memory (cs == 1)
+template <bool ROWC, typename T>  // ROWC: R's columns are contiguous in memory (cs == 1)
 __global__ __launch_bounds__(256) void gram_mfma(const double2* __restrict__ psi, int64_t rs, int64_t cs,
-                                                 int n, int64_t K, double2* __restrict__ rho, int nb) {
-    __shared__ double Ar[kGB][kGK + 1], Ai[kGB][kGK + 1], Br[kGB][kGK + 1], Bi[kGB][kGK + 1];
+                                                 int n, int64_t K, T* __restrict__ rho) {
+    constexpr bool CX = kCx<T>;
+    constexpr int kIm = CX ? kGB : 1;  // rows of the imaginary-part tiles (unused when real)
+    __shared__ double Ar[kGB][kGK + 1], Br[kGB][kGK + 1], Ai[kIm][kGK + 1], Bi[kIm][kGK + 1];
     // triangular block index -> (I, J), I >= J
     int b = blockIdx.x, I = 0;
     while (b > I) {
@@ -47,6 +104,7 @@ __global__ __launch_bounds__(256) void gram_mfma(const double2* __restrict__ psi
     const int J = b;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+    const double* const psr = reinterpret_cast<const double*>(psi);
     dbl4 accr[2][2], acci[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -69,37 +127,58 @@ __global__ __launch_bounds__(256) void gram_mfma(const double2* __restrict__ psi
                 rr = idx % kGB;
                 kk = idx / kGB;
             }
-            double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-            if (k0 + kk < K) {
-                if (r0 + rr < n) va = psi[int64_t(r0 + rr) * rs + (k0 + kk) * cs];
-                if (c0 + rr < n) vb = psi[int64_t(c0 + rr) * rs + (k0 + kk) * cs];
+            const bool kok = k0 + kk < K;
+            const bool aok = kok && r0 + rr < n, bok = kok && c0 + rr < n;
+            const int64_t ia = int64_t(r0 + rr) * rs + (k0 + kk) * cs, ib = int64_t(c0 + rr) * rs + (k0 + kk) * cs;
+            if constexpr (CX) {
+                double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+                if (aok) va = psi[ia];
+                if (bok) vb = psi[ib];
+                Ar[rr][kk] = va.x;
+                Ai[rr][kk] = va.y;
+                Br[rr][kk] = vb.x;
+                Bi[rr][kk] = vb.y;
+            } else {
+                double va = 0.0, vb = 0.0;
+                if (aok) va = psr[2 * ia];  // the real part only
+                if (bok) vb = psr[2 * ib];
+                Ar[rr][kk] = va;
+                Br[rr][kk] = vb;
             }
-            Ar[rr][kk] = va.x;
-            Ai[rr][kk] = va.y;
-            Br[rr][kk] = vb.x;
-            Bi[rr][kk] = vb.y;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 4) {
             const int ka = kk + (lane >> 4), ra = lane & 15;
-            double ar[2], ai[2], br[2], bi[2];
+            double ar[2], br[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 ar[i] = Ar[wr + 16 * i + ra][ka];
-                ai[i] = Ai[wr + 16 * i + ra][ka];
                 br[i] = Br[wc + 16 * i + ra][ka];
-                bi[i] = Bi[wc + 16 * i + ra][ka];
             }
+            if constexpr (CX) {
+                double ai[2], bi[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], accr[i][j], 0, 0, 0);
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[i], bi[j], acci[i][j], 0, 0, 0);
+                for (int i = 0; i < 2; ++i) {
+                    ai[i] = Ai[wr + 16 * i + ra][ka];
+                    bi[i] = Bi[wc + 16 * i + ra][ka];
                 }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], accr[i][j], 0, 0, 0);
+                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
+                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[i], bi[j], acci[i][j], 0, 0, 0);
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -112,11 +191,7 @@ __global__ __launch_bounds__(256) void gram_mfma(const double2* __restrict__ psi
             for (int q = 0; q < 4; ++q) {
                 const int row = r0 + wr + 16 * i + (lane >> 4) + 4 * q;
                 const int col = c0 + wc + 16 * j + (lane & 15);
-                if (row < n && col < n) {
-                    const double re = accr[i][j][q], im = acci[i][j][q];
-                    rho[int64_t(row) * n + col] = make_double2(re, im);
-                    if (I != J) rho[int64_t(col) * n + row] = make_double2(re, -im);
-                }
+                if (row < n && col < n) rho[int64_t(row) * n + col] = mk<T>(accr[i][j][q], acci[i][j][q]);
             }
 }
 
@@ -134,7 +209,7 @@ __global__ __launch_bounds__(256) void gram_mfma(const double2* __restrict__ psi
 // the panel is folded into A_s by one rank-2 kPanel update on the matrix cores (hh_flush). The
 // trailing matrix thus streams once per step instead of being read and written.
 //
-// Device state:
+// Device state (T entries):
 //   v[n]   the step's Householder vector (rows >= k+1); vn the next one
 //   y[n]   tau A v, then w (rows >= k+1)
 //   ys[n]  the product A v (rows >= k+1), then the finished column
@@ -147,11 +222,6 @@ constexpr int kPanel = 32;       // pending rank-2 updates before a flush
 constexpr int kPW = 2 * kPanel;  // panel columns
 constexpr int kDotRows = 256;    // rows per panel-dot workgroup of the sweep
 
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * b
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
-
 // Workgroups 0..ndot-1 (only when np > 0; two per chunk of kDotRows rows from s, one per half of
 // the panel columns): dpart[chunk][m] = the sum over the chunk's rows i of conj(P_m[i]) v[i], for
 // the panel columns m in use (m mod kPanel < np); wave w of half h takes columns
@@ -162,43 +232,56 @@ __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -
 // block B so gets slot b from tile (B, b) for b < B, (B, B) for b = B and (b, B) for b > B: every
 // slot exactly once, summed in a fixed order by hh_reduce_panel. The tiles (R, 0) also copy
 // column s of A_s to cn (rows >= s).
-__global__ __launch_bounds__(256) void hh_sweep(const double2* __restrict__ A, int n, int s,
-                                                const double2* __restrict__ v, double2* __restrict__ part,
-                                                double2* __restrict__ cn, const double2* __restrict__ P, int np,
-                                                int ndot, double2* __restrict__ dpart) {
-    __shared__ double2 colred[4][kSB];
-    __shared__ double2 rowred[kSB];
+// One exchange round of the transposing butterfly per level, H = 8, 4, 2, 1 rows still held per
+// lane at lane offsets 4H = 32, 16, 8, 4: a lane keeps the half of its rows selected by that lane
+// bit and adds the partner's values of them. After the four rounds lane l holds row (l >> 2) & 15
+// summed over its group of 4 lanes. Written as a recursion so that every row index is a constant.
+template <int H, typename T>
+__device__ __forceinline__ void row_butterfly(T* rp, int lane) {
+    if constexpr (H >= 1) {
+        constexpr int O = 4 * H;
+        const bool up = (lane & O) != 0;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const T keep = up ? rp[q + H] : rp[q];
+            const T send = up ? rp[q] : rp[q + H];
+            rp[q] = add(keep, shfl_x(send, O));
+        }
+        row_butterfly<H / 2>(rp, lane);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void hh_sweep(const T* __restrict__ A, int n, int s, const T* __restrict__ v,
+                                                T* __restrict__ part, T* __restrict__ cn, const T* __restrict__ P,
+                                                int np, int ndot, T* __restrict__ dpart) {
+    __shared__ T colred[4][kSB];
+    __shared__ T rowred[kSB];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const double2 zero = make_double2(0.0, 0.0);
+    const T zero = mk<T>(0.0, 0.0);
     if (int(blockIdx.x) < ndot) {
         constexpr int kM = kPanel / 4;  // panel columns per wave
         const int g = int(blockIdx.x) >> 1, m0 = kPanel * (int(blockIdx.x) & 1) + kM * wv;
         const int i0 = s + g * kDotRows;
-        double2 acc[kM];
+        T acc[kM];
 #pragma unroll
         for (int mm = 0; mm < kM; ++mm) acc[mm] = zero;
         for (int q = 0; q < kDotRows / 64; ++q) {
             const int i = i0 + 64 * q + lane;
             if (i >= n) break;
-            const double2 vi = v[i];
+            const T vi = v[i];
 #pragma unroll
             for (int mm = 0; mm < kM; ++mm) {
                 const int m = m0 + mm;
-                if ((m % kPanel) < np) {  // uniform over the wave
-                    const double2 a = P[int64_t(m) * n + i];
-                    acc[mm].x += a.x * vi.x + a.y * vi.y;
-                    acc[mm].y += a.x * vi.y - a.y * vi.x;
-                }
+                if ((m % kPanel) < np)  // uniform over the wave
+                    acc[mm] = add(acc[mm], mul(cj(P[int64_t(m) * n + i]), vi));
             }
         }
 #pragma unroll
         for (int mm = 0; mm < kM; ++mm) {
-            double2 a = acc[mm];
+            T a = acc[mm];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                a.x += __shfl_down(a.x, off, 64);
-                a.y += __shfl_down(a.y, off, 64);
-            }
+            for (int off = 32; off > 0; off >>= 1) a = add(a, shfl_dn(a, off));
             if (lane == 0) dpart[int64_t(g) * kPW + m0 + mm] = a;
         }
         return;
@@ -211,16 +294,16 @@ __global__ __launch_bounds__(256) void hh_sweep(const double2* __restrict__ A, i
     const int C = b;
     const int j = s + C * kSB + lane;
     const bool jok = j < n;
-    double2 vj = make_double2(0.0, 0.0);
+    T vj = zero;
     if (jok) vj = v[j];
     // the wave's 16 rows, all loads issued before any use
     constexpr int kRW = kSB / 4;
     const int i0 = __builtin_amdgcn_readfirstlane(s + R * kSB + wv * kRW);  // the same on every lane
-    double2 a[kRW];
+    T a[kRW];
 #pragma unroll
     for (int rr = 0; rr < kRW; ++rr) {
         const int i = i0 + rr;
-        a[rr] = make_double2(0.0, 0.0);
+        a[rr] = zero;
         if (jok && i < n && j <= i) a[rr] = A[int64_t(i) * n + j];
     }
     if (C == 0 && lane == 0) {  // j == s
@@ -229,40 +312,22 @@ __global__ __launch_bounds__(256) void hh_sweep(const double2* __restrict__ A, i
             if (i0 + rr < n) cn[i0 + rr] = a[rr];
     }
     // column sums of the strictly lower entries; then a[rr] becomes the row product A_ij v_j
-    double2 colacc = zero;
+    T colacc = zero;
 #pragma unroll
     for (int rr = 0; rr < kRW; ++rr) {
         const int i = i0 + rr;
         if (i < n) {
-            const double2 q = cmulc(conjd(a[rr]), v[i]);
-            if (j < i) {
-                colacc.x += q.x;
-                colacc.y += q.y;
-            }
+            const T q = mul(cj(a[rr]), v[i]);
+            if (j < i) colacc = add(colacc, q);
         }
-        a[rr] = cmulc(a[rr], vj);
+        a[rr] = mul(a[rr], vj);
     }
-    double2* const rp = a;
-    // row sums over the 64 lanes, all 16 rows at once: at each of the exchanges 32, 16, 8, 4 a lane
-    // keeps the half of its rows selected by that lane bit and adds the partner's values of them;
-    // after 4 exchanges lane l holds row (l >> 2) & 15 summed over its group of 4 lanes, which the
-    // exchanges 2 and 1 complete
+    T* const rp = a;
+    // row sums over the 64 lanes, all 16 rows at once (row_butterfly); the exchanges 2 and 1 then
+    // complete the sums over each group of 4 lanes
+    row_butterfly<kRW / 2>(rp, lane);
 #pragma unroll
-    for (int h = kRW / 2, o = 32; h >= 1; h >>= 1, o >>= 1) {
-        const bool up = (lane & o) != 0;
-#pragma unroll
-        for (int q = 0; q < h; ++q) {
-            const double2 keep = up ? rp[q + h] : rp[q];
-            const double2 send = up ? rp[q] : rp[q + h];
-            rp[q].x = keep.x + __shfl_xor(send.x, o, 64);
-            rp[q].y = keep.y + __shfl_xor(send.y, o, 64);
-        }
-    }
-#pragma unroll
-    for (int o = 2; o >= 1; o >>= 1) {
-        rp[0].x += __shfl_xor(rp[0].x, o, 64);
-        rp[0].y += __shfl_xor(rp[0].y, o, 64);
-    }
+    for (int o = 2; o >= 1; o >>= 1) rp[0] = add(rp[0], shfl_x(rp[0], o));
     if ((lane & 3) == 0) {
         const int li = wv * kRW + (lane >> 2);
         const int i = s + R * kSB + li;
@@ -274,15 +339,9 @@ __global__ __launch_bounds__(256) void hh_sweep(const double2* __restrict__ A, i
     colred[wv][lane] = colacc;
     __syncthreads();
     if (wv == 0 && jok) {
-        double2 cs = colred[0][lane];
-        for (int q = 1; q < 4; ++q) {
-            cs.x += colred[q][lane].x;
-            cs.y += colred[q][lane].y;
-        }
-        if (R == C) {
-            cs.x += rowred[lane].x;
-            cs.y += rowred[lane].y;
-        }
+        T cs = colred[0][lane];
+        for (int q = 1; q < 4; ++q) cs = add(cs, colred[q][lane]);
+        if (R == C) cs = add(cs, rowred[lane]);
         part[int64_t(R) * n + j] = cs;
     }
 }
@@ -295,79 +354,61 @@ __global__ __launch_bounds__(256) void hh_sweep(const double2* __restrict__ A, i
 // order (a fixed order, so results are reproducible).
 constexpr int kRedRows = 32, kRedGroups = 8;
 
-__global__ __launch_bounds__(kRedRows * kRedGroups) void hh_reduce_panel(
-    const double2* __restrict__ part, int nslots, int c, int n, double2* __restrict__ ys, double2* __restrict__ cn,
-    const double2* __restrict__ P, int np, const double2* __restrict__ dpart, int nchunk) {
-    __shared__ double2 red[kRedGroups][kRedRows];
-    __shared__ double2 redc[kRedGroups][kRedRows];
-    __shared__ double2 dq[4][kPW];  // dot sums over chunks q = 4 u + quarter
-    __shared__ double2 dsum[kPW];   // v_j^H v at j, w_j^H v at kPanel + j
-    __shared__ double2 pc[kPW];     // v_j[c] at j, w_j[c] at kPanel + j
+template <typename T>
+__global__ __launch_bounds__(kRedRows * kRedGroups) void hh_reduce_panel(const T* __restrict__ part, int nslots,
+                                                                        int c, int n, T* __restrict__ ys,
+                                                                        T* __restrict__ cn, const T* __restrict__ P,
+                                                                        int np, const T* __restrict__ dpart,
+                                                                        int nchunk) {
+    __shared__ T red[kRedGroups][kRedRows];
+    __shared__ T redc[kRedGroups][kRedRows];
+    __shared__ T dq[4][kPW];  // dot sums over chunks q = 4 u + quarter
+    __shared__ T dsum[kPW];   // v_j^H v at j, w_j^H v at kPanel + j
+    __shared__ T pc[kPW];     // v_j[c] at j, w_j[c] at kPanel + j
     const int tid = int(threadIdx.x), r = tid % kRedRows, g = tid / kRedRows;
+    const T zero = mk<T>(0.0, 0.0);
     if (np > 0) {
         // thread (quarter u, column m) sums chunks u, u + 4, ...; the quarters are then added in order
         const int m = tid % kPW, u = tid / kPW;
-        double2 a = make_double2(0.0, 0.0);
+        T a = zero;
         if ((m % kPanel) < np) {
 #pragma unroll 4
-            for (int q = u; q < nchunk; q += 4) {
-                const double2 p = dpart[int64_t(q) * kPW + m];
-                a.x += p.x;
-                a.y += p.y;
-            }
+            for (int q = u; q < nchunk; q += 4) a = add(a, dpart[int64_t(q) * kPW + m]);
             if (u == 0) pc[m] = P[int64_t(m) * n + c];
         }
         dq[u][m] = a;
         __syncthreads();
         if (tid < kPW) {
-            double2 t4 = dq[0][tid];
-            for (int q = 1; q < 4; ++q) {
-                t4.x += dq[q][tid].x;
-                t4.y += dq[q][tid].y;
-            }
+            T t4 = dq[0][tid];
+            for (int q = 1; q < 4; ++q) t4 = add(t4, dq[q][tid]);
             dsum[tid] = t4;
         }
         __syncthreads();
     }
     const int i = c + int(blockIdx.x) * kRedRows + r;
-    double2 acc = make_double2(0.0, 0.0), cc = make_double2(0.0, 0.0);
+    T acc = zero, cc = zero;
     if (i < n) {
 #pragma unroll 4
-        for (int b = g; b < nslots; b += kRedGroups) {
-            const double2 p = part[int64_t(b) * n + i];
-            acc.x += p.x;
-            acc.y += p.y;
-        }
+        for (int b = g; b < nslots; b += kRedGroups) acc = add(acc, part[int64_t(b) * n + i]);
 #pragma unroll 2
         for (int jj = g; jj < np; jj += kRedGroups) {
-            const double2 vj = P[int64_t(jj) * n + i], wj = P[int64_t(kPanel + jj) * n + i];
-            const double2 a1 = cmulc(vj, dsum[kPanel + jj]), a2 = cmulc(wj, dsum[jj]);
-            acc.x -= a1.x + a2.x;
-            acc.y -= a1.y + a2.y;
-            const double2 c1 = cmulc(vj, conjd(pc[kPanel + jj])), c2 = cmulc(wj, conjd(pc[jj]));
-            cc.x += c1.x + c2.x;
-            cc.y += c1.y + c2.y;
+            const T vj = P[int64_t(jj) * n + i], wj = P[int64_t(kPanel + jj) * n + i];
+            acc = sub(acc, add(mul(vj, dsum[kPanel + jj]), mul(wj, dsum[jj])));
+            cc = add(cc, add(mul(vj, cj(pc[kPanel + jj])), mul(wj, cj(pc[jj]))));
         }
     }
     red[g][r] = acc;
     redc[g][r] = cc;
     __syncthreads();
     if (g == 0 && i < n) {
-        double2 sum = red[0][r], csum = redc[0][r];
+        T sum = red[0][r], csum = redc[0][r];
 #pragma unroll
         for (int q = 1; q < kRedGroups; ++q) {
-            sum.x += red[q][r].x;
-            sum.y += red[q][r].y;
-            csum.x += redc[q][r].x;
-            csum.y += redc[q][r].y;
+            sum = add(sum, red[q][r]);
+            csum = add(csum, redc[q][r]);
         }
         ys[i] = sum;
-        if (np > 0) {
-            double2 a = cn[i];
-            a.x -= csum.x;
-            a.y -= csum.y;
-            cn[i] = a;
-        }
+        if (np > 0) cn[i] = sub(cn[i], csum);
     }
 }
 
@@ -379,140 +420,123 @@ __global__ __launch_bounds__(kRedRows * kRedGroups) void hh_reduce_panel(
 // builds the first Householder vector from column 0.
 constexpr int kStepThreads = 1024;
 
-__device__ double block_reduce(double v, double* lds) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// sum over the workgroup, in a fixed order
+template <typename T>
+__device__ T block_sum(T v, T* lds) {
+    for (int off = 32; off > 0; off >>= 1) v = add(v, shfl_dn(v, off));
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) lds[wv] = v;
     __syncthreads();
-    double s = 0.0;
-    for (int i = 0; i < kStepThreads / 64; ++i) s += lds[i];
+    T s = lds[0];
+    for (int i = 1; i < kStepThreads / 64; ++i) s = add(s, lds[i]);
     __syncthreads();
     return s;
 }
 
-// the same for a complex value: both parts reduced together, in a fixed order
-__device__ double2 block_reduce2(double2 v, double2* lds) {
-    for (int off = 32; off > 0; off >>= 1) {
-        v.x += __shfl_down(v.x, off, 64);
-        v.y += __shfl_down(v.y, off, 64);
+// The reflector that zeroes a column below its first entry al, given nx = the squared norm of the
+// rest: beta = -sign(Re al) |column|, tau = (beta - al) / beta, and inv = 1 / (al - beta), the
+// scale of the rest of the vector (H = I when the rest is zero and al is real).
+template <typename T>
+__device__ __forceinline__ void reflector(T al, double nx, T* tau, double* beta, T* inv) {
+    *tau = mk<T>(0.0, 0.0);
+    *inv = mk<T>(0.0, 0.0);
+    if (nx == 0.0 && im(al) == 0.0) {
+        *beta = re(al);
+        return;
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) lds[wv] = v;
-    __syncthreads();
-    double2 s = make_double2(0.0, 0.0);
-    for (int i = 0; i < kStepThreads / 64; ++i) {
-        s.x += lds[i].x;
-        s.y += lds[i].y;
-    }
-    __syncthreads();
-    return s;
+    const double nrm = sqrt(abs2(al) + nx);
+    const double b = re(al) >= 0.0 ? -nrm : nrm;
+    *beta = b;
+    *tau = mk<T>((b - re(al)) / b, -im(al) / b);
+    const T den = mk<T>(re(al) - b, im(al));
+    const double dd = abs2(den);
+    *inv = mk<T>(re(den) / dd, -im(den) / dd);
 }
 
 // cin: column k+1 of the trailing matrix before the step's own update, contiguous (rows >= k+1),
 // or null to read it from the matrix (k = -1). Every thread keeps the same rows
 // i = k+1+t, k+1+t+1024, ... through the passes, so a value it wrote is read back by the same thread.
-__global__ __launch_bounds__(kStepThreads) void hh_step(const double2* __restrict__ A, int n, int k,
-                                                        double2* __restrict__ v, double2* __restrict__ y,
-                                                        double2* __restrict__ vn, double2* __restrict__ ys,
+template <typename T>
+__global__ __launch_bounds__(kStepThreads) void hh_step(const T* __restrict__ A, int n, int k, T* __restrict__ v,
+                                                        T* __restrict__ y, T* __restrict__ vn, T* __restrict__ ys,
                                                         double* __restrict__ d, double* __restrict__ e,
-                                                        double2* __restrict__ sc, const double2* __restrict__ cin,
-                                                        double2* __restrict__ pv, double2* __restrict__ pw) {
-    double2* const col = ys;  // column c of the trailing matrix after this step's update
+                                                        T* __restrict__ sc, const T* __restrict__ cin,
+                                                        T* __restrict__ pv, T* __restrict__ pw) {
+    T* const col = ys;  // column c of the trailing matrix after this step's update
     __shared__ double lds[kStepThreads / 64];
-    __shared__ double2 lds2[kStepThreads / 64];
-    __shared__ double2 syc;
+    __shared__ T lds2[kStepThreads / 64];
+    __shared__ T syc;
     const int t = threadIdx.x;
     const int c = k + 1;  // column of the trailing matrix to finish now
     double nx = 0.0;      // |column c|^2 over rows c+2..n-1
     if (k >= 0) {
-        const double2 tau = sc[0];
+        const T tau = sc[0];
         // y_i = tau * (A v)_i, i = k+1..n-1; also y^H v
-        double2 yhv = make_double2(0.0, 0.0);
+        T yhv = mk<T>(0.0, 0.0);
         for (int i = c + t; i < n; i += kStepThreads) {
-            const double2 yi = cmulc(tau, ys[i]);
+            const T yi = mul(tau, ys[i]);
             y[i] = yi;
             if (i == c) syc = yi;
-            const double2 vi = v[i];
-            // y^H v = sum conj(y_i) v_i
-            yhv.x += yi.x * vi.x + yi.y * vi.y;
-            yhv.y += yi.x * vi.y - yi.y * vi.x;
+            yhv = add(yhv, mul(cj(yi), v[i]));
         }
-        yhv = block_reduce2(yhv, lds2);
+        yhv = block_sum(yhv, lds2);
         // alpha = -1/2 tau (y^H v); w = y + alpha v
-        const double2 tt = cmulc(tau, yhv);
-        const double2 alpha = make_double2(-0.5 * tt.x, -0.5 * tt.y);
-        const double2 vc = v[c], avc = cmulc(alpha, vc);
-        const double2 wc = make_double2(syc.x + avc.x, syc.y + avc.y);
+        const T alpha = scale(mul(tau, yhv), -0.5);
+        const T vc = v[c];
+        const T wc = add(syc, mul(alpha, vc));
         // w, and the update of column c (rows c..n-1): A[i][c] -= v_i conj(w_c) + w_i conj(v_c).
         // Column c is finished by this step (later steps take rows and columns > c), so the
         // updated column goes to col = ys (free once y is formed) instead of back into A
         for (int i = c + t; i < n; i += kStepThreads) {
-            const double2 vi = v[i], yi = y[i];
-            const double2 av = cmulc(alpha, vi);
-            const double2 wi = make_double2(yi.x + av.x, yi.y + av.y);
+            const T vi = v[i];
+            const T wi = add(y[i], mul(alpha, vi));
             y[i] = wi;
             pv[i] = vi;
             pw[i] = wi;
-            double2 a = cin[i];
-            const double2 t1 = cmulc(vi, conjd(wc)), t2 = cmulc(wi, conjd(vc));
-            a.x -= t1.x + t2.x;
-            a.y -= t1.y + t2.y;
+            const T a = sub(cin[i], add(mul(vi, cj(wc)), mul(wi, cj(vc))));
             col[i] = a;
-            if (i >= c + 2) nx += a.x * a.x + a.y * a.y;
+            if (i >= c + 2) nx += abs2(a);
         }
     } else {
         for (int i = c + t; i < n; i += kStepThreads) {
-            const double2 a = A[int64_t(i) * n + c];
+            const T a = A[int64_t(i) * n + c];
             col[i] = a;
-            if (i >= c + 2) nx += a.x * a.x + a.y * a.y;
+            if (i >= c + 2) nx += abs2(a);
         }
     }
-    nx = block_reduce(nx, lds);  // its barriers also publish col
+    nx = block_sum(nx, lds);  // its barriers also publish col
     // diagonal of row c and Householder vector of column c below the diagonal (rows c+1..)
-    if (t == 0) d[c] = col[c].x;
+    if (t == 0) d[c] = re(col[c]);
     if (c + 1 >= n) return;
-    const double2 al = col[c + 1];
-    double2 tau = make_double2(0.0, 0.0);
+    T tau, inv;
     double beta;
-    double2 inv = make_double2(0.0, 0.0);
-    if (nx == 0.0 && al.y == 0.0) {
-        beta = al.x;  // H = I
-    } else {
-        const double nrm = sqrt(al.x * al.x + al.y * al.y + nx);
-        beta = al.x >= 0.0 ? -nrm : nrm;
-        tau = make_double2((beta - al.x) / beta, -al.y / beta);
-        // 1 / (alpha - beta)
-        const double2 den = make_double2(al.x - beta, al.y);
-        const double dd = den.x * den.x + den.y * den.y;
-        inv = make_double2(den.x / dd, -den.y / dd);
-    }
+    reflector(col[c + 1], nx, &tau, &beta, &inv);
     if (t == 0) {
         e[c] = fabs(beta);
         sc[0] = tau;
-        vn[c + 1] = make_double2(1.0, 0.0);
+        vn[c + 1] = mk<T>(1.0, 0.0);
     }
-    for (int i = c + 2 + t; i < n; i += kStepThreads) vn[i] = cmulc(col[i], inv);
+    for (int i = c + 2 + t; i < n; i += kStepThreads) vn[i] = mul(col[i], inv);
 }
 
 // The step kernel for k >= 0 with every row of the column held in registers (thread t owns rows
 // c + t + 1024 q, q < RPT, as in hh_step): ys, v and the column are read once, and only the panel
 // columns and the next Householder vector are written. Covers n - k - 1 <= 1024 RPT rows.
-template <int RPT>
-__global__ __launch_bounds__(kStepThreads) void hh_step_reg(int n, int k, const double2* __restrict__ v,
-                                                            double2* __restrict__ vn, const double2* __restrict__ ys,
-                                                            double* __restrict__ d, double* __restrict__ e,
-                                                            double2* __restrict__ sc, const double2* __restrict__ cin,
-                                                            double2* __restrict__ pv, double2* __restrict__ pw) {
+template <typename T, int RPT>
+__global__ __launch_bounds__(kStepThreads) void hh_step_reg(int n, int k, const T* __restrict__ v, T* __restrict__ vn,
+                                                            const T* __restrict__ ys, double* __restrict__ d,
+                                                            double* __restrict__ e, T* __restrict__ sc,
+                                                            const T* __restrict__ cin, T* __restrict__ pv,
+                                                            T* __restrict__ pw) {
     __shared__ double lds[kStepThreads / 64];
-    __shared__ double2 lds2[kStepThreads / 64];
-    __shared__ double2 sh_yc, sh_vc, sh_col[2];
+    __shared__ T lds2[kStepThreads / 64];
+    __shared__ T sh_yc, sh_vc, sh_col[2];
     const int t = threadIdx.x;
     const int c = k + 1;
-    const double2 tau = sc[0];
-    const double2 zero = make_double2(0.0, 0.0);
-    double2 yv[RPT], vv[RPT], cv[RPT];
+    const T tau = sc[0];
+    const T zero = mk<T>(0.0, 0.0);
+    T yv[RPT], vv[RPT], cv[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int i = c + t + kStepThreads * q;
@@ -526,65 +550,49 @@ __global__ __launch_bounds__(kStepThreads) void hh_step_reg(int n, int k, const 
         }
     }
     // y = tau (A v) and y^H v
-    double2 yhv = zero;
+    T yhv = zero;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        yv[q] = cmulc(tau, yv[q]);
-        yhv.x += yv[q].x * vv[q].x + yv[q].y * vv[q].y;
-        yhv.y += yv[q].x * vv[q].y - yv[q].y * vv[q].x;
+        yv[q] = mul(tau, yv[q]);
+        yhv = add(yhv, mul(cj(yv[q]), vv[q]));
     }
     if (t == 0) {  // row c
         sh_yc = yv[0];
         sh_vc = vv[0];
     }
-    yhv = block_reduce2(yhv, lds2);  // its barriers also publish sh_yc, sh_vc
-    const double2 tt = cmulc(tau, yhv);
-    const double2 alpha = make_double2(-0.5 * tt.x, -0.5 * tt.y);
-    const double2 vc = sh_vc, avc = cmulc(alpha, vc);
-    const double2 wc = make_double2(sh_yc.x + avc.x, sh_yc.y + avc.y);
+    yhv = block_sum(yhv, lds2);  // its barriers also publish sh_yc, sh_vc
+    const T alpha = scale(mul(tau, yhv), -0.5);
+    const T vc = sh_vc;
+    const T wc = add(sh_yc, mul(alpha, vc));
     // w = y + alpha v to the panel with v; column c finished with the step's own rank-2 term
     double nx = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int i = c + t + kStepThreads * q;
         if (i < n) {
-            const double2 av = cmulc(alpha, vv[q]);
-            const double2 wi = make_double2(yv[q].x + av.x, yv[q].y + av.y);
+            const T wi = add(yv[q], mul(alpha, vv[q]));
             pv[i] = vv[q];
             pw[i] = wi;
-            const double2 t1 = cmulc(vv[q], conjd(wc)), t2 = cmulc(wi, conjd(vc));
-            cv[q].x -= t1.x + t2.x;
-            cv[q].y -= t1.y + t2.y;
-            if (i >= c + 2) nx += cv[q].x * cv[q].x + cv[q].y * cv[q].y;
+            cv[q] = sub(cv[q], add(mul(vv[q], cj(wc)), mul(wi, cj(vc))));
+            if (i >= c + 2) nx += abs2(cv[q]);
         }
     }
     if (t < 2) sh_col[t] = cv[0];  // rows c and c + 1
-    nx = block_reduce(nx, lds);    // its barriers also publish sh_col
-    if (t == 0) d[c] = sh_col[0].x;
+    nx = block_sum(nx, lds);       // its barriers also publish sh_col
+    if (t == 0) d[c] = re(sh_col[0]);
     if (c + 1 >= n) return;
-    const double2 al = sh_col[1];
-    double2 tau_n = zero;
+    T tau_n, inv;
     double beta;
-    double2 inv = zero;
-    if (nx == 0.0 && al.y == 0.0) {
-        beta = al.x;  // H = I
-    } else {
-        const double nrm = sqrt(al.x * al.x + al.y * al.y + nx);
-        beta = al.x >= 0.0 ? -nrm : nrm;
-        tau_n = make_double2((beta - al.x) / beta, -al.y / beta);
-        const double2 den = make_double2(al.x - beta, al.y);
-        const double dd = den.x * den.x + den.y * den.y;
-        inv = make_double2(den.x / dd, -den.y / dd);
-    }
+    reflector(sh_col[1], nx, &tau_n, &beta, &inv);
     if (t == 0) {
         e[c] = fabs(beta);
         sc[0] = tau_n;
-        vn[c + 1] = make_double2(1.0, 0.0);
+        vn[c + 1] = mk<T>(1.0, 0.0);
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int i = c + t + kStepThreads * q;
-        if (i >= c + 2 && i < n) vn[i] = cmulc(cv[q], inv);
+        if (i >= c + 2 && i < n) vn[i] = mul(cv[q], inv);
     }
 }
 constexpr int kStepRegRows = 8;  // rows per thread of hh_step_reg
@@ -594,9 +602,11 @@ constexpr int kStepRegRows = 8;  // rows per thread of hh_step_reg
 // is sum_j (v_j w_j^H + w_j v_j^H) over the np pairs in use. 64 x 64 tiles (I >= J) of the
 // trailing block, 4 waves of 2 x 2 FP64 MFMA tiles each (the Gram kernel's layout), the 2 kPanel
 // panel columns through LDS 16 at a time.
-__global__ __launch_bounds__(256) void hh_flush(double2* __restrict__ A, int n, int s, const double2* __restrict__ P,
-                                                int np) {
-    __shared__ double Ar[kGB][kGK + 1], Ai[kGB][kGK + 1], Br[kGB][kGK + 1], Bi[kGB][kGK + 1];
+template <typename T>
+__global__ __launch_bounds__(256) void hh_flush(T* __restrict__ A, int n, int s, const T* __restrict__ P, int np) {
+    constexpr bool CX = kCx<T>;
+    constexpr int kIm = CX ? kGB : 1;
+    __shared__ double Ar[kGB][kGK + 1], Br[kGB][kGK + 1], Ai[kIm][kGK + 1], Bi[kIm][kGK + 1];
     int b = blockIdx.x, I = 0;
     while (b > I) {
         b -= I + 1;
@@ -621,37 +631,51 @@ __global__ __launch_bounds__(256) void hh_flush(double2* __restrict__ A, int n, 
             const int rr = idx % kGB, kk = idx / kGB;
             const int m = k0 + kk;
             const int mz = (m + kPanel) % kPW;
-            double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+            T va = mk<T>(0.0, 0.0), vb = mk<T>(0.0, 0.0);
             if ((m % kPanel) < np) {
                 if (r0 + rr < n) va = P[int64_t(m) * n + r0 + rr];
                 if (c0 + rr < n) vb = P[int64_t(mz) * n + c0 + rr];
             }
-            Ar[rr][kk] = va.x;
-            Ai[rr][kk] = va.y;
-            Br[rr][kk] = vb.x;
-            Bi[rr][kk] = vb.y;
+            Ar[rr][kk] = re(va);
+            Br[rr][kk] = re(vb);
+            if constexpr (CX) {
+                Ai[rr][kk] = im(va);
+                Bi[rr][kk] = im(vb);
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 4) {
             const int ka = kk + (lane >> 4), ra = lane & 15;
-            double ar[2], ai[2], br[2], bi[2];
+            double ar[2], br[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 ar[i] = Ar[wr + 16 * i + ra][ka];
-                ai[i] = Ai[wr + 16 * i + ra][ka];
                 br[i] = Br[wc + 16 * i + ra][ka];
-                bi[i] = Bi[wc + 16 * i + ra][ka];
             }
+            if constexpr (CX) {
+                double ai[2], bi[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], accr[i][j], 0, 0, 0);
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[i], bi[j], acci[i][j], 0, 0, 0);
+                for (int i = 0; i < 2; ++i) {
+                    ai[i] = Ai[wr + 16 * i + ra][ka];
+                    bi[i] = Bi[wc + 16 * i + ra][ka];
                 }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], accr[i][j], 0, 0, 0);
+                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
+                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[i], bi[j], acci[i][j], 0, 0, 0);
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -664,12 +688,9 @@ __global__ __launch_bounds__(256) void hh_flush(double2* __restrict__ A, int n, 
             for (int q = 0; q < 4; ++q) {
                 const int row = r0 + wr + 16 * i + (lane >> 4) + 4 * q;
                 const int col = c0 + wc + 16 * j + (lane & 15);
-                if (row < n && col <= row) {
-                    double2 a = A[int64_t(row) * n + col];
-                    a.x -= accr[i][j][q];
-                    a.y -= acci[i][j][q];
-                    A[int64_t(row) * n + col] = a;
-                }
+                if (row < n && col <= row)
+                    A[int64_t(row) * n + col] =
+                        sub(A[int64_t(row) * n + col], mk<T>(accr[i][j][q], acci[i][j][q]));
             }
 }
 
@@ -773,19 +794,22 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect(const double* __restri
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// The workspace areas, sized for complex entries; the real path uses the first half of each.
+template <typename T>
 struct EntWS {
-    double2* rho;
-    double2* v;
-    double2* y;
-    double2* vn;
-    double2* ys;
-    double2* cn;  // the step's column of the trailing matrix, contiguous
-    double2* part;
-    double2* dpart;
-    double2* panel;
+    T* rho;
+    T* v;
+    T* y;
+    T* vn;
+    T* ys;
+    T* cn;  // the step's column of the trailing matrix, contiguous
+    T* part;
+    T* dpart;
+    T* panel;
     double* d;
     double* e;
-    double2* sc;
+    T* sc;
+    int* flag;  // imaginary parts seen
 };
 
 // partial-sum slots of the sweep (its block count), at least 2 (the bisection reuses the area for
@@ -800,33 +824,94 @@ size_t entropy_bytes(int n) {
            2 * align256(size_t(n) * sizeof(double)) + align256(4 * sizeof(double2));
 }
 
-EntWS carve_ent(void* ws, int n) {
+template <typename T>
+EntWS<T> carve_ent(void* ws, int n) {
     char* p = static_cast<char*>(ws);
-    EntWS w;
-    w.rho = reinterpret_cast<double2*>(p);
-    p += align256(size_t(n) * n * sizeof(double2));
-    w.v = reinterpret_cast<double2*>(p);
-    p += align256(size_t(n) * sizeof(double2));
-    w.y = reinterpret_cast<double2*>(p);
-    p += align256(size_t(n) * sizeof(double2));
-    w.vn = reinterpret_cast<double2*>(p);
-    p += align256(size_t(n) * sizeof(double2));
-    w.ys = reinterpret_cast<double2*>(p);
-    p += align256(size_t(n) * sizeof(double2));
-    w.cn = reinterpret_cast<double2*>(p);
-    p += align256(size_t(n) * sizeof(double2));
-    w.part = reinterpret_cast<double2*>(p);
-    p += align256(size_t(part_slots(n)) * n * sizeof(double2));
-    w.dpart = reinterpret_cast<double2*>(p);
-    p += align256(size_t(dot_chunks(n)) * kPW * sizeof(double2));
-    w.panel = reinterpret_cast<double2*>(p);
-    p += align256(size_t(kPW) * n * sizeof(double2));
-    w.d = reinterpret_cast<double*>(p);
-    p += align256(size_t(n) * sizeof(double));
-    w.e = reinterpret_cast<double*>(p);
-    p += align256(size_t(n) * sizeof(double));
-    w.sc = reinterpret_cast<double2*>(p);
+    auto take = [&](size_t bytes) {
+        char* q = p;
+        p += align256(bytes);
+        return q;
+    };
+    EntWS<T> w;
+    w.rho = reinterpret_cast<T*>(take(size_t(n) * n * sizeof(double2)));
+    w.v = reinterpret_cast<T*>(take(size_t(n) * sizeof(double2)));
+    w.y = reinterpret_cast<T*>(take(size_t(n) * sizeof(double2)));
+    w.vn = reinterpret_cast<T*>(take(size_t(n) * sizeof(double2)));
+    w.ys = reinterpret_cast<T*>(take(size_t(n) * sizeof(double2)));
+    w.cn = reinterpret_cast<T*>(take(size_t(n) * sizeof(double2)));
+    w.part = reinterpret_cast<T*>(take(size_t(part_slots(n)) * n * sizeof(double2)));
+    w.dpart = reinterpret_cast<T*>(take(size_t(dot_chunks(n)) * kPW * sizeof(double2)));
+    w.panel = reinterpret_cast<T*>(take(size_t(kPW) * n * sizeof(double2)));
+    w.d = reinterpret_cast<double*>(take(size_t(n) * sizeof(double)));
+    w.e = reinterpret_cast<double*>(take(size_t(n) * sizeof(double)));
+    char* sc = take(4 * sizeof(double2));
+    w.sc = reinterpret_cast<T*>(sc);  // sc[0] = tau
+    w.flag = reinterpret_cast<int*>(sc + 2 * sizeof(double2));
     return w;
+}
+
+// Steps 1 and 2 in arithmetic T: the Gram matrix of R (n x K, R = M when left_small, else M^T)
+// and its reduction to the tridiagonal (w.d, w.e), all on stream s.
+template <typename T>
+ed_status gram_tridiagonal(const EntWS<T>& w0, const double2* p, bool left_small, int n, int64_t K, hipStream_t s) {
+    EntWS<T> w = w0;
+    // 1. Gram matrix on the matrix cores
+    const int nb = (n + kGB - 1) / kGB;
+    const int nblocks = nb * (nb + 1) / 2;
+    if (left_small)  // R = M: row a of M is psi[a*K .. a*K+K)
+        hipLaunchKernelGGL((gram_mfma<true, T>), dim3(nblocks), dim3(256), 0, s, p, K, int64_t(1), n, K, w.rho);
+    else  // R = M^T: R[b][a] = psi[a*n + b] with n = 2^(L-l) columns of M
+        hipLaunchKernelGGL((gram_mfma<false, T>), dim3(nblocks), dim3(256), 0, s, p, int64_t(1), int64_t(n), n, K,
+                           w.rho);
+    ED_HIP_TRY(hipGetLastError());
+    if (n < 2) return ED_OK;
+    // 2. Householder tridiagonalisation
+    ED_HIP_TRY(hipMemsetAsync(w.v, 0, size_t(n) * sizeof(T), s));
+    ED_HIP_TRY(hipMemsetAsync(w.y, 0, size_t(n) * sizeof(T), s));
+    ED_HIP_TRY(hipMemsetAsync(w.vn, 0, size_t(n) * sizeof(T), s));
+    ED_HIP_TRY(hipMemsetAsync(w.ys, 0, size_t(n) * sizeof(T), s));
+    // first Householder vector from column 0
+    hipLaunchKernelGGL(hh_step<T>, dim3(1), dim3(kStepThreads), 0, s, static_cast<const T*>(w.rho), n, -1, w.v, w.y,
+                       w.vn, w.ys, w.d, w.e, w.sc, static_cast<const T*>(nullptr), static_cast<T*>(nullptr),
+                       static_cast<T*>(nullptr));
+    int np = 0;  // pending pairs in the panel
+    for (int k = 0; k + 1 < n; ++k) {
+        // the current vector (rows >= k+1) becomes v; the trailing block is rows/cols >= k+1
+        std::swap(w.v, w.vn);
+        const int s0 = k + 1;
+        const int r = n - s0;
+        const int nbs = (r + kSB - 1) / kSB;
+        const int nchunk = np > 0 ? (r + kDotRows - 1) / kDotRows : 0;
+        const int ndot = 2 * nchunk;
+        T* const pv = w.panel + size_t(np) * n;
+        T* const pw = w.panel + size_t(kPanel + np) * n;
+        // A_s v (read-only sweep of the lower triangle), column k+1 of A_s, panel dots
+        hipLaunchKernelGGL(hh_sweep<T>, dim3(ndot + nbs * (nbs + 1) / 2), dim3(256), 0, s,
+                           static_cast<const T*>(w.rho), n, s0, static_cast<const T*>(w.v), w.part, w.cn,
+                           static_cast<const T*>(w.panel), np, ndot, w.dpart);
+        // A v and column k+1 of the trailing matrix, with the panel's share
+        hipLaunchKernelGGL(hh_reduce_panel<T>, dim3((r + kRedRows - 1) / kRedRows), dim3(kRedRows * kRedGroups), 0, s,
+                           static_cast<const T*>(w.part), nbs, s0, n, w.ys, w.cn, static_cast<const T*>(w.panel), np,
+                           static_cast<const T*>(w.dpart), nchunk);
+        // step kernel: y, w, column k+1 finished, next Householder vector into vn; (v, w) to the panel
+        if (r <= kStepThreads * kStepRegRows)
+            hipLaunchKernelGGL((hh_step_reg<T, kStepRegRows>), dim3(1), dim3(kStepThreads), 0, s, n, k,
+                               static_cast<const T*>(w.v), w.vn, static_cast<const T*>(w.ys), w.d, w.e, w.sc,
+                               static_cast<const T*>(w.cn), pv, pw);
+        else
+            hipLaunchKernelGGL(hh_step<T>, dim3(1), dim3(kStepThreads), 0, s, static_cast<const T*>(w.rho), n, k, w.v,
+                               w.y, w.vn, w.ys, w.d, w.e, w.sc, static_cast<const T*>(w.cn), pv, pw);
+        ++np;
+        if (np == kPanel && k + 2 < n) {
+            // fold the panel into the lower triangle of rows/cols >= k+2
+            const int nbf = (n - (k + 2) + kGB - 1) / kGB;
+            hipLaunchKernelGGL(hh_flush<T>, dim3(nbf * (nbf + 1) / 2), dim3(256), 0, s, w.rho, n, k + 2,
+                               static_cast<const T*>(w.panel), np);
+            np = 0;
+        }
+        ED_HIP_TRY(hipGetLastError());
+    }
+    return ED_OK;
 }
 
 }  // namespace
@@ -843,7 +928,7 @@ extern "C" ed_status ed_entropy_workspace(int L, int l_cut, size_t* bytes) {
 }
 
 extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum,
-                                void* ws, size_t ws_bytes, void* stream) {
+                                int* real_arith, void* ws, size_t ws_bytes, void* stream) {
     if (!psi || !S) return fail(ED_ERR_ARG, "null argument");
     if (d != 2) return fail(ED_ERR_UNSUPPORTED, "only d = 2 is supported");
     size_t need = 0;
@@ -855,79 +940,35 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
     const int ls = left_small ? l_cut : L - l_cut;
     const int n = 1 << ls;
     const int64_t K = int64_t(1) << (L - ls);
-    EntWS w = carve_ent(ws, n);
+    const int64_t D = int64_t(1) << L;
     const double2* p = reinterpret_cast<const double2*>(psi);
-    // 1. Gram matrix on the matrix cores
-    const int nb = (n + kGB - 1) / kGB;
-    const int nblocks = nb * (nb + 1) / 2;
-    if (left_small) {
-        // R = M: row a of M is psi[a*K .. a*K+K)
-        hipLaunchKernelGGL((gram_mfma<true>), dim3(nblocks), dim3(256), 0, s, p, K, int64_t(1), n, K, w.rho, nb);
-    } else {
-        // R = M^T: R[b][a] = psi[a*n + b] with n = 2^(L-l) columns of M
-        hipLaunchKernelGGL((gram_mfma<false>), dim3(nblocks), dim3(256), 0, s, p, int64_t(1), int64_t(n), n, K, w.rho, nb);
-    }
+    // real or complex arithmetic: does any amplitude have a nonzero imaginary part?
+    const EntWS<double2> wc = carve_ent<double2>(ws, n);
+    ED_HIP_TRY(hipMemsetAsync(wc.flag, 0, sizeof(int), s));
+    hipLaunchKernelGGL(imag_any, dim3(unsigned(std::min<int64_t>((D + 255) / 256, 2048))), dim3(256), 0, s, p, D,
+                       wc.flag);
     ED_HIP_TRY(hipGetLastError());
-    // 2. Householder tridiagonalisation
-    ED_HIP_TRY(hipMemsetAsync(w.v, 0, size_t(n) * sizeof(double2), s));
-    ED_HIP_TRY(hipMemsetAsync(w.y, 0, size_t(n) * sizeof(double2), s));
-    ED_HIP_TRY(hipMemsetAsync(w.vn, 0, size_t(n) * sizeof(double2), s));
-    ED_HIP_TRY(hipMemsetAsync(w.ys, 0, size_t(n) * sizeof(double2), s));
-    if (n > 1) {
-        // first Householder vector from column 0
-        hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, -1, w.v, w.y, w.vn, w.ys, w.d,
-                           w.e, w.sc, static_cast<const double2*>(nullptr), static_cast<double2*>(nullptr),
-                           static_cast<double2*>(nullptr));
-        int np = 0;  // pending pairs in the panel
-        for (int k = 0; k + 1 < n; ++k) {
-            // the current vector (rows >= k+1) becomes v; the trailing block is rows/cols >= k+1
-            std::swap(w.v, w.vn);
-            const int s0 = k + 1;
-            const int r = n - s0;
-            const int nbs = (r + kSB - 1) / kSB;
-            const int nchunk = np > 0 ? (r + kDotRows - 1) / kDotRows : 0;
-            const int ndot = 2 * nchunk;
-            // A_s v (read-only sweep of the lower triangle), column k+1 of A_s, panel dots
-            hipLaunchKernelGGL(hh_sweep, dim3(ndot + nbs * (nbs + 1) / 2), dim3(256), 0, s, w.rho, n, s0, w.v, w.part,
-                               w.cn, w.panel, np, ndot, w.dpart);
-            // A v and column k+1 of the trailing matrix, with the panel's share
-            hipLaunchKernelGGL(hh_reduce_panel, dim3((r + kRedRows - 1) / kRedRows), dim3(kRedRows * kRedGroups), 0, s,
-                               w.part, nbs, s0, n, w.ys, w.cn, w.panel, np, w.dpart, nchunk);
-            // step kernel: y, w, column k+1 finished, next Householder vector into vn; (v, w) to the panel
-            if (r <= kStepThreads * kStepRegRows)
-                hipLaunchKernelGGL(hh_step_reg<kStepRegRows>, dim3(1), dim3(kStepThreads), 0, s, n, k,
-                                   static_cast<const double2*>(w.v), w.vn, static_cast<const double2*>(w.ys), w.d, w.e,
-                                   w.sc, static_cast<const double2*>(w.cn), w.panel + size_t(np) * n,
-                                   w.panel + size_t(kPanel + np) * n);
-            else
-                hipLaunchKernelGGL(hh_step, dim3(1), dim3(kStepThreads), 0, s, w.rho, n, k, w.v, w.y, w.vn, w.ys,
-                                   w.d, w.e, w.sc, static_cast<const double2*>(w.cn), w.panel + size_t(np) * n,
-                                   w.panel + size_t(kPanel + np) * n);
-            ++np;
-            if (np == kPanel && k + 2 < n) {
-                // fold the panel into the lower triangle of rows/cols >= k+2
-                const int nbf = (n - (k + 2) + kGB - 1) / kGB;
-                hipLaunchKernelGGL(hh_flush, dim3(nbf * (nbf + 1) / 2), dim3(256), 0, s, w.rho, n, k + 2, w.panel, np);
-                np = 0;
-            }
-            ED_HIP_TRY(hipGetLastError());
-        }
-    }
+    int cx = 1;
+    ED_HIP_TRY(hipMemcpyAsync(&cx, wc.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    ED_HIP_TRY(hipStreamSynchronize(s));
+    const bool real = cx == 0;
+    if (real_arith) *real_arith = real ? 1 : 0;
+    const EntWS<double> wr = carve_ent<double>(ws, n);
+    if (real) ED_TRY(gram_tridiagonal<double>(wr, p, left_small, n, K, s));
+    else ED_TRY(gram_tridiagonal<double2>(wc, p, left_small, n, K, s));
     // 3. eigenvalues of the tridiagonal matrix by bisection on the GPU (the partial-sum area is
     // free now: n eigenvalues, n squared off-diagonals, 4 bounds), sorted on the host
     std::vector<double> dd(n);
     if (n == 1) {
-        // rho is the 1x1 matrix |psi|^2
-        double2 r11;
-        ED_HIP_TRY(hipMemcpyAsync(&r11, w.rho, sizeof(double2), hipMemcpyDeviceToHost, s));
+        // rho is the 1x1 matrix |psi|^2, its real part first in either arithmetic
+        ED_HIP_TRY(hipMemcpyAsync(dd.data(), wr.rho, sizeof(double), hipMemcpyDeviceToHost, s));
         ED_HIP_TRY(hipStreamSynchronize(s));
-        dd[0] = r11.x;
     } else {
-        double* lam = reinterpret_cast<double*>(w.part);
+        double* lam = wr.part;
         double* e2 = lam + n;
         double* bnd = e2 + n;
-        hipLaunchKernelGGL(tri_bounds, dim3(1), dim3(kBndThreads), 0, s, w.d, w.e, n, e2, bnd);
-        hipLaunchKernelGGL(tri_bisect, dim3((n * kMS + kBisThreads - 1) / kBisThreads), dim3(kBisThreads), 0, s, w.d,
+        hipLaunchKernelGGL(tri_bounds, dim3(1), dim3(kBndThreads), 0, s, wr.d, wr.e, n, e2, bnd);
+        hipLaunchKernelGGL(tri_bisect, dim3((n * kMS + kBisThreads - 1) / kBisThreads), dim3(kBisThreads), 0, s, wr.d,
                            e2, n, bnd, lam);
         ED_HIP_TRY(hipGetLastError());
         ED_HIP_TRY(hipMemcpyAsync(dd.data(), lam, sizeof(double) * n, hipMemcpyDeviceToHost, s));

@@ -33,6 +33,37 @@ def test_entropy_random_states(L, l):
     assert np.max(np.abs(spec - ref)) < 1e-13
 
 
+@pytest.mark.parametrize("L,l", [(2, 1), (7, 3), (7, 5), (10, 5), (13, 4), (14, 7), (17, 9), (19, 6)])
+def test_entropy_real_states(L, l):
+    """A real state (every imaginary part exactly zero) takes the real-arithmetic reduction; the
+    same state times a global phase, and the state with one imaginary part of 1e-300, take the
+    complex one. Each against the oracle's SVD of that same state."""
+    print(f"entropy real L={L} l={l}", flush=True)
+    psi = E.random_state(L, 60 + L, normalise=False, real=True)
+    S, spec, inf = P.entropy(dev(psi), L, l, spectrum=True, info=True)
+    assert inf["real_arith"]
+    ref = OO.schmidt_spectrum(psi, L, l)
+    Sref = OO.bond_entropy(psi, L, l)
+    assert abs(S - Sref) <= 1e-10 * abs(Sref) + 1e-12
+    assert np.max(np.abs(spec - ref)) < 1e-13
+    ph = psi * np.exp(0.7j)
+    S2, spec2, inf2 = P.entropy(dev(ph), L, l, spectrum=True, info=True)
+    assert not inf2["real_arith"]
+    assert abs(S2 - OO.bond_entropy(ph, L, l)) <= 1e-10 * abs(Sref) + 1e-12
+    assert np.max(np.abs(spec2 - OO.schmidt_spectrum(ph, L, l))) < 1e-13
+    q = psi.copy()
+    q[-1] += 1e-300j
+    S3, inf3 = P.entropy(dev(q), L, l, info=True)
+    assert not inf3["real_arith"]
+    assert abs(S3 - Sref) <= 1e-10 * abs(Sref) + 1e-12
+
+
+def test_entropy_complex_state_flag():
+    L = 10
+    S, inf = P.entropy(dev(E.random_state(L, 5)), L, 5, info=True)
+    assert not inf["real_arith"] and S > 0
+
+
 def test_entropy_special_states():
     L = 12
     S = P.entropy(dev(E.product_state(L, 1234)), L, 6)
@@ -62,21 +93,24 @@ def _host_threads():
     return max(1, min(16, os.cpu_count() or 1))
 
 
-@pytest.mark.parametrize("kind", ["random", "graded"])
+@pytest.mark.parametrize("kind", ["random", "graded", "random_real", "graded_real"])
 def test_entropy_half_cut_n4096(kind):
     """The half cut at L = 24 (M is 4096 x 4096, the size class of the L = 26 workload's 8192):
     a complex-normal state (flat, Page-like spectrum) and a state whose Schmidt spectrum falls off
-    geometrically over 40 decades with 3584 exact zeros (rank 512), against the oracle's SVD of
-    the same state. The Gram route resolves eigenvalues to about 1e-16 of the largest; those below
-    that floor add at most n 1e-16 |ln 1e-16| ~ 1.5e-11 to S, inside the 1e-10 relative bound."""
+    geometrically over 40 decades with 3584 exact zeros (rank 512), each complex and real (the
+    real-arithmetic reduction), against the oracle's SVD of the same state. The Gram route
+    resolves eigenvalues to about 1e-16 of the largest; those below that floor add at most
+    n 1e-16 |ln 1e-16| ~ 1.5e-11 to S, inside the 1e-10 relative bound."""
     from threadpoolctl import threadpool_limits
     L, l = 24, 12
     print(f"entropy L={L} l={l} {kind}", flush=True)
-    if kind == "random":
-        psi = E.random_state(L, 24)
+    real = kind.endswith("_real")
+    if kind.startswith("random"):
+        psi = E.random_state(L, 24, real=real)
     else:
-        psi = E.graded_schmidt_state(L, l, 512, 6.0, 25)
-    S, spec = P.entropy(dev(psi), L, l, spectrum=True)
+        psi = E.graded_schmidt_state(L, l, 512, 6.0, 25, real=real)
+    S, spec, inf = P.entropy(dev(psi), L, l, spectrum=True, info=True)
+    assert inf["real_arith"] == real
     print(f"  GPU S = {S!r}", flush=True)
     with threadpool_limits(limits=_host_threads()):
         ref = OO.schmidt_spectrum(psi, L, l)
