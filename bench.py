@@ -336,22 +336,24 @@ _SHARED = {}
 def row_trotter_L28(P, E, torch, dev, steps=100):
     """The L = 28 quench of the Krylov row with the Suzuki-Trotter propagators (Sec. ed:sec:trotter):
     orders 4 and 2, per-step time, the algorithmic bandwidth of the gate passes (each pass reads and
-    writes the state once: 32 B per amplitude; 3 passes per layer at L = 28) and the largest
-    difference of <sigma^z_k>(t) from the Krylov run when that row ran before."""
+    writes the state once: 32 B per amplitude; the library reports the passes of a step, runs of
+    three layers fused) and the largest difference of <sigma^z_k>(t) from the Krylov run when that
+    row ran before."""
     import numpy as np
     L, dt = 28, 0.05
     m = P.Model(E.tfim(L, 0.5))
     out = {"workload": f"TFIM g=0.5 L=28 quench from all up, dt=0.05, {steps} Trotter steps (order 4 and 2)"}
     layers = {4: 11, 2: 3}
-    passes_per_layer = 3
     for order in (4, 2):
+        npass = P.trotter_passes(m, order)
         psi = torch.zeros(1 << L, dtype=torch.complex128, device=dev)
         psi[0] = 1.0
         with Timer(torch, None) as t:
             _, obs = P.trotter_evolve(m, psi, dt, steps, order=order)
         per_step = t.s / steps
-        nbytes = layers[order] * passes_per_layer * 32.0 * (1 << L)
-        r = {"seconds": round(t.s, 3), "ms_per_step": round(1e3 * per_step, 2),
+        nbytes = npass * 32.0 * (1 << L)
+        r = {"seconds": round(t.s, 3), "ms_per_step": round(1e3 * per_step, 2), "layers": layers[order],
+             "passes_per_step": npass,
              "gate_pass_GBps": round(nbytes / per_step / 1e9, 1), "norm_drift": float(abs(obs["norm"] - 1).max()),
              "sz_final_site1": float(obs["sz"][-1, 0])}
         ref = _SHARED.get("quench28_sz")

@@ -274,12 +274,26 @@ ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double dt, int n_
  * obs     as for ed_krylov_evolve (host arrays of n_steps + 1 entries, each may be NULL);
  *         energy = <psi|H|psi>/<psi|psi> costs one H psi per record and needs the workspace of
  *         ed_trotter_workspace(model, with_energy = 1, ...).
+ * Workspace: ed_trotter_workspace bytes (scratch, two state vectors when with_energy = 1, and a
+ *         48 KiB table of the gate matrices, copied in at the start of the call).
  * Errors: ED_ERR_ARG (null model/psi/ws, order not 2 or 4, n_steps < 0, dt not finite),
  * ED_ERR_WORKSPACE. Synchronises stream.
  * ---------------------------------------------------------------------------------------- */
 ed_status ed_trotter_workspace(const ed_model* model, int with_energy, size_t* bytes);
 ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, double dt, int n_steps, int order,
                             const ed_observe* obs, void* ws, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * ed_trotter_passes: the number of in-place passes over the state that one ed_trotter_evolve
+ * step of the given order makes (Sec. ed:sec:trotter), each reading and writing the state once.
+ * The step's layers are applied in runs of three consecutive layers; a run streams the state
+ * through LDS tiles (the 12 low bits, then windows of 8 bits above 4 contiguous low bits) and a
+ * pass applies, layer by layer, every gate its tile holds whose earlier-layer neighbours are
+ * already applied. passes host. No device work.
+ * Errors: ED_ERR_ARG (null model/passes, order not 2 or 4), ED_ERR_UNSUPPORTED (long-range or
+ * Liouville models).
+ * ---------------------------------------------------------------------------------------- */
+ed_status ed_trotter_passes(const ed_model* model, int order, int* passes);
 
 /* ----------------------------------------------------------------------------------------
  * ed_measure: norm and all-site <sigma^z> of a state in one read pass (Sec. IV: the diagonal of

@@ -299,6 +299,13 @@ def trotter_evolve(model, psi, dt, n_steps, order=4, observe=True, energy=False,
     return psi, obs
 
 
+def trotter_passes(model, order=4):
+    """In-place passes over the state per Trotter step of the given order (ed_trotter_passes)."""
+    n = C.c_int()
+    call("ed_trotter_passes", model.handle, int(order), C.byref(n))
+    return n.value
+
+
 def measure(psi, L, stream=None):
     """(sz[L], norm) of a device state in one pass (ed_measure)."""
     _check_state(psi, 1 << L)

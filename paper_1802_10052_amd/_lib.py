@@ -141,6 +141,7 @@ def _declare(l):
                                 C.POINTER(KrylovInfo), P, C.c_size_t, P])
     _fn(l, "ed_trotter_workspace", [P, C.c_int, S])
     _fn(l, "ed_trotter_evolve", [P, P, C.c_double, C.c_int, C.c_int, C.POINTER(Observe), P, C.c_size_t, P])
+    _fn(l, "ed_trotter_passes", [P, C.c_int, C.POINTER(C.c_int)])
     _fn(l, "ed_measure_workspace", [C.c_int, S])
     _fn(l, "ed_entropy_workspace", [C.c_int, C.c_int, S])
     TD, TP, TO, TI = C.POINTER(TrajDesc), C.POINTER(TrajParams), C.POINTER(TrajOut), C.POINTER(TrajInfo)

@@ -5,12 +5,14 @@
 // k; each site's terms are shared by the bonds that contain it (1/2 each, 1 for a site in a single
 // bond). A layer exp(-i t H_o) (or H_e) is the product of the commuting two-site propagators
 // exp(-i t h_k); the paper contracts each with two legs of the rank-L state tensor (tensordot plus
-// a permutation). Here a layer streams the state through LDS tiles in a few in-place passes (the
-// 12 low bits, then windows of 8 high bits above 4 contiguous low bits, each starting at the first
-// bond of the layer not yet covered): every gate of the layer is applied in the first pass whose
-// tile holds both of its bits. Gates of one layer act on disjoint bits, so they commute and the order of the
-// passes is free; a tile is read completely before it is written, and tiles of a pass are
-// disjoint, so the passes work in place.
+// a permutation). Here runs of kFuse consecutive layers stream the state through LDS tiles in a
+// few in-place passes (the 12 low bits, then windows of 8 high bits above 4 contiguous low bits):
+// a pass applies its gates layer by layer, and each gate goes to the first pass whose tile holds
+// both of its bits and in which every gate of an earlier layer that shares one of its bits has
+// already been applied (in an earlier pass, or earlier in the same pass). Gates of one layer act
+// on disjoint bits and commute, so this keeps the order of the product wherever it matters; a
+// tile is read completely before it is written, and tiles of a pass are disjoint, so the passes
+// work in place.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -27,18 +29,22 @@ constexpr int kGThreads = 256;
 constexpr int kGTileBits = 12;
 constexpr int kGSlots = (1 << kGTileBits) / kGThreads;  // 16
 constexpr int kGLow = 4;                                 // contiguous low bits of a window tile
-constexpr int kMaxGates = kGTileBits / 2;                // gates of one parity inside a tile
+constexpr int kFuse = 3;                                 // consecutive layers per run of passes
+constexpr int kMaxGates = kFuse * (kGTileBits / 2);      // gates of one pass
+constexpr int kTableGates = 192;                         // gate matrices one evolve call holds
+constexpr size_t kGateTableBytes = size_t(kTableGates) * 16 * sizeof(double2);
 
-// One pass of one layer: tile geometry and the gates it applies. A gate on tile-local bits
-// (q, q+1) maps the local pair index l = 2 bit(q+1) + bit(q) (bit q+1 is the left site of the
-// bond) by the 4x4 matrix U[l][m].
+// One pass: tile geometry and the gates it applies, sorted by (layer, q). A gate on tile-local
+// bits (q, q+1) maps the local pair index l = 2 bit(q+1) + bit(q) (bit q+1 is the left site of the
+// bond) by the 4x4 matrix U[16 g + 4 l + m], in device memory.
 struct GatePass {
     int first;   // contiguous tile of the tbits low bits
     int c, h0;   // window tile: c low bits, window bits [h0, h0 + tbits - c)
     int tbits;   // tile bits (min(L, 12))
     int ngate;
     int q[kMaxGates];
-    double2 U[kMaxGates][16];
+    int layer[kMaxGates];  // position of the gate's layer in the run
+    const double2* U;
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -95,14 +101,16 @@ __global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi
         const int i = t + kGThreads * k;
         if (i < N) v[k] = psi[gate_index(gp, n, i)];
     }
-    // register gates first (bits q, q+1 >= 8): the four amplitudes are slots of one thread
+    // the first layer's gates on register bits (q, q+1 >= 8) first: the four amplitudes are slots
+    // of one thread (they commute with the rest of that layer)
+    auto in_regs = [&](int g) { return gp.layer[g] == 0 && gp.q[g] >= 8 && (1 << (gp.q[g] + 2)) <= N; };
     for (int g = 0; g < gp.ngate; ++g) {
-        const int q = gp.q[g];
-        if (q < 8 || (1 << (q + 2)) > N) continue;
-        switch (q - 8) {
-            case 0: reg_gate<0>(v, gp.U[g]); break;
-            case 1: reg_gate<1>(v, gp.U[g]); break;
-            default: reg_gate<2>(v, gp.U[g]); break;
+        if (!in_regs(g)) continue;
+        const double2* U = gp.U + 16 * g;
+        switch (gp.q[g] - 8) {
+            case 0: reg_gate<0>(v, U); break;
+            case 1: reg_gate<1>(v, U); break;
+            default: reg_gate<2>(v, U); break;
         }
     }
 #pragma unroll
@@ -111,16 +119,17 @@ __global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi
         if (i < N) s[i] = v[k];
     }
     __syncthreads();
-    // LDS gates (bit q is a thread bit): each thread owns whole groups of the amplitudes a gate
-    // mixes (the index with zero bits inserted at q), reads them, writes them back. Two gates on
-    // adjacent pairs (q, q+1), (q+2, q+3) share one round on groups of 16. Gates are sorted by q.
+    // LDS gates, in list order: each thread owns whole groups of the amplitudes a gate mixes (the
+    // index with zero bits inserted at q), reads them, writes them back. Two gates of one layer on
+    // adjacent pairs (q, q+1), (q+2, q+3) share one round on groups of 16.
     for (int g = 0; g < gp.ngate; ++g) {
         const int q = gp.q[g];
-        if (q >= 8 && (1 << (q + 2)) <= N) continue;  // done in registers
-        const double2* U = gp.U[g];
-        const bool two = g + 1 < gp.ngate && gp.q[g + 1] == q + 2 && !(q + 2 >= 8 && (1 << (q + 4)) <= N);
+        if (in_regs(g)) continue;  // done in registers
+        const double2* U = gp.U + 16 * g;
+        const bool two =
+            g + 1 < gp.ngate && gp.layer[g + 1] == gp.layer[g] && gp.q[g + 1] == q + 2 && !in_regs(g + 1);
         if (two) {
-            const double2* U2 = gp.U[g + 1];
+            const double2* U2 = gp.U + 16 * (g + 1);
             const int lowm = (1 << q) - 1;
             for (int j = t; j < (N >> 4); j += kGThreads) {
                 const int b = (j & lowm) | ((j >> q) << (q + 4));
@@ -196,30 +205,9 @@ __global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi
     }
 }
 
-// Tile geometries of the passes of one layer: the 12 low bits, then windows of 8 bits above 4
-// contiguous low bits (256-byte runs), each starting at the lower bit of the first bond of the
-// layer not yet covered (the layer's bonds are disjoint, so windows need not overlap). `lows`
-// lists the lower bits of the layer's bonds in increasing order.
 struct Geometry {
     int first, c, h0, tbits;
 };
-
-std::vector<Geometry> pass_geometry(int L, const std::vector<int>& lows) {
-    std::vector<Geometry> g;
-    const int T = std::min(L, kGTileBits);
-    g.push_back({1, T, T, T});
-    const int wb = kGTileBits - kGLow;
-    for (int p : lows) {
-        if (p + 1 < T) continue;
-        const Geometry& last = g.back();
-        const bool in_last = !last.first && p >= last.h0 && p + 1 < last.h0 + wb;
-        if (in_last) continue;
-        int h0 = p;
-        if (h0 + wb > L) h0 = L - wb;
-        g.push_back({0, kGLow, h0, kGTileBits});
-    }
-    return g;
-}
 
 // Global bit of tile-local bit q in a pass.
 int global_bit(const Geometry& ge, int q) { return ge.first ? q : (q < ge.c ? q : ge.h0 + (q - ge.c)); }
@@ -246,53 +234,87 @@ void bond_hamiltonian(const ed_model* m, int p, cplx* h) {
         }
 }
 
-// Passes of one layer: the propagators exp(-i t h) of the bonds whose left site k has the given
-// parity (1: odd k, H_o; 0: even k, H_e), each given to the first pass that holds both its bits.
-std::vector<GatePass> build_layer(const ed_model* m, int parity, double t) {
+// Passes of a run of consecutive layers (part, time): layer l holds the propagators exp(-i t_l h)
+// of the bonds whose left site k has the layer's parity (1: odd k, H_o; 0: even k, H_e). The first
+// pass is the contiguous tile of the 12 low bits; each later pass is a window of 8 bits above 4
+// contiguous low bits, starting at the lowest bond still pending. A gate (l, p) on bits (p, p+1)
+// is ready once every gate of an earlier layer on bonds p - 1, p, p + 1 has a pass; going through
+// the layers in order, each pass takes the ready gates its tile holds. The matrices go to
+// table (host copy) and the passes point at dev_table. Returns false when a gate finds no pass or
+// the table is full.
+bool build_run(const ed_model* m, const std::vector<std::pair<int, double>>& run, double dt,
+               std::vector<double2>* table, const double2* dev_table, std::vector<GatePass>* out) {
     const int L = m->L;
-    std::vector<int> lows;
-    for (int p = 0; p + 1 < L; ++p)
-        if (((L - p - 1) & 1) == parity) lows.push_back(p);
-    const std::vector<Geometry> geo = pass_geometry(L, lows);
-    std::vector<GatePass> passes(geo.size());
+    const int F = int(run.size());
+    const int T = std::min(L, kGTileBits);
+    const int wb = kGTileBits - kGLow;
+    auto is_bond = [&](int l, int p) { return p >= 0 && p + 1 < L && ((L - p - 1) & 1) == run[l].first; };
+    std::vector<std::vector<int>> at(F, std::vector<int>(L, -1));  // pass of gate (l, p)
+    int pending = 0;
+    for (int l = 0; l < F; ++l)
+        for (int p = 0; p + 1 < L; ++p) pending += is_bond(l, p);
+    auto ready = [&](int l, int p) {
+        for (int e = 0; e < l; ++e)
+            for (int d = -1; d <= 1; ++d)
+                if (is_bond(e, p + d) && at[e][p + d] < 0) return false;
+        return true;
+    };
+    std::vector<Geometry> geo;
+    std::vector<std::vector<std::pair<int, int>>> gates;  // (layer, p) of each pass, by layer then p
+    auto fill = [&](const Geometry& ge, int lo, int hi) {  // gates with both bits in [lo, hi)
+        const int pass = int(geo.size());
+        std::vector<std::pair<int, int>> gs;
+        for (int l = 0; l < F; ++l)
+            for (int p = lo; p + 1 < hi; ++p)
+                if (is_bond(l, p) && at[l][p] < 0 && ready(l, p)) {
+                    at[l][p] = pass;
+                    gs.push_back({l, p});
+                    --pending;
+                }
+        geo.push_back(ge);
+        gates.push_back(gs);
+        return !gs.empty();
+    };
+    fill({1, T, T, T}, 0, T);
+    while (pending > 0) {
+        int h0 = L;
+        for (int l = 0; l < F; ++l)
+            for (int p = 0; p + 1 < L; ++p)
+                if (is_bond(l, p) && at[l][p] < 0) h0 = std::min(h0, p);
+        h0 = std::min(h0, L - wb);
+        if (h0 < kGLow) return false;
+        if (!fill({0, kGLow, h0, kGTileBits}, h0, h0 + wb)) return false;
+    }
     for (size_t i = 0; i < geo.size(); ++i) {
-        std::memset(&passes[i], 0, sizeof(GatePass));
-        passes[i].first = geo[i].first;
-        passes[i].c = geo[i].c;
-        passes[i].h0 = geo[i].h0;
-        passes[i].tbits = geo[i].tbits;
-    }
-    for (int p = 0; p + 1 < L; ++p) {
-        const int k = L - p - 1;
-        if ((k & 1) != parity) continue;
-        cplx h[16], A[16], U[16];
-        bool assigned = false;
-        bond_hamiltonian(m, p, h);
-        for (int e = 0; e < 16; ++e) A[e] = cplx(0.0, -t) * h[e];
-        expm_complex(4, A, U);
-        for (size_t i = 0; i < geo.size(); ++i) {
-            int q = -1;
-            for (int qq = 0; qq + 1 < geo[i].tbits; ++qq)
-                if (global_bit(geo[i], qq) == p && global_bit(geo[i], qq + 1) == p + 1 && (geo[i].first || qq >= geo[i].c))
-                    q = qq;
-            if (q < 0) continue;
-            GatePass& gp = passes[i];
+        if (gates[i].empty()) continue;
+        if (int(gates[i].size()) > kMaxGates) return false;
+        if (table->size() / 16 + gates[i].size() > size_t(kTableGates)) return false;
+        GatePass gp;
+        std::memset(&gp, 0, sizeof(GatePass));
+        gp.first = geo[i].first;
+        gp.c = geo[i].c;
+        gp.h0 = geo[i].h0;
+        gp.tbits = geo[i].tbits;
+        gp.U = dev_table ? dev_table + table->size() : nullptr;  // null when only counting passes
+        for (const auto& lp : gates[i]) {
+            const int l = lp.first, p = lp.second;
+            const int q = geo[i].first ? p : geo[i].c + (p - geo[i].h0);
+            if (global_bit(geo[i], q) != p || global_bit(geo[i], q + 1) != p + 1) return false;
+            cplx h[16], A[16], U[16];
+            bond_hamiltonian(m, p, h);
+            for (int e = 0; e < 16; ++e) A[e] = cplx(0.0, -run[l].second * dt) * h[e];
+            expm_complex(4, A, U);
+            for (int e = 0; e < 16; ++e) table->push_back(make_double2(U[e].real(), U[e].imag()));
             gp.q[gp.ngate] = q;
-            for (int e = 0; e < 16; ++e) gp.U[gp.ngate][e] = make_double2(U[e].real(), U[e].imag());
+            gp.layer[gp.ngate] = l;
             ++gp.ngate;
-            assigned = true;
-            break;
         }
-        if (!assigned) return {};
+        out->push_back(gp);
     }
-    // drop passes without gates
-    std::vector<GatePass> out;
-    for (const GatePass& gp : passes)
-        if (gp.ngate > 0) out.push_back(gp);
-    return out;
+    return true;
 }
 
-hipError_t run_layer(const std::vector<GatePass>& passes, double2* psi, int L, hipStream_t s) {
+hipError_t run_passes(const std::vector<GatePass>& passes, double2* psi, int L, hipStream_t s) {
     for (const GatePass& gp : passes) {
         const int64_t tiles = int64_t(1) << (L - gp.tbits);
         hipLaunchKernelGGL(gate_pass, dim3(unsigned(tiles)), dim3(kGThreads), 0, s, psi, gp);
@@ -302,13 +324,55 @@ hipError_t run_layer(const std::vector<GatePass>& passes, double2* psi, int L, h
     return hipSuccess;
 }
 
+// The layers of one step (part, fraction of dt): Eq. ed:eq:trotter2 or Eq. ed:eq:trotter4 with
+// the constants of Eq. ed:eq:trotter4c; part 0 = H_e (even k), 1 = H_o (odd k).
+std::vector<std::pair<int, double>> step_layers(int order) {
+    const double tau3 = 1.0 / (2.0 * (4.0 - std::cbrt(4.0)));
+    const double tau1 = 1.0 - 8.0 * tau3, tau2 = 0.5 * (1.0 - 6.0 * tau3), tau4 = 2.0 * tau3;
+    if (order == 2) return {{0, 0.5}, {1, 1.0}, {0, 0.5}};
+    return {{0, tau3}, {1, tau4}, {0, tau4}, {1, tau4}, {0, tau2}, {1, tau1},
+            {0, tau2}, {1, tau4}, {0, tau4}, {1, tau4}, {0, tau3}};
+}
+
+// The passes of one step: the step's layers in runs of kFuse, one set of passes per distinct run
+// (runs), the run of each position (which); the gate matrices go to table, the passes point at
+// dev_table.
+struct StepPlan {
+    std::vector<std::vector<GatePass>> runs;
+    std::vector<int> which;
+    std::vector<double2> table;
+};
+
+ed_status plan_step(const ed_model* m, int order, double dt, const double2* dev_table, StepPlan* sp) {
+    const std::vector<std::pair<int, double>> seq = step_layers(order);
+    std::vector<std::vector<std::pair<int, double>>> keys;
+    for (size_t i0 = 0; i0 < seq.size(); i0 += kFuse) {
+        const std::vector<std::pair<int, double>> run(seq.begin() + i0, seq.begin() + std::min(seq.size(), i0 + kFuse));
+        int found = -1;
+        for (size_t j = 0; j < keys.size(); ++j)
+            if (keys[j] == run) found = int(j);
+        if (found < 0) {
+            std::vector<GatePass> passes;
+            if (!build_run(m, run, dt, &sp->table, dev_table, &passes))
+                return fail(ED_ERR_UNSUPPORTED, "internal error: no Trotter pass plan for L = " + std::to_string(m->L));
+            keys.push_back(run);
+            sp->runs.push_back(passes);
+            found = int(keys.size()) - 1;
+        }
+        sp->which.push_back(found);
+    }
+    return ED_OK;
+}
+
 }  // namespace
 }  // namespace ed
 
 extern "C" ed_status ed_trotter_workspace(const ed_model* model, int with_energy, size_t* bytes) {
     if (!model || !bytes) return ed::fail(ED_ERR_ARG, "null argument");
     const int64_t D = int64_t(1) << model->L;
-    *bytes = ed::core_scratch_bytes() + (with_energy ? size_t(2) * size_t(D) * sizeof(double2) + 256 : 0);
+    // the scratch of the norm and energy kernels, two state vectors for the energy, the gate table
+    *bytes = ed::core_scratch_bytes() + (with_energy ? size_t(2) * size_t(D) * sizeof(double2) + 256 : 0) +
+             ed::kGateTableBytes;
     return ED_OK;
 }
 
@@ -332,33 +396,18 @@ extern "C" ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, doubl
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* v = reinterpret_cast<double2*>(psi);
 
-    // layer sequence (part, fraction of dt): Eq. ed:eq:trotter2 or Eq. ed:eq:trotter4 with the
-    // constants of Eq. ed:eq:trotter4c; part 0 = H_e (even k), 1 = H_o (odd k)
-    const double tau3 = 1.0 / (2.0 * (4.0 - std::cbrt(4.0)));
-    const double tau1 = 1.0 - 8.0 * tau3, tau2 = 0.5 * (1.0 - 6.0 * tau3), tau4 = 2.0 * tau3;
-    std::vector<std::pair<int, double>> seq;
-    if (order == 2) {
-        seq = {{0, 0.5}, {1, 1.0}, {0, 0.5}};
-    } else {
-        seq = {{0, tau3}, {1, tau4}, {0, tau4}, {1, tau4}, {0, tau2}, {1, tau1},
-               {0, tau2}, {1, tau4}, {0, tau4}, {1, tau4}, {0, tau3}};
-    }
-    // one set of passes per distinct (part, fraction)
-    std::vector<std::pair<int, double>> keys;
-    std::vector<std::vector<GatePass>> layers;
-    std::vector<int> which(seq.size());
-    for (size_t i = 0; i < seq.size(); ++i) {
-        int found = -1;
-        for (size_t j = 0; j < keys.size(); ++j)
-            if (keys[j] == seq[i]) found = int(j);
-        if (found < 0) {
-            keys.push_back(seq[i]);
-            layers.push_back(build_layer(model, seq[i].first, seq[i].second * dt));
-            if (layers.back().empty() && L > 2 - seq[i].first)
-                return fail(ED_ERR_UNSUPPORTED, "internal error: a Trotter gate has no pass for L = " + std::to_string(L));
-            found = int(keys.size()) - 1;
-        }
-        which[i] = found;
+    // the step's passes; their gate matrices in the table at the end of the workspace
+    const size_t vec_bytes = want_e ? (size_t(2) * size_t(D) * sizeof(double2) + 255) & ~size_t(255) : 0;
+    const size_t table_off = core_scratch_bytes() + vec_bytes;  // after what carve hands out
+    if (table_off + kGateTableBytes > ws_bytes) return fail(ED_ERR_WORKSPACE, "workspace too small for the gate table");
+    const double2* dev_table = reinterpret_cast<const double2*>(static_cast<char*>(ws) + table_off);
+    StepPlan sp;
+    ED_TRY(plan_step(model, order, dt, dev_table, &sp));
+    const std::vector<double2>& table = sp.table;
+    if (!table.empty()) {
+        ED_HIP_TRY(hipMemcpyAsync(const_cast<double2*>(dev_table), table.data(), table.size() * sizeof(double2),
+                                  hipMemcpyHostToDevice, s));
+        ED_HIP_TRY(hipStreamSynchronize(s));  // the host table is a local
     }
     auto record = [&](int step) -> ed_status {
         if (obs && (obs->sz || obs->norm)) {
@@ -375,12 +424,25 @@ extern "C" ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, doubl
     };
     ED_TRY(record(0));
     for (int st = 0; st < n_steps; ++st) {
-        for (size_t i = 0; i < seq.size(); ++i) {
-            const hipError_t e = run_layer(layers[which[i]], v, L, s);
+        for (int r : sp.which) {
+            const hipError_t e = run_passes(sp.runs[r], v, L, s);
             if (e != hipSuccess) return fail(ED_ERR_HIP, std::string("Trotter layer launch: ") + hipGetErrorString(e));
         }
         ED_TRY(record(st + 1));
     }
     ED_HIP_TRY(hipStreamSynchronize(s));
+    return ED_OK;
+}
+
+extern "C" ed_status ed_trotter_passes(const ed_model* model, int order, int* passes) {
+    using namespace ed;
+    if (!model || !passes) return fail(ED_ERR_ARG, "null argument");
+    if (order != 2 && order != 4) return fail(ED_ERR_ARG, "order must be 2 or 4");
+    if (model->lr || model->lv_L > 0) return fail(ED_ERR_UNSUPPORTED, "the Trotter layers take site and bond rules only");
+    StepPlan sp;
+    ED_TRY(plan_step(model, order, 0.0, nullptr, &sp));
+    int n = 0;
+    for (int r : sp.which) n += int(sp.runs[r].size());
+    *passes = n;
     return ED_OK;
 }

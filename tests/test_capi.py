@@ -58,6 +58,8 @@ def test_model_create_argument_errors():
 def test_apply_rejects_null_arguments():
     lib = _lib.lib()
     assert lib.ed_apply_H(None, None, None, None) == -1
+    n = C.c_int(-5)
+    assert lib.ed_trotter_passes(None, 4, C.byref(n)) == -1 and n.value == -5
 
 
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),

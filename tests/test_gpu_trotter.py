@@ -34,7 +34,7 @@ def models(L):
     }
 
 
-@pytest.mark.parametrize("L", [2, 3, 5, 8, 11, 12, 13, 16, 20])
+@pytest.mark.parametrize("L", [2, 3, 5, 8, 11, 12, 13, 16, 17, 20])
 @pytest.mark.parametrize("order", [2, 4])
 def test_trotter_vs_oracle(L, order):
     print(f"trotter L={L} order={order}", flush=True)
@@ -127,3 +127,13 @@ def test_trotter_error_paths():
     o = _lib.Observe(None, e.ctypes.data, None)
     assert lib.ed_trotter_evolve(m.handle, *args, 2, C.byref(o), C.c_void_p(ws.data_ptr()), nb.value, None) == -5
     assert lib.ed_trotter_evolve(m.handle, *args, 2, None, C.c_void_p(ws.data_ptr()), nb.value, None) == 0
+
+
+@pytest.mark.parametrize("L,p4,p2", [(10, 4, 1), (14, 8, 2), (20, 12, 3), (28, 16, 4)])
+def test_trotter_pass_count(L, p4, p2):
+    """Runs of three layers: one contiguous pass per run while L <= 12, then windows of 8 bits
+    above the 12 low bits, each starting at the lowest bond still pending (the counts of the
+    schedule written out by hand for these lengths)."""
+    m = P.Model(E.tfim(L, 0.5))
+    assert P.trotter_passes(m, 4) == p4
+    assert P.trotter_passes(m, 2) == p2
