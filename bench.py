@@ -337,7 +337,7 @@ def row_trotter_L28(P, E, torch, dev, steps=100):
     """The L = 28 quench of the Krylov row with the Suzuki-Trotter propagators (Sec. ed:sec:trotter):
     orders 4 and 2, per-step time, the algorithmic bandwidth of the gate passes (each pass reads and
     writes the state once: 32 B per amplitude; the library reports the passes of a step, runs of
-    three layers fused) and the largest difference of <sigma^z_k>(t) from the Krylov run when that
+    four layers fused) and the largest difference of <sigma^z_k>(t) from the Krylov run when that
     row ran before."""
     import numpy as np
     L, dt = 28, 0.05

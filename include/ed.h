@@ -286,7 +286,7 @@ ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, double dt, int n
 /* ----------------------------------------------------------------------------------------
  * ed_trotter_passes: the number of in-place passes over the state that one ed_trotter_evolve
  * step of the given order makes (Sec. ed:sec:trotter), each reading and writing the state once.
- * The step's layers are applied in runs of three consecutive layers; a run streams the state
+ * The step's layers are applied in runs of four consecutive layers; a run streams the state
  * through LDS tiles (the 12 low bits, then windows of 8 bits above 4 contiguous low bits) and a
  * pass applies, layer by layer, every gate its tile holds whose earlier-layer neighbours are
  * already applied. passes host. No device work.

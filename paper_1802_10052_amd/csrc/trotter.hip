@@ -25,26 +25,30 @@
 namespace ed {
 namespace {
 
-constexpr int kGThreads = 256;
+constexpr int kGThreads = 512;
+constexpr int kGThreadBits = kGThreads == 256 ? 8 : kGThreads == 512 ? 9 : 10;
 constexpr int kGTileBits = 12;
-constexpr int kGSlots = (1 << kGTileBits) / kGThreads;  // 16
+constexpr int kGSlots = (1 << kGTileBits) / kGThreads;  // amplitudes per thread
+constexpr int kGSlotBits = kGTileBits - kGThreadBits;
+constexpr bool kPairRounds = false;  // two gates on adjacent pairs share one LDS round
 constexpr int kGLow = 4;                                 // contiguous low bits of a window tile
-constexpr int kFuse = 3;                                 // consecutive layers per run of passes
+constexpr int kFuse = 4;                                 // consecutive layers per run of passes
 constexpr int kMaxGates = kFuse * (kGTileBits / 2);      // gates of one pass
-constexpr int kTableGates = 192;                         // gate matrices one evolve call holds
-constexpr size_t kGateTableBytes = size_t(kTableGates) * 16 * sizeof(double2);
+constexpr int kTableGates = 192;                         // gates one evolve call holds
+// the gate table: 16 double2 (the matrix) per gate, then 2 ints (q, layer) per gate
+constexpr size_t kGateTableBytes = size_t(kTableGates) * (16 * sizeof(double2) + 2 * sizeof(int));
 
-// One pass: tile geometry and the gates it applies, sorted by (layer, q). A gate on tile-local
-// bits (q, q+1) maps the local pair index l = 2 bit(q+1) + bit(q) (bit q+1 is the left site of the
-// bond) by the 4x4 matrix U[16 g + 4 l + m], in device memory.
+// One pass: tile geometry and the gates it applies, sorted by (layer, q), in device memory: gate g
+// of the pass acts on tile-local bits (q, q+1) = (G[2 g], G[2 g] + 1) for the layer G[2 g + 1] of
+// the run, and maps the local pair index l = 2 bit(q+1) + bit(q) (bit q+1 is the left site of the
+// bond) by the 4x4 matrix U[16 g + 4 l + m].
 struct GatePass {
     int first;   // contiguous tile of the tbits low bits
     int c, h0;   // window tile: c low bits, window bits [h0, h0 + tbits - c)
     int tbits;   // tile bits (min(L, 12))
     int ngate;
-    int q[kMaxGates];
-    int layer[kMaxGates];  // position of the gate's layer in the run
     const double2* U;
+    const int* G;
 };
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -60,10 +64,12 @@ __device__ __forceinline__ int64_t gate_index(const GatePass& gp, int64_t n, int
     return (nlo << gp.c) | (nhi << (gp.h0 + w)) | int64_t(i & lowmask) | (int64_t(i >> gp.c) << gp.h0);
 }
 
-// Gate on register bits (8 + R, 9 + R): slots k, k | 1 << R, k | 2 << R, k | 3 << R hold the
-// pair indices l = 0..3 of one group (compile-time slot indices keep v in registers).
+// Gate on register bits (kGThreadBits + R, kGThreadBits + R + 1): slots k, k | 1 << R, k | 2 << R,
+// k | 3 << R hold the pair indices l = 0..3 of one group (compile-time slot indices keep v in
+// registers).
 template <int R>
 __device__ __forceinline__ void reg_gate(double2 (&v)[kGSlots], const double2* __restrict__ U) {
+    static_assert(R + 2 <= kGSlotBits, "gate bits beyond the register slots");
 #pragma unroll
     for (int k = 0; k < kGSlots; ++k) {
         if (((k >> R) & 3) != 0) continue;
@@ -87,10 +93,18 @@ __device__ __forceinline__ void reg_gate(double2 (&v)[kGSlots], const double2* _
     }
 }
 
-// Tile-local index of slot k of thread t: i = t + kGThreads k (bits 0..7 across threads, 8..11
-// across the 16 register slots). Gates whose two bits are both register bits are applied in
-// registers while the tile is loaded; the others update groups of four amplitudes in LDS.
-__global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi, GatePass gp) {
+// A gate of the first layer whose two bits are register bits of an N-amplitude tile.
+__device__ __forceinline__ bool in_regs(int layer, int q, int N) {
+    return layer == 0 && q >= kGThreadBits && (1 << (q + 2)) <= N;
+}
+
+// Tile-local index of slot k of thread t: i = t + kGThreads k (the low kGThreadBits bits across
+// threads, the rest across the register slots). Gates of the first layer whose two bits are both
+// register bits are applied in registers while the tile is loaded; the others update groups of
+// four amplitudes in LDS.
+__global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi, GatePass gp,
+                                                       const double2* __restrict__ Utab,
+                                                       const int* __restrict__ G) {
     __shared__ double2 s[1 << kGTileBits];
     const int t = threadIdx.x;
     const int N = 1 << gp.tbits;
@@ -103,14 +117,19 @@ __global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi
     }
     // the first layer's gates on register bits (q, q+1 >= 8) first: the four amplitudes are slots
     // of one thread (they commute with the rest of that layer)
-    auto in_regs = [&](int g) { return gp.layer[g] == 0 && gp.q[g] >= 8 && (1 << (gp.q[g] + 2)) <= N; };
+    // (a switch in the kernel body: written as a chain of ifs, or inside a helper taking the slots
+    // by reference, the slots went to scratch memory)
     for (int g = 0; g < gp.ngate; ++g) {
-        if (!in_regs(g)) continue;
-        const double2* U = gp.U + 16 * g;
-        switch (gp.q[g] - 8) {
+        if (!in_regs(G[2 * g + 1], G[2 * g], N)) continue;
+        const double2* U = Utab + 16 * g;
+        switch (G[2 * g] - kGThreadBits) {
             case 0: reg_gate<0>(v, U); break;
-            case 1: reg_gate<1>(v, U); break;
-            default: reg_gate<2>(v, U); break;
+            case 1:
+                if constexpr (kGSlotBits >= 3) reg_gate<1>(v, U);
+                break;
+            default:
+                if constexpr (kGSlotBits >= 4) reg_gate<2>(v, U);
+                break;
         }
     }
 #pragma unroll
@@ -123,13 +142,13 @@ __global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi
     // index with zero bits inserted at q), reads them, writes them back. Two gates of one layer on
     // adjacent pairs (q, q+1), (q+2, q+3) share one round on groups of 16.
     for (int g = 0; g < gp.ngate; ++g) {
-        const int q = gp.q[g];
-        if (in_regs(g)) continue;  // done in registers
-        const double2* U = gp.U + 16 * g;
-        const bool two =
-            g + 1 < gp.ngate && gp.layer[g + 1] == gp.layer[g] && gp.q[g + 1] == q + 2 && !in_regs(g + 1);
+        const int q = G[2 * g], layer = G[2 * g + 1];
+        if (in_regs(layer, q, N)) continue;  // done in registers
+        const double2* U = Utab + 16 * g;
+        const bool two = kPairRounds && g + 1 < gp.ngate && G[2 * g + 3] == layer && G[2 * g + 2] == q + 2 &&
+                         !in_regs(layer, q + 2, N);
         if (two) {
-            const double2* U2 = gp.U + 16 * (g + 1);
+            const double2* U2 = Utab + 16 * (g + 1);
             const int lowm = (1 << q) - 1;
             for (int j = t; j < (N >> 4); j += kGThreads) {
                 const int b = (j & lowm) | ((j >> q) << (q + 4));
@@ -240,10 +259,11 @@ void bond_hamiltonian(const ed_model* m, int p, cplx* h) {
 // contiguous low bits, starting at the lowest bond still pending. A gate (l, p) on bits (p, p+1)
 // is ready once every gate of an earlier layer on bonds p - 1, p, p + 1 has a pass; going through
 // the layers in order, each pass takes the ready gates its tile holds. The matrices go to
-// table (host copy) and the passes point at dev_table. Returns false when a gate finds no pass or
-// the table is full.
+// table and the (q, layer) pairs to meta (host copies); the passes point at dev_table and
+// dev_meta. Returns false when a gate finds no pass or the table is full.
 bool build_run(const ed_model* m, const std::vector<std::pair<int, double>>& run, double dt,
-               std::vector<double2>* table, const double2* dev_table, std::vector<GatePass>* out) {
+               std::vector<double2>* table, std::vector<int>* meta, const double2* dev_table,
+               const int* dev_meta, std::vector<GatePass>* out) {
     const int L = m->L;
     const int F = int(run.size());
     const int T = std::min(L, kGTileBits);
@@ -296,6 +316,7 @@ bool build_run(const ed_model* m, const std::vector<std::pair<int, double>>& run
         gp.h0 = geo[i].h0;
         gp.tbits = geo[i].tbits;
         gp.U = dev_table ? dev_table + table->size() : nullptr;  // null when only counting passes
+        gp.G = dev_meta ? dev_meta + meta->size() : nullptr;
         for (const auto& lp : gates[i]) {
             const int l = lp.first, p = lp.second;
             const int q = geo[i].first ? p : geo[i].c + (p - geo[i].h0);
@@ -305,8 +326,8 @@ bool build_run(const ed_model* m, const std::vector<std::pair<int, double>>& run
             for (int e = 0; e < 16; ++e) A[e] = cplx(0.0, -run[l].second * dt) * h[e];
             expm_complex(4, A, U);
             for (int e = 0; e < 16; ++e) table->push_back(make_double2(U[e].real(), U[e].imag()));
-            gp.q[gp.ngate] = q;
-            gp.layer[gp.ngate] = l;
+            meta->push_back(q);
+            meta->push_back(l);
             ++gp.ngate;
         }
         out->push_back(gp);
@@ -317,7 +338,7 @@ bool build_run(const ed_model* m, const std::vector<std::pair<int, double>>& run
 hipError_t run_passes(const std::vector<GatePass>& passes, double2* psi, int L, hipStream_t s) {
     for (const GatePass& gp : passes) {
         const int64_t tiles = int64_t(1) << (L - gp.tbits);
-        hipLaunchKernelGGL(gate_pass, dim3(unsigned(tiles)), dim3(kGThreads), 0, s, psi, gp);
+        hipLaunchKernelGGL(gate_pass, dim3(unsigned(tiles)), dim3(kGThreads), 0, s, psi, gp, gp.U, gp.G);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -335,15 +356,17 @@ std::vector<std::pair<int, double>> step_layers(int order) {
 }
 
 // The passes of one step: the step's layers in runs of kFuse, one set of passes per distinct run
-// (runs), the run of each position (which); the gate matrices go to table, the passes point at
-// dev_table.
+// (runs), the run of each position (which); the gate matrices go to table and their (q, layer)
+// to meta, the passes point at dev_table and dev_meta.
 struct StepPlan {
     std::vector<std::vector<GatePass>> runs;
     std::vector<int> which;
     std::vector<double2> table;
+    std::vector<int> meta;
 };
 
-ed_status plan_step(const ed_model* m, int order, double dt, const double2* dev_table, StepPlan* sp) {
+ed_status plan_step(const ed_model* m, int order, double dt, const double2* dev_table, const int* dev_meta,
+                    StepPlan* sp) {
     const std::vector<std::pair<int, double>> seq = step_layers(order);
     std::vector<std::vector<std::pair<int, double>>> keys;
     for (size_t i0 = 0; i0 < seq.size(); i0 += kFuse) {
@@ -353,7 +376,7 @@ ed_status plan_step(const ed_model* m, int order, double dt, const double2* dev_
             if (keys[j] == run) found = int(j);
         if (found < 0) {
             std::vector<GatePass> passes;
-            if (!build_run(m, run, dt, &sp->table, dev_table, &passes))
+            if (!build_run(m, run, dt, &sp->table, &sp->meta, dev_table, dev_meta, &passes))
                 return fail(ED_ERR_UNSUPPORTED, "internal error: no Trotter pass plan for L = " + std::to_string(m->L));
             keys.push_back(run);
             sp->runs.push_back(passes);
@@ -400,14 +423,16 @@ extern "C" ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, doubl
     const size_t vec_bytes = want_e ? (size_t(2) * size_t(D) * sizeof(double2) + 255) & ~size_t(255) : 0;
     const size_t table_off = core_scratch_bytes() + vec_bytes;  // after what carve hands out
     if (table_off + kGateTableBytes > ws_bytes) return fail(ED_ERR_WORKSPACE, "workspace too small for the gate table");
-    const double2* dev_table = reinterpret_cast<const double2*>(static_cast<char*>(ws) + table_off);
+    char* const tab = static_cast<char*>(ws) + table_off;
+    double2* const dev_table = reinterpret_cast<double2*>(tab);
+    int* const dev_meta = reinterpret_cast<int*>(tab + size_t(kTableGates) * 16 * sizeof(double2));
     StepPlan sp;
-    ED_TRY(plan_step(model, order, dt, dev_table, &sp));
-    const std::vector<double2>& table = sp.table;
-    if (!table.empty()) {
-        ED_HIP_TRY(hipMemcpyAsync(const_cast<double2*>(dev_table), table.data(), table.size() * sizeof(double2),
+    ED_TRY(plan_step(model, order, dt, dev_table, dev_meta, &sp));
+    if (!sp.table.empty()) {
+        ED_HIP_TRY(hipMemcpyAsync(dev_table, sp.table.data(), sp.table.size() * sizeof(double2),
                                   hipMemcpyHostToDevice, s));
-        ED_HIP_TRY(hipStreamSynchronize(s));  // the host table is a local
+        ED_HIP_TRY(hipMemcpyAsync(dev_meta, sp.meta.data(), sp.meta.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        ED_HIP_TRY(hipStreamSynchronize(s));  // the host tables are locals
     }
     auto record = [&](int step) -> ed_status {
         if (obs && (obs->sz || obs->norm)) {
@@ -440,7 +465,7 @@ extern "C" ed_status ed_trotter_passes(const ed_model* model, int order, int* pa
     if (order != 2 && order != 4) return fail(ED_ERR_ARG, "order must be 2 or 4");
     if (model->lr || model->lv_L > 0) return fail(ED_ERR_UNSUPPORTED, "the Trotter layers take site and bond rules only");
     StepPlan sp;
-    ED_TRY(plan_step(model, order, 0.0, nullptr, &sp));
+    ED_TRY(plan_step(model, order, 0.0, nullptr, nullptr, &sp));
     int n = 0;
     for (int r : sp.which) n += int(sp.runs[r].size());
     *passes = n;

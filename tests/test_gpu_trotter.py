@@ -129,9 +129,9 @@ def test_trotter_error_paths():
     assert lib.ed_trotter_evolve(m.handle, *args, 2, None, C.c_void_p(ws.data_ptr()), nb.value, None) == 0
 
 
-@pytest.mark.parametrize("L,p4,p2", [(10, 4, 1), (14, 8, 2), (20, 12, 3), (28, 16, 4)])
+@pytest.mark.parametrize("L,p4,p2", [(10, 3, 1), (14, 6, 2), (20, 9, 3), (28, 14, 4)])
 def test_trotter_pass_count(L, p4, p2):
-    """Runs of three layers: one contiguous pass per run while L <= 12, then windows of 8 bits
+    """Runs of four layers: one contiguous pass per run while L <= 12, then windows of 8 bits
     above the 12 low bits, each starting at the lowest bond still pending (the counts of the
     schedule written out by hand for these lengths)."""
     m = P.Model(E.tfim(L, 0.5))
