@@ -753,13 +753,26 @@ __global__ __launch_bounds__(kBndThreads) void tri_bounds(const double* __restri
     }
 }
 
+// 1/q from the hardware reciprocal and two Newton steps r <- r + r (1 - q r), each of which squares
+// the relative error: within an ulp or two of the quotient, at a third of the instructions of a
+// correctly rounded division. |q| >= pivmin keeps 1/q finite. (Bisection only needs each count to
+// be the exact count of a slightly perturbed T, which a faithful quotient gives; the bracketing
+// below keeps count(lo) <= k < count(hi) whatever the counts are.)
+__device__ __forceinline__ double recip(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    r = fma(r, fma(-q, r, 1.0), r);
+    return r;
+}
+
 __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n, double x,
                                            double pivmin) {
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     int cnt = q < 0.0;
+#pragma unroll 4
     for (int i = 1; i < n; ++i) {
-        q = (d[i] - x) - e2[i - 1] / q;
+        q = (d[i] - x) - e2[i - 1] * recip(q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
     }
