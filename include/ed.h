@@ -333,13 +333,16 @@ ed_status ed_measure_noalloc(const ed_c64* psi, int L, double* sz, double* norm,
  * nonzero.
  * psi        device, D amplitudes (any nonzero norm)
  * S          host; spectrum host (may be NULL): min(2^l, 2^(L-l)) eigenvalues, descending.
- * real_arith host (may be NULL): set to 1 when the real arithmetic ran, else 0.
  * Limits: 0 <= l_cut <= L, min(l_cut, L - l_cut) <= 14. Synchronises stream.
  * Workspace: ed_entropy_workspace (the Gram matrix, 16 * 4^min(l, L-l) bytes, plus vectors).
+ * ed_entropy_ex: the same, and real_arith (host, may be NULL) is set to 1 when the real
+ * arithmetic ran, else 0.
  * ---------------------------------------------------------------------------------------- */
 ed_status ed_entropy_workspace(int L, int l_cut, size_t* bytes);
-ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, int* real_arith,
-                     void* ws, size_t ws_bytes, void* stream);
+ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, void* ws,
+                     size_t ws_bytes, void* stream);
+ed_status ed_entropy_ex(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, int* real_arith,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
  * Liouville space (Sec. VI.B, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket, App. F). The density

@@ -346,8 +346,12 @@ def entropy(psi, L, l_cut=None, spectrum=False, stream=None, info=False):
     S = C.c_double()
     real = C.c_int(0)
     spec = np.zeros(1 << min(l, L - l)) if spectrum else None
-    call("ed_entropy", _dptr(psi), int(L), 2, l, C.byref(S), spec.ctypes.data if spectrum else None,
-         C.byref(real), _dptr(ws), nb.value, _stream_ptr(stream))
+    if info:
+        call("ed_entropy_ex", _dptr(psi), int(L), 2, l, C.byref(S), spec.ctypes.data if spectrum else None,
+             C.byref(real), _dptr(ws), nb.value, _stream_ptr(stream))
+    else:
+        call("ed_entropy", _dptr(psi), int(L), 2, l, C.byref(S), spec.ctypes.data if spectrum else None,
+             _dptr(ws), nb.value, _stream_ptr(stream))
     out = (S.value, spec) if spectrum else (S.value,)
     if info:
         out = out + ({"real_arith": bool(real.value)},)

@@ -155,8 +155,9 @@ def _declare(l):
     _fn(l, "ed_evolve_adjoint", [P, C.c_int, C.c_double, P, P, P, AP, C.POINTER(C.c_double), P, P, C.c_size_t, P])
     _fn(l, "ed_evolve_loss_workspace", [P, AP, S])
     _fn(l, "ed_evolve_loss", [P, C.c_int, C.c_double, P, P, P, AP, C.POINTER(C.c_double), P, C.c_size_t, P])
-    _fn(l, "ed_entropy", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, C.POINTER(C.c_int), P,
-                          C.c_size_t, P])
+    _fn(l, "ed_entropy", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, P, C.c_size_t, P])
+    _fn(l, "ed_entropy_ex", [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), P, C.POINTER(C.c_int), P,
+                             C.c_size_t, P])
     _fn(l, "ed_measure", [P, C.c_int, P, P, P, C.c_size_t, P])
     _fn(l, "ed_measure_noalloc", [P, C.c_int, P, P, P])
     _fn(l, "ed_stream_copy", [P, P, C.c_int64, P])

@@ -940,8 +940,9 @@ extern "C" ed_status ed_entropy_workspace(int L, int l_cut, size_t* bytes) {
     return ED_OK;
 }
 
-extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum,
-                                int* real_arith, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+ed_status entropy_impl(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, int* real_arith,
+                       void* ws, size_t ws_bytes, void* stream) {
     if (!psi || !S) return fail(ED_ERR_ARG, "null argument");
     if (d != 2) return fail(ED_ERR_UNSUPPORTED, "only d = 2 is supported");
     size_t need = 0;
@@ -1000,4 +1001,15 @@ extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, doub
     if (spectrum)
         for (int i = 0; i < n; ++i) spectrum[i] = dd[n - 1 - i] / tr;  // descending
     return ED_OK;
+}
+}  // namespace
+
+extern "C" ed_status ed_entropy(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum, void* ws,
+                                size_t ws_bytes, void* stream) {
+    return entropy_impl(psi, L, d, l_cut, S, spectrum, nullptr, ws, ws_bytes, stream);
+}
+
+extern "C" ed_status ed_entropy_ex(const ed_c64* psi, int L, int d, int l_cut, double* S, double* spectrum,
+                                   int* real_arith, void* ws, size_t ws_bytes, void* stream) {
+    return entropy_impl(psi, L, d, l_cut, S, spectrum, real_arith, ws, ws_bytes, stream);
 }
