@@ -275,7 +275,8 @@ ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double dt, int n_
  *         energy = <psi|H|psi>/<psi|psi> costs one H psi per record and needs the workspace of
  *         ed_trotter_workspace(model, with_energy = 1, ...).
  * Workspace: ed_trotter_workspace bytes (scratch, two state vectors when with_energy = 1, and a
- *         48 KiB table of the gate matrices, copied in at the start of the call).
+ *         50 KiB table of the gate matrices and their tile bits, copied in at the start of the
+ *         call, which synchronises the stream once before the first pass).
  * Errors: ED_ERR_ARG (null model/psi/ws, order not 2 or 4, n_steps < 0, dt not finite),
  * ED_ERR_WORKSPACE. Synchronises stream.
  * ---------------------------------------------------------------------------------------- */
