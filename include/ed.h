@@ -228,9 +228,11 @@ ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, const ed_la
  * Hermitian only). Arnoldi (hermitian = 0) needs reorth = 1.
  * psi     device, D amplitudes, in place: psi(0) on entry, psi(n_steps dt) on exit; no
  *         renormalisation (the norm drift is measured).
- * obs     host arrays, each may be NULL: sz[(n_steps+1) * L] = <sigma^z_k>/<psi|psi> for sites
+ * obs     arrays, each may be NULL: sz[(n_steps+1) * L] = <sigma^z_k>/<psi|psi> for sites
  *         k = 1..L at t = 0, dt, ..., energy[n_steps+1] = <psi|H|psi>/<psi|psi>,
- *         norm[n_steps+1] = |psi|.
+ *         norm[n_steps+1] = |psi|. Host arrays when obs->on_device = 0; device arrays when it
+ *         is 1 (the values are staged on the host during the call and copied to the device
+ *         arrays before it returns).
  * info    host (may be NULL).
  * Workspace: ed_krylov_workspace = (m_max + 1) D complex + scratch. Limits: 1 <= m_max <= 64.
  * ---------------------------------------------------------------------------------------- */
@@ -246,6 +248,7 @@ typedef struct {
     double* sz;
     double* energy;
     double* norm;
+    int on_device; /* 0: the arrays are host memory; 1: device memory */
 } ed_observe;
 
 typedef struct {

@@ -239,11 +239,26 @@ def lanczos_ground(model, v0, tol=1e-10, max_iter=200, max_basis=None, n_keep=0,
     return e0.value, psi0, d
 
 
+def _observe(shapes, device):
+    """Output arrays of an evolve call: numpy arrays, or with device set float64 tensors there
+    (ed_observe.on_device = 1). Returns (dict, Observe)."""
+    if device is None:
+        obs = {k: np.zeros(v) for k, v in shapes.items()}
+        ptr = {k: a.ctypes.data for k, a in obs.items()}
+    else:
+        obs = {k: torch.zeros(v, dtype=torch.float64, device=device) for k, v in shapes.items()}
+        ptr = {k: a.data_ptr() for k, a in obs.items()}
+    o = _lib.Observe(ptr.get("sz"), ptr.get("energy"), ptr.get("norm"), 0 if device is None else 1)
+    return obs, o
+
+
 def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reorth=0, hermitian=True,
-                  observe=True, stream=None):
+                  observe=True, stream=None, device_obs=False):
     """Krylov time evolution of psi in place (ed_krylov_evolve). Returns (psi, obs, info) with obs
-    holding numpy arrays sz [(n_steps+1), L], energy [n_steps+1], norm [n_steps+1]. For a
+    holding numpy arrays sz [(n_steps+1), L], energy [n_steps+1], norm [n_steps+1] (with
+    device_obs=True, float64 tensors on psi's device, written through device pointers). For a
     Liouville model (hermitian=False): sz [(n_steps+1), sites] of rho, norm = tr(rho), no energy."""
+    odev = psi.device if device_obs else None
     _check_state(psi, model.D)
     if isinstance(model, Liouville):
         p = _lib.KrylovParams(int(m_max), float(tol), int(fixed_m), 1, 0)
@@ -254,8 +269,7 @@ def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reort
         ws = _workspace(nb.value, psi.device)
         obs, o = None, None
         if observe:
-            obs = {"sz": np.zeros((n_steps + 1, model.sites)), "norm": np.zeros(n_steps + 1)}
-            o = _lib.Observe(obs["sz"].ctypes.data, None, obs["norm"].ctypes.data)
+            obs, o = _observe({"sz": (n_steps + 1, model.sites), "norm": (n_steps + 1,)}, odev)
         info = _lib.KrylovInfo()
         call("ed_krylov_evolve", model.handle, _dptr(psi), float(dt), int(n_steps), C.byref(p),
              C.byref(o) if o is not None else None, C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
@@ -268,9 +282,7 @@ def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reort
     obs = None
     o = None
     if observe:
-        obs = {"sz": np.zeros((n_steps + 1, model.L)), "energy": np.zeros(n_steps + 1),
-               "norm": np.zeros(n_steps + 1)}
-        o = _lib.Observe(obs["sz"].ctypes.data, obs["energy"].ctypes.data, obs["norm"].ctypes.data)
+        obs, o = _observe({"sz": (n_steps + 1, model.L), "energy": (n_steps + 1,), "norm": (n_steps + 1,)}, odev)
     info = _lib.KrylovInfo()
     call("ed_krylov_evolve", model.handle, _dptr(psi), float(dt), int(n_steps), C.byref(p),
          C.byref(o) if o is not None else None, C.byref(info), _dptr(ws), nb.value, _stream_ptr(stream))
@@ -278,10 +290,10 @@ def krylov_evolve(model, psi, dt, n_steps, m_max=20, tol=1e-10, fixed_m=0, reort
                       "reorth_skipped": info.reorth_skipped}
 
 
-def trotter_evolve(model, psi, dt, n_steps, order=4, observe=True, energy=False, stream=None):
+def trotter_evolve(model, psi, dt, n_steps, order=4, observe=True, energy=False, stream=None, device_obs=False):
     """Suzuki-Trotter time evolution of psi in place (ed_trotter_evolve, order 2 or 4). Returns
     (psi, obs) with obs holding numpy arrays sz [(n_steps+1), L], norm [n_steps+1] and, with
-    energy=True, energy [n_steps+1]."""
+    energy=True, energy [n_steps+1] (with device_obs=True, float64 tensors on psi's device)."""
     _check_state(psi, model.D)
     nb = C.c_size_t()
     call("ed_trotter_workspace", model.handle, int(bool(energy)), C.byref(nb))
@@ -289,11 +301,10 @@ def trotter_evolve(model, psi, dt, n_steps, order=4, observe=True, energy=False,
     obs = None
     o = None
     if observe or energy:
-        obs = {"sz": np.zeros((n_steps + 1, model.L)), "norm": np.zeros(n_steps + 1)}
+        shapes = {"sz": (n_steps + 1, model.L), "norm": (n_steps + 1,)}
         if energy:
-            obs["energy"] = np.zeros(n_steps + 1)
-        o = _lib.Observe(obs["sz"].ctypes.data, obs["energy"].ctypes.data if energy else None,
-                         obs["norm"].ctypes.data)
+            shapes["energy"] = (n_steps + 1,)
+        obs, o = _observe(shapes, psi.device if device_obs else None)
     call("ed_trotter_evolve", model.handle, _dptr(psi), float(dt), int(n_steps), int(order),
          C.byref(o) if o is not None else None, _dptr(ws), nb.value, _stream_ptr(stream))
     return psi, obs

@@ -45,7 +45,7 @@ class KrylovParams(C.Structure):
 
 
 class Observe(C.Structure):
-    _fields_ = [("sz", C.c_void_p), ("energy", C.c_void_p), ("norm", C.c_void_p)]
+    _fields_ = [("sz", C.c_void_p), ("energy", C.c_void_p), ("norm", C.c_void_p), ("on_device", C.c_int)]
 
 
 class KrylovInfo(C.Structure):

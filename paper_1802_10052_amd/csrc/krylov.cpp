@@ -713,6 +713,8 @@ extern "C" ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double
     ED_TRY(carve(ws, ws_bytes, D, p->m_max + 1, &w));
     int skipped = 0;
     w.cgs_skipped = &skipped;
+    ObsStage stage;
+    obs = stage.begin(obs, n_steps, lvL > 0 ? lvL : L);
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* v = reinterpret_cast<double2*>(psi);
     int total_m = 0, max_m = 0;
@@ -748,6 +750,7 @@ extern "C" ed_status ed_krylov_evolve(const ed_model* model, ed_c64* psi, double
         obs->energy[n_steps] = e;
     }
     ED_HIP_TRY(hipStreamSynchronize(s));
+    ED_TRY(stage.finish(s));
     if (info) {
         info->steps = n_steps;
         info->total_m = total_m;

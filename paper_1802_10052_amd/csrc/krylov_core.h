@@ -62,6 +62,47 @@ ed_status krylov_step(const ed_model* m, const Workspace& w, int j, int lo, int 
 // whether beta_{m-1} |s_{m-1}| <= tol (tested every 8 products) or the space became invariant.
 // Returns ED_ERR_UNSUPPORTED without touching the basis when the cooperative launch cannot have all
 // its workgroups resident (the caller then runs the host-driven recurrence).
+// Observables of an evolve call whose arrays may be device memory (obs->on_device): the call
+// writes host arrays (begin returns the ed_observe to use) and finish copies them to the
+// caller's arrays, synchronising the stream. For host arrays both are pass-throughs.
+struct ObsStage {
+    ed_observe host{};
+    const ed_observe* user = nullptr;
+    std::vector<double> sz, energy, norm;
+    size_t nsz = 0, nt = 0;
+    const ed_observe* begin(const ed_observe* obs, int n_steps, int per_step) {
+        user = obs;
+        if (!obs || !obs->on_device) return obs;
+        nt = size_t(n_steps) + 1;
+        nsz = nt * size_t(per_step);
+        host = *obs;
+        host.on_device = 0;
+        if (obs->sz) {
+            sz.assign(nsz, 0.0);
+            host.sz = sz.data();
+        }
+        if (obs->energy) {
+            energy.assign(nt, 0.0);
+            host.energy = energy.data();
+        }
+        if (obs->norm) {
+            norm.assign(nt, 0.0);
+            host.norm = norm.data();
+        }
+        return &host;
+    }
+    ed_status finish(hipStream_t s) {
+        if (!user || !user->on_device) return ED_OK;
+        if (user->sz) ED_HIP_TRY(hipMemcpyAsync(user->sz, sz.data(), nsz * sizeof(double), hipMemcpyHostToDevice, s));
+        if (user->energy)
+            ED_HIP_TRY(hipMemcpyAsync(user->energy, energy.data(), nt * sizeof(double), hipMemcpyHostToDevice, s));
+        if (user->norm)
+            ED_HIP_TRY(hipMemcpyAsync(user->norm, norm.data(), nt * sizeof(double), hipMemcpyHostToDevice, s));
+        ED_HIP_TRY(hipStreamSynchronize(s));
+        return ED_OK;
+    }
+};
+
 constexpr int kDevLanczosMaxL = 16;
 bool lanczos_device_fits(const ed_model* m, int max_iter);
 ed_status lanczos_device(const ed_model* m, const Workspace& w, int max_iter, double tol, int* m_out,

@@ -418,6 +418,8 @@ extern "C" ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, doubl
     ED_TRY(carve(ws, ws_bytes, D, want_e ? 2 : 0, &w));
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2* v = reinterpret_cast<double2*>(psi);
+    ObsStage stage;
+    obs = stage.begin(obs, n_steps, L);
 
     // the step's passes; their gate matrices in the table at the end of the workspace
     const size_t vec_bytes = want_e ? (size_t(2) * size_t(D) * sizeof(double2) + 255) & ~size_t(255) : 0;
@@ -456,7 +458,7 @@ extern "C" ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, doubl
         ED_TRY(record(st + 1));
     }
     ED_HIP_TRY(hipStreamSynchronize(s));
-    return ED_OK;
+    return stage.finish(s);
 }
 
 extern "C" ed_status ed_trotter_passes(const ed_model* model, int order, int* passes) {

@@ -224,6 +224,22 @@ def test_krylov_fixed_m_and_eigenstate():
     assert info2["max_m"] == 7 and info2["total_m"] == 21
 
 
+def test_krylov_device_observables():
+    """The observables written through device pointers (ed_observe.on_device = 1) equal the host
+    arrays of the same evolution bit for bit (the same values, staged and copied)."""
+    L = 12
+    m = P.Model(E.tfim(L, 0.7))
+    psi0 = E.random_state(L, 8)
+    a = dev(psi0)
+    b = dev(psi0)
+    _, oh, _ = P.krylov_evolve(m, a, 0.1, 6, m_max=20, tol=1e-12)
+    _, od, _ = P.krylov_evolve(m, b, 0.1, 6, m_max=20, tol=1e-12, device_obs=True)
+    for k in ("sz", "energy", "norm"):
+        assert od[k].device.type == "cuda"
+        assert np.array_equal(oh[k], od[k].cpu().numpy()), k
+    assert torch.equal(a, b)
+
+
 def test_measure_matches_oracle():
     for L in (3, 9, 13, 17):
         psi = E.random_state(L, 5, normalise=False)

@@ -96,6 +96,10 @@ def test_liouville_evolution_vs_oracle(L):
         assert abs(obs["norm"][s] - tr) < 1e-10
     sz, tr = P.liouville_measure(rho, L)
     assert abs(tr - 1.0) < 1e-10 and np.abs(sz - OLv.measure(refs[-1], L)[0]).max() < 1e-10
+    # the same evolution with the observables written through device pointers
+    rho2 = to_dev(vec0)
+    _, obs2, _ = P.krylov_evolve(m, rho2, dt, steps, m_max=40, tol=1e-12, hermitian=False, device_obs=True)
+    assert np.array_equal(obs2["sz"].cpu().numpy(), obs["sz"]) and np.array_equal(obs2["norm"].cpu().numpy(), obs["norm"])
 
 
 def test_liouvillian_invariants_L14():

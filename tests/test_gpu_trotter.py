@@ -137,3 +137,15 @@ def test_trotter_pass_count(L, p4, p2):
     m = P.Model(E.tfim(L, 0.5))
     assert P.trotter_passes(m, 4) == p4
     assert P.trotter_passes(m, 2) == p2
+
+
+def test_trotter_device_observables():
+    """Observables through device pointers equal the host arrays of the same evolution."""
+    L = 14
+    m = P.Model(E.xxz(L, 1.0, 0.5, E.random_fields(L, 4)))
+    psi0 = E.product_state(L, E.neel_index(L))
+    a, b = to_dev(psi0), to_dev(psi0)
+    _, oh = P.trotter_evolve(m, a, 0.05, 4, order=4, energy=True)
+    _, od = P.trotter_evolve(m, b, 0.05, 4, order=4, energy=True, device_obs=True)
+    for k in ("sz", "energy", "norm"):
+        assert np.array_equal(oh[k], od[k].cpu().numpy()), k
