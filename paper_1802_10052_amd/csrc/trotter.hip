@@ -25,12 +25,15 @@
 namespace ed {
 namespace {
 
+// 512 threads per 4096-amplitude tile (measured against 256 and 1024), one gate per LDS round:
+// rounds that apply two gates of a layer on adjacent pairs to groups of 16 (kPairRounds) leave
+// half of 512 threads idle and were slower
 constexpr int kGThreads = 512;
 constexpr int kGThreadBits = kGThreads == 256 ? 8 : kGThreads == 512 ? 9 : 10;
 constexpr int kGTileBits = 12;
 constexpr int kGSlots = (1 << kGTileBits) / kGThreads;  // amplitudes per thread
 constexpr int kGSlotBits = kGTileBits - kGThreadBits;
-constexpr bool kPairRounds = false;  // two gates on adjacent pairs share one LDS round
+constexpr bool kPairRounds = false;
 constexpr int kGLow = 4;                                 // contiguous low bits of a window tile
 constexpr int kFuse = 4;                                 // consecutive layers per run of passes
 constexpr int kMaxGates = kFuse * (kGTileBits / 2);      // gates of one pass
@@ -139,8 +142,8 @@ __global__ __launch_bounds__(kGThreads) void gate_pass(double2* __restrict__ psi
     }
     __syncthreads();
     // LDS gates, in list order: each thread owns whole groups of the amplitudes a gate mixes (the
-    // index with zero bits inserted at q), reads them, writes them back. Two gates of one layer on
-    // adjacent pairs (q, q+1), (q+2, q+3) share one round on groups of 16.
+    // index with zero bits inserted at q), reads them, writes them back. With kPairRounds, two
+    // gates of one layer on adjacent pairs (q, q+1), (q+2, q+3) share one round on groups of 16.
     for (int g = 0; g < gp.ngate; ++g) {
         const int q = G[2 * g], layer = G[2 * g + 1];
         if (in_regs(layer, q, N)) continue;  // done in registers
