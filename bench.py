@@ -404,7 +404,7 @@ def row_lrqi_L28(P, E, torch, dev, reps=10, steps=20):
 
 
 def row_rdm_L28(P, E, torch, dev, reps=3):
-    """All single-site and all two-site reduced density matrices (Sec. IV) of a random L = 28
+    """All single-site and all two-site reduced density matrices (Sec. ed:sec:meas) of a random L = 28
     state: 378 pairs in 15 LDS-tiled passes. Algorithmic work: the 6 upper off-diagonal entries of
     each pair's 4x4 matrix are complex multiply-adds over the 2^(L-2) quads of amplitudes (48
     flops per quad and pair); the 4 diagonal entries are marginals of |psi|^2, summed once per
@@ -437,7 +437,7 @@ def row_rdm_L28(P, E, torch, dev, reps=3):
 
 
 def row_liouville_L14(P, E, torch, dev, reps=5, steps=10):
-    """Liouville-space evolution (Sec. VI.B) of the dissipative XXZ chain of the trajectory row
+    """Liouville-space evolution (Sec. ed:sec:Liouville) of the dissipative XXZ chain of the trajectory row
     (J = 1, Delta = 1, gamma = 0.1 sigma^- on every site) at L = 14: the density matrix as a 2^28
     superket (4 GiB). Reported: one product i Lcal |rho>> (the tuned streaming passes of the local
     part plus the jump gather pass; GB/s on the headline's 32 B per amplitude), and Arnoldi time

@@ -7,7 +7,7 @@ so that the oracle and the HIP library share nothing but their inputs.
 Conventions (the paper is silent on them; the readings are listed in the design notes):
   * local basis: index 0 = up (sigma^z = +1), index 1 = down;
   * state index x = sum_k i_k 2^(L-k): site 1 is the most significant digit, as in the
-    row-major rank-L tensor view of the state (Sec. IV, single-site density matrix);
+    row-major rank-L tensor view of the state (Sec. ed:sec:meas, single-site density matrix);
   * bond operators are 4x4 with row/column index i_k*2 + i_{k+1} (site k is the left factor
     of the Kronecker product, App. A bond rule).
 """

@@ -3,13 +3,13 @@
  *
  * The library applies a local 1-D lattice Hamiltonian to a dense complex128 state without ever
  * storing H (the "rule set x psi" product of Sec. ed:sec:krylov, Eq. ed:eq:OKrylov), and builds on that
- * product: Lanczos ground states (Sec. II statics, computed matrix-free), Krylov time steps
- * (Sec. ed:sec:krylov), quantum trajectories (Sec. VI.A), a bond-coupling adjoint gradient and the
- * half-chain bond entropy (Sec. IV).
+ * product: Lanczos ground states (Sec. ed:sec:statics, computed matrix-free), Krylov time steps
+ * (Sec. ed:sec:krylov), quantum trajectories (Sec. ed:sec:QT), a bond-coupling adjoint gradient and the
+ * half-chain bond entropy (Sec. ed:sec:meas).
  *
  * Conventions shared by every call
  *   - d = 2. The state index is x = sum_{k=1..L} i_k 2^(L-k): site 1 is the most significant
- *     digit (the row-major rank-L tensor view of Sec. IV). Local index 0 = up (sigma^z = +1).
+ *     digit (the row-major rank-L tensor view of Sec. ed:sec:meas). Local index 0 = up (sigma^z = +1).
  *     Site k therefore sits at bit p = L-k, and bond (k, k+1) occupies bits (L-k-1, L-k).
  *   - Amplitudes are ed_c64 (interleaved re, im; the layout of torch.complex128), D = 2^L.
  *   - "device" pointers are HIP device memory owned by the caller; the library never frees or
@@ -160,7 +160,7 @@ ed_status ed_apply_H(const ed_model* model, const ed_c64* psi, ed_c64* out, void
 
 /* ----------------------------------------------------------------------------------------
  * ed_lanczos_ground: lowest eigenpair of a Hermitian model, matrix-free. The paper obtains the
- * ground state from the full H with eigh/eigsh (Sec. II, statics); here the same Lanczos
+ * ground state from the full H with eigh/eigsh (Sec. ed:sec:statics); here the same Lanczos
  * recurrence that underlies the Krylov step (Sec. ed:sec:krylov) runs on H psi directly:
  *   v_1 = v0/|v0|; w = H v_j; beta_j = |w| after orthogonalisation; T = V^H H V is the projected
  *   matrix. reorth selects how w is orthogonalised:
@@ -217,7 +217,7 @@ ed_status ed_lanczos_ground(const ed_model* model, const ed_c64* v0, const ed_la
  * ed_krylov_evolve: n_steps Krylov time steps psi(t+dt) = |psi| V_m exp(-i dt T_m) e_1
  * (Sec. ed:sec:krylov): a new Krylov basis of the current state every step, xi_i = [exp(-i dt T_m)]_{i,1}.
  * hermitian = 1: Lanczos, T_m real symmetric tridiagonal (closed systems);
- * hermitian = 0: Arnoldi, T_m upper Hessenberg (non-Hermitian generators, Sec. VI.B).
+ * hermitian = 0: Arnoldi, T_m upper Hessenberg (non-Hermitian generators, Sec. ed:sec:Liouville).
  * Stopping (the paper names a tolerance and a maximal basis size): the a-posteriori estimate
  * |psi| beta_m |[exp(-i dt T_m)]_{m,1}| <= tol, an invariant subspace (beta_m <= 1e-14 |T_m|), or
  * m = m_max. fixed_m > 0 forces exactly min(fixed_m, m_max) vectors unless the space is invariant.
@@ -300,7 +300,7 @@ ed_status ed_trotter_evolve(const ed_model* model, ed_c64* psi, double dt, int n
 ed_status ed_trotter_passes(const ed_model* model, int order, int* passes);
 
 /* ----------------------------------------------------------------------------------------
- * ed_measure: norm and all-site <sigma^z> of a state in one read pass (Sec. IV: the diagonal of
+ * ed_measure: norm and all-site <sigma^z> of a state in one read pass (Sec. ed:sec:meas: the diagonal of
  * every single-site reduced density matrix). psi device; sz host [L] (site order k = 1..L,
  * normalised by <psi|psi>), norm host (may be NULL). Synchronises stream.
  * Workspace: ed_measure_workspace bytes.
@@ -326,7 +326,7 @@ ed_status ed_measure_noalloc(const ed_c64* psi, int L, double* sz, double* norm,
 
 /* ----------------------------------------------------------------------------------------
  * ed_entropy: bond entropy S(l) = -sum_j Lambda_j log Lambda_j (natural log, 0 log 0 = 0) of the
- * bipartition sites 1..l | l+1..L (Sec. IV, bond entropy). Lambda_j are the eigenvalues of
+ * bipartition sites 1..l | l+1..L (Sec. ed:sec:meas, bond entropy). Lambda_j are the eigenvalues of
  * rho_l = M M^dagger / <psi|psi>, M = psi reshaped to 2^l x 2^(L-l) row-major (no copy is made).
  * The Gram matrix of the smaller side is formed on the FP64 matrix cores, reduced to
  * tridiagonal form by Householder steps on the GPU, and its eigenvalues are found by bisection
@@ -349,7 +349,7 @@ ed_status ed_entropy_ex(const ed_c64* psi, int L, int d, int l_cut, double* S, d
                         void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
- * Liouville space (Sec. VI.B, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket, App. F). The density
+ * Liouville space (Sec. ed:sec:Liouville, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket, App. F). The density
  * matrix rho (D x D, D = 2^L) of the Lindblad equation (Eq. ed:eq:lindbladme)
  *   d rho/dt = -i [H, rho] + sum_nu (L_nu rho L_nu^dagger - 1/2 {L_nu^dagger L_nu, rho}),
  * with L_nu = sqrt(rates[z][k-1]) J_z on site k, is stored as the superket |rho>> of D^2 entries,
@@ -383,7 +383,7 @@ ed_status ed_liouville_measure(const ed_c64* rho, int L, double* sz, double* tra
                                void* stream);
 
 /* ----------------------------------------------------------------------------------------
- * ed_rdm: every single-site and every two-site reduced density matrix of a pure state (Sec. IV:
+ * ed_rdm: every single-site and every two-site reduced density matrix of a pure state (Sec. ed:sec:meas:
  * rho of the kept sites is the sum over the traced sites of psi psi^*, the kept legs in front,
  * e.g. rho_1 = [[sum A A^*, sum A B^*], [sum B A^*, sum B B^*]] for psi = [A][B]). Not normalised:
  * Tr rho = <psi|psi>.
@@ -415,7 +415,7 @@ int ed_rdm_plan_pairs(int L, int* pairs, int max_pairs, int* pass_of);
 int ed_rdm_plan_sites(int L, int* bits, int max_bits, int* pass_of);
 
 /* ----------------------------------------------------------------------------------------
- * ed_trace_distances: D(a_m, b_m) = 1/2 Tr |a_m - b_m|, |A| = sqrt(A^dagger A) (Sec. V, the
+ * ed_trace_distances: D(a_m, b_m) = 1/2 Tr |a_m - b_m|, |A| = sqrt(A^dagger A) (Sec. ed:sec:conv, the
  * distance of the error measures eps_local and eps_corr), for count pairs of n x n matrices.
  * a, b  host [count][n][n] complex row-major, meant Hermitian (only the Hermitian part of a - b
  *       enters); out host [count]. D is half the sum of the absolute eigenvalues of a - b, taken
@@ -425,7 +425,7 @@ int ed_rdm_plan_sites(int L, int* bits, int max_bits, int* pass_of);
 ed_status ed_trace_distances(int n, int count, const ed_c64* a, const ed_c64* b, double* out);
 
 /* ----------------------------------------------------------------------------------------
- * Quantum trajectories (Sec. VI.A) of the Lindblad equation with one jump operator per site,
+ * Quantum trajectories (Sec. ed:sec:QT) of the Lindblad equation with one jump operator per site,
  * L_nu = sqrt(rate_nu) J on site nu, and H_eff = H - (i/2) sum_nu L_nu^dagger L_nu built inside.
  * Per trajectory: draw r; evolve the unnormalised state under H_eff (Krylov steps of length dt,
  * Arnoldi basis, stopping tolerance tol, at most m_max vectors) until |psi|^2 = r, the crossing

@@ -1,4 +1,4 @@
-"""H built on the full Hilbert space from Kronecker products (Sec. II, Eqs. ed:eq:genericH and
+"""H built on the full Hilbert space from Kronecker products (Sec. ed:sec:statics, Eqs. ed:eq:genericH and
 ed:eq:OH; site, bond and InfiniteFunc rules of App. A, Eqs. ed:eq:appsiters / ed:eq:appbondrs /
 ed:eq:appinfrs).
 
@@ -72,7 +72,7 @@ def hamiltonian_sparse(desc):
 
 
 def hamiltonian_dense(desc):
-    """Dense H by numpy.kron (the paper's dense build, Sec. II)."""
+    """Dense H by numpy.kron (the paper's dense build, Sec. ed:sec:statics)."""
     L, d = desc.L, desc.d
     D = d ** L
     H = np.zeros((D, D), np.complex128)

@@ -4,7 +4,7 @@ expm_step     method 1: psi(t+dt) = exp(-i H dt) psi(t) with the full propagator
 krylov_step   method 3: psi(t+dt) ~ sum_i xi_i v_i with xi = |psi| [exp(-i dt T_m)]_{:,1} on the
               Krylov basis of psi (Sec. ed:sec:krylov). Hermitian H: Lanczos with full
               reorthogonalisation, T_m tridiagonal; non-Hermitian H: Arnoldi, upper Hessenberg
-              T_m (Sec. VI.B, last paragraph).
+              T_m (Sec. ed:sec:Liouville, last paragraph).
 Stopping rule (the paper only names a tolerance): the a-posteriori estimate
 err_m = |psi| beta_m |[exp(-i dt T_m)]_{m,1}| <= tol, or happy breakdown beta_m <= 1e-14 |T|.
 """

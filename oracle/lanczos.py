@@ -1,7 +1,7 @@
-"""Ground state (Sec. II, statics; the Krylov basis of Sec. ed:sec:krylov).
+"""Ground state (Sec. ed:sec:statics; the Krylov basis of Sec. ed:sec:krylov).
 
 ground_state_eigsh follows the paper's statics (scipy.sparse.linalg.eigsh on the full sparse H,
-Sec. II). lanczos_ground is the textbook Lanczos recurrence with full reorthogonalisation
+Sec. ed:sec:statics). lanczos_ground is the textbook Lanczos recurrence with full reorthogonalisation
 (classical Gram-Schmidt applied twice), which is what the GPU path computes matrix-free.
 """
 import numpy as np

@@ -1,4 +1,4 @@
-"""Liouville-space evolution of the density matrix (Sec. VI.B, Eq. ed:eq:liousuperket, App. F).
+"""Liouville-space evolution of the density matrix (Sec. ed:sec:Liouville, Eq. ed:eq:liousuperket, App. F).
 
 With row-major vec(rho) (index j*D + k for rho_jk), A rho B -> (A (x) B^T) |rho>> (App. F), so
   Lcal = -i (H (x) 1 - 1 (x) H^T)

@@ -1,10 +1,10 @@
-"""Measurements on a pure state (Sec. IV).
+"""Measurements on a pure state (Sec. ed:sec:meas).
 
 sz_all       <sigma^z_k> for every site k, normalised by <psi|psi>; the diagonal of the
-             single-site reduced density matrix rho_k (Sec. IV, the [A][B] block construction).
+             single-site reduced density matrix rho_k (Sec. ed:sec:meas, the [A][B] block construction).
 energy       <psi|H|psi>/<psi|psi>.
 bond_entropy S(l) = -sum_j Lambda_j log Lambda_j with Lambda_j the eigenvalues of
-             rho_l = M M^dagger, M = psi reshaped to d^l x d^(L-l) (Sec. IV, bond entropy; the
+             rho_l = M M^dagger, M = psi reshaped to d^l x d^(L-l) (Sec. ed:sec:meas, bond entropy; the
              paper notes the SVD of M gives the same spectrum). Natural log, 0 log 0 = 0.
 """
 import numpy as np

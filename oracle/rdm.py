@@ -1,12 +1,12 @@
-"""Reduced density matrices and the error measures built on them (Sec. IV, single-site and
-two-site density matrices; Sec. V, Eqs. ed:eq:erhoi, ed:eq:erhoij, ed:eq:eener, ed:eq:eentr and
+"""Reduced density matrices and the error measures built on them (Sec. ed:sec:meas, single-site and
+two-site density matrices; Sec. ed:sec:conv, Eqs. ed:eq:erhoi, ed:eq:erhoij, ed:eq:eener, ed:eq:eentr and
 the convergence rate of Eq. ed:eq:convrate).
 
 Test infrastructure: imported only by the tests, the smoke check and the CPU baseline of the
 benchmark; it shares no code with the HIP library.
 
 rho of the sites K = (k_1 < k_2 < ...) is the partial trace of |psi><psi| over the other sites,
-taken the way Sec. IV lays it out: psi is reshaped into a rank-L tensor (site 1 = first leg),
+taken the way Sec. ed:sec:meas lays it out: psi is reshaped into a rank-L tensor (site 1 = first leg),
 the kept legs are permuted to the front, the tensor is reshaped into a d^|K| x d^(L-|K|) matrix
 A, and rho = A A^dagger. Row and column index of rho: i_{k_1} d^(|K|-1) + ... + i_{k_|K|}.
 No normalisation: Tr rho = <psi|psi>.

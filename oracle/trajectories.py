@@ -1,4 +1,4 @@
-"""Quantum trajectories for the Lindblad equation (Sec. VI.A, after Dalibard et al.).
+"""Quantum trajectories for the Lindblad equation (Sec. ed:sec:QT, after Dalibard et al.).
 
 Per trajectory, with H_eff = H - (i/2) sum_nu L_nu^dagger L_nu:
   1. draw r; evolve the unnormalised state under H_eff until |psi|^2 drops to r;
@@ -36,7 +36,7 @@ class PhiloxDraws:
 
 
 def effective_hamiltonian(H, jump_ops):
-    """H_eff = H - (i/2) sum_nu L_nu^dagger L_nu (the standard reading of Sec. VI.A)."""
+    """H_eff = H - (i/2) sum_nu L_nu^dagger L_nu (the standard reading of Sec. ed:sec:QT)."""
     acc = sp.csr_matrix(H.shape, dtype=np.complex128)
     for Lnu in jump_ops:
         acc = acc + (Lnu.conj().T @ Lnu)

@@ -36,6 +36,12 @@ __global__ __launch_bounds__(256) void hpsi_small(const double2* __restrict__ ps
     out[x] = y;
 }
 
+// Gathered jobs whose partners a wide tile loads before its in-tile terms. A wide tile holds 4
+// amplitudes per thread, so a job costs 16 registers: 4 jobs fit the 128 registers of a
+// 1024-thread workgroup with a real diagonal, 3 with a complex one.
+template <unsigned CLS>
+constexpr int wide_prefetch() { return (CLS & kDiagReal) ? 4 : 3; }
+
 // One tile per workgroup. With gathered bits, consecutive workgroups of one XCD (workgroups are
 // dealt to the 8 XCDs round-robin) take the 2^G tiles that differ only in the gathered bits, so
 // the neighbouring tiles a workgroup reads are being streamed into the same L2 at the same time.
@@ -79,7 +85,8 @@ __global__ __launch_bounds__(kTileThreads * 4) void hpsi_tile_wide(
     const int64_t group = (gl << 3) | xcd;
     const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
     const int64_t n = low | (member << pa.gpos) | (high << (pa.gpos + pa.G));
-    tile_body<CLS, FIRST, true, false, 10, DOT>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s, 0, nullptr, sF, sD);
+    tile_body<CLS, FIRST, true, false, 10, DOT, wide_prefetch<CLS>()>(psi, out, site, bond, dlo, dmid, dhi, pa, n,
+                                                                      s, 0, nullptr, sF, sD);
 }
 
 // Two tiles per workgroup (512 threads, 128 KiB of LDS, one workgroup per CU): the tiles n and

@@ -1,4 +1,4 @@
-// Bond (Schmidt) entropy of a pure state (Sec. IV, bond entropy; S(l) of the convergence
+// Bond (Schmidt) entropy of a pure state (Sec. ed:sec:meas, bond entropy; S(l) of the convergence
 // section): rho_l = M M^dagger with M the state reshaped to d^l x d^(L-l), its eigenvalues
 // Lambda_j, and S = -sum_j Lambda_j log Lambda_j. The paper computes rho_l by a matrix product
 // and takes an eigendecomposition (noting the SVD of M gives the same spectrum).

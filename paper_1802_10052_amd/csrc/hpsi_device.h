@@ -118,7 +118,9 @@ __device__ __forceinline__ void tile_load(const double2* __restrict__ psi, const
 
 // The rest of a tile, once tile_load has filled v (and acc in later passes): stage the tile in
 // LDS, evaluate every term of the pass, store out. Contains a workgroup barrier (two with DOT).
-template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8, bool DOT = false>
+// PF: the partners of the first PF gathered jobs are loaded right after the tile is staged, so
+// that their L2 round trips overlap the in-tile terms' LDS work (0: loaded job by job at the end).
+template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8, bool DOT = false, int PF = 0>
 __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
                                             const double2* __restrict__ site, const double2* __restrict__ bond,
                                             const double2* __restrict__ dlo, const double2* __restrict__ dmid,
@@ -131,6 +133,7 @@ __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
     constexpr int kSl = 1 << (kTileBits - TB);     // register slots per thread
     static_assert(TB >= 8 && TB < kTileBits, "the diagonal tables take bits 0..7 from the thread index");
     static_assert(!PAIR || TB == 8, "paired tiles use 256 threads per tile");
+    static_assert(PF == 0 || (GATHER && !PAIR), "prefetched jobs are read from global memory");
     const int64_t base = tile_base(pa, FIRST, n);
     const int64_t i0 = tile_index(pa, FIRST, base, t);
     const int64_t step = slot_step<TB>(pa, FIRST);
@@ -165,6 +168,19 @@ __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
         }
     }
     __syncthreads();
+    double2 gv[PF > 0 ? PF : 1][kSl];
+    if constexpr (PF > 0) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            if (j < pa.njobs) {
+                const GatherJob& jb = pa.jobs[j];
+                const int sx = jb.sx ? (kSl >> 1) : 0;
+                const double2* __restrict__ pw = pv + (tile_base(pa, FIRST, n ^ jb.txor) - base);
+#pragma unroll
+                for (int k = 0; k < kSl; ++k) gv[j][k] = pw[(k ^ sx) * step];
+            }
+        }
+    }
     if (FIRST && pa.lr) {
         // long-range zz: pairs inside the tile (table) + sum over low bits p < 11 of z_p F_p
         // (bits 0..TB-1 are the thread's, TB..10 the slot's)
@@ -269,7 +285,21 @@ __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
         // gathered terms: partner tile n ^ txor, register slot k ^ sx, coefficients by pattern.
         // (Loading several partner tiles per round trip was measured slower: the one-workgroup
         // launches are bound by the missing overlap of load, LDS and store phases, not by it.)
-        for (int j = 0; j < pa.njobs; ++j) {
+        int j0 = 0;
+        if constexpr (PF > 0) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+                if (j < pa.njobs) {
+                    const GatherJob& jb = pa.jobs[j];
+                    const int p = int((n >> jb.shift) & 3);
+                    const double2 c0 = jb.coef[p][0], c1 = jb.coef[p][1];
+#pragma unroll
+                    for (int k = 0; k < kSl; ++k) cfma<OFFR>(acc[k], k >= kSl / 2 ? c1 : c0, gv[j][k]);
+                }
+            }
+            j0 = PF;
+        }
+        for (int j = j0; j < pa.njobs; ++j) {
             const GatherJob& jb = pa.jobs[j];
             const int sx = jb.sx ? (kSl >> 1) : 0;  // jobs flip at most the tile's top bit
             const int p = int((n >> jb.shift) & 3);
@@ -323,7 +353,7 @@ __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
 }
 
 // One tile of one pass (tile index n): tile_load, then tile_finish (see there).
-template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8, bool DOT = false>
+template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8, bool DOT = false, int PF = 0>
 __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, double2* __restrict__ out,
                                           const double2* __restrict__ site, const double2* __restrict__ bond,
                                           const double2* __restrict__ dlo, const double2* __restrict__ dmid,
@@ -335,8 +365,8 @@ __device__ __forceinline__ void tile_body(const double2* __restrict__ psi, doubl
     double2 v[kSl];
     double2 acc[kSl];
     tile_load<FIRST, TB>(psi, out, pa, n, t, v, acc);
-    tile_finish<CLS, FIRST, GATHER, PAIR, TB, DOT>(out, site, bond, dlo, dmid, dhi, pa, n, s, t, so, sF, sD, psi, v,
-                                                   acc);
+    tile_finish<CLS, FIRST, GATHER, PAIR, TB, DOT, PF>(out, site, bond, dlo, dmid, dhi, pa, n, s, t, so, sF, sD, psi,
+                                                       v, acc);
 }
 
 // Per-amplitude body for one x (small L, or one small state per workgroup): partners read from

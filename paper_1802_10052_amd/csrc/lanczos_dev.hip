@@ -1,4 +1,4 @@
-// Device-resident Lanczos ground state for short chains (Sec. II, statics, by the Lanczos recurrence
+// Device-resident Lanczos ground state for short chains (Sec. ed:sec:statics, by the Lanczos recurrence
 // of Sec. ed:sec:krylov): with full reorthogonalisation and no restart, the whole recurrence runs in
 // one cooperative launch instead of a dozen launches and a host round trip per product.
 //

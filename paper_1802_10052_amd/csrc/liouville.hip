@@ -1,4 +1,4 @@
-// Liouville-space evolution (Sec. VI.B, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket, App. F): the
+// Liouville-space evolution (Sec. ed:sec:Liouville, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket, App. F): the
 // density matrix of an L-site system as the superket |rho>> of 2L digits (row-major vec(rho): the
 // row index is the high L bits, the column index the low L bits), and
 //   i Lcal = H_eff (x) 1 - 1 (x) H_eff^* + i sum_nu gamma_nu J_nu (x) J_nu^*,

@@ -1,6 +1,6 @@
 // Model handle: folds the rule-set terms (Eq. ed:eq:genericH, App. A site and bond rules) into
 // one 2x2 operator per site and one 4x4 operator per bond, classifies the non-zero pattern so the
-// H psi kernels can skip absent terms ("iterate only over non-zero elements", Sec. II), builds the
+// H psi kernels can skip absent terms ("iterate only over non-zero elements", Sec. ed:sec:statics), builds the
 // diagonal tables, and plans the streaming passes of H psi.
 #include <algorithm>
 #include <cmath>

@@ -1,7 +1,7 @@
-// Single-site and two-site reduced density matrices of a pure state (Sec. IV: rho of the kept
+// Single-site and two-site reduced density matrices of a pure state (Sec. ed:sec:meas: rho of the kept
 // sites is the sum over the traced indices of psi psi^*, arranged as the blocks [A][B] of the
 // state with the kept legs in front; only one triangle is needed since rho is Hermitian), and
-// the trace distance D = 1/2 Tr|rho - rho'| of the convergence study (Sec. V).
+// the trace distance D = 1/2 Tr|rho - rho'| of the convergence study (Sec. ed:sec:conv).
 //
 // rho_{k,j} for a pair of sites k < j (bits q = L-k > p = L-j) is, with u = bit q and v = bit p of
 // the index, rho[2u+v][2u'+v'] = sum over the other bits of psi[.. u .. v ..] psi^*[.. u' .. v' ..].
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void rdm_reduce(const double* __restrict__ par
 
 // ---------------------------------------------------------------------------- single sites
 // rho_k alone: for the site at bit b, rho_k[0][0] = sum |psi(x)|^2, rho_k[1][1] = sum |psi(x|B)|^2
-// and rho_k[0][1] = sum psi(x) psi^*(x|B) over the x with bit b clear (Sec. IV, one kept site).
+// and rho_k[0][1] = sum psi(x) psi^*(x|B) over the x with bit b clear (Sec. ed:sec:meas, one kept site).
 // A pass evaluates the bits of its tile that no earlier pass has: the 4 low bits and 8 others in
 // the first pass, 8 others in each later one (ceil((L - 4) / 8) passes).
 constexpr int kRdm1Vals = 4;  // d0, d1, Re c, Im c

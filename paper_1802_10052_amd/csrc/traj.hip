@@ -1,11 +1,11 @@
-// Quantum trajectories for the Lindblad equation (Sec. VI.A). Per trajectory, with
+// Quantum trajectories for the Lindblad equation (Sec. ed:sec:QT). Per trajectory, with
 // H_eff = H - (i/2) sum_nu L_nu^dagger L_nu and L_nu = sqrt(rate_nu) J on site nu:
 //   1. draw r; evolve the unnormalised state under H_eff until |psi|^2 drops to r;
 //   2. draw r_kappa; p_nu = <psi|L_nu^dagger L_nu|psi>, P_nu the normalised cumulative sum;
 //   3. apply L_kappa with P_{kappa-1} < r_kappa <= P_kappa, renormalise, go back to 1.
 // The evolution uses Krylov steps (the paper notes quantum trajectories work with any of its
 // three propagators); H_eff is not Hermitian, so the basis comes from Arnoldi and the projected
-// matrix is upper Hessenberg (Sec. VI.B). The step's basis gives psi(t + tau) for every tau in the
+// matrix is upper Hessenberg (Sec. ed:sec:Liouville). The step's basis gives psi(t + tau) for every tau in the
 // step, so the time at which |psi|^2 reaches r is solved in the small space, without extra H psi.
 //
 // Batched path: one persistent launch. Each workgroup runs its own list of trajectories, dealt on

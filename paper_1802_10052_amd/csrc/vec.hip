@@ -1,7 +1,7 @@
-// Vector kernels of the Krylov methods (Sec. ed:sec:krylov and Sec. II statics, computed matrix-free):
+// Vector kernels of the Krylov methods (Sec. ed:sec:krylov and Sec. ed:sec:statics, computed matrix-free):
 // deterministic dot products against several basis vectors at once, the matching multi-axpy,
 // norm + scaling, the Krylov combination psi = sum_i c_i v_i, and the all-site <sigma^z>
-// reduction of Sec. IV. Every reduction uses a fixed grid, a fixed per-thread assignment and a
+// reduction of Sec. ed:sec:meas. Every reduction uses a fixed grid, a fixed per-thread assignment and a
 // fixed tree, so results are bitwise reproducible from run to run.
 #include "ed_vec.h"
 

@@ -1,4 +1,4 @@
-"""GPU parity of the bond entropy (Sec. IV) against the oracle's SVD of the reshaped state.
+"""GPU parity of the bond entropy (Sec. ed:sec:meas) against the oracle's SVD of the reshaped state.
 
 Tolerance: both sides resolve the Schmidt spectrum to about 1e-16 absolute, so eigenvalues below
 that are noise; their share of S is at most n * 1e-16 * |log 1e-16| ~ 3e-11 at n = 8192. The

@@ -1,4 +1,4 @@
-"""GPU parity of the Liouville-space path (Sec. VI.B, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket,
+"""GPU parity of the Liouville-space path (Sec. ed:sec:Liouville, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket,
 App. F): the Liouvillian model's product i Lcal |rho>> against the oracle's Kronecker-built
 superoperator, Arnoldi time steps against the oracle's exact propagation, and full-size
 invariants (trace and Hermiticity preservation of any rho; the decay identity of the dissipative
@@ -157,7 +157,7 @@ def test_liouville_unsupported_paths():
 
 def test_trajectory_ensemble_vs_liouville_L8():
     """The Liouville path as the exact reference of the batched trajectories (same Lindblad
-    equation, Sec. VI): 2048 GPU trajectories of the dissipative XXZ chain at L = 8 (dt = 0.01,
+    equation, Sec. ed:sec:open): 2048 GPU trajectories of the dissipative XXZ chain at L = 8 (dt = 0.01,
     T = 1) against the GPU superket evolution; every site's ensemble mean of <sigma^z_k>(t) lies
     within 4 standard errors (+1e-3) of tr(sigma^z_k rho(t))."""
     L, gamma, n_traj, dt, steps, stride, seed = 8, 0.1, 2048, 0.01, 100, 10, 21

@@ -1,5 +1,5 @@
-"""GPU parity of ed_rdm (single-site and two-site reduced density matrices, Sec. IV) and of the
-trace-distance error measures (Sec. V, Eqs. ed:eq:erhoi, ed:eq:erhoij) against the oracle's
+"""GPU parity of ed_rdm (single-site and two-site reduced density matrices, Sec. ed:sec:meas) and of the
+trace-distance error measures (Sec. ed:sec:conv, Eqs. ed:eq:erhoi, ed:eq:erhoij) against the oracle's
 reshape/transpose construction, and exact full-size pins.
 
 Tolerances: an entry sums 2^(L-2) products in float64 in a fixed order (per-lane sequential,

@@ -1,4 +1,4 @@
-"""GPU parity of the quantum-trajectory paths (Sec. VI.A) against the oracle on the same Philox
+"""GPU parity of the quantum-trajectory paths (Sec. ed:sec:QT) against the oracle on the same Philox
 streams, plus the closed forms that pin every trajectory of the dissipative XXZ chain:
 from the Neel state with [H, N_up] = 0 the no-jump norm is exp(-gamma n t), so jump times follow
 from the draws alone, and sum_k <sigma^z_k> = -2 (number of jumps so far) exactly."""

@@ -1,4 +1,4 @@
-"""Pins of the Liouville-space oracle (Sec. VI.B, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket,
+"""Pins of the Liouville-space oracle (Sec. ed:sec:Liouville, Eqs. ed:eq:lioutrafo, ed:eq:liousuperket,
 App. F, with the anticommutator of the master equation Eq. ed:eq:lindbladme) beyond the trace and
 decay identities of the trajectory tests: the analytic solutions of single-qubit amplitude damping
 and dephasing, the superket map O' rho O -> (O' (x) O^T)|rho>> on random matrices, trace

@@ -1,5 +1,5 @@
-"""Pins of the reduced-density-matrix oracle (Sec. IV) and of the error measures of the
-convergence study (Sec. V, Eqs. ed:eq:erhoi, ed:eq:erhoij, ed:eq:convrate) against facts that do
+"""Pins of the reduced-density-matrix oracle (Sec. ed:sec:meas) and of the error measures of the
+convergence study (Sec. ed:sec:conv, Eqs. ed:eq:erhoi, ed:eq:erhoij, ed:eq:convrate) against facts that do
 not come from its reshape/transpose code: entries recomputed by a loop over basis indices with
 bit arithmetic, closed forms for product, GHZ and W states, partial-trace consistency, the
 Bloch-vector form of the 2x2 trace distance, pure-state distances, and the convergence orders of
