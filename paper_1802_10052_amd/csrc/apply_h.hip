@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void hpsi_small(const double2* __restrict__ ps
     out[x] = y;
 }
 
-// Gathered jobs whose partners a wide tile loads before its in-tile terms. A wide tile holds 4
+// Gathered jobs whose partners a wide tile loads ahead, per round (two rounds). A wide tile holds 4
 // amplitudes per thread, so a job costs 16 registers: 4 jobs fit the 128 registers of a
 // 1024-thread workgroup with a real diagonal, 3 with a complex one.
 template <unsigned CLS>

@@ -119,7 +119,9 @@ __device__ __forceinline__ void tile_load(const double2* __restrict__ psi, const
 // The rest of a tile, once tile_load has filled v (and acc in later passes): stage the tile in
 // LDS, evaluate every term of the pass, store out. Contains a workgroup barrier (two with DOT).
 // PF: the partners of the first PF gathered jobs are loaded right after the tile is staged, so
-// that their L2 round trips overlap the in-tile terms' LDS work (0: loaded job by job at the end).
+// that their L2 round trips overlap the in-tile terms' LDS work; halfway through the thread bits
+// their terms are added and the next PF jobs' partners loaded into the same registers. Jobs
+// beyond 2 PF (and all jobs when PF = 0) are loaded one by one after the in-tile terms.
 template <unsigned CLS, bool FIRST, bool GATHER = false, bool PAIR = false, int TB = 8, bool DOT = false, int PF = 0>
 __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
                                             const double2* __restrict__ site, const double2* __restrict__ bond,
@@ -169,18 +171,32 @@ __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
     }
     __syncthreads();
     double2 gv[PF > 0 ? PF : 1][kSl];
-    if constexpr (PF > 0) {
+    // jobs j0 .. j0 + PF - 1: load their partners into gv, or add their terms from gv
+    auto pf_load = [&](int j0) {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
-            if (j < pa.njobs) {
-                const GatherJob& jb = pa.jobs[j];
+            if (j0 + j < pa.njobs) {
+                const GatherJob& jb = pa.jobs[j0 + j];
                 const int sx = jb.sx ? (kSl >> 1) : 0;
                 const double2* __restrict__ pw = pv + (tile_base(pa, FIRST, n ^ jb.txor) - base);
 #pragma unroll
                 for (int k = 0; k < kSl; ++k) gv[j][k] = pw[(k ^ sx) * step];
             }
         }
-    }
+    };
+    auto pf_use = [&](int j0) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            if (j0 + j < pa.njobs) {
+                const GatherJob& jb = pa.jobs[j0 + j];
+                const int p = int((n >> jb.shift) & 3);
+                const double2 c0 = jb.coef[p][0], c1 = jb.coef[p][1];
+#pragma unroll
+                for (int k = 0; k < kSl; ++k) cfma<OFFR>(acc[k], k >= kSl / 2 ? c1 : c0, gv[j][k]);
+            }
+        }
+    };
+    if constexpr (PF > 0) pf_load(0);
     if (FIRST && pa.lr) {
         // long-range zz: pairs inside the tile (table) + sum over low bits p < 11 of z_p F_p
         // (bits 0..TB-1 are the thread's, TB..10 the slot's)
@@ -271,6 +287,13 @@ __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
                 }
             }
         }
+        if constexpr (PF > 0) {
+            // halfway through the thread bits: add the first jobs, load the next ones
+            if (q == TB / 2 - 1) {
+                pf_use(0);
+                pf_load(PF);
+            }
+        }
     }
 
     if constexpr (GATHER) {
@@ -287,17 +310,8 @@ __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
         // launches are bound by the missing overlap of load, LDS and store phases, not by it.)
         int j0 = 0;
         if constexpr (PF > 0) {
-#pragma unroll
-            for (int j = 0; j < PF; ++j) {
-                if (j < pa.njobs) {
-                    const GatherJob& jb = pa.jobs[j];
-                    const int p = int((n >> jb.shift) & 3);
-                    const double2 c0 = jb.coef[p][0], c1 = jb.coef[p][1];
-#pragma unroll
-                    for (int k = 0; k < kSl; ++k) cfma<OFFR>(acc[k], k >= kSl / 2 ? c1 : c0, gv[j][k]);
-                }
-            }
-            j0 = PF;
+            pf_use(PF);
+            j0 = 2 * PF;
         }
         for (int j = j0; j < pa.njobs; ++j) {
             const GatherJob& jb = pa.jobs[j];
