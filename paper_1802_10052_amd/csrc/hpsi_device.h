@@ -306,8 +306,9 @@ __device__ __forceinline__ void tile_finish(double2* __restrict__ out,
             for (int k = 0; k < kSl; ++k) cfma<OFFR>(acc[k], k >= kSl / 2 ? c1 : c0, v[k ^ (kSl >> 1)]);
         }
         // gathered terms: partner tile n ^ txor, register slot k ^ sx, coefficients by pattern.
-        // (Loading several partner tiles per round trip was measured slower: the one-workgroup
-        // launches are bound by the missing overlap of load, LDS and store phases, not by it.)
+        // The second round of jobs loaded ahead, then the rest one by one. (What pays is hiding
+        // the partner reads behind the in-tile LDS work; loading several partners per round
+        // trip at this point, after that work, was measured slower.)
         int j0 = 0;
         if constexpr (PF > 0) {
             pf_use(PF);
