@@ -89,6 +89,28 @@ __global__ __launch_bounds__(kTileThreads * 4) void hpsi_tile_wide(
                                                                       s, 0, nullptr, sF, sD);
 }
 
+// The window passes of a wide plan: one tile per 512-thread workgroup (8 amplitudes per thread)
+// without LDS padding, so that two workgroups share a CU and one's loads overlap the other's LDS
+// work. Their gather groups are small (the plan's few window gathers), so twice the tiles in
+// flight still fit an XCD's L2; one gathered job's partners (32 registers) are loaded ahead.
+// Blocks map to tiles like the one-tile launches.
+template <unsigned CLS, bool DOT = false>
+__global__ __launch_bounds__(kTileThreads * 2) void hpsi_tile_mid(
+    const double2* __restrict__ psi, double2* __restrict__ out, const double2* __restrict__ site,
+    const double2* __restrict__ bond, const double2* __restrict__ dlo, const double2* __restrict__ dmid,
+    const double2* __restrict__ dhi, PassArgs pa) {
+    __shared__ double2 s[1 << kTileBits];
+    __shared__ double2 sF[kTileBits];
+    __shared__ double2 sD[kTileThreads * 2 / 64];
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b & 7, j = b >> 3;
+    const int64_t member = j & ((int64_t(1) << pa.G) - 1), gl = j >> pa.G;
+    const int64_t group = (gl << 3) | xcd;
+    const int64_t low = group & ((int64_t(1) << pa.gpos) - 1), high = group >> pa.gpos;
+    const int64_t n = low | (member << pa.gpos) | (high << (pa.gpos + pa.G));
+    tile_body<CLS, false, true, false, 9, DOT, 1>(psi, out, site, bond, dlo, dmid, dhi, pa, n, s, 0, nullptr, sF, sD);
+}
+
 // Two tiles per workgroup (512 threads, 128 KiB of LDS, one workgroup per CU): the tiles n and
 // n ^ (tile-index bit gpos) that differ in the first gathered bit, one per half. Block b is mapped
 // like the one-tile launch, with pairs in place of tiles, so a gather group's pairs still run
@@ -143,9 +165,10 @@ hipError_t launch_variant(const ed_model* m, const double2* psi, double2* out, h
         const unsigned pad = (pd.G > 0 && pd.occ1) ? unsigned(kOccPadBytes) : 0u;
         if (pd.G > 0 && pd.wide) {
             const dim3 wblock{unsigned(4 * kTileThreads)};
+            const dim3 mblock{unsigned(2 * kTileThreads)};
             if (pd.first) hipLaunchKernelGGL((hpsi_tile_wide<CLS, true>), grid, wblock, kOccPadBytes, s, ED_TILE_ARGS);
-            else if (dot) hipLaunchKernelGGL((hpsi_tile_wide<CLS, false, true>), grid, wblock, kOccPadBytes, s, ED_TILE_ARGS);
-            else hipLaunchKernelGGL((hpsi_tile_wide<CLS, false>), grid, wblock, kOccPadBytes, s, ED_TILE_ARGS);
+            else if (dot) hipLaunchKernelGGL((hpsi_tile_mid<CLS, true>), grid, mblock, 0, s, ED_TILE_ARGS);
+            else hipLaunchKernelGGL((hpsi_tile_mid<CLS, false>), grid, mblock, 0, s, ED_TILE_ARGS);
         } else if (pd.G > 0 && pd.pair) {
             const dim3 pgrid{unsigned(tiles / 2)}, pblock{unsigned(2 * kTileThreads)};
             if (pd.first) hipLaunchKernelGGL((hpsi_tile_pair<CLS, true>), pgrid, pblock, 0, s, ED_TILE_ARGS);

@@ -60,7 +60,7 @@ struct PassDesc {
     uint32_t bond_gmask;  // bit i: bond (gb + i, gb + i + 1) belongs to this pass
     int occ1;            // launch with one workgroup per CU (a group's tiles then fit in L2)
     int pair;            // two tiles per workgroup: the first gathered bit's partner comes from LDS
-    int wide;            // 1024 threads per tile, one workgroup per CU
+    int wide;            // first pass: 1024 threads per tile, one per CU; window passes: 512, two per CU
 };
 
 // One gathered term of a pass as the kernels evaluate it: out[x] += coef * psi[partner of x], the
