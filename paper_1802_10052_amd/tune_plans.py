@@ -19,6 +19,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def keep_faster(kept, key, ms, plan):
+    """Models that share a cache key (the transverse-field chain at g = 0.5 and g = 1 has one
+    operator class) are tuned one after the other, and each tune records its own choice. Returns
+    the plan the key should hold: the faster of this tune's and the one kept for the key so far
+    (the earlier one on a tie); `kept` maps key -> (ms, plan) and is updated."""
+    if key in kept and kept[key][0] <= ms:
+        return kept[key][1]
+    kept[key] = (ms, plan)
+    return plan
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
@@ -50,11 +61,10 @@ def main():
         out = torch.empty_like(psi)
         best, ms = m.tune(psi, out, reps=args.reps)
         print(f"{name}: {m.describe_plan(best)} {ms[best]:.3f} ms (of {len(ms)} plans)", flush=True)
-        key = m.plan_key
-        if key in kept and kept[key][0] <= ms[best]:
-            P.plan_cache_put(key, kept[key][1])
-        else:
-            kept[key] = (ms[best], m.describe_plan(best))
+        chosen = m.describe_plan(best)
+        keep = keep_faster(kept, m.plan_key, ms[best], chosen)
+        if keep != chosen:
+            P.plan_cache_put(m.plan_key, keep)
         del psi, out, m
         torch.cuda.empty_cache()
     P.plan_cache_save(args.out)

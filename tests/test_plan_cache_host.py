@@ -75,3 +75,15 @@ def test_shipped_plan_table_parses(lib):
         key, plan = line.rstrip("\n").split("\t")
         assert key.split()[0].startswith("gfx") and " L=" in key and "cands=" in key
         assert plan.startswith(("first", "small"))
+
+
+def test_tune_keeps_the_faster_choice_per_key():
+    """Models sharing a key keep the faster of their tuned plans (the earlier one on a tie)."""
+    from paper_1802_10052_amd.tune_plans import keep_faster
+    kept = {}
+    assert keep_faster(kept, "k", 4.78, "first +G6 wide | c4 h18 +G2 wide") == "first +G6 wide | c4 h18 +G2 wide"
+    assert keep_faster(kept, "k", 4.81, "first +G5 wide | c4 h17 +G3") == "first +G6 wide | c4 h18 +G2 wide"
+    assert keep_faster(kept, "k", 4.78, "first +G5 wide | c4 h17 +G3") == "first +G6 wide | c4 h18 +G2 wide"
+    assert keep_faster(kept, "k", 4.60, "first +G5 wide | c4 h17 +G3") == "first +G5 wide | c4 h17 +G3"
+    assert kept["k"] == (4.60, "first +G5 wide | c4 h17 +G3")
+    assert keep_faster(kept, "other", 9.0, "first | c4 h12") == "first | c4 h12"
